@@ -1,0 +1,194 @@
+"""FP64 CPU oracle of the Exact mapping (paper Sec. II-B, Eq. (1)-(3)).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only callers.  The HIP library never imports,
+links or loads anything here, and nothing here uses the library.
+
+The arithmetic lives in ``exact_oracle.c`` (plain C, FP64, no fast-math) and
+``pseudo_oracle.c``; this file only marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "_build", "liboracle.so")
+_SRCS = [os.path.join(_HERE, "exact_oracle.c")]
+if os.path.exists(os.path.join(_HERE, "pseudo_oracle.c")):
+    _SRCS.append(os.path.join(_HERE, "pseudo_oracle.c"))
+
+M4 = 0
+UNIT = 1
+
+
+def build_lib(force: bool = True) -> str:
+    if force or not os.path.exists(_SO):
+        os.makedirs(os.path.dirname(_SO), exist_ok=True)
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-shared", "-fPIC", "-o", tmp] + _SRCS
+                              + ["-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class _Cells(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int64), ("cell_face_off", ctypes.c_void_p),
+                ("face_vert_off", ctypes.c_void_p), ("face_vert", ctypes.c_void_p),
+                ("face_plane", ctypes.c_void_p), ("verts", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build_lib(force=True)
+        lib = ctypes.CDLL(_SO)
+        d, i64, vp, i = ctypes.c_double, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
+        lib.orc_w.restype = d
+        lib.orc_w.argtypes = [d]
+        lib.orc_F.restype = d
+        lib.orc_F.argtypes = [i, d]
+        lib.orc_G.restype = d
+        lib.orc_G.argtypes = [i, d]
+        lib.orc_moments.argtypes = [d, d, d, vp]
+        lib.orc_pyramid.restype = d
+        lib.orc_pyramid.argtypes = [i, d, d, d]
+        lib.orc_pair_fraction.restype = d
+        lib.orc_pair_fraction.argtypes = [i, vp, d, ctypes.POINTER(_Cells), i64]
+        lib.orc_cell_dist2.restype = d
+        lib.orc_cell_dist2.argtypes = [vp, ctypes.POINTER(_Cells), i64]
+        lib.orc_pairs_brute.restype = i64
+        lib.orc_pairs_brute.argtypes = [i64, vp, vp, ctypes.POINTER(_Cells), vp, vp, i64]
+        lib.orc_pairs.restype = i64
+        lib.orc_pairs.argtypes = [i64, vp, vp, ctypes.POINTER(_Cells), vp, vp, vp, i64]
+        lib.orc_pair_fractions.argtypes = [i, vp, vp, ctypes.POINTER(_Cells), i64, vp, vp, vp]
+        lib.orc_reduce.argtypes = [i64, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp]
+        lib.orc_num_threads.restype = i
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class _Geom:
+    """Keeps contiguous copies alive while the C struct points at them."""
+
+    def __init__(self, cells):
+        self.cf = np.ascontiguousarray(cells.cell_face_off, dtype=np.int64)
+        self.fv = np.ascontiguousarray(cells.face_vert_off, dtype=np.int64)
+        self.fvert = np.ascontiguousarray(cells.face_vert, dtype=np.int32)
+        self.plane = _f64(cells.face_plane)
+        self.verts = _f64(cells.verts)
+        self.s = _Cells(self.cf.size - 1, _p(self.cf).value, _p(self.fv).value, _p(self.fvert).value,
+                        _p(self.plane).value, _p(self.verts).value)
+
+
+# ---------------------------------------------------------------- primitives
+def w(q: float) -> float:
+    return _load().orc_w(q)
+
+
+def F(s: float, profile: int = M4) -> float:
+    return _load().orc_F(profile, s)
+
+
+def G(s: float, profile: int = M4) -> float:
+    return _load().orc_G(profile, s)
+
+
+def moments(r0: float, R0: float, alpha: float) -> np.ndarray:
+    """[r0*P_-1, P_0, P_2, P_3, P_4, P_5] at alpha."""
+    out = np.zeros(6)
+    _load().orc_moments(r0, R0, alpha, _p(out))
+    return out
+
+
+def pyramid(r0: float, R0: float, phi: float, profile: int = M4) -> float:
+    """Integral of W (h = 1) over the right-angled vertex pyramid (r0, R0, phi)."""
+    return _load().orc_pyramid(profile, r0, R0, phi)
+
+
+# ---------------------------------------------------------------- per pair
+def pair_fraction(p, h: float, cells, cell: int, profile: int = M4) -> float:
+    g = _Geom(cells)
+    pp = _f64(p)
+    return _load().orc_pair_fraction(profile, _p(pp), h, ctypes.byref(g.s), cell)
+
+
+def cell_dist2(p, cells, cell: int) -> float:
+    g = _Geom(cells)
+    pp = _f64(p)
+    return _load().orc_cell_dist2(_p(pp), ctypes.byref(g.s), cell)
+
+
+def pairs(xyz, h, cells, brute: bool = False):
+    """(pair_p, pair_c) int32, sorted by cell then particle."""
+    lib = _load()
+    g = _Geom(cells)
+    xyz = _f64(xyz)
+    h = _f64(h)
+    n = h.size
+    if brute:
+        cnt = lib.orc_pairs_brute(n, _p(xyz), _p(h), ctypes.byref(g.s), None, None, 0)
+        pp = np.zeros(cnt, np.int32)
+        pc = np.zeros(cnt, np.int32)
+        lib.orc_pairs_brute(n, _p(xyz), _p(h), ctypes.byref(g.s), _p(pp), _p(pc), cnt)
+        order = np.lexsort((pp, pc))
+        return pp[order], pc[order]
+    box = _f64(cells.box)
+    cnt = lib.orc_pairs(n, _p(xyz), _p(h), ctypes.byref(g.s), _p(box), None, None, 0)
+    pp = np.zeros(cnt, np.int32)
+    pc = np.zeros(cnt, np.int32)
+    lib.orc_pairs(n, _p(xyz), _p(h), ctypes.byref(g.s), _p(box), _p(pp), _p(pc), cnt)
+    return pp, pc
+
+
+def pair_fractions(xyz, h, cells, pair_p, pair_c, profile: int = M4) -> np.ndarray:
+    lib = _load()
+    g = _Geom(cells)
+    xyz = _f64(xyz)
+    h = _f64(h)
+    pp = np.ascontiguousarray(pair_p, dtype=np.int32)
+    pc = np.ascontiguousarray(pair_c, dtype=np.int32)
+    f = np.zeros(pp.size)
+    lib.orc_pair_fractions(profile, _p(xyz), _p(h), ctypes.byref(g.s), pp.size, _p(pp), _p(pc), _p(f))
+    return f
+
+
+def reduce(m, cell_volume, n_cells, pair_p, pair_c, f):
+    lib = _load()
+    m = _f64(m)
+    vol = _f64(cell_volume)
+    pp = np.ascontiguousarray(pair_p, dtype=np.int32)
+    pc = np.ascontiguousarray(pair_c, dtype=np.int32)
+    f = _f64(f)
+    S = np.zeros(m.size)
+    M = np.zeros(n_cells)
+    rho = np.zeros(n_cells)
+    lib.orc_reduce(m.size, _p(m), n_cells, _p(vol), pp.size, _p(pp), _p(pc), _p(f), _p(S), _p(M), _p(rho))
+    return S, M, rho
+
+
+def map_particles(particles, cells, profile: int = M4):
+    """Full Exact mapping: pairs, per-pair fractions, S_a, cell mass and density."""
+    pp, pc = pairs(particles.xyz, particles.h, cells)
+    f = pair_fractions(particles.xyz, particles.h, cells, pp, pc, profile)
+    S, M, rho = reduce(particles.m, cells.cell_volume, cells.n_cells, pp, pc, f)
+    return {"pair_p": pp, "pair_c": pc, "f": f, "S": S, "M": M, "rho": rho}
+
+
+def num_threads() -> int:
+    return _load().orc_num_threads()

@@ -1,0 +1,26 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: larger CPU cases")
+
+
+@pytest.fixture(scope="session")
+def uniform4k():
+    import synth
+    return synth.workload(*synth.UNIFORM_4K)
+
+
+@pytest.fixture(scope="session")
+def uniform4k_oracle(uniform4k):
+    import oracle
+    p, c = uniform4k
+    return oracle.map_particles(p, c)
