@@ -1,0 +1,183 @@
+#!/usr/bin/env python
+"""Throughput of the Exact mapping on one MI355X: particle-cell pairs mapped per second.
+
+One step = one synchronous ``map_particles`` call on the 262,144-particle clumpy
+workload (uniform background plus three Gaussian clumps, sigma 0.05 box,
+density contrast 1e4; box-clipped Voronoi cells of the particles): input
+validation, geometry tables, pair search, integration of every pair, the
+sum-to-one normalisation and the per-cell reduction.  Inputs are resident in
+device memory before the timed region.  The mixed path (FP32 closed-form
+terms) is the headline value; the all-FP64 path is timed beside it.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work model of the integration kernel (counted from its formulas,
+# add/mul = 1, fused multiply-add = 2, divide / square root / atan2 / log1p = 1):
+FLOP_FACE = 7       # wall distance d = c - n.p and r0 = |d|/h
+FLOP_EDGE = 19      # projections rho, l_a, l_b and their scaling by 1/h
+FLOP_ETERM = 8      # per-edge setup: c^2, the support crossing l2 and c (2 square roots)
+FLOP_MOMENT = 66    # closed form at one point: sqrt, asinh, angle difference, piece polynomial
+FLOP_QUAD = 250     # 8-point Gauss-Legendre sub-interval of the shell integrand (8 sqrt, 8 rcp)
+FLOP_ANGLE = 6      # angle of one edge part seen from the foot point (one atan2) times H
+
+PEAK_FP64 = 78.6   # TFLOP/s, MI355X FP64 vector
+PEAK_FP32 = 157.3  # TFLOP/s, MI355X FP32 vector (packed)
+
+
+def algorithmic_flops(st) -> float:
+    return (FLOP_FACE * st["n_face_visits"] + FLOP_EDGE * st["n_edge_visits"] + FLOP_ETERM * st["n_edge_terms"]
+            + FLOP_MOMENT * st["n_moment_evals"] + FLOP_QUAD * st["n_quad_intervals"]
+            + FLOP_ANGLE * st["n_angle_evals"])
+
+
+def to_device(p, c):
+    import torch
+
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    class DevCells:
+        pass
+
+    dc = DevCells()
+    dc.cell_face_off = t(c.cell_face_off)
+    dc.face_vert_off = t(c.face_vert_off)
+    dc.face_vert = t(c.face_vert.astype(np.int32))
+    dc.face_plane = t(c.face_plane)
+    dc.verts = t(c.verts)
+    dc.cell_volume = t(c.cell_volume)
+    dc.box = c.box
+    return t(p.xyz), t(p.m), t(p.h), dc
+
+
+def cpu_baseline(p, c, target_s: float = 12.0):
+    """The FP64 oracle, untuned, on a seeded sample of cells with all their pairs."""
+    import oracle
+
+    rng = np.random.default_rng(12345)
+    n_try = 400
+    sel = np.sort(rng.choice(c.n_cells, n_try, replace=False))
+    t0 = time.perf_counter()
+    pp, pc = oracle.pairs_for_cells(p.xyz, p.h, c, sel)
+    oracle.pair_fractions(p.xyz, p.h, c, pp, pc)
+    dt = time.perf_counter() - t0
+    n_cells = int(min(c.n_cells, max(n_try, n_try * target_s / max(dt, 1e-3))))
+    sel = np.sort(rng.choice(c.n_cells, n_cells, replace=False))
+    t0 = time.perf_counter()
+    pp, pc = oracle.pairs_for_cells(p.xyz, p.h, c, sel)
+    f = oracle.pair_fractions(p.xyz, p.h, c, pp, pc)
+    dt = time.perf_counter() - t0
+    assert np.all(np.isfinite(f))
+    return {"value": pp.size / dt, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{n_cells} of {c.n_cells} cells (seeded), all {pp.size} of their pairs: pair search + "
+                      f"closed-form integrals, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the mapping runs on a single "
+              f"MI355X; see the sharding design for several GPUs)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2404_17084_amd as em
+
+    em.load()
+    print("bench: generating the 262,144-particle clumpy workload", file=sys.stderr, flush=True)
+    p, c = synth.workload(*synth.CLUMPS_256K)
+    xyz, m, h, dc = to_device(p, c)
+    nc = c.n_cells
+    M = torch.zeros(nc, dtype=torch.float64, device="cuda:0")
+    rho = torch.zeros_like(M)
+    S = torch.zeros(p.n, dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+
+    mapper = em.Mapper(device=0)
+    results = {}
+    Ms = {}
+    for prec, name in ((em.MAP_FP64, "fp64"), (em.MAP_MIXED, "mixed")):
+        mapper.set_precision(prec)
+        for _ in range(args.warmup):
+            em.map_particles(mapper.ctx, xyz, m, h, dc, M, rho, S)
+        torch.cuda.synchronize()
+        stats = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            stats.append(em.map_particles(mapper.ctx, xyz, m, h, dc, M, rho, S))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        npairs = stats[-1]["n_pairs"]
+        ms_int = float(np.mean([s["ms_integrate"] for s in stats]))
+        flops = algorithmic_flops(stats[-1])
+        results[name] = {"pairs_per_s": args.steps * npairs / dt, "ms_per_step": 1e3 * dt / args.steps,
+                         "ms_integrate": ms_int, "ms_pairs": float(np.mean([s["ms_pairs"] for s in stats])),
+                         "ms_reduce": float(np.mean([s["ms_reduce"] for s in stats])),
+                         "ms_setup": float(np.mean([s["ms_setup"] for s in stats])),
+                         "flops_per_launch": flops, "tflops_integrate": flops / (ms_int * 1e-3) / 1e12,
+                         "mass_err": abs(stats[-1]["mass_out"] - stats[-1]["mass_in"]),
+                         "max_abs_S_minus_1": stats[-1]["max_abs_S_minus_1"], "n_pairs": npairs,
+                         "n_fixup_terms": stats[-1]["n_fixup_terms"], "n_moment_evals": stats[-1]["n_moment_evals"],
+                         "n_quad_intervals": stats[-1]["n_quad_intervals"], "n_angle_evals": stats[-1]["n_angle_evals"],
+                         "n_edge_visits": stats[-1]["n_edge_visits"], "n_candidates": stats[-1]["n_candidates"]}
+        Ms[name] = M.cpu().numpy().copy()
+        print(f"bench: {name}: {results[name]}", file=sys.stderr, flush=True)
+    mapper.close()
+    rel = np.abs(Ms["mixed"] - Ms["fp64"]) / np.abs(Ms["fp64"])
+
+    mx = results["mixed"]
+    ach = mx["tflops_integrate"]
+    line = {
+        "metric": "particle-cell pairs mapped/s (mixed FP32/FP64, <=1e-5 rel err per cell)",
+        "value": mx["pairs_per_s"],
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mx["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 terms, f64 geometry/sums",
+        "data": "synthetic",
+        "config": {"workload": "clumps-262144: uniform background + 3 Gaussian clumps (sigma 0.05 box, contrast "
+                               "1e4, seed 2), h from 58 neighbours, box-clipped Voronoi cells",
+                   "particles": p.n, "cells": nc, "pairs": mx["n_pairs"], "precision": "mixed"},
+        "fp64": {"pairs_per_s": results["fp64"]["pairs_per_s"], "ms_per_step": results["fp64"]["ms_per_step"],
+                 "ms_integrate": results["fp64"]["ms_integrate"],
+                 "tflops_integrate": results["fp64"]["tflops_integrate"],
+                 "roofline_frac": results["fp64"]["tflops_integrate"] / PEAK_FP64},
+        "speedup_mixed_vs_fp64": mx["pairs_per_s"] / results["fp64"]["pairs_per_s"],
+        "mixed_vs_fp64_max_cell_rel": float(rel.max()),
+        "mass_err_mixed": mx["mass_err"],
+        "stages_ms_mixed": {k: mx[k] for k in ("ms_setup", "ms_pairs", "ms_integrate", "ms_reduce")},
+        "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32, "unit": "TFLOP/s", "frac": ach / PEAK_FP32,
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        print("bench: timing the oracle on a cell sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(p, c)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,170 @@
+/*
+ * exactmap.h -- C ABI of the MI355X (gfx950) Exact-mapping library.
+ *
+ * The library maps SPH particles (positions, masses, smoothing lengths) onto a
+ * grid of convex cells (a box-clipped Voronoi tessellation) as in Sec. II-B of
+ * Lau, Petkova & Bonnell, "Hybrid Radiation Hydrodynamics scheme with gravity
+ * tree-based adaptive optimization algorithm" (arXiv 2404.17084), Eq. (1)-(3):
+ *
+ *     f_ai  = integral over cell V_i of W(|r - r_a|, h_a) dV      (per pair)
+ *     S_a   = sum_i f_ai                                            (per particle)
+ *     M_i   = sum_a m_a f_ai / S_a,   rho_i = M_i / V_i             (per cell)
+ *
+ * W is the M4 cubic spline with support 2h (Sec. III-C, III-D).  A pair (a, i)
+ * exists iff the distance from r_a to the closed cell i is strictly below 2h_a.
+ * The integral is evaluated in closed form as a signed sum over vertex
+ * pyramids (particle apex, one cell wall as base, split into right triangles
+ * about the particle's projection point on the wall), Sec. II-B.
+ *
+ * Conventions for every entry point:
+ *  - Return value: MAP_OK (0) on success, a negative MAP_E* code on failure.
+ *    map_last_error(ctx) then returns a NUL-terminated message owned by ctx,
+ *    valid until the next call on that ctx.  Calls on one ctx are serialised
+ *    by an internal mutex; different ctx objects are independent.
+ *  - Pointers in the *_in structs are borrowed for the duration of the call
+ *    (map_submit copies them before it returns).  mem_kind says where they
+ *    live: MAP_MEM_HOST (pageable or pinned host memory) or MAP_MEM_DEVICE
+ *    (device memory of ctx's device, e.g. torch data_ptr(), fully written
+ *    before the call: the library does not synchronise with other streams).
+ *  - All device memory used internally is owned by the library (per-ctx pool,
+ *    grown on demand, released by map_shutdown).
+ *  - Validation failures are reported before any device work: n < 0, bad
+ *    offsets, faces with fewer than 3 vertices, vertex ids out of range ->
+ *    MAP_EINVAL / MAP_EGEOM; non-finite values, h <= 0, non-unit normals ->
+ *    MAP_EINVAL / MAP_EGEOM (checked on the device, before integration).
+ */
+#ifndef EXACTMAP_H
+#define EXACTMAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MAP_OK = 0,
+    MAP_EINVAL = -1,    /* bad argument or particle data */
+    MAP_ENOMEM = -2,    /* device or host allocation failed, or job larger than the budget */
+    MAP_EDEVICE = -3,   /* HIP runtime or kernel error */
+    MAP_EBUSY = -4,     /* serving queue full */
+    MAP_ENOTFOUND = -5, /* unknown job id */
+    MAP_EGEOM = -6,     /* malformed cell geometry */
+    MAP_ENUMERIC = -7   /* non-finite result */
+};
+
+/* Arithmetic of the per-triangle closed-form terms. */
+enum {
+    MAP_FP64 = 0,  /* everything in FP64 */
+    MAP_MIXED = 1  /* FP64 wall distance, foot point and edge projections; FP32
+                      closed-form terms accumulated in FP64; FP64 recomputation
+                      of terms flagged by a conditioning test; FP64
+                      normalisation and reductions */
+};
+
+enum { MAP_MEM_HOST = 0, MAP_MEM_DEVICE = 1 };
+
+typedef struct map_ctx map_ctx;
+
+typedef struct map_config {
+    int device;                /* HIP device ordinal */
+    int precision;             /* MAP_FP64 or MAP_MIXED, default for map_particles */
+    uint64_t hbm_budget_bytes; /* serving admission budget; 0 = 80% of free device memory */
+    int max_jobs;              /* serving: jobs resident on the device at once (0 = 8) */
+    int max_queue;             /* serving: jobs waiting for admission (0 = 1024) */
+    const char *tune_cache_path; /* autotuner cache file (text); NULL = no cache */
+} map_config;
+
+/* Particles: structure of arrays, FP64. */
+typedef struct map_particles_in {
+    int64_t n;
+    const double *xyz; /* 3n, x0 y0 z0 x1 y1 z1 ... */
+    const double *m;   /* n, masses */
+    const double *h;   /* n, smoothing lengths (> 0) */
+    int mem_kind;
+} map_particles_in;
+
+/* Convex cells in CSR form (FP64 coordinates). */
+typedef struct map_cells_in {
+    int64_t n_cells;
+    int64_t n_faces;
+    int64_t n_face_verts;          /* length of face_vert */
+    int64_t n_verts;
+    const int64_t *cell_face_off;  /* n_cells+1: faces of cell i are [off[i], off[i+1]) */
+    const int64_t *face_vert_off;  /* n_faces+1: slots of face j in face_vert */
+    const int32_t *face_vert;      /* vertex ids, counter-clockwise seen from outside the cell */
+    const double *face_plane;      /* 4 per face: outward unit normal n and c with n.x = c */
+    const double *verts;           /* 3 per vertex */
+    const double *cell_volume;     /* n_cells, or NULL: computed on the device */
+    double box[6];                 /* xlo ylo zlo xhi yhi zhi: bounding box of all cells */
+    int mem_kind;
+} map_cells_in;
+
+typedef struct map_stats {
+    int64_t n_pairs;        /* exact pair set size */
+    int64_t n_candidates;   /* cells tested by the exact meet test */
+    int64_t n_edge_terms;   /* edge terms integrated (faces and edges inside the support) */
+    int64_t n_fixup_terms;  /* MAP_MIXED: edge terms recomputed in FP64 */
+    int64_t n_face_visits;  /* wall planes tested (all walls of every pair's cell) */
+    int64_t n_edge_visits;  /* wall edges projected (walls closer than 2h) */
+    int64_t n_moment_evals; /* closed-form evaluations (asinh, angle difference and polynomial) */
+    int64_t n_quad_intervals; /* MAP_MIXED: 8-point Gauss-Legendre sub-intervals (shell piece) */
+    int64_t n_angle_evals;  /* angles of edge parts beyond the support or with a piece correction */
+    double mass_in;         /* sum of m_a */
+    double mass_out;        /* sum of M_i */
+    double max_abs_S_minus_1; /* over particles whose support lies inside box */
+    double ms_setup;        /* device time: validation and geometry tables */
+    double ms_pairs;        /* device time: pair search and cell ordering */
+    double ms_integrate;    /* device time: the integration kernel(s) */
+    double ms_fixup;        /* device time: FP64 recomputation of flagged terms */
+    double ms_reduce;       /* device time: S_a, normalisation, M_i, rho_i */
+    double ms_total;        /* device time of the whole call */
+} map_stats;
+
+/* Outputs: caller-owned, caller-sized, in mem_kind memory.  Any may be NULL. */
+typedef struct map_out {
+    double *cell_mass;     /* n_cells */
+    double *cell_density;  /* n_cells */
+    double *frac_sum_raw;  /* n particles: S_a before normalisation */
+    double *pair_frac;     /* raw f_ai in the order map_pairs returns (cell, then particle) */
+    int32_t *pair_p;       /* particle of each pair, same order */
+    int32_t *pair_c;       /* cell of each pair, same order */
+    int64_t pair_capacity; /* length of pair_frac / pair_p / pair_c */
+    int mem_kind;
+    map_stats *stats;      /* host memory; may be NULL */
+} map_out;
+
+/* Create a context on cfg->device (cfg may be NULL: device 0, FP64). */
+int map_init(const map_config *cfg, map_ctx **out);
+/* Drain the serving loop, free all device memory and the context. */
+int map_shutdown(map_ctx *ctx);
+const char *map_last_error(map_ctx *ctx);
+/* Change the default precision of map_particles (MAP_FP64 / MAP_MIXED). */
+int map_set_precision(map_ctx *ctx, int precision);
+
+/*
+ * Launch shape of the integration kernel (the autotuner's knobs): threads per
+ * workgroup (256), wavefronts of consecutive pairs taken per queue pop
+ * (1..64), persistent workgroups per compute unit (1..64), and persistent = 0
+ * for a plain one-thread-per-pair launch.  Results do not depend on them.
+ */
+int map_set_tune(map_ctx *ctx, int block, int tile_waves, int grid_per_cu, int persistent);
+int map_get_tune(map_ctx *ctx, int *block, int *tile_waves, int *grid_per_cu, int *persistent);
+
+/*
+ * Pair set of Sec. II-B: every (particle a, cell i) with dist(r_a, cell i) < 2h_a,
+ * sorted by cell, then by particle.  Count-then-fill: with pair_p/pair_c NULL
+ * only *n_pairs is written; otherwise up to capacity pairs are written (host
+ * memory) and *n_pairs is the full count.
+ */
+int map_pairs(map_ctx *ctx, const map_particles_in *p, const map_cells_in *c, int64_t *n_pairs,
+              int32_t *pair_p, int32_t *pair_c, int64_t capacity);
+
+/* Synchronous Exact mapping, Eq. (1)-(3) with sum-to-one normalisation. */
+int map_particles(map_ctx *ctx, const map_particles_in *p, const map_cells_in *c, map_out *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EXACTMAP_H */

@@ -68,6 +68,9 @@ def _load():
         lib.orc_pairs_brute.argtypes = [i64, vp, vp, ctypes.POINTER(_Cells), vp, vp, i64]
         lib.orc_pairs.restype = i64
         lib.orc_pairs.argtypes = [i64, vp, vp, ctypes.POINTER(_Cells), vp, vp, vp, i64]
+        for nm in ("orc_pairs_for_cells", "orc_pairs_for_particles"):
+            getattr(lib, nm).restype = i64
+            getattr(lib, nm).argtypes = [i64, vp, vp, ctypes.POINTER(_Cells), i64, vp, vp, vp, i64]
         lib.orc_pair_fractions.argtypes = [i, vp, vp, ctypes.POINTER(_Cells), i64, vp, vp, vp]
         lib.orc_reduce.argtypes = [i64, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp]
         lib.orc_num_threads.restype = i
@@ -154,6 +157,52 @@ def pairs(xyz, h, cells, brute: bool = False):
     pc = np.zeros(cnt, np.int32)
     lib.orc_pairs(n, _p(xyz), _p(h), ctypes.byref(g.s), _p(box), _p(pp), _p(pc), cnt)
     return pp, pc
+
+
+def _pairs_sel(fn, xyz, h, cells, sel):
+    lib = _load()
+    g = _Geom(cells)
+    xyz = _f64(xyz)
+    h = _f64(h)
+    sel = np.ascontiguousarray(sel, dtype=np.int32)
+    f = getattr(lib, fn)
+    cnt = f(h.size, _p(xyz), _p(h), ctypes.byref(g.s), sel.size, _p(sel), None, None, 0)
+    pp = np.zeros(cnt, np.int32)
+    pc = np.zeros(cnt, np.int32)
+    f(h.size, _p(xyz), _p(h), ctypes.byref(g.s), sel.size, _p(sel), _p(pp), _p(pc), cnt)
+    return pp, pc
+
+
+def pairs_for_cells(xyz, h, cells, sel):
+    """All pairs of the selected cells (brute force over particles)."""
+    return _pairs_sel("orc_pairs_for_cells", xyz, h, cells, sel)
+
+
+def pairs_for_particles(xyz, h, cells, sel):
+    """All pairs of the selected particles (brute force over cells)."""
+    return _pairs_sel("orc_pairs_for_particles", xyz, h, cells, sel)
+
+
+def sampled_cell_mass(particles, cells, sel_cells, profile: int = M4):
+    """M_i and rho_i of the selected cells, with S_a of every particle touching them.
+
+    Returns (M, rho, S_of, pairs) where S_of maps particle -> S_a.
+    """
+    pp, pc = pairs_for_cells(particles.xyz, particles.h, cells, sel_cells)
+    parts = np.unique(pp)
+    qp, qc = pairs_for_particles(particles.xyz, particles.h, cells, parts)
+    fq = pair_fractions(particles.xyz, particles.h, cells, qp, qc, profile)
+    S = np.zeros(particles.h.size)
+    np.add.at(S, qp, fq)
+    f = pair_fractions(particles.xyz, particles.h, cells, pp, pc, profile)
+    M = np.zeros(len(sel_cells))
+    pos = {int(c): t for t, c in enumerate(sel_cells)}
+    for k in range(pp.size):
+        a = pp[k]
+        if S[a] > 0:
+            M[pos[int(pc[k])]] += particles.m[a] * (f[k] / S[a])
+    rho = M / np.asarray(cells.cell_volume)[np.asarray(sel_cells)]
+    return M, rho, S, (pp, pc, f)
 
 
 def pair_fractions(xyz, h, cells, pair_p, pair_c, profile: int = M4) -> np.ndarray:

@@ -394,7 +394,7 @@ int64_t orc_pairs(int64_t n, const double *xyz, const double *h, const orc_cells
             }
         for (int d = 0; d < 3; d++) { bb[6 * i + d] = lo[d]; bb[6 * i + 3 + d] = hi[d]; }
     }
-    int G = (int)ceil(cbrt((double)nc));
+    int G = (int)ceil(2.0 * cbrt((double)nc));
     if (G < 1) G = 1;
     if (G > 256) G = 256;
     double ext[3], inv[3];
@@ -508,6 +508,84 @@ int64_t orc_pairs(int64_t n, const double *xyz, const double *h, const orc_cells
     free(blist);
     free(bb);
 #undef BINRANGE
+    return total;
+}
+
+/*
+ * Pairs restricted to selected cells (brute force over particles) or to
+ * selected particles (brute force over cells), for sampled checks of large
+ * inputs.  Output in selection order, then ascending particle (cell) index.
+ * Returns the pair count; arrays may be NULL (count only).
+ */
+static void cell_box(const orc_cells *C, int64_t i, double *lo, double *hi)
+{
+    for (int d = 0; d < 3; d++) { lo[d] = INFINITY; hi[d] = -INFINITY; }
+    for (int64_t j = C->cell_face_off[i]; j < C->cell_face_off[i + 1]; j++)
+        for (int64_t k = C->face_vert_off[j]; k < C->face_vert_off[j + 1]; k++) {
+            const double *v = C->verts + 3 * (int64_t)C->face_vert[k];
+            for (int d = 0; d < 3; d++) {
+                if (v[d] < lo[d]) lo[d] = v[d];
+                if (v[d] > hi[d]) hi[d] = v[d];
+            }
+        }
+}
+
+static int box_near(const double *p, double r, const double *lo, const double *hi)
+{
+    for (int d = 0; d < 3; d++)
+        if (p[d] + r < lo[d] || p[d] - r > hi[d]) return 0;
+    return 1;
+}
+
+int64_t orc_pairs_for_cells(int64_t n, const double *xyz, const double *h, const orc_cells *C, int64_t nsel,
+                            const int32_t *sel, int32_t *pair_p, int32_t *pair_c, int64_t cap)
+{
+    int64_t *cnt = (int64_t *)calloc(nsel + 1, sizeof(int64_t));
+    for (int pass = 0; pass < 2; pass++) {
+        if (pass == 1) {
+            for (int64_t t = 0; t < nsel; t++) cnt[t + 1] += cnt[t];
+            if (!pair_p) break;
+        }
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t t = 0; t < nsel; t++) {
+            int64_t i = sel[t];
+            double lo[3], hi[3];
+            cell_box(C, i, lo, hi);
+            int64_t k = pass ? cnt[t] : 0;
+            for (int64_t a = 0; a < n; a++) {
+                const double *p = xyz + 3 * a;
+                if (!box_near(p, 2.0 * h[a], lo, hi)) continue;
+                if (!meets(p, h[a], C, i)) continue;
+                if (pass && k < cap) { pair_p[k] = (int32_t)a; pair_c[k] = (int32_t)i; }
+                k++;
+            }
+            if (!pass) cnt[t + 1] = k;
+        }
+    }
+    int64_t total = cnt[nsel];
+    free(cnt);
+    return total;
+}
+
+int64_t orc_pairs_for_particles(int64_t n, const double *xyz, const double *h, const orc_cells *C, int64_t nsel,
+                                const int32_t *sel, int32_t *pair_p, int32_t *pair_c, int64_t cap)
+{
+    int64_t nc = C->n_cells;
+    double *bb = (double *)malloc(sizeof(double) * 6 * (nc > 0 ? nc : 1));
+    for (int64_t i = 0; i < nc; i++) cell_box(C, i, bb + 6 * i, bb + 6 * i + 3);
+    int64_t total = 0;
+    for (int64_t t = 0; t < nsel; t++) {
+        int64_t a = sel[t];
+        if (a < 0 || a >= n) continue;
+        const double *p = xyz + 3 * a;
+        for (int64_t i = 0; i < nc; i++) {
+            if (!box_near(p, 2.0 * h[a], bb + 6 * i, bb + 6 * i + 3)) continue;
+            if (!meets(p, h[a], C, i)) continue;
+            if (pair_p && total < cap) { pair_p[total] = (int32_t)a; pair_c[total] = (int32_t)i; }
+            total++;
+        }
+    }
+    free(bb);
     return total;
 }
 

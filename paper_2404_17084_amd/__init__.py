@@ -1,0 +1,296 @@
+"""Python binding of libexactmap (MI355X Exact mapping of SPH particles onto cells).
+
+Argument marshalling only: every step of the mapping runs in the HIP library.
+The functions keep the C ABI's names (``map_init``, ``map_pairs``,
+``map_particles``, ...).  Host inputs are numpy arrays; device inputs are torch
+CUDA tensors (torch is used only for device memory).  If the built library is
+missing this module raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libexactmap.so")
+
+MAP_OK = 0
+MAP_EINVAL = -1
+MAP_ENOMEM = -2
+MAP_EDEVICE = -3
+MAP_EBUSY = -4
+MAP_ENOTFOUND = -5
+MAP_EGEOM = -6
+MAP_ENUMERIC = -7
+MAP_FP64 = 0
+MAP_MIXED = 1
+MAP_MEM_HOST = 0
+MAP_MEM_DEVICE = 1
+JOB_PENDING, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
+
+_ERRNAMES = {v: k for k, v in dict(MAP_EINVAL=-1, MAP_ENOMEM=-2, MAP_EDEVICE=-3, MAP_EBUSY=-4, MAP_ENOTFOUND=-5,
+                                   MAP_EGEOM=-6, MAP_ENUMERIC=-7).items()}
+
+c_i64, c_i32, c_int, c_dbl, c_vp, c_u64 = (ctypes.c_int64, ctypes.c_int32, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_void_p, ctypes.c_uint64)
+
+
+class map_config(ctypes.Structure):
+    _fields_ = [("device", c_int), ("precision", c_int), ("hbm_budget_bytes", c_u64), ("max_jobs", c_int),
+                ("max_queue", c_int), ("tune_cache_path", ctypes.c_char_p)]
+
+
+class map_particles_in(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("xyz", c_vp), ("m", c_vp), ("h", c_vp), ("mem_kind", c_int)]
+
+
+class map_cells_in(ctypes.Structure):
+    _fields_ = [("n_cells", c_i64), ("n_faces", c_i64), ("n_face_verts", c_i64), ("n_verts", c_i64),
+                ("cell_face_off", c_vp), ("face_vert_off", c_vp), ("face_vert", c_vp), ("face_plane", c_vp),
+                ("verts", c_vp), ("cell_volume", c_vp), ("box", c_dbl * 6), ("mem_kind", c_int)]
+
+
+class map_stats(ctypes.Structure):
+    _fields_ = [("n_pairs", c_i64), ("n_candidates", c_i64), ("n_edge_terms", c_i64), ("n_fixup_terms", c_i64),
+                ("n_face_visits", c_i64), ("n_edge_visits", c_i64), ("n_moment_evals", c_i64),
+                ("n_quad_intervals", c_i64), ("n_angle_evals", c_i64),
+                ("mass_in", c_dbl), ("mass_out", c_dbl), ("max_abs_S_minus_1", c_dbl), ("ms_setup", c_dbl),
+                ("ms_pairs", c_dbl), ("ms_integrate", c_dbl), ("ms_fixup", c_dbl), ("ms_reduce", c_dbl),
+                ("ms_total", c_dbl)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class map_out(ctypes.Structure):
+    _fields_ = [("cell_mass", c_vp), ("cell_density", c_vp), ("frac_sum_raw", c_vp), ("pair_frac", c_vp),
+                ("pair_p", c_vp), ("pair_c", c_vp), ("pair_capacity", c_i64), ("mem_kind", c_int),
+                ("stats", ctypes.POINTER(map_stats))]
+
+
+class MapError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "map_init": (c_int, [ctypes.POINTER(map_config), ctypes.POINTER(c_vp)]),
+    "map_shutdown": (c_int, [c_vp]),
+    "map_last_error": (ctypes.c_char_p, [c_vp]),
+    "map_set_precision": (c_int, [c_vp, c_int]),
+    "map_set_tune": (c_int, [c_vp, c_int, c_int, c_int, c_int]),
+    "map_get_tune": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "map_pairs": (c_int, [c_vp, ctypes.POINTER(map_particles_in), ctypes.POINTER(map_cells_in), c_vp, c_vp, c_vp,
+                          c_i64]),
+    "map_particles": (c_int, [c_vp, ctypes.POINTER(map_particles_in), ctypes.POINTER(map_cells_in),
+                              ctypes.POINTER(map_out)]),
+}
+
+
+def load():
+    """Load the built library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libexactmap is not built ({LIB_PATH}); run __graft_entry__.build() first")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            if hasattr(lib, name):
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(ctx, rc):
+    if rc != MAP_OK:
+        msg = load().map_last_error(ctx) if ctx else b""
+        raise MapError(rc, (msg or b"").decode())
+
+
+# ---------------------------------------------------------------- marshalling
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if _is_torch(x):
+        assert x.is_contiguous()
+        return x.data_ptr()
+    assert isinstance(x, np.ndarray) and x.flags["C_CONTIGUOUS"]
+    return x.ctypes.data
+
+
+def _kind(x):
+    return MAP_MEM_DEVICE if (_is_torch(x) and x.is_cuda) else MAP_MEM_HOST
+
+
+@dataclass
+class _Keep:
+    """Holds contiguous arrays alive for the duration of a call."""
+    items: list
+
+
+def particles_in(xyz, m, h):
+    keep = []
+
+    def prep(a, dt):
+        if _is_torch(a):
+            a = a.contiguous()
+        else:
+            a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a
+
+    xyz, m, h = prep(xyz, np.float64), prep(m, np.float64), prep(h, np.float64)
+    n = int(h.shape[0])
+    s = map_particles_in(n, _ptr(xyz), _ptr(m), _ptr(h), _kind(xyz))
+    return s, _Keep(keep)
+
+
+def cells_in(cells, device_arrays=None):
+    """cells: a synth.Cells (host) or an object with the same fields as torch tensors (device)."""
+    keep = []
+
+    def prep(a, dt):
+        if a is None:
+            return None
+        if _is_torch(a):
+            a = a.contiguous()
+        else:
+            a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a
+
+    cfo = prep(cells.cell_face_off, np.int64)
+    fvo = prep(cells.face_vert_off, np.int64)
+    fv = prep(cells.face_vert, np.int32)
+    plane = prep(cells.face_plane, np.float64)
+    verts = prep(cells.verts, np.float64)
+    vol = prep(getattr(cells, "cell_volume", None), np.float64)
+    box = (c_dbl * 6)(*[float(b) for b in cells.box])
+    s = map_cells_in(int(cfo.shape[0]) - 1, int(plane.shape[0]), int(fv.shape[0]), int(verts.shape[0]), _ptr(cfo),
+                     _ptr(fvo), _ptr(fv), _ptr(plane), _ptr(verts), _ptr(vol), box, _kind(cfo))
+    return s, _Keep(keep)
+
+
+# ---------------------------------------------------------------- ABI-named wrappers
+def map_init(device: int = 0, precision: int = MAP_FP64, hbm_budget_bytes: int = 0, max_jobs: int = 0,
+             max_queue: int = 0, tune_cache_path: str | None = None):
+    lib = load()
+    cfg = map_config(device, precision, hbm_budget_bytes, max_jobs, max_queue,
+                     tune_cache_path.encode() if tune_cache_path else None)
+    ctx = c_vp()
+    _check(None, lib.map_init(ctypes.byref(cfg), ctypes.byref(ctx)))
+    return ctx
+
+
+def map_shutdown(ctx):
+    _check(None, load().map_shutdown(ctx))
+
+
+def map_last_error(ctx) -> str:
+    return (load().map_last_error(ctx) or b"").decode()
+
+
+def map_set_precision(ctx, precision: int):
+    _check(ctx, load().map_set_precision(ctx, precision))
+
+
+def map_set_tune(ctx, block=256, tile_waves=1, grid_per_cu=8, persistent=1):
+    _check(ctx, load().map_set_tune(ctx, block, tile_waves, grid_per_cu, persistent))
+
+
+def map_get_tune(ctx):
+    v = [c_int() for _ in range(4)]
+    _check(ctx, load().map_get_tune(ctx, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def map_pairs(ctx, xyz, m, h, cells, want_pairs: bool = True):
+    """Exact pair set sorted by (cell, particle): returns (pair_p, pair_c) int32, or the count."""
+    lib = load()
+    P, k1 = particles_in(xyz, m, h)
+    C, k2 = cells_in(cells)
+    n = c_i64()
+    _check(ctx, lib.map_pairs(ctx, ctypes.byref(P), ctypes.byref(C), ctypes.byref(n), None, None, 0))
+    if not want_pairs:
+        return int(n.value)
+    pp = np.zeros(n.value, np.int32)
+    pc = np.zeros(n.value, np.int32)
+    _check(ctx, lib.map_pairs(ctx, ctypes.byref(P), ctypes.byref(C), ctypes.byref(n), _ptr(pp), _ptr(pc),
+                              pp.size))
+    return pp, pc
+
+
+def map_particles(ctx, xyz, m, h, cells, cell_mass=None, cell_density=None, frac_sum_raw=None, pair_frac=None,
+                  pair_p=None, pair_c=None):
+    """Synchronous mapping.  Output arrays (numpy or torch CUDA, all of one kind) are
+    filled in place when given.  Returns the statistics as a dict."""
+    lib = load()
+    P, k1 = particles_in(xyz, m, h)
+    C, k2 = cells_in(cells)
+    st = map_stats()
+    outs = [x for x in (cell_mass, cell_density, frac_sum_raw, pair_frac, pair_p, pair_c) if x is not None]
+    kind = _kind(outs[0]) if outs else MAP_MEM_HOST
+    cap = 0
+    for x in (pair_frac, pair_p, pair_c):
+        if x is not None:
+            cap = int(x.shape[0]) if cap == 0 else min(cap, int(x.shape[0]))
+    O = map_out(_ptr(cell_mass), _ptr(cell_density), _ptr(frac_sum_raw), _ptr(pair_frac), _ptr(pair_p),
+                _ptr(pair_c), cap, kind, ctypes.pointer(st))
+    _check(ctx, lib.map_particles(ctx, ctypes.byref(P), ctypes.byref(C), ctypes.byref(O)))
+    return st.as_dict()
+
+
+class Mapper:
+    """Owns one library context."""
+
+    def __init__(self, device: int = 0, precision: int = MAP_FP64, **kw):
+        self.ctx = map_init(device, precision, **kw)
+
+    def close(self):
+        if self.ctx:
+            map_shutdown(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_precision(self, precision):
+        map_set_precision(self.ctx, precision)
+
+    def pairs(self, particles, cells):
+        return map_pairs(self.ctx, particles.xyz, particles.m, particles.h, cells)
+
+    def map(self, particles, cells, want_pairs=False):
+        """Host convenience: returns dict with M, rho, S (and per-pair data if asked)."""
+        nc = cells.cell_face_off.shape[0] - 1
+        M = np.zeros(nc)
+        rho = np.zeros(nc)
+        S = np.zeros(particles.h.shape[0])
+        res = {}
+        if want_pairs:
+            npairs = map_pairs(self.ctx, particles.xyz, particles.m, particles.h, cells, want_pairs=False)
+            f = np.zeros(npairs)
+            pp = np.zeros(npairs, np.int32)
+            pc = np.zeros(npairs, np.int32)
+            st = map_particles(self.ctx, particles.xyz, particles.m, particles.h, cells, M, rho, S, f, pp, pc)
+            res.update(f=f, pair_p=pp, pair_c=pc)
+        else:
+            st = map_particles(self.ctx, particles.xyz, particles.m, particles.h, cells, M, rho, S)
+        res.update(M=M, rho=rho, S=S, stats=st)
+        return res

@@ -1,0 +1,412 @@
+// C ABI of the Exact-mapping library: context, input staging, the synchronous
+// mapping pipeline and its statistics.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+
+#include "em_internal.h"
+#include "em_runtime.h"
+
+using namespace em;
+
+namespace em {
+
+Ctx::Ctx(const map_config *cfg) : ws(cfg ? cfg->device : 0)
+{
+    device = cfg ? cfg->device : 0;
+    precision = cfg ? cfg->precision : MAP_FP64;
+    if (cfg) config = *cfg;
+    EM_HIP(hipSetDevice(device));
+    EM_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+    for (auto &e : ev) EM_HIP(hipEventCreate(&e));
+}
+
+Ctx::~Ctx()
+{
+    (void)hipSetDevice(device);
+    if (stream) (void)hipStreamSynchronize(stream);
+    ws.release();
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (stream) (void)hipStreamDestroy(stream);
+}
+
+static const char *flag_text(unsigned f)
+{
+    if (f & F_CFO_BAD) return "cell_face_off is not a valid offset array (each cell needs >= 4 faces)";
+    if (f & F_FVO_BAD) return "face_vert_off is not a valid offset array";
+    if (f & F_FACE_SMALL) return "a face has fewer than 3 vertices";
+    if (f & F_VID_RANGE) return "face_vert holds a vertex id out of range";
+    if (f & F_PLANE_BAD) return "a face plane is not finite or its normal is not of unit length";
+    if (f & F_VERT_NONFINITE) return "a vertex coordinate is not finite";
+    if (f & F_VOL_BAD) return "a cell volume is not finite and positive";
+    if (f & F_PART_NONFINITE) return "a particle position is not finite";
+    if (f & F_H_NONPOS) return "a smoothing length is not finite and positive";
+    if (f & F_M_BAD) return "a particle mass is not finite and non-negative";
+    if (f & F_RESULT_NONFINITE) return "non-finite cell mass";
+    return "invalid input";
+}
+
+static int flag_code(unsigned f)
+{
+    if (f & (F_CFO_BAD | F_FVO_BAD | F_FACE_SMALL | F_VID_RANGE | F_PLANE_BAD | F_VERT_NONFINITE | F_VOL_BAD))
+        return MAP_EGEOM;
+    if (f & F_RESULT_NONFINITE) return MAP_ENUMERIC;
+    return MAP_EINVAL;
+}
+
+template <typename T>
+static const T *stage(Workspace &ws, int slot, const T *src, int64_t count, int mem_kind, hipStream_t s)
+{
+    if (count <= 0) return ws.get<T>(slot, 1);
+    if (mem_kind == MAP_MEM_DEVICE) return src;
+    T *dst = ws.get<T>(slot, (size_t)count);
+    EM_HIP(hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyHostToDevice, s));
+    return dst;
+}
+
+void check_host_args(const map_particles_in *p, const map_cells_in *c)
+{
+    EM_CHECK(p && c, MAP_EINVAL, "null particle or cell descriptor");
+    EM_CHECK(p->n >= 0, MAP_EINVAL, "particle count is negative");
+    EM_CHECK(c->n_cells >= 0 && c->n_faces >= 0 && c->n_face_verts >= 0 && c->n_verts >= 0, MAP_EGEOM,
+             "negative geometry size");
+    EM_CHECK(p->n < (int64_t)INT32_MAX && c->n_cells < (int64_t)INT32_MAX && c->n_verts < (int64_t)INT32_MAX,
+             MAP_EINVAL, "particle, cell or vertex count above 2^31-1");
+    EM_CHECK(p->mem_kind == MAP_MEM_HOST || p->mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad particle mem_kind");
+    EM_CHECK(c->mem_kind == MAP_MEM_HOST || c->mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad cell mem_kind");
+    if (p->n > 0) EM_CHECK(p->xyz && p->m && p->h, MAP_EINVAL, "null particle array");
+    EM_CHECK(c->cell_face_off && c->face_vert_off, MAP_EGEOM, "null offset array");
+    if (c->n_faces > 0) EM_CHECK(c->face_plane, MAP_EGEOM, "null face_plane");
+    if (c->n_face_verts > 0) EM_CHECK(c->face_vert, MAP_EGEOM, "null face_vert");
+    if (c->n_verts > 0) EM_CHECK(c->verts, MAP_EGEOM, "null verts");
+    for (int d = 0; d < 3; d++)
+        EM_CHECK(std::isfinite(c->box[d]) && std::isfinite(c->box[3 + d]) && c->box[3 + d] > c->box[d], MAP_EGEOM,
+                 "box must be finite with hi > lo");
+    // host-resident offsets can be checked here; device ones are checked on the device
+    if (c->mem_kind == MAP_MEM_HOST) {
+        EM_CHECK(c->cell_face_off[0] == 0 && c->cell_face_off[c->n_cells] == c->n_faces, MAP_EGEOM,
+                 "cell_face_off must start at 0 and end at n_faces");
+        EM_CHECK(c->face_vert_off[0] == 0 && c->face_vert_off[c->n_faces] == c->n_face_verts, MAP_EGEOM,
+                 "face_vert_off must start at 0 and end at n_face_verts");
+    }
+}
+
+// Stage inputs, validate them on the device, build geometry tables.
+void prepare(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_in *c, DevInputs &in, EdgeRec *&edges,
+             double *&aabb, unsigned *&flags, int64_t *&counters, hipStream_t s)
+{
+    check_host_args(p, c);
+    in.n = p->n;
+    in.n_cells = c->n_cells;
+    in.n_faces = c->n_faces;
+    in.n_face_verts = c->n_face_verts;
+    in.n_verts = c->n_verts;
+    for (int d = 0; d < 6; d++) in.box[d] = c->box[d];
+    in.xyz = stage(ws, S_XYZ, p->xyz, 3 * p->n, p->mem_kind, s);
+    in.m = stage(ws, S_M, p->m, p->n, p->mem_kind, s);
+    in.h = stage(ws, S_H, p->h, p->n, p->mem_kind, s);
+    in.cfo = stage(ws, S_CFO, c->cell_face_off, c->n_cells + 1, c->mem_kind, s);
+    in.fvo = stage(ws, S_FVO, c->face_vert_off, c->n_faces + 1, c->mem_kind, s);
+    in.fv = stage(ws, S_FV, c->face_vert, c->n_face_verts, c->mem_kind, s);
+    in.plane = stage(ws, S_PLANE, c->face_plane, 4 * c->n_faces, c->mem_kind, s);
+    in.verts = stage(ws, S_VERTS, c->verts, 3 * c->n_verts, c->mem_kind, s);
+    in.vol = c->cell_volume ? stage(ws, S_VOL, c->cell_volume, c->n_cells, c->mem_kind, s) : nullptr;
+
+    flags = ws.get<unsigned>(S_FLAGS, 4);
+    counters = ws.get<int64_t>(S_COUNTERS, C_NUM);
+    fill_zero_bytes(flags, sizeof(unsigned) * 4, s);
+    fill_zero_bytes(counters, sizeof(int64_t) * C_NUM, s);
+    launch_validate(in, flags, s);
+    unsigned hf = 0;
+    EM_HIP(hipMemcpyAsync(&hf, flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    EM_HIP(hipStreamSynchronize(s));
+    EM_CHECK(hf == 0, flag_code(hf), flag_text(hf));
+
+    edges = ws.get<EdgeRec>(S_EDGE, (size_t)(c->n_face_verts > 0 ? c->n_face_verts : 1));
+    aabb = ws.get<double>(S_AABB, (size_t)(6 * (c->n_cells > 0 ? c->n_cells : 1)));
+    double *vol_out = nullptr;
+    if (!in.vol) {
+        vol_out = ws.get<double>(S_VOL, (size_t)(c->n_cells > 0 ? c->n_cells : 1));
+        in.vol = vol_out;
+    }
+    launch_geometry(in, edges, aabb, vol_out, s);
+    (void)C;
+}
+
+template <typename T>
+static void copy_out(T *dst, const T *src, int64_t count, int mem_kind, hipStream_t s)
+{
+    if (!dst || count <= 0) return;
+    EM_HIP(hipMemcpyAsync(dst, src, sizeof(T) * count,
+                          mem_kind == MAP_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+}
+
+__global__ void k_u32_to_i32(const uint32_t *in, int32_t *out, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (int32_t)in[i];
+}
+
+// The whole mapping of one job on stream s with workspace ws.
+void run_mapping(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_in *c, const map_out *out,
+                 int precision, hipStream_t s, bool timed)
+{
+    EM_CHECK(precision == MAP_FP64 || precision == MAP_MIXED, MAP_EINVAL, "precision must be MAP_FP64 or MAP_MIXED");
+    if (timed) EM_HIP(hipEventRecord(C.ev[0], s));
+    DevInputs in;
+    EdgeRec *edges;
+    double *aabb;
+    unsigned *flags;
+    int64_t *counters;
+    prepare(C, ws, p, c, in, edges, aabb, flags, counters, s);
+    if (timed) EM_HIP(hipEventRecord(C.ev[1], s));
+    PairSet ps = build_pairs(ws, in, aabb, counters, s);
+    if (timed) EM_HIP(hipEventRecord(C.ev[2], s));
+    const int64_t np = ps.n_pairs;
+    double *f = ws.get<double>(S_F, (size_t)(np > 0 ? np : 1));
+    uint32_t *tile_ctr = ws.get<uint32_t>(S_TILE_CTR, 64);
+    const int64_t fix_cap = np / 8 + 65536;
+    uint64_t *fix_items = ws.get<uint64_t>(S_FIX_ITEMS, (size_t)fix_cap);
+    launch_integrate(in, edges, ps, precision, C.tune, f, counters, tile_ctr, fix_items, fix_cap, s);
+    if (timed) EM_HIP(hipEventRecord(C.ev[3], s));
+    int64_t n_fix = 0;
+    if (precision == MAP_MIXED && np > 0) {
+        unsigned hfix = 0;
+        EM_HIP(hipMemcpyAsync(&hfix, tile_ctr + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        EM_HIP(hipStreamSynchronize(s));
+        n_fix = hfix;
+        if (n_fix > fix_cap) {
+            // too many flagged edges for the fixup list: redo every pair in FP64
+            launch_integrate(in, edges, ps, MAP_FP64, C.tune, f, counters, tile_ctr, fix_items, fix_cap, s);
+        } else if (n_fix > 0) {
+            uint32_t *iv = ws.get<uint32_t>(S_FIX_VAL2, (size_t)n_fix);
+            uint64_t *k2 = ws.get<uint64_t>(S_FIX_KEY2, (size_t)n_fix);
+            uint32_t *v2 = reinterpret_cast<uint32_t *>(ws.get<uint64_t>(S_FIX_VALS, (size_t)n_fix * 2));
+            fill_iota_u32(iv, n_fix, s);
+            radix_sort_u64(ws, fix_items, iv, k2, v2, n_fix, 64, s);
+            double *fv = reinterpret_cast<double *>(k2);
+            launch_fixup(in, edges, ps, fix_items, n_fix, fv, s);
+            launch_fixup_apply(fix_items, fv, n_fix, f, s);
+        }
+    }
+    if (timed) EM_HIP(hipEventRecord(C.ev[4], s));
+    double *f_pm = ws.get<double>(S_F_PM, (size_t)(np > 0 ? np : 1));
+    double *S = ws.get<double>(S_S, (size_t)(in.n > 0 ? in.n : 1));
+    double *M = ws.get<double>(S_MCELL, (size_t)(in.n_cells > 0 ? in.n_cells : 1));
+    double *rho = ws.get<double>(S_RHO, (size_t)(in.n_cells > 0 ? in.n_cells : 1));
+    double *red = ws.get<double>(S_RED, 16 + 4 * 256);
+    EM_HIP(hipMemcpyAsync(red + 4, in.box, sizeof(double) * 6, hipMemcpyHostToDevice, s));
+    launch_reduce(in, ps, f, f_pm, S, M, rho, red, flags, s);
+    if (timed) EM_HIP(hipEventRecord(C.ev[5], s));
+
+    // outputs
+    copy_out(out->cell_mass, (const double *)M, in.n_cells, out->mem_kind, s);
+    copy_out(out->cell_density, (const double *)rho, in.n_cells, out->mem_kind, s);
+    copy_out(out->frac_sum_raw, (const double *)S, in.n, out->mem_kind, s);
+    if (out->pair_capacity > 0 && np > 0) {
+        int64_t cnt = np < out->pair_capacity ? np : out->pair_capacity;
+        copy_out(out->pair_frac, (const double *)f, cnt, out->mem_kind, s);
+        if (out->pair_p || out->pair_c) {
+            int32_t *tmp = reinterpret_cast<int32_t *>(ws.get<uint32_t>(S_KEY2, (size_t)np));
+            if (out->pair_p) {
+                hipLaunchKernelGGL(k_u32_to_i32, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, ps.pair_p, tmp,
+                                   cnt);
+                copy_out(out->pair_p, (const int32_t *)tmp, cnt, out->mem_kind, s);
+            }
+            if (out->pair_c) {
+                EM_HIP(hipStreamSynchronize(s));
+                hipLaunchKernelGGL(k_u32_to_i32, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, ps.pair_c, tmp,
+                                   cnt);
+                copy_out(out->pair_c, (const int32_t *)tmp, cnt, out->mem_kind, s);
+            }
+        }
+    }
+    double hred[4] = {0, 0, 0, 0};
+    int64_t hcnt[C_NUM];
+    unsigned hf = 0;
+    EM_HIP(hipMemcpyAsync(hred, red, sizeof(hred), hipMemcpyDeviceToHost, s));
+    EM_HIP(hipMemcpyAsync(hcnt, counters, sizeof(hcnt), hipMemcpyDeviceToHost, s));
+    EM_HIP(hipMemcpyAsync(&hf, flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    EM_HIP(hipStreamSynchronize(s));
+    EM_CHECK(hf == 0, flag_code(hf), flag_text(hf));
+    if (out->stats) {
+        map_stats &st = *out->stats;
+        std::memset(&st, 0, sizeof(st));
+        st.n_pairs = np;
+        st.n_candidates = hcnt[C_CANDIDATES];
+        st.n_edge_terms = hcnt[C_EDGE_TERMS];
+        st.n_fixup_terms = n_fix;
+        st.n_face_visits = hcnt[C_FACES];
+        st.n_edge_visits = hcnt[C_EDGES];
+        st.n_moment_evals = hcnt[C_MOMENTS];
+        st.n_quad_intervals = hcnt[C_QUADS];
+        st.n_angle_evals = hcnt[C_ANGLES];
+        st.mass_out = hred[0];
+        st.max_abs_S_minus_1 = hred[1];
+        st.mass_in = hred[2];
+        if (timed) {
+            float t;
+            EM_HIP(hipEventElapsedTime(&t, C.ev[0], C.ev[1]));
+            st.ms_setup = t;
+            EM_HIP(hipEventElapsedTime(&t, C.ev[1], C.ev[2]));
+            st.ms_pairs = t;
+            EM_HIP(hipEventElapsedTime(&t, C.ev[2], C.ev[3]));
+            st.ms_integrate = t;
+            EM_HIP(hipEventElapsedTime(&t, C.ev[3], C.ev[4]));
+            st.ms_fixup = t;
+            EM_HIP(hipEventElapsedTime(&t, C.ev[4], C.ev[5]));
+            st.ms_reduce = t;
+            EM_HIP(hipEventElapsedTime(&t, C.ev[0], C.ev[5]));
+            st.ms_total = t;
+        }
+    }
+}
+
+}  // namespace em
+
+// ---------------------------------------------------------------- C ABI
+#define API_BODY(ctx, body)                          \
+    do {                                             \
+        if (!(ctx)) return MAP_EINVAL;               \
+        std::lock_guard<std::mutex> _g((ctx)->mu);   \
+        try {                                        \
+            EM_HIP(hipSetDevice((ctx)->device));     \
+            body;                                    \
+            (ctx)->err.clear();                      \
+            return MAP_OK;                           \
+        } catch (const em::Error &e) {               \
+            (ctx)->err = e.msg;                      \
+            return e.code;                           \
+        } catch (const std::bad_alloc &) {           \
+            (ctx)->err = "host allocation failed";   \
+            return MAP_ENOMEM;                       \
+        } catch (const std::exception &e) {          \
+            (ctx)->err = e.what();                   \
+            return MAP_EDEVICE;                      \
+        }                                            \
+    } while (0)
+
+extern "C" {
+
+int map_init(const map_config *cfg, map_ctx **out)
+{
+    if (!out) return MAP_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return MAP_EDEVICE;
+    }
+    int dev = cfg ? cfg->device : 0;
+    if (dev < 0 || dev >= ndev) return MAP_EINVAL;
+    if (cfg && cfg->precision != MAP_FP64 && cfg->precision != MAP_MIXED) return MAP_EINVAL;
+    try {
+        *out = reinterpret_cast<map_ctx *>(new Ctx(cfg));
+    } catch (const em::Error &e) {
+        return e.code;
+    } catch (...) {
+        return MAP_EDEVICE;
+    }
+    return MAP_OK;
+}
+
+int map_shutdown(map_ctx *h)
+{
+    if (!h) return MAP_EINVAL;
+    Ctx *C = reinterpret_cast<Ctx *>(h);
+    serve_stop(*C);
+    delete C;
+    return MAP_OK;
+}
+
+const char *map_last_error(map_ctx *h)
+{
+    if (!h) return "null context";
+    return reinterpret_cast<Ctx *>(h)->err.c_str();
+}
+
+int map_set_precision(map_ctx *h, int precision)
+{
+    Ctx *C = reinterpret_cast<Ctx *>(h);
+    API_BODY(C, {
+        EM_CHECK(precision == MAP_FP64 || precision == MAP_MIXED, MAP_EINVAL, "precision must be MAP_FP64 or MAP_MIXED");
+        C->precision = precision;
+    });
+}
+
+int map_set_tune(map_ctx *h, int block, int tile_waves, int grid_per_cu, int persistent)
+{
+    Ctx *C = reinterpret_cast<Ctx *>(h);
+    API_BODY(C, {
+        EM_CHECK(block == 256, MAP_EINVAL, "block must be 256");
+        EM_CHECK(tile_waves >= 1 && tile_waves <= 64, MAP_EINVAL, "tile_waves must be in [1, 64]");
+        EM_CHECK(grid_per_cu >= 1 && grid_per_cu <= 64, MAP_EINVAL, "grid_per_cu must be in [1, 64]");
+        C->tune.block = block;
+        C->tune.tile_waves = tile_waves;
+        C->tune.grid_per_cu = grid_per_cu;
+        C->tune.persistent = persistent ? 1 : 0;
+    });
+}
+
+int map_get_tune(map_ctx *h, int *block, int *tile_waves, int *grid_per_cu, int *persistent)
+{
+    Ctx *C = reinterpret_cast<Ctx *>(h);
+    API_BODY(C, {
+        if (block) *block = C->tune.block;
+        if (tile_waves) *tile_waves = C->tune.tile_waves;
+        if (grid_per_cu) *grid_per_cu = C->tune.grid_per_cu;
+        if (persistent) *persistent = C->tune.persistent;
+    });
+}
+
+int map_pairs(map_ctx *h, const map_particles_in *p, const map_cells_in *c, int64_t *n_pairs, int32_t *pair_p,
+              int32_t *pair_c, int64_t capacity)
+{
+    Ctx *C = reinterpret_cast<Ctx *>(h);
+    API_BODY(C, {
+        EM_CHECK(n_pairs, MAP_EINVAL, "n_pairs is null");
+        EM_CHECK(capacity >= 0, MAP_EINVAL, "negative capacity");
+        hipStream_t s = C->stream;
+        DevInputs in;
+        EdgeRec *edges;
+        double *aabb;
+        unsigned *flags;
+        int64_t *counters;
+        prepare(*C, C->ws, p, c, in, edges, aabb, flags, counters, s);
+        PairSet ps = build_pairs(C->ws, in, aabb, counters, s);
+        *n_pairs = ps.n_pairs;
+        int64_t cnt = ps.n_pairs < capacity ? ps.n_pairs : capacity;
+        if (cnt > 0 && (pair_p || pair_c)) {
+            int32_t *tmp = reinterpret_cast<int32_t *>(C->ws.get<uint32_t>(S_KEY2, (size_t)ps.n_pairs));
+            if (pair_p) {
+                hipLaunchKernelGGL(k_u32_to_i32, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, ps.pair_p, tmp,
+                                   cnt);
+                EM_HIP(hipMemcpyAsync(pair_p, tmp, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, s));
+                EM_HIP(hipStreamSynchronize(s));
+            }
+            if (pair_c) {
+                hipLaunchKernelGGL(k_u32_to_i32, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, ps.pair_c, tmp,
+                                   cnt);
+                EM_HIP(hipMemcpyAsync(pair_c, tmp, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, s));
+            }
+        }
+        EM_HIP(hipStreamSynchronize(s));
+    });
+}
+
+int map_particles(map_ctx *h, const map_particles_in *p, const map_cells_in *c, map_out *out)
+{
+    Ctx *C = reinterpret_cast<Ctx *>(h);
+    API_BODY(C, {
+        EM_CHECK(out, MAP_EINVAL, "null output descriptor");
+        EM_CHECK(out->mem_kind == MAP_MEM_HOST || out->mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad output mem_kind");
+        run_mapping(*C, C->ws, p, c, out, C->precision, C->stream, true);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,180 @@
+// Input validation and per-cell geometry tables (edge records, bounding boxes,
+// volumes).  Geometry is kept in FP64.
+#include <cmath>
+
+#include "em_internal.h"
+
+namespace em {
+
+// Structure checks: only reads offsets and ids at fixed indices, so malformed
+// input cannot make it read out of bounds.
+__global__ void k_validate_structure(int64_t n_cells, int64_t n_faces, int64_t n_face_verts, int64_t n_verts,
+                                     const int64_t *cfo, const int64_t *fvo, const int32_t *fv, unsigned *flags)
+{
+    int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned f = 0;
+    for (int64_t i = tid; i <= n_cells; i += stride) {
+        int64_t a = cfo[i];
+        if (i == 0 && a != 0) f |= F_CFO_BAD;
+        if (i == n_cells && a != n_faces) f |= F_CFO_BAD;
+        if (i < n_cells) {
+            int64_t b = cfo[i + 1];
+            if (b - a < 4 || a < 0 || b > n_faces) f |= F_CFO_BAD;
+        }
+    }
+    for (int64_t j = tid; j <= n_faces; j += stride) {
+        int64_t a = fvo[j];
+        if (j == 0 && a != 0) f |= F_FVO_BAD;
+        if (j == n_faces && a != n_face_verts) f |= F_FVO_BAD;
+        if (j < n_faces) {
+            int64_t b = fvo[j + 1];
+            if (a < 0 || b > n_face_verts || b < a) f |= F_FVO_BAD;
+            else if (b - a < 3) f |= F_FACE_SMALL;
+        }
+    }
+    for (int64_t s = tid; s < n_face_verts; s += stride) {
+        int32_t v = fv[s];
+        if (v < 0 || (int64_t)v >= n_verts) f |= F_VID_RANGE;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+__global__ void k_validate_values(int64_t n, const double *xyz, const double *m, const double *h, int64_t n_faces,
+                                  const double *plane, int64_t n_verts, const double *verts, int64_t n_cells,
+                                  const double *vol, unsigned *flags)
+{
+    int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned f = 0;
+    for (int64_t a = tid; a < n; a += stride) {
+        double x = xyz[3 * a], y = xyz[3 * a + 1], z = xyz[3 * a + 2];
+        if (!isfinite(x) || !isfinite(y) || !isfinite(z)) f |= F_PART_NONFINITE;
+        double ha = h[a];
+        if (!(ha > 0.0) || !isfinite(ha)) f |= F_H_NONPOS;
+        double ma = m[a];
+        if (!(ma >= 0.0) || !isfinite(ma)) f |= F_M_BAD;
+    }
+    for (int64_t j = tid; j < n_faces; j += stride) {
+        double nx = plane[4 * j], ny = plane[4 * j + 1], nz = plane[4 * j + 2], c = plane[4 * j + 3];
+        double nn = nx * nx + ny * ny + nz * nz;
+        if (!isfinite(c) || !(fabs(nn - 1.0) <= 1e-10)) f |= F_PLANE_BAD;
+    }
+    for (int64_t v = tid; v < n_verts; v += stride) {
+        if (!isfinite(verts[3 * v]) || !isfinite(verts[3 * v + 1]) || !isfinite(verts[3 * v + 2]))
+            f |= F_VERT_NONFINITE;
+    }
+    if (vol)
+        for (int64_t i = tid; i < n_cells; i += stride)
+            if (!(vol[i] > 0.0) || !isfinite(vol[i])) f |= F_VOL_BAD;
+    if (f) atomicOr(flags, f);
+}
+
+void launch_validate(const DevInputs &in, unsigned *flags, hipStream_t s)
+{
+    int64_t big = in.n_face_verts;
+    if (in.n_faces > big) big = in.n_faces;
+    if (in.n_cells > big) big = in.n_cells;
+    if (in.n > big) big = in.n;
+    if (in.n_verts > big) big = in.n_verts;
+    int64_t g = (big + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_validate_structure, dim3((unsigned)g), dim3(256), 0, s, in.n_cells, in.n_faces,
+                       in.n_face_verts, in.n_verts, in.cfo, in.fvo, in.fv, flags);
+    EM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_validate_values, dim3((unsigned)g), dim3(256), 0, s, in.n, in.xyz, in.m, in.h, in.n_faces,
+                       in.plane, in.n_verts, in.verts, in.n_cells, in.vol, flags);
+    EM_HIP(hipGetLastError());
+}
+
+// One thread per face: the directed edges of the face (counter-clockwise about
+// the outward normal n) with unit direction e, in-plane inward normal m = n x e.
+__global__ void k_edge_table(int64_t n_faces, const int64_t *fvo, const int32_t *fv, const double *plane,
+                             const double *verts, EdgeRec *edges)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_faces) return;
+    double nx = plane[4 * j], ny = plane[4 * j + 1], nz = plane[4 * j + 2];
+    int64_t s0 = fvo[j], s1 = fvo[j + 1];
+    int64_t cnt = s1 - s0;
+    for (int64_t k = 0; k < cnt; k++) {
+        const double *a = verts + 3 * (int64_t)fv[s0 + k];
+        const double *b = verts + 3 * (int64_t)fv[s0 + (k + 1 == cnt ? 0 : k + 1)];
+        double ex = b[0] - a[0], ey = b[1] - a[1], ez = b[2] - a[2];
+        double L = sqrt(ex * ex + ey * ey + ez * ez);
+        double inv = L > 0.0 ? 1.0 / L : 0.0;
+        ex *= inv;
+        ey *= inv;
+        ez *= inv;
+        EdgeRec r;
+        r.vx = a[0];
+        r.vy = a[1];
+        r.vz = a[2];
+        r.L = L;
+        r.ex = ex;
+        r.ey = ey;
+        r.ez = ez;
+        r.mx = ny * ez - nz * ey;
+        r.my = nz * ex - nx * ez;
+        r.mz = nx * ey - ny * ex;
+        r.pad0 = 0.0;
+        r.pad1 = 0.0;
+        edges[s0 + k] = r;
+    }
+}
+
+// One thread per cell: bounding box and (optionally) volume from the signed
+// cone decomposition about the cell's first vertex.
+__global__ void k_cell_boxes(int64_t n_cells, const int64_t *cfo, const int64_t *fvo, const int32_t *fv,
+                             const double *plane, const double *verts, double *aabb, double *vol_out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_cells) return;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int64_t f0 = cfo[i], f1 = cfo[i + 1];
+    const double *ref = verts + 3 * (int64_t)fv[fvo[f0]];
+    double vol = 0.0;
+    for (int64_t j = f0; j < f1; j++) {
+        int64_t s0 = fvo[j], s1 = fvo[j + 1];
+        const double *v0 = verts + 3 * (int64_t)fv[s0];
+        double nx = plane[4 * j], ny = plane[4 * j + 1], nz = plane[4 * j + 2], c = plane[4 * j + 3];
+        double area2 = 0.0;
+        for (int64_t s = s0; s < s1; s++) {
+            const double *v = verts + 3 * (int64_t)fv[s];
+            for (int d = 0; d < 3; d++) {
+                lo[d] = fmin(lo[d], v[d]);
+                hi[d] = fmax(hi[d], v[d]);
+            }
+            if (s + 1 < s1 && s > s0) {
+                const double *w = verts + 3 * (int64_t)fv[s + 1];
+                double ax = v[0] - v0[0], ay = v[1] - v0[1], az = v[2] - v0[2];
+                double bx = w[0] - v0[0], by = w[1] - v0[1], bz = w[2] - v0[2];
+                area2 += (ay * bz - az * by) * nx + (az * bx - ax * bz) * ny + (ax * by - ay * bx) * nz;
+            }
+        }
+        double height = c - (nx * ref[0] + ny * ref[1] + nz * ref[2]);
+        vol += height * area2 / 6.0;
+    }
+    for (int d = 0; d < 3; d++) {
+        aabb[6 * i + d] = lo[d];
+        aabb[6 * i + 3 + d] = hi[d];
+    }
+    if (vol_out) vol_out[i] = vol;
+}
+
+void launch_geometry(const DevInputs &in, EdgeRec *edges, double *aabb, double *vol_out, hipStream_t s)
+{
+    if (in.n_faces > 0) {
+        hipLaunchKernelGGL(k_edge_table, dim3((unsigned)((in.n_faces + 255) / 256)), dim3(256), 0, s, in.n_faces,
+                           in.fvo, in.fv, in.plane, in.verts, edges);
+        EM_HIP(hipGetLastError());
+    }
+    if (in.n_cells > 0) {
+        hipLaunchKernelGGL(k_cell_boxes, dim3((unsigned)((in.n_cells + 255) / 256)), dim3(256), 0, s, in.n_cells,
+                           in.cfo, in.fvo, in.fv, in.plane, in.verts, aabb, vol_out);
+        EM_HIP(hipGetLastError());
+    }
+}
+
+}  // namespace em

@@ -1,0 +1,522 @@
+// Integration of the M4 kernel over each (particle, cell) pair, Sec. II-B.
+//
+// Far-field-subtracted form.  With lengths in units of h, the kernel mass in
+// a cone of directions up to radius s is F(s) per steradian, F(s) -> 1/(4 pi)
+// for s >= 2.  Writing F = 1/(4 pi) - F_c splits each vertex-pyramid integral
+// into a solid-angle part and a remainder that vanishes beyond the support:
+//     I(r0, R0, phi) = Omega/(4 pi) - [ Q(phi) - phi H(r0) ],
+//     Q(phi) = r0 int_0^phi G_c(S(alpha)) dalpha,   H(r0) = r0 G_c(r0),
+// where G_c' = F_c/s^2, G_c = 0 for s >= 2, and S(alpha) is the distance from
+// the particle to the edge line's point at in-plane angle alpha.  Summed with
+// the signs of the signed-cone decomposition, the solid-angle parts give the
+// winding number of the cell about the particle (1 inside, 0 outside), so
+//     f = [p inside] - (1/pi) sum_faces sigma_j { sum_edges sign(rho) [Q(l_b) - Q(l_a)] - pi H(r0) A_j },
+// with A_j the signed angle the face's edges subtend at the foot point, and
+// the per-edge Q difference taken along the edge (signed coordinate l from
+// the foot g of the projection point on the edge line).  Walls with r0 >= 2
+// and edges whose line lies beyond 2h contribute nothing to Q; such walls are
+// skipped entirely.
+//
+// pi G_c as polynomials in s (exponents -1, 0, 2, 3, 4, 5):
+//   s <= 1:      -1/(4s) + 7/20 - s^2/6 + 3 s^4/40 - s^5/40
+//   1 <= s <= 2: -4/(15s) + 2/5 - s^2/3 + s^3/4 - 3 s^4/40 + s^5/120
+//              = -(2 - s)^5 (s + 1) / (120 s)
+// and the angular moments P_n = int S^n dalpha are evaluated in closed form
+// from l (t = l/R0, S = sqrt(c^2 + l^2), c^2 = r0^2 + R0^2):
+//   r0 P_-1 = atan2(r0 l, R0 S),  P_0 = atan2(l, R0),  P_2 = r0^2 P_0 + R0 l,
+//   P_3 = (R0 l S + R0 c^2 a)/2 + r0^2 R0 a + r0^2 (r0 P_-1),  a = asinh(l/c),
+//   P_4 = r0^4 P_0 + 2 r0^2 R0 l + R0^3 l + R0 l^3/3,
+//   P_5 = R0 l (S^3/4 + 3 c^2 S/8) + 3 R0 c^4 a/8 + r0^2 P_3.
+// The M4 piece radii s = 1, 2 split the edge at l_k = sqrt(k^2 - c^2).
+#include <cmath>
+
+#include "em_internal.h"
+
+namespace em {
+
+namespace {
+
+__device__ __forceinline__ double f_log1p(double x) { return log1p(x); }
+__device__ __forceinline__ float f_log1p(float x) { return log1pf(x); }
+__device__ __forceinline__ double f_atan2(double y, double x) { return atan2(y, x); }
+__device__ __forceinline__ float f_atan2(float y, float x) { return atan2f(y, x); }
+__device__ __forceinline__ double f_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float f_sqrt(float x) { return sqrtf(x); }
+
+// Work counters of one thread (feed the algorithmic flop model).
+struct Work {
+    unsigned faces = 0, edges = 0, eterms = 0, moments = 0, quads = 0, angles = 0;
+};
+
+// pi * H(r0) = pi * r0 * G_c(r0)
+template <typename R>
+__device__ __forceinline__ R pi_H(R r0)
+{
+    if (r0 <= R(1)) {
+        R r2 = r0 * r0;
+        R r3 = r2 * r0;
+        return R(0.35) * r0 - R(0.25) - r3 * R(1.0 / 6.0) + R(0.075) * r3 * r2 - R(0.025) * r3 * r3;
+    }
+    R u = R(2) - r0;
+    R u2 = u * u;
+    return -(u2 * u2 * u) * (r0 + R(1)) * R(1.0 / 120.0);
+}
+
+// pi r0 (G_shell - G_inner)(r0) = (r0 - 1)^5 (2 r0 + 1) / 60 (zero for r0 >= 1, where G_c is the shell polynomial)
+template <typename R>
+__device__ __forceinline__ R pi_dH(R r0)
+{
+    if (!(r0 < R(1))) return R(0);
+    R u = r0 - R(1);
+    R u2 = u * u;
+    return u2 * u2 * u * (R(2) * r0 + R(1)) * R(1.0 / 60.0);
+}
+
+// angle atan(b/R0) - atan(a/R0) subtended at the foot point by the part [a, b] of the edge line
+template <typename R>
+__device__ __forceinline__ R seg_angle(R R0, R a, R b, Work &wk)
+{
+    wk.angles++;
+    return f_atan2(R0 * (b - a), R0 * R0 + a * b);
+}
+
+// Transcendentals of the closed form at x >= 0 with S = sqrt(c^2 + x^2):
+//   a = asinh(x/c), beta = P_0 - r0 P_-1 = atan(x/R0) - atan(r0 x/(R0 S)).
+template <typename R>
+struct Trans {
+    R x, S, a, beta;
+};
+
+template <typename R>
+__device__ __forceinline__ Trans<R> trans(R r0, R R0, R c2, R c, R x, R S, Work &wk)
+{
+    wk.moments++;
+    Trans<R> t;
+    t.x = x;
+    t.S = S;
+    t.a = f_log1p(x * (R(1) + x / (S + c)) / c);
+    const R R02 = R0 * R0;
+    t.beta = f_atan2(x * R0 * (R02 + x * x), (S + r0) * (R02 * S + r0 * x * x));
+    return t;
+}
+
+// Closed form of pi r0 int_0^alpha(x) [G_p(S) - G_p(r0)] dalpha for the piece
+// polynomial pi G_p = g_-1/s + g_0 + g_2 s^2 + g_3 s^3 + g_4 s^4 + g_5 s^5:
+//   -beta H_odd + r0 R0 T,  H_odd = g_-1 + g_3 r0^4 + g_5 r0^6,
+//   T = g_2 x + g_3 P3' + g_4 (2 r0^2 x + R0^2 x + x^3/3)
+//       + g_5 (x (S^3/4 + 3 c^2 S/8) + 3 c^4 a/8 + r0^2 P3'),
+//   P3' = (x S + c^2 a)/2 + r0^2 a.
+template <typename R>
+__device__ __forceinline__ R core(const Trans<R> &t, R r0, R R0, R A, R c2, R gm1, R g2, R g3, R g4, R g5)
+{
+    const R x = t.x, S = t.S, a = t.a;
+    const R Hodd = gm1 + g3 * A * A + g5 * A * A * A;
+    const R P3r = R(0.5) * (x * S + c2 * a) + A * a;
+    const R T = g2 * x + g3 * P3r + g4 * (R(2) * A * x + R0 * R0 * x + x * x * x * R(1.0 / 3.0)) +
+                g5 * (x * (S * S * S * R(0.25) + R(0.375) * c2 * S) + R(0.375) * c2 * c2 * a + A * P3r);
+    return -t.beta * Hodd + r0 * R0 * T;
+}
+
+template <typename R>
+__device__ __forceinline__ R core_inner(const Trans<R> &t, R r0, R R0, R A, R c2)
+{
+    return core<R>(t, r0, R0, A, c2, R(-0.25), R(-1.0 / 6.0), R(0), R(0.075), R(-0.025));
+}
+
+template <typename R>
+__device__ __forceinline__ R core_shell(const Trans<R> &t, R r0, R R0, R A, R c2)
+{
+    return core<R>(t, r0, R0, A, c2, R(-4.0 / 15.0), R(-1.0 / 3.0), R(0.25), R(-0.075), R(1.0 / 120.0));
+}
+
+__constant__ float kGLx[4] = {0.1834346424956498f, 0.5255324099163290f, 0.7966664774136267f, 0.9602898564975363f};
+__constant__ float kGLw[4] = {0.3626837833783620f, 0.3137066458778873f, 0.2223810344533745f, 0.1012285362903763f};
+
+__device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// shell piece by Gauss-Legendre:  pi r0 R0 int_a^b D_shell(R0^2 + l^2) dl,  a < b
+__device__ __forceinline__ float shell_quad(float r0, float R0, float c2, float dsing, float a, float b, Work &wk)
+{
+    const float V = 2.0f - r0;
+    const float V2 = V * V, V4 = V2 * V2, V5 = V4 * V;
+    const float rp1 = r0 + 1.0f;
+    const float len = b - a;
+    int nsub = (int)ceilf(len * rcp32(1.5f * dsing));
+    nsub = nsub < 1 ? 1 : (nsub > 8 ? 8 : nsub);
+    const float hl = 0.5f * len / (float)nsub;
+    float tot = 0.0f;
+    for (int k = 0; k < nsub; k++) {
+        const float mid = a + (2.0f * (float)k + 1.0f) * hl;
+        float acc = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const float xq = (q & 1) ? -kGLx[q >> 1] : kGLx[q >> 1];
+            const float l = mid + hl * xq;
+            const float S = sqrtf(c2 + l * l);
+            const float U = 2.0f - S;
+            const float U2 = U * U;
+            const float Sig = (((U + V) * U + V2) * U + V2 * V) * U + V4;
+            const float num = rp1 * (r0 * Sig + V5) - r0 * U2 * U2 * U;
+            acc += kGLw[q >> 1] * num * rcp32(S * (S + r0));
+        }
+        tot += acc * hl;
+    }
+    wk.quads += nsub;
+    return tot * R0 * (1.0f / 120.0f);
+}
+
+// Shell-piece integral over [a, b] (a < b, inside |l| <= l2, S >= 1 on it):
+// FP64: the closed form (odd in l); FP32: Gauss-Legendre on the factored integrand.
+__device__ __forceinline__ double shell_part(double r0, double R0, double A, double c2, double c, double dsing,
+                                             double a, double b, const Trans<double> *t1, Work &wk)
+{
+    (void)dsing;
+    double q[2];
+    const double xs[2] = {fabs(a), fabs(b)};
+#pragma unroll
+    for (int e = 0; e < 2; e++) {
+        const double x = xs[e];
+        double v = 0.0;
+        if (x > 0.0) {
+            if (t1 && x == t1->x) {
+                v = core_shell<double>(*t1, r0, R0, A, c2);
+            } else {
+                const double S = sqrt(c2 + x * x);
+                v = core_shell<double>(trans<double>(r0, R0, c2, c, x, S, wk), r0, R0, A, c2);
+            }
+        }
+        q[e] = v;
+    }
+    return (b < 0.0 ? -q[1] : q[1]) - (a < 0.0 ? -q[0] : q[0]);
+}
+
+__device__ __forceinline__ float shell_part(float r0, float R0, float A, float c2, float c, float dsing, float a,
+                                            float b, const Trans<float> *, Work &wk)
+{
+    (void)A;
+    (void)c;
+    return shell_quad(r0, R0, c2, dsing, a, b, wk);
+}
+
+// pi [Qt(l_b) - Qt(l_a)] for one directed edge (R0 > 0), lengths in units of h:
+// the edge's whole share of pi int (G_c(S) - G_c(r0)) dalpha, split into the
+// parts of the edge line beyond the support, in the shell and in the inner ball.
+template <typename R>
+__device__ __forceinline__ R edge_term(R r0, R R0, R la, R lb, R Ht, R dH, Work &wk)
+{
+    const R A = r0 * r0;
+    const R c2 = A + R0 * R0;
+    if (!(c2 < R(4))) return -Ht * seg_angle<R>(R0, la, lb, wk);
+    wk.eterms++;
+    const R l2 = f_sqrt(R(4) - c2);
+    const R c = f_sqrt(c2);
+    R tot = R(0);
+    if (la < -l2) tot -= Ht * seg_angle<R>(R0, la, fmin(lb, -l2), wk);
+    if (lb > l2) tot -= Ht * seg_angle<R>(R0, fmax(la, l2), lb, wk);
+    if (c2 >= R(1)) {
+        const R a = fmax(la, -l2), b = fmin(lb, l2);
+        if (b > a) {
+            tot += shell_part(r0, R0, A, c2, c, c, a, b, (const Trans<R> *)nullptr, wk);
+            if (dH != R(0)) tot += dH * seg_angle<R>(R0, a, b, wk);
+        }
+        return tot;
+    }
+    const R l1 = f_sqrt(R(1) - c2);
+    const bool need1 = (la < -l1) || (lb > l1);
+    Trans<R> t1;
+    if (need1) t1 = trans<R>(r0, R0, c2, c, l1, R(1), wk);
+    // shell parts on either side of the inner ball
+    R a = fmax(la, -l2), b = fmin(lb, -l1);
+    if (b > a) {
+        tot += shell_part(r0, R0, A, c2, c, R(1), a, b, &t1, wk);
+        if (dH != R(0)) tot += dH * seg_angle<R>(R0, a, b, wk);
+    }
+    a = fmax(la, l1);
+    b = fmin(lb, l2);
+    if (b > a) {
+        tot += shell_part(r0, R0, A, c2, c, R(1), a, b, &t1, wk);
+        if (dH != R(0)) tot += dH * seg_angle<R>(R0, a, b, wk);
+    }
+    // inner part
+    a = fmax(la, -l1);
+    b = fmin(lb, l1);
+    if (b > a) {
+        R q[2];
+        const R xs[2] = {fabs(a), fabs(b)};
+#pragma unroll
+        for (int e = 0; e < 2; e++) {
+            const R x = xs[e];
+            R v = R(0);
+            if (x > R(0)) {
+                if (need1 && x == l1) v = core_inner<R>(t1, r0, R0, A, c2);
+                else v = core_inner<R>(trans<R>(r0, R0, c2, c, x, f_sqrt(c2 + x * x), wk), r0, R0, A, c2);
+            }
+            q[e] = v;
+        }
+        tot += (b < R(0) ? -q[1] : q[1]) - (a < R(0) ? -q[0] : q[0]);
+    }
+    return tot;
+}
+
+constexpr double kInvPi = 0.318309886183790671537767526745;
+
+// Conditioning test of one edge in the mixed path: true for near-degenerate
+// triangles that FP32 cannot resolve: the projection point within FP32
+// rounding of the edge line, or the wall plane, the edge line's closest
+// point or the edge itself within FP32 rounding of a piece radius (s = 1, 2)
+// of the kernel, where the FP32 piece assignment is not reliable.
+__device__ __forceinline__ bool needs_fp64(double r0, double R0, double c2)
+{
+    const double e = 9.5367431640625e-07;  // 2^-20
+    return (R0 < e * sqrt(c2)) || (fabs(r0 - 1.0) < e) || (fabs(c2 - 1.0) < e) || (fabs(c2 - 4.0) < 4.0 * e);
+}
+
+// Raw f for one pair.  PREC = MAP_FP64 or MAP_MIXED.  Wall distance, foot
+// point and edge projections are always FP64; in the mixed path the edge
+// terms are FP32 (accumulated in FP64) unless the conditioning test sends the
+// edge to the FP64 fixup pass.
+template <int PREC>
+__device__ __forceinline__ double pair_fraction(double px, double py, double pz, double h, int64_t cell,
+                                                const int64_t *__restrict__ cfo, const int64_t *__restrict__ fvo,
+                                                const double *__restrict__ plane, const EdgeRec *__restrict__ edges,
+                                                Work &wk, uint64_t pair_k, unsigned *fix_count, uint64_t *fix_items,
+                                                unsigned fix_cap)
+{
+    using R = typename std::conditional<PREC == MAP_FP64, double, float>::type;
+    const double invh = 1.0 / h;
+    bool inside = true;
+    double acc = 0.0;
+    const int64_t f0 = cfo[cell], f1 = cfo[cell + 1];
+    for (int64_t j = f0; j < f1; j++) {
+        const double nx = plane[4 * j], ny = plane[4 * j + 1], nz = plane[4 * j + 2], cj = plane[4 * j + 3];
+        const double d = cj - (nx * px + ny * py + nz * pz);
+        wk.faces++;
+        const bool in_j = d >= 0.0;
+        inside = inside && in_j;
+        const double r0d = fabs(d) * invh;
+        if (!(r0d < 2.0)) continue;
+        const R r0 = (R)r0d;
+        const R Ht = pi_H<R>(r0);
+        const R dH = pi_dH<R>(r0);
+        double face = 0.0;
+        const int64_t s0 = fvo[j], s1 = fvo[j + 1];
+        for (int64_t s = s0; s < s1; s++) {
+            const EdgeRec E = edges[s];
+            const double wx = px - E.vx, wy = py - E.vy, wz = pz - E.vz;
+            const double rho = E.mx * wx + E.my * wy + E.mz * wz;
+            wk.edges++;
+            if (rho == 0.0) continue;
+            const double la = -(E.ex * wx + E.ey * wy + E.ez * wz) * invh;
+            const double lb = la + E.L * invh;
+            const double R0d = fabs(rho) * invh;
+            if (PREC == MAP_MIXED && needs_fp64(r0d, R0d, r0d * r0d + R0d * R0d)) {
+                const unsigned slot = atomicAdd(fix_count, 1u);
+                if (slot < fix_cap) fix_items[slot] = (pair_k << 32) | (uint64_t)(uint32_t)s;
+                continue;
+            }
+            const R t = edge_term<R>(r0, (R)R0d, (R)la, (R)lb, Ht, dH, wk);
+            face += (rho > 0.0) ? (double)t : -(double)t;
+        }
+        acc += in_j ? face : -face;
+    }
+    return (inside ? 1.0 : 0.0) - acc * kInvPi;
+}
+
+// FP64 contribution of one edge to f (the fixup pass): the same terms as one
+// iteration of the FP64 edge loop, with its wall's sign.
+__device__ double edge_contribution_fp64(double px, double py, double pz, double h, const double *pl,
+                                         const EdgeRec &E)
+{
+    Work wk;
+    const double invh = 1.0 / h;
+    const double d = pl[3] - (pl[0] * px + pl[1] * py + pl[2] * pz);
+    const double r0 = fabs(d) * invh;
+    if (!(r0 < 2.0)) return 0.0;
+    const double wx = px - E.vx, wy = py - E.vy, wz = pz - E.vz;
+    const double rho = E.mx * wx + E.my * wy + E.mz * wz;
+    if (rho == 0.0) return 0.0;
+    const double la = -(E.ex * wx + E.ey * wy + E.ez * wz) * invh;
+    const double lb = la + E.L * invh;
+    const double t = edge_term<double>(r0, fabs(rho) * invh, la, lb, pi_H<double>(r0), pi_dH<double>(r0), wk);
+    const double face = (rho > 0.0) ? t : -t;
+    return -(d >= 0.0 ? face : -face) * kInvPi;
+}
+
+// wave sums of the work counters, one atomic per counter per wave
+__device__ __forceinline__ void flush_work(const Work &wk, unsigned long long *counters)
+{
+    unsigned long long v[6] = {wk.eterms, wk.faces, wk.edges, wk.moments, wk.quads, wk.angles};
+#pragma unroll
+    for (int q = 0; q < 6; q++)
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(counters + C_EDGE_TERMS, v[0]);
+        atomicAdd(counters + C_FACES, v[1]);
+        atomicAdd(counters + C_EDGES, v[2]);
+        atomicAdd(counters + C_MOMENTS, v[3]);
+        atomicAdd(counters + C_QUADS, v[4]);
+        atomicAdd(counters + C_ANGLES, v[5]);
+    }
+}
+
+struct FixList {
+    unsigned *count;
+    uint64_t *items;
+    unsigned cap;
+};
+
+template <int PREC>
+__device__ __forceinline__ double one_pair(int64_t k, const uint32_t *__restrict__ pair_p,
+                                           const uint32_t *__restrict__ pair_c, const double *__restrict__ xyz,
+                                           const double *__restrict__ h, const int64_t *__restrict__ cfo,
+                                           const int64_t *__restrict__ fvo, const double *__restrict__ plane,
+                                           const EdgeRec *__restrict__ edges, Work &wk, const FixList &fx)
+{
+    const int64_t a = pair_p[k];
+    const int64_t c = pair_c[k];
+    return pair_fraction<PREC>(xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2], h[a], c, cfo, fvo, plane, edges, wk,
+                               (uint64_t)k, fx.count, fx.items, fx.cap);
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(256) k_integrate_flat(int64_t np, const uint32_t *__restrict__ pair_p,
+                                                         const uint32_t *__restrict__ pair_c,
+                                                         const double *__restrict__ xyz, const double *__restrict__ h,
+                                                         const int64_t *__restrict__ cfo,
+                                                         const int64_t *__restrict__ fvo,
+                                                         const double *__restrict__ plane,
+                                                         const EdgeRec *__restrict__ edges, double *__restrict__ f,
+                                                         unsigned long long *counters, FixList fx)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Work wk;
+    if (k < np) f[k] = one_pair<PREC>(k, pair_p, pair_c, xyz, h, cfo, fvo, plane, edges, wk, fx);
+    flush_work(wk, counters);
+}
+
+// Persistent form: each wavefront takes tiles of 64*tile_waves consecutive
+// (cell-ordered) pairs from a queue until the pairs run out.
+template <int PREC>
+__global__ void __launch_bounds__(256) k_integrate_persistent(int64_t np, const uint32_t *__restrict__ pair_p,
+                                                               const uint32_t *__restrict__ pair_c,
+                                                               const double *__restrict__ xyz,
+                                                               const double *__restrict__ h,
+                                                               const int64_t *__restrict__ cfo,
+                                                               const int64_t *__restrict__ fvo,
+                                                               const double *__restrict__ plane,
+                                                               const EdgeRec *__restrict__ edges,
+                                                               double *__restrict__ f, unsigned long long *counters,
+                                                               unsigned *tile_ctr, int tile_waves, FixList fx)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t tile = 64 * (int64_t)tile_waves;
+    const int64_t ntiles = (np + tile - 1) / tile;
+    Work wk;
+    for (;;) {
+        unsigned t = 0;
+        if (lane == 0) t = atomicAdd(tile_ctr, 1u);
+        t = __shfl(t, 0, 64);
+        if ((int64_t)t >= ntiles) break;
+        const int64_t base = (int64_t)t * tile;
+        for (int w = 0; w < tile_waves; w++) {
+            const int64_t k = base + 64 * w + lane;
+            if (k < np) f[k] = one_pair<PREC>(k, pair_p, pair_c, xyz, h, cfo, fvo, plane, edges, wk, fx);
+        }
+    }
+    flush_work(wk, counters);
+}
+
+// FP64 values of flagged edges (fixup items, key = pair << 32 | face-vertex slot)
+__global__ void k_fixup_values(int64_t n_fix, const uint64_t *__restrict__ keys, const uint32_t *__restrict__ pair_p,
+                               const uint32_t *__restrict__ pair_c, const double *__restrict__ xyz,
+                               const double *__restrict__ h, const int64_t *__restrict__ cfo,
+                               const int64_t *__restrict__ fvo, const double *__restrict__ plane,
+                               const EdgeRec *__restrict__ edges, double *__restrict__ vals)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_fix) return;
+    const uint64_t key = keys[i];
+    const int64_t k = (int64_t)(key >> 32);
+    const int64_t s = (int64_t)(key & 0xffffffffu);
+    const int64_t a = pair_p[k], c = pair_c[k];
+    // the face of slot s within the cell
+    int64_t lo = cfo[c], hi = cfo[c + 1] - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (fvo[mid] <= s) lo = mid;
+        else hi = mid - 1;
+    }
+    vals[i] = edge_contribution_fp64(xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2], h[a], plane + 4 * lo, edges[s]);
+}
+
+// Adds the (key-sorted) fixup values of each pair, in key order, to f.
+__global__ void k_fixup_apply(int64_t n_fix, const uint64_t *__restrict__ keys, const double *__restrict__ vals,
+                              double *__restrict__ f)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_fix) return;
+    const uint64_t k = keys[i] >> 32;
+    if (i > 0 && (keys[i - 1] >> 32) == k) return;
+    double sum = 0.0;
+    for (int64_t j = i; j < n_fix && (keys[j] >> 32) == k; j++) sum += vals[j];
+    f[k] += sum;
+}
+
+}  // namespace
+
+void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, int precision,
+                      const IntegrateTune &tune, double *f, int64_t *counters, uint32_t *tile_ctr,
+                      uint64_t *fix_items, int64_t fix_cap, hipStream_t s)
+{
+    const int64_t np = ps.n_pairs;
+    if (np == 0) return;
+    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(counters);
+    FixList fx;
+    fx.count = tile_ctr + 1;
+    fx.items = fix_items;
+    fx.cap = (unsigned)(fix_cap > 0xffffffffLL ? 0xffffffffLL : fix_cap);
+    fill_zero_bytes(tile_ctr, 2 * sizeof(unsigned), s);
+    const int block = 256;
+    if (!tune.persistent) {
+        const unsigned g = (unsigned)((np + block - 1) / block);
+        if (precision == MAP_FP64)
+            hipLaunchKernelGGL(k_integrate_flat<MAP_FP64>, dim3(g), dim3(block), 0, s, np, ps.pair_p, ps.pair_c, in.xyz,
+                               in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, fx);
+        else
+            hipLaunchKernelGGL(k_integrate_flat<MAP_MIXED>, dim3(g), dim3(block), 0, s, np, ps.pair_p, ps.pair_c,
+                               in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, fx);
+        EM_HIP(hipGetLastError());
+        return;
+    }
+    const int tw = tune.tile_waves > 0 ? tune.tile_waves : 1;
+    int64_t tiles = (np + 64 * tw - 1) / (64 * tw);
+    int64_t g = (int64_t)device_cu_count() * (tune.grid_per_cu > 0 ? tune.grid_per_cu : 8);
+    int64_t need = (tiles + (block / 64) - 1) / (block / 64);
+    if (g > need) g = need;
+    if (g < 1) g = 1;
+    if (precision == MAP_FP64)
+        hipLaunchKernelGGL(k_integrate_persistent<MAP_FP64>, dim3((unsigned)g), dim3(block), 0, s, np, ps.pair_p,
+                           ps.pair_c, in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, tile_ctr, tw, fx);
+    else
+        hipLaunchKernelGGL(k_integrate_persistent<MAP_MIXED>, dim3((unsigned)g), dim3(block), 0, s, np, ps.pair_p,
+                           ps.pair_c, in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, tile_ctr, tw, fx);
+    EM_HIP(hipGetLastError());
+}
+
+void launch_fixup(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, const uint64_t *fix_keys,
+                  int64_t n_fix, double *fix_vals, hipStream_t s)
+{
+    if (n_fix <= 0) return;
+    hipLaunchKernelGGL(k_fixup_values, dim3((unsigned)((n_fix + 255) / 256)), dim3(256), 0, s, n_fix, fix_keys,
+                       ps.pair_p, ps.pair_c, in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, fix_vals);
+    EM_HIP(hipGetLastError());
+}
+
+void launch_fixup_apply(const uint64_t *keys, const double *vals, int64_t n_fix, double *f, hipStream_t s)
+{
+    if (n_fix <= 0) return;
+    hipLaunchKernelGGL(k_fixup_apply, dim3((unsigned)((n_fix + 255) / 256)), dim3(256), 0, s, n_fix, keys, vals, f);
+    EM_HIP(hipGetLastError());
+}
+
+}  // namespace em

@@ -1,0 +1,175 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/exactmap.h"
+
+namespace em {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    int code;
+    std::string msg;
+};
+
+#define EM_HIP(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t _e = (expr);                                                               \
+        if (_e != hipSuccess)                                                                 \
+            throw ::em::Error{MAP_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)}; \
+    } while (0)
+
+#define EM_CHECK(cond, code, msg)                  \
+    do {                                           \
+        if (!(cond)) throw ::em::Error{(code), (msg)}; \
+    } while (0)
+
+// ---------------------------------------------------------------- device memory
+// A grow-only set of device buffers.  get() returns a buffer of at least
+// `bytes`, reallocating (and discarding contents) when it is too small.
+class Workspace {
+public:
+    explicit Workspace(int device) : device_(device) {}
+    ~Workspace();
+    Workspace(const Workspace &) = delete;
+    Workspace &operator=(const Workspace &) = delete;
+
+    void *get(int slot, size_t bytes);
+    template <typename T>
+    T *get(int slot, size_t count) { return static_cast<T *>(get(slot, count * sizeof(T))); }
+    size_t bytes_held() const;
+    void release();
+
+private:
+    struct Buf {
+        void *p = nullptr;
+        size_t cap = 0;
+    };
+    int device_;
+    std::vector<Buf> bufs_;
+};
+
+// Buffer slots of one mapping job.
+enum Slot : int {
+    S_XYZ, S_M, S_H,
+    S_CFO, S_FVO, S_FV, S_PLANE, S_VERTS, S_VOL,
+    S_EDGE, S_AABB, S_CBIN,
+    S_FLAGS, S_COUNTERS,
+    S_BINCNT, S_BINOFF, S_BINKEY, S_BINVAL, S_BINKEY2, S_BINVAL2, S_BINLIST, S_BINCNT64, S_BINOFF_G,
+    S_PCNT, S_POFF, S_PC_PM, S_PP_PM, S_IOTA,
+    S_KEY2, S_PERM, S_PAIR_C, S_PAIR_P, S_CCNT, S_CCNT64, S_COFF,
+    S_F, S_F_PM, S_S, S_MCELL, S_RHO, S_RED,
+    S_FIX_ITEMS, S_FIX_VALS, S_FIX_KEY2, S_FIX_VAL2,
+    S_SCAN_TMP, S_SORT_HIST, S_TILE_CTR,
+    S_PSEUDO0, S_PSEUDO1, S_PSEUDO2, S_PSEUDO3, S_PSEUDO4, S_PSEUDO5, S_PSEUDO6, S_PSEUDO7,
+    S_PSEUDO8, S_PSEUDO9, S_PSEUDO10, S_PSEUDO11, S_PSEUDO12, S_PSEUDO13, S_PSEUDO14, S_PSEUDO15,
+    S_NUM_SLOTS
+};
+
+// ---------------------------------------------------------------- geometry records
+// One directed wall edge v_k -> v_{k+1} of a face (slot of face_vert):
+// start vertex v, unit direction e, in-plane inward normal m = n x e, length L.
+struct alignas(16) EdgeRec {
+    double vx, vy, vz, L;
+    double ex, ey, ez, mx;
+    double my, mz, pad0, pad1;
+};
+static_assert(sizeof(EdgeRec) == 96, "edge record layout");
+
+// Validation flag bits (device-side checks)
+enum : unsigned {
+    F_PART_NONFINITE = 1u << 0,
+    F_H_NONPOS = 1u << 1,
+    F_M_BAD = 1u << 2,
+    F_CFO_BAD = 1u << 3,
+    F_FVO_BAD = 1u << 4,
+    F_FACE_SMALL = 1u << 5,
+    F_VID_RANGE = 1u << 6,
+    F_PLANE_BAD = 1u << 7,
+    F_VERT_NONFINITE = 1u << 8,
+    F_VOL_BAD = 1u << 9,
+    F_RESULT_NONFINITE = 1u << 10,
+};
+
+// Counters written by kernels (int64 each)
+enum : int {
+    C_CANDIDATES = 0,
+    C_EDGE_TERMS = 1,
+    C_FIXUPS = 2,
+    C_FACES = 3,
+    C_EDGES = 4,
+    C_MOMENTS = 5,
+    C_QUADS = 6,
+    C_ANGLES = 7,
+    C_NUM = 8
+};
+
+// Device-resident view of one job's inputs.
+struct DevInputs {
+    int64_t n = 0;
+    const double *xyz = nullptr, *m = nullptr, *h = nullptr;
+    int64_t n_cells = 0, n_faces = 0, n_face_verts = 0, n_verts = 0;
+    const int64_t *cfo = nullptr, *fvo = nullptr;
+    const int32_t *fv = nullptr;
+    const double *plane = nullptr, *verts = nullptr, *vol = nullptr;
+    double box[6] = {0, 0, 0, 1, 1, 1};
+};
+
+// Launch tuning of the integration kernel.
+struct IntegrateTune {
+    int block = 256;       // threads per workgroup
+    int tile_waves = 1;    // wavefronts of pairs per tile taken from the queue
+    int grid_per_cu = 8;   // persistent workgroups per compute unit
+    int persistent = 1;    // 1: persistent tile queue, 0: one thread per pair
+};
+
+// ---------------------------------------------------------------- primitives (em_primitives.hip)
+// Exclusive scan of int64 counts: out[0] = 0, out[i+1] = out[i] + in[i]; out has n+1 entries.
+void scan_counts(Workspace &ws, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+// Stable LSD radix sort by the low `bits` bits of 32-bit keys, carrying 32-bit values.
+// Results end in (keys, vals); (keys2, vals2) are scratch of the same size.
+void radix_sort_u32(Workspace &ws, uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2, int64_t n,
+                    int bits, hipStream_t s);
+// The same for 64-bit keys.
+void radix_sort_u64(Workspace &ws, uint64_t *keys, uint32_t *vals, uint64_t *keys2, uint32_t *vals2, int64_t n,
+                    int bits, hipStream_t s);
+void fill_iota_u32(uint32_t *p, int64_t n, hipStream_t s);
+void fill_zero_bytes(void *p, size_t bytes, hipStream_t s);
+int device_cu_count();
+
+// ---------------------------------------------------------------- stages
+// em_geometry.hip
+void launch_validate(const DevInputs &in, unsigned *flags, hipStream_t s);
+void launch_geometry(const DevInputs &in, EdgeRec *edges, double *aabb, double *vol_out, hipStream_t s);
+
+// em_pairs.hip: builds the cell-ordered pair set; returns the pair count.
+struct PairSet {
+    int64_t n_pairs = 0;
+    const uint32_t *pair_c = nullptr;  // cell-major order
+    const uint32_t *pair_p = nullptr;
+    const uint32_t *perm = nullptr;    // cell-major index -> particle-major index
+    const int64_t *poff = nullptr;     // particle-major offsets (n+1)
+    const int64_t *coff = nullptr;     // cell-major offsets (n_cells+1)
+};
+PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, int64_t *counters, hipStream_t s);
+
+// em_integrate.hip: raw f per pair (cell-major order).
+void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, int precision,
+                      const IntegrateTune &tune, double *f, int64_t *counters, uint32_t *tile_ctr,
+                      uint64_t *fix_items, int64_t fix_cap, hipStream_t s);
+void launch_fixup(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, const uint64_t *fix_items,
+                  int64_t n_fix, double *fix_vals, hipStream_t s);
+// adds sorted fixup values into f
+void launch_fixup_apply(const uint64_t *keys, const double *vals, int64_t n_fix, double *f, hipStream_t s);
+
+// em_reduce.hip
+void launch_reduce(const DevInputs &in, const PairSet &ps, const double *f, double *f_pm, double *S, double *M,
+                   double *rho, double *red, unsigned *flags, hipStream_t s);
+
+}  // namespace em

@@ -1,0 +1,386 @@
+// Pair search: every (particle a, cell i) whose closed cell lies closer to r_a
+// than 2 h_a, ordered by cell and then particle.
+//
+// Cells are sorted along a Morton curve of their bounding-box centres and
+// grouped 8 per leaf of an implicit complete binary tree of bounding boxes.
+// Each particle walks the tree without a stack (heap indices) and lists the
+// cells whose boxes come within 2h (candidates); then one thread per
+// candidate decides with the exact distance test below, and a scan compacts
+// the pairs.  Counts are scanned into particle offsets, the
+// pairs are written particle-major, and a stable radix sort by cell gives the
+// cell-major order (particles ascending inside a cell) that the integration
+// and the per-cell reduction use.
+#include <cmath>
+
+#include "em_internal.h"
+
+namespace em {
+
+constexpr int64_t kLeaf = 8;  // cells per leaf of the bounding-volume tree
+
+struct Box {
+    double lo[3];
+    double inv[3];
+};
+
+// Exact distance test.  Squared distance from p to the closed convex cell: 0
+// inside; else the least squared distance to a wall polygon that p sees from
+// outside (d_j < 0): d_j^2 if p projects inside the polygon, else the least
+// squared distance to its edge segments.  Evaluated with plain IEEE adds,
+// multiplies and divides in a fixed order, without fused multiply-adds, so
+// that the decision dist^2 < (2h)^2 is reproducible on any IEEE machine.
+__device__ __noinline__ double cell_dist2(double px, double py, double pz, int64_t cell, const int64_t *cfo,
+                                          const int64_t *fvo, const int32_t *fv, const double *plane,
+                                          const double *verts)
+{
+#pragma clang fp contract(off)
+    bool inside = true;
+    double best = INFINITY;
+    for (int64_t j = cfo[cell]; j < cfo[cell + 1]; j++) {
+        double n0 = plane[4 * j], n1 = plane[4 * j + 1], n2 = plane[4 * j + 2], c = plane[4 * j + 3];
+        double d = c - (n0 * px + n1 * py + n2 * pz);
+        if (!(d < 0.0)) continue;
+        inside = false;
+        int64_t k0 = fvo[j], k1 = fvo[j + 1];
+        int64_t nv = k1 - k0;
+        bool left = true;
+        for (int64_t k = 0; k < nv; k++) {
+            const double *a = verts + 3 * (int64_t)fv[k0 + k];
+            const double *b = verts + 3 * (int64_t)fv[k0 + (k + 1 == nv ? 0 : k + 1)];
+            double ex = b[0] - a[0], ey = b[1] - a[1], ez = b[2] - a[2];
+            double wx = px - a[0], wy = py - a[1], wz = pz - a[2];
+            double cr = (ey * wz - ez * wy) * n0 + (ez * wx - ex * wz) * n1 + (ex * wy - ey * wx) * n2;
+            if (cr < 0.0) {
+                left = false;
+                break;
+            }
+        }
+        double dd;
+        if (left) {
+            dd = d * d;
+        } else {
+            dd = INFINITY;
+            for (int64_t k = 0; k < nv; k++) {
+                const double *a = verts + 3 * (int64_t)fv[k0 + k];
+                const double *b = verts + 3 * (int64_t)fv[k0 + (k + 1 == nv ? 0 : k + 1)];
+                double ex = b[0] - a[0], ey = b[1] - a[1], ez = b[2] - a[2];
+                double wx = px - a[0], wy = py - a[1], wz = pz - a[2];
+                double ee = ex * ex + ey * ey + ez * ez;
+                double t = 0.0;
+                if (ee > 0.0) {
+                    t = (wx * ex + wy * ey + wz * ez) / ee;
+                    if (t < 0.0) t = 0.0;
+                    if (t > 1.0) t = 1.0;
+                }
+                double qx = wx - t * ex, qy = wy - t * ey, qz = wz - t * ez;
+                double e2 = qx * qx + qy * qy + qz * qz;
+                if (e2 < dd) dd = e2;
+            }
+        }
+        if (dd < best) best = dd;
+    }
+    return inside ? 0.0 : best;
+}
+
+// Morton code (21 bits per axis) of each cell's bounding-box centre
+__device__ __forceinline__ uint64_t spread21(uint64_t v)
+{
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__global__ void k_cell_morton(int64_t n_cells, const double *aabb, Box B, uint64_t *key)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_cells) return;
+    uint64_t q[3];
+    for (int d = 0; d < 3; d++) {
+        double cen = 0.5 * (aabb[6 * i + d] + aabb[6 * i + 3 + d]);
+        double t = (cen - B.lo[d]) * B.inv[d] * 2097152.0;
+        t = t < 0.0 ? 0.0 : (t > 2097151.0 ? 2097151.0 : t);
+        q[d] = (uint64_t)t;
+    }
+    key[i] = spread21(q[0]) | (spread21(q[1]) << 1) | (spread21(q[2]) << 2);
+}
+
+// Leaves of the implicit tree: heap nodes [NL, 2NL), leaf j holds the cells
+// cperm[kLeaf*(j-NL) .. +kLeaf).  Empty leaves get an inverted box.
+__global__ void k_leaf_boxes(int64_t n_cells, int64_t NL, const uint32_t *cperm, const double *aabb, double *nodes)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= NL) return;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t t = kLeaf * j; t < kLeaf * (j + 1) && t < n_cells; t++) {
+        const double *bb = aabb + 6 * (int64_t)cperm[t];
+        for (int d = 0; d < 3; d++) {
+            lo[d] = fmin(lo[d], bb[d]);
+            hi[d] = fmax(hi[d], bb[3 + d]);
+        }
+    }
+    double *o = nodes + 6 * (NL + j);
+    for (int d = 0; d < 3; d++) {
+        o[d] = lo[d];
+        o[3 + d] = hi[d];
+    }
+}
+
+__global__ void k_parent_boxes(int64_t first, int64_t count, double *nodes)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    int64_t i = first + t;
+    const double *a = nodes + 6 * (2 * i), *b = nodes + 6 * (2 * i + 1);
+    double *o = nodes + 6 * i;
+    for (int d = 0; d < 3; d++) {
+        o[d] = fmin(a[d], b[d]);
+        o[3 + d] = fmax(a[3 + d], b[3 + d]);
+    }
+}
+
+__device__ __forceinline__ double box_dist2(const double *bb, double px, double py, double pz)
+{
+    double dx = fmax(fmax(bb[0] - px, px - bb[3]), 0.0);
+    double dy = fmax(fmax(bb[1] - py, py - bb[4]), 0.0);
+    double dz = fmax(fmax(bb[2] - pz, pz - bb[5]), 0.0);
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// FILL = false: count candidate cells per particle; FILL = true: write them.
+// Candidates are the cells whose bounding box comes closer than 2h to the
+// particle.  Stackless depth-first walk of the implicit tree (heap indices:
+// children 2i, 2i+1); only box tests here, so lanes stay in step.
+template <bool FILL>
+__global__ void k_candidates(int64_t n, const double *__restrict__ xyz, const double *__restrict__ h,
+                             int64_t n_cells, const double *__restrict__ aabb, const double *__restrict__ nodes,
+                             int64_t NL, const uint32_t *__restrict__ cperm, int64_t *__restrict__ ccount,
+                             const int64_t *__restrict__ coffs, uint32_t *__restrict__ cand_c,
+                             uint32_t *__restrict__ cand_p)
+{
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const double px = xyz[3 * a], py = xyz[3 * a + 1], pz = xyz[3 * a + 2];
+    const double r = 2.0 * h[a];
+    const double r2_loose = r * r * (1.0 + 1e-9);
+    int64_t count = 0;
+    const int64_t out = FILL ? coffs[a] : 0;
+    int64_t i = 1;
+    for (;;) {
+        const bool hit = box_dist2(nodes + 6 * i, px, py, pz) <= r2_loose;
+        if (hit && i < NL) {
+            i = 2 * i;
+            continue;
+        }
+        if (hit) {
+            const int64_t t0 = kLeaf * (i - NL);
+            for (int64_t t = t0; t < t0 + kLeaf && t < n_cells; t++) {
+                const uint32_t c = cperm[t];
+                if (box_dist2(aabb + 6 * (int64_t)c, px, py, pz) > r2_loose) continue;
+                if (FILL) {
+                    cand_c[out + count] = c;
+                    cand_p[out + count] = (uint32_t)a;
+                }
+                count++;
+            }
+        }
+        while (i & 1) i >>= 1;
+        if (i == 0) break;
+        i += 1;
+    }
+    if (!FILL) ccount[a] = count;
+}
+
+// One thread per candidate: 1 if the pair exists.  A cell whose whole bounding
+// box lies within 0.999999 * 2h of the particle is accepted without the exact
+// test (its exact distance is then certainly below 2h); otherwise the exact
+// test decides.
+__global__ void k_exact(int64_t nc_total, const uint32_t *__restrict__ cand_c, const uint32_t *__restrict__ cand_p,
+                        const double *__restrict__ xyz, const double *__restrict__ h,
+                        const double *__restrict__ aabb, const int64_t *__restrict__ cfo,
+                        const int64_t *__restrict__ fvo, const int32_t *__restrict__ fv,
+                        const double *__restrict__ plane, const double *__restrict__ verts, int64_t *__restrict__ flag,
+                        unsigned long long *exact_counter)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long tested = 0;
+    if (q < nc_total) {
+        const int64_t c = cand_c[q], a = cand_p[q];
+        const double px = xyz[3 * a], py = xyz[3 * a + 1], pz = xyz[3 * a + 2];
+        const double r = 2.0 * h[a];
+        const double r2 = r * r;
+        const double *bb = aabb + 6 * c;
+        const double fx = fmax(fabs(bb[0] - px), fabs(bb[3] - px));
+        const double fy = fmax(fabs(bb[1] - py), fabs(bb[4] - py));
+        const double fz = fmax(fabs(bb[2] - pz), fabs(bb[5] - pz));
+        int64_t ok;
+        if (fx * fx + fy * fy + fz * fz < r2 * 0.999998) {
+            ok = 1;
+        } else {
+            tested = 1;
+            ok = cell_dist2(px, py, pz, c, cfo, fvo, fv, plane, verts) < r2 ? 1 : 0;
+        }
+        flag[q] = ok;
+    }
+    for (int o = 32; o > 0; o >>= 1) tested += __shfl_xor(tested, o, 64);
+    if ((threadIdx.x & 63) == 0 && tested) atomicAdd(exact_counter, tested);
+}
+
+__global__ void k_compact(int64_t nc_total, const uint32_t *__restrict__ cand_c, const uint32_t *__restrict__ cand_p,
+                          const int64_t *__restrict__ fpos, uint32_t *__restrict__ pc_pm, uint32_t *__restrict__ pp_pm)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nc_total) return;
+    const int64_t pos = fpos[q];
+    if (fpos[q + 1] != pos) {
+        pc_pm[pos] = cand_c[q];
+        pp_pm[pos] = cand_p[q];
+    }
+}
+
+__global__ void k_particle_offsets(int64_t n, const int64_t *__restrict__ coffs, const int64_t *__restrict__ fpos,
+                                   int64_t *__restrict__ poff)
+{
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a <= n) poff[a] = fpos[coffs[a]];
+}
+
+__global__ void k_u32_to_i64(const unsigned *in, int64_t *out, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i];
+}
+
+__global__ void k_gather_particle(const uint32_t *perm, const uint32_t *pp_pm, uint32_t *pair_p, int64_t np,
+                                  unsigned *ccnt, const uint32_t *pair_c)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    pair_p[k] = pp_pm[perm[k]];
+    atomicAdd(&ccnt[pair_c[k]], 1u);
+}
+
+static int bits_for(uint64_t maxval)
+{
+    int b = 1;
+    while (b < 64 && (maxval >> b) != 0) b++;
+    return b;
+}
+
+PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, int64_t *counters, hipStream_t s)
+{
+    PairSet ps;
+    const int64_t n = in.n, nc = in.n_cells;
+    int64_t *poff = ws.get<int64_t>(S_POFF, (size_t)n + 1);
+    int64_t *coff = ws.get<int64_t>(S_COFF, (size_t)nc + 1);
+    ps.poff = poff;
+    ps.coff = coff;
+    if (n == 0 || nc == 0) {
+        fill_zero_bytes(poff, sizeof(int64_t) * (n + 1), s);
+        fill_zero_bytes(coff, sizeof(int64_t) * (nc + 1), s);
+        return ps;
+    }
+    // bounding-volume tree over the cells in Morton order of their box centres
+    Box B;
+    for (int d = 0; d < 3; d++) {
+        double ext = in.box[3 + d] - in.box[d];
+        EM_CHECK(ext > 0.0 && std::isfinite(ext), MAP_EINVAL, "box has non-positive extent");
+        B.lo[d] = in.box[d];
+        B.inv[d] = 1.0 / ext;
+    }
+    uint64_t *ckey = reinterpret_cast<uint64_t *>(ws.get<int64_t>(S_BINKEY, (size_t)nc));
+    uint64_t *ckey2 = reinterpret_cast<uint64_t *>(ws.get<int64_t>(S_BINKEY2, (size_t)nc));
+    uint32_t *cperm = ws.get<uint32_t>(S_BINVAL, (size_t)nc);
+    uint32_t *cperm2 = ws.get<uint32_t>(S_BINVAL2, (size_t)nc);
+    hipLaunchKernelGGL(k_cell_morton, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, nc, aabb, B, ckey);
+    EM_HIP(hipGetLastError());
+    fill_iota_u32(cperm, nc, s);
+    radix_sort_u64(ws, ckey, cperm, ckey2, cperm2, nc, 63, s);
+    int64_t nleaf = (nc + kLeaf - 1) / kLeaf, NL = 1;
+    while (NL < nleaf) NL <<= 1;
+    double *nodes = ws.get<double>(S_BINOFF_G, (size_t)(12 * NL));
+    hipLaunchKernelGGL(k_leaf_boxes, dim3((unsigned)((NL + 255) / 256)), dim3(256), 0, s, nc, NL,
+                       (const uint32_t *)cperm, aabb, nodes);
+    EM_HIP(hipGetLastError());
+    for (int64_t first = NL / 2; first >= 1; first /= 2) {
+        hipLaunchKernelGGL(k_parent_boxes, dim3((unsigned)((first + 255) / 256)), dim3(256), 0, s, first, first,
+                           nodes);
+        EM_HIP(hipGetLastError());
+    }
+
+    // candidates per particle (tree walk, box tests only)
+    int64_t *ccount = ws.get<int64_t>(S_PCNT, (size_t)n);
+    int64_t *coffs = ws.get<int64_t>(S_CCNT64, (size_t)(n + 1));
+    const unsigned pb = 128;
+    const unsigned pg = (unsigned)((n + pb - 1) / pb);
+    hipLaunchKernelGGL(k_candidates<false>, dim3(pg), dim3(pb), 0, s, n, in.xyz, in.h, nc, aabb,
+                       (const double *)nodes, NL, (const uint32_t *)cperm, ccount, (const int64_t *)nullptr,
+                       (uint32_t *)nullptr, (uint32_t *)nullptr);
+    EM_HIP(hipGetLastError());
+    scan_counts(ws, ccount, coffs, n, s);
+    int64_t ncand = 0;
+    EM_HIP(hipMemcpyAsync(&ncand, coffs + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    EM_HIP(hipStreamSynchronize(s));
+    EM_CHECK(ncand < (int64_t)UINT32_MAX, MAP_ENOMEM, "candidate count exceeds 2^32-1");
+    uint32_t *cand_c = ws.get<uint32_t>(S_KEY2, (size_t)(ncand > 0 ? ncand : 1));
+    uint32_t *cand_p = ws.get<uint32_t>(S_IOTA, (size_t)(ncand > 0 ? ncand : 1));
+    hipLaunchKernelGGL(k_candidates<true>, dim3(pg), dim3(pb), 0, s, n, in.xyz, in.h, nc, aabb,
+                       (const double *)nodes, NL, (const uint32_t *)cperm, (int64_t *)nullptr,
+                       (const int64_t *)coffs, cand_c, cand_p);
+    EM_HIP(hipGetLastError());
+    // exact test, one thread per candidate, then compaction
+    int64_t *flag = ws.get<int64_t>(S_F_PM, (size_t)(ncand > 0 ? ncand : 1));
+    int64_t *fpos = ws.get<int64_t>(S_F, (size_t)(ncand + 1));
+    unsigned long long *cand = reinterpret_cast<unsigned long long *>(counters + C_CANDIDATES);
+    if (ncand > 0) {
+        hipLaunchKernelGGL(k_exact, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand,
+                           (const uint32_t *)cand_c, (const uint32_t *)cand_p, in.xyz, in.h, aabb, in.cfo, in.fvo,
+                           in.fv, in.plane, in.verts, flag, cand);
+        EM_HIP(hipGetLastError());
+    }
+    scan_counts(ws, flag, fpos, ncand, s);
+    hipLaunchKernelGGL(k_particle_offsets, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s, n,
+                       (const int64_t *)coffs, (const int64_t *)fpos, poff);
+    EM_HIP(hipGetLastError());
+    int64_t np = 0;
+    EM_HIP(hipMemcpyAsync(&np, poff + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    EM_HIP(hipStreamSynchronize(s));
+    EM_CHECK(np < (int64_t)UINT32_MAX, MAP_ENOMEM, "pair count exceeds 2^32-1");
+    ps.n_pairs = np;
+    if (np == 0) {
+        fill_zero_bytes(coff, sizeof(int64_t) * (nc + 1), s);
+        return ps;
+    }
+    uint32_t *pc = ws.get<uint32_t>(S_PC_PM, (size_t)np);
+    uint32_t *pp_pm = ws.get<uint32_t>(S_PP_PM, (size_t)np);
+    if (ncand > 0) {
+        hipLaunchKernelGGL(k_compact, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand,
+                           (const uint32_t *)cand_c, (const uint32_t *)cand_p, (const int64_t *)fpos, pc, pp_pm);
+        EM_HIP(hipGetLastError());
+    }
+    // cell-major order: stable sort of particle-major pairs by cell
+    uint32_t *perm = ws.get<uint32_t>(S_PERM, (size_t)np);
+    uint32_t *k2 = ws.get<uint32_t>(S_KEY2, (size_t)np);
+    uint32_t *v2 = ws.get<uint32_t>(S_IOTA, (size_t)np);
+    int64_t *ccnt64 = ws.get<int64_t>(S_CCNT64, (size_t)nc);
+    fill_iota_u32(perm, np, s);
+    radix_sort_u32(ws, pc, perm, k2, v2, np, bits_for((uint64_t)nc - 1), s);
+    uint32_t *pair_p = ws.get<uint32_t>(S_PAIR_P, (size_t)np);
+    unsigned *ccnt = ws.get<unsigned>(S_CCNT, (size_t)nc);
+    fill_zero_bytes(ccnt, sizeof(unsigned) * nc, s);
+    hipLaunchKernelGGL(k_gather_particle, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, perm, pp_pm, pair_p,
+                       np, ccnt, (const uint32_t *)pc);
+    EM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_u32_to_i64, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, ccnt, ccnt64, nc);
+    EM_HIP(hipGetLastError());
+    scan_counts(ws, ccnt64, coff, nc, s);
+    ps.pair_c = pc;
+    ps.pair_p = pair_p;
+    ps.perm = perm;
+    return ps;
+}
+
+}  // namespace em

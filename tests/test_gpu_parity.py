@@ -1,0 +1,222 @@
+"""Parity of the HIP library with the FP64 oracle, called through the C ABI.
+
+Bars (per the target of the mapping): pair sets identical; all-FP64 path within
+1e-10 relative per cell (and 1e-12 absolute per pair fraction); mixed path
+within 1e-5 relative per cell; mass conserved to 1e-9 in both.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_2404_17084_amd as em
+
+pytestmark = pytest.mark.gpu
+
+FP64_CELL_REL = 1e-10
+FP64_PAIR_ABS = 1e-12
+MIXED_CELL_REL = 1e-5
+MASS_ABS = 1e-9
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mapper():
+    m = em.Mapper(device=0)
+    yield m
+    m.close()
+
+
+@pytest.fixture(scope="module")
+def clumps256k():
+    return synth.workload(*synth.CLUMPS_256K)
+
+
+def _run(mapper, p, c, precision, want_pairs=True):
+    mapper.set_precision(precision)
+    return mapper.map(p, c, want_pairs=want_pairs)
+
+
+# ------------------------------------------------------------------ uniform 4096 (full oracle)
+def test_pairs_identical_uniform4k(mapper, uniform4k, uniform4k_oracle):
+    say("case: pairs uniform 4096")
+    p, c = uniform4k
+    pp, pc = mapper.pairs(p, c)
+    assert np.array_equal(pp, uniform4k_oracle["pair_p"])
+    assert np.array_equal(pc, uniform4k_oracle["pair_c"])
+
+
+def test_fp64_parity_uniform4k(mapper, uniform4k, uniform4k_oracle):
+    say("case: FP64 uniform 4096")
+    p, c = uniform4k
+    r = _run(mapper, p, c, em.MAP_FP64)
+    o = uniform4k_oracle
+    assert np.array_equal(r["pair_p"], o["pair_p"]) and np.array_equal(r["pair_c"], o["pair_c"])
+    assert np.abs(r["f"] - o["f"]).max() < FP64_PAIR_ABS
+    assert np.abs(r["S"] - o["S"]).max() < 1e-12
+    rel = np.abs(r["M"] - o["M"]) / o["M"]
+    assert rel.max() < FP64_CELL_REL, rel.max()
+    assert np.abs(r["rho"] - o["rho"]).max() / o["rho"].max() < FP64_CELL_REL
+    st = r["stats"]
+    assert st["n_pairs"] == o["f"].size
+    assert abs(st["mass_out"] - p.m.sum()) < MASS_ABS
+    assert abs(r["M"].sum() - p.m.sum()) < 1e-12
+
+
+def test_mixed_parity_uniform4k(mapper, uniform4k, uniform4k_oracle):
+    say("case: mixed uniform 4096")
+    p, c = uniform4k
+    r = _run(mapper, p, c, em.MAP_MIXED)
+    o = uniform4k_oracle
+    rel = np.abs(r["M"] - o["M"]) / o["M"]
+    say(f"mixed uniform4k: max cell rel err {rel.max():.3e}, max pair abs err {np.abs(r['f'] - o['f']).max():.3e}, "
+        f"fixups {r['stats']['n_fixup_terms']}")
+    assert rel.max() < MIXED_CELL_REL
+    assert abs(r["M"].sum() - p.m.sum()) < MASS_ABS
+
+
+def test_deterministic_bits(mapper, uniform4k):
+    say("case: determinism")
+    p, c = uniform4k
+    for prec in (em.MAP_FP64, em.MAP_MIXED):
+        a = _run(mapper, p, c, prec)
+        b = _run(mapper, p, c, prec)
+        assert np.array_equal(a["M"], b["M"]) and np.array_equal(a["f"], b["f"]) and np.array_equal(a["S"], b["S"])
+
+
+# ------------------------------------------------------------------ ragged and edge cases
+def test_ragged_small_clumps(mapper):
+    say("case: clumps 1000 ragged")
+    p, c = synth.workload("clumps", 1000, 21)
+    o = oracle.map_particles(p, c)
+    for prec, tol in ((em.MAP_FP64, FP64_CELL_REL), (em.MAP_MIXED, MIXED_CELL_REL)):
+        r = _run(mapper, p, c, prec)
+        assert np.array_equal(r["pair_p"], o["pair_p"]) and np.array_equal(r["pair_c"], o["pair_c"])
+        assert (np.abs(r["M"] - o["M"]) / o["M"]).max() < tol
+
+
+def test_single_cell_fraction_one(mapper):
+    say("case: single cell")
+    from tests.test_oracle_pins import box_cell
+    c = box_cell((0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    p = synth.Particles(np.array([[0.5, 0.5, 0.5]]), np.array([2.0]), np.array([0.2]))
+    for prec in (em.MAP_FP64, em.MAP_MIXED):
+        r = _run(mapper, p, c, prec)
+        assert r["f"].size == 1
+        assert abs(r["f"][0] - 1.0) < 1e-14
+        assert abs(r["M"][0] - 2.0) < 1e-14
+
+
+def test_one_wall_half_space(mapper):
+    say("case: one wall")
+    from tests.test_oracle_pins import box_cell, half_space
+    c = box_cell((0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    us = np.array([0.3, 0.77, 1.0, 1.5])
+    h = 0.1
+    xyz = np.column_stack([us * h, np.full(4, 0.5), np.full(4, 0.5)])
+    p = synth.Particles(xyz, np.full(4, 0.25), np.full(4, h))
+    r = _run(mapper, p, c, em.MAP_FP64)
+    ref = np.array([1 - half_space(u) for u in us])
+    assert np.abs(r["S"] - ref).max() < 1e-13
+
+
+def test_particle_on_wall_plane(mapper):
+    say("case: particle on a wall plane")
+    p, c = synth.workload("uniform", 64, 23)
+    # move particle 5 onto a wall plane of its own cell (the face's plane)
+    j = c.cell_face_off[5]
+    n, cc = c.face_plane[j, :3], c.face_plane[j, 3]
+    x = p.xyz.copy()
+    x[5] = x[5] + (cc - n @ x[5]) * n
+    p2 = synth.Particles(x, p.m, p.h)
+    o = oracle.map_particles(p2, c)
+    r = _run(mapper, p2, c, em.MAP_FP64)
+    assert np.array_equal(r["pair_c"], o["pair_c"])
+    assert np.abs(r["f"] - o["f"]).max() < 1e-12
+
+
+def test_empty_inputs(mapper):
+    say("case: empty particles")
+    p, c = synth.workload("uniform", 32, 24)
+    e = synth.Particles(np.zeros((0, 3)), np.zeros(0), np.zeros(0))
+    r = _run(mapper, e, c, em.MAP_FP64, want_pairs=False)
+    assert r["stats"]["n_pairs"] == 0 and np.all(r["M"] == 0)
+
+
+@pytest.mark.parametrize("what", ["h_zero", "nan_pos", "bad_offsets", "vid_range", "small_face", "bad_normal"])
+def test_invalid_inputs_rejected(mapper, what):
+    say(f"case: invalid input {what}")
+    p, c = synth.workload("uniform", 32, 25)
+    xyz, m, h = p.xyz.copy(), p.m.copy(), p.h.copy()
+    cc = synth.Cells(c.cell_face_off.copy(), c.face_vert_off.copy(), c.face_vert.copy(), c.face_plane.copy(),
+                     c.face_nb, c.verts.copy(), c.cell_volume.copy(), c.box)
+    expect = em.MAP_EINVAL
+    if what == "h_zero":
+        h[3] = 0.0
+    elif what == "nan_pos":
+        xyz[7, 1] = np.nan
+    elif what == "bad_offsets":
+        cc.cell_face_off[5] = cc.cell_face_off[6] + 1
+        expect = em.MAP_EGEOM
+    elif what == "vid_range":
+        cc.face_vert[10] = c.n_verts + 5
+        expect = em.MAP_EGEOM
+    elif what == "small_face":
+        cc.face_vert_off[3] = cc.face_vert_off[2] + 2
+        expect = em.MAP_EGEOM
+    elif what == "bad_normal":
+        cc.face_plane[4, :3] *= 1.5
+        expect = em.MAP_EGEOM
+    with pytest.raises(em.MapError) as ei:
+        mapper.map(synth.Particles(xyz, m, h), cc)
+    assert ei.value.code == expect
+    # the context stays usable
+    r = mapper.map(p, c)
+    assert abs(r["M"].sum() - p.m.sum()) < 1e-12
+
+
+# ------------------------------------------------------------------ clumps 262144 (sampled oracle)
+@pytest.fixture(scope="module")
+def clumps_gpu(mapper, clumps256k):
+    p, c = clumps256k
+    out = {}
+    for prec in (em.MAP_FP64, em.MAP_MIXED):
+        say(f"case: clumps 262144 precision {prec}")
+        out[prec] = _run(mapper, p, c, prec)
+    return out
+
+
+def test_clumps_pairs_sampled(clumps256k, clumps_gpu):
+    p, c = clumps256k
+    r = clumps_gpu[em.MAP_FP64]
+    sel = np.sort(np.random.default_rng(7).choice(c.n_cells, 64, replace=False))
+    pp, pc = oracle.pairs_for_cells(p.xyz, p.h, c, sel)
+    for i in sel:
+        gpu = r["pair_p"][r["pair_c"] == i]
+        ref = np.sort(pp[pc == i])
+        assert np.array_equal(gpu, ref), i
+    sp = np.random.default_rng(8).choice(p.n, 64, replace=False)
+    qp, qc = oracle.pairs_for_particles(p.xyz, p.h, c, sp)
+    counts = np.bincount(r["pair_p"], minlength=p.n)
+    assert np.array_equal(counts[sp], np.array([(qp == a).sum() for a in sp]))
+
+
+@pytest.mark.parametrize("prec,tol", [(em.MAP_FP64, FP64_CELL_REL), (em.MAP_MIXED, MIXED_CELL_REL)])
+def test_clumps_cells_sampled(clumps256k, clumps_gpu, prec, tol):
+    p, c = clumps256k
+    r = clumps_gpu[prec]
+    sel = np.sort(np.random.default_rng(9).choice(c.n_cells, 48, replace=False))
+    M, rho, S, _ = oracle.sampled_cell_mass(p, c, sel)
+    rel = np.abs(r["M"][sel] - M) / M
+    say(f"clumps precision {prec}: sampled cell rel err max {rel.max():.3e}")
+    assert rel.max() < tol
+    assert abs(r["stats"]["mass_out"] - 1.0) < MASS_ABS
+    assert abs(r["M"].sum() - 1.0) < MASS_ABS
+    interior = np.all((p.xyz - 2 * p.h[:, None] > 0) & (p.xyz + 2 * p.h[:, None] < 1), axis=1)
+    assert np.abs(r["S"][interior] - 1).max() < (1e-12 if prec == em.MAP_FP64 else 1e-5)
