@@ -143,13 +143,17 @@ const char *map_last_error(map_ctx *ctx);
 int map_set_precision(map_ctx *ctx, int precision);
 
 /*
- * Launch shape of the integration kernel (the autotuner's knobs): threads per
- * workgroup (256), wavefronts of consecutive pairs taken per queue pop
- * (1..64), persistent workgroups per compute unit (1..64), and persistent = 0
- * for a plain one-thread-per-pair launch.  Results do not depend on them.
+ * Launch shape of the integration kernel (the autotuner's knobs): register
+ * budget as resident wavefronts per SIMD (0 = compiler default; FP64 kernel
+ * 2..4, mixed kernel 4..6), wavefronts of consecutive pairs taken per queue
+ * pop (1..64), persistent workgroups of 256 threads per compute unit (1..64),
+ * and the work distribution: 1 = persistent queue of pair tiles, 2 =
+ * persistent queue of single-cell tiles, 0 = one thread per pair.  For a given
+ * distribution, results are bitwise independent of the other knobs and of
+ * scheduling; the distributions are separate kernels and agree to rounding.
  */
-int map_set_tune(map_ctx *ctx, int block, int tile_waves, int grid_per_cu, int persistent);
-int map_get_tune(map_ctx *ctx, int *block, int *tile_waves, int *grid_per_cu, int *persistent);
+int map_set_tune(map_ctx *ctx, int waves, int tile_waves, int grid_per_cu, int persistent);
+int map_get_tune(map_ctx *ctx, int *waves, int *tile_waves, int *grid_per_cu, int *persistent);
 
 /*
  * Pair set of Sec. II-B: every (particle a, cell i) with dist(r_a, cell i) < 2h_a,

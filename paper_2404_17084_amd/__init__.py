@@ -207,8 +207,8 @@ def map_set_precision(ctx, precision: int):
     _check(ctx, load().map_set_precision(ctx, precision))
 
 
-def map_set_tune(ctx, block=256, tile_waves=1, grid_per_cu=8, persistent=1):
-    _check(ctx, load().map_set_tune(ctx, block, tile_waves, grid_per_cu, persistent))
+def map_set_tune(ctx, waves=0, tile_waves=1, grid_per_cu=8, persistent=1):
+    _check(ctx, load().map_set_tune(ctx, waves, tile_waves, grid_per_cu, persistent))
 
 
 def map_get_tune(ctx):

@@ -128,7 +128,7 @@ void prepare(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_i
     EM_CHECK(hf == 0, flag_code(hf), flag_text(hf));
 
     edges = ws.get<EdgeRec>(S_EDGE, (size_t)(c->n_face_verts > 0 ? c->n_face_verts : 1));
-    aabb = ws.get<double>(S_AABB, (size_t)(6 * (c->n_cells > 0 ? c->n_cells : 1)));
+    aabb = ws.get<double>(S_AABB, (size_t)(9 * (c->n_cells > 0 ? c->n_cells : 1)));
     double *vol_out = nullptr;
     if (!in.vol) {
         vol_out = ws.get<double>(S_VOL, (size_t)(c->n_cells > 0 ? c->n_cells : 1));
@@ -165,7 +165,8 @@ void run_mapping(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cel
     int64_t *counters;
     prepare(C, ws, p, c, in, edges, aabb, flags, counters, s);
     if (timed) EM_HIP(hipEventRecord(C.ev[1], s));
-    PairSet ps = build_pairs(ws, in, aabb, counters, s);
+    PairSet ps = build_pairs(ws, in, aabb, edges, counters, s);
+    if (C.tune.persistent == 2) build_tiles(ws, in, ps, s);
     if (timed) EM_HIP(hipEventRecord(C.ev[2], s));
     const int64_t np = ps.n_pairs;
     double *f = ws.get<double>(S_F, (size_t)(np > 0 ? np : 1));
@@ -339,25 +340,26 @@ int map_set_precision(map_ctx *h, int precision)
     });
 }
 
-int map_set_tune(map_ctx *h, int block, int tile_waves, int grid_per_cu, int persistent)
+int map_set_tune(map_ctx *h, int waves, int tile_waves, int grid_per_cu, int persistent)
 {
     Ctx *C = reinterpret_cast<Ctx *>(h);
     API_BODY(C, {
-        EM_CHECK(block == 256, MAP_EINVAL, "block must be 256");
+        EM_CHECK(waves >= 0 && waves <= 8, MAP_EINVAL, "waves must be in [0, 8]");
+        EM_CHECK(persistent >= 0 && persistent <= 2, MAP_EINVAL, "persistent must be 0, 1 or 2");
         EM_CHECK(tile_waves >= 1 && tile_waves <= 64, MAP_EINVAL, "tile_waves must be in [1, 64]");
         EM_CHECK(grid_per_cu >= 1 && grid_per_cu <= 64, MAP_EINVAL, "grid_per_cu must be in [1, 64]");
-        C->tune.block = block;
+        C->tune.waves = waves;
         C->tune.tile_waves = tile_waves;
         C->tune.grid_per_cu = grid_per_cu;
-        C->tune.persistent = persistent ? 1 : 0;
+        C->tune.persistent = persistent;
     });
 }
 
-int map_get_tune(map_ctx *h, int *block, int *tile_waves, int *grid_per_cu, int *persistent)
+int map_get_tune(map_ctx *h, int *waves, int *tile_waves, int *grid_per_cu, int *persistent)
 {
     Ctx *C = reinterpret_cast<Ctx *>(h);
     API_BODY(C, {
-        if (block) *block = C->tune.block;
+        if (waves) *waves = C->tune.waves;
         if (tile_waves) *tile_waves = C->tune.tile_waves;
         if (grid_per_cu) *grid_per_cu = C->tune.grid_per_cu;
         if (persistent) *persistent = C->tune.persistent;
@@ -378,7 +380,7 @@ int map_pairs(map_ctx *h, const map_particles_in *p, const map_cells_in *c, int6
         unsigned *flags;
         int64_t *counters;
         prepare(*C, C->ws, p, c, in, edges, aabb, flags, counters, s);
-        PairSet ps = build_pairs(C->ws, in, aabb, counters, s);
+        PairSet ps = build_pairs(C->ws, in, aabb, edges, counters, s);
         *n_pairs = ps.n_pairs;
         int64_t cnt = ps.n_pairs < capacity ? ps.n_pairs : capacity;
         if (cnt > 0 && (pair_p || pair_c)) {

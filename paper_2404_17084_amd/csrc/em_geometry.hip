@@ -124,11 +124,15 @@ __global__ void k_edge_table(int64_t n_faces, const int64_t *fvo, const int32_t 
     }
 }
 
-// One thread per cell: bounding box and (optionally) volume from the signed
-// cone decomposition about the cell's first vertex.
+// One thread per cell: bounding box, an interior point (mean of the wall
+// vertex slots, inside the convex cell; stored after the n_cells boxes) and
+// (optionally) the volume from the signed cone decomposition about the cell's
+// first vertex.
 __global__ void k_cell_boxes(int64_t n_cells, const int64_t *cfo, const int64_t *fvo, const int32_t *fv,
                              const double *plane, const double *verts, double *aabb, double *vol_out)
 {
+    double cen[3] = {0.0, 0.0, 0.0};
+    int64_t nslot = 0;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_cells) return;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -145,7 +149,9 @@ __global__ void k_cell_boxes(int64_t n_cells, const int64_t *cfo, const int64_t 
             for (int d = 0; d < 3; d++) {
                 lo[d] = fmin(lo[d], v[d]);
                 hi[d] = fmax(hi[d], v[d]);
+                cen[d] += v[d];
             }
+            nslot++;
             if (s + 1 < s1 && s > s0) {
                 const double *w = verts + 3 * (int64_t)fv[s + 1];
                 double ax = v[0] - v0[0], ay = v[1] - v0[1], az = v[2] - v0[2];
@@ -159,6 +165,7 @@ __global__ void k_cell_boxes(int64_t n_cells, const int64_t *cfo, const int64_t 
     for (int d = 0; d < 3; d++) {
         aabb[6 * i + d] = lo[d];
         aabb[6 * i + 3 + d] = hi[d];
+        aabb[6 * n_cells + 3 * i + d] = cen[d] / (double)nslot;
     }
     if (vol_out) vol_out[i] = vol;
 }

@@ -165,95 +165,146 @@ __device__ __forceinline__ float shell_quad(float r0, float R0, float c2, float 
     return tot * R0 * (1.0f / 120.0f);
 }
 
-// Shell-piece integral over [a, b] (a < b, inside |l| <= l2, S >= 1 on it):
-// FP64: the closed form (odd in l); FP32: Gauss-Legendre on the factored integrand.
-__device__ __forceinline__ double shell_part(double r0, double R0, double A, double c2, double c, double dsing,
-                                             double a, double b, const Trans<double> *t1, Work &wk)
+__device__ __forceinline__ float shell_quad_t(float r0, float R0, float c2, float dsing, float a, float b, Work &wk)
 {
-    (void)dsing;
-    double q[2];
-    const double xs[2] = {fabs(a), fabs(b)};
-#pragma unroll
-    for (int e = 0; e < 2; e++) {
-        const double x = xs[e];
-        double v = 0.0;
-        if (x > 0.0) {
-            if (t1 && x == t1->x) {
-                v = core_shell<double>(*t1, r0, R0, A, c2);
-            } else {
-                const double S = sqrt(c2 + x * x);
-                v = core_shell<double>(trans<double>(r0, R0, c2, c, x, S, wk), r0, R0, A, c2);
-            }
-        }
-        q[e] = v;
-    }
-    return (b < 0.0 ? -q[1] : q[1]) - (a < 0.0 ? -q[0] : q[0]);
-}
-
-__device__ __forceinline__ float shell_part(float r0, float R0, float A, float c2, float c, float dsing, float a,
-                                            float b, const Trans<float> *, Work &wk)
-{
-    (void)A;
-    (void)c;
     return shell_quad(r0, R0, c2, dsing, a, b, wk);
 }
 
+__device__ __forceinline__ double shell_quad_t(double, double, double, double, double, double, Work &)
+{
+    return 0.0;
+}
+
 // pi [Qt(l_b) - Qt(l_a)] for one directed edge (R0 > 0), lengths in units of h:
-// the edge's whole share of pi int (G_c(S) - G_c(r0)) dalpha, split into the
-// parts of the edge line beyond the support, in the shell and in the inner ball.
+// the edge's whole share of pi int (G_c(S) - G_c(r0)) dalpha.  The signed edge
+// interval is cut at the support crossings +-l2 and (when c < 1) the inner
+// crossings +-l1 into parts beyond the support (-H times their angle), shell
+// parts and an inner part (closed forms at their endpoints, odd in l; the
+// FP32 path integrates shell parts by quadrature instead), plus the piece
+// correction dH times the angle of the shell parts when r0 < 1.
+//
+// All cases are expressed as one fixed list of tasks - up to 4 angles, 3
+// closed-form points (|l_a|, |l_b| clamped, and l1; each point serves both
+// piece polynomials with its own weights) and 2 quadrature intervals - so that
+// the lanes of a wavefront, which hold different particles, run each task
+// type in the same code instead of one branch per geometric case.
+template <typename R>
+__device__ __forceinline__ R sgnr(R x)
+{
+    return x > R(0) ? R(1) : (x < R(0) ? R(-1) : R(0));
+}
+
 template <typename R>
 __device__ __forceinline__ R edge_term(R r0, R R0, R la, R lb, R Ht, R dH, Work &wk)
 {
+    constexpr bool kQuad = std::is_same<R, float>::value;
     const R A = r0 * r0;
     const R c2 = A + R0 * R0;
-    if (!(c2 < R(4))) return -Ht * seg_angle<R>(R0, la, lb, wk);
-    wk.eterms++;
-    const R l2 = f_sqrt(R(4) - c2);
-    const R c = f_sqrt(c2);
-    R tot = R(0);
-    if (la < -l2) tot -= Ht * seg_angle<R>(R0, la, fmin(lb, -l2), wk);
-    if (lb > l2) tot -= Ht * seg_angle<R>(R0, fmax(la, l2), lb, wk);
-    if (c2 >= R(1)) {
-        const R a = fmax(la, -l2), b = fmin(lb, l2);
-        if (b > a) {
-            tot += shell_part(r0, R0, A, c2, c, c, a, b, (const Trans<R> *)nullptr, wk);
-            if (dH != R(0)) tot += dH * seg_angle<R>(R0, a, b, wk);
+    // angle tasks: (a, b, weight)
+    R aa0 = la, ab0 = lb, aw0 = R(0), aa1 = R(0), ab1 = R(0), aw1 = R(0);
+    R aa2 = R(0), ab2 = R(0), aw2 = R(0), aa3 = R(0), ab3 = R(0), aw3 = R(0);
+    // closed-form point weights (inner, shell) at |ca|, |cb| and l1
+    R wi0 = R(0), wi1 = R(0), wi2 = R(0), ws0 = R(0), ws1 = R(0), ws2 = R(0);
+    // quadrature intervals
+    R qa0 = R(0), qb0 = R(0), qa1 = R(0), qb1 = R(0);
+    bool q0 = false, q1 = false;
+    R l2 = R(0), c = R(1), l1 = R(0), ca = la, cb = lb;
+    if (!(c2 < R(4))) {
+        aw0 = -Ht;  // the whole edge lies beyond the support
+    } else {
+        wk.eterms++;
+        l2 = f_sqrt(R(4) - c2);
+        c = f_sqrt(c2);
+        ca = fmin(fmax(la, -l2), l2);
+        cb = fmin(fmax(lb, -l2), l2);
+        if (la < -l2) {
+            aw0 = -Ht;
+            ab0 = fmin(lb, -l2);
         }
-        return tot;
-    }
-    const R l1 = f_sqrt(R(1) - c2);
-    const bool need1 = (la < -l1) || (lb > l1);
-    Trans<R> t1;
-    if (need1) t1 = trans<R>(r0, R0, c2, c, l1, R(1), wk);
-    // shell parts on either side of the inner ball
-    R a = fmax(la, -l2), b = fmin(lb, -l1);
-    if (b > a) {
-        tot += shell_part(r0, R0, A, c2, c, R(1), a, b, &t1, wk);
-        if (dH != R(0)) tot += dH * seg_angle<R>(R0, a, b, wk);
-    }
-    a = fmax(la, l1);
-    b = fmin(lb, l2);
-    if (b > a) {
-        tot += shell_part(r0, R0, A, c2, c, R(1), a, b, &t1, wk);
-        if (dH != R(0)) tot += dH * seg_angle<R>(R0, a, b, wk);
-    }
-    // inner part
-    a = fmax(la, -l1);
-    b = fmin(lb, l1);
-    if (b > a) {
-        R q[2];
-        const R xs[2] = {fabs(a), fabs(b)};
-#pragma unroll
-        for (int e = 0; e < 2; e++) {
-            const R x = xs[e];
-            R v = R(0);
-            if (x > R(0)) {
-                if (need1 && x == l1) v = core_inner<R>(t1, r0, R0, A, c2);
-                else v = core_inner<R>(trans<R>(r0, R0, c2, c, x, f_sqrt(c2 + x * x), wk), r0, R0, A, c2);
+        if (lb > l2) {
+            aa1 = fmax(la, l2);
+            ab1 = lb;
+            aw1 = -Ht;
+        }
+        if (c2 >= R(1)) {
+            if (cb > ca) {
+                if (kQuad) {
+                    q0 = true;
+                    qa0 = ca;
+                    qb0 = cb;
+                } else {
+                    ws1 += sgnr(cb);
+                    ws0 -= sgnr(ca);
+                }
+                aa2 = ca;
+                ab2 = cb;
+                aw2 = dH;
             }
-            q[e] = v;
+        } else {
+            l1 = f_sqrt(R(1) - c2);
+            // left shell part [max(ca, -l2), min(cb, -l1)]
+            if (ca < -l1) {
+                const R B = fmin(cb, -l1);
+                if (kQuad) {
+                    q0 = true;
+                    qa0 = ca;
+                    qb0 = B;
+                } else {
+                    ws0 -= sgnr(ca);
+                    if (B == cb) ws1 += sgnr(cb);
+                    else ws2 -= R(1);  // B = -l1
+                }
+                aa2 = ca;
+                ab2 = B;
+                aw2 = dH;
+            }
+            // right shell part [max(ca, l1), min(cb, l2)]
+            if (cb > l1) {
+                const R Aq = fmax(ca, l1);
+                if (kQuad) {
+                    q1 = true;
+                    qa1 = Aq;
+                    qb1 = cb;
+                } else {
+                    ws1 += sgnr(cb);
+                    if (Aq == ca) ws0 -= sgnr(ca);
+                    else ws2 -= R(1);  // A = +l1
+                }
+                aa3 = Aq;
+                ab3 = cb;
+                aw3 = dH;
+            }
+            // inner part [max(ca, -l1), min(cb, l1)]
+            const R Ai = fmax(ca, -l1), Bi = fmin(cb, l1);
+            if (Bi > Ai) {
+                if (Bi == cb) wi1 += sgnr(cb);
+                else wi2 += R(1);  // B = +l1
+                if (Ai == ca) wi0 -= sgnr(ca);
+                else wi2 += R(1);  // A = -l1: -sgn(A) core(l1) = +core(l1)
+            }
         }
-        tot += (b < R(0) ? -q[1] : q[1]) - (a < R(0) ? -q[0] : q[0]);
+    }
+    R tot = R(0);
+    if (aw0 != R(0)) tot += aw0 * seg_angle<R>(R0, aa0, ab0, wk);
+    if (aw1 != R(0)) tot += aw1 * seg_angle<R>(R0, aa1, ab1, wk);
+    if (aw2 != R(0)) tot += aw2 * seg_angle<R>(R0, aa2, ab2, wk);
+    if (aw3 != R(0)) tot += aw3 * seg_angle<R>(R0, aa3, ab3, wk);
+    const R x0 = fabs(ca), x1 = fabs(cb);
+    if ((wi0 != R(0) || ws0 != R(0)) && x0 > R(0)) {
+        const Trans<R> t = trans<R>(r0, R0, c2, c, x0, x0 == l2 ? R(2) : f_sqrt(c2 + x0 * x0), wk);
+        tot += wi0 * core_inner<R>(t, r0, R0, A, c2) + ws0 * core_shell<R>(t, r0, R0, A, c2);
+    }
+    if ((wi1 != R(0) || ws1 != R(0)) && x1 > R(0)) {
+        const Trans<R> t = trans<R>(r0, R0, c2, c, x1, x1 == l2 ? R(2) : f_sqrt(c2 + x1 * x1), wk);
+        tot += wi1 * core_inner<R>(t, r0, R0, A, c2) + ws1 * core_shell<R>(t, r0, R0, A, c2);
+    }
+    if (wi2 != R(0) || ws2 != R(0)) {
+        const Trans<R> t = trans<R>(r0, R0, c2, c, l1, R(1), wk);
+        tot += wi2 * core_inner<R>(t, r0, R0, A, c2) + ws2 * core_shell<R>(t, r0, R0, A, c2);
+    }
+    if (kQuad) {
+        if (q0) tot += shell_quad_t(r0, R0, c2, c2 >= R(1) ? c : R(1), qa0, qb0, wk);
+        if (q1) tot += shell_quad_t(r0, R0, c2, R(1), qa1, qb1, wk);
     }
     return tot;
 }
@@ -396,8 +447,8 @@ __global__ void __launch_bounds__(256) k_integrate_flat(int64_t np, const uint32
 
 // Persistent form: each wavefront takes tiles of 64*tile_waves consecutive
 // (cell-ordered) pairs from a queue until the pairs run out.
-template <int PREC>
-__global__ void __launch_bounds__(256) k_integrate_persistent(int64_t np, const uint32_t *__restrict__ pair_p,
+template <int PREC, int WPE>
+__global__ void __launch_bounds__(256, WPE) k_integrate_persistent(int64_t np, const uint32_t *__restrict__ pair_p,
                                                                const uint32_t *__restrict__ pair_c,
                                                                const double *__restrict__ xyz,
                                                                const double *__restrict__ h,
@@ -422,6 +473,107 @@ __global__ void __launch_bounds__(256) k_integrate_persistent(int64_t np, const 
             const int64_t k = base + 64 * w + lane;
             if (k < np) f[k] = one_pair<PREC>(k, pair_p, pair_c, xyz, h, cfo, fvo, plane, edges, wk, fx);
         }
+    }
+    flush_work(wk, counters);
+}
+
+// ---------------------------------------------------------------- cell tiles
+// A tile is up to 64 consecutive pairs of one cell (key = cell << 32 | tile
+// index within the cell).  A wavefront integrating a tile shares the cell, so
+// the cell's walls and edge records are wave-uniform: they are read with
+// scalar loads into scalar registers, and the face/edge loops are uniform.
+__global__ void k_tile_counts(int64_t n_cells, const int64_t *__restrict__ coff, int64_t *__restrict__ tcnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_cells) tcnt[i] = (coff[i + 1] - coff[i] + 63) / 64;
+}
+
+__global__ void k_tile_fill(int64_t n_cells, const int64_t *__restrict__ toff, uint64_t *__restrict__ tiles)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_cells) return;
+    for (int64_t u = 0; u < toff[i + 1] - toff[i]; u++) tiles[toff[i] + u] = ((uint64_t)i << 32) | (uint64_t)u;
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(256) k_integrate_tiles(int64_t n_tiles, const uint64_t *__restrict__ tiles,
+                                                          const int64_t *__restrict__ coff,
+                                                          const uint32_t *__restrict__ pair_p,
+                                                          const double *__restrict__ xyz,
+                                                          const double *__restrict__ h,
+                                                          const int64_t *__restrict__ cfo,
+                                                          const int64_t *__restrict__ fvo,
+                                                          const double *__restrict__ plane,
+                                                          const EdgeRec *__restrict__ edges, double *__restrict__ f,
+                                                          unsigned long long *counters, unsigned *tile_ctr, FixList fx)
+{
+    using R = typename std::conditional<PREC == MAP_FP64, double, float>::type;
+    const int lane = threadIdx.x & 63;
+    Work wk;
+    for (;;) {
+        unsigned t = 0;
+        if (lane == 0) t = atomicAdd(tile_ctr, 1u);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if ((int64_t)t >= n_tiles) break;
+        const uint64_t key = tiles[t];
+        const int64_t cell = uniform64((int64_t)(key >> 32));
+        const int64_t start = uniform64(coff[cell] + 64 * (int64_t)(key & 0xffffffffu));
+        const int64_t end = uniform64(coff[cell + 1]);
+        const int64_t k = start + lane;
+        const bool active = k < end;
+        double px = 0.0, py = 0.0, pz = 0.0, hh = 1.0;
+        if (active) {
+            const int64_t a = pair_p[k];
+            px = xyz[3 * a];
+            py = xyz[3 * a + 1];
+            pz = xyz[3 * a + 2];
+            hh = h[a];
+        }
+        const double invh = 1.0 / hh;
+        bool inside = true;
+        double acc = 0.0;
+        const int64_t f0 = uniform64(cfo[cell]), f1 = uniform64(cfo[cell + 1]);
+        for (int64_t j = f0; j < f1; j++) {
+            const double nx = plane[4 * j], ny = plane[4 * j + 1], nz = plane[4 * j + 2], cj = plane[4 * j + 3];
+            const double d = cj - (nx * px + ny * py + nz * pz);
+            wk.faces += active;
+            const bool in_j = d >= 0.0;
+            inside = inside && in_j;
+            const double r0d = fabs(d) * invh;
+            const int64_t s0 = uniform64(fvo[j]), s1 = uniform64(fvo[j + 1]);
+            if (active && r0d < 2.0) {
+                const R r0 = (R)r0d;
+                const R Ht = pi_H<R>(r0);
+                const R dH = pi_dH<R>(r0);
+                double face = 0.0;
+                for (int64_t s = s0; s < s1; s++) {
+                    const EdgeRec &E = edges[s];
+                    const double wx = px - E.vx, wy = py - E.vy, wz = pz - E.vz;
+                    const double rho = E.mx * wx + E.my * wy + E.mz * wz;
+                    wk.edges++;
+                    if (rho == 0.0) continue;
+                    const double la = -(E.ex * wx + E.ey * wy + E.ez * wz) * invh;
+                    const double lb = la + E.L * invh;
+                    const double R0d = fabs(rho) * invh;
+                    if (PREC == MAP_MIXED && needs_fp64(r0d, R0d, r0d * r0d + R0d * R0d)) {
+                        const unsigned slot = atomicAdd(fx.count, 1u);
+                        if (slot < fx.cap) fx.items[slot] = ((uint64_t)k << 32) | (uint64_t)(uint32_t)s;
+                        continue;
+                    }
+                    const R tv = edge_term<R>(r0, (R)R0d, (R)la, (R)lb, Ht, dH, wk);
+                    face += (rho > 0.0) ? (double)tv : -(double)tv;
+                }
+                acc += in_j ? face : -face;
+            }
+        }
+        if (active) f[k] = (inside ? 1.0 : 0.0) - acc * kInvPi;
     }
     flush_work(wk, counters);
 }
@@ -464,6 +616,27 @@ __global__ void k_fixup_apply(int64_t n_fix, const uint64_t *__restrict__ keys, 
 
 }  // namespace
 
+void build_tiles(Workspace &ws, const DevInputs &in, PairSet &ps, hipStream_t s)
+{
+    const int64_t nc = in.n_cells;
+    ps.n_tiles = 0;
+    if (nc == 0 || ps.n_pairs == 0) return;
+    int64_t *tcnt = ws.get<int64_t>(S_TILE_CNT, (size_t)nc);
+    int64_t *toff = ws.get<int64_t>(S_TILE_OFF, (size_t)nc + 1);
+    hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, nc, ps.coff, tcnt);
+    EM_HIP(hipGetLastError());
+    scan_counts(ws, tcnt, toff, nc, s);
+    int64_t nt = 0;
+    EM_HIP(hipMemcpyAsync(&nt, toff + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    EM_HIP(hipStreamSynchronize(s));
+    uint64_t *tiles = ws.get<uint64_t>(S_TILES, (size_t)(nt > 0 ? nt : 1));
+    hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, nc, (const int64_t *)toff,
+                       tiles);
+    EM_HIP(hipGetLastError());
+    ps.tiles = tiles;
+    ps.n_tiles = nt;
+}
+
 void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, int precision,
                       const IntegrateTune &tune, double *f, int64_t *counters, uint32_t *tile_ctr,
                       uint64_t *fix_items, int64_t fix_cap, hipStream_t s)
@@ -488,18 +661,42 @@ void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &
         EM_HIP(hipGetLastError());
         return;
     }
+    if (tune.persistent == 2 && ps.tiles) {
+        int64_t g = (int64_t)device_cu_count() * (tune.grid_per_cu > 0 ? tune.grid_per_cu : 8);
+        int64_t need = (ps.n_tiles + (block / 64) - 1) / (block / 64);
+        if (g > need) g = need;
+        if (g < 1) g = 1;
+        if (precision == MAP_FP64)
+            hipLaunchKernelGGL(k_integrate_tiles<MAP_FP64>, dim3((unsigned)g), dim3(block), 0, s, ps.n_tiles,
+                               ps.tiles, ps.coff, ps.pair_p, in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt,
+                               tile_ctr, fx);
+        else
+            hipLaunchKernelGGL(k_integrate_tiles<MAP_MIXED>, dim3((unsigned)g), dim3(block), 0, s, ps.n_tiles,
+                               ps.tiles, ps.coff, ps.pair_p, in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt,
+                               tile_ctr, fx);
+        EM_HIP(hipGetLastError());
+        return;
+    }
     const int tw = tune.tile_waves > 0 ? tune.tile_waves : 1;
     int64_t tiles = (np + 64 * tw - 1) / (64 * tw);
     int64_t g = (int64_t)device_cu_count() * (tune.grid_per_cu > 0 ? tune.grid_per_cu : 8);
     int64_t need = (tiles + (block / 64) - 1) / (block / 64);
     if (g > need) g = need;
     if (g < 1) g = 1;
-    if (precision == MAP_FP64)
-        hipLaunchKernelGGL(k_integrate_persistent<MAP_FP64>, dim3((unsigned)g), dim3(block), 0, s, np, ps.pair_p,
-                           ps.pair_c, in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, tile_ctr, tw, fx);
-    else
-        hipLaunchKernelGGL(k_integrate_persistent<MAP_MIXED>, dim3((unsigned)g), dim3(block), 0, s, np, ps.pair_p,
-                           ps.pair_c, in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, tile_ctr, tw, fx);
+#define EM_LAUNCH_P(P, W)                                                                                         \
+    hipLaunchKernelGGL((k_integrate_persistent<P, W>), dim3((unsigned)g), dim3(block), 0, s, np, ps.pair_p,      \
+                       ps.pair_c, in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, tile_ctr, tw, fx)
+    const int w = tune.waves;
+    if (precision == MAP_FP64) {
+        if (w >= 4) EM_LAUNCH_P(MAP_FP64, 4);
+        else if (w == 3) EM_LAUNCH_P(MAP_FP64, 3);
+        else EM_LAUNCH_P(MAP_FP64, 2);
+    } else {
+        if (w >= 6) EM_LAUNCH_P(MAP_MIXED, 6);
+        else if (w == 5) EM_LAUNCH_P(MAP_MIXED, 5);
+        else EM_LAUNCH_P(MAP_MIXED, 4);
+    }
+#undef EM_LAUNCH_P
     EM_HIP(hipGetLastError());
 }
 

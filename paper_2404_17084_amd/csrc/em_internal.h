@@ -66,7 +66,7 @@ enum Slot : int {
     S_KEY2, S_PERM, S_PAIR_C, S_PAIR_P, S_CCNT, S_CCNT64, S_COFF,
     S_F, S_F_PM, S_S, S_MCELL, S_RHO, S_RED,
     S_FIX_ITEMS, S_FIX_VALS, S_FIX_KEY2, S_FIX_VAL2,
-    S_SCAN_TMP, S_SORT_HIST, S_TILE_CTR,
+    S_SCAN_TMP, S_SORT_HIST, S_TILE_CTR, S_TILE_CNT, S_TILE_OFF, S_TILES,
     S_PSEUDO0, S_PSEUDO1, S_PSEUDO2, S_PSEUDO3, S_PSEUDO4, S_PSEUDO5, S_PSEUDO6, S_PSEUDO7,
     S_PSEUDO8, S_PSEUDO9, S_PSEUDO10, S_PSEUDO11, S_PSEUDO12, S_PSEUDO13, S_PSEUDO14, S_PSEUDO15,
     S_NUM_SLOTS
@@ -126,7 +126,9 @@ struct IntegrateTune {
     int block = 256;       // threads per workgroup
     int tile_waves = 1;    // wavefronts of pairs per tile taken from the queue
     int grid_per_cu = 8;   // persistent workgroups per compute unit
-    int persistent = 1;    // 1: persistent tile queue, 0: one thread per pair
+    int persistent = 1;    // 2: persistent queue of cell tiles, 1: persistent queue of pair tiles,
+                           // 0: one thread per pair
+    int waves = 0;         // register budget as waves per SIMD (FP64: 2-4, mixed: 4-6; 0 = lowest)
 };
 
 // ---------------------------------------------------------------- primitives (em_primitives.hip)
@@ -156,10 +158,14 @@ struct PairSet {
     const uint32_t *perm = nullptr;    // cell-major index -> particle-major index
     const int64_t *poff = nullptr;     // particle-major offsets (n+1)
     const int64_t *coff = nullptr;     // cell-major offsets (n_cells+1)
+    const uint64_t *tiles = nullptr;   // cell tiles of <= 64 pairs (cell << 32 | index)
+    int64_t n_tiles = 0;
 };
-PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, int64_t *counters, hipStream_t s);
+PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, const EdgeRec *edges,
+                    int64_t *counters, hipStream_t s);
 
 // em_integrate.hip: raw f per pair (cell-major order).
+void build_tiles(Workspace &ws, const DevInputs &in, PairSet &ps, hipStream_t s);
 void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, int precision,
                       const IntegrateTune &tune, double *f, int64_t *counters, uint32_t *tile_ctr,
                       uint64_t *fix_items, int64_t fix_cap, hipStream_t s);

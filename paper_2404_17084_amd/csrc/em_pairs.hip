@@ -30,8 +30,7 @@ struct Box {
 // multiplies and divides in a fixed order, without fused multiply-adds, so
 // that the decision dist^2 < (2h)^2 is reproducible on any IEEE machine.
 __device__ __noinline__ double cell_dist2(double px, double py, double pz, int64_t cell, const int64_t *cfo,
-                                          const int64_t *fvo, const int32_t *fv, const double *plane,
-                                          const double *verts)
+                                          const int64_t *fvo, const EdgeRec *edges, const double *plane)
 {
 #pragma clang fp contract(off)
     bool inside = true;
@@ -45,10 +44,11 @@ __device__ __noinline__ double cell_dist2(double px, double py, double pz, int64
         int64_t nv = k1 - k0;
         bool left = true;
         for (int64_t k = 0; k < nv; k++) {
-            const double *a = verts + 3 * (int64_t)fv[k0 + k];
-            const double *b = verts + 3 * (int64_t)fv[k0 + (k + 1 == nv ? 0 : k + 1)];
-            double ex = b[0] - a[0], ey = b[1] - a[1], ez = b[2] - a[2];
-            double wx = px - a[0], wy = py - a[1], wz = pz - a[2];
+            // edge records hold exact copies of the vertex coordinates
+            const EdgeRec &A = edges[k0 + k];
+            const EdgeRec &B = edges[k0 + (k + 1 == nv ? 0 : k + 1)];
+            double ex = B.vx - A.vx, ey = B.vy - A.vy, ez = B.vz - A.vz;
+            double wx = px - A.vx, wy = py - A.vy, wz = pz - A.vz;
             double cr = (ey * wz - ez * wy) * n0 + (ez * wx - ex * wz) * n1 + (ex * wy - ey * wx) * n2;
             if (cr < 0.0) {
                 left = false;
@@ -61,10 +61,10 @@ __device__ __noinline__ double cell_dist2(double px, double py, double pz, int64
         } else {
             dd = INFINITY;
             for (int64_t k = 0; k < nv; k++) {
-                const double *a = verts + 3 * (int64_t)fv[k0 + k];
-                const double *b = verts + 3 * (int64_t)fv[k0 + (k + 1 == nv ? 0 : k + 1)];
-                double ex = b[0] - a[0], ey = b[1] - a[1], ez = b[2] - a[2];
-                double wx = px - a[0], wy = py - a[1], wz = pz - a[2];
+                const EdgeRec &A = edges[k0 + k];
+                const EdgeRec &B = edges[k0 + (k + 1 == nv ? 0 : k + 1)];
+                double ex = B.vx - A.vx, ey = B.vy - A.vy, ez = B.vz - A.vz;
+                double wx = px - A.vx, wy = py - A.vy, wz = pz - A.vz;
                 double ee = ex * ex + ey * ey + ez * ez;
                 double t = 0.0;
                 if (ee > 0.0) {
@@ -194,15 +194,16 @@ __global__ void k_candidates(int64_t n, const double *__restrict__ xyz, const do
     if (!FILL) ccount[a] = count;
 }
 
-// One thread per candidate: 1 if the pair exists.  A cell whose whole bounding
-// box lies within 0.999999 * 2h of the particle is accepted without the exact
-// test (its exact distance is then certainly below 2h); otherwise the exact
-// test decides.
+// One thread per candidate: 1 if the pair exists.  A cell is accepted without
+// the exact test when an interior point of it (the mean of its wall vertices)
+// or its whole bounding box lies within (1 - 1e-6) 2h of the particle: its
+// distance is then certainly below 2h.  Otherwise the exact test decides.
 __global__ void k_exact(int64_t nc_total, const uint32_t *__restrict__ cand_c, const uint32_t *__restrict__ cand_p,
                         const double *__restrict__ xyz, const double *__restrict__ h,
-                        const double *__restrict__ aabb, const int64_t *__restrict__ cfo,
-                        const int64_t *__restrict__ fvo, const int32_t *__restrict__ fv,
-                        const double *__restrict__ plane, const double *__restrict__ verts, int64_t *__restrict__ flag,
+                        const double *__restrict__ aabb, const double *__restrict__ centre,
+                        const int64_t *__restrict__ cfo, const int64_t *__restrict__ fvo,
+                        const EdgeRec *__restrict__ edges,
+                        const double *__restrict__ plane, int64_t *__restrict__ flag,
                         unsigned long long *exact_counter)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -216,12 +217,13 @@ __global__ void k_exact(int64_t nc_total, const uint32_t *__restrict__ cand_c, c
         const double fx = fmax(fabs(bb[0] - px), fabs(bb[3] - px));
         const double fy = fmax(fabs(bb[1] - py), fabs(bb[4] - py));
         const double fz = fmax(fabs(bb[2] - pz), fabs(bb[5] - pz));
+        const double gx = centre[3 * c] - px, gy = centre[3 * c + 1] - py, gz = centre[3 * c + 2] - pz;
         int64_t ok;
-        if (fx * fx + fy * fy + fz * fz < r2 * 0.999998) {
+        if (fx * fx + fy * fy + fz * fz < r2 * 0.999998 || gx * gx + gy * gy + gz * gz < r2 * 0.999998) {
             ok = 1;
         } else {
             tested = 1;
-            ok = cell_dist2(px, py, pz, c, cfo, fvo, fv, plane, verts) < r2 ? 1 : 0;
+            ok = cell_dist2(px, py, pz, c, cfo, fvo, edges, plane) < r2 ? 1 : 0;
         }
         flag[q] = ok;
     }
@@ -270,7 +272,8 @@ static int bits_for(uint64_t maxval)
     return b;
 }
 
-PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, int64_t *counters, hipStream_t s)
+PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, const EdgeRec *edges,
+                    int64_t *counters, hipStream_t s)
 {
     PairSet ps;
     const int64_t n = in.n, nc = in.n_cells;
@@ -337,8 +340,8 @@ PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, int6
     unsigned long long *cand = reinterpret_cast<unsigned long long *>(counters + C_CANDIDATES);
     if (ncand > 0) {
         hipLaunchKernelGGL(k_exact, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand,
-                           (const uint32_t *)cand_c, (const uint32_t *)cand_p, in.xyz, in.h, aabb, in.cfo, in.fvo,
-                           in.fv, in.plane, in.verts, flag, cand);
+                           (const uint32_t *)cand_c, (const uint32_t *)cand_p, in.xyz, in.h, aabb, aabb + 6 * nc,
+                           in.cfo, in.fvo, edges, in.plane, flag, cand);
         EM_HIP(hipGetLastError());
     }
     scan_counts(ws, flag, fpos, ncand, s);
