@@ -92,6 +92,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the mapping runs on a single "
@@ -115,8 +116,14 @@ def main():
     mapper = em.Mapper(device=0)
     results = {}
     Ms = {}
+    tuned = {}
     for prec, name in ((em.MAP_FP64, "fp64"), (em.MAP_MIXED, "mixed")):
         mapper.set_precision(prec)
+        if not args.no_tune:
+            shape, ms = em.map_autotune(mapper.ctx, xyz, m, h, dc, prec)
+            tuned[name] = {"waves": shape[0], "tile_waves": shape[1], "grid_per_cu": shape[2],
+                           "distribution": shape[3], "ms_integrate": ms}
+            print(f"bench: autotuned {name}: {tuned[name]}", file=sys.stderr, flush=True)
         for _ in range(args.warmup):
             em.map_particles(mapper.ctx, xyz, m, h, dc, M, rho, S)
         torch.cuda.synchronize()
@@ -170,6 +177,7 @@ def main():
         "mixed_vs_fp64_max_cell_rel": float(rel.max()),
         "mass_err_mixed": mx["mass_err"],
         "stages_ms_mixed": {k: mx[k] for k in ("ms_setup", "ms_pairs", "ms_integrate", "ms_reduce")},
+        "launch_shape": tuned,
         "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32, "unit": "TFLOP/s", "frac": ach / PEAK_FP32,
                      "traffic": None},
     }

@@ -143,17 +143,31 @@ const char *map_last_error(map_ctx *ctx);
 int map_set_precision(map_ctx *ctx, int precision);
 
 /*
- * Launch shape of the integration kernel (the autotuner's knobs): register
- * budget as resident wavefronts per SIMD (0 = compiler default; FP64 kernel
- * 2..4, mixed kernel 4..6), wavefronts of consecutive pairs taken per queue
- * pop (1..64), persistent workgroups of 256 threads per compute unit (1..64),
- * and the work distribution: 1 = persistent queue of pair tiles, 2 =
- * persistent queue of single-cell tiles, 0 = one thread per pair.  For a given
- * distribution, results are bitwise independent of the other knobs and of
- * scheduling; the distributions are separate kernels and agree to rounding.
+ * Launch shape of the integration kernel for one precision (the autotuner's
+ * knobs): register budget as resident wavefronts per SIMD (0 = compiler
+ * default; FP64 kernel 2..4, mixed kernel 4..6), wavefronts of consecutive
+ * pairs taken per queue pop (1..64), persistent workgroups of 256 threads per
+ * compute unit (1..64), and the work distribution: 1 = persistent queue of
+ * pair tiles, 2 = persistent queue of single-cell tiles, 0 = one thread per
+ * pair, -1 = clear the explicit setting (back to the tuned table/default).
+ * For a given distribution, results are bitwise independent of the other
+ * knobs and of scheduling; the distributions are separate kernels and agree
+ * to rounding.  map_get_tune reports the shape used for n_pairs pairs.
  */
-int map_set_tune(map_ctx *ctx, int waves, int tile_waves, int grid_per_cu, int persistent);
-int map_get_tune(map_ctx *ctx, int *waves, int *tile_waves, int *grid_per_cu, int *persistent);
+int map_set_tune(map_ctx *ctx, int precision, int waves, int tile_waves, int grid_per_cu, int persistent);
+int map_get_tune(map_ctx *ctx, int precision, int64_t n_pairs, int *waves, int *tile_waves, int *grid_per_cu,
+                 int *persistent);
+
+/*
+ * Autotuner: builds the pair set of (p, c), times every candidate launch shape
+ * of the integration kernel at the given precision on the device, and stores
+ * the fastest for the pair count's size class (and in cfg->tune_cache_path,
+ * one line per entry, when set; the file is read back by map_init).  best[4]
+ * receives (waves, tile_waves, grid_per_cu, persistent); *best_ms the
+ * integration time of that shape.  Either may be NULL.
+ */
+int map_autotune(map_ctx *ctx, const map_particles_in *p, const map_cells_in *c, int precision, int *best,
+                 double *best_ms);
 
 /*
  * Pair set of Sec. II-B: every (particle a, cell i) with dist(r_a, cell i) < 2h_a,

@@ -85,8 +85,10 @@ _SIGS = {
     "map_shutdown": (c_int, [c_vp]),
     "map_last_error": (ctypes.c_char_p, [c_vp]),
     "map_set_precision": (c_int, [c_vp, c_int]),
-    "map_set_tune": (c_int, [c_vp, c_int, c_int, c_int, c_int]),
-    "map_get_tune": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "map_set_tune": (c_int, [c_vp, c_int, c_int, c_int, c_int, c_int]),
+    "map_get_tune": (c_int, [c_vp, c_int, c_i64, c_vp, c_vp, c_vp, c_vp]),
+    "map_autotune": (c_int, [c_vp, ctypes.POINTER(map_particles_in), ctypes.POINTER(map_cells_in), c_int, c_vp,
+                             c_vp]),
     "map_pairs": (c_int, [c_vp, ctypes.POINTER(map_particles_in), ctypes.POINTER(map_cells_in), c_vp, c_vp, c_vp,
                           c_i64]),
     "map_particles": (c_int, [c_vp, ctypes.POINTER(map_particles_in), ctypes.POINTER(map_cells_in),
@@ -207,14 +209,26 @@ def map_set_precision(ctx, precision: int):
     _check(ctx, load().map_set_precision(ctx, precision))
 
 
-def map_set_tune(ctx, waves=0, tile_waves=1, grid_per_cu=8, persistent=1):
-    _check(ctx, load().map_set_tune(ctx, waves, tile_waves, grid_per_cu, persistent))
+def map_set_tune(ctx, precision, waves=0, tile_waves=1, grid_per_cu=8, persistent=1):
+    """Explicit launch shape for one precision; persistent=-1 clears it."""
+    _check(ctx, load().map_set_tune(ctx, precision, waves, tile_waves, grid_per_cu, persistent))
 
 
-def map_get_tune(ctx):
+def map_get_tune(ctx, precision, n_pairs=1):
     v = [c_int() for _ in range(4)]
-    _check(ctx, load().map_get_tune(ctx, *[ctypes.byref(x) for x in v]))
+    _check(ctx, load().map_get_tune(ctx, precision, n_pairs, *[ctypes.byref(x) for x in v]))
     return tuple(x.value for x in v)
+
+
+def map_autotune(ctx, xyz, m, h, cells, precision):
+    """Times the candidate launch shapes; returns ((waves, tile_waves, grid_per_cu, persistent), ms)."""
+    lib = load()
+    P, k1 = particles_in(xyz, m, h)
+    C, k2 = cells_in(cells)
+    best = (c_int * 4)()
+    ms = c_dbl()
+    _check(ctx, lib.map_autotune(ctx, ctypes.byref(P), ctypes.byref(C), precision, best, ctypes.byref(ms)))
+    return tuple(best), ms.value
 
 
 def map_pairs(ctx, xyz, m, h, cells, want_pairs: bool = True):

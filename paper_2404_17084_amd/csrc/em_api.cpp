@@ -23,6 +23,10 @@ Ctx::Ctx(const map_config *cfg) : ws(cfg ? cfg->device : 0)
     EM_HIP(hipSetDevice(device));
     EM_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
     for (auto &e : ev) EM_HIP(hipEventCreate(&e));
+    hipDeviceProp_t prop;
+    EM_HIP(hipGetDeviceProperties(&prop, device));
+    arch = prop.gcnArchName;
+    tune_cache_load(*this);
 }
 
 Ctx::~Ctx()
@@ -166,14 +170,15 @@ void run_mapping(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cel
     prepare(C, ws, p, c, in, edges, aabb, flags, counters, s);
     if (timed) EM_HIP(hipEventRecord(C.ev[1], s));
     PairSet ps = build_pairs(ws, in, aabb, edges, counters, s);
-    if (C.tune.persistent == 2) build_tiles(ws, in, ps, s);
+    const IntegrateTune tune = pick_tune(C, precision, ps.n_pairs);
+    if (tune.persistent == 2) build_tiles(ws, in, ps, s);
     if (timed) EM_HIP(hipEventRecord(C.ev[2], s));
     const int64_t np = ps.n_pairs;
     double *f = ws.get<double>(S_F, (size_t)(np > 0 ? np : 1));
     uint32_t *tile_ctr = ws.get<uint32_t>(S_TILE_CTR, 64);
     const int64_t fix_cap = np / 8 + 65536;
     uint64_t *fix_items = ws.get<uint64_t>(S_FIX_ITEMS, (size_t)fix_cap);
-    launch_integrate(in, edges, ps, precision, C.tune, f, counters, tile_ctr, fix_items, fix_cap, s);
+    launch_integrate(in, edges, ps, precision, tune, f, counters, tile_ctr, fix_items, fix_cap, s);
     if (timed) EM_HIP(hipEventRecord(C.ev[3], s));
     int64_t n_fix = 0;
     if (precision == MAP_MIXED && np > 0) {
@@ -183,7 +188,10 @@ void run_mapping(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cel
         n_fix = hfix;
         if (n_fix > fix_cap) {
             // too many flagged edges for the fixup list: redo every pair in FP64
-            launch_integrate(in, edges, ps, MAP_FP64, C.tune, f, counters, tile_ctr, fix_items, fix_cap, s);
+            IntegrateTune t64 = tune;
+            t64.waves = 0;
+            if (t64.persistent == 2) t64.persistent = 1;
+            launch_integrate(in, edges, ps, MAP_FP64, t64, f, counters, tile_ctr, fix_items, fix_cap, s);
         } else if (n_fix > 0) {
             uint32_t *iv = ws.get<uint32_t>(S_FIX_VAL2, (size_t)n_fix);
             uint64_t *k2 = ws.get<uint64_t>(S_FIX_KEY2, (size_t)n_fix);
@@ -340,29 +348,39 @@ int map_set_precision(map_ctx *h, int precision)
     });
 }
 
-int map_set_tune(map_ctx *h, int waves, int tile_waves, int grid_per_cu, int persistent)
+int map_set_tune(map_ctx *h, int precision, int waves, int tile_waves, int grid_per_cu, int persistent)
 {
     Ctx *C = reinterpret_cast<Ctx *>(h);
     API_BODY(C, {
-        EM_CHECK(waves >= 0 && waves <= 8, MAP_EINVAL, "waves must be in [0, 8]");
-        EM_CHECK(persistent >= 0 && persistent <= 2, MAP_EINVAL, "persistent must be 0, 1 or 2");
-        EM_CHECK(tile_waves >= 1 && tile_waves <= 64, MAP_EINVAL, "tile_waves must be in [1, 64]");
-        EM_CHECK(grid_per_cu >= 1 && grid_per_cu <= 64, MAP_EINVAL, "grid_per_cu must be in [1, 64]");
-        C->tune.waves = waves;
-        C->tune.tile_waves = tile_waves;
-        C->tune.grid_per_cu = grid_per_cu;
-        C->tune.persistent = persistent;
+        EM_CHECK(precision == MAP_FP64 || precision == MAP_MIXED, MAP_EINVAL, "precision must be MAP_FP64 or MAP_MIXED");
+        EM_CHECK(persistent >= -1 && persistent <= 2, MAP_EINVAL, "persistent must be -1 (clear), 0, 1 or 2");
+        if (persistent < 0) {
+            C->has_explicit[precision] = false;
+        } else {
+            EM_CHECK(waves >= 0 && waves <= 8, MAP_EINVAL, "waves must be in [0, 8]");
+            EM_CHECK(tile_waves >= 1 && tile_waves <= 64, MAP_EINVAL, "tile_waves must be in [1, 64]");
+            EM_CHECK(grid_per_cu >= 1 && grid_per_cu <= 64, MAP_EINVAL, "grid_per_cu must be in [1, 64]");
+            IntegrateTune &t = C->tune_explicit[precision];
+            t.waves = waves;
+            t.tile_waves = tile_waves;
+            t.grid_per_cu = grid_per_cu;
+            t.persistent = persistent;
+            C->has_explicit[precision] = true;
+        }
     });
 }
 
-int map_get_tune(map_ctx *h, int *waves, int *tile_waves, int *grid_per_cu, int *persistent)
+int map_get_tune(map_ctx *h, int precision, int64_t n_pairs, int *waves, int *tile_waves, int *grid_per_cu,
+                 int *persistent)
 {
     Ctx *C = reinterpret_cast<Ctx *>(h);
     API_BODY(C, {
-        if (waves) *waves = C->tune.waves;
-        if (tile_waves) *tile_waves = C->tune.tile_waves;
-        if (grid_per_cu) *grid_per_cu = C->tune.grid_per_cu;
-        if (persistent) *persistent = C->tune.persistent;
+        EM_CHECK(precision == MAP_FP64 || precision == MAP_MIXED, MAP_EINVAL, "precision must be MAP_FP64 or MAP_MIXED");
+        const IntegrateTune t = pick_tune(*C, precision, n_pairs);
+        if (waves) *waves = t.waves;
+        if (tile_waves) *tile_waves = t.tile_waves;
+        if (grid_per_cu) *grid_per_cu = t.grid_per_cu;
+        if (persistent) *persistent = t.persistent;
     });
 }
 

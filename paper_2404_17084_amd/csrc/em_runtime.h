@@ -1,8 +1,10 @@
 // Library context and the stages shared by the synchronous and served paths.
 #pragma once
 
+#include <map>
 #include <mutex>
 #include <string>
+#include <utility>
 
 #include "em_internal.h"
 
@@ -21,9 +23,21 @@ struct Ctx {
     std::mutex mu;
     std::string err;
     Workspace ws;
-    IntegrateTune tune;
+    // launch tuning of the integration kernel, per precision: an explicit
+    // map_set_tune wins over the autotuner's table (keyed by precision and
+    // the log2 size class of the pair count), which wins over the default
+    IntegrateTune tune_explicit[2];
+    bool has_explicit[2] = {false, false};
+    std::map<std::pair<int, int>, IntegrateTune> tune_table;
+    std::string arch;
     Server *server = nullptr;
 };
+
+IntegrateTune default_tune(int precision);
+IntegrateTune pick_tune(const Ctx &C, int precision, int64_t n_pairs);
+int size_class(int64_t n_pairs);
+void tune_cache_load(Ctx &C);
+void tune_cache_save(const Ctx &C);
 
 void check_host_args(const map_particles_in *p, const map_cells_in *c);
 void prepare(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_in *c, DevInputs &in, EdgeRec *&edges,

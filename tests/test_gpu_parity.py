@@ -220,3 +220,20 @@ def test_clumps_cells_sampled(clumps256k, clumps_gpu, prec, tol):
     assert abs(r["M"].sum() - 1.0) < MASS_ABS
     interior = np.all((p.xyz - 2 * p.h[:, None] > 0) & (p.xyz + 2 * p.h[:, None] < 1), axis=1)
     assert np.abs(r["S"][interior] - 1).max() < (1e-12 if prec == em.MAP_FP64 else 1e-5)
+
+
+def test_autotune_and_cache(tmp_path, uniform4k):
+    say("case: autotune and cache")
+    p, c = uniform4k
+    cache = str(tmp_path / "tune.txt")
+    with em.Mapper(device=0, tune_cache_path=cache) as mp:
+        mp.set_precision(em.MAP_MIXED)
+        ref = mp.map(p, c)
+        shape, ms = em.map_autotune(mp.ctx, p.xyz, p.m, p.h, c, em.MAP_MIXED)
+        assert ms > 0 and shape[3] in (1, 2)
+        r = mp.map(p, c)
+        assert (np.abs(r["M"] - ref["M"]) / ref["M"]).max() < 1e-12
+    lines = open(cache).read().split()
+    assert len(lines) >= 8
+    with em.Mapper(device=0, tune_cache_path=cache) as mp2:
+        assert em.map_get_tune(mp2.ctx, em.MAP_MIXED, r["stats"]["n_pairs"]) == tuple(shape)
