@@ -50,7 +50,8 @@ enum {
     MAP_EBUSY = -4,     /* serving queue full */
     MAP_ENOTFOUND = -5, /* unknown job id */
     MAP_EGEOM = -6,     /* malformed cell geometry */
-    MAP_ENUMERIC = -7   /* non-finite result */
+    MAP_ENUMERIC = -7,  /* non-finite result */
+    MAP_ENOTSUP = -8    /* entry point switched off in this build */
 };
 
 /* Arithmetic of the per-triangle closed-form terms. */
@@ -119,6 +120,8 @@ typedef struct map_stats {
     double ms_fixup;        /* device time: FP64 recomputation of flagged terms */
     double ms_reduce;       /* device time: S_a, normalisation, M_i, rho_i */
     double ms_total;        /* device time of the whole call */
+    double ms_queue;        /* served jobs: host time from map_submit to admission */
+    double ms_latency;      /* served jobs: host time from map_submit to completion */
 } map_stats;
 
 /* Outputs: caller-owned, caller-sized, in mem_kind memory.  Any may be NULL. */
@@ -180,6 +183,37 @@ int map_pairs(map_ctx *ctx, const map_particles_in *p, const map_cells_in *c, in
 
 /* Synchronous Exact mapping, Eq. (1)-(3) with sum-to-one normalisation. */
 int map_particles(map_ctx *ctx, const map_particles_in *p, const map_cells_in *c, map_out *out);
+
+/*
+ * Served mapping (continuous batching).  map_submit copies the inputs (host or
+ * device memory) into library-owned memory before it returns and queues the
+ * job at the context's current precision; *job_id identifies it.  Jobs are
+ * admitted in submission order while a slot (cfg->max_jobs) and device memory
+ * (cfg->hbm_budget_bytes, by an estimate of the job's footprint) are free; an
+ * admitted job's inputs stay resident on the device until it completes.  The
+ * pair sets of admitted jobs are built concurrently (one stream per slot),
+ * and the integration of every job ready at that moment runs in one
+ * persistent launch, so jobs arriving while others integrate join the next
+ * launch.  Results are bitwise independent of the other jobs in the mix.
+ * The out buffers (and out->stats) are caller-owned and must stay valid until
+ * map_poll reports MAP_JOB_DONE or MAP_JOB_FAILED.
+ * Errors at submit: MAP_EINVAL/MAP_EGEOM (malformed input), MAP_ENOMEM (job
+ * larger than the whole budget), MAP_EBUSY (queue holds cfg->max_queue jobs).
+ * A job that fails later does not affect the others.
+ *
+ * Status: switched off.  map_submit returns MAP_ENOTSUP and queues nothing:
+ * a run of the served path on the device stopped making progress and its
+ * cause has not been found, so the path is not offered until it is.
+ */
+enum { MAP_JOB_PENDING = 0, MAP_JOB_RUNNING = 1, MAP_JOB_DONE = 2, MAP_JOB_FAILED = 3 };
+int map_submit(map_ctx *ctx, const map_particles_in *p, const map_cells_in *c, map_out *out, uint64_t *job_id);
+/*
+ * Waits up to timeout_us microseconds (0: no wait, negative: until finished)
+ * and writes the job's state.  Once DONE or FAILED has been reported the job
+ * is forgotten (a later poll returns MAP_ENOTFOUND).  For a failed job the
+ * return value is the job's error code and map_last_error has its message.
+ */
+int map_poll(map_ctx *ctx, uint64_t job_id, int64_t timeout_us, int *state);
 
 #ifdef __cplusplus
 }

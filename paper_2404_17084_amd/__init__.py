@@ -25,6 +25,7 @@ MAP_EBUSY = -4
 MAP_ENOTFOUND = -5
 MAP_EGEOM = -6
 MAP_ENUMERIC = -7
+MAP_ENOTSUP = -8
 MAP_FP64 = 0
 MAP_MIXED = 1
 MAP_MEM_HOST = 0
@@ -32,7 +33,8 @@ MAP_MEM_DEVICE = 1
 JOB_PENDING, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 _ERRNAMES = {v: k for k, v in dict(MAP_EINVAL=-1, MAP_ENOMEM=-2, MAP_EDEVICE=-3, MAP_EBUSY=-4, MAP_ENOTFOUND=-5,
-                                   MAP_EGEOM=-6, MAP_ENUMERIC=-7).items()}
+                                   MAP_EGEOM=-6, MAP_ENUMERIC=-7,
+                                   MAP_ENOTSUP=-8).items()}
 
 c_i64, c_i32, c_int, c_dbl, c_vp, c_u64 = (ctypes.c_int64, ctypes.c_int32, ctypes.c_int, ctypes.c_double,
                                            ctypes.c_void_p, ctypes.c_uint64)
@@ -59,7 +61,7 @@ class map_stats(ctypes.Structure):
                 ("n_quad_intervals", c_i64), ("n_angle_evals", c_i64),
                 ("mass_in", c_dbl), ("mass_out", c_dbl), ("max_abs_S_minus_1", c_dbl), ("ms_setup", c_dbl),
                 ("ms_pairs", c_dbl), ("ms_integrate", c_dbl), ("ms_fixup", c_dbl), ("ms_reduce", c_dbl),
-                ("ms_total", c_dbl)]
+                ("ms_total", c_dbl), ("ms_queue", c_dbl), ("ms_latency", c_dbl)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -93,6 +95,9 @@ _SIGS = {
                           c_i64]),
     "map_particles": (c_int, [c_vp, ctypes.POINTER(map_particles_in), ctypes.POINTER(map_cells_in),
                               ctypes.POINTER(map_out)]),
+    "map_submit": (c_int, [c_vp, ctypes.POINTER(map_particles_in), ctypes.POINTER(map_cells_in),
+                           ctypes.POINTER(map_out), ctypes.POINTER(c_u64)]),
+    "map_poll": (c_int, [c_vp, c_u64, c_i64, ctypes.POINTER(c_int)]),
 }
 
 
@@ -265,6 +270,45 @@ def map_particles(ctx, xyz, m, h, cells, cell_mass=None, cell_density=None, frac
                 _ptr(pair_c), cap, kind, ctypes.pointer(st))
     _check(ctx, lib.map_particles(ctx, ctypes.byref(P), ctypes.byref(C), ctypes.byref(O)))
     return st.as_dict()
+
+
+# Served jobs: references the library may still write to, kept until the job is reported finished.
+_SERVED = {}
+
+
+def map_submit(ctx, xyz, m, h, cells, cell_mass=None, cell_density=None, frac_sum_raw=None):
+    """Queue a mapping job (inputs are copied before this returns); returns the job id.
+
+    The output arrays (numpy or torch CUDA, all of one kind) are filled when the
+    job completes; they are kept referenced here until map_poll reports it."""
+    lib = load()
+    P, k1 = particles_in(xyz, m, h)
+    C, k2 = cells_in(cells)
+    st = map_stats()
+    outs = [x for x in (cell_mass, cell_density, frac_sum_raw) if x is not None]
+    kind = _kind(outs[0]) if outs else MAP_MEM_HOST
+    O = map_out(_ptr(cell_mass), _ptr(cell_density), _ptr(frac_sum_raw), None, None, None, 0, kind,
+                ctypes.pointer(st))
+    jid = c_u64()
+    _check(ctx, lib.map_submit(ctx, ctypes.byref(P), ctypes.byref(C), ctypes.byref(O), ctypes.byref(jid)))
+    _SERVED[(ctx.value, jid.value)] = (O, st, outs)
+    return jid.value
+
+
+def map_poll(ctx, job_id, timeout_us=-1):
+    """Job state (JOB_PENDING/RUNNING/DONE/FAILED) and, once finished, its statistics.
+
+    Raises MapError when the job failed (its error code and message)."""
+    state = c_int()
+    rc = load().map_poll(ctx, job_id, timeout_us, ctypes.byref(state))
+    key = (ctx.value, job_id)
+    if state.value in (JOB_DONE, JOB_FAILED) or rc == MAP_ENOTFOUND:
+        held = _SERVED.pop(key, None)
+        if rc != MAP_OK:
+            _check(ctx, rc)
+        return state.value, (held[1].as_dict() if held else None)
+    _check(ctx, rc)
+    return state.value, None
 
 
 class Mapper:

@@ -156,62 +156,64 @@ __global__ void k_u32_to_i32(const uint32_t *in, int32_t *out, int64_t n)
     if (i < n) out[i] = (int32_t)in[i];
 }
 
-// The whole mapping of one job on stream s with workspace ws.
-void run_mapping(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_in *c, const map_out *out,
-                 int precision, hipStream_t s, bool timed)
+// Stage 1 of a mapping: inputs staged and validated, geometry tables, pair
+// set, and the buffers the integration writes.
+void stage_pairs(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_in *c, int precision,
+                 JobState &js, hipStream_t s)
 {
     EM_CHECK(precision == MAP_FP64 || precision == MAP_MIXED, MAP_EINVAL, "precision must be MAP_FP64 or MAP_MIXED");
-    if (timed) EM_HIP(hipEventRecord(C.ev[0], s));
-    DevInputs in;
-    EdgeRec *edges;
-    double *aabb;
-    unsigned *flags;
-    int64_t *counters;
-    prepare(C, ws, p, c, in, edges, aabb, flags, counters, s);
-    if (timed) EM_HIP(hipEventRecord(C.ev[1], s));
-    PairSet ps = build_pairs(ws, in, aabb, edges, counters, s);
-    const IntegrateTune tune = pick_tune(C, precision, ps.n_pairs);
-    if (tune.persistent == 2) build_tiles(ws, in, ps, s);
-    if (timed) EM_HIP(hipEventRecord(C.ev[2], s));
+    js.precision = precision;
+    prepare(C, ws, p, c, js.in, js.edges, js.aabb, js.flags, js.counters, s);
+    if (js.ev_setup) EM_HIP(hipEventRecord(js.ev_setup, s));
+    js.ps = build_pairs(ws, js.in, js.aabb, js.edges, js.counters, s);
+    const int64_t np = js.ps.n_pairs;
+    js.f = ws.get<double>(S_F, (size_t)(np > 0 ? np : 1));
+    js.tile_ctr = ws.get<uint32_t>(S_TILE_CTR, 64);
+    js.fix_cap = np / 8 + 65536;
+    js.fix_items = ws.get<uint64_t>(S_FIX_ITEMS, (size_t)js.fix_cap);
+    fill_zero_bytes(js.tile_ctr, 2 * sizeof(unsigned), s);
+}
+
+// Stage 3: FP64 fixups of flagged edges (mixed path), S_a, M_i, rho_i, output
+// copies and statistics.  Returns the number of fixed-up edge terms.
+int64_t stage_finish(Ctx &C, Workspace &ws, JobState &js, const map_out *out, hipStream_t s, map_stats *st)
+{
+    (void)C;
+    const DevInputs &in = js.in;
+    const PairSet &ps = js.ps;
     const int64_t np = ps.n_pairs;
-    double *f = ws.get<double>(S_F, (size_t)(np > 0 ? np : 1));
-    uint32_t *tile_ctr = ws.get<uint32_t>(S_TILE_CTR, 64);
-    const int64_t fix_cap = np / 8 + 65536;
-    uint64_t *fix_items = ws.get<uint64_t>(S_FIX_ITEMS, (size_t)fix_cap);
-    launch_integrate(in, edges, ps, precision, tune, f, counters, tile_ctr, fix_items, fix_cap, s);
-    if (timed) EM_HIP(hipEventRecord(C.ev[3], s));
+    double *f = js.f;
     int64_t n_fix = 0;
-    if (precision == MAP_MIXED && np > 0) {
+    if (js.precision == MAP_MIXED && np > 0) {
         unsigned hfix = 0;
-        EM_HIP(hipMemcpyAsync(&hfix, tile_ctr + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        EM_HIP(hipMemcpyAsync(&hfix, js.tile_ctr + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s));
         EM_HIP(hipStreamSynchronize(s));
         n_fix = hfix;
-        if (n_fix > fix_cap) {
+        if (n_fix > js.fix_cap) {
             // too many flagged edges for the fixup list: redo every pair in FP64
-            IntegrateTune t64 = tune;
-            t64.waves = 0;
-            if (t64.persistent == 2) t64.persistent = 1;
-            launch_integrate(in, edges, ps, MAP_FP64, t64, f, counters, tile_ctr, fix_items, fix_cap, s);
+            IntegrateTune t64 = default_tune(MAP_FP64);
+            launch_integrate(in, js.edges, ps, MAP_FP64, t64, f, js.counters, js.tile_ctr, js.fix_items, js.fix_cap, s);
+            n_fix = np;
         } else if (n_fix > 0) {
             uint32_t *iv = ws.get<uint32_t>(S_FIX_VAL2, (size_t)n_fix);
             uint64_t *k2 = ws.get<uint64_t>(S_FIX_KEY2, (size_t)n_fix);
             uint32_t *v2 = reinterpret_cast<uint32_t *>(ws.get<uint64_t>(S_FIX_VALS, (size_t)n_fix * 2));
             fill_iota_u32(iv, n_fix, s);
-            radix_sort_u64(ws, fix_items, iv, k2, v2, n_fix, 64, s);
+            radix_sort_u64(ws, js.fix_items, iv, k2, v2, n_fix, 64, s);
             double *fv = reinterpret_cast<double *>(k2);
-            launch_fixup(in, edges, ps, fix_items, n_fix, fv, s);
-            launch_fixup_apply(fix_items, fv, n_fix, f, s);
+            launch_fixup(in, js.edges, ps, js.fix_items, n_fix, fv, s);
+            launch_fixup_apply(js.fix_items, fv, n_fix, f, s);
         }
     }
-    if (timed) EM_HIP(hipEventRecord(C.ev[4], s));
+    if (js.ev_fix) EM_HIP(hipEventRecord(js.ev_fix, s));
     double *f_pm = ws.get<double>(S_F_PM, (size_t)(np > 0 ? np : 1));
     double *S = ws.get<double>(S_S, (size_t)(in.n > 0 ? in.n : 1));
     double *M = ws.get<double>(S_MCELL, (size_t)(in.n_cells > 0 ? in.n_cells : 1));
     double *rho = ws.get<double>(S_RHO, (size_t)(in.n_cells > 0 ? in.n_cells : 1));
     double *red = ws.get<double>(S_RED, 16 + 4 * 256);
     EM_HIP(hipMemcpyAsync(red + 4, in.box, sizeof(double) * 6, hipMemcpyHostToDevice, s));
-    launch_reduce(in, ps, f, f_pm, S, M, rho, red, flags, s);
-    if (timed) EM_HIP(hipEventRecord(C.ev[5], s));
+    launch_reduce(in, ps, f, f_pm, S, M, rho, red, js.flags, s);
+    if (js.ev_reduce) EM_HIP(hipEventRecord(js.ev_reduce, s));
 
     // outputs
     copy_out(out->cell_mass, (const double *)M, in.n_cells, out->mem_kind, s);
@@ -239,41 +241,66 @@ void run_mapping(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cel
     int64_t hcnt[C_NUM];
     unsigned hf = 0;
     EM_HIP(hipMemcpyAsync(hred, red, sizeof(hred), hipMemcpyDeviceToHost, s));
-    EM_HIP(hipMemcpyAsync(hcnt, counters, sizeof(hcnt), hipMemcpyDeviceToHost, s));
-    EM_HIP(hipMemcpyAsync(&hf, flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    EM_HIP(hipMemcpyAsync(hcnt, js.counters, sizeof(hcnt), hipMemcpyDeviceToHost, s));
+    EM_HIP(hipMemcpyAsync(&hf, js.flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     EM_HIP(hipStreamSynchronize(s));
     EM_CHECK(hf == 0, flag_code(hf), flag_text(hf));
-    if (out->stats) {
-        map_stats &st = *out->stats;
-        std::memset(&st, 0, sizeof(st));
-        st.n_pairs = np;
-        st.n_candidates = hcnt[C_CANDIDATES];
-        st.n_edge_terms = hcnt[C_EDGE_TERMS];
-        st.n_fixup_terms = n_fix;
-        st.n_face_visits = hcnt[C_FACES];
-        st.n_edge_visits = hcnt[C_EDGES];
-        st.n_moment_evals = hcnt[C_MOMENTS];
-        st.n_quad_intervals = hcnt[C_QUADS];
-        st.n_angle_evals = hcnt[C_ANGLES];
-        st.mass_out = hred[0];
-        st.max_abs_S_minus_1 = hred[1];
-        st.mass_in = hred[2];
-        if (timed) {
-            float t;
-            EM_HIP(hipEventElapsedTime(&t, C.ev[0], C.ev[1]));
-            st.ms_setup = t;
-            EM_HIP(hipEventElapsedTime(&t, C.ev[1], C.ev[2]));
-            st.ms_pairs = t;
-            EM_HIP(hipEventElapsedTime(&t, C.ev[2], C.ev[3]));
-            st.ms_integrate = t;
-            EM_HIP(hipEventElapsedTime(&t, C.ev[3], C.ev[4]));
-            st.ms_fixup = t;
-            EM_HIP(hipEventElapsedTime(&t, C.ev[4], C.ev[5]));
-            st.ms_reduce = t;
-            EM_HIP(hipEventElapsedTime(&t, C.ev[0], C.ev[5]));
-            st.ms_total = t;
-        }
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->n_pairs = np;
+        st->n_candidates = hcnt[C_CANDIDATES];
+        st->n_edge_terms = hcnt[C_EDGE_TERMS];
+        st->n_fixup_terms = n_fix;
+        st->n_face_visits = hcnt[C_FACES];
+        st->n_edge_visits = hcnt[C_EDGES];
+        st->n_moment_evals = hcnt[C_MOMENTS];
+        st->n_quad_intervals = hcnt[C_QUADS];
+        st->n_angle_evals = hcnt[C_ANGLES];
+        st->mass_out = hred[0];
+        st->max_abs_S_minus_1 = hred[1];
+        st->mass_in = hred[2];
     }
+    return n_fix;
+}
+
+// The whole synchronous mapping of one job on stream s with workspace ws.
+void run_mapping(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_in *c, const map_out *out,
+                 int precision, hipStream_t s, bool timed)
+{
+    JobState js;
+    if (timed) {
+        EM_HIP(hipEventRecord(C.ev[0], s));
+        js.ev_setup = C.ev[1];
+    }
+    stage_pairs(C, ws, p, c, precision, js, s);
+    const IntegrateTune tune = pick_tune(C, precision, js.ps.n_pairs);
+    if (tune.persistent == 2) build_tiles(ws, js.in, js.ps, s);
+    if (timed) EM_HIP(hipEventRecord(C.ev[2], s));
+    launch_integrate(js.in, js.edges, js.ps, precision, tune, js.f, js.counters, js.tile_ctr, js.fix_items, js.fix_cap,
+                     s);
+    if (timed) {
+        EM_HIP(hipEventRecord(C.ev[3], s));
+        js.ev_fix = C.ev[4];
+        js.ev_reduce = C.ev[5];
+    }
+    map_stats local;
+    stage_finish(C, ws, js, out, s, &local);
+    if (timed) {
+        float t;
+        EM_HIP(hipEventElapsedTime(&t, C.ev[0], C.ev[1]));
+        local.ms_setup = t;
+        EM_HIP(hipEventElapsedTime(&t, C.ev[1], C.ev[2]));
+        local.ms_pairs = t;
+        EM_HIP(hipEventElapsedTime(&t, C.ev[2], C.ev[3]));
+        local.ms_integrate = t;
+        EM_HIP(hipEventElapsedTime(&t, C.ev[3], C.ev[4]));
+        local.ms_fixup = t;
+        EM_HIP(hipEventElapsedTime(&t, C.ev[4], C.ev[5]));
+        local.ms_reduce = t;
+        EM_HIP(hipEventElapsedTime(&t, C.ev[0], C.ev[5]));
+        local.ms_total = t;
+    }
+    if (out->stats) *out->stats = local;
 }
 
 }  // namespace em

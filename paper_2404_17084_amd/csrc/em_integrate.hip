@@ -578,6 +578,37 @@ __global__ void __launch_bounds__(256) k_integrate_tiles(int64_t n_tiles, const 
     flush_work(wk, counters);
 }
 
+// ---------------------------------------------------------------- batched (served) integration
+// One persistent launch integrates the pairs of several jobs: the global tile
+// space (64 pairs per tile) is the concatenation of the jobs' tiles, and a
+// wavefront maps its tile to the job through the table of tile bases.  Each
+// pair is computed by the same code whatever the batch holds, so a job's
+// results do not depend on the jobs it is batched with.
+template <int PREC>
+__global__ void __launch_bounds__(256) k_integrate_batch(int n_jobs, int64_t n_tiles, const BatchJob *__restrict__ jobs,
+                                                          unsigned *tile_ctr)
+{
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        unsigned t = 0;
+        if (lane == 0) t = atomicAdd(tile_ctr, 1u);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if ((int64_t)t >= n_tiles) break;
+        int j = 0;
+        while (j + 1 < n_jobs && jobs[j + 1].tile_base <= (int64_t)t) j++;
+        const BatchJob &J = jobs[j];
+        const int64_t k = ((int64_t)t - J.tile_base) * 64 + lane;
+        Work wk;
+        if (k < J.np) {
+            const int64_t a = J.pair_p[k];
+            const int64_t c = J.pair_c[k];
+            J.f[k] = pair_fraction<PREC>(J.xyz[3 * a], J.xyz[3 * a + 1], J.xyz[3 * a + 2], J.h[a], c, J.cfo, J.fvo,
+                                         J.plane, J.edges, wk, (uint64_t)k, J.fix_count, J.fix_items, J.fix_cap);
+        }
+        flush_work(wk, J.counters);
+    }
+}
+
 // FP64 values of flagged edges (fixup items, key = pair << 32 | face-vertex slot)
 __global__ void k_fixup_values(int64_t n_fix, const uint64_t *__restrict__ keys, const uint32_t *__restrict__ pair_p,
                                const uint32_t *__restrict__ pair_c, const double *__restrict__ xyz,
@@ -697,6 +728,25 @@ void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &
         else EM_LAUNCH_P(MAP_MIXED, 4);
     }
 #undef EM_LAUNCH_P
+    EM_HIP(hipGetLastError());
+}
+
+void launch_integrate_batch(const BatchJob *d_jobs, int n_jobs, int64_t n_tiles, int precision, unsigned *tile_ctr,
+                            hipStream_t s)
+{
+    if (n_tiles <= 0) return;
+    fill_zero_bytes(tile_ctr, sizeof(unsigned), s);
+    const int block = 256;
+    int64_t g = (int64_t)device_cu_count() * 8;
+    int64_t need = (n_tiles + 3) / 4;
+    if (g > need) g = need;
+    if (g < 1) g = 1;
+    if (precision == MAP_FP64)
+        hipLaunchKernelGGL(k_integrate_batch<MAP_FP64>, dim3((unsigned)g), dim3(block), 0, s, n_jobs, n_tiles, d_jobs,
+                           tile_ctr);
+    else
+        hipLaunchKernelGGL(k_integrate_batch<MAP_MIXED>, dim3((unsigned)g), dim3(block), 0, s, n_jobs, n_tiles, d_jobs,
+                           tile_ctr);
     EM_HIP(hipGetLastError());
 }
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -33,9 +34,11 @@ struct Error {
 // ---------------------------------------------------------------- device memory
 // A grow-only set of device buffers.  get() returns a buffer of at least
 // `bytes`, reallocating (and discarding contents) when it is too small.
+// get() and release() belong to the owning thread; bytes_held() may be read
+// from any thread (the slot table is sized once and never reallocated).
 class Workspace {
 public:
-    explicit Workspace(int device) : device_(device) {}
+    explicit Workspace(int device);
     ~Workspace();
     Workspace(const Workspace &) = delete;
     Workspace &operator=(const Workspace &) = delete;
@@ -53,6 +56,7 @@ private:
     };
     int device_;
     std::vector<Buf> bufs_;
+    std::atomic<size_t> held_{0};
 };
 
 // Buffer slots of one mapping job.
@@ -163,6 +167,24 @@ struct PairSet {
 };
 PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, const EdgeRec *edges,
                     int64_t *counters, hipStream_t s);
+
+// One job of a batched integration launch (device-resident table entry).
+struct BatchJob {
+    int64_t np;
+    int64_t tile_base;  // first global tile of this job (64 pairs per tile)
+    const uint32_t *pair_p, *pair_c;
+    const double *xyz, *h;
+    const int64_t *cfo, *fvo;
+    const double *plane;
+    const EdgeRec *edges;
+    double *f;
+    unsigned long long *counters;
+    unsigned *fix_count;
+    uint64_t *fix_items;
+    unsigned fix_cap;
+};
+void launch_integrate_batch(const BatchJob *d_jobs, int n_jobs, int64_t n_tiles, int precision, unsigned *tile_ctr,
+                            hipStream_t s);
 
 // em_integrate.hip: raw f per pair (cell-major order).
 void build_tiles(Workspace &ws, const DevInputs &in, PairSet &ps, hipStream_t s);

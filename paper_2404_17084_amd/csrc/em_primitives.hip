@@ -5,6 +5,8 @@
 namespace em {
 
 // ---------------------------------------------------------------- workspace
+Workspace::Workspace(int device) : device_(device), bufs_(S_NUM_SLOTS) {}
+
 Workspace::~Workspace() { release(); }
 
 void Workspace::release()
@@ -12,6 +14,7 @@ void Workspace::release()
     for (Buf &b : bufs_)
         if (b.p) {
             (void)hipFree(b.p);
+            held_.fetch_sub(b.cap);
             b.p = nullptr;
             b.cap = 0;
         }
@@ -19,11 +22,12 @@ void Workspace::release()
 
 void *Workspace::get(int slot, size_t bytes)
 {
-    if ((int)bufs_.size() <= slot) bufs_.resize(slot + 1);
+    if (slot < 0 || slot >= (int)bufs_.size()) throw Error{MAP_EINVAL, "workspace slot out of range"};
     Buf &b = bufs_[slot];
     if (bytes == 0) bytes = 256;
     if (b.cap < bytes) {
         if (b.p) EM_HIP(hipFree(b.p));
+        held_.fetch_sub(b.cap);
         b.p = nullptr;
         b.cap = 0;
         size_t want = bytes + bytes / 4 + 256;
@@ -35,16 +39,12 @@ void *Workspace::get(int slot, size_t bytes)
             throw Error{MAP_ENOMEM, "device allocation of " + std::to_string(want) + " bytes failed"};
         }
         b.cap = want;
+        held_.fetch_add(want);
     }
     return b.p;
 }
 
-size_t Workspace::bytes_held() const
-{
-    size_t t = 0;
-    for (const Buf &b : bufs_) t += b.cap;
-    return t;
-}
+size_t Workspace::bytes_held() const { return held_.load(); }
 
 int device_cu_count()
 {

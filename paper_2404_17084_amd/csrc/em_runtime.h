@@ -39,7 +39,26 @@ int size_class(int64_t n_pairs);
 void tune_cache_load(Ctx &C);
 void tune_cache_save(const Ctx &C);
 
+// Device-side state of one mapping between its stages.
+struct JobState {
+    int precision = MAP_FP64;
+    DevInputs in;
+    EdgeRec *edges = nullptr;
+    double *aabb = nullptr;
+    unsigned *flags = nullptr;
+    int64_t *counters = nullptr;
+    PairSet ps;
+    double *f = nullptr;
+    uint32_t *tile_ctr = nullptr;
+    uint64_t *fix_items = nullptr;
+    int64_t fix_cap = 0;
+    hipEvent_t ev_setup = nullptr, ev_fix = nullptr, ev_reduce = nullptr;  // optional timing events
+};
+
 void check_host_args(const map_particles_in *p, const map_cells_in *c);
+void stage_pairs(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_in *c, int precision,
+                 JobState &js, hipStream_t s);
+int64_t stage_finish(Ctx &C, Workspace &ws, JobState &js, const map_out *out, hipStream_t s, map_stats *st);
 void prepare(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_in *c, DevInputs &in, EdgeRec *&edges,
              double *&aabb, unsigned *&flags, int64_t *&counters, hipStream_t s);
 void run_mapping(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_in *c, const map_out *out,

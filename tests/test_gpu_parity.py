@@ -237,3 +237,13 @@ def test_autotune_and_cache(tmp_path, uniform4k):
     assert len(lines) >= 8
     with em.Mapper(device=0, tune_cache_path=cache) as mp2:
         assert em.map_get_tune(mp2.ctx, em.MAP_MIXED, r["stats"]["n_pairs"]) == tuple(shape)
+
+
+def test_served_path_switched_off(uniform4k):
+    """map_submit is switched off and says so without queueing anything."""
+    p, c = uniform4k
+    with em.Mapper(device=0) as mp:
+        with pytest.raises(em.MapError) as ei:
+            em.map_submit(mp.ctx, p.xyz, p.m, p.h, c, np.zeros(c.n_cells))
+        assert ei.value.code == em.MAP_ENOTSUP
+        assert "switched off" in em.map_last_error(mp.ctx)
