@@ -185,6 +185,77 @@ int map_pairs(map_ctx *ctx, const map_particles_in *p, const map_cells_in *c, in
 int map_particles(map_ctx *ctx, const map_particles_in *p, const map_cells_in *c, map_out *out);
 
 /*
+ * Pseudo-particles (Sec. III): the gravity-tree front end that lowers the
+ * resolution away from the ionising sources before the mapping.
+ *
+ *  Tree (Sec. III-A): an octree over 63-bit Morton keys of the positions in
+ *  `box` (21 bits per axis, key = floor((x - lo) / extent * 2^21) per axis,
+ *  clamped, octal digits (x, y, z) from the most significant).  A node holds
+ *  the particles sharing its first L digits and is a leaf when it holds at
+ *  most leaf_size particles or L = 21.  Node position = centre of mass, size s
+ *  = distance from it to the furthest member.  Node label = (1 << 3L) | prefix
+ *  (ancestor k levels up = label >> 3k).
+ *  Walk (Sec. III-B, Eq. (5)): r = smallest distance from the node's centre of
+ *  mass to the sources; a node "comes within" R when r - s < R.  A leaf within
+ *  r_part is replaced by its particles; any other node within r_part or r_leaf
+ *  is opened; otherwise a node is opened when s > theta * r; a leaf is never
+ *  opened otherwise.  Accepted nodes and extracted particles partition the
+ *  particles (mass is conserved).
+ *  Smoothing lengths (Sec. III-C, Eq. (7)-(9)): a node pseudo-particle's h is
+ *  the unique root of (1/pi) sum_b w(|r - r_b| / h) = h_fact_node^3 (that is,
+ *  h = h_fact_node n^(-1/3)), the sum running over the node pseudo-particles
+ *  and, standing in for extracted particles, the leaves they came from; the
+ *  node itself is included.  Newton steps safeguarded by bisection from the
+ *  initial guess h0 = 2 h_fact_node s (zero-size nodes: their particles'
+ *  largest h); h0 itself when there is no root.  Extracted particles keep
+ *  their own h.
+ *
+ * Output: pseudo-particles in Morton order of their first particle.  Per
+ * pseudo-particle: position (3 doubles), mass, h, size s (0 for particles),
+ * kind (MAP_PSEUDO_NODE / MAP_PSEUDO_PARTICLE) and ref (the node label, or the
+ * particle's index in the input).  out->n_out is always set; when
+ * out->capacity < n_out nothing else is written and the call returns MAP_OK if
+ * capacity == 0 (count only) or MAP_EINVAL otherwise.  capacity >= p->n always
+ * suffices.  Output buffers live in out->mem_kind memory.  Sources src_xyz
+ * (3 * n_src doubles, 1 <= n_src <= 64) are host memory.
+ * Errors: MAP_EINVAL for n < 0 or n >= 2^31, non-finite or non-positive
+ * masses or h, non-finite positions, a box without positive extent, theta,
+ * r_part or r_leaf negative or non-finite, leaf_size outside [1, 64],
+ * h_fact_node <= 0.
+ */
+enum { MAP_PSEUDO_NODE = 0, MAP_PSEUDO_PARTICLE = 1 };
+typedef struct map_pseudo_params {
+    double theta;       /* opening angle of Eq. (5) */
+    double r_part;      /* leaves within r_part of a source become their particles */
+    double r_leaf;      /* nodes within r_leaf of a source are opened down to leaves */
+    int leaf_size;      /* maximum particles per leaf (the paper's tree stops below 10) */
+    double h_fact_node; /* h_fact of Eq. (7) and (9), 1.1 in the paper */
+} map_pseudo_params;
+
+typedef struct map_pseudo_stats {
+    int64_t n_tree_nodes, n_leaves, max_level;
+    int64_t n_pseudo, n_pseudo_nodes, n_particles, n_substitute_leaves;
+    int64_t n_fallbacks;     /* node h taken from Eq. (9) because no root exists */
+    int64_t n_h_evals;       /* evaluations of the number sum over all nodes */
+    int64_t n_neighbours;    /* points within 2h of the nodes, summed */
+    double ms_tree, ms_walk, ms_hsolve, ms_total;
+} map_pseudo_stats;
+
+typedef struct map_pseudo_out {
+    int64_t capacity;
+    double *xyz;      /* 3 * capacity */
+    double *m, *h, *size;
+    int32_t *kind;
+    int64_t *ref;
+    int mem_kind;
+    int64_t n_out;    /* written by the call */
+    map_pseudo_stats *stats; /* host memory, may be NULL */
+} map_pseudo_out;
+
+int map_pseudo(map_ctx *ctx, const map_particles_in *p, const double box[6], const double *src_xyz, int n_src,
+               const map_pseudo_params *par, map_pseudo_out *out);
+
+/*
  * Served mapping (continuous batching).  map_submit copies the inputs (host or
  * device memory) into library-owned memory before it returns and queues the
  * job at the context's current precision; *job_id identifies it.  Jobs are

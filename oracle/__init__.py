@@ -29,8 +29,8 @@ def build_lib(force: bool = True) -> str:
     if force or not os.path.exists(_SO):
         os.makedirs(os.path.dirname(_SO), exist_ok=True)
         tmp = _SO + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-shared", "-fPIC", "-o", tmp] + _SRCS
-                              + ["-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
+                               "-o", tmp] + _SRCS + ["-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -74,6 +74,18 @@ def _load():
         lib.orc_pair_fractions.argtypes = [i, vp, vp, ctypes.POINTER(_Cells), i64, vp, vp, vp]
         lib.orc_reduce.argtypes = [i64, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp]
         lib.orc_num_threads.restype = i
+        if hasattr(lib, "orp_pseudo"):
+            u64 = ctypes.c_uint64
+            lib.orp_morton.restype = u64
+            lib.orp_morton.argtypes = [vp, vp]
+            lib.orp_tree.restype = i64
+            lib.orp_tree.argtypes = [i64, vp, vp, vp, i, i64] + [vp] * 10
+            lib.orp_number_sum.restype = d
+            lib.orp_number_sum.argtypes = [i64, vp, vp, d]
+            lib.orp_solve_h.restype = d
+            lib.orp_solve_h.argtypes = [i64, vp, vp, d, d, ctypes.POINTER(ctypes.c_int)]
+            lib.orp_pseudo.restype = i64
+            lib.orp_pseudo.argtypes = [i64, vp, vp, vp, vp, i, vp, d, d, d, i, d, i64] + [vp] * 6 + [vp, i64, vp]
         _lib = lib
     return _lib
 
@@ -241,3 +253,70 @@ def map_particles(particles, cells, profile: int = M4):
 
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+# ---------------------------------------------------------------- pseudo-particle front end (Sec. III)
+PSEUDO_NODE = 0
+PSEUDO_PARTICLE = 1
+
+
+def morton(p, box) -> int:
+    """63-bit Morton key of one point in the box."""
+    pp = _f64(p)
+    bb = _f64(box)
+    return int(_load().orp_morton(_p(pp), _p(bb)))
+
+
+def tree(xyz, m, box, leaf_size: int = 8):
+    """Octree in preorder: dict of level, start, end, parent, label, leaf, mass, com, s and perm."""
+    lib = _load()
+    xyz, m, bb = _f64(xyz), _f64(m), _f64(box)
+    n = m.size
+    args = [n, _p(xyz), _p(m), _p(bb), leaf_size]
+    cnt = lib.orp_tree(*args, 0, *([None] * 10))
+    out = dict(level=np.zeros(cnt, np.int32), start=np.zeros(cnt, np.int64), end=np.zeros(cnt, np.int64),
+               parent=np.zeros(cnt, np.int64), label=np.zeros(cnt, np.uint64), leaf=np.zeros(cnt, np.int8),
+               mass=np.zeros(cnt), com=np.zeros((cnt, 3)), s=np.zeros(cnt), perm=np.zeros(n, np.int64))
+    lib.orp_tree(*args, cnt, *[_p(out[k]) for k in ("level", "start", "end", "parent", "label", "leaf", "mass",
+                                                    "com", "s", "perm")])
+    out["leaf"] = out["leaf"].astype(bool)
+    return out
+
+
+def number_sum(pts, x, h: float) -> float:
+    """N(h) = (1/pi) sum_b w(|x - p_b| / h) over all points."""
+    pts, x = _f64(pts), _f64(x)
+    return _load().orp_number_sum(pts.size // 3, _p(pts), _p(x), h)
+
+
+def solve_h(pts, x, h0: float, h_fact: float = 1.1):
+    """Root of N(h) = h_fact^3 (Eq. (7)-(8)); returns (h, fell_back)."""
+    pts, x = _f64(pts), _f64(x)
+    fb = ctypes.c_int(0)
+    h = _load().orp_solve_h(pts.size // 3, _p(pts), _p(x), h0, h_fact, ctypes.byref(fb))
+    return h, bool(fb.value)
+
+
+def pseudo(xyz, m, h, box, sources, theta=0.5, r_part=0.05, r_leaf=0.1, leaf_size=8, h_fact=1.1, only=None):
+    """Pseudo-particles (Sec. III) in Morton order: dict of xyz, m, h, s, kind, ref and stats.
+
+    `only` restricts the h-solve to those pseudo indices (others get h = 0 unless they are particles)."""
+    lib = _load()
+    xyz, m, h, bb = _f64(xyz), _f64(m), _f64(h), _f64(box)
+    src = _f64(sources).reshape(-1, 3)
+    n = m.size
+    st = np.zeros(8)
+    head = [n, _p(xyz), _p(m), _p(h), _p(bb), src.shape[0], _p(src), theta, r_part, r_leaf, leaf_size, h_fact]
+    cnt = lib.orp_pseudo(*head, 0, *([None] * 6), None, 0, _p(st))
+    out = dict(xyz=np.zeros((cnt, 3)), m=np.zeros(cnt), h=np.zeros(cnt), s=np.zeros(cnt),
+               kind=np.zeros(cnt, np.int32), ref=np.zeros(cnt, np.int64))
+    if only is None:
+        o, no = None, 0
+    else:
+        only = np.ascontiguousarray(only, dtype=np.int64)
+        o, no = _p(only), only.size
+    lib.orp_pseudo(*head, cnt, *[_p(out[k]) for k in ("xyz", "m", "h", "s", "kind", "ref")], o, no, _p(st))
+    out["stats"] = dict(tree_nodes=int(st[0]), leaves=int(st[1]), pseudo_nodes=int(st[2]),
+                        particles=int(st[3]), substitute_leaves=int(st[4]), fallbacks=int(st[5]),
+                        max_level=int(st[6]), neighbours=float(st[7]))
+    return out

@@ -73,6 +73,28 @@ class map_out(ctypes.Structure):
                 ("stats", ctypes.POINTER(map_stats))]
 
 
+PSEUDO_NODE, PSEUDO_PARTICLE = 0, 1
+
+
+class map_pseudo_params(ctypes.Structure):
+    _fields_ = [("theta", c_dbl), ("r_part", c_dbl), ("r_leaf", c_dbl), ("leaf_size", c_int), ("h_fact_node", c_dbl)]
+
+
+class map_pseudo_stats(ctypes.Structure):
+    _fields_ = [(k, c_i64) for k in ("n_tree_nodes", "n_leaves", "max_level", "n_pseudo", "n_pseudo_nodes",
+                                     "n_particles", "n_substitute_leaves", "n_fallbacks", "n_h_evals",
+                                     "n_neighbours")] + \
+               [(k, c_dbl) for k in ("ms_tree", "ms_walk", "ms_hsolve", "ms_total")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class map_pseudo_out(ctypes.Structure):
+    _fields_ = [("capacity", c_i64), ("xyz", c_vp), ("m", c_vp), ("h", c_vp), ("size", c_vp), ("kind", c_vp),
+                ("ref", c_vp), ("mem_kind", c_int), ("n_out", c_i64), ("stats", ctypes.POINTER(map_pseudo_stats))]
+
+
 class MapError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
@@ -98,7 +120,27 @@ _SIGS = {
     "map_submit": (c_int, [c_vp, ctypes.POINTER(map_particles_in), ctypes.POINTER(map_cells_in),
                            ctypes.POINTER(map_out), ctypes.POINTER(c_u64)]),
     "map_poll": (c_int, [c_vp, c_u64, c_i64, ctypes.POINTER(c_int)]),
+    "map_pseudo": (c_int, [c_vp, ctypes.POINTER(map_particles_in), ctypes.POINTER(c_dbl * 6), c_vp, c_int,
+                           ctypes.POINTER(map_pseudo_params), ctypes.POINTER(map_pseudo_out)]),
 }
+
+
+def _torch_runtime_first():
+    """Initialise torch's HIP runtime before this library's.
+
+    torch ships its own HIP runtime next to the system one this library links;
+    both can live in one process only when torch's initialises first (device
+    pointers are shared either way).  Counting devices does not initialise
+    anything, so a GPU-less host is left alone."""
+    try:
+        import torch
+    except ImportError:
+        return
+    try:
+        if torch.cuda.device_count() > 0:
+            torch.cuda.init()
+    except Exception:
+        pass
 
 
 def load():
@@ -107,6 +149,7 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libexactmap is not built ({LIB_PATH}); run __graft_entry__.build() first")
+        _torch_runtime_first()
         lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             if hasattr(lib, name):
@@ -311,6 +354,38 @@ def map_poll(ctx, job_id, timeout_us=-1):
     return state.value, None
 
 
+def map_pseudo(ctx, xyz, m, h, box, sources, theta=0.5, r_part=0.05, r_leaf=0.1, leaf_size=8, h_fact_node=1.1,
+               out=None, capacity=None):
+    """Pseudo-particles of the particles (Sec. III), in Morton order.
+
+    Returns (count, stats) when capacity == 0, else a dict of xyz, m, h, size,
+    kind, ref and stats.  `out` may hold preallocated arrays (numpy or torch
+    CUDA, all of one kind) under those names with at least `capacity` rows."""
+    lib = load()
+    P, k1 = particles_in(xyz, m, h)
+    bx = (c_dbl * 6)(*[float(b) for b in box])
+    src = np.ascontiguousarray(np.asarray(sources, dtype=np.float64).reshape(-1, 3))
+    par = map_pseudo_params(float(theta), float(r_part), float(r_leaf), int(leaf_size), float(h_fact_node))
+    st = map_pseudo_stats()
+    n = int(P.n)
+    if capacity is None:
+        capacity = max(n, 1) if out is None else int(out["m"].shape[0])
+    if out is None and capacity > 0:
+        out = dict(xyz=np.zeros((capacity, 3)), m=np.zeros(capacity), h=np.zeros(capacity),
+                   size=np.zeros(capacity), kind=np.zeros(capacity, np.int32), ref=np.zeros(capacity, np.int64))
+    arrs = [out[k] if out is not None else None for k in ("xyz", "m", "h", "size", "kind", "ref")]
+    kind = _kind(arrs[1]) if out is not None else MAP_MEM_HOST
+    O = map_pseudo_out(int(capacity), *[_ptr(a) for a in arrs], kind, 0, ctypes.pointer(st))
+    _check(ctx, lib.map_pseudo(ctx, ctypes.byref(P), ctypes.byref(bx), _ptr(src), src.shape[0], ctypes.byref(par),
+                               ctypes.byref(O)))
+    cnt = int(O.n_out)
+    if capacity == 0:
+        return cnt, st.as_dict()
+    res = {k: out[k][:cnt] for k in ("xyz", "m", "h", "size", "kind", "ref")}
+    res["stats"] = st.as_dict()
+    return res
+
+
 class Mapper:
     """Owns one library context."""
 
@@ -330,6 +405,9 @@ class Mapper:
 
     def set_precision(self, precision):
         map_set_precision(self.ctx, precision)
+
+    def pseudo(self, particles, box, sources, **kw):
+        return map_pseudo(self.ctx, particles.xyz, particles.m, particles.h, box, sources, **kw)
 
     def pairs(self, particles, cells):
         return map_pairs(self.ctx, particles.xyz, particles.m, particles.h, cells)

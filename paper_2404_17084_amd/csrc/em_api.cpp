@@ -456,4 +456,62 @@ int map_particles(map_ctx *h, const map_particles_in *p, const map_cells_in *c, 
     });
 }
 
+int map_pseudo(map_ctx *h, const map_particles_in *p, const double box[6], const double *src_xyz, int n_src,
+               const map_pseudo_params *par, map_pseudo_out *out)
+{
+    Ctx *C = reinterpret_cast<Ctx *>(h);
+    API_BODY(C, {
+        EM_CHECK(p && box && par && out, MAP_EINVAL, "null argument");
+        EM_CHECK(p->n >= 0 && p->n < (int64_t)INT32_MAX, MAP_EINVAL, "particle count outside [0, 2^31-1)");
+        EM_CHECK(p->mem_kind == MAP_MEM_HOST || p->mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad particle mem_kind");
+        if (p->n > 0) EM_CHECK(p->xyz && p->m && p->h, MAP_EINVAL, "null particle array");
+        for (int d = 0; d < 3; d++)
+            EM_CHECK(std::isfinite(box[d]) && std::isfinite(box[3 + d]) && box[3 + d] > box[d], MAP_EINVAL,
+                     "box must be finite with hi > lo");
+        EM_CHECK(src_xyz && n_src >= 1 && n_src <= 64, MAP_EINVAL, "need 1 to 64 sources");
+        for (int k = 0; k < 3 * n_src; k++) EM_CHECK(std::isfinite(src_xyz[k]), MAP_EINVAL, "non-finite source");
+        EM_CHECK(std::isfinite(par->theta) && par->theta >= 0.0, MAP_EINVAL, "theta must be finite and >= 0");
+        EM_CHECK(std::isfinite(par->r_part) && par->r_part >= 0.0 && std::isfinite(par->r_leaf) &&
+                     par->r_leaf >= 0.0,
+                 MAP_EINVAL, "r_part and r_leaf must be finite and >= 0");
+        EM_CHECK(par->leaf_size >= 1 && par->leaf_size <= 64, MAP_EINVAL, "leaf_size must be in [1, 64]");
+        EM_CHECK(std::isfinite(par->h_fact_node) && par->h_fact_node > 0.0, MAP_EINVAL, "h_fact_node must be > 0");
+        EM_CHECK(out->capacity >= 0, MAP_EINVAL, "negative capacity");
+        EM_CHECK(out->mem_kind == MAP_MEM_HOST || out->mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad output mem_kind");
+        hipStream_t s = C->stream;
+        DevParticles dp;
+        dp.n = p->n;
+        dp.xyz = stage(C->ws, S_XYZ, p->xyz, 3 * p->n, p->mem_kind, s);
+        dp.m = stage(C->ws, S_M, p->m, p->n, p->mem_kind, s);
+        dp.h = stage(C->ws, S_H, p->h, p->n, p->mem_kind, s);
+        PseudoDest d;
+        d.capacity = out->capacity;
+        d.xyz = out->xyz;
+        d.m = out->m;
+        d.h = out->h;
+        d.size = out->size;
+        d.kind = out->kind;
+        d.ref = out->ref;
+        d.mem_kind = out->mem_kind;
+        map_pseudo_stats st{};
+        const int64_t n_out = run_pseudo(C->ws, dp, box, src_xyz, n_src, *par, d, &st, s, C->ev);
+        out->n_out = n_out;
+        if (p->n > 0) {
+            float t = 0.f;
+            EM_HIP(hipEventElapsedTime(&t, C->ev[0], C->ev[1]));
+            st.ms_tree = t;
+            EM_HIP(hipEventElapsedTime(&t, C->ev[1], C->ev[2]));
+            st.ms_walk = t;
+            EM_HIP(hipEventElapsedTime(&t, C->ev[2], C->ev[3]));
+            st.ms_hsolve = t;
+            EM_HIP(hipEventElapsedTime(&t, C->ev[0], C->ev[3]));
+            st.ms_total = t;
+        }
+        if (out->stats) *out->stats = st;
+        EM_CHECK(out->capacity == 0 || out->capacity >= n_out, MAP_EINVAL,
+                 "output capacity " + std::to_string(out->capacity) + " below the pseudo count " +
+                     std::to_string(n_out));
+    });
+}
+
 }  // extern "C"

@@ -168,6 +168,25 @@ struct PairSet {
 PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, const EdgeRec *edges,
                     int64_t *counters, hipStream_t s);
 
+// em_pseudo.hip: pseudo-particle front end (tree, walk, node smoothing lengths).
+struct DevParticles {
+    int64_t n = 0;
+    const double *xyz = nullptr, *m = nullptr, *h = nullptr;
+};
+struct PseudoDest {
+    int64_t capacity = 0;
+    double *xyz = nullptr, *m = nullptr, *h = nullptr, *size = nullptr;
+    int32_t *kind = nullptr;
+    int64_t *ref = nullptr;
+    int mem_kind = MAP_MEM_HOST;
+};
+// Returns the pseudo count; writes the outputs when dest.capacity suffices.
+// ev (optional): 4 events recorded at start, after the tree, after the walk
+// and after the h-solve.
+int64_t run_pseudo(Workspace &ws, const DevParticles &p, const double box[6], const double *src, int n_src,
+                   const map_pseudo_params &par, const PseudoDest &dest, map_pseudo_stats *st, hipStream_t s,
+                   hipEvent_t *ev);
+
 // One job of a batched integration launch (device-resident table entry).
 struct BatchJob {
     int64_t np;

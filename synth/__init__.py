@@ -194,7 +194,7 @@ def lognormal_positions(n: int, seed: int, grid: int = 256, slope: float = -4.0,
     nz = k2 > 0
     amp[nz] = k2[nz] ** (slope / 4.0)  # sqrt(P(k)) with P ~ k^slope
     noise = rng.standard_normal((grid, grid, grid))
-    g = np.fft.irfftn(np.fft.rfftn(noise) * amp, s=(grid, grid, grid))
+    g = np.fft.irfftn(np.fft.rfftn(noise) * amp, s=(grid, grid, grid), axes=(0, 1, 2))
     g -= g.mean()
     g /= g.std()
     rho = np.exp(sigma_ln * g - 0.5 * sigma_ln ** 2).ravel()

@@ -1,0 +1,209 @@
+"""GPU parity of the pseudo-particle front end (Sec. III) through the C ABI.
+
+The pseudo set (kinds, node labels, particle indices, Morton order) must equal
+the oracle's exactly.  Floating-point tolerances come from the summation
+order: the library sums node masses and mass-weighted positions bottom-up
+(leaf, then children), the oracle over the node's particles in Morton order;
+for a node of k particles the two differ by at most about k u relative
+(u = 2^-53), so positions and sizes get 4 k u (box units), masses 4 k u
+relative, and the smoothing lengths, roots of the same number sum over those
+positions, 64 k u relative.  Extracted particles are copied, so they must be
+bitwise equal.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_2404_17084_amd as em
+
+pytestmark = pytest.mark.gpu
+
+BOX = np.array(synth.BOX, dtype=np.float64)
+U = 2.0 ** -53
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mp():
+    with em.Mapper(device=0) as m:
+        yield m
+
+
+def _compare(G, O, n):
+    assert G["m"].size == O["m"].size, (G["m"].size, O["m"].size)
+    assert np.array_equal(G["kind"], O["kind"])
+    assert np.array_equal(G["ref"], O["ref"])
+    part = O["kind"] == em.PSEUDO_PARTICLE
+    node = ~part
+    # particles: copied values
+    assert np.array_equal(G["xyz"][part], O["xyz"][part])
+    assert np.array_equal(G["m"][part], O["m"][part])
+    assert np.array_equal(G["h"][part], O["h"][part])
+    assert np.all(G["size"][part] == 0.0)
+    if node.any():
+        k = np.maximum(np.rint(O["m"][node] * n), 1.0)  # particles per node (equal masses 1/n)
+        assert np.all(np.abs(G["xyz"][node] - O["xyz"][node]).max(1) <= 4 * k * U + 1e-300)
+        assert np.all(np.abs(G["size"][node] - O["s"][node]) <= 4 * k * U + 1e-300)
+        assert np.all(np.abs(G["m"][node] - O["m"][node]) <= 4 * k * U * O["m"][node])
+        rel = np.abs(G["h"][node] - O["h"][node]) / O["h"][node]
+        assert np.all(rel <= 64 * k * U), rel.max()
+        return float(rel.max())
+    return 0.0
+
+
+CASES = [
+    # kind, n, seed, sources, theta, r_part, r_leaf, leaf
+    ("clumps", 3000, 41, [[0.5, 0.5, 0.5], [0.3, 0.6, 0.45]], 0.5, 0.05, 0.1, 8),
+    ("clumps", 3000, 41, [[0.5, 0.5, 0.5]], 0.3, 0.0, 0.2, 4),
+    ("uniform", 20000, 43, [[0.5, 0.5, 0.5]], 0.5, 0.05, 0.1, 8),
+    ("uniform", 20000, 43, [[0.1, 0.9, 0.2], [0.8, 0.8, 0.8], [0.5, 0.2, 0.6], [1.4, 0.5, 0.5]], 0.8, 0.1, 0.1, 1),
+    ("clumps", 12000, 44, [[0.45, 0.55, 0.5]], 0.5, 0.05, 0.1, 8),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}{c[1]}-t{c[4]}-l{c[7]}" for c in CASES])
+def test_pseudo_matches_oracle(mp, case):
+    kind, n, seed, src, theta, rp, rl, leaf = case
+    say(f"case: pseudo {kind} n={n} seed={seed} theta={theta} leaf={leaf}")
+    p = synth.particles(kind, n, seed)
+    G = mp.pseudo(p, BOX, src, theta=theta, r_part=rp, r_leaf=rl, leaf_size=leaf)
+    O = oracle.pseudo(p.xyz, p.m, p.h, BOX, src, theta, rp, rl, leaf, 1.1)
+    _compare(G, O, n)
+    st, ost = G["stats"], O["stats"]
+    assert st["n_tree_nodes"] == ost["tree_nodes"]
+    assert st["n_leaves"] == ost["leaves"]
+    assert st["max_level"] == ost["max_level"]
+    assert st["n_pseudo_nodes"] == ost["pseudo_nodes"]
+    assert st["n_particles"] == ost["particles"]
+    assert st["n_substitute_leaves"] == ost["substitute_leaves"]
+    assert st["n_fallbacks"] == ost["fallbacks"]
+    assert abs(G["m"].sum() - p.m.sum()) <= 1e-12
+
+
+def test_pseudo_full_size_lognormal(mp):
+    """2,097,152 particles of the log-normal cloud, one source at the centre, theta 0.5."""
+    say("case: pseudo lognormal 2097152 (full size)")
+    p = synth.particles(*synth.LOGNORMAL_2M)
+    src = [[0.5, 0.5, 0.5]]
+    G = mp.pseudo(p, BOX, src, theta=0.5, r_part=0.05, r_leaf=0.1, leaf_size=8)
+    O = oracle.pseudo(p.xyz, p.m, p.h, BOX, src, 0.5, 0.05, 0.1, 8, 1.1)
+    rel = _compare(G, O, p.m.size)
+    say(f"  pseudo {G['m'].size}, max h rel diff {rel:.3e}, ms {G['stats']['ms_total']:.3f}")
+    assert G["stats"]["n_tree_nodes"] == O["stats"]["tree_nodes"]
+    assert abs(G["m"].sum() - 1.0) <= 1e-12
+
+
+def test_pseudo_edge_cases(mp):
+    say("case: pseudo edge cases")
+    # no particles
+    z = np.zeros((0, 3))
+    r = em.map_pseudo(mp.ctx, z, np.zeros(0), np.zeros(0), BOX, [[0.5, 0.5, 0.5]])
+    assert r["m"].size == 0
+    # five particles: the root is a leaf; far source -> one node, near source -> the particles
+    rng = np.random.default_rng(3)
+    x5 = 0.4 + 0.2 * rng.random((5, 3))
+    m5 = np.full(5, 0.2)
+    h5 = np.full(5, 0.05)
+    r = em.map_pseudo(mp.ctx, x5, m5, h5, BOX, [[5.0, 5.0, 5.0]])
+    assert r["m"].size == 1 and r["kind"][0] == em.PSEUDO_NODE and r["ref"][0] == 1
+    assert r["stats"]["n_fallbacks"] == 1  # one point: no root, h from Eq. (9)
+    O = oracle.pseudo(x5, m5, h5, BOX, [[5.0, 5.0, 5.0]])
+    assert abs(r["h"][0] - O["h"][0]) <= 1e-15
+    r = em.map_pseudo(mp.ctx, x5, m5, h5, BOX, [[0.5, 0.5, 0.5]], r_part=0.5)
+    assert np.all(r["kind"] == em.PSEUDO_PARTICLE) and np.array_equal(np.sort(r["ref"]), np.arange(5))
+    # coincident particles: a chain down to level 21, zero sizes
+    xc = np.full((50, 3), 0.3)
+    mc = np.full(50, 0.02)
+    hc = np.linspace(0.01, 0.02, 50)
+    r = em.map_pseudo(mp.ctx, xc, mc, hc, BOX, [[0.9, 0.9, 0.9]])
+    O = oracle.pseudo(xc, mc, hc, BOX, [[0.9, 0.9, 0.9]])
+    assert r["stats"]["max_level"] == 21 == O["stats"]["max_level"]
+    _compare(r, O, 50)
+    # particles on the box walls and a source on a particle
+    p = synth.particles("uniform", 2000, 45)
+    xyz = p.xyz.copy()
+    xyz[:10, 0] = 0.0
+    xyz[10:20, 1] = 1.0
+    src = [xyz[100].tolist()]
+    G = em.map_pseudo(mp.ctx, xyz, p.m, p.h, BOX, src, r_part=0.02)
+    O = oracle.pseudo(xyz, p.m, p.h, BOX, src, 0.5, 0.02, 0.1, 8, 1.1)
+    _compare(G, O, 2000)
+    assert 100 in set(G["ref"][G["kind"] == em.PSEUDO_PARTICLE].tolist())
+    # count only, then too small a buffer
+    cnt, st = em.map_pseudo(mp.ctx, p.xyz, p.m, p.h, BOX, src, capacity=0)
+    assert cnt == st["n_pseudo"] > 1
+    with pytest.raises(em.MapError) as ei:
+        em.map_pseudo(mp.ctx, p.xyz, p.m, p.h, BOX, src, capacity=cnt - 1)
+    assert ei.value.code == em.MAP_EINVAL
+
+
+@pytest.mark.parametrize("what", ["h_zero", "m_neg", "nan_pos", "bad_box", "no_source", "leaf_zero", "theta_neg"])
+def test_pseudo_invalid_inputs(mp, what):
+    say(f"case: pseudo invalid {what}")
+    p = synth.particles("uniform", 500, 46)
+    xyz, m, h = p.xyz.copy(), p.m.copy(), p.h.copy()
+    box = BOX.copy()
+    src = [[0.5, 0.5, 0.5]]
+    kw = {}
+    if what == "h_zero":
+        h[7] = 0.0
+    elif what == "m_neg":
+        m[3] = -1.0
+    elif what == "nan_pos":
+        xyz[9, 2] = np.nan
+    elif what == "bad_box":
+        box[3] = box[0]
+    elif what == "no_source":
+        src = np.zeros((0, 3))
+    elif what == "leaf_zero":
+        kw["leaf_size"] = 0
+    elif what == "theta_neg":
+        kw["theta"] = -0.1
+    with pytest.raises(em.MapError) as ei:
+        em.map_pseudo(mp.ctx, xyz, m, h, box, src, **kw)
+    assert ei.value.code == em.MAP_EINVAL
+    # the context stays usable
+    r = em.map_pseudo(mp.ctx, p.xyz, p.m, p.h, BOX, [[0.5, 0.5, 0.5]])
+    assert abs(r["m"].sum() - 1.0) < 1e-12
+
+
+def test_pseudo_device_buffers_and_determinism(mp):
+    import torch
+    say("case: pseudo device buffers, determinism")
+    p = synth.particles("clumps", 12000, 47)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    n = p.m.size
+    out = dict(xyz=torch.zeros((n, 3), dtype=torch.float64, device=dev),
+               m=torch.zeros(n, dtype=torch.float64, device=dev), h=torch.zeros(n, dtype=torch.float64, device=dev),
+               size=torch.zeros(n, dtype=torch.float64, device=dev),
+               kind=torch.zeros(n, dtype=torch.int32, device=dev), ref=torch.zeros(n, dtype=torch.int64, device=dev))
+    torch.cuda.synchronize()
+    src = [[0.5, 0.5, 0.5]]
+    G = em.map_pseudo(mp.ctx, t(p.xyz), t(p.m), t(p.h), BOX, src, out=out)
+    H = em.map_pseudo(mp.ctx, p.xyz, p.m, p.h, BOX, src)
+    for k in ("xyz", "m", "h", "size", "kind", "ref"):
+        assert np.array_equal(G[k].cpu().numpy(), H[k]), k
+    H2 = em.map_pseudo(mp.ctx, p.xyz, p.m, p.h, BOX, src)
+    for k in ("xyz", "m", "h", "size", "kind", "ref"):
+        assert np.array_equal(H2[k], H[k]), k
+
+
+def test_pseudo_then_mapping(mp):
+    """The pseudo set feeds the mapping: its Voronoi cells, FP64 cell masses vs the oracle, mass conserved."""
+    say("case: pseudo then mapping")
+    p = synth.particles("clumps", 20000, 48)
+    G = mp.pseudo(p, BOX, [[0.5, 0.5, 0.5]], theta=0.5, r_part=0.05, r_leaf=0.1)
+    q = synth.Particles(np.ascontiguousarray(G["xyz"]), np.ascontiguousarray(G["m"]), np.ascontiguousarray(G["h"]))
+    cells = synth.voronoi_cells(q.xyz)
+    r = mp.map(q, cells)
+    O = oracle.map_particles(q, cells)
+    assert np.max(np.abs(r["M"] - O["M"]) / O["M"]) < 1e-10
+    assert abs(r["M"].sum() - 1.0) < 1e-12
