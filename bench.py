@@ -86,6 +86,64 @@ def cpu_baseline(p, c, target_s: float = 12.0):
                       f"closed-form integrals, {dt:.1f} s"}
 
 
+def pseudo_leg(em, steps: int, warmup: int):
+    """The pseudo-particle path: front end on the 2,097,152-particle log-normal cloud (one source at the
+    centre, theta 0.5, r_part 0.05, r_leaf 0.1, leaf <= 8), then the mixed mapping of the pseudo set."""
+    import torch
+    import synth
+
+    print("bench: generating the 2,097,152-particle log-normal cloud", file=sys.stderr, flush=True)
+    p = synth.particles(*synth.LOGNORMAL_2M)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    xyz, m, h = t(p.xyz), t(p.m), t(p.h)
+    n = p.n
+    out = dict(xyz=torch.zeros((n, 3), dtype=torch.float64, device=dev),
+               m=torch.zeros(n, dtype=torch.float64, device=dev), h=torch.zeros(n, dtype=torch.float64, device=dev),
+               size=torch.zeros(n, dtype=torch.float64, device=dev),
+               kind=torch.zeros(n, dtype=torch.int32, device=dev), ref=torch.zeros(n, dtype=torch.int64, device=dev))
+    torch.cuda.synchronize()
+    src = [[0.5, 0.5, 0.5]]
+    par = dict(theta=0.5, r_part=0.05, r_leaf=0.1, leaf_size=8, h_fact_node=1.1)
+    mp = em.Mapper(device=0, precision=em.MAP_MIXED)
+    for _ in range(warmup):
+        em.map_pseudo(mp.ctx, xyz, m, h, synth.BOX, src, out=out, **par)
+    torch.cuda.synchronize()
+    sts = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = em.map_pseudo(mp.ctx, xyz, m, h, synth.BOX, src, out=out, **par)
+        sts.append(r["stats"])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    st = sts[-1]
+    q = synth.Particles(r["xyz"].cpu().numpy().copy(), r["m"].cpu().numpy().copy(), r["h"].cpu().numpy().copy())
+    cells = synth.voronoi_cells(q.xyz)
+    qx, qm, qh, qc = to_device(q, cells)
+    M = torch.zeros(cells.n_cells, dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        em.map_particles(mp.ctx, qx, qm, qh, qc, M)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ms = em.map_particles(mp.ctx, qx, qm, qh, qc, M)
+    torch.cuda.synchronize()
+    dm = (time.perf_counter() - t0) / steps
+    mp.close()
+    return {"workload": "lognormal-2097152: log-normal density (sigma_ln 1.5, P(k) ~ k^-4, 256^3 mesh, seed 3), "
+                        "h from 58 neighbours; one source at the box centre, theta 0.5, r_part 0.05, r_leaf 0.1, "
+                        "leaf <= 8, h_fact 1.1",
+            "particles": n, "pseudo": st["n_pseudo"], "pseudo_nodes": st["n_pseudo_nodes"],
+            "particles_kept": st["n_particles"], "tree_nodes": st["n_tree_nodes"], "max_level": st["max_level"],
+            "h_fallbacks": st["n_fallbacks"], "mean_neighbours": st["n_neighbours"] / max(st["n_pseudo_nodes"], 1),
+            "ms_front_end": 1e3 * dt, "ms_tree": float(np.mean([s["ms_tree"] for s in sts])),
+            "ms_walk": float(np.mean([s["ms_walk"] for s in sts])),
+            "ms_hsolve": float(np.mean([s["ms_hsolve"] for s in sts])),
+            "particles_per_s_front_end": n / dt,
+            "pseudo_pairs": ms["n_pairs"], "ms_map_pseudo": 1e3 * dm, "pairs_per_s_pseudo": ms["n_pairs"] / dm,
+            "mass_err_pseudo": abs(ms["mass_out"] - ms["mass_in"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +151,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--no-pseudo", action="store_true", help="skip the pseudo-particle leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the mapping runs on a single "
@@ -181,6 +240,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32, "unit": "TFLOP/s", "frac": ach / PEAK_FP32,
                      "traffic": None},
     }
+    if not args.no_pseudo:
+        line["pseudo_path"] = pseudo_leg(em, args.steps, args.warmup)
+        print(f"bench: pseudo path: {line['pseudo_path']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on a cell sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(p, c)

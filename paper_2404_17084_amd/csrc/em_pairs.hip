@@ -29,57 +29,69 @@ struct Box {
 // squared distance to its edge segments.  Evaluated with plain IEEE adds,
 // multiplies and divides in a fixed order, without fused multiply-adds, so
 // that the decision dist^2 < (2h)^2 is reproducible on any IEEE machine.
-__device__ __noinline__ double cell_dist2(double px, double py, double pz, int64_t cell, const int64_t *cfo,
-                                          const int64_t *fvo, const EdgeRec *edges, const double *plane)
+// cell_meets decides dist^2 < r2 with that arithmetic, with two shortcuts
+// that cannot change the decision.  (1) The cell lies inside every face's
+// half-space, so its distance is at least max_j(-d_j); when that bound
+// exceeds sqrt(r2) by a relative margin far above the rounding of the
+// polygon distances, the pair is rejected.  (2) The first face or edge
+// distance computed below r2 accepts the pair, since the minimum is no
+// larger.
+__device__ __noinline__ bool cell_meets(double px, double py, double pz, double r2, int64_t cell,
+                                        const int64_t *cfo, const int64_t *fvo, const EdgeRec *edges,
+                                        const double *plane)
 {
 #pragma clang fp contract(off)
+    const int64_t j0 = cfo[cell], j1 = cfo[cell + 1];
+    double far = 0.0;
     bool inside = true;
-    double best = INFINITY;
-    for (int64_t j = cfo[cell]; j < cfo[cell + 1]; j++) {
-        double n0 = plane[4 * j], n1 = plane[4 * j + 1], n2 = plane[4 * j + 2], c = plane[4 * j + 3];
-        double d = c - (n0 * px + n1 * py + n2 * pz);
+    for (int64_t j = j0; j < j1; j++) {
+        const double d = plane[4 * j + 3] - (plane[4 * j] * px + plane[4 * j + 1] * py + plane[4 * j + 2] * pz);
+        if (d < 0.0) {
+            inside = false;
+            if (-d > far) far = -d;
+        }
+    }
+    if (inside) return true;
+    if (far * far > r2 * (1.0 + 1e-9)) return false;
+    for (int64_t j = j0; j < j1; j++) {
+        const double n0 = plane[4 * j], n1 = plane[4 * j + 1], n2 = plane[4 * j + 2], c = plane[4 * j + 3];
+        const double d = c - (n0 * px + n1 * py + n2 * pz);
         if (!(d < 0.0)) continue;
-        inside = false;
-        int64_t k0 = fvo[j], k1 = fvo[j + 1];
-        int64_t nv = k1 - k0;
+        const int64_t k0 = fvo[j], k1 = fvo[j + 1];
+        const int64_t nv = k1 - k0;
         bool left = true;
         for (int64_t k = 0; k < nv; k++) {
-            // edge records hold exact copies of the vertex coordinates
             const EdgeRec &A = edges[k0 + k];
             const EdgeRec &B = edges[k0 + (k + 1 == nv ? 0 : k + 1)];
-            double ex = B.vx - A.vx, ey = B.vy - A.vy, ez = B.vz - A.vz;
-            double wx = px - A.vx, wy = py - A.vy, wz = pz - A.vz;
-            double cr = (ey * wz - ez * wy) * n0 + (ez * wx - ex * wz) * n1 + (ex * wy - ey * wx) * n2;
+            const double ex = B.vx - A.vx, ey = B.vy - A.vy, ez = B.vz - A.vz;
+            const double wx = px - A.vx, wy = py - A.vy, wz = pz - A.vz;
+            const double cr = (ey * wz - ez * wy) * n0 + (ez * wx - ex * wz) * n1 + (ex * wy - ey * wx) * n2;
             if (cr < 0.0) {
                 left = false;
                 break;
             }
         }
-        double dd;
         if (left) {
-            dd = d * d;
-        } else {
-            dd = INFINITY;
-            for (int64_t k = 0; k < nv; k++) {
-                const EdgeRec &A = edges[k0 + k];
-                const EdgeRec &B = edges[k0 + (k + 1 == nv ? 0 : k + 1)];
-                double ex = B.vx - A.vx, ey = B.vy - A.vy, ez = B.vz - A.vz;
-                double wx = px - A.vx, wy = py - A.vy, wz = pz - A.vz;
-                double ee = ex * ex + ey * ey + ez * ez;
-                double t = 0.0;
-                if (ee > 0.0) {
-                    t = (wx * ex + wy * ey + wz * ez) / ee;
-                    if (t < 0.0) t = 0.0;
-                    if (t > 1.0) t = 1.0;
-                }
-                double qx = wx - t * ex, qy = wy - t * ey, qz = wz - t * ez;
-                double e2 = qx * qx + qy * qy + qz * qz;
-                if (e2 < dd) dd = e2;
-            }
+            if (d * d < r2) return true;
+            continue;
         }
-        if (dd < best) best = dd;
+        for (int64_t k = 0; k < nv; k++) {
+            const EdgeRec &A = edges[k0 + k];
+            const EdgeRec &B = edges[k0 + (k + 1 == nv ? 0 : k + 1)];
+            const double ex = B.vx - A.vx, ey = B.vy - A.vy, ez = B.vz - A.vz;
+            const double wx = px - A.vx, wy = py - A.vy, wz = pz - A.vz;
+            const double ee = ex * ex + ey * ey + ez * ez;
+            double t = 0.0;
+            if (ee > 0.0) {
+                t = (wx * ex + wy * ey + wz * ez) / ee;
+                if (t < 0.0) t = 0.0;
+                if (t > 1.0) t = 1.0;
+            }
+            const double qx = wx - t * ex, qy = wy - t * ey, qz = wz - t * ez;
+            if (qx * qx + qy * qy + qz * qz < r2) return true;
+        }
     }
-    return inside ? 0.0 : best;
+    return false;
 }
 
 // Morton code (21 bits per axis) of each cell's bounding-box centre
@@ -194,22 +206,25 @@ __global__ void k_candidates(int64_t n, const double *__restrict__ xyz, const do
     if (!FILL) ccount[a] = count;
 }
 
-// One thread per candidate: 1 if the pair exists.  A cell is accepted without
-// the exact test when an interior point of it (the mean of its wall vertices)
-// or its whole bounding box lies within (1 - 1e-6) 2h of the particle: its
-// distance is then certainly below 2h.  Otherwise the exact test decides.
-__global__ void k_exact(int64_t nc_total, const uint32_t *__restrict__ cand_c, const uint32_t *__restrict__ cand_p,
-                        const double *__restrict__ xyz, const double *__restrict__ h,
-                        const double *__restrict__ aabb, const double *__restrict__ centre,
-                        const int64_t *__restrict__ cfo, const int64_t *__restrict__ fvo,
-                        const EdgeRec *__restrict__ edges,
+// One thread per candidate, candidates in cell order (consecutive threads
+// share a cell, so its walls stay in cache): 1 if the pair exists, written to
+// the candidate's own slot.  A cell is accepted without the exact test when
+// an interior point of it (the mean of its wall vertices) or its whole
+// bounding box lies within (1 - 1e-6) 2h of the particle: its distance is
+// then certainly below 2h.  Otherwise the exact test decides.
+__global__ void k_exact(int64_t nc_total, const uint32_t *__restrict__ sorted_c, const uint32_t *__restrict__ sorted_q,
+                        const uint32_t *__restrict__ cand_p, const double *__restrict__ xyz,
+                        const double *__restrict__ h, const double *__restrict__ aabb,
+                        const double *__restrict__ centre, const int64_t *__restrict__ cfo,
+                        const int64_t *__restrict__ fvo, const EdgeRec *__restrict__ edges,
                         const double *__restrict__ plane, int64_t *__restrict__ flag,
                         unsigned long long *exact_counter)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long tested = 0;
-    if (q < nc_total) {
-        const int64_t c = cand_c[q], a = cand_p[q];
+    if (t < nc_total) {
+        const int64_t c = sorted_c[t], q = sorted_q[t];
+        const int64_t a = cand_p[q];
         const double px = xyz[3 * a], py = xyz[3 * a + 1], pz = xyz[3 * a + 2];
         const double r = 2.0 * h[a];
         const double r2 = r * r;
@@ -223,7 +238,7 @@ __global__ void k_exact(int64_t nc_total, const uint32_t *__restrict__ cand_c, c
             ok = 1;
         } else {
             tested = 1;
-            ok = cell_dist2(px, py, pz, c, cfo, fvo, edges, plane) < r2 ? 1 : 0;
+            ok = cell_meets(px, py, pz, r2, c, cfo, fvo, edges, plane) ? 1 : 0;
         }
         flag[q] = ok;
     }
@@ -334,14 +349,21 @@ PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, cons
                        (const double *)nodes, NL, (const uint32_t *)cperm, (int64_t *)nullptr,
                        (const int64_t *)coffs, cand_c, cand_p);
     EM_HIP(hipGetLastError());
-    // exact test, one thread per candidate, then compaction
+    // exact test, one thread per candidate in cell order, then compaction
     int64_t *flag = ws.get<int64_t>(S_F_PM, (size_t)(ncand > 0 ? ncand : 1));
     int64_t *fpos = ws.get<int64_t>(S_F, (size_t)(ncand + 1));
     unsigned long long *cand = reinterpret_cast<unsigned long long *>(counters + C_CANDIDATES);
     if (ncand > 0) {
+        uint32_t *sc = ws.get<uint32_t>(S_PC_PM, (size_t)ncand);
+        uint32_t *sq = ws.get<uint32_t>(S_PP_PM, (size_t)ncand);
+        uint32_t *sc2 = ws.get<uint32_t>(S_PERM, (size_t)ncand);
+        uint32_t *sq2 = ws.get<uint32_t>(S_PAIR_P, (size_t)ncand);
+        EM_HIP(hipMemcpyAsync(sc, cand_c, sizeof(uint32_t) * ncand, hipMemcpyDeviceToDevice, s));
+        fill_iota_u32(sq, ncand, s);
+        radix_sort_u32(ws, sc, sq, sc2, sq2, ncand, bits_for((uint64_t)nc - 1), s);
         hipLaunchKernelGGL(k_exact, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand,
-                           (const uint32_t *)cand_c, (const uint32_t *)cand_p, in.xyz, in.h, aabb, aabb + 6 * nc,
-                           in.cfo, in.fvo, edges, in.plane, flag, cand);
+                           (const uint32_t *)sc, (const uint32_t *)sq, (const uint32_t *)cand_p, in.xyz, in.h, aabb,
+                           aabb + 6 * nc, in.cfo, in.fvo, edges, in.plane, flag, cand);
         EM_HIP(hipGetLastError());
     }
     scan_counts(ws, flag, fpos, ncand, s);

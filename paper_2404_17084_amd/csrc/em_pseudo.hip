@@ -23,10 +23,10 @@
 //
 // Smoothing lengths (Sec. III-C, Eq. (7)-(9)).  The number sum
 // N(h) = (1/pi) sum_b w(|x - x_b| / h) runs over the node pseudo-particles and
-// the leaves standing in for extracted particles, grouped 8 per leaf of an
-// implicit box tree in Morton order; each node solves N(h) = h_fact^3 by
-// Newton steps kept inside a bisection bracket, each evaluation one stackless
-// ball query of radius 2h (points visited in Morton order).
+// the leaves standing in for extracted particles, grouped 8 per box in Morton
+// order.  One wavefront per node solves N(h) = h_fact^3 by Newton steps kept
+// inside a bisection bracket; each evaluation tests 64 boxes per step against
+// the ball of radius 2h and adds the contributions in point order.
 #include <cmath>
 
 #include "em_internal.h"
@@ -445,19 +445,6 @@ __global__ void k_pt_leaf_boxes(int64_t n_pts, int64_t NL, const double4 *__rest
     }
 }
 
-__global__ void k_pt_parent_boxes(int64_t first, int64_t count, double *__restrict__ bx)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= count) return;
-    const int64_t i = first + t;
-    const double *a = bx + 6 * (2 * i), *b = bx + 6 * (2 * i + 1);
-    double *o = bx + 6 * i;
-    for (int d = 0; d < 3; d++) {
-        o[d] = fmin(a[d], b[d]);
-        o[3 + d] = fmax(a[3 + d], b[3 + d]);
-    }
-}
-
 __device__ __forceinline__ double box_gap2(const double *bb, double px, double py, double pz)
 {
 #pragma clang fp contract(off)
@@ -488,35 +475,55 @@ struct NumSum {
     int64_t count;
 };
 
-// sum over the points within 2h, visited in point order
-__device__ NumSum number_sum(double px, double py, double pz, double h, int64_t n_pts,
-                             const double4 *__restrict__ pts, const double *__restrict__ bx, int64_t NL)
+// One wavefront evaluates the number sum for one node.  Lane l tests leaf
+// base+l of the point tree and evaluates its (up to 8) points; the values are
+// then added by every lane in point order (leaf by leaf, point by point), so
+// the sum equals the plain sequential sum over all points (terms beyond the
+// support are exact zeros) whatever the launch shape.
+__device__ NumSum number_sum_wave(double px, double py, double pz, double h, int64_t n_pts,
+                                  const double4 *__restrict__ pts, const double *__restrict__ bx, int64_t NL,
+                                  int64_t nleaf, int lane)
 {
 #pragma clang fp contract(off)
     NumSum r{0.0, 0.0, 0};
     const double R2 = 4.0 * h * h * (1.0 + 1e-9);
-    int64_t i = 1;
-    for (;;) {
-        const bool hit = box_gap2(bx + 6 * i, px, py, pz) <= R2;
-        if (hit && i < NL) {
-            i = 2 * i;
-            continue;
+    for (int64_t base = 0; base < nleaf; base += 64) {
+        const int64_t j = base + lane;
+        double wv[kPtLeaf], dv[kPtLeaf];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < kPtLeaf; k++) {
+            wv[k] = 0.0;
+            dv[k] = 0.0;
         }
-        if (hit) {
-            const int64_t t0 = kPtLeaf * (i - NL);
-            for (int64_t t = t0; t < t0 + kPtLeaf && t < n_pts; t++) {
-                const double4 p = pts[t];
-                const double q = sqrt(dist2(px, py, pz, p.x, p.y, p.z)) / h;
-                if (q < 2.0) {
-                    r.sum_w += m4_w(q);
-                    r.sum_qdw += m4_qdw(q);
-                    r.count++;
+        if (j < nleaf && box_gap2(bx + 6 * (NL + j), px, py, pz) <= R2) {
+#pragma unroll
+            for (int k = 0; k < kPtLeaf; k++) {
+                const int64_t t = kPtLeaf * j + k;
+                if (t < n_pts) {
+                    const double4 p = pts[t];
+                    const double q = sqrt(dist2(px, py, pz, p.x, p.y, p.z)) / h;
+                    if (q < 2.0) {
+                        wv[k] = m4_w(q);
+                        dv[k] = m4_qdw(q);
+                        any = true;
+                    }
                 }
             }
         }
-        while (i & 1) i >>= 1;
-        if (i == 0) break;
-        i += 1;
+        unsigned long long mask = __ballot(any);
+        while (mask) {
+            const int l = __ffsll((long long)mask) - 1;
+            mask &= mask - 1;
+#pragma unroll
+            for (int k = 0; k < kPtLeaf; k++) {
+                const double v = __shfl(wv[k], l, 64);
+                const double d = __shfl(dv[k], l, 64);
+                r.sum_w += v;
+                r.sum_qdw += d;
+                r.count += v != 0.0 ? 1 : 0;
+            }
+        }
     }
     return r;
 }
@@ -525,102 +532,102 @@ struct HStats {
     unsigned long long evals, neighbours, fallbacks;
 };
 
-__global__ void k_hsolve(int64_t n_pts, const double4 *__restrict__ pts, const double *__restrict__ bx, int64_t NL,
-                         const int64_t *__restrict__ pt_slot, const int32_t *__restrict__ pt_node, Nodes T,
-                         const uint32_t *__restrict__ perm, const double *__restrict__ hpart, double h_fact,
-                         double *__restrict__ out_h, unsigned long long *__restrict__ counters)
+// One wavefront per point; points that are pseudo nodes solve N(h) = h_fact^3.
+// All lanes run the same control flow on the same (wave-uniform) values.
+__global__ void __launch_bounds__(256) k_hsolve(int64_t n_pts, const double4 *__restrict__ pts,
+                                                const double *__restrict__ bx, int64_t NL, int64_t nleaf,
+                                                const int64_t *__restrict__ pt_slot,
+                                                const int32_t *__restrict__ pt_node, Nodes T,
+                                                const uint32_t *__restrict__ perm, const double *__restrict__ hpart,
+                                                double h_fact, double *__restrict__ out_h,
+                                                unsigned long long *__restrict__ counters)
 {
 #pragma clang fp contract(off)
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (t >= n_pts || pt_slot[t] < 0) return;  // wave-uniform
     unsigned long long evals = 0, nb = 0, fb = 0;
-    if (t < n_pts && pt_slot[t] >= 0) {
-        const int32_t nd = pt_node[t];
-        const double4 x = pts[t];
-        const double s = sqrt(__longlong_as_double((long long)T.d2[nd]));
-        double h0;
-        if (s > 0.0) {
-            h0 = h_fact * 2.0 * s;
-        } else {
-            h0 = 0.0;
-            for (int32_t k = T.start[nd]; k < T.end[nd]; k++) h0 = fmax(h0, hpart[perm[k]]);
-        }
-        const double target = h_fact * h_fact * h_fact;
-        double result = h0;
-        bool ok = h0 > 0.0 && (double)n_pts / M_PI > target;
-        double lo = 0.0, hi = h0;
-        NumSum Nh{};
-        if (ok) {
-            int k = 0;
-            Nh = number_sum(x.x, x.y, x.z, hi, n_pts, pts, bx, NL);
-            evals++;
-            if (Nh.sum_w / M_PI < target) {
-                do {
-                    lo = hi;
-                    hi = 2.0 * hi;
-                    Nh = number_sum(x.x, x.y, x.z, hi, n_pts, pts, bx, NL);
-                    evals++;
-                } while (Nh.sum_w / M_PI < target && ++k < 200);
-            } else {
-                lo = 0.5 * hi;
-                NumSum Nl = number_sum(x.x, x.y, x.z, lo, n_pts, pts, bx, NL);
+    const int32_t nd = pt_node[t];
+    const double4 x = pts[t];
+    const double s = sqrt(__longlong_as_double((long long)T.d2[nd]));
+    double h0;
+    if (s > 0.0) {
+        h0 = h_fact * 2.0 * s;
+    } else {
+        h0 = 0.0;
+        for (int32_t k = T.start[nd]; k < T.end[nd]; k++) h0 = fmax(h0, hpart[perm[k]]);
+    }
+    const double target = h_fact * h_fact * h_fact;
+    double result = h0;
+    bool ok = h0 > 0.0 && (double)n_pts / M_PI > target;
+    double lo = 0.0, hi = h0;
+    NumSum Nh{};
+    if (ok) {
+        int k = 0;
+        Nh = number_sum_wave(x.x, x.y, x.z, hi, n_pts, pts, bx, NL, nleaf, lane);
+        evals++;
+        if (Nh.sum_w / M_PI < target) {
+            do {
+                lo = hi;
+                hi = 2.0 * hi;
+                Nh = number_sum_wave(x.x, x.y, x.z, hi, n_pts, pts, bx, NL, nleaf, lane);
                 evals++;
-                while (Nl.sum_w / M_PI >= target && ++k < 200) {
-                    hi = lo;
-                    Nh = Nl;
-                    lo = 0.5 * lo;
-                    Nl = number_sum(x.x, x.y, x.z, lo, n_pts, pts, bx, NL);
-                    evals++;
-                }
+            } while (Nh.sum_w / M_PI < target && ++k < 200);
+        } else {
+            lo = 0.5 * hi;
+            NumSum Nl = number_sum_wave(x.x, x.y, x.z, lo, n_pts, pts, bx, NL, nleaf, lane);
+            evals++;
+            while (Nl.sum_w / M_PI >= target && ++k < 200) {
+                hi = lo;
+                Nh = Nl;
+                lo = 0.5 * lo;
+                Nl = number_sum_wave(x.x, x.y, x.z, lo, n_pts, pts, bx, NL, nleaf, lane);
+                evals++;
             }
-            ok = k < 200;
         }
-        if (ok) {
-            // N(lo) < target <= N(hi); Newton from hi, safeguarded by the bracket
-            // Newton iterates may approach the root from one side only, so a
-            // converged iterate (not the far end of the bracket) is the answer
-            double hc = hi;
-            NumSum Nc = Nh;
+        ok = k < 200;
+    }
+    if (ok) {
+        // N(lo) < target <= N(hi); Newton steps kept inside the bracket.  The
+        // iterates may approach the root from one side only, so a converged
+        // iterate, not the far end of the bracket, is the answer.
+        double hc = hi;
+        NumSum Nc = Nh;
+        result = hi;
+        nb = (unsigned long long)Nh.count;
+        for (int it = 0; it < 100 && hi - lo > 1e-15 * hi; it++) {
+            const double N = Nc.sum_w / M_PI;
+            const double dN = -Nc.sum_qdw / (M_PI * hc);
+            double hn = dN > 0.0 ? hc - (N - target) / dN : 0.5 * (lo + hi);
+            if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
+            if (hn <= lo || hn >= hi) break;
+            const NumSum Nn = number_sum_wave(x.x, x.y, x.z, hn, n_pts, pts, bx, NL, nleaf, lane);
+            evals++;
+            if (Nn.sum_w / M_PI >= target) {
+                hi = hn;
+                Nh = Nn;
+            } else {
+                lo = hn;
+            }
+            const bool tiny = fabs(hn - hc) <= 4e-16 * hn;
+            hc = hn;
+            Nc = Nn;
             result = hi;
             nb = (unsigned long long)Nh.count;
-            for (int it = 0; it < 100 && hi - lo > 1e-15 * hi; it++) {
-                const double N = Nc.sum_w / M_PI;
-                const double dN = -Nc.sum_qdw / (M_PI * hc);
-                double hn = dN > 0.0 ? hc - (N - target) / dN : 0.5 * (lo + hi);
-                if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
-                if (hn <= lo || hn >= hi) break;
-                const NumSum Nn = number_sum(x.x, x.y, x.z, hn, n_pts, pts, bx, NL);
-                evals++;
-                if (Nn.sum_w / M_PI >= target) {
-                    hi = hn;
-                    Nh = Nn;
-                } else {
-                    lo = hn;
-                }
-                const bool tiny = fabs(hn - hc) <= 4e-16 * hn;
-                hc = hn;
-                Nc = Nn;
-                result = hi;
-                nb = (unsigned long long)Nh.count;
-                if (tiny) {
-                    result = hn;
-                    nb = (unsigned long long)Nn.count;
-                    break;
-                }
+            if (tiny) {
+                result = hn;
+                nb = (unsigned long long)Nn.count;
+                break;
             }
-        } else {
-            fb = 1;
         }
+    } else {
+        fb = 1;
+    }
+    if (lane == 0) {
         out_h[pt_slot[t]] = result;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        evals += __shfl_xor(evals, o, 64);
-        nb += __shfl_xor(nb, o, 64);
-        fb += __shfl_xor(fb, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0 && (evals || fb)) {
         atomicAdd(counters + 0, evals);
         atomicAdd(counters + 1, nb);
-        atomicAdd(counters + 2, fb);
+        if (fb) atomicAdd(counters + 2, fb);
     }
 }
 
@@ -860,12 +867,8 @@ int64_t run_pseudo(Workspace &ws, const DevParticles &P, const double box[6], co
         hipLaunchKernelGGL(k_pt_leaf_boxes, dim3(grid_of(NL)), dim3(256), 0, s, n_pts, NL, (const double4 *)pts,
                            bx);
         EM_HIP(hipGetLastError());
-        for (int64_t first = NL / 2; first >= 1; first /= 2) {
-            hipLaunchKernelGGL(k_pt_parent_boxes, dim3(grid_of(first)), dim3(256), 0, s, first, first, bx);
-            EM_HIP(hipGetLastError());
-        }
-        hipLaunchKernelGGL(k_hsolve, dim3(grid_of(n_pts, 64)), dim3(64), 0, s, n_pts, (const double4 *)pts,
-                           (const double *)bx, NL, (const int64_t *)pt_slot, (const int32_t *)pt_node, T,
+        hipLaunchKernelGGL(k_hsolve, dim3(grid_of(64 * n_pts)), dim3(256), 0, s, n_pts, (const double4 *)pts,
+                           (const double *)bx, NL, nleaf, (const int64_t *)pt_slot, (const int32_t *)pt_node, T,
                            (const uint32_t *)perm, P.h, par.h_fact_node, O.h, hc);
         EM_HIP(hipGetLastError());
     }
