@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-pseudo", action="store_true", help="skip the pseudo-particle leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="finish with one plain 1 GiB device-to-device copy (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the mapping runs on a single "
@@ -246,6 +248,13 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on a cell sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(p, c)
+    if args.copy_calibration:
+        src_t = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        dst_t = torch.empty_like(src_t)
+        torch.cuda.synchronize()
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = 1 << 30
     print(json.dumps(line), flush=True)
 
 

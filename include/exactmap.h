@@ -151,7 +151,9 @@ int map_set_precision(map_ctx *ctx, int precision);
  * default; FP64 kernel 2..4, mixed kernel 4..6), wavefronts of consecutive
  * pairs taken per queue pop (1..64), persistent workgroups of 256 threads per
  * compute unit (1..64), and the work distribution: 1 = persistent queue of
- * pair tiles, 2 = persistent queue of single-cell tiles, 0 = one thread per
+ * pair tiles, 2 = persistent queue of single-cell tiles, 3 = persistent queue
+ * of pair tiles whose edge terms are run as wavefront-wide task batches
+ * (mixed precision only; the FP64 path runs 3 as 1), 0 = one thread per
  * pair, -1 = clear the explicit setting (back to the tuned table/default).
  * For a given distribution, results are bitwise independent of the other
  * knobs and of scheduling; the distributions are separate kernels and agree

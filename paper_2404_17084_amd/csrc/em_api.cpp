@@ -380,7 +380,7 @@ int map_set_tune(map_ctx *h, int precision, int waves, int tile_waves, int grid_
     Ctx *C = reinterpret_cast<Ctx *>(h);
     API_BODY(C, {
         EM_CHECK(precision == MAP_FP64 || precision == MAP_MIXED, MAP_EINVAL, "precision must be MAP_FP64 or MAP_MIXED");
-        EM_CHECK(persistent >= -1 && persistent <= 2, MAP_EINVAL, "persistent must be -1 (clear), 0, 1 or 2");
+        EM_CHECK(persistent >= -1 && persistent <= 3, MAP_EINVAL, "persistent must be -1 (clear), 0, 1, 2 or 3");
         if (persistent < 0) {
             C->has_explicit[precision] = false;
         } else {

@@ -477,6 +477,348 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_persistent(int64_t np, c
     flush_work(wk, counters);
 }
 
+// ---------------------------------------------------------------- queued tasks (mixed path)
+// The edge terms split into independent tasks of three kinds: angles (one
+// atan2), closed-form points (one trans + core) and shell quadrature
+// sub-intervals (8 Gauss-Legendre points).  In a wavefront of 64 pairs most
+// lanes need only a few of the possible tasks at a given edge, so running
+// every kind whenever any lane needs it leaves most lanes idle.  Here each
+// lane classifies its edge and pushes its tasks, with their weights and the
+// edge's sign, onto per-wavefront stacks in LDS; a stack holding 64 tasks is
+// run by the whole wavefront at once, and every result is added to its
+// pair's FP64 accumulator (LDS).  Lanes walk their cell's wall slots with one
+// wave-uniform counter, so the pushes and runs are in uniform control flow.
+constexpr int kQ = 128;  // stack capacity: below 64 pending before a push of at most 64
+
+struct WaveStacks {
+    float ang[4][kQ];  // R0, a, b, weight
+    int ang_o[kQ];
+    float pnt[7][kQ];  // r0, R0, c2, c, x, S, weight
+    int pnt_o[kQ];
+    float qd[5][kQ];   // r0, c2, mid, half-length, weight
+    int qd_o[kQ];
+    double acc[64];
+};
+
+__device__ __forceinline__ int wave_push(bool want, int &count)
+{
+    const unsigned long long m = __ballot(want);
+    const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+    const int slot = count + below;
+    count += __popcll(m);
+    return slot;
+}
+
+__device__ __forceinline__ void lds_sync_wave()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void run_angle(WaveStacks &W, int i, Work &wk)
+{
+    const float R0 = W.ang[0][i], a = W.ang[1][i], b = W.ang[2][i], w = W.ang[3][i];
+    const float v = w * seg_angle<float>(R0, a, b, wk);
+    atomicAdd(&W.acc[W.ang_o[i]], (double)v);
+}
+
+__device__ __forceinline__ void run_point(WaveStacks &W, int i, Work &wk)
+{
+    const float r0 = W.pnt[0][i], R0 = W.pnt[1][i], c2 = W.pnt[2][i], c = W.pnt[3][i];
+    const float x = W.pnt[4][i], S = W.pnt[5][i], w = W.pnt[6][i];
+    const Trans<float> t = trans<float>(r0, R0, c2, c, x, S, wk);
+    const float v = w * core_inner<float>(t, r0, R0, r0 * r0, c2);
+    atomicAdd(&W.acc[W.pnt_o[i]], (double)v);
+}
+
+// one sub-interval of the shell integrand, as in shell_quad
+__device__ __forceinline__ void run_quad(WaveStacks &W, int i, Work &wk)
+{
+    const float r0 = W.qd[0][i], c2 = W.qd[1][i], mid = W.qd[2][i], hl = W.qd[3][i], w = W.qd[4][i];
+    const float V = 2.0f - r0;
+    const float V2 = V * V, V4 = V2 * V2, V5 = V4 * V;
+    const float rp1 = r0 + 1.0f;
+    float acc = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        const float xq = (q & 1) ? -kGLx[q >> 1] : kGLx[q >> 1];
+        const float l = mid + hl * xq;
+        const float S = sqrtf(c2 + l * l);
+        const float U = 2.0f - S;
+        const float U2 = U * U;
+        const float Sig = (((U + V) * U + V2) * U + V2 * V) * U + V4;
+        const float num = rp1 * (r0 * Sig + V5) - r0 * U2 * U2 * U;
+        acc += kGLw[q >> 1] * num * rcp32(S * (S + r0));
+    }
+    wk.quads++;
+    atomicAdd(&W.acc[W.qd_o[i]], (double)(w * acc));
+}
+
+template <int KIND>
+__device__ __forceinline__ void run_one(WaveStacks &W, int i, Work &wk)
+{
+    if (KIND == 0) run_angle(W, i, wk);
+    else if (KIND == 1) run_point(W, i, wk);
+    else run_quad(W, i, wk);
+}
+
+// run the top 64 entries when 64 are pending (all = false), or all pending ones
+template <int KIND>
+__device__ __forceinline__ void run_stack(WaveStacks &W, int &count, int lane, bool all, Work &wk)
+{
+    if (count >= 64) {
+        lds_sync_wave();
+        run_one<KIND>(W, count - 64 + lane, wk);
+        count -= 64;
+        lds_sync_wave();
+    }
+    if (all && count > 0) {
+        lds_sync_wave();
+        if (lane < count) run_one<KIND>(W, lane, wk);
+        count = 0;
+        lds_sync_wave();
+    }
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <int WPE>
+__global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const uint32_t *__restrict__ pair_p,
+                                                           const uint32_t *__restrict__ pair_c,
+                                                           const double *__restrict__ xyz,
+                                                           const double *__restrict__ h,
+                                                           const int64_t *__restrict__ cfo,
+                                                           const int64_t *__restrict__ fvo,
+                                                           const double *__restrict__ plane,
+                                                           const EdgeRec *__restrict__ edges,
+                                                           double *__restrict__ f, unsigned long long *counters,
+                                                           unsigned *tile_ctr, FixList fx)
+{
+    __shared__ WaveStacks stacks[4];
+    const int lane = threadIdx.x & 63;
+    WaveStacks &W = stacks[threadIdx.x >> 6];
+    const int64_t ntiles = (np + 63) / 64;
+    Work wk;
+    for (;;) {
+        unsigned t = 0;
+        if (lane == 0) t = atomicAdd(tile_ctr, 1u);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if ((int64_t)t >= ntiles) break;
+        const int64_t k = (int64_t)t * 64 + lane;
+        const bool active = k < np;
+        double px = 0.0, py = 0.0, pz = 0.0, invh = 1.0;
+        int64_t s = 0, s_end = 0, j = 0;
+        if (active) {
+            const int64_t a = pair_p[k];
+            const int64_t c = pair_c[k];
+            px = xyz[3 * a];
+            py = xyz[3 * a + 1];
+            pz = xyz[3 * a + 2];
+            invh = 1.0 / h[a];
+            j = cfo[c] - 1;
+            s = fvo[cfo[c]];
+            s_end = fvo[cfo[c + 1]];
+        }
+        W.acc[lane] = 0.0;
+        int64_t face_end = s;  // first slot past the current wall: the first step opens the cell's first wall
+        const int n_steps = wave_max((int)(s_end - s));
+        int nA = 0, nP = 0, nQ = 0;
+        bool inside = true;
+        bool face_ok = false;
+        double r0d = 0.0;
+        float r0 = 0.0f, Ht = 0.0f, dH = 0.0f, fsign = 1.0f;
+        for (int it = 0; it < n_steps; it++, s++) {
+            const bool valid = s < s_end;
+            if (valid && s == face_end) {
+                j++;
+                face_end = fvo[j + 1];
+                const double d = plane[4 * j + 3] - (plane[4 * j] * px + plane[4 * j + 1] * py + plane[4 * j + 2] * pz);
+                wk.faces++;
+                const bool in_j = d >= 0.0;
+                inside = inside && in_j;
+                fsign = in_j ? 1.0f : -1.0f;
+                r0d = fabs(d) * invh;
+                face_ok = r0d < 2.0;
+                r0 = (float)r0d;
+                Ht = pi_H<float>(r0);
+                dH = pi_dH<float>(r0);
+            }
+            // one edge: FP64 projections, FP32 classification into tasks
+            bool live = valid && face_ok;
+            float R0 = 0.0f, la = 0.0f, lb = 0.0f, sg = 0.0f;
+            if (live) {
+                const EdgeRec E = edges[s];
+                const double wx = px - E.vx, wy = py - E.vy, wz = pz - E.vz;
+                const double rho = E.mx * wx + E.my * wy + E.mz * wz;
+                wk.edges++;
+                if (rho == 0.0) {
+                    live = false;
+                } else {
+                    const double lad = -(E.ex * wx + E.ey * wy + E.ez * wz) * invh;
+                    const double lbd = lad + E.L * invh;
+                    const double R0d = fabs(rho) * invh;
+                    const double c2d = r0d * r0d + R0d * R0d;
+                    if (needs_fp64(r0d, R0d, c2d)) {
+                        const unsigned slot = atomicAdd(fx.count, 1u);
+                        if (slot < fx.cap) fx.items[slot] = ((uint64_t)k << 32) | (uint64_t)(uint32_t)s;
+                        live = false;
+                    } else {
+                        R0 = (float)R0d;
+                        la = (float)lad;
+                        lb = (float)lbd;
+                        sg = (rho > 0.0 ? 1.0f : -1.0f) * fsign;
+                    }
+                }
+            }
+            // classification (the mixed form of edge_term)
+            const float A = r0 * r0;
+            const float c2 = A + R0 * R0;
+            float aa[4] = {la, 0.f, 0.f, 0.f}, ab[4] = {lb, 0.f, 0.f, 0.f}, aw[4] = {0.f, 0.f, 0.f, 0.f};
+            float wi0 = 0.f, wi1 = 0.f, wi2 = 0.f;
+            float qa0 = 0.f, qb0 = 0.f, qa1 = 0.f, qb1 = 0.f, qd0 = 1.f;
+            bool q0 = false, q1 = false;
+            float l2 = 0.f, c = 1.f, l1 = 0.f, ca = la, cb = lb;
+            if (live) {
+                if (!(c2 < 4.0f)) {
+                    aw[0] = -Ht;
+                } else {
+                    wk.eterms++;
+                    l2 = sqrtf(4.0f - c2);
+                    c = sqrtf(c2);
+                    ca = fminf(fmaxf(la, -l2), l2);
+                    cb = fminf(fmaxf(lb, -l2), l2);
+                    if (la < -l2) {
+                        aw[0] = -Ht;
+                        ab[0] = fminf(lb, -l2);
+                    }
+                    if (lb > l2) {
+                        aa[1] = fmaxf(la, l2);
+                        ab[1] = lb;
+                        aw[1] = -Ht;
+                    }
+                    if (c2 >= 1.0f) {
+                        if (cb > ca) {
+                            q0 = true;
+                            qa0 = ca;
+                            qb0 = cb;
+                            qd0 = c;
+                            aa[2] = ca;
+                            ab[2] = cb;
+                            aw[2] = dH;
+                        }
+                    } else {
+                        l1 = sqrtf(1.0f - c2);
+                        if (ca < -l1) {
+                            const float B = fminf(cb, -l1);
+                            q0 = true;
+                            qa0 = ca;
+                            qb0 = B;
+                            aa[2] = ca;
+                            ab[2] = B;
+                            aw[2] = dH;
+                        }
+                        if (cb > l1) {
+                            const float Aq = fmaxf(ca, l1);
+                            q1 = true;
+                            qa1 = Aq;
+                            qb1 = cb;
+                            aa[3] = Aq;
+                            ab[3] = cb;
+                            aw[3] = dH;
+                        }
+                        const float Ai = fmaxf(ca, -l1), Bi = fminf(cb, l1);
+                        if (Bi > Ai) {
+                            if (Bi == cb) wi1 += sgnr(cb);
+                            else wi2 += 1.0f;
+                            if (Ai == ca) wi0 -= sgnr(ca);
+                            else wi2 += 1.0f;
+                        }
+                    }
+                }
+            }
+            // pushes (uniform), each followed by a run of a full stack
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const bool want = live && aw[q] != 0.0f;
+                const int slot = wave_push(want, nA);
+                if (want) {
+                    W.ang[0][slot] = R0;
+                    W.ang[1][slot] = aa[q];
+                    W.ang[2][slot] = ab[q];
+                    W.ang[3][slot] = sg * aw[q];
+                    W.ang_o[slot] = lane;
+                }
+                run_stack<0>(W, nA, lane, false, wk);
+            }
+            {
+                const float x0 = fabsf(ca), x1 = fabsf(cb);
+                const bool w0 = live && wi0 != 0.0f && x0 > 0.0f;
+                const bool w1 = live && wi1 != 0.0f && x1 > 0.0f;
+                const bool w2 = live && wi2 != 0.0f;
+#pragma unroll
+                for (int q = 0; q < 3; q++) {
+                    const bool want = q == 0 ? w0 : (q == 1 ? w1 : w2);
+                    const float x = q == 0 ? x0 : (q == 1 ? x1 : l1);
+                    const float wt = q == 0 ? wi0 : (q == 1 ? wi1 : wi2);
+                    const int slot = wave_push(want, nP);
+                    if (want) {
+                        W.pnt[0][slot] = r0;
+                        W.pnt[1][slot] = R0;
+                        W.pnt[2][slot] = c2;
+                        W.pnt[3][slot] = c;
+                        W.pnt[4][slot] = x;
+                        W.pnt[5][slot] = q == 2 ? 1.0f : (x == l2 ? 2.0f : sqrtf(c2 + x * x));
+                        W.pnt[6][slot] = sg * wt;
+                        W.pnt_o[slot] = lane;
+                    }
+                    run_stack<1>(W, nP, lane, false, wk);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                const bool qv = live && (q == 0 ? q0 : q1);
+                const float qa = q == 0 ? qa0 : qa1, qb = q == 0 ? qb0 : qb1, ds = q == 0 ? qd0 : 1.0f;
+                const float len = qb - qa;
+                int nsub = 0;
+                float hl = 0.0f;
+                if (qv) {
+                    nsub = (int)ceilf(len * rcp32(1.5f * ds));
+                    nsub = nsub < 1 ? 1 : (nsub > 8 ? 8 : nsub);
+                    hl = 0.5f * len / (float)nsub;
+                }
+                const float wq = sg * R0 * hl * (1.0f / 120.0f);
+                const int kmax = wave_max(nsub);
+                for (int kk = 0; kk < kmax; kk++) {
+                    const bool want = kk < nsub;
+                    const int slot = wave_push(want, nQ);
+                    if (want) {
+                        W.qd[0][slot] = r0;
+                        W.qd[1][slot] = c2;
+                        W.qd[2][slot] = qa + (2.0f * (float)kk + 1.0f) * hl;
+                        W.qd[3][slot] = hl;
+                        W.qd[4][slot] = wq;
+                        W.qd_o[slot] = lane;
+                    }
+                    run_stack<2>(W, nQ, lane, false, wk);
+                }
+            }
+        }
+        run_stack<0>(W, nA, lane, true, wk);
+        run_stack<1>(W, nP, lane, true, wk);
+        run_stack<2>(W, nQ, lane, true, wk);
+        lds_sync_wave();
+        if (active) f[k] = (inside ? 1.0 : 0.0) - W.acc[lane] * kInvPi;
+        lds_sync_wave();
+    }
+    flush_work(wk, counters);
+}
+
 // ---------------------------------------------------------------- cell tiles
 // A tile is up to 64 consecutive pairs of one cell (key = cell << 32 | tile
 // index within the cell).  A wavefront integrating a tile shares the cell, so
@@ -689,6 +1031,20 @@ void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &
         else
             hipLaunchKernelGGL(k_integrate_flat<MAP_MIXED>, dim3(g), dim3(block), 0, s, np, ps.pair_p, ps.pair_c,
                                in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, fx);
+        EM_HIP(hipGetLastError());
+        return;
+    }
+    if (tune.persistent == 3 && precision == MAP_MIXED) {
+        int64_t g = (int64_t)device_cu_count() * (tune.grid_per_cu > 0 ? tune.grid_per_cu : 8);
+        const int64_t need = ((np + 63) / 64 + (block / 64) - 1) / (block / 64);
+        if (g > need) g = need;
+        if (g < 1) g = 1;
+        if (tune.waves >= 3)
+            hipLaunchKernelGGL(k_integrate_queued<3>, dim3((unsigned)g), dim3(block), 0, s, np, ps.pair_p, ps.pair_c,
+                               in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, tile_ctr, fx);
+        else
+            hipLaunchKernelGGL(k_integrate_queued<2>, dim3((unsigned)g), dim3(block), 0, s, np, ps.pair_p, ps.pair_c,
+                               in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, tile_ctr, fx);
         EM_HIP(hipGetLastError());
         return;
     }

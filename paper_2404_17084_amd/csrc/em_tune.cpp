@@ -68,7 +68,7 @@ void tune_cache_load(Ctx &C)
         double ms;
         if (!(ss >> arch >> prec >> cls >> w >> tw >> g >> pers >> ms)) continue;
         if (arch != C.arch || (prec != MAP_FP64 && prec != MAP_MIXED)) continue;
-        if (w < 0 || w > 8 || tw < 1 || tw > 64 || g < 1 || g > 64 || pers < 0 || pers > 2) continue;
+        if (w < 0 || w > 8 || tw < 1 || tw > 64 || g < 1 || g > 64 || pers < 0 || pers > 3) continue;
         IntegrateTune t;
         t.waves = w;
         t.tile_waves = tw;
@@ -127,14 +127,15 @@ extern "C" int map_autotune(map_ctx *h, const map_particles_in *p, const map_cel
         const int wvmx[] = {0, 5};
         const int tws[] = {1, 2};
         const int grids[] = {4, 8};
-        const int dists[] = {1, 2};
+        const int dists[] = {1, 2, 3};
         IntegrateTune best = default_tune(precision);
         float best_t = 1e30f;
         for (int wi = 0; wi < 2; wi++)
             for (int d : dists)
                 for (int tw : tws)
                     for (int g : grids) {
-                        if (d == 2 && tw != 1) continue;  // cell tiles ignore tile_waves
+                        if (d >= 2 && tw != 1) continue;  // cell tiles and task batches ignore tile_waves
+                        if (d == 3 && precision == MAP_FP64) continue;  // task batches are mixed-only
                         IntegrateTune t;
                         t.waves = precision == MAP_FP64 ? wv64[wi] : wvmx[wi];
                         t.persistent = d;
