@@ -206,13 +206,12 @@ int64_t stage_finish(Ctx &C, Workspace &ws, JobState &js, const map_out *out, hi
         }
     }
     if (js.ev_fix) EM_HIP(hipEventRecord(js.ev_fix, s));
-    double *f_pm = ws.get<double>(S_F_PM, (size_t)(np > 0 ? np : 1));
     double *S = ws.get<double>(S_S, (size_t)(in.n > 0 ? in.n : 1));
     double *M = ws.get<double>(S_MCELL, (size_t)(in.n_cells > 0 ? in.n_cells : 1));
     double *rho = ws.get<double>(S_RHO, (size_t)(in.n_cells > 0 ? in.n_cells : 1));
     double *red = ws.get<double>(S_RED, 16 + 4 * 256);
     EM_HIP(hipMemcpyAsync(red + 4, in.box, sizeof(double) * 6, hipMemcpyHostToDevice, s));
-    launch_reduce(in, ps, f, f_pm, S, M, rho, red, js.flags, s);
+    launch_reduce(in, ps, f, S, M, rho, red, js.flags, s);
     if (js.ev_reduce) EM_HIP(hipEventRecord(js.ev_reduce, s));
 
     // outputs

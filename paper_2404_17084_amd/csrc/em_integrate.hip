@@ -500,22 +500,6 @@ struct WaveStacks {
     double acc[64];
 };
 
-__device__ __forceinline__ int wave_push(bool want, int &count)
-{
-    const unsigned long long m = __ballot(want);
-    const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-    const int slot = count + below;
-    count += __popcll(m);
-    return slot;
-}
-
-__device__ __forceinline__ void lds_sync_wave()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __device__ __forceinline__ void run_angle(WaveStacks &W, int i, Work &wk)
 {
     const float R0 = W.ang[0][i], a = W.ang[1][i], b = W.ang[2][i], w = W.ang[3][i];

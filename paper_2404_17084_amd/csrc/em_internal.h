@@ -135,6 +135,27 @@ struct IntegrateTune {
     int waves = 0;         // register budget as waves per SIMD (FP64: 2-4, mixed: 4-6; 0 = lowest)
 };
 
+// ---------------------------------------------------------------- wavefront helpers
+// Slot of this lane in a wave-wide push (lanes with want = true, in lane
+// order); count (wave-uniform) grows by the number of pushing lanes.  Call in
+// wave-uniform control flow.
+__device__ __forceinline__ int wave_push(bool want, int &count)
+{
+    const unsigned long long m = __ballot(want);
+    const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+    const int slot = count + below;
+    count += __popcll(m);
+    return slot;
+}
+
+// Orders LDS writes of one wavefront before its later reads by other lanes.
+__device__ __forceinline__ void lds_sync_wave()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------- primitives (em_primitives.hip)
 // Exclusive scan of int64 counts: out[0] = 0, out[i+1] = out[i] + in[i]; out has n+1 entries.
 void scan_counts(Workspace &ws, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
@@ -159,7 +180,7 @@ struct PairSet {
     int64_t n_pairs = 0;
     const uint32_t *pair_c = nullptr;  // cell-major order
     const uint32_t *pair_p = nullptr;
-    const uint32_t *perm = nullptr;    // cell-major index -> particle-major index
+    const uint32_t *perm = nullptr;    // particle-major position -> cell-major index
     const int64_t *poff = nullptr;     // particle-major offsets (n+1)
     const int64_t *coff = nullptr;     // cell-major offsets (n_cells+1)
     const uint64_t *tiles = nullptr;   // cell tiles of <= 64 pairs (cell << 32 | index)
@@ -216,7 +237,7 @@ void launch_fixup(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, 
 void launch_fixup_apply(const uint64_t *keys, const double *vals, int64_t n_fix, double *f, hipStream_t s);
 
 // em_reduce.hip
-void launch_reduce(const DevInputs &in, const PairSet &ps, const double *f, double *f_pm, double *S, double *M,
+void launch_reduce(const DevInputs &in, const PairSet &ps, const double *f, double *S, double *M,
                    double *rho, double *red, unsigned *flags, hipStream_t s);
 
 }  // namespace em

@@ -164,8 +164,12 @@ __device__ __forceinline__ double box_dist2(const double *bb, double px, double 
 
 // FILL = false: count candidate cells per particle; FILL = true: write them.
 // Candidates are the cells whose bounding box comes closer than 2h to the
-// particle.  Stackless depth-first walk of the implicit tree (heap indices:
-// children 2i, 2i+1); only box tests here, so lanes stay in step.
+// particle.  A wavefront walks the implicit tree (heap indices: children 2i,
+// 2i+1) as one packet: it descends into a node when the node's box meets any
+// lane's ball, and at a leaf each lane whose ball meets the leaf box tests the
+// leaf's cells.  Each lane gets exactly the cells of its own walk, in leaf
+// order; neighbouring particles (consecutive in Morton order) share most of
+// their paths, so the lanes stay busy.
 template <bool FILL>
 __global__ void k_candidates(int64_t n, const double *__restrict__ xyz, const double *__restrict__ h,
                              int64_t n_cells, const double *__restrict__ aabb, const double *__restrict__ nodes,
@@ -174,16 +178,22 @@ __global__ void k_candidates(int64_t n, const double *__restrict__ xyz, const do
                              uint32_t *__restrict__ cand_p)
 {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= n) return;
-    const double px = xyz[3 * a], py = xyz[3 * a + 1], pz = xyz[3 * a + 2];
-    const double r = 2.0 * h[a];
-    const double r2_loose = r * r * (1.0 + 1e-9);
+    const bool active = a < n;
+    double px = 0.0, py = 0.0, pz = 0.0, r2_loose = -1.0;
+    if (active) {
+        px = xyz[3 * a];
+        py = xyz[3 * a + 1];
+        pz = xyz[3 * a + 2];
+        const double r = 2.0 * h[a];
+        r2_loose = r * r * (1.0 + 1e-9);
+    }
     int64_t count = 0;
-    const int64_t out = FILL ? coffs[a] : 0;
+    const int64_t out = (FILL && active) ? coffs[a] : 0;
     int64_t i = 1;
     for (;;) {
-        const bool hit = box_dist2(nodes + 6 * i, px, py, pz) <= r2_loose;
-        if (hit && i < NL) {
+        const bool hit = active && box_dist2(nodes + 6 * i, px, py, pz) <= r2_loose;
+        const bool any = __ballot(hit) != 0;
+        if (any && i < NL) {
             i = 2 * i;
             continue;
         }
@@ -203,81 +213,81 @@ __global__ void k_candidates(int64_t n, const double *__restrict__ xyz, const do
         if (i == 0) break;
         i += 1;
     }
-    if (!FILL) ccount[a] = count;
+    if (!FILL && active) ccount[a] = count;
 }
 
-// One thread per candidate, candidates in cell order (consecutive threads
-// share a cell, so its walls stay in cache): 1 if the pair exists, written to
-// the candidate's own slot.  A cell is accepted without the exact test when
+// Candidates in cell order.  A cell is accepted without the exact test when
 // an interior point of it (the mean of its wall vertices) or its whole
 // bounding box lies within (1 - 1e-6) 2h of the particle: its distance is
-// then certainly below 2h.  Otherwise the exact test decides.
-__global__ void k_exact(int64_t nc_total, const uint32_t *__restrict__ sorted_c, const uint32_t *__restrict__ sorted_q,
+// then certainly below 2h.  The other candidates go through a compacted list
+// to the exact test (one thread each, consecutive threads mostly on one cell).
+__global__ void k_quick(int64_t ncand, const uint32_t *__restrict__ cand_c, const uint32_t *__restrict__ cand_p,
+                        const double *__restrict__ xyz, const double *__restrict__ h,
+                        const double *__restrict__ aabb, const double *__restrict__ centre,
+                        int64_t *__restrict__ flag, int64_t *__restrict__ need)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncand) return;
+    const int64_t c = cand_c[i], a = cand_p[i];
+    const double px = xyz[3 * a], py = xyz[3 * a + 1], pz = xyz[3 * a + 2];
+    const double r = 2.0 * h[a];
+    const double r2 = r * r;
+    const double *bb = aabb + 6 * c;
+    const double fx = fmax(fabs(bb[0] - px), fabs(bb[3] - px));
+    const double fy = fmax(fabs(bb[1] - py), fabs(bb[4] - py));
+    const double fz = fmax(fabs(bb[2] - pz), fabs(bb[5] - pz));
+    const double gx = centre[3 * c] - px, gy = centre[3 * c + 1] - py, gz = centre[3 * c + 2] - pz;
+    const bool ok = fx * fx + fy * fy + fz * fz < r2 * 0.999998 || gx * gx + gy * gy + gz * gz < r2 * 0.999998;
+    flag[i] = ok ? 1 : 0;
+    need[i] = ok ? 0 : 1;
+}
+
+__global__ void k_set_u64(unsigned long long *p, unsigned long long v)
+{
+    if (threadIdx.x == 0) *p = v;
+}
+
+__global__ void k_need_list(int64_t ncand, const int64_t *__restrict__ need, const int64_t *__restrict__ npos,
+                            uint32_t *__restrict__ list)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ncand && need[i]) list[npos[i]] = (uint32_t)i;
+}
+
+__global__ void k_exact(int64_t n_need, const uint32_t *__restrict__ list, const uint32_t *__restrict__ cand_c,
                         const uint32_t *__restrict__ cand_p, const double *__restrict__ xyz,
-                        const double *__restrict__ h, const double *__restrict__ aabb,
-                        const double *__restrict__ centre, const int64_t *__restrict__ cfo,
+                        const double *__restrict__ h, const int64_t *__restrict__ cfo,
                         const int64_t *__restrict__ fvo, const EdgeRec *__restrict__ edges,
-                        const double *__restrict__ plane, int64_t *__restrict__ flag,
-                        unsigned long long *exact_counter)
+                        const double *__restrict__ plane, int64_t *__restrict__ flag)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long tested = 0;
-    if (t < nc_total) {
-        const int64_t c = sorted_c[t], q = sorted_q[t];
-        const int64_t a = cand_p[q];
-        const double px = xyz[3 * a], py = xyz[3 * a + 1], pz = xyz[3 * a + 2];
-        const double r = 2.0 * h[a];
-        const double r2 = r * r;
-        const double *bb = aabb + 6 * c;
-        const double fx = fmax(fabs(bb[0] - px), fabs(bb[3] - px));
-        const double fy = fmax(fabs(bb[1] - py), fabs(bb[4] - py));
-        const double fz = fmax(fabs(bb[2] - pz), fabs(bb[5] - pz));
-        const double gx = centre[3 * c] - px, gy = centre[3 * c + 1] - py, gz = centre[3 * c + 2] - pz;
-        int64_t ok;
-        if (fx * fx + fy * fy + fz * fz < r2 * 0.999998 || gx * gx + gy * gy + gz * gz < r2 * 0.999998) {
-            ok = 1;
-        } else {
-            tested = 1;
-            ok = cell_meets(px, py, pz, r2, c, cfo, fvo, edges, plane) ? 1 : 0;
-        }
-        flag[q] = ok;
-    }
-    for (int o = 32; o > 0; o >>= 1) tested += __shfl_xor(tested, o, 64);
-    if ((threadIdx.x & 63) == 0 && tested) atomicAdd(exact_counter, tested);
+    if (t >= n_need) return;
+    const int64_t i = list[t];
+    const int64_t c = cand_c[i], a = cand_p[i];
+    const double r = 2.0 * h[a];
+    flag[i] = cell_meets(xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2], r * r, c, cfo, fvo, edges, plane) ? 1 : 0;
 }
 
-__global__ void k_compact(int64_t nc_total, const uint32_t *__restrict__ cand_c, const uint32_t *__restrict__ cand_p,
-                          const int64_t *__restrict__ fpos, uint32_t *__restrict__ pc_pm, uint32_t *__restrict__ pp_pm)
+__global__ void k_compact(int64_t ncand, const uint32_t *__restrict__ cand_c, const uint32_t *__restrict__ cand_p,
+                          const int64_t *__restrict__ flag, const int64_t *__restrict__ fpos,
+                          uint32_t *__restrict__ pair_c, uint32_t *__restrict__ pair_p)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nc_total) return;
-    const int64_t pos = fpos[q];
-    if (fpos[q + 1] != pos) {
-        pc_pm[pos] = cand_c[q];
-        pp_pm[pos] = cand_p[q];
-    }
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncand || !flag[i]) return;
+    const int64_t o = fpos[i];
+    pair_c[o] = cand_c[i];
+    pair_p[o] = cand_p[i];
 }
 
-__global__ void k_particle_offsets(int64_t n, const int64_t *__restrict__ coffs, const int64_t *__restrict__ fpos,
-                                   int64_t *__restrict__ poff)
+// Segment offsets of sorted keys: off[v] = first i with keys[i] >= v, v = 0..n_seg.
+__global__ void k_seg_offsets(int64_t n_items, const uint32_t *__restrict__ keys, int64_t n_seg,
+                              int64_t *__restrict__ off)
 {
-    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a <= n) poff[a] = fpos[coffs[a]];
-}
-
-__global__ void k_u32_to_i64(const unsigned *in, int64_t *out, int64_t n)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = in[i];
-}
-
-__global__ void k_gather_particle(const uint32_t *perm, const uint32_t *pp_pm, uint32_t *pair_p, int64_t np,
-                                  unsigned *ccnt, const uint32_t *pair_c)
-{
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= np) return;
-    pair_p[k] = pp_pm[perm[k]];
-    atomicAdd(&ccnt[pair_c[k]], 1u);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n_items) return;
+    const int64_t prev = i == 0 ? -1 : (int64_t)keys[i - 1];
+    const int64_t cur = i == n_items ? n_seg : (int64_t)keys[i];
+    for (int64_t v = prev + 1; v <= cur; v++) off[v] = i;
 }
 
 static int bits_for(uint64_t maxval)
@@ -349,60 +359,69 @@ PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, cons
                        (const double *)nodes, NL, (const uint32_t *)cperm, (int64_t *)nullptr,
                        (const int64_t *)coffs, cand_c, cand_p);
     EM_HIP(hipGetLastError());
-    // exact test, one thread per candidate in cell order, then compaction
+    // candidates in cell order (stable: particles stay ascending within a cell), then the test
     int64_t *flag = ws.get<int64_t>(S_F_PM, (size_t)(ncand > 0 ? ncand : 1));
     int64_t *fpos = ws.get<int64_t>(S_F, (size_t)(ncand + 1));
     unsigned long long *cand = reinterpret_cast<unsigned long long *>(counters + C_CANDIDATES);
     if (ncand > 0) {
-        uint32_t *sc = ws.get<uint32_t>(S_PC_PM, (size_t)ncand);
-        uint32_t *sq = ws.get<uint32_t>(S_PP_PM, (size_t)ncand);
         uint32_t *sc2 = ws.get<uint32_t>(S_PERM, (size_t)ncand);
-        uint32_t *sq2 = ws.get<uint32_t>(S_PAIR_P, (size_t)ncand);
-        EM_HIP(hipMemcpyAsync(sc, cand_c, sizeof(uint32_t) * ncand, hipMemcpyDeviceToDevice, s));
-        fill_iota_u32(sq, ncand, s);
-        radix_sort_u32(ws, sc, sq, sc2, sq2, ncand, bits_for((uint64_t)nc - 1), s);
-        hipLaunchKernelGGL(k_exact, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand,
-                           (const uint32_t *)sc, (const uint32_t *)sq, (const uint32_t *)cand_p, in.xyz, in.h, aabb,
-                           aabb + 6 * nc, in.cfo, in.fvo, edges, in.plane, flag, cand);
+        uint32_t *sp2 = ws.get<uint32_t>(S_PC_PM, (size_t)ncand);
+        radix_sort_u32(ws, cand_c, cand_p, sc2, sp2, ncand, bits_for((uint64_t)nc - 1), s);
+        int64_t *need = ws.get<int64_t>(S_CCNT64, (size_t)ncand);  // the candidate offsets are no longer needed
+        int64_t *npos = ws.get<int64_t>(S_BINCNT64, (size_t)ncand + 1);
+        const unsigned gq = (unsigned)((ncand + 255) / 256);
+        hipLaunchKernelGGL(k_quick, dim3(gq), dim3(256), 0, s, ncand, (const uint32_t *)cand_c,
+                           (const uint32_t *)cand_p, in.xyz, in.h, aabb, aabb + 6 * nc, flag, need);
+        EM_HIP(hipGetLastError());
+        scan_counts(ws, need, npos, ncand, s);
+        int64_t n_need = 0;
+        EM_HIP(hipMemcpyAsync(&n_need, npos + ncand, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        EM_HIP(hipStreamSynchronize(s));
+        if (n_need > 0) {
+            uint32_t *list = ws.get<uint32_t>(S_BINLIST, (size_t)n_need);
+            hipLaunchKernelGGL(k_need_list, dim3(gq), dim3(256), 0, s, ncand, (const int64_t *)need,
+                               (const int64_t *)npos, list);
+            EM_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_exact, dim3((unsigned)((n_need + 255) / 256)), dim3(256), 0, s, n_need,
+                               (const uint32_t *)list, (const uint32_t *)cand_c, (const uint32_t *)cand_p, in.xyz,
+                               in.h, in.cfo, in.fvo, edges, in.plane, flag);
+            EM_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, cand, (unsigned long long)n_need);
         EM_HIP(hipGetLastError());
     }
     scan_counts(ws, flag, fpos, ncand, s);
-    hipLaunchKernelGGL(k_particle_offsets, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s, n,
-                       (const int64_t *)coffs, (const int64_t *)fpos, poff);
-    EM_HIP(hipGetLastError());
     int64_t np = 0;
-    EM_HIP(hipMemcpyAsync(&np, poff + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    EM_HIP(hipMemcpyAsync(&np, fpos + ncand, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     EM_HIP(hipStreamSynchronize(s));
     EM_CHECK(np < (int64_t)UINT32_MAX, MAP_ENOMEM, "pair count exceeds 2^32-1");
     ps.n_pairs = np;
     if (np == 0) {
+        fill_zero_bytes(poff, sizeof(int64_t) * (n + 1), s);
         fill_zero_bytes(coff, sizeof(int64_t) * (nc + 1), s);
         return ps;
     }
-    uint32_t *pc = ws.get<uint32_t>(S_PC_PM, (size_t)np);
-    uint32_t *pp_pm = ws.get<uint32_t>(S_PP_PM, (size_t)np);
-    if (ncand > 0) {
-        hipLaunchKernelGGL(k_compact, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand,
-                           (const uint32_t *)cand_c, (const uint32_t *)cand_p, (const int64_t *)fpos, pc, pp_pm);
-        EM_HIP(hipGetLastError());
-    }
-    // cell-major order: stable sort of particle-major pairs by cell
-    uint32_t *perm = ws.get<uint32_t>(S_PERM, (size_t)np);
-    uint32_t *k2 = ws.get<uint32_t>(S_KEY2, (size_t)np);
-    uint32_t *v2 = ws.get<uint32_t>(S_IOTA, (size_t)np);
-    int64_t *ccnt64 = ws.get<int64_t>(S_CCNT64, (size_t)nc);
-    fill_iota_u32(perm, np, s);
-    radix_sort_u32(ws, pc, perm, k2, v2, np, bits_for((uint64_t)nc - 1), s);
+    // cell-major pairs and cell offsets
+    uint32_t *pair_c = ws.get<uint32_t>(S_PAIR_C, (size_t)np);
     uint32_t *pair_p = ws.get<uint32_t>(S_PAIR_P, (size_t)np);
-    unsigned *ccnt = ws.get<unsigned>(S_CCNT, (size_t)nc);
-    fill_zero_bytes(ccnt, sizeof(unsigned) * nc, s);
-    hipLaunchKernelGGL(k_gather_particle, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, perm, pp_pm, pair_p,
-                       np, ccnt, (const uint32_t *)pc);
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand,
+                       (const uint32_t *)cand_c, (const uint32_t *)cand_p, (const int64_t *)flag,
+                       (const int64_t *)fpos, pair_c, pair_p);
     EM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_u32_to_i64, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, ccnt, ccnt64, nc);
+    hipLaunchKernelGGL(k_seg_offsets, dim3((unsigned)((np + 1 + 255) / 256)), dim3(256), 0, s, np,
+                       (const uint32_t *)pair_c, nc, coff);
     EM_HIP(hipGetLastError());
-    scan_counts(ws, ccnt64, coff, nc, s);
-    ps.pair_c = pc;
+    // particle-major view: stable sort of the cell-major pairs by particle
+    uint32_t *pk = ws.get<uint32_t>(S_KEY2, (size_t)np);
+    uint32_t *perm = ws.get<uint32_t>(S_PERM, (size_t)np);
+    EM_HIP(hipMemcpyAsync(pk, pair_p, sizeof(uint32_t) * np, hipMemcpyDeviceToDevice, s));
+    fill_iota_u32(perm, np, s);
+    radix_sort_u32(ws, pk, perm, ws.get<uint32_t>(S_IOTA, (size_t)np), ws.get<uint32_t>(S_PC_PM, (size_t)np), np,
+                   bits_for((uint64_t)n - 1), s);
+    hipLaunchKernelGGL(k_seg_offsets, dim3((unsigned)((np + 1 + 255) / 256)), dim3(256), 0, s, np,
+                       (const uint32_t *)pk, n, poff);
+    EM_HIP(hipGetLastError());
+    ps.pair_c = pair_c;
     ps.pair_p = pair_p;
     ps.perm = perm;
     return ps;

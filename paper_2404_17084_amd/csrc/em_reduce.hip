@@ -24,19 +24,14 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-__global__ void k_scatter_pm(int64_t np, const uint32_t *perm, const double *f, double *f_pm)
-{
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < np) f_pm[perm[k]] = f[k];
-}
-
-__global__ void k_particle_sum(int64_t n, const int64_t *poff, const double *f_pm, double *S)
+// S_a over the particle's pairs in cell order (perm: particle-major position -> cell-major index)
+__global__ void k_particle_sum(int64_t n, const int64_t *poff, const uint32_t *perm, const double *f, double *S)
 {
     const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (a >= n) return;
     double v = 0.0;
-    for (int64_t q = poff[a] + lane; q < poff[a + 1]; q += 64) v += f_pm[q];
+    for (int64_t q = poff[a] + lane; q < poff[a + 1]; q += 64) v += f[perm[q]];
     v = wave_sum(v);
     if (lane == 0) S[a] = v;
 }
@@ -129,15 +124,13 @@ __global__ void k_stats_final(int nb, const double *part, double *red, unsigned 
 
 }  // namespace
 
-void launch_reduce(const DevInputs &in, const PairSet &ps, const double *f, double *f_pm, double *S, double *M,
+void launch_reduce(const DevInputs &in, const PairSet &ps, const double *f, double *S, double *M,
                    double *rho, double *red, unsigned *flags, hipStream_t s)
 {
-    const int64_t np = ps.n_pairs, n = in.n, nc = in.n_cells;
-    if (np > 0)
-        hipLaunchKernelGGL(k_scatter_pm, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, np, ps.perm, f, f_pm);
+    const int64_t n = in.n, nc = in.n_cells;
     if (n > 0)
         hipLaunchKernelGGL(k_particle_sum, dim3((unsigned)((n * 64 + 255) / 256)), dim3(256), 0, s, n, ps.poff,
-                           (const double *)f_pm, S);
+                           ps.perm, f, S);
     if (nc > 0)
         hipLaunchKernelGGL(k_cell_mass, dim3((unsigned)((nc * 64 + 255) / 256)), dim3(256), 0, s, nc, ps.coff,
                            ps.pair_p, f, (const double *)S, in.m, in.vol, M, rho);
