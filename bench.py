@@ -33,6 +33,12 @@ FLOP_MOMENT = 66    # closed form at one point: sqrt, asinh, angle difference, p
 FLOP_QUAD = 250     # 8-point Gauss-Legendre sub-interval of the shell integrand (8 sqrt, 8 rcp)
 FLOP_ANGLE = 6      # angle of one edge part seen from the foot point (one atan2) times H
 
+# HBM bytes per launch of the mixed integration kernel from FETCH_SIZE/WRITE_SIZE counter runs scaled by a
+# 1 GiB copy (profiles/traffic_integrate_queued_clumps262144.md), valid for the source it was measured on.
+TRAFFIC_SOURCE = "paper_2404_17084_amd/csrc/em_integrate.hip"
+TRAFFIC_SHA256_PREFIX = "3321c15b7abc1b57"
+TRAFFIC_BYTES = 6.356e9 + 0.281e9
+
 PEAK_FP64 = 78.6   # TFLOP/s, MI355X FP64 vector
 PEAK_FP32 = 157.3  # TFLOP/s, MI355X FP32 vector (packed)
 
@@ -41,6 +47,18 @@ def algorithmic_flops(st) -> float:
     return (FLOP_FACE * st["n_face_visits"] + FLOP_EDGE * st["n_edge_visits"] + FLOP_ETERM * st["n_edge_terms"]
             + FLOP_MOMENT * st["n_moment_evals"] + FLOP_QUAD * st["n_quad_intervals"]
             + FLOP_ANGLE * st["n_angle_evals"])
+
+
+def measured_traffic():
+    """Counter-based HBM bytes of the integration kernel, or None once its source has changed."""
+    import hashlib
+
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_SOURCE), "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()
+    except OSError:
+        return None
+    return TRAFFIC_BYTES if digest.startswith(TRAFFIC_SHA256_PREFIX) else None
 
 
 def to_device(p, c):
@@ -152,6 +170,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-pseudo", action="store_true", help="skip the pseudo-particle leg")
+    ap.add_argument("--mixed-shape", default=None,
+                    help="explicit mixed launch shape 'waves,tile_waves,grid_per_cu,distribution' instead of tuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with one plain 1 GiB device-to-device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -180,7 +200,11 @@ def main():
     tuned = {}
     for prec, name in ((em.MAP_FP64, "fp64"), (em.MAP_MIXED, "mixed")):
         mapper.set_precision(prec)
-        if not args.no_tune:
+        if prec == em.MAP_MIXED and args.mixed_shape:
+            w, tw, g, d = (int(v) for v in args.mixed_shape.split(","))
+            em.map_set_tune(mapper.ctx, prec, w, tw, g, d)
+            tuned[name] = {"waves": w, "tile_waves": tw, "grid_per_cu": g, "distribution": d, "ms_integrate": None}
+        elif not args.no_tune:
             shape, ms = em.map_autotune(mapper.ctx, xyz, m, h, dc, prec)
             tuned[name] = {"waves": shape[0], "tile_waves": shape[1], "grid_per_cu": shape[2],
                            "distribution": shape[3], "ms_integrate": ms}
@@ -240,7 +264,7 @@ def main():
         "stages_ms_mixed": {k: mx[k] for k in ("ms_setup", "ms_pairs", "ms_integrate", "ms_reduce")},
         "launch_shape": tuned,
         "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32, "unit": "TFLOP/s", "frac": ach / PEAK_FP32,
-                     "traffic": None},
+                     "traffic": measured_traffic()},
     }
     if not args.no_pseudo:
         line["pseudo_path"] = pseudo_leg(em, args.steps, args.warmup)

@@ -319,7 +319,7 @@ constexpr double kInvPi = 0.318309886183790671537767526745;
 __device__ __forceinline__ bool needs_fp64(double r0, double R0, double c2)
 {
     const double e = 9.5367431640625e-07;  // 2^-20
-    return (R0 < e * sqrt(c2)) || (fabs(r0 - 1.0) < e) || (fabs(c2 - 1.0) < e) || (fabs(c2 - 4.0) < 4.0 * e);
+    return (R0 * R0 < e * e * c2) || (fabs(r0 - 1.0) < e) || (fabs(c2 - 1.0) < e) || (fabs(c2 - 4.0) < 4.0 * e);
 }
 
 // Raw f for one pair.  PREC = MAP_FP64 or MAP_MIXED.  Wall distance, foot
