@@ -304,6 +304,11 @@ void run_mapping(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cel
 
 }  // namespace em
 
+// The served path (em_serve.cpp) stays off until the stall seen in its first
+// device run is explained; its host logic is exercised on the CPU against a
+// fake device (tests/serve_host).
+bool em::serving_enabled() { return false; }
+
 // ---------------------------------------------------------------- C ABI
 #define API_BODY(ctx, body)                          \
     do {                                             \

@@ -135,27 +135,6 @@ struct IntegrateTune {
     int waves = 0;         // register budget as waves per SIMD (FP64: 2-4, mixed: 4-6; 0 = lowest)
 };
 
-// ---------------------------------------------------------------- wavefront helpers
-// Slot of this lane in a wave-wide push (lanes with want = true, in lane
-// order); count (wave-uniform) grows by the number of pushing lanes.  Call in
-// wave-uniform control flow.
-__device__ __forceinline__ int wave_push(bool want, int &count)
-{
-    const unsigned long long m = __ballot(want);
-    const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-    const int slot = count + below;
-    count += __popcll(m);
-    return slot;
-}
-
-// Orders LDS writes of one wavefront before its later reads by other lanes.
-__device__ __forceinline__ void lds_sync_wave()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // ---------------------------------------------------------------- primitives (em_primitives.hip)
 // Exclusive scan of int64 counts: out[0] = 0, out[i+1] = out[i] + in[i]; out has n+1 entries.
 void scan_counts(Workspace &ws, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);

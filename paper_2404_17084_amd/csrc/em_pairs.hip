@@ -13,6 +13,7 @@
 #include <cmath>
 
 #include "em_internal.h"
+#include "em_wave.h"
 
 namespace em {
 

@@ -64,5 +64,9 @@ void prepare(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_i
 void run_mapping(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_in *c, const map_out *out,
                  int precision, hipStream_t s, bool timed);
 void serve_stop(Ctx &C);
+// Device-memory footprint estimate of a served job (admission against the budget).
+size_t job_footprint(const map_particles_in *p, const map_cells_in *c);
+// Whether map_submit accepts jobs (em_api.cpp).
+bool serving_enabled();
 
 }  // namespace em

@@ -82,7 +82,7 @@ struct Server {
 // Footprint estimate of a job on the device: inputs, geometry tables and the
 // pair-proportional buffers (about 64 bytes per pair, ~140 pairs per particle
 // for smoothing lengths with ~58 neighbours).
-static size_t footprint(const map_particles_in *p, const map_cells_in *c)
+size_t job_footprint(const map_particles_in *p, const map_cells_in *c)
 {
     const double pairs = 140.0 * (double)p->n + 64.0;
     double b = 40.0 * p->n + 16.0 * c->n_cells + 48.0 * c->n_faces + 100.0 * c->n_face_verts + 24.0 * c->n_verts +
@@ -346,7 +346,7 @@ extern "C" int map_submit(map_ctx *h, const map_particles_in *p, const map_cells
     Ctx *C = reinterpret_cast<Ctx *>(h);
     std::lock_guard<std::mutex> guard(C->mu);
     try {
-        EM_CHECK(false, MAP_ENOTSUP,
+        EM_CHECK(serving_enabled(), MAP_ENOTSUP,
                  "served mapping is switched off: a device run of it stopped making progress and the cause is not "
                  "yet found; use map_particles");
         EM_HIP(hipSetDevice(C->device));
@@ -383,7 +383,7 @@ extern "C" int map_submit(map_ctx *h, const map_particles_in *p, const map_cells
         j->out = *out;
         j->user_stats = out->stats;
         j->out.stats = nullptr;
-        j->footprint = footprint(&j->pin, &j->cin);
+        j->footprint = job_footprint(&j->pin, &j->cin);
         Server &S = server_of(*C);
         std::lock_guard<std::mutex> lk(S.mu);
         EM_CHECK(j->footprint <= S.budget, MAP_ENOMEM,
