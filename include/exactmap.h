@@ -152,9 +152,9 @@ int map_set_precision(map_ctx *ctx, int precision);
  * pairs taken per queue pop (1..64), persistent workgroups of 256 threads per
  * compute unit (1..64), and the work distribution: 1 = persistent queue of
  * pair tiles, 2 = persistent queue of single-cell tiles, 3 = persistent queue
- * of pair tiles whose edge terms are run as wavefront-wide task batches
- * (mixed precision only; the FP64 path runs 3 as 1), 0 = one thread per
- * pair, -1 = clear the explicit setting (back to the tuned table/default).
+ * of pair tiles whose edge terms are run as wavefront-wide task batches, 0 =
+ * one thread per pair, -1 = clear the explicit setting (back to the tuned
+ * table/default).
  * For a given distribution, results are bitwise independent of the other
  * knobs and of scheduling; the distributions are separate kernels and agree
  * to rounding.  map_get_tune reports the shape used for n_pairs pairs.

@@ -804,6 +804,229 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
     flush_work(wk, counters);
 }
 
+// FP64 form of the task batches: no quadrature (the shell piece keeps its
+// closed form), so two task kinds: angles and closed-form points carrying
+// both piece weights.
+struct WaveStacks64 {
+    double ang[4][kQ];  // R0, a, b, weight
+    int ang_o[kQ];
+    double pnt[8][kQ];  // r0, R0, c2, c, x, S, inner weight, shell weight
+    int pnt_o[kQ];
+    double acc[64];
+};
+
+template <int KIND>
+__device__ __forceinline__ void run_one64(WaveStacks64 &W, int i, Work &wk)
+{
+    if (KIND == 0) {
+        const double R0 = W.ang[0][i], a = W.ang[1][i], b = W.ang[2][i], w = W.ang[3][i];
+        atomicAdd(&W.acc[W.ang_o[i]], w * seg_angle<double>(R0, a, b, wk));
+    } else {
+        const double r0 = W.pnt[0][i], R0 = W.pnt[1][i], c2 = W.pnt[2][i], c = W.pnt[3][i];
+        const double x = W.pnt[4][i], S = W.pnt[5][i], wi = W.pnt[6][i], wsh = W.pnt[7][i];
+        const Trans<double> t = trans<double>(r0, R0, c2, c, x, S, wk);
+        const double A = r0 * r0;
+        atomicAdd(&W.acc[W.pnt_o[i]], wi * core_inner<double>(t, r0, R0, A, c2) + wsh * core_shell<double>(t, r0, R0, A, c2));
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ void run_stack64(WaveStacks64 &W, int &count, int lane, bool all, Work &wk)
+{
+    if (count >= 64) {
+        lds_sync_wave();
+        run_one64<KIND>(W, count - 64 + lane, wk);
+        count -= 64;
+        lds_sync_wave();
+    }
+    if (all && count > 0) {
+        lds_sync_wave();
+        if (lane < count) run_one64<KIND>(W, lane, wk);
+        count = 0;
+        lds_sync_wave();
+    }
+}
+
+__global__ void __launch_bounds__(256, 2) k_integrate_queued64(int64_t np, const uint32_t *__restrict__ pair_p,
+                                                           const uint32_t *__restrict__ pair_c,
+                                                           const double *__restrict__ xyz,
+                                                           const double *__restrict__ h,
+                                                           const int64_t *__restrict__ cfo,
+                                                           const int64_t *__restrict__ fvo,
+                                                           const double *__restrict__ plane,
+                                                           const EdgeRec *__restrict__ edges,
+                                                           double *__restrict__ f, unsigned long long *counters,
+                                                           unsigned *tile_ctr)
+{
+    __shared__ WaveStacks64 stacks[4];
+    const int lane = threadIdx.x & 63;
+    WaveStacks64 &W = stacks[threadIdx.x >> 6];
+    const int64_t ntiles = (np + 63) / 64;
+    Work wk;
+    for (;;) {
+        unsigned t = 0;
+        if (lane == 0) t = atomicAdd(tile_ctr, 1u);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if ((int64_t)t >= ntiles) break;
+        const int64_t k = (int64_t)t * 64 + lane;
+        const bool active = k < np;
+        double px = 0.0, py = 0.0, pz = 0.0, invh = 1.0;
+        int64_t s = 0, s_end = 0, j = 0;
+        if (active) {
+            const int64_t a = pair_p[k];
+            const int64_t c = pair_c[k];
+            px = xyz[3 * a];
+            py = xyz[3 * a + 1];
+            pz = xyz[3 * a + 2];
+            invh = 1.0 / h[a];
+            j = cfo[c] - 1;
+            s = fvo[cfo[c]];
+            s_end = fvo[cfo[c + 1]];
+        }
+        W.acc[lane] = 0.0;
+        int64_t face_end = s;
+        const int n_steps = wave_max((int)(s_end - s));
+        int nA = 0, nP = 0;
+        bool inside = true;
+        bool face_ok = false;
+        double r0 = 0.0, Ht = 0.0, dH = 0.0, fsign = 1.0;
+        for (int it = 0; it < n_steps; it++, s++) {
+            const bool valid = s < s_end;
+            if (valid && s == face_end) {
+                j++;
+                face_end = fvo[j + 1];
+                const double d = plane[4 * j + 3] - (plane[4 * j] * px + plane[4 * j + 1] * py + plane[4 * j + 2] * pz);
+                wk.faces++;
+                const bool in_j = d >= 0.0;
+                inside = inside && in_j;
+                fsign = in_j ? 1.0 : -1.0;
+                r0 = fabs(d) * invh;
+                face_ok = r0 < 2.0;
+                Ht = pi_H<double>(r0);
+                dH = pi_dH<double>(r0);
+            }
+            bool live = valid && face_ok;
+            double R0 = 0.0, la = 0.0, lb = 0.0, sg = 0.0;
+            if (live) {
+                const EdgeRec E = edges[s];
+                const double wx = px - E.vx, wy = py - E.vy, wz = pz - E.vz;
+                const double rho = E.mx * wx + E.my * wy + E.mz * wz;
+                wk.edges++;
+                if (rho == 0.0) {
+                    live = false;
+                } else {
+                    la = -(E.ex * wx + E.ey * wy + E.ez * wz) * invh;
+                    lb = la + E.L * invh;
+                    R0 = fabs(rho) * invh;
+                    sg = (rho > 0.0 ? 1.0 : -1.0) * fsign;
+                }
+            }
+            // classification (the FP64 form of edge_term)
+            const double A = r0 * r0;
+            const double c2 = A + R0 * R0;
+            double aa[4] = {la, 0.0, 0.0, 0.0}, ab[4] = {lb, 0.0, 0.0, 0.0}, aw[4] = {0.0, 0.0, 0.0, 0.0};
+            double wi[3] = {0.0, 0.0, 0.0}, wsh[3] = {0.0, 0.0, 0.0};
+            double l2 = 0.0, c = 1.0, l1 = 0.0, ca = la, cb = lb;
+            if (live) {
+                if (!(c2 < 4.0)) {
+                    aw[0] = -Ht;
+                } else {
+                    wk.eterms++;
+                    l2 = sqrt(4.0 - c2);
+                    c = sqrt(c2);
+                    ca = fmin(fmax(la, -l2), l2);
+                    cb = fmin(fmax(lb, -l2), l2);
+                    if (la < -l2) {
+                        aw[0] = -Ht;
+                        ab[0] = fmin(lb, -l2);
+                    }
+                    if (lb > l2) {
+                        aa[1] = fmax(la, l2);
+                        ab[1] = lb;
+                        aw[1] = -Ht;
+                    }
+                    if (c2 >= 1.0) {
+                        if (cb > ca) {
+                            wsh[1] += sgnr(cb);
+                            wsh[0] -= sgnr(ca);
+                            aa[2] = ca;
+                            ab[2] = cb;
+                            aw[2] = dH;
+                        }
+                    } else {
+                        l1 = sqrt(1.0 - c2);
+                        if (ca < -l1) {
+                            const double B = fmin(cb, -l1);
+                            wsh[0] -= sgnr(ca);
+                            if (B == cb) wsh[1] += sgnr(cb);
+                            else wsh[2] -= 1.0;
+                            aa[2] = ca;
+                            ab[2] = B;
+                            aw[2] = dH;
+                        }
+                        if (cb > l1) {
+                            const double Aq = fmax(ca, l1);
+                            wsh[1] += sgnr(cb);
+                            if (Aq == ca) wsh[0] -= sgnr(ca);
+                            else wsh[2] -= 1.0;
+                            aa[3] = Aq;
+                            ab[3] = cb;
+                            aw[3] = dH;
+                        }
+                        const double Ai = fmax(ca, -l1), Bi = fmin(cb, l1);
+                        if (Bi > Ai) {
+                            if (Bi == cb) wi[1] += sgnr(cb);
+                            else wi[2] += 1.0;
+                            if (Ai == ca) wi[0] -= sgnr(ca);
+                            else wi[2] += 1.0;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const bool want = live && aw[q] != 0.0;
+                const int slot = wave_push(want, nA);
+                if (want) {
+                    W.ang[0][slot] = R0;
+                    W.ang[1][slot] = aa[q];
+                    W.ang[2][slot] = ab[q];
+                    W.ang[3][slot] = sg * aw[q];
+                    W.ang_o[slot] = lane;
+                }
+                run_stack64<0>(W, nA, lane, false, wk);
+            }
+            {
+                const double xs[3] = {fabs(ca), fabs(cb), l1};
+#pragma unroll
+                for (int q = 0; q < 3; q++) {
+                    const double x = xs[q];
+                    const bool want = live && (wi[q] != 0.0 || wsh[q] != 0.0) && (q == 2 || x > 0.0);
+                    const int slot = wave_push(want, nP);
+                    if (want) {
+                        W.pnt[0][slot] = r0;
+                        W.pnt[1][slot] = R0;
+                        W.pnt[2][slot] = c2;
+                        W.pnt[3][slot] = c;
+                        W.pnt[4][slot] = x;
+                        W.pnt[5][slot] = q == 2 ? 1.0 : (x == l2 ? 2.0 : sqrt(c2 + x * x));
+                        W.pnt[6][slot] = sg * wi[q];
+                        W.pnt[7][slot] = sg * wsh[q];
+                        W.pnt_o[slot] = lane;
+                    }
+                    run_stack64<1>(W, nP, lane, false, wk);
+                }
+            }
+        }
+        run_stack64<0>(W, nA, lane, true, wk);
+        run_stack64<1>(W, nP, lane, true, wk);
+        lds_sync_wave();
+        if (active) f[k] = (inside ? 1.0 : 0.0) - W.acc[lane] * kInvPi;
+        lds_sync_wave();
+    }
+    flush_work(wk, counters);
+}
+
 // ---------------------------------------------------------------- cell tiles
 // A tile is up to 64 consecutive pairs of one cell (key = cell << 32 | tile
 // index within the cell).  A wavefront integrating a tile shares the cell, so
@@ -1016,6 +1239,16 @@ void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &
         else
             hipLaunchKernelGGL(k_integrate_flat<MAP_MIXED>, dim3(g), dim3(block), 0, s, np, ps.pair_p, ps.pair_c,
                                in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, fx);
+        EM_HIP(hipGetLastError());
+        return;
+    }
+    if (tune.persistent == 3 && precision == MAP_FP64) {
+        int64_t g = (int64_t)device_cu_count() * (tune.grid_per_cu > 0 ? tune.grid_per_cu : 8);
+        const int64_t need = ((np + 63) / 64 + (block / 64) - 1) / (block / 64);
+        if (g > need) g = need;
+        if (g < 1) g = 1;
+        hipLaunchKernelGGL(k_integrate_queued64, dim3((unsigned)g), dim3(block), 0, s, np, ps.pair_p, ps.pair_c,
+                           in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, tile_ctr);
         EM_HIP(hipGetLastError());
         return;
     }

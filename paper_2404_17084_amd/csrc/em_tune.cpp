@@ -135,7 +135,6 @@ extern "C" int map_autotune(map_ctx *h, const map_particles_in *p, const map_cel
                 for (int tw : tws)
                     for (int g : grids) {
                         if (d >= 2 && tw != 1) continue;  // cell tiles and task batches ignore tile_waves
-                        if (d == 3 && precision == MAP_FP64) continue;  // task batches are mixed-only
                         IntegrateTune t;
                         t.waves = precision == MAP_FP64 ? wv64[wi] : wvmx[wi];
                         t.persistent = d;

@@ -90,6 +90,22 @@ def test_deterministic_bits(mapper, uniform4k):
         assert np.array_equal(a["M"], b["M"]) and np.array_equal(a["f"], b["f"]) and np.array_equal(a["S"], b["S"])
 
 
+def test_fp64_task_batches_uniform4k(mapper, uniform4k, uniform4k_oracle):
+    """Distribution 3 in FP64: oracle parity at the FP64 bars, determinism."""
+    say("case: FP64 task batches uniform 4096")
+    p, c = uniform4k
+    em.map_set_tune(mapper.ctx, em.MAP_FP64, persistent=3)
+    try:
+        a = _run(mapper, p, c, em.MAP_FP64)
+        b = _run(mapper, p, c, em.MAP_FP64)
+    finally:
+        em.map_set_tune(mapper.ctx, em.MAP_FP64, persistent=-1)
+    o = uniform4k_oracle
+    assert np.abs(a["f"] - o["f"]).max() < FP64_PAIR_ABS
+    assert (np.abs(a["M"] - o["M"]) / o["M"]).max() < FP64_CELL_REL
+    assert np.array_equal(a["M"], b["M"]) and np.array_equal(a["f"], b["f"])
+
+
 def test_mixed_task_batches_uniform4k(mapper, uniform4k, uniform4k_oracle):
     """Distribution 3 (edge terms as wavefront task batches): oracle parity, determinism."""
     say("case: mixed task batches uniform 4096")
@@ -115,7 +131,7 @@ def test_ragged_small_clumps(mapper):
     p, c = synth.workload("clumps", 1000, 21)
     o = oracle.map_particles(p, c)
     for prec, tol, dist in ((em.MAP_FP64, FP64_CELL_REL, 1), (em.MAP_MIXED, MIXED_CELL_REL, 1),
-                            (em.MAP_MIXED, MIXED_CELL_REL, 3)):
+                            (em.MAP_MIXED, MIXED_CELL_REL, 3), (em.MAP_FP64, FP64_CELL_REL, 3)):
         em.map_set_tune(mapper.ctx, prec, persistent=dist)
         r = _run(mapper, p, c, prec)
         em.map_set_tune(mapper.ctx, prec, persistent=-1)
@@ -205,6 +221,7 @@ def test_invalid_inputs_rejected(mapper, what):
 
 # ------------------------------------------------------------------ clumps 262144 (sampled oracle)
 QUEUED = "mixed-queued"  # mixed path with its edge terms run as wavefront task batches (distribution 3)
+QUEUED64 = "fp64-queued"  # the same for the FP64 path
 
 
 @pytest.fixture(scope="module")
@@ -218,6 +235,9 @@ def clumps_gpu(mapper, clumps256k):
     say("case: clumps 262144 mixed, task batches")
     em.map_set_tune(mapper.ctx, em.MAP_MIXED, persistent=3)
     out[QUEUED] = _run(mapper, p, c, em.MAP_MIXED)
+    say("case: clumps 262144 FP64, task batches")
+    em.map_set_tune(mapper.ctx, em.MAP_FP64, persistent=3)
+    out[QUEUED64] = _run(mapper, p, c, em.MAP_FP64)
     for prec in (em.MAP_FP64, em.MAP_MIXED):
         em.map_set_tune(mapper.ctx, prec, persistent=-1)
     return out
@@ -239,7 +259,7 @@ def test_clumps_pairs_sampled(clumps256k, clumps_gpu):
 
 
 @pytest.mark.parametrize("prec,tol", [(em.MAP_FP64, FP64_CELL_REL), (em.MAP_MIXED, MIXED_CELL_REL),
-                                      (QUEUED, MIXED_CELL_REL)])
+                                      (QUEUED, MIXED_CELL_REL), (QUEUED64, FP64_CELL_REL)])
 def test_clumps_cells_sampled(clumps256k, clumps_gpu, prec, tol):
     p, c = clumps256k
     r = clumps_gpu[prec]
@@ -251,11 +271,15 @@ def test_clumps_cells_sampled(clumps256k, clumps_gpu, prec, tol):
     assert abs(r["stats"]["mass_out"] - 1.0) < MASS_ABS
     assert abs(r["M"].sum() - 1.0) < MASS_ABS
     interior = np.all((p.xyz - 2 * p.h[:, None] > 0) & (p.xyz + 2 * p.h[:, None] < 1), axis=1)
-    assert np.abs(r["S"][interior] - 1).max() < (1e-12 if prec == em.MAP_FP64 else 1e-5)
+    assert np.abs(r["S"][interior] - 1).max() < (1e-12 if prec in (em.MAP_FP64, QUEUED64) else 1e-5)
     if prec == QUEUED:  # the two mixed distributions agree to FP32 rounding of the terms
         ref = clumps_gpu[em.MAP_MIXED]
         assert np.array_equal(ref["pair_p"], r["pair_p"]) and np.array_equal(ref["pair_c"], r["pair_c"])
         assert (np.abs(r["M"] - ref["M"]) / ref["M"]).max() < MIXED_CELL_REL
+    if prec == QUEUED64:  # the FP64 distributions differ only in the order of FP64 additions
+        ref = clumps_gpu[em.MAP_FP64]
+        assert np.abs(r["f"] - ref["f"]).max() < FP64_PAIR_ABS
+        assert (np.abs(r["M"] - ref["M"]) / ref["M"]).max() < FP64_CELL_REL
 
 
 def test_autotune_and_cache(tmp_path, uniform4k):
