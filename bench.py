@@ -30,7 +30,7 @@ FLOP_FACE = 7       # wall distance d = c - n.p and r0 = |d|/h
 FLOP_EDGE = 19      # projections rho, l_a, l_b and their scaling by 1/h
 FLOP_ETERM = 8      # per-edge setup: c^2, the support crossing l2 and c (2 square roots)
 FLOP_MOMENT = 66    # closed form at one point: sqrt, asinh, angle difference, piece polynomial
-FLOP_QUAD = 250     # 8-point Gauss-Legendre sub-interval of the shell integrand (8 sqrt, 8 rcp)
+FLOP_QPOINT = 31    # one Gauss-Legendre point of the shell integrand (a sqrt and a reciprocal among them)
 FLOP_ANGLE = 6      # angle of one edge part seen from the foot point (one atan2) times H
 
 # HBM bytes per launch of the mixed integration kernel from FETCH_SIZE/WRITE_SIZE counter runs scaled by a
@@ -45,7 +45,7 @@ PEAK_FP32 = 157.3  # TFLOP/s, MI355X FP32 vector (packed)
 
 def algorithmic_flops(st) -> float:
     return (FLOP_FACE * st["n_face_visits"] + FLOP_EDGE * st["n_edge_visits"] + FLOP_ETERM * st["n_edge_terms"]
-            + FLOP_MOMENT * st["n_moment_evals"] + FLOP_QUAD * st["n_quad_intervals"]
+            + FLOP_MOMENT * st["n_moment_evals"] + FLOP_QPOINT * st["n_quad_points"]
             + FLOP_ANGLE * st["n_angle_evals"])
 
 
@@ -229,7 +229,8 @@ def main():
                          "mass_err": abs(stats[-1]["mass_out"] - stats[-1]["mass_in"]),
                          "max_abs_S_minus_1": stats[-1]["max_abs_S_minus_1"], "n_pairs": npairs,
                          "n_fixup_terms": stats[-1]["n_fixup_terms"], "n_moment_evals": stats[-1]["n_moment_evals"],
-                         "n_quad_intervals": stats[-1]["n_quad_intervals"], "n_angle_evals": stats[-1]["n_angle_evals"],
+                         "n_quad_intervals": stats[-1]["n_quad_intervals"], "n_quad_points": stats[-1]["n_quad_points"],
+                         "n_angle_evals": stats[-1]["n_angle_evals"],
                          "n_edge_visits": stats[-1]["n_edge_visits"], "n_candidates": stats[-1]["n_candidates"]}
         Ms[name] = M.cpu().numpy().copy()
         print(f"bench: {name}: {results[name]}", file=sys.stderr, flush=True)

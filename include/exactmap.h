@@ -111,6 +111,7 @@ typedef struct map_stats {
     int64_t n_moment_evals; /* closed-form evaluations (asinh, angle difference and polynomial) */
     int64_t n_quad_intervals; /* MAP_MIXED: 8-point Gauss-Legendre sub-intervals (shell piece) */
     int64_t n_angle_evals;  /* angles of edge parts beyond the support or with a piece correction */
+    int64_t n_quad_points;  /* Gauss-Legendre points of the shell quadrature (mixed path) */
     double mass_in;         /* sum of m_a */
     double mass_out;        /* sum of M_i */
     double max_abs_S_minus_1; /* over particles whose support lies inside box */

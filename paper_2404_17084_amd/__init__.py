@@ -58,7 +58,7 @@ class map_cells_in(ctypes.Structure):
 class map_stats(ctypes.Structure):
     _fields_ = [("n_pairs", c_i64), ("n_candidates", c_i64), ("n_edge_terms", c_i64), ("n_fixup_terms", c_i64),
                 ("n_face_visits", c_i64), ("n_edge_visits", c_i64), ("n_moment_evals", c_i64),
-                ("n_quad_intervals", c_i64), ("n_angle_evals", c_i64),
+                ("n_quad_intervals", c_i64), ("n_angle_evals", c_i64), ("n_quad_points", c_i64),
                 ("mass_in", c_dbl), ("mass_out", c_dbl), ("max_abs_S_minus_1", c_dbl), ("ms_setup", c_dbl),
                 ("ms_pairs", c_dbl), ("ms_integrate", c_dbl), ("ms_fixup", c_dbl), ("ms_reduce", c_dbl),
                 ("ms_total", c_dbl), ("ms_queue", c_dbl), ("ms_latency", c_dbl)]

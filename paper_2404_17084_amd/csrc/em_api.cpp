@@ -255,6 +255,7 @@ int64_t stage_finish(Ctx &C, Workspace &ws, JobState &js, const map_out *out, hi
         st->n_moment_evals = hcnt[C_MOMENTS];
         st->n_quad_intervals = hcnt[C_QUADS];
         st->n_angle_evals = hcnt[C_ANGLES];
+        st->n_quad_points = hcnt[C_QPOINTS];
         st->mass_out = hred[0];
         st->max_abs_S_minus_1 = hred[1];
         st->mass_in = hred[2];

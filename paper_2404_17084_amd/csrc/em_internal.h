@@ -111,7 +111,8 @@ enum : int {
     C_MOMENTS = 5,
     C_QUADS = 6,
     C_ANGLES = 7,
-    C_NUM = 8
+    C_QPOINTS = 8,
+    C_NUM = 9
 };
 
 // Device-resident view of one job's inputs.
