@@ -132,7 +132,7 @@ void prepare(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_i
     EM_CHECK(hf == 0, flag_code(hf), flag_text(hf));
 
     edges = ws.get<EdgeRec>(S_EDGE, (size_t)(c->n_face_verts > 0 ? c->n_face_verts : 1));
-    aabb = ws.get<double>(S_AABB, (size_t)(9 * (c->n_cells > 0 ? c->n_cells : 1)));
+    aabb = ws.get<double>(S_AABB, (size_t)(11 * (c->n_cells > 0 ? c->n_cells : 1)));
     double *vol_out = nullptr;
     if (!in.vol) {
         vol_out = ws.get<double>(S_VOL, (size_t)(c->n_cells > 0 ? c->n_cells : 1));

@@ -162,11 +162,26 @@ __global__ void k_cell_boxes(int64_t n_cells, const int64_t *cfo, const int64_t 
         double height = c - (nx * ref[0] + ny * ref[1] + nz * ref[2]);
         vol += height * area2 / 6.0;
     }
+    double g[3];
     for (int d = 0; d < 3; d++) {
+        g[d] = cen[d] / (double)nslot;
         aabb[6 * i + d] = lo[d];
         aabb[6 * i + 3 + d] = hi[d];
-        aabb[6 * n_cells + 3 * i + d] = cen[d] / (double)nslot;
+        aabb[6 * n_cells + 3 * i + d] = g[d];
     }
+    // radii of the balls about the interior point g inside the cell (least
+    // wall-plane distance) and containing it (greatest vertex distance)
+    double rin = INFINITY, rc2 = 0.0;
+    for (int64_t j = f0; j < f1; j++) {
+        rin = fmin(rin, plane[4 * j + 3] - (plane[4 * j] * g[0] + plane[4 * j + 1] * g[1] + plane[4 * j + 2] * g[2]));
+        for (int64_t s = fvo[j]; s < fvo[j + 1]; s++) {
+            const double *v = verts + 3 * (int64_t)fv[s];
+            const double dx = v[0] - g[0], dy = v[1] - g[1], dz = v[2] - g[2];
+            rc2 = fmax(rc2, dx * dx + dy * dy + dz * dz);
+        }
+    }
+    aabb[9 * n_cells + 2 * i] = fmax(rin, 0.0);
+    aabb[9 * n_cells + 2 * i + 1] = sqrt(rc2);
     if (vol_out) vol_out[i] = vol;
 }
 

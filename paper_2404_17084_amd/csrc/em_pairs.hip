@@ -217,15 +217,18 @@ __global__ void k_candidates(int64_t n, const double *__restrict__ xyz, const do
     if (!FILL && active) ccount[a] = count;
 }
 
-// Candidates in cell order.  A cell is accepted without the exact test when
-// an interior point of it (the mean of its wall vertices) or its whole
-// bounding box lies within (1 - 1e-6) 2h of the particle: its distance is
-// then certainly below 2h.  The other candidates go through a compacted list
-// to the exact test (one thread each, consecutive threads mostly on one cell).
+// Candidates in cell order.  Settled without the exact test: accepted when
+// the cell's whole bounding box lies within (1 - 1e-6) 2h of the particle, or
+// when the ball about the cell's interior point g inside the cell (radius
+// rin) comes closer than (1 - 1e-9) 2h; rejected when the ball about g that
+// contains the cell (radius rc) stays (1 + 1e-9) 2h or more away.  The
+// margins exceed the rounding of every distance involved, so these decisions
+// are the exact test's.  The rest go through a compacted list to the exact
+// test (one thread each, consecutive threads mostly on one cell).
 __global__ void k_quick(int64_t ncand, const uint32_t *__restrict__ cand_c, const uint32_t *__restrict__ cand_p,
                         const double *__restrict__ xyz, const double *__restrict__ h,
                         const double *__restrict__ aabb, const double *__restrict__ centre,
-                        int64_t *__restrict__ flag, int64_t *__restrict__ need)
+                        const double *__restrict__ radii, int64_t *__restrict__ flag, int64_t *__restrict__ need)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ncand) return;
@@ -238,9 +241,11 @@ __global__ void k_quick(int64_t ncand, const uint32_t *__restrict__ cand_c, cons
     const double fy = fmax(fabs(bb[1] - py), fabs(bb[4] - py));
     const double fz = fmax(fabs(bb[2] - pz), fabs(bb[5] - pz));
     const double gx = centre[3 * c] - px, gy = centre[3 * c + 1] - py, gz = centre[3 * c + 2] - pz;
-    const bool ok = fx * fx + fy * fy + fz * fz < r2 * 0.999998 || gx * gx + gy * gy + gz * gz < r2 * 0.999998;
+    const double dg = sqrt(gx * gx + gy * gy + gz * gz);
+    const bool ok = fx * fx + fy * fy + fz * fz < r2 * 0.999998 || dg - radii[2 * c] < r * (1.0 - 1e-9);
+    const bool no = !ok && dg - radii[2 * c + 1] >= r * (1.0 + 1e-9);
     flag[i] = ok ? 1 : 0;
-    need[i] = ok ? 0 : 1;
+    need[i] = (ok || no) ? 0 : 1;
 }
 
 __global__ void k_set_u64(unsigned long long *p, unsigned long long v)
@@ -372,7 +377,7 @@ PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, cons
         int64_t *npos = ws.get<int64_t>(S_BINCNT64, (size_t)ncand + 1);
         const unsigned gq = (unsigned)((ncand + 255) / 256);
         hipLaunchKernelGGL(k_quick, dim3(gq), dim3(256), 0, s, ncand, (const uint32_t *)cand_c,
-                           (const uint32_t *)cand_p, in.xyz, in.h, aabb, aabb + 6 * nc, flag, need);
+                           (const uint32_t *)cand_p, in.xyz, in.h, aabb, aabb + 6 * nc, aabb + 9 * nc, flag, need);
         EM_HIP(hipGetLastError());
         scan_counts(ws, need, npos, ncand, s);
         int64_t n_need = 0;
