@@ -118,31 +118,48 @@ __global__ void k_edge_table(int64_t n_faces, const int64_t *fvo, const int32_t 
         r.mx = ny * ez - nz * ey;
         r.my = nz * ex - nx * ez;
         r.mz = nx * ey - ny * ex;
-        r.pad0 = 0.0;
-        r.pad1 = 0.0;
         edges[s0 + k] = r;
     }
 }
 
-// One thread per cell: bounding box, an interior point (mean of the wall
-// vertex slots, inside the convex cell; stored after the n_cells boxes) and
-// (optionally) the volume from the signed cone decomposition about the cell's
-// first vertex.
+__device__ __forceinline__ double wsum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wmin(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wmax(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// One wavefront per cell, lanes over its walls: bounding box, an interior
+// point g (the mean of the wall vertices), the volume (when asked), and the
+// radii of the balls about g inside the cell (least wall-plane distance) and
+// containing it (greatest vertex distance).  Lanes combine in a fixed order.
 __global__ void k_cell_boxes(int64_t n_cells, const int64_t *cfo, const int64_t *fvo, const int32_t *fv,
                              const double *plane, const double *verts, double *aabb, double *vol_out)
 {
-    double cen[3] = {0.0, 0.0, 0.0};
-    int64_t nslot = 0;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
     if (i >= n_cells) return;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    int64_t f0 = cfo[i], f1 = cfo[i + 1];
+    double cen[3] = {0.0, 0.0, 0.0};
+    double nslot = 0.0, vol = 0.0;
+    const int64_t f0 = cfo[i], f1 = cfo[i + 1];
     const double *ref = verts + 3 * (int64_t)fv[fvo[f0]];
-    double vol = 0.0;
-    for (int64_t j = f0; j < f1; j++) {
-        int64_t s0 = fvo[j], s1 = fvo[j + 1];
+    for (int64_t j = f0 + lane; j < f1; j += 64) {
+        const int64_t s0 = fvo[j], s1 = fvo[j + 1];
         const double *v0 = verts + 3 * (int64_t)fv[s0];
-        double nx = plane[4 * j], ny = plane[4 * j + 1], nz = plane[4 * j + 2], c = plane[4 * j + 3];
+        const double nx = plane[4 * j], ny = plane[4 * j + 1], nz = plane[4 * j + 2], c = plane[4 * j + 3];
         double area2 = 0.0;
         for (int64_t s = s0; s < s1; s++) {
             const double *v = verts + 3 * (int64_t)fv[s];
@@ -151,28 +168,27 @@ __global__ void k_cell_boxes(int64_t n_cells, const int64_t *cfo, const int64_t 
                 hi[d] = fmax(hi[d], v[d]);
                 cen[d] += v[d];
             }
-            nslot++;
+            nslot += 1.0;
             if (s + 1 < s1 && s > s0) {
                 const double *w = verts + 3 * (int64_t)fv[s + 1];
-                double ax = v[0] - v0[0], ay = v[1] - v0[1], az = v[2] - v0[2];
-                double bx = w[0] - v0[0], by = w[1] - v0[1], bz = w[2] - v0[2];
+                const double ax = v[0] - v0[0], ay = v[1] - v0[1], az = v[2] - v0[2];
+                const double bx = w[0] - v0[0], by = w[1] - v0[1], bz = w[2] - v0[2];
                 area2 += (ay * bz - az * by) * nx + (az * bx - ax * bz) * ny + (ax * by - ay * bx) * nz;
             }
         }
-        double height = c - (nx * ref[0] + ny * ref[1] + nz * ref[2]);
+        const double height = c - (nx * ref[0] + ny * ref[1] + nz * ref[2]);
         vol += height * area2 / 6.0;
     }
     double g[3];
+    const double ns = wsum(nslot);
     for (int d = 0; d < 3; d++) {
-        g[d] = cen[d] / (double)nslot;
-        aabb[6 * i + d] = lo[d];
-        aabb[6 * i + 3 + d] = hi[d];
-        aabb[6 * n_cells + 3 * i + d] = g[d];
+        lo[d] = wmin(lo[d]);
+        hi[d] = wmax(hi[d]);
+        g[d] = wsum(cen[d]) / ns;
     }
-    // radii of the balls about the interior point g inside the cell (least
-    // wall-plane distance) and containing it (greatest vertex distance)
+    vol = wsum(vol);
     double rin = INFINITY, rc2 = 0.0;
-    for (int64_t j = f0; j < f1; j++) {
+    for (int64_t j = f0 + lane; j < f1; j += 64) {
         rin = fmin(rin, plane[4 * j + 3] - (plane[4 * j] * g[0] + plane[4 * j + 1] * g[1] + plane[4 * j + 2] * g[2]));
         for (int64_t s = fvo[j]; s < fvo[j + 1]; s++) {
             const double *v = verts + 3 * (int64_t)fv[s];
@@ -180,9 +196,18 @@ __global__ void k_cell_boxes(int64_t n_cells, const int64_t *cfo, const int64_t 
             rc2 = fmax(rc2, dx * dx + dy * dy + dz * dz);
         }
     }
-    aabb[9 * n_cells + 2 * i] = fmax(rin, 0.0);
-    aabb[9 * n_cells + 2 * i + 1] = sqrt(rc2);
-    if (vol_out) vol_out[i] = vol;
+    rin = wmin(rin);
+    rc2 = wmax(rc2);
+    if (lane == 0) {
+        for (int d = 0; d < 3; d++) {
+            aabb[6 * i + d] = lo[d];
+            aabb[6 * i + 3 + d] = hi[d];
+            aabb[6 * n_cells + 3 * i + d] = g[d];
+        }
+        aabb[9 * n_cells + 2 * i] = fmax(rin, 0.0);
+        aabb[9 * n_cells + 2 * i + 1] = sqrt(rc2);
+        if (vol_out) vol_out[i] = vol;
+    }
 }
 
 void launch_geometry(const DevInputs &in, EdgeRec *edges, double *aabb, double *vol_out, hipStream_t s)
@@ -193,7 +218,7 @@ void launch_geometry(const DevInputs &in, EdgeRec *edges, double *aabb, double *
         EM_HIP(hipGetLastError());
     }
     if (in.n_cells > 0) {
-        hipLaunchKernelGGL(k_cell_boxes, dim3((unsigned)((in.n_cells + 255) / 256)), dim3(256), 0, s, in.n_cells,
+        hipLaunchKernelGGL(k_cell_boxes, dim3((unsigned)((in.n_cells * 64 + 255) / 256)), dim3(256), 0, s, in.n_cells,
                            in.cfo, in.fvo, in.fv, in.plane, in.verts, aabb, vol_out);
         EM_HIP(hipGetLastError());
     }

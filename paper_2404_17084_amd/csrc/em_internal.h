@@ -82,9 +82,9 @@ enum Slot : int {
 struct alignas(16) EdgeRec {
     double vx, vy, vz, L;
     double ex, ey, ez, mx;
-    double my, mz, pad0, pad1;
+    double my, mz;
 };
-static_assert(sizeof(EdgeRec) == 96, "edge record layout");
+static_assert(sizeof(EdgeRec) == 80, "edge record layout");
 
 // Validation flag bits (device-side checks)
 enum : unsigned {
