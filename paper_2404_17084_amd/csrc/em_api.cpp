@@ -79,8 +79,9 @@ void check_host_args(const map_particles_in *p, const map_cells_in *c)
     EM_CHECK(p->n >= 0, MAP_EINVAL, "particle count is negative");
     EM_CHECK(c->n_cells >= 0 && c->n_faces >= 0 && c->n_face_verts >= 0 && c->n_verts >= 0, MAP_EGEOM,
              "negative geometry size");
-    EM_CHECK(p->n < (int64_t)INT32_MAX && c->n_cells < (int64_t)INT32_MAX && c->n_verts < (int64_t)INT32_MAX,
-             MAP_EINVAL, "particle, cell or vertex count above 2^31-1");
+    EM_CHECK(p->n < (int64_t)INT32_MAX && c->n_cells < (int64_t)INT32_MAX && c->n_verts < (int64_t)INT32_MAX &&
+                 c->n_faces < (int64_t)INT32_MAX && c->n_face_verts < (int64_t)INT32_MAX,
+             MAP_EINVAL, "particle, cell, wall, wall-vertex or vertex count above 2^31-1");
     EM_CHECK(p->mem_kind == MAP_MEM_HOST || p->mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad particle mem_kind");
     EM_CHECK(c->mem_kind == MAP_MEM_HOST || c->mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad cell mem_kind");
     if (p->n > 0) EM_CHECK(p->xyz && p->m && p->h, MAP_EINVAL, "null particle array");

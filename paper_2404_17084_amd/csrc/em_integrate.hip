@@ -494,26 +494,25 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_persistent(int64_t np, c
 constexpr int kQ = 128;  // stack capacity: below 64 pending before a push of at most 64
 
 struct WaveStacks {
-    float ang[4][kQ];  // R0, a, b, weight
-    int ang_o[kQ];
-    float pnt[7][kQ];  // r0, R0, c2, c, x, S, weight
-    int pnt_o[kQ];
+    float ang[3][kQ];  // atan2 arguments R0 (b - a) and R0^2 + a b of seg_angle, weight
+    float pnt[5][kQ];  // r0, R0, x, S, weight (c^2 and c are recomputed, as at the push)
     float qd[5][kQ];   // r0, c2, mid, half-length, weight
-    int qd_o[kQ];
+    uint8_t ang_o[kQ], pnt_o[kQ], qd_o[kQ];  // owner lanes
     double acc[64];
 };
 
 __device__ __forceinline__ void run_angle(WaveStacks &W, int i, Work &wk)
 {
-    const float R0 = W.ang[0][i], a = W.ang[1][i], b = W.ang[2][i], w = W.ang[3][i];
-    const float v = w * seg_angle<float>(R0, a, b, wk);
+    wk.angles++;
+    const float v = W.ang[2][i] * atan2f(W.ang[0][i], W.ang[1][i]);
     atomicAdd(&W.acc[W.ang_o[i]], (double)v);
 }
 
 __device__ __forceinline__ void run_point(WaveStacks &W, int i, Work &wk)
 {
-    const float r0 = W.pnt[0][i], R0 = W.pnt[1][i], c2 = W.pnt[2][i], c = W.pnt[3][i];
-    const float x = W.pnt[4][i], S = W.pnt[5][i], w = W.pnt[6][i];
+    const float r0 = W.pnt[0][i], R0 = W.pnt[1][i];
+    const float c2 = r0 * r0 + R0 * R0, c = sqrtf(c2);
+    const float x = W.pnt[2][i], S = W.pnt[3][i], w = W.pnt[4][i];
     const Trans<float> t = trans<float>(r0, R0, c2, c, x, S, wk);
     const float v = w * core_inner<float>(t, r0, R0, r0 * r0, c2);
     atomicAdd(&W.acc[W.pnt_o[i]], (double)v);
@@ -609,7 +608,7 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
         const int64_t k = (int64_t)t * 64 + lane;
         const bool active = k < np;
         double px = 0.0, py = 0.0, pz = 0.0, invh = 1.0;
-        int64_t s = 0, s_end = 0, j = 0;
+        int32_t s = 0, s_end = 0, j = 0;
         if (active) {
             const int64_t a = pair_p[k];
             const int64_t c = pair_c[k];
@@ -617,12 +616,12 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
             py = xyz[3 * a + 1];
             pz = xyz[3 * a + 2];
             invh = 1.0 / h[a];
-            j = cfo[c] - 1;
-            s = fvo[cfo[c]];
-            s_end = fvo[cfo[c + 1]];
+            j = (int32_t)cfo[c] - 1;
+            s = (int32_t)fvo[cfo[c]];
+            s_end = (int32_t)fvo[cfo[c + 1]];
         }
         W.acc[lane] = 0.0;
-        int64_t face_end = s;  // first slot past the current wall: the first step opens the cell's first wall
+        int32_t face_end = s;  // first slot past the current wall: the first step opens the cell's first wall
         const int n_steps = wave_max((int)(s_end - s));
         int nA = 0, nP = 0, nQ = 0;
         bool inside = true;
@@ -633,7 +632,7 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
             const bool valid = s < s_end;
             if (valid && s == face_end) {
                 j++;
-                face_end = fvo[j + 1];
+                face_end = (int32_t)fvo[j + 1];
                 const double d = plane[4 * j + 3] - (plane[4 * j] * px + plane[4 * j + 1] * py + plane[4 * j + 2] * pz);
                 wk.faces++;
                 const bool in_j = d >= 0.0;
@@ -744,11 +743,10 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
                 const bool want = live && aw[q] != 0.0f;
                 const int slot = wave_push(want, nA);
                 if (want) {
-                    W.ang[0][slot] = R0;
-                    W.ang[1][slot] = aa[q];
-                    W.ang[2][slot] = ab[q];
-                    W.ang[3][slot] = sg * aw[q];
-                    W.ang_o[slot] = lane;
+                    W.ang[0][slot] = R0 * (ab[q] - aa[q]);
+                    W.ang[1][slot] = R0 * R0 + aa[q] * ab[q];
+                    W.ang[2][slot] = sg * aw[q];
+                    W.ang_o[slot] = (uint8_t)lane;
                 }
                 run_stack<0>(W, nA, lane, false, wk);
             }
@@ -766,12 +764,10 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
                     if (want) {
                         W.pnt[0][slot] = r0;
                         W.pnt[1][slot] = R0;
-                        W.pnt[2][slot] = c2;
-                        W.pnt[3][slot] = c;
-                        W.pnt[4][slot] = x;
-                        W.pnt[5][slot] = q == 2 ? 1.0f : (x == l2 ? 2.0f : sqrtf(c2 + x * x));
-                        W.pnt[6][slot] = sg * wt;
-                        W.pnt_o[slot] = lane;
+                        W.pnt[2][slot] = x;
+                        W.pnt[3][slot] = q == 2 ? 1.0f : (x == l2 ? 2.0f : sqrtf(c2 + x * x));
+                        W.pnt[4][slot] = sg * wt;
+                        W.pnt_o[slot] = (uint8_t)lane;
                     }
                     run_stack<1>(W, nP, lane, false, wk);
                 }
@@ -798,7 +794,7 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
                         W.qd[2][slot] = qa + (2.0f * (float)kk + 1.0f) * hl;
                         W.qd[3][slot] = hl;
                         W.qd[4][slot] = wq;
-                        W.qd_o[slot] = lane;
+                        W.qd_o[slot] = (uint8_t)lane;
                     }
                     run_stack<2>(W, nQ, lane, false, wk);
                 }
