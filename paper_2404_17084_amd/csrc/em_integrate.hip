@@ -31,6 +31,7 @@
 #include <cmath>
 
 #include "em_internal.h"
+#include "em_fmath.h"
 #include "em_wave.h"
 
 namespace em {
@@ -38,11 +39,13 @@ namespace em {
 namespace {
 
 __device__ __forceinline__ double f_log1p(double x) { return log1p(x); }
-__device__ __forceinline__ float f_log1p(float x) { return log1pf(x); }
+__device__ __forceinline__ float f_log1p(float x) { return log1p_f32(x); }  // x >= 0 in the edge terms
 __device__ __forceinline__ double f_atan2(double y, double x) { return atan2(y, x); }
-__device__ __forceinline__ float f_atan2(float y, float x) { return atan2f(y, x); }
+__device__ __forceinline__ float f_atan2(float y, float x) { return atan2_f32(y, x); }  // y >= 0 in the edge terms
 __device__ __forceinline__ double f_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float f_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ float f_sqrt(float x) { return sqrt_f32(x); }
+__device__ __forceinline__ double f_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float f_rcp(float x) { return rcp_f32(x); }
 
 // Work counters of one thread (feed the algorithmic flop model).
 struct Work {
@@ -95,7 +98,7 @@ __device__ __forceinline__ Trans<R> trans(R r0, R R0, R c2, R c, R x, R S, Work 
     Trans<R> t;
     t.x = x;
     t.S = S;
-    t.a = f_log1p(x * (R(1) + x / (S + c)) / c);
+    t.a = f_log1p(x * (R(1) + x * f_rcp(S + c)) * f_rcp(c));
     const R R02 = R0 * R0;
     t.beta = f_atan2(x * R0 * (R02 + x * x), (S + r0) * (R02 * S + r0 * x * x));
     return t;
@@ -144,7 +147,7 @@ __device__ __forceinline__ float shell_quad(float r0, float R0, float c2, float 
     const float len = b - a;
     int nsub = (int)ceilf(len * rcp32(1.5f * dsing));
     nsub = nsub < 1 ? 1 : (nsub > 8 ? 8 : nsub);
-    const float hl = 0.5f * len / (float)nsub;
+    const float hl = 0.5f * len * rcp_f32((float)nsub);
     float tot = 0.0f;
     for (int k = 0; k < nsub; k++) {
         const float mid = a + (2.0f * (float)k + 1.0f) * hl;
@@ -153,7 +156,7 @@ __device__ __forceinline__ float shell_quad(float r0, float R0, float c2, float 
         for (int q = 0; q < 8; q++) {
             const float xq = (q & 1) ? -kGLx[q >> 1] : kGLx[q >> 1];
             const float l = mid + hl * xq;
-            const float S = sqrtf(c2 + l * l);
+            const float S = sqrt_f32(c2 + l * l);
             const float U = 2.0f - S;
             const float U2 = U * U;
             const float Sig = (((U + V) * U + V2) * U + V2 * V) * U + V4;
@@ -317,11 +320,14 @@ constexpr double kInvPi = 0.318309886183790671537767526745;
 // triangles that FP32 cannot resolve: the projection point within FP32
 // rounding of the edge line, or the wall plane, the edge line's closest
 // point or the edge itself within FP32 rounding of a piece radius (s = 1, 2)
-// of the kernel, where the FP32 piece assignment is not reliable.
+// of the kernel, where the FP32 piece assignment is not reliable; also the
+// particle within 2^-30 h of the edge line (c^2 < 2^-60), which keeps the FP32
+// square roots and reciprocals away from denormal arguments.
 __device__ __forceinline__ bool needs_fp64(double r0, double R0, double c2)
 {
     const double e = 9.5367431640625e-07;  // 2^-20
-    return (R0 * R0 < e * e * c2) || (fabs(r0 - 1.0) < e) || (fabs(c2 - 1.0) < e) || (fabs(c2 - 4.0) < 4.0 * e);
+    return (R0 * R0 < e * e * c2) || (c2 < 8.673617379884035e-19) || (fabs(r0 - 1.0) < e) ||
+           (fabs(c2 - 1.0) < e) || (fabs(c2 - 4.0) < 4.0 * e);
 }
 
 // Raw f for one pair.  PREC = MAP_FP64 or MAP_MIXED.  Wall distance, foot
@@ -504,14 +510,14 @@ struct WaveStacks {
 __device__ __forceinline__ void run_angle(WaveStacks &W, int i, Work &wk)
 {
     wk.angles++;
-    const float v = W.ang[2][i] * atan2f(W.ang[0][i], W.ang[1][i]);
+    const float v = W.ang[2][i] * atan2_f32(W.ang[0][i], W.ang[1][i]);
     atomicAdd(&W.acc[W.ang_o[i]], (double)v);
 }
 
 __device__ __forceinline__ void run_point(WaveStacks &W, int i, Work &wk)
 {
     const float r0 = W.pnt[0][i], R0 = W.pnt[1][i];
-    const float c2 = r0 * r0 + R0 * R0, c = sqrtf(c2);
+    const float c2 = r0 * r0 + R0 * R0, c = sqrt_f32(c2);
     const float x = W.pnt[2][i], S = W.pnt[3][i], w = W.pnt[4][i];
     const Trans<float> t = trans<float>(r0, R0, c2, c, x, S, wk);
     const float v = w * core_inner<float>(t, r0, R0, r0 * r0, c2);
@@ -538,7 +544,7 @@ __device__ __forceinline__ void run_quad(WaveStacks &W, int i, Work &wk)
     for (int q = 0; q < 4; q++) {
         const float xq = (q & 1) ? -kGL4x[q >> 1] : kGL4x[q >> 1];
         const float l = mid + hl * xq;
-        const float S = sqrtf(c2 + l * l);
+        const float S = sqrt_f32(c2 + l * l);
         const float U = 2.0f - S;
         const float U2 = U * U;
         const float Sig = (((U + V) * U + V2) * U + V2 * V) * U + V4;
@@ -684,8 +690,8 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
                     aw[0] = -Ht;
                 } else {
                     wk.eterms++;
-                    l2 = sqrtf(4.0f - c2);
-                    c = sqrtf(c2);
+                    l2 = sqrt_f32(4.0f - c2);
+                    c = sqrt_f32(c2);
                     ca = fminf(fmaxf(la, -l2), l2);
                     cb = fminf(fmaxf(lb, -l2), l2);
                     if (la < -l2) {
@@ -708,7 +714,7 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
                             aw[2] = dH;
                         }
                     } else {
-                        l1 = sqrtf(1.0f - c2);
+                        l1 = sqrt_f32(1.0f - c2);
                         if (ca < -l1) {
                             const float B = fminf(cb, -l1);
                             q0 = true;
@@ -765,7 +771,7 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
                         W.pnt[0][slot] = r0;
                         W.pnt[1][slot] = R0;
                         W.pnt[2][slot] = x;
-                        W.pnt[3][slot] = q == 2 ? 1.0f : (x == l2 ? 2.0f : sqrtf(c2 + x * x));
+                        W.pnt[3][slot] = q == 2 ? 1.0f : (x == l2 ? 2.0f : sqrt_f32(c2 + x * x));
                         W.pnt[4][slot] = sg * wt;
                         W.pnt_o[slot] = (uint8_t)lane;
                     }
@@ -782,7 +788,7 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
                 if (qv) {
                     nsub = (int)ceilf(len * rcp32(0.4f * ds));
                     nsub = nsub < 1 ? 1 : (nsub > 16 ? 16 : nsub);
-                    hl = 0.5f * len / (float)nsub;
+                    hl = 0.5f * len * rcp_f32((float)nsub);
                 }
                 const float wq = sg * R0 * hl * (1.0f / 120.0f);
                 for (int kk = 0; __ballot(kk < nsub) != 0; kk++) {
