@@ -582,11 +582,169 @@ __device__ __forceinline__ void run_stack(WaveStacks &W, int &count, int lane, b
     }
 }
 
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ int wave_max(int v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
     return v;
+}
+
+// One step of the mixed task batches: this lane's edge (slot s of the current
+// wall; live = the lane has a wall within the support and an edge at this
+// step) is projected in FP64, classified in FP32 and its tasks are pushed;
+// full stacks run as they fill.  Wave-uniform control flow; r0d, r0, Ht, dH
+// and fsign describe the lane's current wall.
+__device__ __forceinline__ void mixed_edge_step(WaveStacks &W, int lane, Work &wk, int &nA, int &nP, int &nQ, bool live,
+                                                const EdgeRec *__restrict__ edges, int32_t s, double px, double py,
+                                                double pz, double invh, double r0d, float r0, float Ht, float dH,
+                                                float fsign, int64_t k, FixList fx, double &acc_in)
+{
+    float R0 = 0.0f, la = 0.0f, lb = 0.0f, sg = 0.0f;
+    if (live) {
+        const EdgeRec E = edges[s];
+        const double wx = px - E.vx, wy = py - E.vy, wz = pz - E.vz;
+        const double rho = E.mx * wx + E.my * wy + E.mz * wz;
+        wk.edges++;
+        if (rho == 0.0) {
+            live = false;
+        } else {
+            const double lad = -(E.ex * wx + E.ey * wy + E.ez * wz) * invh;
+            const double lbd = lad + E.L * invh;
+            const double R0d = fabs(rho) * invh;
+            const double c2d = r0d * r0d + R0d * R0d;
+            if (needs_fp64(r0d, R0d, c2d)) {
+                const unsigned slot = atomicAdd(fx.count, 1u);
+                if (slot < fx.cap) fx.items[slot] = ((uint64_t)k << 32) | (uint64_t)(uint32_t)s;
+                live = false;
+            } else {
+                R0 = (float)R0d;
+                la = (float)lad;
+                lb = (float)lbd;
+                sg = (rho > 0.0 ? 1.0f : -1.0f) * fsign;
+            }
+        }
+    }
+    // classification (the mixed form of edge_term).  The edge [la, lb] splits
+    // into the parts beyond the support (|l| > l2), the shell parts and the
+    // inner part (|l| < l1, when c < 1): [la, ca] + [cb, lb] beyond,
+    // [ca, ia] + [ib, cb] shell, [ia, ib] inner, every part oriented and
+    // possibly empty.  Far edges (c >= 2) are all beyond (l2 = 0).
+    const float A = r0 * r0;
+    const float c2 = A + R0 * R0;
+    const bool near = live && c2 < 4.0f;
+    const bool has_inner = near && c2 < 1.0f;
+    const float l2 = near ? sqrt_f32(4.0f - c2) : 0.0f;
+    const float l1 = has_inner ? sqrt_f32(1.0f - c2) : 0.0f;
+    const float c = near && !has_inner ? sqrt_f32(c2) : 1.0f;
+    const float ca = fminf(fmaxf(-l2, la), lb);
+    const float cb = fminf(fmaxf(l2, ca), lb);
+    const float ia = has_inner ? fminf(fmaxf(-l1, ca), cb) : cb;
+    const float ib = has_inner ? fminf(fmaxf(l1, ia), cb) : cb;
+    if (near) wk.eterms++;
+    // angle terms: -H times the beyond parts' angle, dH times the shell
+    // parts' angle.  The angle of two parts is the argument of the product of
+    // their complex numbers (R0^2 + a b) + i R0 (b - a) (sum below pi).  One
+    // angle per lane is taken here; a lane that has both pushes the shell
+    // angle as a task.
+    const bool has_b = live && (la < ca || cb < lb);
+    const bool has_s = near && dH != 0.0f && (ca < ia || ib < cb);
+    float zx, zy;
+    {
+        const float R02 = R0 * R0;
+        const bool b = has_b;
+        const float a1 = b ? la : ca, b1 = b ? ca : ia, a2 = b ? cb : ib, b2 = b ? lb : cb;
+        const float x1 = R02 + a1 * b1, y1 = R0 * (b1 - a1), x2 = R02 + a2 * b2, y2 = R0 * (b2 - a2);
+        zx = x1 * x2 - y1 * y2;
+        zy = x1 * y2 + x2 * y1;
+    }
+    const float w_in = has_b ? -Ht * sg : (has_s ? dH * sg : 0.0f);
+    acc_in += (double)(w_in * atan2_f32(zy, zx));
+    wk.angles += (has_b || has_s) ? 1u : 0u;
+    {
+        const bool want = has_b && has_s;
+        if (__ballot(want) != 0) {
+            const int slot = wave_push(want, nA);
+            if (want) {
+                const float R02 = R0 * R0;
+                const float x1 = R02 + ca * ia, y1 = R0 * (ia - ca), x2 = R02 + ib * cb, y2 = R0 * (cb - ib);
+                W.ang[0][slot] = x1 * y2 + x2 * y1;
+                W.ang[1][slot] = x1 * x2 - y1 * y2;
+                W.ang[2][slot] = dH * sg;
+                W.ang_o[slot] = (uint8_t)lane;
+            }
+            run_stack<0>(W, nA, lane, false, wk);
+        }
+    }
+    // inner part: closed-form points at its ends (odd in l: F(ib) - F(ia))
+    float wi0 = 0.f, wi1 = 0.f, wi2 = 0.f;
+    if (has_inner && ib > ia) {
+        if (ib == cb) wi1 += sgnr(cb);
+        else wi2 += 1.0f;
+        if (ia == ca) wi0 -= sgnr(ca);
+        else wi2 += 1.0f;
+    }
+    // shell parts by quadrature: [ca, ia] and [ib, cb]
+    const bool q0 = near && ia > ca, q1 = near && cb > ib;
+    const float qa0 = ca, qb0 = ia, qa1 = ib, qb1 = cb, qd0 = has_inner ? 1.0f : c;
+    {
+        const float x0 = fabsf(ca), x1 = fabsf(cb);
+        const bool w0 = live && wi0 != 0.0f && x0 > 0.0f;
+        const bool w1 = live && wi1 != 0.0f && x1 > 0.0f;
+        const bool w2 = live && wi2 != 0.0f;
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            const bool want = q == 0 ? w0 : (q == 1 ? w1 : w2);
+            const float x = q == 0 ? x0 : (q == 1 ? x1 : l1);
+            const float wt = q == 0 ? wi0 : (q == 1 ? wi1 : wi2);
+            const int slot = wave_push(want, nP);
+            if (want) {
+                W.pnt[0][slot] = r0;
+                W.pnt[1][slot] = R0;
+                W.pnt[2][slot] = x;
+                W.pnt[3][slot] = q == 2 ? 1.0f : (x == l2 ? 2.0f : sqrt_f32(c2 + x * x));
+                W.pnt[4][slot] = sg * wt;
+                W.pnt_o[slot] = (uint8_t)lane;
+            }
+            run_stack<1>(W, nP, lane, false, wk);
+        }
+    }
+    // both shell parts' sub-intervals in one uniform loop
+    int n0 = 0, n1 = 0;
+    float hl0 = 0.0f, hl1 = 0.0f;
+    if (q0) {
+        const float len = qb0 - qa0;
+        n0 = min(max((int)ceilf(len * rcp_f32(0.4f * qd0)), 1), 16);
+        hl0 = 0.5f * len * rcp_f32((float)n0);
+    }
+    if (q1) {
+        const float len = qb1 - qa1;
+        n1 = min(max((int)ceilf(len * rcp_f32(0.4f)), 1), 16);
+        hl1 = 0.5f * len * rcp_f32((float)n1);
+    }
+    const int nq = n0 + n1;
+    const float wq0 = sg * R0 * hl0 * (1.0f / 120.0f), wq1 = sg * R0 * hl1 * (1.0f / 120.0f);
+    for (int kk = 0; __ballot(kk < nq) != 0; kk++) {
+        const bool want = kk < nq;
+        const int slot = wave_push(want, nQ);
+        if (want) {
+            const bool first = kk < n0;
+            const float hl = first ? hl0 : hl1;
+            W.qd[0][slot] = r0;
+            W.qd[1][slot] = c2;
+            W.qd[2][slot] = first ? qa0 + (2.0f * (float)kk + 1.0f) * hl0 : qa1 + (2.0f * (float)(kk - n0) + 1.0f) * hl1;
+            W.qd[3][slot] = hl;
+            W.qd[4][slot] = first ? wq0 : wq1;
+            W.qd_o[slot] = (uint8_t)lane;
+        }
+        run_stack<2>(W, nQ, lane, false, wk);
+    }
 }
 
 template <int WPE>
@@ -630,6 +788,7 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
         int32_t face_end = s;  // first slot past the current wall: the first step opens the cell's first wall
         const int n_steps = wave_max((int)(s_end - s));
         int nA = 0, nP = 0, nQ = 0;
+        double acc_in = 0.0;  // this lane's terms taken in place (not as tasks)
         bool inside = true;
         bool face_ok = false;
         double r0d = 0.0;
@@ -650,167 +809,14 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
                 Ht = pi_H<float>(r0);
                 dH = pi_dH<float>(r0);
             }
-            // one edge: FP64 projections, FP32 classification into tasks
-            bool live = valid && face_ok;
-            float R0 = 0.0f, la = 0.0f, lb = 0.0f, sg = 0.0f;
-            if (live) {
-                const EdgeRec E = edges[s];
-                const double wx = px - E.vx, wy = py - E.vy, wz = pz - E.vz;
-                const double rho = E.mx * wx + E.my * wy + E.mz * wz;
-                wk.edges++;
-                if (rho == 0.0) {
-                    live = false;
-                } else {
-                    const double lad = -(E.ex * wx + E.ey * wy + E.ez * wz) * invh;
-                    const double lbd = lad + E.L * invh;
-                    const double R0d = fabs(rho) * invh;
-                    const double c2d = r0d * r0d + R0d * R0d;
-                    if (needs_fp64(r0d, R0d, c2d)) {
-                        const unsigned slot = atomicAdd(fx.count, 1u);
-                        if (slot < fx.cap) fx.items[slot] = ((uint64_t)k << 32) | (uint64_t)(uint32_t)s;
-                        live = false;
-                    } else {
-                        R0 = (float)R0d;
-                        la = (float)lad;
-                        lb = (float)lbd;
-                        sg = (rho > 0.0 ? 1.0f : -1.0f) * fsign;
-                    }
-                }
-            }
-            // classification (the mixed form of edge_term)
-            const float A = r0 * r0;
-            const float c2 = A + R0 * R0;
-            float aa[4] = {la, 0.f, 0.f, 0.f}, ab[4] = {lb, 0.f, 0.f, 0.f}, aw[4] = {0.f, 0.f, 0.f, 0.f};
-            float wi0 = 0.f, wi1 = 0.f, wi2 = 0.f;
-            float qa0 = 0.f, qb0 = 0.f, qa1 = 0.f, qb1 = 0.f, qd0 = 1.f;
-            bool q0 = false, q1 = false;
-            float l2 = 0.f, c = 1.f, l1 = 0.f, ca = la, cb = lb;
-            if (live) {
-                if (!(c2 < 4.0f)) {
-                    aw[0] = -Ht;
-                } else {
-                    wk.eterms++;
-                    l2 = sqrt_f32(4.0f - c2);
-                    c = sqrt_f32(c2);
-                    ca = fminf(fmaxf(la, -l2), l2);
-                    cb = fminf(fmaxf(lb, -l2), l2);
-                    if (la < -l2) {
-                        aw[0] = -Ht;
-                        ab[0] = fminf(lb, -l2);
-                    }
-                    if (lb > l2) {
-                        aa[1] = fmaxf(la, l2);
-                        ab[1] = lb;
-                        aw[1] = -Ht;
-                    }
-                    if (c2 >= 1.0f) {
-                        if (cb > ca) {
-                            q0 = true;
-                            qa0 = ca;
-                            qb0 = cb;
-                            qd0 = c;
-                            aa[2] = ca;
-                            ab[2] = cb;
-                            aw[2] = dH;
-                        }
-                    } else {
-                        l1 = sqrt_f32(1.0f - c2);
-                        if (ca < -l1) {
-                            const float B = fminf(cb, -l1);
-                            q0 = true;
-                            qa0 = ca;
-                            qb0 = B;
-                            aa[2] = ca;
-                            ab[2] = B;
-                            aw[2] = dH;
-                        }
-                        if (cb > l1) {
-                            const float Aq = fmaxf(ca, l1);
-                            q1 = true;
-                            qa1 = Aq;
-                            qb1 = cb;
-                            aa[3] = Aq;
-                            ab[3] = cb;
-                            aw[3] = dH;
-                        }
-                        const float Ai = fmaxf(ca, -l1), Bi = fminf(cb, l1);
-                        if (Bi > Ai) {
-                            if (Bi == cb) wi1 += sgnr(cb);
-                            else wi2 += 1.0f;
-                            if (Ai == ca) wi0 -= sgnr(ca);
-                            else wi2 += 1.0f;
-                        }
-                    }
-                }
-            }
-            // pushes (uniform), each followed by a run of a full stack
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const bool want = live && aw[q] != 0.0f;
-                const int slot = wave_push(want, nA);
-                if (want) {
-                    W.ang[0][slot] = R0 * (ab[q] - aa[q]);
-                    W.ang[1][slot] = R0 * R0 + aa[q] * ab[q];
-                    W.ang[2][slot] = sg * aw[q];
-                    W.ang_o[slot] = (uint8_t)lane;
-                }
-                run_stack<0>(W, nA, lane, false, wk);
-            }
-            {
-                const float x0 = fabsf(ca), x1 = fabsf(cb);
-                const bool w0 = live && wi0 != 0.0f && x0 > 0.0f;
-                const bool w1 = live && wi1 != 0.0f && x1 > 0.0f;
-                const bool w2 = live && wi2 != 0.0f;
-#pragma unroll
-                for (int q = 0; q < 3; q++) {
-                    const bool want = q == 0 ? w0 : (q == 1 ? w1 : w2);
-                    const float x = q == 0 ? x0 : (q == 1 ? x1 : l1);
-                    const float wt = q == 0 ? wi0 : (q == 1 ? wi1 : wi2);
-                    const int slot = wave_push(want, nP);
-                    if (want) {
-                        W.pnt[0][slot] = r0;
-                        W.pnt[1][slot] = R0;
-                        W.pnt[2][slot] = x;
-                        W.pnt[3][slot] = q == 2 ? 1.0f : (x == l2 ? 2.0f : sqrt_f32(c2 + x * x));
-                        W.pnt[4][slot] = sg * wt;
-                        W.pnt_o[slot] = (uint8_t)lane;
-                    }
-                    run_stack<1>(W, nP, lane, false, wk);
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < 2; q++) {
-                const bool qv = live && (q == 0 ? q0 : q1);
-                const float qa = q == 0 ? qa0 : qa1, qb = q == 0 ? qb0 : qb1, ds = q == 0 ? qd0 : 1.0f;
-                const float len = qb - qa;
-                int nsub = 0;
-                float hl = 0.0f;
-                if (qv) {
-                    nsub = (int)ceilf(len * rcp32(0.4f * ds));
-                    nsub = nsub < 1 ? 1 : (nsub > 16 ? 16 : nsub);
-                    hl = 0.5f * len * rcp_f32((float)nsub);
-                }
-                const float wq = sg * R0 * hl * (1.0f / 120.0f);
-                for (int kk = 0; __ballot(kk < nsub) != 0; kk++) {
-                    const bool want = kk < nsub;
-                    const int slot = wave_push(want, nQ);
-                    if (want) {
-                        W.qd[0][slot] = r0;
-                        W.qd[1][slot] = c2;
-                        W.qd[2][slot] = qa + (2.0f * (float)kk + 1.0f) * hl;
-                        W.qd[3][slot] = hl;
-                        W.qd[4][slot] = wq;
-                        W.qd_o[slot] = (uint8_t)lane;
-                    }
-                    run_stack<2>(W, nQ, lane, false, wk);
-                }
-            }
+            mixed_edge_step(W, lane, wk, nA, nP, nQ, valid && face_ok, edges, s, px, py, pz, invh, r0d, r0, Ht, dH,
+                            fsign, k, fx, acc_in);
         }
         run_stack<0>(W, nA, lane, true, wk);
         run_stack<1>(W, nP, lane, true, wk);
         run_stack<2>(W, nQ, lane, true, wk);
         lds_sync_wave();
-        if (active) f[k] = (inside ? 1.0 : 0.0) - W.acc[lane] * kInvPi;
+        if (active) f[k] = (inside ? 1.0 : 0.0) - (W.acc[lane] + acc_in) * kInvPi;
         lds_sync_wave();
     }
     flush_work(wk, counters);
@@ -1055,13 +1061,6 @@ __global__ void k_tile_fill(int64_t n_cells, const int64_t *__restrict__ toff, u
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_cells) return;
     for (int64_t u = 0; u < toff[i + 1] - toff[i]; u++) tiles[toff[i] + u] = ((uint64_t)i << 32) | (uint64_t)u;
-}
-
-__device__ __forceinline__ int64_t uniform64(int64_t v)
-{
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 template <int PREC>
