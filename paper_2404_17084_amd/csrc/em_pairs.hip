@@ -37,16 +37,15 @@ struct Box {
 // polygon distances, the pair is rejected.  (2) The first face or edge
 // distance computed below r2 accepts the pair, since the minimum is no
 // larger.
-__device__ __noinline__ bool cell_meets(double px, double py, double pz, double r2, int64_t cell,
-                                        const int64_t *cfo, const int64_t *fvo, const EdgeRec *edges,
-                                        const double *plane)
+template <class G>
+__device__ __forceinline__ bool meets_impl(double px, double py, double pz, double r2, const G &g)
 {
 #pragma clang fp contract(off)
-    const int64_t j0 = cfo[cell], j1 = cfo[cell + 1];
+    const int nf = g.n_faces();
     double far = 0.0;
     bool inside = true;
-    for (int64_t j = j0; j < j1; j++) {
-        const double d = plane[4 * j + 3] - (plane[4 * j] * px + plane[4 * j + 1] * py + plane[4 * j + 2] * pz);
+    for (int j = 0; j < nf; j++) {
+        const double d = g.pl(j, 3) - (g.pl(j, 0) * px + g.pl(j, 1) * py + g.pl(j, 2) * pz);
         if (d < 0.0) {
             inside = false;
             if (-d > far) far = -d;
@@ -54,18 +53,17 @@ __device__ __noinline__ bool cell_meets(double px, double py, double pz, double 
     }
     if (inside) return true;
     if (far * far > r2 * (1.0 + 1e-9)) return false;
-    for (int64_t j = j0; j < j1; j++) {
-        const double n0 = plane[4 * j], n1 = plane[4 * j + 1], n2 = plane[4 * j + 2], c = plane[4 * j + 3];
+    for (int j = 0; j < nf; j++) {
+        const double n0 = g.pl(j, 0), n1 = g.pl(j, 1), n2 = g.pl(j, 2), c = g.pl(j, 3);
         const double d = c - (n0 * px + n1 * py + n2 * pz);
         if (!(d < 0.0)) continue;
-        const int64_t k0 = fvo[j], k1 = fvo[j + 1];
-        const int64_t nv = k1 - k0;
+        const int k0 = g.slot0(j), nv = g.slot0(j + 1) - k0;
         bool left = true;
-        for (int64_t k = 0; k < nv; k++) {
-            const EdgeRec &A = edges[k0 + k];
-            const EdgeRec &B = edges[k0 + (k + 1 == nv ? 0 : k + 1)];
-            const double ex = B.vx - A.vx, ey = B.vy - A.vy, ez = B.vz - A.vz;
-            const double wx = px - A.vx, wy = py - A.vy, wz = pz - A.vz;
+        for (int k = 0; k < nv; k++) {
+            const int kb = k0 + (k + 1 == nv ? 0 : k + 1);
+            const double ax = g.vx(k0 + k, 0), ay = g.vx(k0 + k, 1), az = g.vx(k0 + k, 2);
+            const double ex = g.vx(kb, 0) - ax, ey = g.vx(kb, 1) - ay, ez = g.vx(kb, 2) - az;
+            const double wx = px - ax, wy = py - ay, wz = pz - az;
             const double cr = (ey * wz - ez * wy) * n0 + (ez * wx - ex * wz) * n1 + (ex * wy - ey * wx) * n2;
             if (cr < 0.0) {
                 left = false;
@@ -76,11 +74,11 @@ __device__ __noinline__ bool cell_meets(double px, double py, double pz, double 
             if (d * d < r2) return true;
             continue;
         }
-        for (int64_t k = 0; k < nv; k++) {
-            const EdgeRec &A = edges[k0 + k];
-            const EdgeRec &B = edges[k0 + (k + 1 == nv ? 0 : k + 1)];
-            const double ex = B.vx - A.vx, ey = B.vy - A.vy, ez = B.vz - A.vz;
-            const double wx = px - A.vx, wy = py - A.vy, wz = pz - A.vz;
+        for (int k = 0; k < nv; k++) {
+            const int kb = k0 + (k + 1 == nv ? 0 : k + 1);
+            const double ax = g.vx(k0 + k, 0), ay = g.vx(k0 + k, 1), az = g.vx(k0 + k, 2);
+            const double ex = g.vx(kb, 0) - ax, ey = g.vx(kb, 1) - ay, ez = g.vx(kb, 2) - az;
+            const double wx = px - ax, wy = py - ay, wz = pz - az;
             const double ee = ex * ex + ey * ey + ez * ez;
             double t = 0.0;
             if (ee > 0.0) {
@@ -93,6 +91,40 @@ __device__ __noinline__ bool cell_meets(double px, double py, double pz, double 
         }
     }
     return false;
+}
+
+// One cell's walls read from the global tables (slots relative to the cell's first).
+struct CellGlobal {
+    const double *plane;  // at the cell's first wall
+    const int64_t *fvo;   // at the cell's first wall
+    const EdgeRec *edges;  // at the cell's first slot
+    int nf;
+    __device__ int n_faces() const { return nf; }
+    __device__ double pl(int j, int q) const { return plane[4 * j + q]; }
+    __device__ int slot0(int j) const { return (int)(fvo[j] - fvo[0]); }
+    __device__ double vx(int k, int q) const { return q == 0 ? edges[k].vx : (q == 1 ? edges[k].vy : edges[k].vz); }
+};
+
+// The same cell staged in LDS by one wavefront.
+constexpr int kExactMaxFaces = 48, kExactMaxSlots = 192;
+struct CellLds {
+    double pl_[kExactMaxFaces][4];
+    double v_[kExactMaxSlots][3];
+    int so_[kExactMaxFaces + 1];
+    int nf;
+    __device__ int n_faces() const { return nf; }
+    __device__ double pl(int j, int q) const { return pl_[j][q]; }
+    __device__ int slot0(int j) const { return so_[j]; }
+    __device__ double vx(int k, int q) const { return v_[k][q]; }
+};
+
+__device__ __noinline__ bool cell_meets(double px, double py, double pz, double r2, int64_t cell,
+                                        const int64_t *cfo, const int64_t *fvo, const EdgeRec *edges,
+                                        const double *plane)
+{
+    const int64_t j0 = cfo[cell];
+    CellGlobal g{plane + 4 * j0, fvo + j0, edges + fvo[j0], (int)(cfo[cell + 1] - j0)};
+    return meets_impl(px, py, pz, r2, g);
 }
 
 // Morton code (21 bits per axis) of each cell's bounding-box centre
@@ -260,18 +292,64 @@ __global__ void k_need_list(int64_t ncand, const int64_t *__restrict__ need, con
     if (i < ncand && need[i]) list[npos[i]] = (uint32_t)i;
 }
 
-__global__ void k_exact(int64_t n_need, const uint32_t *__restrict__ list, const uint32_t *__restrict__ cand_c,
-                        const uint32_t *__restrict__ cand_p, const double *__restrict__ xyz,
-                        const double *__restrict__ h, const int64_t *__restrict__ cfo,
-                        const int64_t *__restrict__ fvo, const EdgeRec *__restrict__ edges,
-                        const double *__restrict__ plane, int64_t *__restrict__ flag)
+// Exact test of the listed candidates, one wavefront per 64 consecutive list
+// entries (the list is in cell order).  The wavefront stages each distinct
+// cell of its entries in LDS (walls, slot offsets, slot vertices) and the
+// lanes of that cell test against the staged copy; cells too large for the
+// staging area are tested from global memory.
+__global__ void __launch_bounds__(256) k_exact(int64_t n_need, const uint32_t *__restrict__ list,
+                                               const uint32_t *__restrict__ cand_c, const uint32_t *__restrict__ cand_p,
+                                               const double *__restrict__ xyz, const double *__restrict__ h,
+                                               const int64_t *__restrict__ cfo, const int64_t *__restrict__ fvo,
+                                               const EdgeRec *__restrict__ edges, const double *__restrict__ plane,
+                                               int64_t *__restrict__ flag)
 {
+    __shared__ CellLds stage[4];
+    CellLds &L = stage[threadIdx.x >> 6];
+    const int lane = threadIdx.x & 63;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_need) return;
-    const int64_t i = list[t];
-    const int64_t c = cand_c[i], a = cand_p[i];
-    const double r = 2.0 * h[a];
-    flag[i] = cell_meets(xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2], r * r, c, cfo, fvo, edges, plane) ? 1 : 0;
+    const bool valid = t < n_need;
+    int64_t i = 0, c = -1, a = 0;
+    if (valid) {
+        i = list[t];
+        c = cand_c[i];
+        a = cand_p[i];
+    }
+    double px = 0.0, py = 0.0, pz = 0.0, r2 = 0.0;
+    if (valid) {
+        px = xyz[3 * a];
+        py = xyz[3 * a + 1];
+        pz = xyz[3 * a + 2];
+        const double r = 2.0 * h[a];
+        r2 = r * r;
+    }
+    bool hit = false;
+    unsigned long long todo = __ballot(valid);
+    while (todo != 0) {
+        const int leader = __builtin_ctzll(todo);
+        const int64_t cc = (int64_t)__shfl((long long)c, leader, 64);
+        const bool mine = valid && c == cc;
+        todo &= ~__ballot(mine);
+        const int64_t j0 = cfo[cc], nf = cfo[cc + 1] - j0;
+        const int64_t s0 = fvo[j0], ns = fvo[j0 + nf] - s0;
+        if (nf <= kExactMaxFaces && ns <= kExactMaxSlots) {
+            lds_sync_wave();
+            for (int q = lane; q < 4 * nf; q += 64) L.pl_[q >> 2][q & 3] = plane[4 * j0 + q];
+            for (int q = lane; q <= nf; q += 64) L.so_[q] = (int)(fvo[j0 + q] - s0);
+            for (int q = lane; q < ns; q += 64) {
+                const EdgeRec &E = edges[s0 + q];
+                L.v_[q][0] = E.vx;
+                L.v_[q][1] = E.vy;
+                L.v_[q][2] = E.vz;
+            }
+            if (lane == 0) L.nf = (int)nf;
+            lds_sync_wave();
+            if (mine) hit = meets_impl(px, py, pz, r2, L);
+        } else if (mine) {
+            hit = cell_meets(px, py, pz, r2, cc, cfo, fvo, edges, plane);
+        }
+    }
+    if (valid) flag[i] = hit ? 1 : 0;
 }
 
 __global__ void k_compact(int64_t ncand, const uint32_t *__restrict__ cand_c, const uint32_t *__restrict__ cand_p,
