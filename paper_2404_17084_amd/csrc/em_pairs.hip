@@ -105,17 +105,19 @@ struct CellGlobal {
     __device__ double vx(int k, int q) const { return q == 0 ? edges[k].vx : (q == 1 ? edges[k].vy : edges[k].vz); }
 };
 
-// The same cell staged in LDS by one wavefront.
-constexpr int kExactMaxFaces = 48, kExactMaxSlots = 192;
-struct CellLds {
+// One cell staged in LDS by a wavefront for the screened distance test:
+// wall planes in FP64 (the exact test's plane pass) and, per slot, the edge
+// start vertex relative to the cell centre g, the unit direction, the unit
+// in-wall normal (pointing into the wall polygon) and the length, in FP32.
+constexpr int kExactMaxFaces = 40, kExactMaxSlots = 160;
+struct CellFast {
     double pl_[kExactMaxFaces][4];
-    double v_[kExactMaxSlots][3];
+    float v_[kExactMaxSlots][3];
+    float e_[kExactMaxSlots][3];
+    float m_[kExactMaxSlots][3];
+    float L_[kExactMaxSlots];
     int so_[kExactMaxFaces + 1];
     int nf;
-    __device__ int n_faces() const { return nf; }
-    __device__ double pl(int j, int q) const { return pl_[j][q]; }
-    __device__ int slot0(int j) const { return so_[j]; }
-    __device__ double vx(int k, int q) const { return v_[k][q]; }
 };
 
 __device__ __noinline__ bool cell_meets(double px, double py, double pz, double r2, int64_t cell,
@@ -294,33 +296,40 @@ __global__ void k_need_list(int64_t ncand, const int64_t *__restrict__ need, con
 
 // Exact test of the listed candidates, one wavefront per 64 consecutive list
 // entries (the list is in cell order).  The wavefront stages each distinct
-// cell of its entries in LDS (walls, slot offsets, slot vertices) and the
-// lanes of that cell test against the staged copy; cells too large for the
-// staging area are tested from global memory.
+// cell of its entries in LDS; each lane then (1) runs the exact test's plane
+// pass (inside: accept; a wall plane beyond the radius by the relative margin:
+// reject), (2) computes the squared distance D to the cell in FP32 about the
+// cell centre (least over the walls seen from outside of d^2 when the foot
+// point is inside the wall polygon, else of the squared distances to the
+// wall's edge segments) and decides when |D - r^2| exceeds a bound on its
+// rounding, tol = 1e-6 (r + 2 rc)^2 (every vector involved is shorter than
+// r + 2 rc, FP32 rounding of D is below 10 u (r + 2 rc)^2), and (3) runs the
+// exact test from the global tables for the rest (D within tol of r^2) and
+// for cells too large for the staging area.
 __global__ void __launch_bounds__(256) k_exact(int64_t n_need, const uint32_t *__restrict__ list,
                                                const uint32_t *__restrict__ cand_c, const uint32_t *__restrict__ cand_p,
                                                const double *__restrict__ xyz, const double *__restrict__ h,
                                                const int64_t *__restrict__ cfo, const int64_t *__restrict__ fvo,
                                                const EdgeRec *__restrict__ edges, const double *__restrict__ plane,
+                                               const double *__restrict__ centre, const double *__restrict__ radii,
                                                int64_t *__restrict__ flag)
 {
-    __shared__ CellLds stage[4];
-    CellLds &L = stage[threadIdx.x >> 6];
+#pragma clang fp contract(off)
+    __shared__ CellFast stage[4];
+    CellFast &L = stage[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = t < n_need;
     int64_t i = 0, c = -1, a = 0;
+    double px = 0.0, py = 0.0, pz = 0.0, r2 = 0.0, r = 0.0;
     if (valid) {
         i = list[t];
         c = cand_c[i];
         a = cand_p[i];
-    }
-    double px = 0.0, py = 0.0, pz = 0.0, r2 = 0.0;
-    if (valid) {
         px = xyz[3 * a];
         py = xyz[3 * a + 1];
         pz = xyz[3 * a + 2];
-        const double r = 2.0 * h[a];
+        r = 2.0 * h[a];
         r2 = r * r;
     }
     bool hit = false;
@@ -332,22 +341,70 @@ __global__ void __launch_bounds__(256) k_exact(int64_t n_need, const uint32_t *_
         todo &= ~__ballot(mine);
         const int64_t j0 = cfo[cc], nf = cfo[cc + 1] - j0;
         const int64_t s0 = fvo[j0], ns = fvo[j0 + nf] - s0;
+        const double gx = centre[3 * cc], gy = centre[3 * cc + 1], gz = centre[3 * cc + 2];
+        bool exact = mine;
         if (nf <= kExactMaxFaces && ns <= kExactMaxSlots) {
             lds_sync_wave();
             for (int q = lane; q < 4 * nf; q += 64) L.pl_[q >> 2][q & 3] = plane[4 * j0 + q];
             for (int q = lane; q <= nf; q += 64) L.so_[q] = (int)(fvo[j0 + q] - s0);
             for (int q = lane; q < ns; q += 64) {
                 const EdgeRec &E = edges[s0 + q];
-                L.v_[q][0] = E.vx;
-                L.v_[q][1] = E.vy;
-                L.v_[q][2] = E.vz;
+                L.v_[q][0] = (float)(E.vx - gx);
+                L.v_[q][1] = (float)(E.vy - gy);
+                L.v_[q][2] = (float)(E.vz - gz);
+                L.e_[q][0] = (float)E.ex;
+                L.e_[q][1] = (float)E.ey;
+                L.e_[q][2] = (float)E.ez;
+                L.m_[q][0] = (float)E.mx;
+                L.m_[q][1] = (float)E.my;
+                L.m_[q][2] = (float)E.mz;
+                L.L_[q] = (float)E.L;
             }
             if (lane == 0) L.nf = (int)nf;
             lds_sync_wave();
-            if (mine) hit = meets_impl(px, py, pz, r2, L);
-        } else if (mine) {
-            hit = cell_meets(px, py, pz, r2, cc, cfo, fvo, edges, plane);
+            if (mine) {
+                exact = false;
+                // (1) the exact test's plane pass, same arithmetic
+                double far = 0.0;
+                bool inside = true;
+                for (int j = 0; j < nf; j++) {
+                    const double d = L.pl_[j][3] - (L.pl_[j][0] * px + L.pl_[j][1] * py + L.pl_[j][2] * pz);
+                    if (d < 0.0) {
+                        inside = false;
+                        if (-d > far) far = -d;
+                    }
+                }
+                if (inside) {
+                    hit = true;
+                } else if (!(far * far > r2 * (1.0 + 1e-9))) {
+                    // (2) screened distance in FP32 about g
+                    const float qx = (float)(px - gx), qy = (float)(py - gy), qz = (float)(pz - gz);
+                    float D = INFINITY;
+                    for (int j = 0; j < (int)nf; j++) {
+                        const double d = L.pl_[j][3] - (L.pl_[j][0] * px + L.pl_[j][1] * py + L.pl_[j][2] * pz);
+                        if (!(d < 0.0)) continue;
+                        bool in_poly = true;
+                        float Dj = INFINITY;
+                        for (int k = L.so_[j]; k < L.so_[j + 1]; k++) {
+                            const float wx = qx - L.v_[k][0], wy = qy - L.v_[k][1], wz = qz - L.v_[k][2];
+                            in_poly = in_poly && fmaf(L.m_[k][0], wx, fmaf(L.m_[k][1], wy, L.m_[k][2] * wz)) >= 0.0f;
+                            const float sp = fmaf(L.e_[k][0], wx, fmaf(L.e_[k][1], wy, L.e_[k][2] * wz));
+                            const float tt = fminf(fmaxf(sp, 0.0f), L.L_[k]);
+                            const float ux = fmaf(-tt, L.e_[k][0], wx), uy = fmaf(-tt, L.e_[k][1], wy),
+                                        uz = fmaf(-tt, L.e_[k][2], wz);
+                            Dj = fminf(Dj, fmaf(ux, ux, fmaf(uy, uy, uz * uz)));
+                        }
+                        D = fminf(D, in_poly ? (float)(d * d) : Dj);
+                    }
+                    const double rr = r + 2.0 * radii[2 * cc + 1];
+                    const double tol = 1e-6 * rr * rr;
+                    if ((double)D < r2 - tol) hit = true;
+                    else if (!((double)D > r2 + tol)) exact = true;
+                }
+            }
         }
+        // (3) the exact test from the global tables
+        if (exact) hit = cell_meets(px, py, pz, r2, cc, cfo, fvo, edges, plane);
     }
     if (valid) flag[i] = hit ? 1 : 0;
 }
@@ -468,7 +525,7 @@ PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, cons
             EM_HIP(hipGetLastError());
             hipLaunchKernelGGL(k_exact, dim3((unsigned)((n_need + 255) / 256)), dim3(256), 0, s, n_need,
                                (const uint32_t *)list, (const uint32_t *)cand_c, (const uint32_t *)cand_p, in.xyz,
-                               in.h, in.cfo, in.fvo, edges, in.plane, flag);
+                               in.h, in.cfo, in.fvo, edges, in.plane, aabb + 6 * nc, aabb + 9 * nc, flag);
             EM_HIP(hipGetLastError());
         }
         hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, cand, (unsigned long long)n_need);
