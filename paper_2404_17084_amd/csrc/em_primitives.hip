@@ -201,24 +201,31 @@ void scan_counts(Workspace &ws, const int64_t *in, int64_t *out, int64_t n, hipS
 }
 
 // ---------------------------------------------------------------- radix sort
+// LSD radix sort with digits of up to 10 bits: a key width of b bits takes
+// ceil(b / 10) passes, the width split evenly between them (18-bit keys: two
+// passes of 9 bits, so the result lands back in the input buffers).
 constexpr int RS_BLOCK = 256;
 constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_BLOCK * RS_ITEMS;
 constexpr int RS_WAVES = RS_BLOCK / 64;
+constexpr int RS_MAX_BITS = 10;
+constexpr int RS_MAX_BUCKETS = 1 << RS_MAX_BITS;
 
 template <typename K>
-__global__ void k_rs_hist(const K *keys, int64_t n, int shift, int64_t nblocks, int64_t *hist)
+__global__ void k_rs_hist(const K *keys, int64_t n, int shift, int rb, int64_t nblocks, int64_t *hist)
 {
-    __shared__ unsigned cnt[256];
-    cnt[threadIdx.x] = 0;
+    __shared__ unsigned cnt[RS_MAX_BUCKETS];
+    const int nb = 1 << rb;
+    for (int t = threadIdx.x; t < nb; t += RS_BLOCK) cnt[t] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const unsigned mask = (unsigned)nb - 1u;
     for (int k = 0; k < RS_ITEMS; k++) {
         int64_t i = base + (int64_t)k * RS_BLOCK + threadIdx.x;
-        if (i < n) atomicAdd(&cnt[(unsigned)(keys[i] >> shift) & 255u], 1u);
+        if (i < n) atomicAdd(&cnt[(unsigned)(keys[i] >> shift) & mask], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+    for (int t = threadIdx.x; t < nb; t += RS_BLOCK) hist[(int64_t)t * nblocks + blockIdx.x] = cnt[t];
 }
 
 // Stable scatter: items of a tile are taken in order, 256 at a time; the rank of
@@ -226,15 +233,19 @@ __global__ void k_rs_hist(const K *keys, int64_t n, int shift, int64_t nblocks, 
 // digits in earlier waves of the chunk) + (equal digits in lower lanes).
 template <typename K>
 __global__ void k_rs_scatter(const K *keys, const uint32_t *vals, K *keys_out, uint32_t *vals_out, int64_t n,
-                             int shift, int64_t nblocks, const int64_t *offsets)
+                             int shift, int rb, int64_t nblocks, const int64_t *offsets)
 {
-    __shared__ int64_t run[256];
-    __shared__ unsigned wcnt[RS_WAVES][256];
+    __shared__ int64_t run[RS_MAX_BUCKETS];
+    __shared__ unsigned wcnt[RS_WAVES][RS_MAX_BUCKETS];
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wave = t >> 6;
-    run[t] = offsets[(int64_t)t * nblocks + blockIdx.x];
-    for (int w = 0; w < RS_WAVES; w++) wcnt[w][t] = 0;
+    const int nb = 1 << rb;
+    const unsigned mask = (unsigned)nb - 1u;
+    for (int q = t; q < nb; q += RS_BLOCK) {
+        run[q] = offsets[(int64_t)q * nblocks + blockIdx.x];
+        for (int w = 0; w < RS_WAVES; w++) wcnt[w][q] = 0;
+    }
     __syncthreads();
     const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     int64_t base = (int64_t)blockIdx.x * RS_TILE;
@@ -243,12 +254,14 @@ __global__ void k_rs_scatter(const K *keys, const uint32_t *vals, K *keys_out, u
         bool valid = i < n;
         K key = valid ? keys[i] : K(0);
         uint32_t val = valid ? vals[i] : 0u;
-        unsigned d = (unsigned)(key >> shift) & 255u;
+        unsigned d = (unsigned)(key >> shift) & mask;
         unsigned long long peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; b++) {
-            unsigned long long bb = __ballot((d >> b) & 1u);
-            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        for (int b = 0; b < RS_MAX_BITS; b++) {
+            if (b < rb) {
+                unsigned long long bb = __ballot((d >> b) & 1u);
+                peers &= ((d >> b) & 1u) ? bb : ~bb;
+            }
         }
         unsigned rank_in_wave = (unsigned)__popcll(peers & lt);
         if (valid && rank_in_wave == 0) wcnt[wave][d] = (unsigned)__popcll(peers);
@@ -260,12 +273,14 @@ __global__ void k_rs_scatter(const K *keys, const uint32_t *vals, K *keys_out, u
             vals_out[dest] = val;
         }
         __syncthreads();
-        unsigned add = 0;
-        for (int w = 0; w < RS_WAVES; w++) {
-            add += wcnt[w][t];
-            wcnt[w][t] = 0;
+        for (int q = t; q < nb; q += RS_BLOCK) {
+            unsigned add = 0;
+            for (int w = 0; w < RS_WAVES; w++) {
+                add += wcnt[w][q];
+                wcnt[w][q] = 0;
+            }
+            run[q] += add;
         }
-        run[t] += add;
         __syncthreads();
     }
 }
@@ -275,20 +290,21 @@ static void radix_sort(Workspace &ws, K *keys, uint32_t *vals, K *keys2, uint32_
                        hipStream_t s)
 {
     if (n <= 1 || bits <= 0) return;
-    int64_t nblocks = (n + RS_TILE - 1) / RS_TILE;
-    int64_t *hist = ws.get<int64_t>(S_SORT_HIST, (size_t)(256 * nblocks) * 2 + 1);
-    int64_t *offs = hist + 256 * nblocks;
+    const int passes = (bits + RS_MAX_BITS - 1) / RS_MAX_BITS;
+    const int rb = (bits + passes - 1) / passes;
+    const int64_t nblocks = (n + RS_TILE - 1) / RS_TILE;
+    int64_t *hist = ws.get<int64_t>(S_SORT_HIST, (size_t)(nblocks << rb) * 2 + 1);
+    int64_t *offs = hist + (nblocks << rb);
     K *src_k = keys, *dst_k = keys2;
     uint32_t *src_v = vals, *dst_v = vals2;
-    int passes = (bits + 7) / 8;
     for (int p = 0; p < passes; p++) {
-        int shift = 8 * p;
-        hipLaunchKernelGGL(k_rs_hist<K>, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, s, src_k, n, shift, nblocks,
+        const int shift = rb * p;
+        hipLaunchKernelGGL(k_rs_hist<K>, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, s, src_k, n, shift, rb, nblocks,
                            hist);
         EM_HIP(hipGetLastError());
-        scan_counts(ws, hist, offs, 256 * nblocks, s);
+        scan_counts(ws, hist, offs, nblocks << rb, s);
         hipLaunchKernelGGL(k_rs_scatter<K>, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, s, src_k, src_v, dst_k,
-                           dst_v, n, shift, nblocks, (const int64_t *)offs);
+                           dst_v, n, shift, rb, nblocks, (const int64_t *)offs);
         EM_HIP(hipGetLastError());
         std::swap(src_k, dst_k);
         std::swap(src_v, dst_v);
