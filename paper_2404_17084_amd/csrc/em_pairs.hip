@@ -205,15 +205,20 @@ __device__ __forceinline__ double box_dist2(const double *bb, double px, double 
 // leaf's cells.  Each lane gets exactly the cells of its own walk, in leaf
 // order; neighbouring particles (consecutive in Morton order) share most of
 // their paths, so the lanes stay busy.
-template <bool FILL>
+template <int MODE>
 __global__ void k_candidates(int64_t n, const double *__restrict__ xyz, const double *__restrict__ h,
                              int64_t n_cells, const double *__restrict__ aabb, const double *__restrict__ nodes,
                              int64_t NL, const uint32_t *__restrict__ cperm, int64_t *__restrict__ ccount,
-                             const int64_t *__restrict__ coffs, uint32_t *__restrict__ cand_c,
-                             uint32_t *__restrict__ cand_p)
+                             const int64_t *__restrict__ coffs, uint32_t *__restrict__ buf, int K,
+                             uint32_t *__restrict__ cand_c, uint32_t *__restrict__ cand_p,
+                             unsigned *__restrict__ max_count)
 {
+    // MODE 0: count every particle's candidates and keep the first K of them in
+    // buf (K per particle); MODE 1: write the candidates past the first K of the
+    // particles that have more, at their final places.
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = a < n;
+    bool active = a < n;
+    if (MODE == 1 && active) active = ccount[a] > K;
     double px = 0.0, py = 0.0, pz = 0.0, r2_loose = -1.0;
     if (active) {
         px = xyz[3 * a];
@@ -222,8 +227,10 @@ __global__ void k_candidates(int64_t n, const double *__restrict__ xyz, const do
         const double r = 2.0 * h[a];
         r2_loose = r * r * (1.0 + 1e-9);
     }
+    if (MODE == 1 && __ballot(active) == 0) return;
     int64_t count = 0;
-    const int64_t out = (FILL && active) ? coffs[a] : 0;
+    const int64_t out = (MODE == 1 && active) ? coffs[a] : 0;
+    uint32_t *mine = buf + (MODE == 0 ? a * (int64_t)K : 0);
     int64_t i = 1;
     for (;;) {
         const bool hit = active && box_dist2(nodes + 6 * i, px, py, pz) <= r2_loose;
@@ -237,7 +244,8 @@ __global__ void k_candidates(int64_t n, const double *__restrict__ xyz, const do
             for (int64_t t = t0; t < t0 + kLeaf && t < n_cells; t++) {
                 const uint32_t c = cperm[t];
                 if (box_dist2(aabb + 6 * (int64_t)c, px, py, pz) > r2_loose) continue;
-                if (FILL) {
+                if (MODE == 0 && count < K) mine[count] = c;
+                if (MODE == 1 && count >= K) {
                     cand_c[out + count] = c;
                     cand_p[out + count] = (uint32_t)a;
                 }
@@ -248,7 +256,30 @@ __global__ void k_candidates(int64_t n, const double *__restrict__ xyz, const do
         if (i == 0) break;
         i += 1;
     }
-    if (!FILL && active) ccount[a] = count;
+    if (MODE == 0) {
+        if (active) ccount[a] = count;
+        unsigned m = (unsigned)(count < 0xffffffffLL ? count : 0xffffffffLL);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o, 64));
+        if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(max_count, m);
+    }
+}
+
+// The first K candidates of every particle from buf to their places in the
+// particle-major candidate list, one wavefront per particle.
+__global__ void k_cand_gather(int64_t n, int K, const int64_t *__restrict__ ccount, const int64_t *__restrict__ coffs,
+                              const uint32_t *__restrict__ buf, uint32_t *__restrict__ cand_c,
+                              uint32_t *__restrict__ cand_p)
+{
+    const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (a >= n) return;
+    const int64_t cnt = ccount[a] < K ? ccount[a] : K;
+    const int64_t o = coffs[a];
+    for (int64_t k = lane; k < cnt; k += 64) {
+        cand_c[o + k] = buf[a * K + k];
+        cand_p[o + k] = (uint32_t)a;
+    }
 }
 
 // Candidates in cell order.  Settled without the exact test: accepted when
@@ -480,26 +511,40 @@ PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, cons
         EM_HIP(hipGetLastError());
     }
 
-    // candidates per particle (tree walk, box tests only)
+    // candidates per particle (tree walk, box tests only): one walk keeps the
+    // first K of each particle's candidates; particles with more walk again
     int64_t *ccount = ws.get<int64_t>(S_PCNT, (size_t)n);
     int64_t *coffs = ws.get<int64_t>(S_CCNT64, (size_t)(n + 1));
+    const int K = (int)std::max<int64_t>(32, std::min<int64_t>(512, (int64_t(1) << 28) / n));
+    uint32_t *cbuf = ws.get<uint32_t>(S_CAND_BUF, (size_t)(n * K));
+    unsigned *cmax = ws.get<unsigned>(S_CAND_MAX, 64);
+    fill_zero_bytes(cmax, sizeof(unsigned), s);
     const unsigned pb = 128;
     const unsigned pg = (unsigned)((n + pb - 1) / pb);
-    hipLaunchKernelGGL(k_candidates<false>, dim3(pg), dim3(pb), 0, s, n, in.xyz, in.h, nc, aabb,
-                       (const double *)nodes, NL, (const uint32_t *)cperm, ccount, (const int64_t *)nullptr,
-                       (uint32_t *)nullptr, (uint32_t *)nullptr);
+    hipLaunchKernelGGL(k_candidates<0>, dim3(pg), dim3(pb), 0, s, n, in.xyz, in.h, nc, aabb, (const double *)nodes,
+                       NL, (const uint32_t *)cperm, ccount, (const int64_t *)nullptr, cbuf, K, (uint32_t *)nullptr,
+                       (uint32_t *)nullptr, cmax);
     EM_HIP(hipGetLastError());
     scan_counts(ws, ccount, coffs, n, s);
     int64_t ncand = 0;
+    unsigned max_cand = 0;
     EM_HIP(hipMemcpyAsync(&ncand, coffs + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    EM_HIP(hipMemcpyAsync(&max_cand, cmax, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     EM_HIP(hipStreamSynchronize(s));
     EM_CHECK(ncand < (int64_t)UINT32_MAX, MAP_ENOMEM, "candidate count exceeds 2^32-1");
     uint32_t *cand_c = ws.get<uint32_t>(S_KEY2, (size_t)(ncand > 0 ? ncand : 1));
     uint32_t *cand_p = ws.get<uint32_t>(S_IOTA, (size_t)(ncand > 0 ? ncand : 1));
-    hipLaunchKernelGGL(k_candidates<true>, dim3(pg), dim3(pb), 0, s, n, in.xyz, in.h, nc, aabb,
-                       (const double *)nodes, NL, (const uint32_t *)cperm, (int64_t *)nullptr,
-                       (const int64_t *)coffs, cand_c, cand_p);
-    EM_HIP(hipGetLastError());
+    if (ncand > 0) {
+        hipLaunchKernelGGL(k_cand_gather, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, K,
+                           (const int64_t *)ccount, (const int64_t *)coffs, (const uint32_t *)cbuf, cand_c, cand_p);
+        EM_HIP(hipGetLastError());
+    }
+    if ((int64_t)max_cand > K) {
+        hipLaunchKernelGGL(k_candidates<1>, dim3(pg), dim3(pb), 0, s, n, in.xyz, in.h, nc, aabb,
+                           (const double *)nodes, NL, (const uint32_t *)cperm, ccount, (const int64_t *)coffs, cbuf, K,
+                           cand_c, cand_p, cmax);
+        EM_HIP(hipGetLastError());
+    }
     // candidates in cell order (stable: particles stay ascending within a cell), then the test
     int64_t *flag = ws.get<int64_t>(S_F_PM, (size_t)(ncand > 0 ? ncand : 1));
     int64_t *fpos = ws.get<int64_t>(S_F, (size_t)(ncand + 1));

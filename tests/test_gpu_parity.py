@@ -139,6 +139,22 @@ def test_ragged_small_clumps(mapper):
         assert (np.abs(r["M"] - o["M"]) / o["M"]).max() < tol
 
 
+def test_wide_supports(mapper):
+    """Particles whose supports cover most cells: more candidate cells than the
+    walk keeps per particle in its first pass, so the overflow walk runs."""
+    say("case: wide supports (candidate overflow)")
+    p, c = synth.workload("uniform", 2048, 25)
+    h = p.h.copy()
+    h[[3, 700, 1500]] = [0.3, 0.45, 0.6]
+    p2 = synth.Particles(p.xyz, p.m, h)
+    o = oracle.map_particles(p2, c)
+    assert np.bincount(o["pair_p"], minlength=p.n)[[700, 1500]].min() > 512
+    for prec, tol in ((em.MAP_FP64, FP64_CELL_REL), (em.MAP_MIXED, MIXED_CELL_REL)):
+        r = _run(mapper, p2, c, prec)
+        assert np.array_equal(r["pair_p"], o["pair_p"]) and np.array_equal(r["pair_c"], o["pair_c"])
+        assert (np.abs(r["M"] - o["M"]) / o["M"]).max() < tol
+
+
 def test_single_cell_fraction_one(mapper):
     say("case: single cell")
     from tests.test_oracle_pins import box_cell
