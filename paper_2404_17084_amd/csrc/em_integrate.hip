@@ -682,39 +682,36 @@ __device__ __forceinline__ void mixed_edge_step(WaveStacks &W, int lane, Work &w
             run_stack<0>(W, nA, lane, false, wk);
         }
     }
-    // inner part: closed-form points at its ends (odd in l: F(ib) - F(ia))
-    float wi0 = 0.f, wi1 = 0.f, wi2 = 0.f;
-    if (has_inner && ib > ia) {
-        if (ib == cb) wi1 += sgnr(cb);
-        else wi2 += 1.0f;
-        if (ia == ca) wi0 -= sgnr(ca);
-        else wi2 += 1.0f;
+    // inner part: closed-form points at its two ends, F(ib) - F(ia) with F odd
+    // in l; an end at +-l1 is the point l1 (weight +1, S = 1), an end of the
+    // edge the point |l| (weight -+sgn l)
+    {
+        const bool inner = has_inner && ib > ia;
+        const bool a_l1 = ia != ca, b_l1 = ib != cb;
+        const float xa = a_l1 ? l1 : fabsf(ca), xb = b_l1 ? l1 : fabsf(cb);
+        const float wa = a_l1 ? 1.0f : -sgnr(ca), wb = b_l1 ? 1.0f : sgnr(cb);
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            const float x = q == 0 ? xa : xb, wt = q == 0 ? wa : wb;
+            const bool at_l1 = q == 0 ? a_l1 : b_l1;
+            const bool want = inner && wt != 0.0f && x > 0.0f;
+            if (__ballot(want) != 0) {
+                const int slot = wave_push(want, nP);
+                if (want) {
+                    W.pnt[0][slot] = r0;
+                    W.pnt[1][slot] = R0;
+                    W.pnt[2][slot] = x;
+                    W.pnt[3][slot] = at_l1 ? 1.0f : sqrt_f32(c2 + x * x);
+                    W.pnt[4][slot] = sg * wt;
+                    W.pnt_o[slot] = (uint8_t)lane;
+                }
+                run_stack<1>(W, nP, lane, false, wk);
+            }
+        }
     }
     // shell parts by quadrature: [ca, ia] and [ib, cb]
     const bool q0 = near && ia > ca, q1 = near && cb > ib;
     const float qa0 = ca, qb0 = ia, qa1 = ib, qb1 = cb, qd0 = has_inner ? 1.0f : c;
-    {
-        const float x0 = fabsf(ca), x1 = fabsf(cb);
-        const bool w0 = live && wi0 != 0.0f && x0 > 0.0f;
-        const bool w1 = live && wi1 != 0.0f && x1 > 0.0f;
-        const bool w2 = live && wi2 != 0.0f;
-#pragma unroll
-        for (int q = 0; q < 3; q++) {
-            const bool want = q == 0 ? w0 : (q == 1 ? w1 : w2);
-            const float x = q == 0 ? x0 : (q == 1 ? x1 : l1);
-            const float wt = q == 0 ? wi0 : (q == 1 ? wi1 : wi2);
-            const int slot = wave_push(want, nP);
-            if (want) {
-                W.pnt[0][slot] = r0;
-                W.pnt[1][slot] = R0;
-                W.pnt[2][slot] = x;
-                W.pnt[3][slot] = q == 2 ? 1.0f : (x == l2 ? 2.0f : sqrt_f32(c2 + x * x));
-                W.pnt[4][slot] = sg * wt;
-                W.pnt_o[slot] = (uint8_t)lane;
-            }
-            run_stack<1>(W, nP, lane, false, wk);
-        }
-    }
     // both shell parts' sub-intervals in one uniform loop
     int n0 = 0, n1 = 0;
     float hl0 = 0.0f, hl1 = 0.0f;
