@@ -149,16 +149,18 @@ int map_set_precision(map_ctx *ctx, int precision);
 /*
  * Launch shape of the integration kernel for one precision (the autotuner's
  * knobs): register budget as resident wavefronts per SIMD (0 = compiler
- * default; FP64 kernel 2..4, mixed kernel 4..6), wavefronts of consecutive
+ * default; FP64 kernels 2..4, mixed kernels 4..6; the mixed task-batch
+ * kernel has budgets for 2, 3 and 6), wavefronts of consecutive
  * pairs taken per queue pop (1..64), persistent workgroups of 256 threads per
  * compute unit (1..64), and the work distribution: 1 = persistent queue of
  * pair tiles, 2 = persistent queue of single-cell tiles, 3 = persistent queue
  * of pair tiles whose edge terms are run as wavefront-wide task batches, 0 =
  * one thread per pair, -1 = clear the explicit setting (back to the tuned
  * table/default).
- * For a given distribution, results are bitwise independent of the other
- * knobs and of scheduling; the distributions are separate kernels and agree
- * to rounding.  map_get_tune reports the shape used for n_pairs pairs.
+ * Untuned default: distribution 3 for both precisions.  For a given
+ * distribution, results are bitwise independent of the other knobs and of
+ * scheduling; the distributions are separate kernels and agree to rounding.
+ * map_get_tune reports the shape used for n_pairs pairs.
  */
 int map_set_tune(map_ctx *ctx, int precision, int waves, int tile_waves, int grid_per_cu, int persistent);
 int map_get_tune(map_ctx *ctx, int precision, int64_t n_pairs, int *waves, int *tile_waves, int *grid_per_cu,

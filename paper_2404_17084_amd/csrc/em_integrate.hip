@@ -499,11 +499,12 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_persistent(int64_t np, c
 // wave-uniform counter, so the pushes and runs are in uniform control flow.
 constexpr int kQ = 128;  // stack capacity: below 64 pending before a push of at most 64
 
+constexpr int kQA = 64;  // angle stack capacity: run before a push that would overflow it
 struct WaveStacks {
-    float ang[3][kQ];  // atan2 arguments R0 (b - a) and R0^2 + a b of seg_angle, weight
-    float pnt[5][kQ];  // r0, R0, x, S, weight (c^2 and c are recomputed, as at the push)
-    float qd[5][kQ];   // r0, c2, mid, half-length, weight
-    uint8_t ang_o[kQ], pnt_o[kQ], qd_o[kQ];  // owner lanes
+    float ang[3][kQA];  // atan2 arguments of the angle (imaginary, real part), weight
+    float pnt[4][kQ];   // r0, R0, x (negated when S = 1), weight (c^2, c and S are recomputed)
+    float qd[5][kQ];    // r0, c2, mid, half-length, weight
+    uint8_t ang_o[kQA], pnt_o[kQ], qd_o[kQ];  // owner lanes
     double acc[64];
 };
 
@@ -518,7 +519,8 @@ __device__ __forceinline__ void run_point(WaveStacks &W, int i, Work &wk)
 {
     const float r0 = W.pnt[0][i], R0 = W.pnt[1][i];
     const float c2 = r0 * r0 + R0 * R0, c = sqrt_f32(c2);
-    const float x = W.pnt[2][i], S = W.pnt[3][i], w = W.pnt[4][i];
+    const float xs = W.pnt[2][i], w = W.pnt[3][i];
+    const float x = fabsf(xs), S = xs < 0.0f ? 1.0f : sqrt_f32(c2 + x * x);
     const Trans<float> t = trans<float>(r0, R0, c2, c, x, S, wk);
     const float v = w * core_inner<float>(t, r0, R0, r0 * r0, c2);
     atomicAdd(&W.acc[W.pnt_o[i]], (double)v);
@@ -669,7 +671,9 @@ __device__ __forceinline__ void mixed_edge_step(WaveStacks &W, int lane, Work &w
     wk.angles += (has_b || has_s) ? 1u : 0u;
     {
         const bool want = has_b && has_s;
-        if (__ballot(want) != 0) {
+        const unsigned long long m = __ballot(want);
+        if (m != 0) {
+            if (nA + __popcll(m) > kQA) run_stack<0>(W, nA, lane, true, wk);
             const int slot = wave_push(want, nA);
             if (want) {
                 const float R02 = R0 * R0;
@@ -700,9 +704,8 @@ __device__ __forceinline__ void mixed_edge_step(WaveStacks &W, int lane, Work &w
                 if (want) {
                     W.pnt[0][slot] = r0;
                     W.pnt[1][slot] = R0;
-                    W.pnt[2][slot] = x;
-                    W.pnt[3][slot] = at_l1 ? 1.0f : sqrt_f32(c2 + x * x);
-                    W.pnt[4][slot] = sg * wt;
+                    W.pnt[2][slot] = at_l1 ? -x : x;
+                    W.pnt[3][slot] = sg * wt;
                     W.pnt_o[slot] = (uint8_t)lane;
                 }
                 run_stack<1>(W, nP, lane, false, wk);
@@ -1265,7 +1268,10 @@ void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &
         const int64_t need = ((np + 63) / 64 + (block / 64) - 1) / (block / 64);
         if (g > need) g = need;
         if (g < 1) g = 1;
-        if (tune.waves >= 3)
+        if (tune.waves >= 6)
+            hipLaunchKernelGGL(k_integrate_queued<6>, dim3((unsigned)g), dim3(block), 0, s, np, ps.pair_p, ps.pair_c,
+                               in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, tile_ctr, fx);
+        else if (tune.waves >= 3)
             hipLaunchKernelGGL(k_integrate_queued<3>, dim3((unsigned)g), dim3(block), 0, s, np, ps.pair_p, ps.pair_c,
                                in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, tile_ctr, fx);
         else
