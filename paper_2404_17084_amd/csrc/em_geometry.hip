@@ -3,6 +3,7 @@
 #include <cmath>
 
 #include "em_internal.h"
+#include "em_wave.h"
 
 namespace em {
 
@@ -88,22 +89,39 @@ void launch_validate(const DevInputs &in, unsigned *flags, hipStream_t s)
     EM_HIP(hipGetLastError());
 }
 
-// One thread per face: the directed edges of the face (counter-clockwise about
-// the outward normal n) with unit direction e, in-plane inward normal m = n x e.
-__global__ void k_edge_table(int64_t n_faces, const int64_t *fvo, const int32_t *fv, const double *plane,
-                             const double *verts, EdgeRec *edges)
+// Directed edges of every face (counter-clockwise about the outward normal
+// n) with unit direction e and in-plane inward normal m = n x e, one record
+// per slot.  A wavefront takes 64 consecutive faces and gives its lanes
+// consecutive slots (coalesced 80-byte record stores); a lane finds its
+// slot's face by binary search in the wavefront's face offsets (faces have
+// at least 3 slots, checked by the structure validation that runs first).
+__global__ void __launch_bounds__(256) k_edge_table(int64_t n_faces, const int64_t *fvo, const int32_t *fv,
+                                                    const double *plane, const double *verts, EdgeRec *edges)
 {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_faces) return;
-    double nx = plane[4 * j], ny = plane[4 * j + 1], nz = plane[4 * j + 2];
-    int64_t s0 = fvo[j], s1 = fvo[j + 1];
-    int64_t cnt = s1 - s0;
-    for (int64_t k = 0; k < cnt; k++) {
-        const double *a = verts + 3 * (int64_t)fv[s0 + k];
-        const double *b = verts + 3 * (int64_t)fv[s0 + (k + 1 == cnt ? 0 : k + 1)];
+    __shared__ int64_t off[4][65];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t j0 = ((int64_t)blockIdx.x * 4 + w) * 64;
+    if (j0 >= n_faces) return;
+    const int nf = (int)(n_faces - j0 < 64 ? n_faces - j0 : 64);
+    if (lane < nf) off[w][lane] = fvo[j0 + lane];
+    if (lane == 0) off[w][nf] = fvo[j0 + nf];
+    lds_sync_wave();
+    const int64_t s_end = off[w][nf];
+    for (int64_t q = off[w][0] + lane; q < s_end; q += 64) {
+        int lo = 0, hi = nf - 1;  // face f with off[f] <= q < off[f + 1]
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[w][mid] <= q) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t j = j0 + lo;
+        const int64_t qn = q + 1 == off[w][lo + 1] ? off[w][lo] : q + 1;
+        const double *a = verts + 3 * (int64_t)fv[q];
+        const double *b = verts + 3 * (int64_t)fv[qn];
+        const double nx = plane[4 * j], ny = plane[4 * j + 1], nz = plane[4 * j + 2];
         double ex = b[0] - a[0], ey = b[1] - a[1], ez = b[2] - a[2];
-        double L = sqrt(ex * ex + ey * ey + ez * ez);
-        double inv = L > 0.0 ? 1.0 / L : 0.0;
+        const double L = sqrt(ex * ex + ey * ey + ez * ez);
+        const double inv = L > 0.0 ? 1.0 / L : 0.0;
         ex *= inv;
         ey *= inv;
         ez *= inv;
@@ -118,7 +136,7 @@ __global__ void k_edge_table(int64_t n_faces, const int64_t *fvo, const int32_t 
         r.mx = ny * ez - nz * ey;
         r.my = nz * ex - nx * ez;
         r.mz = nx * ey - ny * ex;
-        edges[s0 + k] = r;
+        edges[q] = r;
     }
 }
 
@@ -148,6 +166,8 @@ __device__ __forceinline__ double wmax(double v)
 __global__ void k_cell_boxes(int64_t n_cells, const int64_t *cfo, const int64_t *fvo, const int32_t *fv,
                              const double *plane, const double *verts, double *aabb, double *vol_out)
 {
+    // one wavefront per cell, lanes over the cell's slots; a lane finds its
+    // slot's wall by binary search in the wall offsets
     const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (i >= n_cells) return;
@@ -155,29 +175,33 @@ __global__ void k_cell_boxes(int64_t n_cells, const int64_t *cfo, const int64_t 
     double cen[3] = {0.0, 0.0, 0.0};
     double nslot = 0.0, vol = 0.0;
     const int64_t f0 = cfo[i], f1 = cfo[i + 1];
-    const double *ref = verts + 3 * (int64_t)fv[fvo[f0]];
-    for (int64_t j = f0 + lane; j < f1; j += 64) {
-        const int64_t s0 = fvo[j], s1 = fvo[j + 1];
-        const double *v0 = verts + 3 * (int64_t)fv[s0];
-        const double nx = plane[4 * j], ny = plane[4 * j + 1], nz = plane[4 * j + 2], c = plane[4 * j + 3];
-        double area2 = 0.0;
-        for (int64_t s = s0; s < s1; s++) {
-            const double *v = verts + 3 * (int64_t)fv[s];
-            for (int d = 0; d < 3; d++) {
-                lo[d] = fmin(lo[d], v[d]);
-                hi[d] = fmax(hi[d], v[d]);
-                cen[d] += v[d];
-            }
-            nslot += 1.0;
-            if (s + 1 < s1 && s > s0) {
-                const double *w = verts + 3 * (int64_t)fv[s + 1];
-                const double ax = v[0] - v0[0], ay = v[1] - v0[1], az = v[2] - v0[2];
-                const double bx = w[0] - v0[0], by = w[1] - v0[1], bz = w[2] - v0[2];
-                area2 += (ay * bz - az * by) * nx + (az * bx - ax * bz) * ny + (ax * by - ay * bx) * nz;
-            }
+    const int64_t sb = fvo[f0], se = fvo[f1];
+    const double *ref = verts + 3 * (int64_t)fv[sb];
+    for (int64_t q = sb + lane; q < se; q += 64) {
+        int64_t jl = f0, jh = f1 - 1;  // wall j with fvo[j] <= q < fvo[j + 1]
+        while (jl < jh) {
+            const int64_t mid = (jl + jh + 1) >> 1;
+            if (fvo[mid] <= q) jl = mid;
+            else jh = mid - 1;
         }
-        const double height = c - (nx * ref[0] + ny * ref[1] + nz * ref[2]);
-        vol += height * area2 / 6.0;
+        const int64_t j = jl, s0 = fvo[j], s1 = fvo[j + 1];
+        const double *v = verts + 3 * (int64_t)fv[q];
+        for (int d = 0; d < 3; d++) {
+            lo[d] = fmin(lo[d], v[d]);
+            hi[d] = fmax(hi[d], v[d]);
+            cen[d] += v[d];
+        }
+        nslot += 1.0;
+        if (q > s0 && q + 1 < s1) {  // triangle (v_0, v_q, v_q+1) of the wall's fan
+            const double *v0 = verts + 3 * (int64_t)fv[s0];
+            const double *w = verts + 3 * (int64_t)fv[q + 1];
+            const double nx = plane[4 * j], ny = plane[4 * j + 1], nz = plane[4 * j + 2], c = plane[4 * j + 3];
+            const double ax = v[0] - v0[0], ay = v[1] - v0[1], az = v[2] - v0[2];
+            const double bx = w[0] - v0[0], by = w[1] - v0[1], bz = w[2] - v0[2];
+            const double t = (ay * bz - az * by) * nx + (az * bx - ax * bz) * ny + (ax * by - ay * bx) * nz;
+            const double height = c - (nx * ref[0] + ny * ref[1] + nz * ref[2]);
+            vol += height * t / 6.0;
+        }
     }
     double g[3];
     const double ns = wsum(nslot);
@@ -188,13 +212,12 @@ __global__ void k_cell_boxes(int64_t n_cells, const int64_t *cfo, const int64_t 
     }
     vol = wsum(vol);
     double rin = INFINITY, rc2 = 0.0;
-    for (int64_t j = f0 + lane; j < f1; j += 64) {
+    for (int64_t j = f0 + lane; j < f1; j += 64)
         rin = fmin(rin, plane[4 * j + 3] - (plane[4 * j] * g[0] + plane[4 * j + 1] * g[1] + plane[4 * j + 2] * g[2]));
-        for (int64_t s = fvo[j]; s < fvo[j + 1]; s++) {
-            const double *v = verts + 3 * (int64_t)fv[s];
-            const double dx = v[0] - g[0], dy = v[1] - g[1], dz = v[2] - g[2];
-            rc2 = fmax(rc2, dx * dx + dy * dy + dz * dz);
-        }
+    for (int64_t q = sb + lane; q < se; q += 64) {
+        const double *v = verts + 3 * (int64_t)fv[q];
+        const double dx = v[0] - g[0], dy = v[1] - g[1], dz = v[2] - g[2];
+        rc2 = fmax(rc2, dx * dx + dy * dy + dz * dz);
     }
     rin = wmin(rin);
     rc2 = wmax(rc2);
