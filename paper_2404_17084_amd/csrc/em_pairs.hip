@@ -1,15 +1,15 @@
 // Pair search: every (particle a, cell i) whose closed cell lies closer to r_a
 // than 2 h_a, ordered by cell and then particle.
 //
-// Cells are sorted along a Morton curve of their bounding-box centres and
-// grouped 8 per leaf of an implicit complete binary tree of bounding boxes.
-// Each particle walks the tree without a stack (heap indices) and lists the
-// cells whose boxes come within 2h (candidates); then one thread per
-// candidate decides with the exact distance test below, and a scan compacts
-// the pairs.  Counts are scanned into particle offsets, the
-// pairs are written particle-major, and a stable radix sort by cell gives the
-// cell-major order (particles ascending inside a cell) that the integration
-// and the per-cell reduction use.
+// The particles, in storage order, are grouped 8 per leaf of an implicit
+// complete binary tree of the boxes their supports can reach.  Each cell
+// walks the tree without a stack (heap indices) and lists the particles whose
+// support comes within its bounding box (candidates), already in cell-major
+// order with particles ascending.  Cheap ball and box tests settle most
+// candidates, the rest take the exact distance test below (FP32 screening
+// with a rounding bound, then the exact IEEE arithmetic near the threshold),
+// and a scan compacts the pairs.  A stable radix sort of the pairs by
+// particle gives the particle-major view used by the per-particle sums.
 #include <cmath>
 
 #include "em_internal.h"
@@ -17,12 +17,7 @@
 
 namespace em {
 
-constexpr int64_t kLeaf = 8;  // cells per leaf of the bounding-volume tree
-
-struct Box {
-    double lo[3];
-    double inv[3];
-};
+constexpr int64_t kLeaf = 8;  // particles per leaf of the bounding-volume tree
 
 // Exact distance test.  Squared distance from p to the closed convex cell: 0
 // inside; else the least squared distance to a wall polygon that p sees from
@@ -129,41 +124,16 @@ __device__ __noinline__ bool cell_meets(double px, double py, double pz, double 
     return meets_impl(px, py, pz, r2, g);
 }
 
-// Morton code (21 bits per axis) of each cell's bounding-box centre
-__device__ __forceinline__ uint64_t spread21(uint64_t v)
-{
-    v &= 0x1fffffull;
-    v = (v | (v << 32)) & 0x1f00000000ffffull;
-    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
-    v = (v | (v << 8)) & 0x100f00f00f00f00full;
-    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
-    v = (v | (v << 2)) & 0x1249249249249249ull;
-    return v;
-}
-
-__global__ void k_cell_morton(int64_t n_cells, const double *aabb, Box B, uint64_t *key)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_cells) return;
-    uint64_t q[3];
-    for (int d = 0; d < 3; d++) {
-        double cen = 0.5 * (aabb[6 * i + d] + aabb[6 * i + 3 + d]);
-        double t = (cen - B.lo[d]) * B.inv[d] * 2097152.0;
-        t = t < 0.0 ? 0.0 : (t > 2097151.0 ? 2097151.0 : t);
-        q[d] = (uint64_t)t;
-    }
-    key[i] = spread21(q[0]) | (spread21(q[1]) << 1) | (spread21(q[2]) << 2);
-}
 
 // Leaves of the implicit tree: heap nodes [NL, 2NL), leaf j holds the cells
 // cperm[kLeaf*(j-NL) .. +kLeaf).  Empty leaves get an inverted box.
-__global__ void k_leaf_boxes(int64_t n_cells, int64_t NL, const uint32_t *cperm, const double *aabb, double *nodes)
+__global__ void k_leaf_boxes(int64_t n_items, int64_t NL, const uint32_t *perm, const double *aabb, double *nodes)
 {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= NL) return;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int64_t t = kLeaf * j; t < kLeaf * (j + 1) && t < n_cells; t++) {
-        const double *bb = aabb + 6 * (int64_t)cperm[t];
+    for (int64_t t = kLeaf * j; t < kLeaf * (j + 1) && t < n_items; t++) {
+        const double *bb = aabb + 6 * (perm ? (int64_t)perm[t] : t);
         for (int d = 0; d < 3; d++) {
             lo[d] = fmin(lo[d], bb[d]);
             hi[d] = fmax(hi[d], bb[3 + d]);
@@ -173,6 +143,23 @@ __global__ void k_leaf_boxes(int64_t n_cells, int64_t NL, const uint32_t *cperm,
     for (int d = 0; d < 3; d++) {
         o[d] = lo[d];
         o[3 + d] = hi[d];
+    }
+}
+
+// Box of every point a particle's support can reach: x +- 2h (1 + 1e-8), widened
+// by 1e-15 (|x| + 2h) for the rounding of its ends, so that it meets every cell
+// box that the candidate test below accepts.
+__global__ void k_particle_boxes(int64_t n, const double *__restrict__ xyz, const double *__restrict__ h,
+                                 double *__restrict__ pbox)
+{
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const double R = 2.0 * h[a] * (1.0 + 1e-8);
+    for (int d = 0; d < 3; d++) {
+        const double x = xyz[3 * a + d];
+        const double pad = 1e-15 * (fabs(x) + R);
+        pbox[6 * a + d] = (x - R) - pad;
+        pbox[6 * a + 3 + d] = (x + R) + pad;
     }
 }
 
@@ -197,43 +184,51 @@ __device__ __forceinline__ double box_dist2(const double *bb, double px, double 
     return dx * dx + dy * dy + dz * dz;
 }
 
-// FILL = false: count candidate cells per particle; FILL = true: write them.
-// Candidates are the cells whose bounding box comes closer than 2h to the
-// particle.  A wavefront walks the implicit tree (heap indices: children 2i,
-// 2i+1) as one packet: it descends into a node when the node's box meets any
-// lane's ball, and at a leaf each lane whose ball meets the leaf box tests the
-// leaf's cells.  Each lane gets exactly the cells of its own walk, in leaf
-// order; neighbouring particles (consecutive in Morton order) share most of
-// their paths, so the lanes stay busy.
+// Candidates of every cell: the particles whose support ball (radius 2h, with
+// a relative 1e-9 on its square) comes within the cell's bounding box.  The
+// particles form an implicit complete binary tree (heap indices: children 2i,
+// 2i+1) over leaves of 8 consecutive particles, each node holding the box of
+// its particles' reach boxes.  A wavefront of 64 consecutive cells walks it as
+// one packet: it descends into a node when the node's box meets any lane's
+// cell box, and at a leaf each lane whose box meets the leaf box tests the
+// leaf's particles.  Leaves are visited left to right, so each cell lists its
+// particles in ascending order: the candidate list comes out cell-major with
+// particles ascending, with no sort.  Particles stored in a spatially coherent
+// order (Morton, Hilbert, as SPH codes keep them) give tight boxes; any order
+// gives the same candidates.
+// MODE 0 counts every cell's candidates and keeps the first K of them in buf
+// (K per cell); MODE 1 writes the candidates past the first K of the cells that
+// have more, at their final places.
 template <int MODE>
-__global__ void k_candidates(int64_t n, const double *__restrict__ xyz, const double *__restrict__ h,
-                             int64_t n_cells, const double *__restrict__ aabb, const double *__restrict__ nodes,
-                             int64_t NL, const uint32_t *__restrict__ cperm, int64_t *__restrict__ ccount,
+__global__ void k_candidates(int64_t n_cells, const double *__restrict__ aabb, int64_t n,
+                             const double *__restrict__ xyz, const double *__restrict__ h,
+                             const double *__restrict__ nodes, int64_t NL, int64_t *__restrict__ ccount,
                              const int64_t *__restrict__ coffs, uint32_t *__restrict__ buf, int K,
                              uint32_t *__restrict__ cand_c, uint32_t *__restrict__ cand_p,
                              unsigned *__restrict__ max_count)
 {
-    // MODE 0: count every particle's candidates and keep the first K of them in
-    // buf (K per particle); MODE 1: write the candidates past the first K of the
-    // particles that have more, at their final places.
-    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool active = a < n;
-    if (MODE == 1 && active) active = ccount[a] > K;
-    double px = 0.0, py = 0.0, pz = 0.0, r2_loose = -1.0;
-    if (active) {
-        px = xyz[3 * a];
-        py = xyz[3 * a + 1];
-        pz = xyz[3 * a + 2];
-        const double r = 2.0 * h[a];
-        r2_loose = r * r * (1.0 + 1e-9);
-    }
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool active = c < n_cells;
+    if (MODE == 1 && active) active = ccount[c] > K;
     if (MODE == 1 && __ballot(active) == 0) return;
+    double lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
+    if (active) {
+        lo0 = aabb[6 * c];
+        lo1 = aabb[6 * c + 1];
+        lo2 = aabb[6 * c + 2];
+        hi0 = aabb[6 * c + 3];
+        hi1 = aabb[6 * c + 4];
+        hi2 = aabb[6 * c + 5];
+    }
+    const double cb[6] = {lo0, lo1, lo2, hi0, hi1, hi2};
     int64_t count = 0;
-    const int64_t out = (MODE == 1 && active) ? coffs[a] : 0;
-    uint32_t *mine = buf + (MODE == 0 ? a * (int64_t)K : 0);
+    const int64_t out = (MODE == 1 && active) ? coffs[c] : 0;
+    uint32_t *mine = buf + (MODE == 0 ? c * (int64_t)K : 0);
     int64_t i = 1;
     for (;;) {
-        const bool hit = active && box_dist2(nodes + 6 * i, px, py, pz) <= r2_loose;
+        const double *nb = nodes + 6 * i;
+        const bool hit = active && nb[0] <= hi0 && lo0 <= nb[3] && nb[1] <= hi1 && lo1 <= nb[4] && nb[2] <= hi2 &&
+                         lo2 <= nb[5];
         const bool any = __ballot(hit) != 0;
         if (any && i < NL) {
             i = 2 * i;
@@ -241,13 +236,13 @@ __global__ void k_candidates(int64_t n, const double *__restrict__ xyz, const do
         }
         if (hit) {
             const int64_t t0 = kLeaf * (i - NL);
-            for (int64_t t = t0; t < t0 + kLeaf && t < n_cells; t++) {
-                const uint32_t c = cperm[t];
-                if (box_dist2(aabb + 6 * (int64_t)c, px, py, pz) > r2_loose) continue;
-                if (MODE == 0 && count < K) mine[count] = c;
+            for (int64_t t = t0; t < t0 + kLeaf && t < n; t++) {
+                const double r = 2.0 * h[t];
+                if (box_dist2(cb, xyz[3 * t], xyz[3 * t + 1], xyz[3 * t + 2]) > r * r * (1.0 + 1e-9)) continue;
+                if (MODE == 0 && count < K) mine[count] = (uint32_t)t;
                 if (MODE == 1 && count >= K) {
-                    cand_c[out + count] = c;
-                    cand_p[out + count] = (uint32_t)a;
+                    cand_c[out + count] = (uint32_t)c;
+                    cand_p[out + count] = (uint32_t)t;
                 }
                 count++;
             }
@@ -257,7 +252,7 @@ __global__ void k_candidates(int64_t n, const double *__restrict__ xyz, const do
         i += 1;
     }
     if (MODE == 0) {
-        if (active) ccount[a] = count;
+        if (active) ccount[c] = count;
         unsigned m = (unsigned)(count < 0xffffffffLL ? count : 0xffffffffLL);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o, 64));
@@ -265,20 +260,20 @@ __global__ void k_candidates(int64_t n, const double *__restrict__ xyz, const do
     }
 }
 
-// The first K candidates of every particle from buf to their places in the
-// particle-major candidate list, one wavefront per particle.
-__global__ void k_cand_gather(int64_t n, int K, const int64_t *__restrict__ ccount, const int64_t *__restrict__ coffs,
-                              const uint32_t *__restrict__ buf, uint32_t *__restrict__ cand_c,
-                              uint32_t *__restrict__ cand_p)
+// The first K candidates of every cell from buf to their places in the
+// cell-major candidate list, one wavefront per cell.
+__global__ void k_cand_gather(int64_t n_cells, int K, const int64_t *__restrict__ ccount,
+                              const int64_t *__restrict__ coffs, const uint32_t *__restrict__ buf,
+                              uint32_t *__restrict__ cand_c, uint32_t *__restrict__ cand_p)
 {
-    const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (a >= n) return;
-    const int64_t cnt = ccount[a] < K ? ccount[a] : K;
-    const int64_t o = coffs[a];
+    if (c >= n_cells) return;
+    const int64_t cnt = ccount[c] < K ? ccount[c] : K;
+    const int64_t o = coffs[c];
     for (int64_t k = lane; k < cnt; k += 64) {
-        cand_c[o + k] = buf[a * K + k];
-        cand_p[o + k] = (uint32_t)a;
+        cand_c[o + k] = (uint32_t)c;
+        cand_p[o + k] = buf[c * K + k];
     }
 }
 
@@ -483,27 +478,19 @@ PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, cons
         fill_zero_bytes(coff, sizeof(int64_t) * (nc + 1), s);
         return ps;
     }
-    // bounding-volume tree over the cells in Morton order of their box centres
-    Box B;
     for (int d = 0; d < 3; d++) {
-        double ext = in.box[3 + d] - in.box[d];
+        const double ext = in.box[3 + d] - in.box[d];
         EM_CHECK(ext > 0.0 && std::isfinite(ext), MAP_EINVAL, "box has non-positive extent");
-        B.lo[d] = in.box[d];
-        B.inv[d] = 1.0 / ext;
     }
-    uint64_t *ckey = reinterpret_cast<uint64_t *>(ws.get<int64_t>(S_BINKEY, (size_t)nc));
-    uint64_t *ckey2 = reinterpret_cast<uint64_t *>(ws.get<int64_t>(S_BINKEY2, (size_t)nc));
-    uint32_t *cperm = ws.get<uint32_t>(S_BINVAL, (size_t)nc);
-    uint32_t *cperm2 = ws.get<uint32_t>(S_BINVAL2, (size_t)nc);
-    hipLaunchKernelGGL(k_cell_morton, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, nc, aabb, B, ckey);
+    // bounding-volume tree over the particles' reach boxes, leaves of 8 particles in storage order
+    double *pbox = ws.get<double>(S_PBOX, (size_t)(6 * n));
+    hipLaunchKernelGGL(k_particle_boxes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, in.xyz, in.h, pbox);
     EM_HIP(hipGetLastError());
-    fill_iota_u32(cperm, nc, s);
-    radix_sort_u64(ws, ckey, cperm, ckey2, cperm2, nc, 63, s);
-    int64_t nleaf = (nc + kLeaf - 1) / kLeaf, NL = 1;
+    int64_t nleaf = (n + kLeaf - 1) / kLeaf, NL = 1;
     while (NL < nleaf) NL <<= 1;
     double *nodes = ws.get<double>(S_BINOFF_G, (size_t)(12 * NL));
-    hipLaunchKernelGGL(k_leaf_boxes, dim3((unsigned)((NL + 255) / 256)), dim3(256), 0, s, nc, NL,
-                       (const uint32_t *)cperm, aabb, nodes);
+    hipLaunchKernelGGL(k_leaf_boxes, dim3((unsigned)((NL + 255) / 256)), dim3(256), 0, s, n, NL,
+                       (const uint32_t *)nullptr, (const double *)pbox, nodes);
     EM_HIP(hipGetLastError());
     for (int64_t first = NL / 2; first >= 1; first /= 2) {
         hipLaunchKernelGGL(k_parent_boxes, dim3((unsigned)((first + 255) / 256)), dim3(256), 0, s, first, first,
@@ -511,49 +498,45 @@ PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, cons
         EM_HIP(hipGetLastError());
     }
 
-    // candidates per particle (tree walk, box tests only): one walk keeps the
-    // first K of each particle's candidates; particles with more walk again
-    int64_t *ccount = ws.get<int64_t>(S_PCNT, (size_t)n);
-    int64_t *coffs = ws.get<int64_t>(S_CCNT64, (size_t)(n + 1));
-    const int K = (int)std::max<int64_t>(32, std::min<int64_t>(512, (int64_t(1) << 28) / n));
-    uint32_t *cbuf = ws.get<uint32_t>(S_CAND_BUF, (size_t)(n * K));
+    // candidates per cell (tree walk, box tests only), cell-major with
+    // particles ascending: one walk keeps the first K of each cell's
+    // candidates; cells with more walk again
+    int64_t *ccount = ws.get<int64_t>(S_PCNT, (size_t)nc);
+    int64_t *coffs = ws.get<int64_t>(S_CCNT64, (size_t)(nc + 1));
+    const int K = (int)std::max<int64_t>(32, std::min<int64_t>(512, (int64_t(1) << 28) / nc));
+    uint32_t *cbuf = ws.get<uint32_t>(S_CAND_BUF, (size_t)(nc * K));
     unsigned *cmax = ws.get<unsigned>(S_CAND_MAX, 64);
     fill_zero_bytes(cmax, sizeof(unsigned), s);
     const unsigned pb = 128;
-    const unsigned pg = (unsigned)((n + pb - 1) / pb);
-    hipLaunchKernelGGL(k_candidates<0>, dim3(pg), dim3(pb), 0, s, n, in.xyz, in.h, nc, aabb, (const double *)nodes,
-                       NL, (const uint32_t *)cperm, ccount, (const int64_t *)nullptr, cbuf, K, (uint32_t *)nullptr,
-                       (uint32_t *)nullptr, cmax);
+    const unsigned pg = (unsigned)((nc + pb - 1) / pb);
+    hipLaunchKernelGGL(k_candidates<0>, dim3(pg), dim3(pb), 0, s, nc, aabb, n, in.xyz, in.h, (const double *)nodes,
+                       NL, ccount, (const int64_t *)nullptr, cbuf, K, (uint32_t *)nullptr, (uint32_t *)nullptr, cmax);
     EM_HIP(hipGetLastError());
-    scan_counts(ws, ccount, coffs, n, s);
+    scan_counts(ws, ccount, coffs, nc, s);
     int64_t ncand = 0;
     unsigned max_cand = 0;
-    EM_HIP(hipMemcpyAsync(&ncand, coffs + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    EM_HIP(hipMemcpyAsync(&ncand, coffs + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     EM_HIP(hipMemcpyAsync(&max_cand, cmax, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     EM_HIP(hipStreamSynchronize(s));
     EM_CHECK(ncand < (int64_t)UINT32_MAX, MAP_ENOMEM, "candidate count exceeds 2^32-1");
     uint32_t *cand_c = ws.get<uint32_t>(S_KEY2, (size_t)(ncand > 0 ? ncand : 1));
     uint32_t *cand_p = ws.get<uint32_t>(S_IOTA, (size_t)(ncand > 0 ? ncand : 1));
     if (ncand > 0) {
-        hipLaunchKernelGGL(k_cand_gather, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, K,
+        hipLaunchKernelGGL(k_cand_gather, dim3((unsigned)((nc + 3) / 4)), dim3(256), 0, s, nc, K,
                            (const int64_t *)ccount, (const int64_t *)coffs, (const uint32_t *)cbuf, cand_c, cand_p);
         EM_HIP(hipGetLastError());
     }
     if ((int64_t)max_cand > K) {
-        hipLaunchKernelGGL(k_candidates<1>, dim3(pg), dim3(pb), 0, s, n, in.xyz, in.h, nc, aabb,
-                           (const double *)nodes, NL, (const uint32_t *)cperm, ccount, (const int64_t *)coffs, cbuf, K,
-                           cand_c, cand_p, cmax);
+        hipLaunchKernelGGL(k_candidates<1>, dim3(pg), dim3(pb), 0, s, nc, aabb, n, in.xyz, in.h,
+                           (const double *)nodes, NL, ccount, (const int64_t *)coffs, cbuf, K, cand_c, cand_p, cmax);
         EM_HIP(hipGetLastError());
     }
-    // candidates in cell order (stable: particles stay ascending within a cell), then the test
+    // the test (candidates are in cell order)
     int64_t *flag = ws.get<int64_t>(S_F_PM, (size_t)(ncand > 0 ? ncand : 1));
     int64_t *fpos = ws.get<int64_t>(S_F, (size_t)(ncand + 1));
     unsigned long long *cand = reinterpret_cast<unsigned long long *>(counters + C_CANDIDATES);
     if (ncand > 0) {
-        uint32_t *sc2 = ws.get<uint32_t>(S_PERM, (size_t)ncand);
-        uint32_t *sp2 = ws.get<uint32_t>(S_PC_PM, (size_t)ncand);
-        radix_sort_u32(ws, cand_c, cand_p, sc2, sp2, ncand, bits_for((uint64_t)nc - 1), s);
-        int64_t *need = ws.get<int64_t>(S_CCNT64, (size_t)ncand);  // the candidate offsets are no longer needed
+        int64_t *need = ws.get<int64_t>(S_BINCNT, (size_t)ncand);
         int64_t *npos = ws.get<int64_t>(S_BINCNT64, (size_t)ncand + 1);
         const unsigned gq = (unsigned)((ncand + 255) / 256);
         hipLaunchKernelGGL(k_quick, dim3(gq), dim3(256), 0, s, ncand, (const uint32_t *)cand_c,
