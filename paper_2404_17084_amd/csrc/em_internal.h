@@ -71,7 +71,7 @@ enum Slot : int {
     S_F, S_F_PM, S_S, S_MCELL, S_RHO, S_RED,
     S_FIX_ITEMS, S_FIX_VALS, S_FIX_KEY2, S_FIX_VAL2,
     S_SCAN_TMP, S_SORT_HIST, S_TILE_CTR, S_TILE_CNT, S_TILE_OFF, S_TILES,
-    S_CAND_BUF, S_CAND_MAX, S_PBOX,
+    S_CAND_BUF, S_CAND_MAX, S_PBOX, S_NCNT, S_NOFF, S_QCNT, S_ECNT, S_PCNT2,
     S_PSEUDO0, S_PSEUDO1, S_PSEUDO2, S_PSEUDO3, S_PSEUDO4, S_PSEUDO5, S_PSEUDO6, S_PSEUDO7,
     S_PSEUDO8, S_PSEUDO9, S_PSEUDO10, S_PSEUDO11, S_PSEUDO12, S_PSEUDO13, S_PSEUDO14, S_PSEUDO15,
     S_NUM_SLOTS

@@ -196,15 +196,25 @@ __device__ __forceinline__ double box_dist2(const double *bb, double px, double 
 // particles ascending, with no sort.  Particles stored in a spatially coherent
 // order (Morton, Hilbert, as SPH codes keep them) give tight boxes; any order
 // gives the same candidates.
-// MODE 0 counts every cell's candidates and keeps the first K of them in buf
-// (K per cell); MODE 1 writes the candidates past the first K of the cells that
-// have more, at their final places.
+// The walk also settles what it can without the exact test: accepted when
+// the cell's whole bounding box lies within (1 - 1e-6) 2h of the particle, or
+// when the ball about the cell's interior point g (radius rin) comes closer
+// than (1 - 1e-9) 2h; dropped when the ball about g that contains the cell
+// (radius rc) stays (1 + 1e-9) 2h or more away.  The margins exceed the
+// rounding of every distance involved, so these decisions are the exact
+// test's.  The rest are marked for the exact test.
+// MODE 0 counts every cell's kept candidates (kept, marked, accepted) and
+// stores the first K of them in buf (particle index, bit 31 = marked); MODE 1
+// writes the candidates past the first K of the cells that have more, at
+// their final places, with their marks and exact-test list entries.
 template <int MODE>
-__global__ void k_candidates(int64_t n_cells, const double *__restrict__ aabb, int64_t n,
-                             const double *__restrict__ xyz, const double *__restrict__ h,
-                             const double *__restrict__ nodes, int64_t NL, int64_t *__restrict__ ccount,
-                             const int64_t *__restrict__ coffs, uint32_t *__restrict__ buf, int K,
-                             uint32_t *__restrict__ cand_c, uint32_t *__restrict__ cand_p,
+__global__ void k_candidates(int64_t n_cells, const double *__restrict__ aabb, const double *__restrict__ centre,
+                             const double *__restrict__ radii, int64_t n, const double *__restrict__ xyz,
+                             const double *__restrict__ h, const double *__restrict__ nodes, int64_t NL,
+                             int64_t *__restrict__ ccount, int64_t *__restrict__ ncount, int64_t *__restrict__ qcount,
+                             const int64_t *__restrict__ coffs, const int64_t *__restrict__ noffs,
+                             uint32_t *__restrict__ buf, int K, uint32_t *__restrict__ cand_c,
+                             uint32_t *__restrict__ cand_p, uint8_t *__restrict__ flag, uint32_t *__restrict__ list,
                              unsigned *__restrict__ max_count)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -212,6 +222,7 @@ __global__ void k_candidates(int64_t n_cells, const double *__restrict__ aabb, i
     if (MODE == 1 && active) active = ccount[c] > K;
     if (MODE == 1 && __ballot(active) == 0) return;
     double lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
+    double gx = 0.0, gy = 0.0, gz = 0.0, rin = 0.0, rc = 0.0;
     if (active) {
         lo0 = aabb[6 * c];
         lo1 = aabb[6 * c + 1];
@@ -219,10 +230,16 @@ __global__ void k_candidates(int64_t n_cells, const double *__restrict__ aabb, i
         hi0 = aabb[6 * c + 3];
         hi1 = aabb[6 * c + 4];
         hi2 = aabb[6 * c + 5];
+        gx = centre[3 * c];
+        gy = centre[3 * c + 1];
+        gz = centre[3 * c + 2];
+        rin = radii[2 * c];
+        rc = radii[2 * c + 1];
     }
     const double cb[6] = {lo0, lo1, lo2, hi0, hi1, hi2};
-    int64_t count = 0;
+    int64_t count = 0, nmark = 0, nacc = 0;
     const int64_t out = (MODE == 1 && active) ? coffs[c] : 0;
+    const int64_t nout = (MODE == 1 && active) ? noffs[c] : 0;
     uint32_t *mine = buf + (MODE == 0 ? c * (int64_t)K : 0);
     int64_t i = 1;
     for (;;) {
@@ -237,13 +254,26 @@ __global__ void k_candidates(int64_t n_cells, const double *__restrict__ aabb, i
         if (hit) {
             const int64_t t0 = kLeaf * (i - NL);
             for (int64_t t = t0; t < t0 + kLeaf && t < n; t++) {
+                const double px = xyz[3 * t], py = xyz[3 * t + 1], pz = xyz[3 * t + 2];
                 const double r = 2.0 * h[t];
-                if (box_dist2(cb, xyz[3 * t], xyz[3 * t + 1], xyz[3 * t + 2]) > r * r * (1.0 + 1e-9)) continue;
-                if (MODE == 0 && count < K) mine[count] = (uint32_t)t;
+                const double r2 = r * r;
+                if (box_dist2(cb, px, py, pz) > r2 * (1.0 + 1e-9)) continue;
+                const double fx = fmax(fabs(lo0 - px), fabs(hi0 - px));
+                const double fy = fmax(fabs(lo1 - py), fabs(hi1 - py));
+                const double fz = fmax(fabs(lo2 - pz), fabs(hi2 - pz));
+                const double dx = gx - px, dy = gy - py, dz = gz - pz;
+                const double dg = sqrt(dx * dx + dy * dy + dz * dz);
+                const bool ok = fx * fx + fy * fy + fz * fz < r2 * 0.999998 || dg - rin < r * (1.0 - 1e-9);
+                if (!ok && dg - rc >= r * (1.0 + 1e-9)) continue;
+                if (MODE == 0 && count < K) mine[count] = (uint32_t)t | (ok ? 0u : 0x80000000u);
                 if (MODE == 1 && count >= K) {
                     cand_c[out + count] = (uint32_t)c;
                     cand_p[out + count] = (uint32_t)t;
+                    flag[out + count] = ok ? 1 : 0;
+                    if (!ok) list[nout + nmark] = (uint32_t)(out + count);
                 }
+                nmark += ok ? 0 : 1;
+                nacc += ok ? 1 : 0;
                 count++;
             }
         }
@@ -252,7 +282,11 @@ __global__ void k_candidates(int64_t n_cells, const double *__restrict__ aabb, i
         i += 1;
     }
     if (MODE == 0) {
-        if (active) ccount[c] = count;
+        if (active) {
+            ccount[c] = count;
+            ncount[c] = nmark;
+            qcount[c] = nacc;
+        }
         unsigned m = (unsigned)(count < 0xffffffffLL ? count : 0xffffffffLL);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o, 64));
@@ -261,64 +295,76 @@ __global__ void k_candidates(int64_t n_cells, const double *__restrict__ aabb, i
 }
 
 // The first K candidates of every cell from buf to their places in the
-// cell-major candidate list, one wavefront per cell.
+// cell-major candidate list, with their marks and exact-test list entries (in
+// candidate order), one wavefront per cell.
 __global__ void k_cand_gather(int64_t n_cells, int K, const int64_t *__restrict__ ccount,
-                              const int64_t *__restrict__ coffs, const uint32_t *__restrict__ buf,
-                              uint32_t *__restrict__ cand_c, uint32_t *__restrict__ cand_p)
+                              const int64_t *__restrict__ coffs, const int64_t *__restrict__ noffs,
+                              const uint32_t *__restrict__ buf, uint32_t *__restrict__ cand_c,
+                              uint32_t *__restrict__ cand_p, uint8_t *__restrict__ flag, uint32_t *__restrict__ list)
 {
     const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (c >= n_cells) return;
     const int64_t cnt = ccount[c] < K ? ccount[c] : K;
     const int64_t o = coffs[c];
-    for (int64_t k = lane; k < cnt; k += 64) {
-        cand_c[o + k] = (uint32_t)c;
-        cand_p[o + k] = buf[c * K + k];
+    int64_t nl = noffs[c];
+    for (int64_t k0 = 0; k0 < cnt; k0 += 64) {
+        const int64_t k = k0 + lane;
+        const bool valid = k < cnt;
+        const uint32_t e = valid ? buf[c * K + k] : 0u;
+        const bool marked = valid && (e >> 31) != 0;
+        const unsigned long long m = __ballot(marked);
+        if (valid) {
+            cand_c[o + k] = (uint32_t)c;
+            cand_p[o + k] = e & 0x7fffffffu;
+            flag[o + k] = marked ? 0 : 1;
+        }
+        if (marked) {
+            const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            list[nl + below] = (uint32_t)(o + k);
+        }
+        nl += __popcll(m);
     }
 }
 
-// Candidates in cell order.  Settled without the exact test: accepted when
-// the cell's whole bounding box lies within (1 - 1e-6) 2h of the particle, or
-// when the ball about the cell's interior point g inside the cell (radius
-// rin) comes closer than (1 - 1e-9) 2h; rejected when the ball about g that
-// contains the cell (radius rc) stays (1 + 1e-9) 2h or more away.  The
-// margins exceed the rounding of every distance involved, so these decisions
-// are the exact test's.  The rest go through a compacted list to the exact
-// test (one thread each, consecutive threads mostly on one cell).
-__global__ void k_quick(int64_t ncand, const uint32_t *__restrict__ cand_c, const uint32_t *__restrict__ cand_p,
-                        const double *__restrict__ xyz, const double *__restrict__ h,
-                        const double *__restrict__ aabb, const double *__restrict__ centre,
-                        const double *__restrict__ radii, int64_t *__restrict__ flag, int64_t *__restrict__ need)
+// Pairs per cell: accepted by the walk's tests plus accepted by the exact test.
+__global__ void k_pair_counts(int64_t n_cells, const int64_t *__restrict__ qcount, const unsigned *__restrict__ ecount,
+                              int64_t *__restrict__ pcount)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ncand) return;
-    const int64_t c = cand_c[i], a = cand_p[i];
-    const double px = xyz[3 * a], py = xyz[3 * a + 1], pz = xyz[3 * a + 2];
-    const double r = 2.0 * h[a];
-    const double r2 = r * r;
-    const double *bb = aabb + 6 * c;
-    const double fx = fmax(fabs(bb[0] - px), fabs(bb[3] - px));
-    const double fy = fmax(fabs(bb[1] - py), fabs(bb[4] - py));
-    const double fz = fmax(fabs(bb[2] - pz), fabs(bb[5] - pz));
-    const double gx = centre[3 * c] - px, gy = centre[3 * c + 1] - py, gz = centre[3 * c + 2] - pz;
-    const double dg = sqrt(gx * gx + gy * gy + gz * gz);
-    const bool ok = fx * fx + fy * fy + fz * fz < r2 * 0.999998 || dg - radii[2 * c] < r * (1.0 - 1e-9);
-    const bool no = !ok && dg - radii[2 * c + 1] >= r * (1.0 + 1e-9);
-    flag[i] = ok ? 1 : 0;
-    need[i] = (ok || no) ? 0 : 1;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n_cells) pcount[c] = qcount[c] + (int64_t)ecount[c];
 }
+
+// Accepted candidates of each cell to the cell-major pair list (candidate
+// order kept), one wavefront per cell.
+__global__ void k_compact(int64_t n_cells, const int64_t *__restrict__ coffs, const int64_t *__restrict__ coff,
+                          const uint32_t *__restrict__ cand_p, const uint8_t *__restrict__ flag,
+                          uint32_t *__restrict__ pair_c, uint32_t *__restrict__ pair_p)
+{
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (c >= n_cells) return;
+    const int64_t b = coffs[c], e = coffs[c + 1];
+    int64_t o = coff[c];
+    for (int64_t k0 = b; k0 < e; k0 += 64) {
+        const int64_t k = k0 + lane;
+        const bool take = k < e && flag[k] != 0;
+        const unsigned long long m = __ballot(take);
+        if (take) {
+            const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            pair_c[o + below] = (uint32_t)c;
+            pair_p[o + below] = cand_p[k];
+        }
+        o += __popcll(m);
+    }
+}
+
 
 __global__ void k_set_u64(unsigned long long *p, unsigned long long v)
 {
     if (threadIdx.x == 0) *p = v;
 }
 
-__global__ void k_need_list(int64_t ncand, const int64_t *__restrict__ need, const int64_t *__restrict__ npos,
-                            uint32_t *__restrict__ list)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < ncand && need[i]) list[npos[i]] = (uint32_t)i;
-}
 
 // Exact test of the listed candidates, one wavefront per 64 consecutive list
 // entries (the list is in cell order).  The wavefront stages each distinct
@@ -338,7 +384,7 @@ __global__ void __launch_bounds__(256) k_exact(int64_t n_need, const uint32_t *_
                                                const int64_t *__restrict__ cfo, const int64_t *__restrict__ fvo,
                                                const EdgeRec *__restrict__ edges, const double *__restrict__ plane,
                                                const double *__restrict__ centre, const double *__restrict__ radii,
-                                               int64_t *__restrict__ flag)
+                                               uint8_t *__restrict__ flag, unsigned *__restrict__ ecount)
 {
 #pragma clang fp contract(off)
     __shared__ CellFast stage[4];
@@ -432,19 +478,12 @@ __global__ void __launch_bounds__(256) k_exact(int64_t n_need, const uint32_t *_
         // (3) the exact test from the global tables
         if (exact) hit = cell_meets(px, py, pz, r2, cc, cfo, fvo, edges, plane);
     }
-    if (valid) flag[i] = hit ? 1 : 0;
+    if (valid) {
+        flag[i] = hit ? 1 : 0;
+        if (hit) atomicAdd(&ecount[c], 1u);
+    }
 }
 
-__global__ void k_compact(int64_t ncand, const uint32_t *__restrict__ cand_c, const uint32_t *__restrict__ cand_p,
-                          const int64_t *__restrict__ flag, const int64_t *__restrict__ fpos,
-                          uint32_t *__restrict__ pair_c, uint32_t *__restrict__ pair_p)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ncand || !flag[i]) return;
-    const int64_t o = fpos[i];
-    pair_c[o] = cand_c[i];
-    pair_p[o] = cand_p[i];
-}
 
 // Segment offsets of sorted keys: off[v] = first i with keys[i] >= v, v = 0..n_seg.
 __global__ void k_seg_offsets(int64_t n_items, const uint32_t *__restrict__ keys, int64_t n_seg,
@@ -498,87 +537,82 @@ PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, cons
         EM_HIP(hipGetLastError());
     }
 
-    // candidates per cell (tree walk, box tests only), cell-major with
+    // candidates per cell (tree walk with the cheap tests), cell-major with
     // particles ascending: one walk keeps the first K of each cell's
     // candidates; cells with more walk again
     int64_t *ccount = ws.get<int64_t>(S_PCNT, (size_t)nc);
     int64_t *coffs = ws.get<int64_t>(S_CCNT64, (size_t)(nc + 1));
+    int64_t *ncount = ws.get<int64_t>(S_NCNT, (size_t)nc);
+    int64_t *noffs = ws.get<int64_t>(S_NOFF, (size_t)(nc + 1));
+    int64_t *qcount = ws.get<int64_t>(S_QCNT, (size_t)nc);
     const int K = (int)std::max<int64_t>(32, std::min<int64_t>(512, (int64_t(1) << 28) / nc));
     uint32_t *cbuf = ws.get<uint32_t>(S_CAND_BUF, (size_t)(nc * K));
     unsigned *cmax = ws.get<unsigned>(S_CAND_MAX, 64);
     fill_zero_bytes(cmax, sizeof(unsigned), s);
+    const double *centre = aabb + 6 * nc, *radii = aabb + 9 * nc;
     const unsigned pb = 128;
     const unsigned pg = (unsigned)((nc + pb - 1) / pb);
-    hipLaunchKernelGGL(k_candidates<0>, dim3(pg), dim3(pb), 0, s, nc, aabb, n, in.xyz, in.h, (const double *)nodes,
-                       NL, ccount, (const int64_t *)nullptr, cbuf, K, (uint32_t *)nullptr, (uint32_t *)nullptr, cmax);
+    hipLaunchKernelGGL(k_candidates<0>, dim3(pg), dim3(pb), 0, s, nc, aabb, centre, radii, n, in.xyz, in.h,
+                       (const double *)nodes, NL, ccount, ncount, qcount, (const int64_t *)nullptr,
+                       (const int64_t *)nullptr, cbuf, K, (uint32_t *)nullptr, (uint32_t *)nullptr, (uint8_t *)nullptr,
+                       (uint32_t *)nullptr, cmax);
     EM_HIP(hipGetLastError());
     scan_counts(ws, ccount, coffs, nc, s);
-    int64_t ncand = 0;
+    scan_counts(ws, ncount, noffs, nc, s);
+    int64_t ncand = 0, n_need = 0;
     unsigned max_cand = 0;
     EM_HIP(hipMemcpyAsync(&ncand, coffs + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    EM_HIP(hipMemcpyAsync(&n_need, noffs + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     EM_HIP(hipMemcpyAsync(&max_cand, cmax, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     EM_HIP(hipStreamSynchronize(s));
     EM_CHECK(ncand < (int64_t)UINT32_MAX, MAP_ENOMEM, "candidate count exceeds 2^32-1");
     uint32_t *cand_c = ws.get<uint32_t>(S_KEY2, (size_t)(ncand > 0 ? ncand : 1));
     uint32_t *cand_p = ws.get<uint32_t>(S_IOTA, (size_t)(ncand > 0 ? ncand : 1));
+    uint8_t *flag = reinterpret_cast<uint8_t *>(ws.get<uint32_t>(S_F_PM, (size_t)(ncand / 4 + 1)));
+    uint32_t *list = ws.get<uint32_t>(S_BINLIST, (size_t)(n_need > 0 ? n_need : 1));
+    unsigned *ecount = ws.get<unsigned>(S_ECNT, (size_t)nc);
+    fill_zero_bytes(ecount, sizeof(unsigned) * nc, s);
     if (ncand > 0) {
         hipLaunchKernelGGL(k_cand_gather, dim3((unsigned)((nc + 3) / 4)), dim3(256), 0, s, nc, K,
-                           (const int64_t *)ccount, (const int64_t *)coffs, (const uint32_t *)cbuf, cand_c, cand_p);
+                           (const int64_t *)ccount, (const int64_t *)coffs, (const int64_t *)noffs,
+                           (const uint32_t *)cbuf, cand_c, cand_p, flag, list);
         EM_HIP(hipGetLastError());
     }
     if ((int64_t)max_cand > K) {
-        hipLaunchKernelGGL(k_candidates<1>, dim3(pg), dim3(pb), 0, s, nc, aabb, n, in.xyz, in.h,
-                           (const double *)nodes, NL, ccount, (const int64_t *)coffs, cbuf, K, cand_c, cand_p, cmax);
+        hipLaunchKernelGGL(k_candidates<1>, dim3(pg), dim3(pb), 0, s, nc, aabb, centre, radii, n, in.xyz, in.h,
+                           (const double *)nodes, NL, ccount, ncount, qcount, (const int64_t *)coffs,
+                           (const int64_t *)noffs, cbuf, K, cand_c, cand_p, flag, list, cmax);
         EM_HIP(hipGetLastError());
     }
-    // the test (candidates are in cell order)
-    int64_t *flag = ws.get<int64_t>(S_F_PM, (size_t)(ncand > 0 ? ncand : 1));
-    int64_t *fpos = ws.get<int64_t>(S_F, (size_t)(ncand + 1));
+    // the exact test of the marked candidates (listed in candidate order)
+    if (n_need > 0) {
+        hipLaunchKernelGGL(k_exact, dim3((unsigned)((n_need + 255) / 256)), dim3(256), 0, s, n_need,
+                           (const uint32_t *)list, (const uint32_t *)cand_c, (const uint32_t *)cand_p, in.xyz, in.h,
+                           in.cfo, in.fvo, edges, in.plane, centre, radii, flag, ecount);
+        EM_HIP(hipGetLastError());
+    }
     unsigned long long *cand = reinterpret_cast<unsigned long long *>(counters + C_CANDIDATES);
-    if (ncand > 0) {
-        int64_t *need = ws.get<int64_t>(S_BINCNT, (size_t)ncand);
-        int64_t *npos = ws.get<int64_t>(S_BINCNT64, (size_t)ncand + 1);
-        const unsigned gq = (unsigned)((ncand + 255) / 256);
-        hipLaunchKernelGGL(k_quick, dim3(gq), dim3(256), 0, s, ncand, (const uint32_t *)cand_c,
-                           (const uint32_t *)cand_p, in.xyz, in.h, aabb, aabb + 6 * nc, aabb + 9 * nc, flag, need);
-        EM_HIP(hipGetLastError());
-        scan_counts(ws, need, npos, ncand, s);
-        int64_t n_need = 0;
-        EM_HIP(hipMemcpyAsync(&n_need, npos + ncand, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        EM_HIP(hipStreamSynchronize(s));
-        if (n_need > 0) {
-            uint32_t *list = ws.get<uint32_t>(S_BINLIST, (size_t)n_need);
-            hipLaunchKernelGGL(k_need_list, dim3(gq), dim3(256), 0, s, ncand, (const int64_t *)need,
-                               (const int64_t *)npos, list);
-            EM_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_exact, dim3((unsigned)((n_need + 255) / 256)), dim3(256), 0, s, n_need,
-                               (const uint32_t *)list, (const uint32_t *)cand_c, (const uint32_t *)cand_p, in.xyz,
-                               in.h, in.cfo, in.fvo, edges, in.plane, aabb + 6 * nc, aabb + 9 * nc, flag);
-            EM_HIP(hipGetLastError());
-        }
-        hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, cand, (unsigned long long)n_need);
-        EM_HIP(hipGetLastError());
-    }
-    scan_counts(ws, flag, fpos, ncand, s);
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, cand, (unsigned long long)n_need);
+    EM_HIP(hipGetLastError());
+    // pairs per cell, their offsets, and the cell-major pair list
+    int64_t *pcount = ws.get<int64_t>(S_PCNT2, (size_t)nc);
+    hipLaunchKernelGGL(k_pair_counts, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, nc,
+                       (const int64_t *)qcount, (const unsigned *)ecount, pcount);
+    EM_HIP(hipGetLastError());
+    scan_counts(ws, pcount, coff, nc, s);
     int64_t np = 0;
-    EM_HIP(hipMemcpyAsync(&np, fpos + ncand, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    EM_HIP(hipMemcpyAsync(&np, coff + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     EM_HIP(hipStreamSynchronize(s));
     EM_CHECK(np < (int64_t)UINT32_MAX, MAP_ENOMEM, "pair count exceeds 2^32-1");
     ps.n_pairs = np;
     if (np == 0) {
         fill_zero_bytes(poff, sizeof(int64_t) * (n + 1), s);
-        fill_zero_bytes(coff, sizeof(int64_t) * (nc + 1), s);
         return ps;
     }
-    // cell-major pairs and cell offsets
     uint32_t *pair_c = ws.get<uint32_t>(S_PAIR_C, (size_t)np);
     uint32_t *pair_p = ws.get<uint32_t>(S_PAIR_P, (size_t)np);
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand,
-                       (const uint32_t *)cand_c, (const uint32_t *)cand_p, (const int64_t *)flag,
-                       (const int64_t *)fpos, pair_c, pair_p);
-    EM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_seg_offsets, dim3((unsigned)((np + 1 + 255) / 256)), dim3(256), 0, s, np,
-                       (const uint32_t *)pair_c, nc, coff);
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)((nc + 3) / 4)), dim3(256), 0, s, nc, (const int64_t *)coffs,
+                       (const int64_t *)coff, (const uint32_t *)cand_p, (const uint8_t *)flag, pair_c, pair_p);
     EM_HIP(hipGetLastError());
     // particle-major view: stable sort of the cell-major pairs by particle
     uint32_t *pk = ws.get<uint32_t>(S_KEY2, (size_t)np);
