@@ -330,6 +330,15 @@ __device__ __forceinline__ bool needs_fp64(double r0, double R0, double c2)
            (fabs(c2 - 1.0) < e) || (fabs(c2 - 4.0) < 4.0 * e);
 }
 
+// The same test on the FP32 values the terms use (r0, R0 rounded from FP64;
+// the FP32 rounding of c^2 is 2^-24 relative, far inside the 2^-20 margins).
+__device__ __forceinline__ bool needs_fp64_f32(float r0, float R0, float c2)
+{
+    const float e = 9.5367431640625e-07f;  // 2^-20
+    return (R0 * R0 < 9.094947017729282e-13f * c2) || (c2 < 8.673617379884035e-19f) || (fabsf(r0 - 1.0f) < e) ||
+           (fabsf(c2 - 1.0f) < e) || (fabsf(c2 - 4.0f) < 4.0f * e);
+}
+
 // Raw f for one pair.  PREC = MAP_FP64 or MAP_MIXED.  Wall distance, foot
 // point and edge projections are always FP64; in the mixed path the edge
 // terms are FP32 (accumulated in FP64) unless the conditioning test sends the
@@ -538,20 +547,21 @@ __constant__ float kGL4w[2] = {0.6521451548625461f, 0.3478548451374538f};
 __device__ __forceinline__ void run_quad(WaveStacks &W, int i, Work &wk)
 {
     const float r0 = W.qd[0][i], c2 = W.qd[1][i], mid = W.qd[2][i], hl = W.qd[3][i], w = W.qd[4][i];
+    // the numerator (r0+1)(r0 Sigma + V^5) - r0 U^5 as a polynomial in U with
+    // coefficients a0..a5 (a1..a4 = (r0+1) r0 V^(4-k), a0 = (r0+1)(V^5 + r0 V^4), a5 = -r0)
     const float V = 2.0f - r0;
-    const float V2 = V * V, V4 = V2 * V2, V5 = V4 * V;
-    const float rp1 = r0 + 1.0f;
+    const float V2 = V * V, V3 = V2 * V, V4 = V2 * V2;
+    const float t = (r0 + 1.0f) * r0;
+    const float a0 = (r0 + 1.0f) * fmaf(r0, V4, V4 * V), a1 = t * V3, a2 = t * V2, a3 = t * V;
     float acc = 0.0f;
 #pragma unroll
     for (int q = 0; q < 4; q++) {
         const float xq = (q & 1) ? -kGL4x[q >> 1] : kGL4x[q >> 1];
-        const float l = mid + hl * xq;
-        const float S = sqrt_f32(c2 + l * l);
+        const float l = fmaf(hl, xq, mid);
+        const float S = sqrt_f32(fmaf(l, l, c2));
         const float U = 2.0f - S;
-        const float U2 = U * U;
-        const float Sig = (((U + V) * U + V2) * U + V2 * V) * U + V4;
-        const float num = rp1 * (r0 * Sig + V5) - r0 * U2 * U2 * U;
-        acc += kGL4w[q >> 1] * num * rcp32(S * (S + r0));
+        const float num = fmaf(fmaf(fmaf(fmaf(fmaf(-r0, U, t), U, a3), U, a2), U, a1), U, a0);
+        acc = fmaf(kGL4w[q >> 1], num * rcp_f32(S * (S + r0)), acc);
     }
     wk.quads++;
     wk.qpoints += 4;
@@ -619,14 +629,13 @@ __device__ __forceinline__ void mixed_edge_step(WaveStacks &W, int lane, Work &w
         } else {
             const double lad = -(E.ex * wx + E.ey * wy + E.ez * wz) * invh;
             const double lbd = lad + E.L * invh;
-            const double R0d = fabs(rho) * invh;
-            const double c2d = r0d * r0d + R0d * R0d;
-            if (needs_fp64(r0d, R0d, c2d)) {
+            const float R0f = (float)(fabs(rho) * invh);
+            if (needs_fp64_f32(r0, R0f, fmaf(r0, r0, R0f * R0f))) {
                 const unsigned slot = atomicAdd(fx.count, 1u);
                 if (slot < fx.cap) fx.items[slot] = ((uint64_t)k << 32) | (uint64_t)(uint32_t)s;
                 live = false;
             } else {
-                R0 = (float)R0d;
+                R0 = R0f;
                 la = (float)lad;
                 lb = (float)lbd;
                 sg = (rho > 0.0 ? 1.0f : -1.0f) * fsign;
