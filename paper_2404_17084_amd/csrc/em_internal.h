@@ -161,8 +161,6 @@ struct PairSet {
     int64_t n_pairs = 0;
     const uint32_t *pair_c = nullptr;  // cell-major order
     const uint32_t *pair_p = nullptr;
-    const uint32_t *perm = nullptr;    // particle-major position -> cell-major index
-    const int64_t *poff = nullptr;     // particle-major offsets (n+1)
     const int64_t *coff = nullptr;     // cell-major offsets (n_cells+1)
     const uint64_t *tiles = nullptr;   // cell tiles of <= 64 pairs (cell << 32 | index)
     int64_t n_tiles = 0;

@@ -8,8 +8,7 @@
 // order with particles ascending.  Cheap ball and box tests settle most
 // candidates, the rest take the exact distance test below (FP32 screening
 // with a rounding bound, then the exact IEEE arithmetic near the threshold),
-// and a scan compacts the pairs.  A stable radix sort of the pairs by
-// particle gives the particle-major view used by the per-particle sums.
+// and a wavefront per cell compacts the pairs.
 #include <cmath>
 
 #include "em_internal.h"
@@ -496,24 +495,14 @@ __global__ void k_seg_offsets(int64_t n_items, const uint32_t *__restrict__ keys
     for (int64_t v = prev + 1; v <= cur; v++) off[v] = i;
 }
 
-static int bits_for(uint64_t maxval)
-{
-    int b = 1;
-    while (b < 64 && (maxval >> b) != 0) b++;
-    return b;
-}
-
 PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, const EdgeRec *edges,
                     int64_t *counters, hipStream_t s)
 {
     PairSet ps;
     const int64_t n = in.n, nc = in.n_cells;
-    int64_t *poff = ws.get<int64_t>(S_POFF, (size_t)n + 1);
     int64_t *coff = ws.get<int64_t>(S_COFF, (size_t)nc + 1);
-    ps.poff = poff;
     ps.coff = coff;
     if (n == 0 || nc == 0) {
-        fill_zero_bytes(poff, sizeof(int64_t) * (n + 1), s);
         fill_zero_bytes(coff, sizeof(int64_t) * (nc + 1), s);
         return ps;
     }
@@ -605,28 +594,14 @@ PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, cons
     EM_HIP(hipStreamSynchronize(s));
     EM_CHECK(np < (int64_t)UINT32_MAX, MAP_ENOMEM, "pair count exceeds 2^32-1");
     ps.n_pairs = np;
-    if (np == 0) {
-        fill_zero_bytes(poff, sizeof(int64_t) * (n + 1), s);
-        return ps;
-    }
+    if (np == 0) return ps;
     uint32_t *pair_c = ws.get<uint32_t>(S_PAIR_C, (size_t)np);
     uint32_t *pair_p = ws.get<uint32_t>(S_PAIR_P, (size_t)np);
     hipLaunchKernelGGL(k_compact, dim3((unsigned)((nc + 3) / 4)), dim3(256), 0, s, nc, (const int64_t *)coffs,
                        (const int64_t *)coff, (const uint32_t *)cand_p, (const uint8_t *)flag, pair_c, pair_p);
     EM_HIP(hipGetLastError());
-    // particle-major view: stable sort of the cell-major pairs by particle
-    uint32_t *pk = ws.get<uint32_t>(S_KEY2, (size_t)np);
-    uint32_t *perm = ws.get<uint32_t>(S_PERM, (size_t)np);
-    EM_HIP(hipMemcpyAsync(pk, pair_p, sizeof(uint32_t) * np, hipMemcpyDeviceToDevice, s));
-    fill_iota_u32(perm, np, s);
-    radix_sort_u32(ws, pk, perm, ws.get<uint32_t>(S_IOTA, (size_t)np), ws.get<uint32_t>(S_PC_PM, (size_t)np), np,
-                   bits_for((uint64_t)n - 1), s);
-    hipLaunchKernelGGL(k_seg_offsets, dim3((unsigned)((np + 1 + 255) / 256)), dim3(256), 0, s, np,
-                       (const uint32_t *)pk, n, poff);
-    EM_HIP(hipGetLastError());
     ps.pair_c = pair_c;
     ps.pair_p = pair_p;
-    ps.perm = perm;
     return ps;
 }
 

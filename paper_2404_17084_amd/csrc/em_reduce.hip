@@ -1,7 +1,8 @@
 // Reductions of Eq. (3): per-particle sums S_a (sum-to-one normalisation),
 // per-cell masses M_i = sum_a m_a f_ai / S_a and densities rho_i = M_i / V_i.
-// One wavefront per particle or cell, lanes strided over the segment, a fixed
-// butterfly to combine lanes: the result does not depend on scheduling.
+// S_a is summed in 2^-52 fixed point with integer atomics (exact, so the
+// result does not depend on the order of the additions); the cell sums use one
+// wavefront per cell, lanes strided over the segment and a fixed butterfly.
 #include <cmath>
 
 #include "em_internal.h"
@@ -24,16 +25,24 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// S_a over the particle's pairs in cell order (perm: particle-major position -> cell-major index)
-__global__ void k_particle_sum(int64_t n, const int64_t *poff, const uint32_t *perm, const double *f, double *S)
+// S_a: every pair adds round(f 2^52) to its particle's 64-bit counter (each
+// term rounded by at most 2^-53, the sum exact), then the counters become
+// doubles in place.
+__global__ void k_particle_sum(int64_t np, const uint32_t *__restrict__ pair_p, const double *__restrict__ f,
+                               unsigned long long *__restrict__ acc)
 {
-    const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    const long long q = __double2ll_rn(f[k] * 4503599627370496.0);
+    atomicAdd(&acc[pair_p[k]], (unsigned long long)q);
+}
+
+__global__ void k_fixed_to_double(int64_t n, double *S)
+{
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= n) return;
-    double v = 0.0;
-    for (int64_t q = poff[a] + lane; q < poff[a + 1]; q += 64) v += f[perm[q]];
-    v = wave_sum(v);
-    if (lane == 0) S[a] = v;
+    const long long q = reinterpret_cast<const long long *>(S)[a];
+    S[a] = (double)q * 2.220446049250313e-16;
 }
 
 __global__ void k_cell_mass(int64_t nc, const int64_t *coff, const uint32_t *pair_p, const double *f,
@@ -128,9 +137,13 @@ void launch_reduce(const DevInputs &in, const PairSet &ps, const double *f, doub
                    double *rho, double *red, unsigned *flags, hipStream_t s)
 {
     const int64_t n = in.n, nc = in.n_cells;
-    if (n > 0)
-        hipLaunchKernelGGL(k_particle_sum, dim3((unsigned)((n * 64 + 255) / 256)), dim3(256), 0, s, n, ps.poff,
-                           ps.perm, f, S);
+    if (n > 0) {
+        fill_zero_bytes(S, sizeof(double) * n, s);
+        if (ps.n_pairs > 0)
+            hipLaunchKernelGGL(k_particle_sum, dim3((unsigned)((ps.n_pairs + 255) / 256)), dim3(256), 0, s,
+                               ps.n_pairs, ps.pair_p, f, reinterpret_cast<unsigned long long *>(S));
+        hipLaunchKernelGGL(k_fixed_to_double, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, S);
+    }
     if (nc > 0)
         hipLaunchKernelGGL(k_cell_mass, dim3((unsigned)((nc * 64 + 255) / 256)), dim3(256), 0, s, nc, ps.coff,
                            ps.pair_p, f, (const double *)S, in.m, in.vol, M, rho);
