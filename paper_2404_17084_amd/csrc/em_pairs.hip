@@ -106,10 +106,9 @@ struct CellGlobal {
 constexpr int kExactMaxFaces = 40, kExactMaxSlots = 160;
 struct CellFast {
     double pl_[kExactMaxFaces][4];
-    float v_[kExactMaxSlots][3];
-    float e_[kExactMaxSlots][3];
-    float m_[kExactMaxSlots][3];
-    float L_[kExactMaxSlots];
+    float4 a_[kExactMaxSlots];  // vertex - g (x, y, z), length
+    float4 b_[kExactMaxSlots];  // e (x, y, z), m.x
+    float2 c_[kExactMaxSlots];  // m.y, m.z
     int so_[kExactMaxFaces + 1];
     int nf;
 };
@@ -420,16 +419,9 @@ __global__ void __launch_bounds__(256) k_exact(int64_t n_need, const uint32_t *_
             for (int q = lane; q <= nf; q += 64) L.so_[q] = (int)(fvo[j0 + q] - s0);
             for (int q = lane; q < ns; q += 64) {
                 const EdgeRec &E = edges[s0 + q];
-                L.v_[q][0] = (float)(E.vx - gx);
-                L.v_[q][1] = (float)(E.vy - gy);
-                L.v_[q][2] = (float)(E.vz - gz);
-                L.e_[q][0] = (float)E.ex;
-                L.e_[q][1] = (float)E.ey;
-                L.e_[q][2] = (float)E.ez;
-                L.m_[q][0] = (float)E.mx;
-                L.m_[q][1] = (float)E.my;
-                L.m_[q][2] = (float)E.mz;
-                L.L_[q] = (float)E.L;
+                L.a_[q] = make_float4((float)(E.vx - gx), (float)(E.vy - gy), (float)(E.vz - gz), (float)E.L);
+                L.b_[q] = make_float4((float)E.ex, (float)E.ey, (float)E.ez, (float)E.mx);
+                L.c_[q] = make_float2((float)E.my, (float)E.mz);
             }
             if (lane == 0) L.nf = (int)nf;
             lds_sync_wave();
@@ -438,10 +430,12 @@ __global__ void __launch_bounds__(256) k_exact(int64_t n_need, const uint32_t *_
                 // (1) the exact test's plane pass, same arithmetic
                 double far = 0.0;
                 bool inside = true;
+                unsigned long long seen = 0;  // walls seen from outside
                 for (int j = 0; j < nf; j++) {
                     const double d = L.pl_[j][3] - (L.pl_[j][0] * px + L.pl_[j][1] * py + L.pl_[j][2] * pz);
                     if (d < 0.0) {
                         inside = false;
+                        seen |= 1ull << j;
                         if (-d > far) far = -d;
                     }
                 }
@@ -451,18 +445,19 @@ __global__ void __launch_bounds__(256) k_exact(int64_t n_need, const uint32_t *_
                     // (2) screened distance in FP32 about g
                     const float qx = (float)(px - gx), qy = (float)(py - gy), qz = (float)(pz - gz);
                     float D = INFINITY;
-                    for (int j = 0; j < (int)nf; j++) {
+                    for (unsigned long long sm = seen; sm != 0; sm &= sm - 1) {
+                        const int j = __builtin_ctzll(sm);
                         const double d = L.pl_[j][3] - (L.pl_[j][0] * px + L.pl_[j][1] * py + L.pl_[j][2] * pz);
-                        if (!(d < 0.0)) continue;
                         bool in_poly = true;
                         float Dj = INFINITY;
                         for (int k = L.so_[j]; k < L.so_[j + 1]; k++) {
-                            const float wx = qx - L.v_[k][0], wy = qy - L.v_[k][1], wz = qz - L.v_[k][2];
-                            in_poly = in_poly && fmaf(L.m_[k][0], wx, fmaf(L.m_[k][1], wy, L.m_[k][2] * wz)) >= 0.0f;
-                            const float sp = fmaf(L.e_[k][0], wx, fmaf(L.e_[k][1], wy, L.e_[k][2] * wz));
-                            const float tt = fminf(fmaxf(sp, 0.0f), L.L_[k]);
-                            const float ux = fmaf(-tt, L.e_[k][0], wx), uy = fmaf(-tt, L.e_[k][1], wy),
-                                        uz = fmaf(-tt, L.e_[k][2], wz);
+                            const float4 A = L.a_[k], B = L.b_[k];
+                            const float2 C = L.c_[k];
+                            const float wx = qx - A.x, wy = qy - A.y, wz = qz - A.z;
+                            in_poly = in_poly && fmaf(B.w, wx, fmaf(C.x, wy, C.y * wz)) >= 0.0f;
+                            const float sp = fmaf(B.x, wx, fmaf(B.y, wy, B.z * wz));
+                            const float tt = fminf(fmaxf(sp, 0.0f), A.w);
+                            const float ux = fmaf(-tt, B.x, wx), uy = fmaf(-tt, B.y, wy), uz = fmaf(-tt, B.z, wz);
                             Dj = fminf(Dj, fmaf(ux, ux, fmaf(uy, uy, uz * uz)));
                         }
                         D = fminf(D, in_poly ? (float)(d * d) : Dj);
