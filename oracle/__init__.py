@@ -73,6 +73,7 @@ def _load():
             getattr(lib, nm).argtypes = [i64, vp, vp, ctypes.POINTER(_Cells), i64, vp, vp, vp, i64]
         lib.orc_pair_fractions.argtypes = [i, vp, vp, ctypes.POINTER(_Cells), i64, vp, vp, vp]
         lib.orc_reduce.argtypes = [i64, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp]
+        lib.orc_map_back.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp]
         lib.orc_num_threads.restype = i
         if hasattr(lib, "orp_pseudo"):
             u64 = ctypes.c_uint64
@@ -249,6 +250,19 @@ def map_particles(particles, cells, profile: int = M4):
     f = pair_fractions(particles.xyz, particles.h, cells, pp, pc, profile)
     S, M, rho = reduce(particles.m, cells.cell_volume, cells.n_cells, pp, pc, f)
     return {"pair_p": pp, "pair_c": pc, "f": f, "S": S, "M": M, "rho": rho}
+
+
+def map_back(q_cell, mapping, n):
+    """Inverse mapping, Eq. (4): particle values from cell values with the pair
+    weights of ``mapping`` (a ``map_particles`` result) normalised by S_a."""
+    pp = np.ascontiguousarray(mapping["pair_p"], dtype=np.int32)
+    pc = np.ascontiguousarray(mapping["pair_c"], dtype=np.int32)
+    f = _f64(mapping["f"])
+    S = _f64(mapping["S"])
+    q = _f64(q_cell)
+    out = np.zeros(n)
+    _load().orc_map_back(n, pp.size, _p(pp), _p(pc), _p(f), _p(S), _p(q), _p(out))
+    return out
 
 
 def num_threads() -> int:

@@ -616,6 +616,21 @@ void orc_reduce(int64_t n, const double *m, int64_t n_cells, const double *vol, 
     for (int64_t i = 0; i < n_cells; i++) rho[i] = (vol && vol[i] > 0.0) ? M[i] / vol[i] : 0.0;
 }
 
+/*
+ * Inverse mapping (Sec. II-B, Eq. (4)): a particle value from the cell values
+ * weighted by the particle's kernel integrals over the cells, with the same
+ * sum-to-one normalisation as the forward mapping,
+ *   q_a = (sum over pairs of particle a of q_i f) / S_a,   0 when S_a = 0,
+ * so that sum_a m_a q_a = sum_i q_i M_i.  Plain sequential sums in pair order.
+ */
+void orc_map_back(int64_t n, int64_t npairs, const int32_t *pair_p, const int32_t *pair_c, const double *f,
+                  const double *S, const double *q_cell, double *q_part)
+{
+    for (int64_t a = 0; a < n; a++) q_part[a] = 0.0;
+    for (int64_t q = 0; q < npairs; q++) q_part[pair_p[q]] += q_cell[pair_c[q]] * f[q];
+    for (int64_t a = 0; a < n; a++) q_part[a] = S[a] > 0.0 ? q_part[a] / S[a] : 0.0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
