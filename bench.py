@@ -162,6 +162,29 @@ def pseudo_leg(em, steps: int, warmup: int):
             "mass_err_pseudo": abs(ms["mass_out"] - ms["mass_in"])}
 
 
+def back_leg(em, mapper, p, M, nc, steps):
+    """Inverse mapping (Eq. (4)) with the pairs of the last (mixed) mapping: a
+    random cell field gathered to the particles, device buffers."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    q = torch.rand(nc, dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(7))
+    out = torch.zeros(p.n, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    em.map_back(mapper.ctx, q, out)  # builds the particle-major view of the pairs
+    torch.cuda.synchronize()
+    first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        em.map_back(mapper.ctx, q, out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    mq = float(torch.dot(torch.from_numpy(p.m).to(dev), out))
+    mref = float(torch.dot(q, M))
+    return {"ms_first_call": 1e3 * first, "ms": 1e3 * dt, "mass_rel_err": abs(mq - mref) / abs(mref)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -234,6 +257,8 @@ def main():
                          "n_edge_visits": stats[-1]["n_edge_visits"], "n_candidates": stats[-1]["n_candidates"]}
         Ms[name] = M.cpu().numpy().copy()
         print(f"bench: {name}: {results[name]}", file=sys.stderr, flush=True)
+    back = back_leg(em, mapper, p, M, nc, args.steps)
+    print(f"bench: inverse mapping: {back}", file=sys.stderr, flush=True)
     mapper.close()
     rel = np.abs(Ms["mixed"] - Ms["fp64"]) / np.abs(Ms["fp64"])
 
@@ -264,6 +289,7 @@ def main():
         "mass_err_mixed": mx["mass_err"],
         "stages_ms_mixed": {k: mx[k] for k in ("ms_setup", "ms_pairs", "ms_integrate", "ms_reduce")},
         "launch_shape": tuned,
+        "inverse_mapping": back,
         "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32, "unit": "TFLOP/s", "frac": ach / PEAK_FP32,
                      "traffic": measured_traffic()},
     }

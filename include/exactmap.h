@@ -190,6 +190,24 @@ int map_pairs(map_ctx *ctx, const map_particles_in *p, const map_cells_in *c, in
 int map_particles(map_ctx *ctx, const map_particles_in *p, const map_cells_in *c, map_out *out);
 
 /*
+ * Inverse mapping, Sec. II-B Eq. (4): particle values from cell values with
+ * the pair weights of this context's last successful map_particles call,
+ * normalised as in the forward mapping,
+ *   q_a = sum_i q_i f_ai / S_a          (0 for a particle that meets no cell),
+ * so that sum_a m_a q_a = sum_i q_i M_i (the mapped quantity's mass is kept).
+ * cell_values: n_cells doubles of that mapping's cells (host or device memory,
+ * mem_kind, borrowed); particle_values: n doubles written in cell-index order
+ * of summation per particle (out_mem_kind; caller-owned).  The first call
+ * after a mapping also builds the particle-major view of its pairs (a stable
+ * sort, kept until the next call that reuses the context's workspace).
+ * Errors: MAP_EINVAL when no mapping of this context can be inverted (none
+ * yet, or map_pairs, map_pseudo, map_autotune or a failed map_particles ran
+ * since), for NULL buffers with nonzero counts or a bad mem_kind.  Values are
+ * not checked: a non-finite cell value gives non-finite particle values.
+ */
+int map_back(map_ctx *ctx, const double *cell_values, int mem_kind, double *particle_values, int out_mem_kind);
+
+/*
  * Pseudo-particles (Sec. III): the gravity-tree front end that lowers the
  * resolution away from the ionising sources before the mapping.
  *

@@ -117,6 +117,7 @@ _SIGS = {
                           c_i64]),
     "map_particles": (c_int, [c_vp, ctypes.POINTER(map_particles_in), ctypes.POINTER(map_cells_in),
                               ctypes.POINTER(map_out)]),
+    "map_back": (c_int, [c_vp, c_vp, c_int, c_vp, c_int]),
     "map_submit": (c_int, [c_vp, ctypes.POINTER(map_particles_in), ctypes.POINTER(map_cells_in),
                            ctypes.POINTER(map_out), ctypes.POINTER(c_u64)]),
     "map_poll": (c_int, [c_vp, c_u64, c_i64, ctypes.POINTER(c_int)]),
@@ -311,8 +312,37 @@ def map_particles(ctx, xyz, m, h, cells, cell_mass=None, cell_density=None, frac
             cap = int(x.shape[0]) if cap == 0 else min(cap, int(x.shape[0]))
     O = map_out(_ptr(cell_mass), _ptr(cell_density), _ptr(frac_sum_raw), _ptr(pair_frac), _ptr(pair_p),
                 _ptr(pair_c), cap, kind, ctypes.pointer(st))
+    _last_n.pop(_ctx_key(ctx), None)
     _check(ctx, lib.map_particles(ctx, ctypes.byref(P), ctypes.byref(C), ctypes.byref(O)))
+    _last_n[_ctx_key(ctx)] = int(P.n)
     return st.as_dict()
+
+
+def map_back(ctx, cell_values, out=None):
+    """Inverse mapping (Eq. (4)) with the pairs of the context's last map_particles:
+    particle values from cell values.  cell_values: numpy or torch CUDA float64;
+    out: a preallocated array of the particle count (numpy or torch CUDA), or
+    None for a new numpy array (its length is the last mapping's particle count)."""
+    lib = load()
+    if _is_torch(cell_values):
+        q = cell_values.contiguous()
+    else:
+        q = np.ascontiguousarray(cell_values, dtype=np.float64)
+    if out is None:
+        n = _last_n.get(_ctx_key(ctx))
+        if n is None:
+            raise MapError(MAP_EINVAL, "map_back: no mapping of this context to invert")
+        out = np.zeros(n)
+    _check(ctx, lib.map_back(ctx, _ptr(q), _kind(q), _ptr(out), _kind(out)))
+    return out
+
+
+# particle count of each context's last map_particles call (size of map_back's result)
+_last_n = {}
+
+
+def _ctx_key(ctx):
+    return ctx.value if isinstance(ctx, ctypes.c_void_p) else int(ctx)
 
 
 # Served jobs: references the library may still write to, kept until the job is reported finished.
@@ -405,6 +435,10 @@ class Mapper:
 
     def set_precision(self, precision):
         map_set_precision(self.ctx, precision)
+
+    def back(self, cell_values, out=None):
+        """Inverse mapping with the pairs of this mapper's last map()."""
+        return map_back(self.ctx, cell_values, out)
 
     def pseudo(self, particles, box, sources, **kw):
         return map_pseudo(self.ctx, particles.xyz, particles.m, particles.h, box, sources, **kw)

@@ -302,6 +302,11 @@ void run_mapping(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cel
         local.ms_total = t;
     }
     if (out->stats) *out->stats = local;
+    C.back.valid = true;
+    C.back.have_view = false;
+    C.back.n = js.in.n;
+    C.back.n_cells = js.in.n_cells;
+    C.back.n_pairs = js.ps.n_pairs;
 }
 
 }  // namespace em
@@ -422,6 +427,7 @@ int map_pairs(map_ctx *h, const map_particles_in *p, const map_cells_in *c, int6
 {
     Ctx *C = reinterpret_cast<Ctx *>(h);
     API_BODY(C, {
+        C->back.valid = false;
         EM_CHECK(n_pairs, MAP_EINVAL, "n_pairs is null");
         EM_CHECK(capacity >= 0, MAP_EINVAL, "negative capacity");
         hipStream_t s = C->stream;
@@ -456,9 +462,47 @@ int map_particles(map_ctx *h, const map_particles_in *p, const map_cells_in *c, 
 {
     Ctx *C = reinterpret_cast<Ctx *>(h);
     API_BODY(C, {
+        C->back.valid = false;
         EM_CHECK(out, MAP_EINVAL, "null output descriptor");
         EM_CHECK(out->mem_kind == MAP_MEM_HOST || out->mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad output mem_kind");
         run_mapping(*C, C->ws, p, c, out, C->precision, C->stream, true);
+    });
+}
+
+int map_back(map_ctx *h, const double *cell_values, int mem_kind, double *particle_values, int out_mem_kind)
+{
+    Ctx *C = reinterpret_cast<Ctx *>(h);
+    API_BODY(C, {
+        EM_CHECK(C->back.valid, MAP_EINVAL,
+                 "no mapping to invert: map_back uses the pairs of the last successful map_particles call of this "
+                 "context, and another call has run since or none has");
+        EM_CHECK(mem_kind == MAP_MEM_HOST || mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad input mem_kind");
+        EM_CHECK(out_mem_kind == MAP_MEM_HOST || out_mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad output mem_kind");
+        const int64_t n = C->back.n;
+        const int64_t nc = C->back.n_cells;
+        const int64_t np = C->back.n_pairs;
+        EM_CHECK(nc == 0 || cell_values, MAP_EINVAL, "null cell values");
+        EM_CHECK(n == 0 || particle_values, MAP_EINVAL, "null particle values");
+        hipStream_t s = C->stream;
+        Workspace &ws = C->ws;
+        if (n > 0) {
+            uint32_t *perm = ws.get<uint32_t>(S_PERM, (size_t)(np > 0 ? np : 1));
+            int64_t *poff = ws.get<int64_t>(S_POFF, (size_t)n + 1);
+            const uint32_t *pair_p = ws.get<uint32_t>(S_PAIR_P, (size_t)(np > 0 ? np : 1));
+            const uint32_t *pair_c = ws.get<uint32_t>(S_PAIR_C, (size_t)(np > 0 ? np : 1));
+            const double *f = ws.get<double>(S_F, (size_t)(np > 0 ? np : 1));
+            const double *S = ws.get<double>(S_S, (size_t)n);
+            if (!C->back.have_view) {
+                build_particle_view(ws, pair_p, np, n, perm, poff, s);
+                C->back.have_view = true;
+            }
+            const double *q = stage(ws, S_BACK_IN, cell_values, nc, mem_kind, s);
+            double *out = out_mem_kind == MAP_MEM_DEVICE ? particle_values : ws.get<double>(S_BACK_OUT, (size_t)n);
+            launch_map_back(n, poff, perm, pair_c, f, S, q, out, s);
+            if (out_mem_kind == MAP_MEM_HOST)
+                EM_HIP(hipMemcpyAsync(particle_values, out, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        }
+        EM_HIP(hipStreamSynchronize(s));
     });
 }
 
@@ -467,6 +511,7 @@ int map_pseudo(map_ctx *h, const map_particles_in *p, const double box[6], const
 {
     Ctx *C = reinterpret_cast<Ctx *>(h);
     API_BODY(C, {
+        C->back.valid = false;
         EM_CHECK(p && box && par && out, MAP_EINVAL, "null argument");
         EM_CHECK(p->n >= 0 && p->n < (int64_t)INT32_MAX, MAP_EINVAL, "particle count outside [0, 2^31-1)");
         EM_CHECK(p->mem_kind == MAP_MEM_HOST || p->mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad particle mem_kind");

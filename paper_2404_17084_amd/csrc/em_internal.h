@@ -71,7 +71,7 @@ enum Slot : int {
     S_F, S_F_PM, S_S, S_MCELL, S_RHO, S_RED,
     S_FIX_ITEMS, S_FIX_VALS, S_FIX_KEY2, S_FIX_VAL2,
     S_SCAN_TMP, S_SORT_HIST, S_TILE_CTR, S_TILE_CNT, S_TILE_OFF, S_TILES,
-    S_CAND_BUF, S_CAND_MAX, S_PBOX, S_NCNT, S_NOFF, S_QCNT, S_ECNT, S_PCNT2,
+    S_CAND_BUF, S_CAND_MAX, S_PBOX, S_NCNT, S_NOFF, S_QCNT, S_ECNT, S_PCNT2, S_BACK_IN, S_BACK_OUT,
     S_PSEUDO0, S_PSEUDO1, S_PSEUDO2, S_PSEUDO3, S_PSEUDO4, S_PSEUDO5, S_PSEUDO6, S_PSEUDO7,
     S_PSEUDO8, S_PSEUDO9, S_PSEUDO10, S_PSEUDO11, S_PSEUDO12, S_PSEUDO13, S_PSEUDO14, S_PSEUDO15,
     S_NUM_SLOTS
@@ -167,6 +167,13 @@ struct PairSet {
 };
 PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, const EdgeRec *edges,
                     int64_t *counters, hipStream_t s);
+// Particle-major view of cell-major pairs: perm (particle-major position ->
+// cell-major index, cells ascending within a particle) and poff (n+1).
+void build_particle_view(Workspace &ws, const uint32_t *pair_p, int64_t n_pairs, int64_t n, uint32_t *perm,
+                         int64_t *poff, hipStream_t s);
+// Inverse mapping: q_part[a] = sum over a's pairs of q_cell[c] f / S_a (0 when S_a = 0).
+void launch_map_back(int64_t n, const int64_t *poff, const uint32_t *perm, const uint32_t *pair_c, const double *f,
+                     const double *S, const double *q_cell, double *q_part, hipStream_t s);
 
 // em_pseudo.hip: pseudo-particle front end (tree, walk, node smoothing lengths).
 struct DevParticles {

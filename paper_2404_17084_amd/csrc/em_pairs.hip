@@ -490,6 +490,25 @@ __global__ void k_seg_offsets(int64_t n_items, const uint32_t *__restrict__ keys
     for (int64_t v = prev + 1; v <= cur; v++) off[v] = i;
 }
 
+void build_particle_view(Workspace &ws, const uint32_t *pair_p, int64_t n_pairs, int64_t n, uint32_t *perm,
+                         int64_t *poff, hipStream_t s)
+{
+    if (n_pairs == 0) {
+        fill_zero_bytes(poff, sizeof(int64_t) * (n + 1), s);
+        return;
+    }
+    uint32_t *key = ws.get<uint32_t>(S_KEY2, (size_t)n_pairs);
+    EM_HIP(hipMemcpyAsync(key, pair_p, sizeof(uint32_t) * n_pairs, hipMemcpyDeviceToDevice, s));
+    fill_iota_u32(perm, n_pairs, s);
+    int bits = 1;
+    while (bits < 32 && ((uint64_t)(n - 1) >> bits) != 0) bits++;
+    radix_sort_u32(ws, key, perm, ws.get<uint32_t>(S_IOTA, (size_t)n_pairs), ws.get<uint32_t>(S_PC_PM, (size_t)n_pairs),
+                   n_pairs, bits, s);
+    hipLaunchKernelGGL(k_seg_offsets, dim3((unsigned)((n_pairs + 1 + 255) / 256)), dim3(256), 0, s, n_pairs,
+                       (const uint32_t *)key, n, poff);
+    EM_HIP(hipGetLastError());
+}
+
 PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, const EdgeRec *edges,
                     int64_t *counters, hipStream_t s)
 {

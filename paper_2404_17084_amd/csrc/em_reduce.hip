@@ -45,6 +45,24 @@ __global__ void k_fixed_to_double(int64_t n, double *S)
     S[a] = (double)q * 2.220446049250313e-16;
 }
 
+// Inverse mapping, one wavefront per particle over its pairs in cell order
+// (lanes strided, fixed butterfly): q_a = sum_i q_i f_ai / S_a.
+__global__ void k_map_back(int64_t n, const int64_t *__restrict__ poff, const uint32_t *__restrict__ perm,
+                           const uint32_t *__restrict__ pair_c, const double *__restrict__ f,
+                           const double *__restrict__ S, const double *__restrict__ q_cell, double *__restrict__ q_part)
+{
+    const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (a >= n) return;
+    double v = 0.0;
+    for (int64_t q = poff[a] + lane; q < poff[a + 1]; q += 64) {
+        const uint32_t k = perm[q];
+        v += q_cell[pair_c[k]] * f[k];
+    }
+    v = wave_sum(v);
+    if (lane == 0) q_part[a] = S[a] > 0.0 ? v / S[a] : 0.0;
+}
+
 __global__ void k_cell_mass(int64_t nc, const int64_t *coff, const uint32_t *pair_p, const double *f,
                             const double *S, const double *m, const double *vol, double *M, double *rho)
 {
@@ -132,6 +150,15 @@ __global__ void k_stats_final(int nb, const double *part, double *red, unsigned 
 }
 
 }  // namespace
+
+void launch_map_back(int64_t n, const int64_t *poff, const uint32_t *perm, const uint32_t *pair_c, const double *f,
+                     const double *S, const double *q_cell, double *q_part, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_map_back, dim3((unsigned)((n * 64 + 255) / 256)), dim3(256), 0, s, n, poff, perm, pair_c, f,
+                       S, q_cell, q_part);
+    EM_HIP(hipGetLastError());
+}
 
 void launch_reduce(const DevInputs &in, const PairSet &ps, const double *f, double *S, double *M,
                    double *rho, double *red, unsigned *flags, hipStream_t s)

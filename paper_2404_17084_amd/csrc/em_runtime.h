@@ -31,6 +31,13 @@ struct Ctx {
     std::map<std::pair<int, int>, IntegrateTune> tune_table;
     std::string arch;
     Server *server = nullptr;
+    // the last map_particles result, kept in the workspace for map_back: the
+    // cell-major pairs, their fractions and S_a (and, once built, the
+    // particle-major view of the pairs)
+    struct {
+        bool valid = false, have_view = false;
+        int64_t n = 0, n_cells = 0, n_pairs = 0;
+    } back;
 };
 
 IntegrateTune default_tune(int precision);

@@ -108,6 +108,7 @@ extern "C" int map_autotune(map_ctx *h, const map_particles_in *p, const map_cel
     if (!h) return MAP_EINVAL;
     Ctx *C = reinterpret_cast<Ctx *>(h);
     std::lock_guard<std::mutex> guard(C->mu);
+    C->back.valid = false;  // the tuner reuses the workspace
     try {
         EM_HIP(hipSetDevice(C->device));
         EM_CHECK(precision == MAP_FP64 || precision == MAP_MIXED, MAP_EINVAL, "precision must be MAP_FP64 or MAP_MIXED");
