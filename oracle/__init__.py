@@ -87,6 +87,9 @@ def _load():
             lib.orp_solve_h.argtypes = [i64, vp, vp, d, d, ctypes.POINTER(ctypes.c_int)]
             lib.orp_pseudo.restype = i64
             lib.orp_pseudo.argtypes = [i64, vp, vp, vp, vp, i, vp, d, d, d, i, d, i64] + [vp] * 6 + [vp, i64, vp]
+            lib.orp_pseudo2.restype = i64
+            lib.orp_pseudo2.argtypes = ([i64, vp, vp, vp, vp, i, vp, d, d, d, i, d, i64, vp, i64, vp, i64] +
+                                        [vp] * 7 + [vp, i64, vp])
         _lib = lib
     return _lib
 
@@ -311,26 +314,141 @@ def solve_h(pts, x, h0: float, h_fact: float = 1.1):
     return h, bool(fb.value)
 
 
-def pseudo(xyz, m, h, box, sources, theta=0.5, r_part=0.05, r_leaf=0.1, leaf_size=8, h_fact=1.1, only=None):
-    """Pseudo-particles (Sec. III) in Morton order: dict of xyz, m, h, s, kind, ref and stats.
+def pseudo(xyz, m, h, box, sources, theta=0.5, r_part=0.05, r_leaf=0.1, leaf_size=8, h_fact=1.1, only=None,
+           open_labels=None, regions=None):
+    """Pseudo-particles (Sec. III) in Morton order: dict of xyz, m, h, s, kind, ref, leaf and stats.
 
-    `only` restricts the h-solve to those pseudo indices (others get h = 0 unless they are particles)."""
+    `only` restricts the h-solve to those pseudo indices (others get h = 0 unless they are particles).
+    `open_labels` (node labels) and `regions` (rows cx, cy, cz, R, s_min) force openings of the walk
+    (re-walk after a failed resolution check, remembered regions; Sec. III-B)."""
     lib = _load()
     xyz, m, h, bb = _f64(xyz), _f64(m), _f64(h), _f64(box)
     src = _f64(sources).reshape(-1, 3)
     n = m.size
-    st = np.zeros(8)
-    head = [n, _p(xyz), _p(m), _p(h), _p(bb), src.shape[0], _p(src), theta, r_part, r_leaf, leaf_size, h_fact]
-    cnt = lib.orp_pseudo(*head, 0, *([None] * 6), None, 0, _p(st))
+    ol = np.ascontiguousarray(np.zeros(0, np.int64) if open_labels is None else open_labels, dtype=np.int64)
+    rg = _f64(np.zeros((0, 5)) if regions is None else regions).reshape(-1, 5)
+    st = np.zeros(9)
+    head = [n, _p(xyz), _p(m), _p(h), _p(bb), src.shape[0], _p(src), theta, r_part, r_leaf, leaf_size, h_fact,
+            ol.size, _p(ol), rg.shape[0], _p(rg)]
+    cnt = lib.orp_pseudo2(*head, 0, *([None] * 7), None, 0, _p(st))
     out = dict(xyz=np.zeros((cnt, 3)), m=np.zeros(cnt), h=np.zeros(cnt), s=np.zeros(cnt),
-               kind=np.zeros(cnt, np.int32), ref=np.zeros(cnt, np.int64))
+               kind=np.zeros(cnt, np.int32), ref=np.zeros(cnt, np.int64), leaf=np.zeros(cnt, np.int8))
     if only is None:
         o, no = None, 0
     else:
         only = np.ascontiguousarray(only, dtype=np.int64)
         o, no = _p(only), only.size
-    lib.orp_pseudo(*head, cnt, *[_p(out[k]) for k in ("xyz", "m", "h", "s", "kind", "ref")], o, no, _p(st))
+    lib.orp_pseudo2(*head, cnt, *[_p(out[k]) for k in ("xyz", "m", "h", "s", "kind", "ref", "leaf")], o, no,
+                    _p(st))
+    out["leaf"] = out["leaf"].astype(bool)
     out["stats"] = dict(tree_nodes=int(st[0]), leaves=int(st[1]), pseudo_nodes=int(st[2]),
                         particles=int(st[3]), substitute_leaves=int(st[4]), fallbacks=int(st[5]),
-                        max_level=int(st[6]), neighbours=float(st[7]))
+                        max_level=int(st[6]), neighbours=float(st[7]), s_root=float(st[8]))
     return out
+
+
+# ---------------------------------------------------------------- adaptive re-walk (Sec. III-B, Eq. (6))
+def neutral_limit(s, s_root: float, K: float):
+    """Eq. (6): f_neu,limit = (1/K) (K - s_root / s_node), written as (K - s_root / s) / K."""
+    s = np.asarray(s, dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        return (K - s_root / s) / K
+
+
+def resolution_check(P, f_neu, K: float):
+    """Nodes under-resolved by Eq. (6): node pseudo-particles with s > 0 and f_neu below the limit.
+
+    Extracted particles are never checked (Sec. III-B); a zero-size node has no limit."""
+    f_neu = np.asarray(f_neu, dtype=np.float64)
+    node = (P["kind"] == PSEUDO_NODE) & (P["s"] > 0.0)
+    fail = np.zeros(P["kind"].size, dtype=bool)
+    fail[node] = f_neu[node] < neutral_limit(P["s"][node], P["stats"]["s_root"], K)
+    return fail
+
+
+def _rmin(xyz, sources):
+    """Smallest distance from each point to the sources (the walk's r)."""
+    src = _f64(sources).reshape(-1, 3)
+    r = np.full(xyz.shape[0], np.inf)
+    for q in src:
+        d = np.sqrt((xyz[:, 0] - q[0]) * (xyz[:, 0] - q[0]) + (xyz[:, 1] - q[1]) * (xyz[:, 1] - q[1]) +
+                    (xyz[:, 2] - q[2]) * (xyz[:, 2] - q[2]))
+        r = np.minimum(r, d)
+    return r
+
+
+def _level(label: int) -> int:
+    return (int(label).bit_length() - 1) // 3
+
+
+def _descends(label: int, anc: int) -> bool:
+    """Whether node `label` is node `anc` or one of its descendants (anc = label >> 3k)."""
+    k = _level(label) - _level(anc)
+    return k >= 0 and (int(label) >> (3 * k)) == int(anc)
+
+
+def pseudo_adaptive(xyz, m, h, box, sources, field, theta=0.5, r_part=0.05, r_leaf=0.1, leaf_size=8, h_fact=1.1,
+                    K=100.0, regions=None, max_walks=32):
+    """Adaptive tree walk of Sec. III-B, driven by a neutral-fraction field.
+
+    field(P) gives the neutral fraction of every pseudo-particle of the set P
+    (the radiative-transfer step).  Each walk is checked with Eq. (6); the
+    labels of failing internal nodes are opened in the next walk, and when a
+    leaf fails r_part grows to the smallest value that extracts every failing
+    leaf (times 1 + 2^-30), r_leaf by the same factor (to at least r_part when
+    r_part was 0).  Walks repeat until a set passes or max_walks walks ran.
+    Remembered regions (rows cx, cy, cz, R, s_min) force openings from the
+    first walk; afterwards a region is dropped when no pseudo-particle of the
+    final set lies inside it (|x - c| < R) or the smallest neutral fraction
+    inside is at least Eq. (6)'s limit for a node of size R (the node it was
+    recorded for would now pass), and each node that failed adds the region
+    (its centre of mass, its size, the smallest size among the final set's
+    node pseudo-particles descending from it, 0 if none).
+    Returns the final set (as `pseudo`) with f_neu, walks, converged, r_part,
+    r_leaf, failed (labels per walk), regions (rows) and dropped (count)."""
+    regions_in = _f64(np.zeros((0, 5)) if regions is None else regions).reshape(-1, 5)
+    opened = []
+    failed = []          # per walk: labels of failing nodes (pseudo order)
+    records = []         # (label, cx, cy, cz, s) of every failing node
+    walks, converged = 0, False
+    P = f = None
+    while walks < max_walks:
+        P = pseudo(xyz, m, h, box, sources, theta, r_part, r_leaf, leaf_size, h_fact,
+                   open_labels=np.array(opened, np.int64), regions=regions_in)
+        walks += 1
+        f = np.asarray(field(P), dtype=np.float64)
+        fail = resolution_check(P, f, K)
+        idx = np.nonzero(fail)[0]
+        failed.append([int(P["ref"][i]) for i in idx])
+        if idx.size == 0:
+            converged = True
+            break
+        for i in idx:
+            records.append((int(P["ref"][i]), *P["xyz"][i], P["s"][i]))
+        inner = idx[~P["leaf"][idx]]
+        opened.extend(int(P["ref"][i]) for i in inner)
+        leaves = idx[P["leaf"][idx]]
+        if leaves.size:
+            need = float(np.max(_rmin(P["xyz"][leaves], sources) - P["s"][leaves]))
+            new = need * (1.0 + 2.0 ** -30) + 1e-300
+            r_leaf = r_leaf * (new / r_part) if r_part > 0.0 else max(r_leaf, new)
+            r_part = new
+    # remembered regions
+    s_root = P["stats"]["s_root"]
+    keep = []
+    for g in regions_in:
+        d = np.sqrt((P["xyz"][:, 0] - g[0]) * (P["xyz"][:, 0] - g[0]) + (P["xyz"][:, 1] - g[1]) *
+                    (P["xyz"][:, 1] - g[1]) + (P["xyz"][:, 2] - g[2]) * (P["xyz"][:, 2] - g[2]))
+        inside = d < g[3]
+        if inside.any() and not (f[inside].min() >= float(neutral_limit(g[3], s_root, K))):
+            keep.append(g)
+    nodes = np.nonzero(P["kind"] == PSEUDO_NODE)[0]
+    new_rows = []
+    for lab, cx, cy, cz, s in records:
+        sizes = [P["s"][i] for i in nodes if _descends(int(P["ref"][i]), lab)]
+        new_rows.append((cx, cy, cz, s, min(sizes) if sizes else 0.0))
+    out_regions = np.array(keep + new_rows, dtype=np.float64).reshape(-1, 5)
+    P = dict(P)
+    P.update(f_neu=f, walks=walks, converged=converged, r_part=r_part, r_leaf=r_leaf, failed=failed,
+             regions=out_regions, dropped=regions_in.shape[0] - len(keep))
+    return P

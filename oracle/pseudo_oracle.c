@@ -32,6 +32,12 @@
  *    h); the same value is the fallback when no root exists (N(inf) =
  *    n_points / pi <= h_fact^3) or the bracket cannot be found.
  *  - Output order: pseudo-particles in Morton order of their first particle.
+ *  - Re-walk (Sec. III-B, after Eq. (6)): an internal node is also opened
+ *    when its label is in a given list (nodes that failed the resolution
+ *    check) or when its ball comes within a remembered region (centre c,
+ *    radius R, smallest descendant size s_min: |com - c| - s < R) while it is
+ *    still larger than that descendant (s > s_min).  Leaves are opened by
+ *    r_part only.
  *
  * Functions with pins (tests/test_pseudo_pins.py): orp_morton (cube
  * containment), orp_tree (partition, leaf sizes, label arithmetic, brute-force
@@ -254,6 +260,10 @@ typedef struct {
     const double *src;
     int n_src;
     double theta, r_part, r_leaf;
+    int64_t n_open;
+    const int64_t *open;   /* labels of nodes to open */
+    int64_t n_reg;
+    const double *reg;     /* remembered regions: cx, cy, cz, R, s_min */
 } orp_walk_par;
 
 enum { ORP_NODE = 0, ORP_PARTICLE = 1 };
@@ -289,6 +299,23 @@ static double orp_rmin(const orp_node *nd, const orp_walk_par *P)
     return best;
 }
 
+/* opening forced by a failed resolution check (label listed) or by a
+ * remembered region the node comes within while larger than its s_min */
+static int orp_forced(const orp_node *nd, const orp_walk_par *P)
+{
+    for (int64_t k = 0; k < P->n_open; k++)
+        if ((uint64_t)P->open[k] == nd->label) return 1;
+    for (int64_t k = 0; k < P->n_reg; k++) {
+        const double *g = P->reg + 5 * k;
+        const double dx = nd->com[0] - g[0];
+        const double dy = nd->com[1] - g[1];
+        const double dz = nd->com[2] - g[2];
+        const double d = sqrt(dx * dx + dy * dy + dz * dz);
+        if (d - nd->s < g[3] && nd->s > g[4]) return 1;
+    }
+    return 0;
+}
+
 /* depth-first walk (Sec. III-B): pseudo list in Morton order; `subs` gets the
  * leaves whose particles were extracted */
 static void orp_walk(const orp_tree_t *T, int64_t id, const orp_walk_par *P, orp_list *out, orp_list *subs)
@@ -306,7 +333,7 @@ static void orp_walk(const orp_tree_t *T, int64_t id, const orp_walk_par *P, orp
         }
         return;
     }
-    const int open = in_part || in_leaf || nd->s > P->theta * r;
+    const int open = in_part || in_leaf || nd->s > P->theta * r || orp_forced(nd, P);
     if (!open) {
         orp_push(out, id, ORP_NODE);
         return;
@@ -372,22 +399,26 @@ double orp_solve_h(int64_t n_pts, const double *pts, const double *x, double h0,
  * Pseudo-particles of n particles (Sec. III).  Returns the pseudo count; the
  * arrays are filled when cap >= count:
  *   xyz (3), m, h, s (node size, 0 for particles), kind (0 node, 1 particle),
- *   ref (node label, or the particle's index).
- * stats[0..7]: tree nodes, leaves, pseudo nodes, extracted particles,
+ *   ref (node label, or the particle's index), leaf (1 for a node
+ *   pseudo-particle that is a leaf; may be NULL).
+ * stats[0..8]: tree nodes, leaves, pseudo nodes, extracted particles,
  * substitute leaves, h fallbacks, max tree level, neighbour points (< 2h)
- * summed over the node pseudo-particles.
+ * summed over the node pseudo-particles, size of the root node.
+ * open (n_open labels) and reg (n_reg regions of 5 doubles) force openings
+ * as described in the header; both may be empty.
  * `only` (optional, n_only entries, indices into the pseudo list) limits the
  * h-solve to those pseudo-particles (the rest get h = 0); NULL solves all.
  */
-int64_t orp_pseudo(int64_t n, const double *xyz, const double *m, const double *h, const double *box, int n_src,
-                   const double *src, double theta, double r_part, double r_leaf, int leaf_size, double h_fact,
-                   int64_t cap, double *o_xyz, double *o_m, double *o_h, double *o_s, int32_t *o_kind,
-                   int64_t *o_ref, const int64_t *only, int64_t n_only, double *stats)
+int64_t orp_pseudo2(int64_t n, const double *xyz, const double *m, const double *h, const double *box, int n_src,
+                    const double *src, double theta, double r_part, double r_leaf, int leaf_size, double h_fact,
+                    int64_t n_open, const int64_t *open, int64_t n_reg, const double *reg, int64_t cap,
+                    double *o_xyz, double *o_m, double *o_h, double *o_s, int32_t *o_kind, int64_t *o_ref,
+                    int8_t *o_leaf, const int64_t *only, int64_t n_only, double *stats)
 {
     orp_tree_t T;
     orp_tree_make(&T, n, xyz, m, h, box, leaf_size);
     orp_list out = {0}, subs = {0};
-    orp_walk_par P = {src, n_src, theta, r_part, r_leaf};
+    orp_walk_par P = {src, n_src, theta, r_part, r_leaf, n_open, open, n_reg, reg};
     if (n > 0) orp_walk(&T, 0, &P, &out, &subs);
     const int64_t np = out.n;
     if (stats) {
@@ -408,6 +439,7 @@ int64_t orp_pseudo(int64_t n, const double *xyz, const double *m, const double *
         stats[5] = 0.0;
         stats[6] = (double)maxl;
         stats[7] = 0.0;
+        stats[8] = n > 0 ? T.nodes[0].s : 0.0;
     }
     if (cap >= np) {
         /* points of the h-solve: node pseudo-particles and substitute leaves, by first particle */
@@ -439,6 +471,7 @@ int64_t orp_pseudo(int64_t n, const double *xyz, const double *m, const double *
                 o_kind[i] = ORP_NODE;
                 o_ref[i] = (int64_t)d->label;
                 o_h[i] = 0.0;
+                if (o_leaf) o_leaf[i] = (int8_t)d->leaf;
             } else {
                 const int64_t a = T.perm[out.node[i]];
                 o_xyz[3 * i] = xyz[3 * a];
@@ -449,6 +482,7 @@ int64_t orp_pseudo(int64_t n, const double *xyz, const double *m, const double *
                 o_kind[i] = ORP_PARTICLE;
                 o_ref[i] = a;
                 o_h[i] = h[a];
+                if (o_leaf) o_leaf[i] = 0;
             }
         }
         /* solve */
@@ -490,5 +524,18 @@ int64_t orp_pseudo(int64_t n, const double *xyz, const double *m, const double *
     free(subs.node);
     free(subs.kind);
     orp_tree_free(&T);
+    return np;
+}
+
+/* the walk of Sec. III-B without forced openings (stats: 8 entries) */
+int64_t orp_pseudo(int64_t n, const double *xyz, const double *m, const double *h, const double *box, int n_src,
+                   const double *src, double theta, double r_part, double r_leaf, int leaf_size, double h_fact,
+                   int64_t cap, double *o_xyz, double *o_m, double *o_h, double *o_s, int32_t *o_kind,
+                   int64_t *o_ref, const int64_t *only, int64_t n_only, double *stats)
+{
+    double st[9];
+    const int64_t np = orp_pseudo2(n, xyz, m, h, box, n_src, src, theta, r_part, r_leaf, leaf_size, h_fact, 0, NULL,
+                                   0, NULL, cap, o_xyz, o_m, o_h, o_s, o_kind, o_ref, NULL, only, n_only, st);
+    if (stats) memcpy(stats, st, sizeof(double) * 8);
     return np;
 }

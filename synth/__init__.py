@@ -279,6 +279,24 @@ def voronoi_cells(xyz: np.ndarray, box=BOX, k0: int = 48) -> Cells:
 
 
 # --------------------------------------------------------------------------
+# neutral-fraction field (stand-in for the radiative transfer)
+# --------------------------------------------------------------------------
+def ionised_spheres(xyz: np.ndarray, centres, radius: float, width: float) -> np.ndarray:
+    """Neutral fraction of an H II region around each centre: 0 within `radius`
+    of the nearest centre, rising linearly to 1 at `radius + width`.
+
+    Stands in for the neutral fractions a radiative-transfer run would return
+    for the pseudo-particles (Sec. III-B); the adaptive walk only needs a
+    field that is ionised near the sources and neutral far from them."""
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    c = np.asarray(centres, dtype=np.float64).reshape(-1, 3)
+    d = np.full(xyz.shape[0], np.inf)
+    for q in c:
+        d = np.minimum(d, np.sqrt(((xyz - q) ** 2).sum(axis=1)))
+    return np.clip((d - radius) / width, 0.0, 1.0)
+
+
+# --------------------------------------------------------------------------
 # named workloads
 # --------------------------------------------------------------------------
 def particles(kind: str, n: int, seed: int, **kw) -> Particles:
