@@ -279,6 +279,81 @@ int map_pseudo(map_ctx *ctx, const map_particles_in *p, const double box[6], con
                const map_pseudo_params *par, map_pseudo_out *out);
 
 /*
+ * Adaptive tree walk (Sec. III-B, Eq. (6)): pseudo-particles refined until
+ * every node pseudo-particle is resolved for the neutral fractions that the
+ * radiative transfer returns for it.
+ *
+ * The tree is built once; then walk after walk: the walk of map_pseudo, with
+ * internal nodes also opened when their label failed an earlier walk of this
+ * call or when they come within a remembered region (below); node smoothing
+ * lengths; `neutral` is called with the set (host memory, valid during the
+ * call) and fills the neutral fraction of each pseudo-particle; the check of
+ * Eq. (6): a node pseudo-particle of size s > 0 fails when
+ *     f_neu < f_neu,limit = (K - s_root / s) / K,
+ * s_root being the root node's size (extracted particles and zero-size nodes
+ * are not checked).  Failing internal nodes are opened in the next walk; when
+ * a leaf fails, r_part grows to (1 + 2^-30) times the largest r - s among the
+ * failing leaves (r: the leaf's distance to the nearest source), so that each
+ * of them is extracted, and r_leaf by the same factor (to at least r_part when
+ * r_part was 0).  The walks stop at the first set that passes or after
+ * max_walks walks; `out` receives the last set (as map_pseudo; out->capacity
+ * must be at least its count, and p->n always suffices).
+ *
+ * Remembered regions (the memory across steps): the context keeps a list of
+ * regions, 5 doubles each (centre x, y, z, radius R, smallest descendant size
+ * s_min).  A node "comes within" a region when |com - c| - s < R and is then
+ * opened while s > s_min (leaves only by r_part).  At the end of the call a
+ * region is dropped when no pseudo-particle of the final set lies inside it
+ * (|x - c| < R) or when the smallest neutral fraction inside is at least the
+ * limit of Eq. (6) for a node of size R (the node it stands for would pass:
+ * it has become shielded), and every node that failed during the call adds a
+ * region: its centre of mass, its size, and the smallest size among the
+ * final set's node pseudo-particles that descend from it (0 if none).  The
+ * list is read and replaced with map_get_regions / map_set_regions (at most
+ * MAP_MAX_REGIONS regions; the call fails with MAP_ENOMEM beyond).
+ *
+ * `neutral` must not call into the library with the same context.  A nonzero
+ * return from it stops the call with MAP_EINVAL (regions unchanged).
+ * Errors: those of map_pseudo; MAP_EINVAL for K <= 0 or non-finite, max_walks
+ * < 1, a NULL callback, or neutral fractions that are not finite.
+ */
+typedef int (*map_neutral_fn)(void *user, int64_t n_pseudo, const double *xyz, const double *m, const double *h,
+                              const double *size, const int32_t *kind, double *f_neu);
+
+typedef struct map_adapt_params {
+    double K;               /* Eq. (6); 100 in the paper's runs */
+    int max_walks;          /* walks per call, >= 1 */
+    map_neutral_fn neutral; /* the radiative-transfer step */
+    void *user;             /* passed to neutral */
+} map_adapt_params;
+
+typedef struct map_adapt_stats {
+    int64_t n_walks;           /* walks run (1: the first set passed) */
+    int64_t converged;         /* 1 when the last set passed */
+    int64_t n_failed;          /* node pseudo-particles that failed, over all walks */
+    int64_t n_r_part_growths;  /* walks after which r_part grew */
+    int64_t n_regions_in, n_regions_dropped, n_regions_out;
+    double r_part, r_leaf;     /* radii for a next walk: those of the last walk, grown if a leaf failed in it */
+    double s_root;             /* size of the root node */
+    double ms_tree;            /* tree build (device) */
+    double ms_walks;           /* walks, smoothing lengths and checks (host clock, callback excluded) */
+    double ms_callback;        /* time spent in `neutral` */
+    double ms_total;           /* the whole call (host clock) */
+} map_adapt_stats;
+
+#define MAP_MAX_REGIONS 1048576
+int map_pseudo_adaptive(map_ctx *ctx, const map_particles_in *p, const double box[6], const double *src_xyz,
+                        int n_src, const map_pseudo_params *par, const map_adapt_params *ap, map_pseudo_out *out,
+                        map_adapt_stats *stats);
+/* Count-then-fill read of the context's regions (host memory, 5 doubles each):
+ * *n_regions is always set; regions are written when capacity >= *n_regions. */
+int map_get_regions(map_ctx *ctx, int64_t capacity, double *regions, int64_t *n_regions);
+/* Replaces the context's regions (host memory; n_regions = 0 clears them).
+ * MAP_EINVAL for non-finite values, R <= 0 or s_min < 0; MAP_ENOMEM beyond
+ * MAP_MAX_REGIONS. */
+int map_set_regions(map_ctx *ctx, int64_t n_regions, const double *regions);
+
+/*
  * Served mapping (continuous batching).  map_submit copies the inputs (host or
  * device memory) into library-owned memory before it returns and queues the
  * job at the context's current precision; *job_id identifies it.  Jobs are

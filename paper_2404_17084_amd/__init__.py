@@ -95,6 +95,26 @@ class map_pseudo_out(ctypes.Structure):
                 ("ref", c_vp), ("mem_kind", c_int), ("n_out", c_i64), ("stats", ctypes.POINTER(map_pseudo_stats))]
 
 
+# neutral-fraction callback of the adaptive walk (host arrays)
+NEUTRAL_FN = ctypes.CFUNCTYPE(c_int, c_vp, c_i64, ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl),
+                              ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl), ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(c_dbl))
+
+
+class map_adapt_params(ctypes.Structure):
+    _fields_ = [("K", c_dbl), ("max_walks", c_int), ("neutral", NEUTRAL_FN), ("user", c_vp)]
+
+
+class map_adapt_stats(ctypes.Structure):
+    _fields_ = [(k, c_i64) for k in ("n_walks", "converged", "n_failed", "n_r_part_growths", "n_regions_in",
+                                     "n_regions_dropped", "n_regions_out")] + \
+               [(k, c_dbl) for k in ("r_part", "r_leaf", "s_root", "ms_tree", "ms_walks", "ms_callback",
+                                     "ms_total")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class MapError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
@@ -123,6 +143,11 @@ _SIGS = {
     "map_poll": (c_int, [c_vp, c_u64, c_i64, ctypes.POINTER(c_int)]),
     "map_pseudo": (c_int, [c_vp, ctypes.POINTER(map_particles_in), ctypes.POINTER(c_dbl * 6), c_vp, c_int,
                            ctypes.POINTER(map_pseudo_params), ctypes.POINTER(map_pseudo_out)]),
+    "map_pseudo_adaptive": (c_int, [c_vp, ctypes.POINTER(map_particles_in), ctypes.POINTER(c_dbl * 6), c_vp, c_int,
+                                    ctypes.POINTER(map_pseudo_params), ctypes.POINTER(map_adapt_params),
+                                    ctypes.POINTER(map_pseudo_out), ctypes.POINTER(map_adapt_stats)]),
+    "map_get_regions": (c_int, [c_vp, c_i64, c_vp, ctypes.POINTER(c_i64)]),
+    "map_set_regions": (c_int, [c_vp, c_i64, c_vp]),
 }
 
 
@@ -416,6 +441,72 @@ def map_pseudo(ctx, xyz, m, h, box, sources, theta=0.5, r_part=0.05, r_leaf=0.1,
     return res
 
 
+def map_pseudo_adaptive(ctx, xyz, m, h, box, sources, neutral, K=100.0, max_walks=32, theta=0.5, r_part=0.05,
+                        r_leaf=0.1, leaf_size=8, h_fact_node=1.1):
+    """Adaptive tree walk (Sec. III-B, Eq. (6)) with the context's remembered regions.
+
+    neutral(P) returns the neutral fraction of each pseudo-particle of the set
+    P (a dict of host arrays xyz, m, h, size, kind).  Returns the final set
+    (as map_pseudo, host arrays) with "stats" and "adapt" (walks, radii,
+    region counts)."""
+    lib = load()
+    P, k1 = particles_in(xyz, m, h)
+    bx = (c_dbl * 6)(*[float(b) for b in box])
+    src = np.ascontiguousarray(np.asarray(sources, dtype=np.float64).reshape(-1, 3))
+    par = map_pseudo_params(float(theta), float(r_part), float(r_leaf), int(leaf_size), float(h_fact_node))
+    raised = []
+
+    def cb(user, n, px, pm, ph, ps, pk, pf):
+        try:
+            if n > 0:
+                S = dict(xyz=np.ctypeslib.as_array(px, (n, 3)), m=np.ctypeslib.as_array(pm, (n,)),
+                         h=np.ctypeslib.as_array(ph, (n,)), size=np.ctypeslib.as_array(ps, (n,)),
+                         kind=np.ctypeslib.as_array(pk, (n,)))
+                np.ctypeslib.as_array(pf, (n,))[:] = np.asarray(neutral(S), dtype=np.float64).reshape(n)
+            return 0
+        except Exception as e:  # re-raised once the call has returned
+            raised.append(e)
+            return 1
+
+    fn = NEUTRAL_FN(cb)
+    ap = map_adapt_params(float(K), int(max_walks), fn, None)
+    n = int(P.n)
+    cap = max(n, 1)
+    out = dict(xyz=np.zeros((cap, 3)), m=np.zeros(cap), h=np.zeros(cap), size=np.zeros(cap),
+               kind=np.zeros(cap, np.int32), ref=np.zeros(cap, np.int64))
+    st = map_pseudo_stats()
+    ast = map_adapt_stats()
+    O = map_pseudo_out(cap, *[_ptr(out[k]) for k in ("xyz", "m", "h", "size", "kind", "ref")], MAP_MEM_HOST, 0,
+                       ctypes.pointer(st))
+    rc = lib.map_pseudo_adaptive(ctx, ctypes.byref(P), ctypes.byref(bx), _ptr(src), src.shape[0],
+                                 ctypes.byref(par), ctypes.byref(ap), ctypes.byref(O), ctypes.byref(ast))
+    if raised:
+        raise raised[0]
+    _check(ctx, rc)
+    cnt = int(O.n_out)
+    res = {k: out[k][:cnt] for k in ("xyz", "m", "h", "size", "kind", "ref")}
+    res["stats"] = st.as_dict()
+    res["adapt"] = ast.as_dict()
+    return res
+
+
+def map_get_regions(ctx):
+    """The context's remembered regions, an (n, 5) array of cx, cy, cz, R, s_min."""
+    lib = load()
+    n = c_i64()
+    _check(ctx, lib.map_get_regions(ctx, 0, None, ctypes.byref(n)))
+    out = np.zeros((n.value, 5))
+    if n.value:
+        _check(ctx, lib.map_get_regions(ctx, n.value, _ptr(out), ctypes.byref(n)))
+    return out
+
+
+def map_set_regions(ctx, regions):
+    """Replaces the context's remembered regions (rows cx, cy, cz, R, s_min)."""
+    r = np.ascontiguousarray(np.asarray(regions, dtype=np.float64).reshape(-1, 5))
+    _check(ctx, load().map_set_regions(ctx, r.shape[0], _ptr(r) if r.size else None))
+
+
 class Mapper:
     """Owns one library context."""
 
@@ -442,6 +533,17 @@ class Mapper:
 
     def pseudo(self, particles, box, sources, **kw):
         return map_pseudo(self.ctx, particles.xyz, particles.m, particles.h, box, sources, **kw)
+
+    def pseudo_adaptive(self, particles, box, sources, neutral, **kw):
+        return map_pseudo_adaptive(self.ctx, particles.xyz, particles.m, particles.h, box, sources, neutral, **kw)
+
+    @property
+    def regions(self):
+        return map_get_regions(self.ctx)
+
+    @regions.setter
+    def regions(self, value):
+        map_set_regions(self.ctx, value)
 
     def pairs(self, particles, cells):
         return map_pairs(self.ctx, particles.xyz, particles.m, particles.h, cells)

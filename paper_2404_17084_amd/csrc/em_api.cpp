@@ -506,46 +506,131 @@ int map_back(map_ctx *h, const double *cell_values, int mem_kind, double *partic
     });
 }
 
+}  // extern "C"
+
+namespace em {
+
+// Arguments shared by map_pseudo and map_pseudo_adaptive.
+static void check_pseudo_args(const map_particles_in *p, const double box[6], const double *src_xyz, int n_src,
+                              const map_pseudo_params *par, const map_pseudo_out *out)
+{
+    EM_CHECK(p && box && par && out, MAP_EINVAL, "null argument");
+    EM_CHECK(p->n >= 0 && p->n < (int64_t)INT32_MAX, MAP_EINVAL, "particle count outside [0, 2^31-1)");
+    EM_CHECK(p->mem_kind == MAP_MEM_HOST || p->mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad particle mem_kind");
+    if (p->n > 0) EM_CHECK(p->xyz && p->m && p->h, MAP_EINVAL, "null particle array");
+    for (int d = 0; d < 3; d++)
+        EM_CHECK(std::isfinite(box[d]) && std::isfinite(box[3 + d]) && box[3 + d] > box[d], MAP_EINVAL,
+                 "box must be finite with hi > lo");
+    EM_CHECK(src_xyz && n_src >= 1 && n_src <= 64, MAP_EINVAL, "need 1 to 64 sources");
+    for (int k = 0; k < 3 * n_src; k++) EM_CHECK(std::isfinite(src_xyz[k]), MAP_EINVAL, "non-finite source");
+    EM_CHECK(std::isfinite(par->theta) && par->theta >= 0.0, MAP_EINVAL, "theta must be finite and >= 0");
+    EM_CHECK(std::isfinite(par->r_part) && par->r_part >= 0.0 && std::isfinite(par->r_leaf) && par->r_leaf >= 0.0,
+             MAP_EINVAL, "r_part and r_leaf must be finite and >= 0");
+    EM_CHECK(par->leaf_size >= 1 && par->leaf_size <= 64, MAP_EINVAL, "leaf_size must be in [1, 64]");
+    EM_CHECK(std::isfinite(par->h_fact_node) && par->h_fact_node > 0.0, MAP_EINVAL, "h_fact_node must be > 0");
+    EM_CHECK(out->capacity >= 0, MAP_EINVAL, "negative capacity");
+    EM_CHECK(out->mem_kind == MAP_MEM_HOST || out->mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad output mem_kind");
+}
+
+static PseudoDest dest_of(const map_pseudo_out *out)
+{
+    PseudoDest d;
+    d.capacity = out->capacity;
+    d.xyz = out->xyz;
+    d.m = out->m;
+    d.h = out->h;
+    d.size = out->size;
+    d.kind = out->kind;
+    d.ref = out->ref;
+    d.mem_kind = out->mem_kind;
+    return d;
+}
+
+static DevParticles stage_particles(Ctx &C, const map_particles_in *p, hipStream_t s)
+{
+    DevParticles dp;
+    dp.n = p->n;
+    dp.xyz = stage(C.ws, S_XYZ, p->xyz, 3 * p->n, p->mem_kind, s);
+    dp.m = stage(C.ws, S_M, p->m, p->n, p->mem_kind, s);
+    dp.h = stage(C.ws, S_H, p->h, p->n, p->mem_kind, s);
+    return dp;
+}
+
+}  // namespace em
+
+extern "C" {
+
+int map_pseudo_adaptive(map_ctx *h, const map_particles_in *p, const double box[6], const double *src_xyz,
+                        int n_src, const map_pseudo_params *par, const map_adapt_params *ap, map_pseudo_out *out,
+                        map_adapt_stats *stats)
+{
+    Ctx *C = reinterpret_cast<Ctx *>(h);
+    API_BODY(C, {
+        C->back.valid = false;
+        check_pseudo_args(p, box, src_xyz, n_src, par, out);
+        EM_CHECK(ap && ap->neutral, MAP_EINVAL, "null adaptive parameters or callback");
+        EM_CHECK(std::isfinite(ap->K) && ap->K > 0.0, MAP_EINVAL, "K must be finite and > 0");
+        EM_CHECK(ap->max_walks >= 1, MAP_EINVAL, "max_walks must be >= 1");
+        hipStream_t s = C->stream;
+        const DevParticles dp = stage_particles(*C, p, s);
+        map_pseudo_stats st{};
+        map_adapt_stats ast{};
+        std::vector<double> regions = C->regions;
+        const int64_t n_out =
+            run_pseudo_adaptive(C->ws, dp, box, src_xyz, n_src, *par, *ap, regions, dest_of(out), &st, &ast, s, C->ev);
+        out->n_out = n_out;
+        EM_CHECK(out->capacity >= n_out, MAP_EINVAL,
+                 "output capacity " + std::to_string(out->capacity) + " below the pseudo count " +
+                     std::to_string(n_out));
+        C->regions.swap(regions);
+        st.ms_tree = ast.ms_tree;
+        st.ms_total = ast.ms_total;
+        if (out->stats) *out->stats = st;
+        if (stats) *stats = ast;
+    });
+}
+
+int map_get_regions(map_ctx *h, int64_t capacity, double *regions, int64_t *n_regions)
+{
+    Ctx *C = reinterpret_cast<Ctx *>(h);
+    API_BODY(C, {
+        EM_CHECK(n_regions && capacity >= 0, MAP_EINVAL, "null count or negative capacity");
+        const int64_t n = (int64_t)C->regions.size() / 5;
+        *n_regions = n;
+        if (capacity >= n && n > 0) {
+            EM_CHECK(regions, MAP_EINVAL, "null regions buffer");
+            std::memcpy(regions, C->regions.data(), sizeof(double) * 5 * n);
+        }
+    });
+}
+
+int map_set_regions(map_ctx *h, int64_t n_regions, const double *regions)
+{
+    Ctx *C = reinterpret_cast<Ctx *>(h);
+    API_BODY(C, {
+        EM_CHECK(n_regions >= 0, MAP_EINVAL, "negative region count");
+        EM_CHECK(n_regions <= MAP_MAX_REGIONS, MAP_ENOMEM, "more than MAP_MAX_REGIONS regions");
+        EM_CHECK(n_regions == 0 || regions, MAP_EINVAL, "null regions");
+        for (int64_t r = 0; r < n_regions; r++) {
+            const double *g = regions + 5 * r;
+            for (int k = 0; k < 5; k++) EM_CHECK(std::isfinite(g[k]), MAP_EINVAL, "non-finite region value");
+            EM_CHECK(g[3] > 0.0 && g[4] >= 0.0, MAP_EINVAL, "region radius must be > 0 and s_min >= 0");
+        }
+        C->regions.assign(regions, regions + 5 * n_regions);
+    });
+}
+
 int map_pseudo(map_ctx *h, const map_particles_in *p, const double box[6], const double *src_xyz, int n_src,
                const map_pseudo_params *par, map_pseudo_out *out)
 {
     Ctx *C = reinterpret_cast<Ctx *>(h);
     API_BODY(C, {
         C->back.valid = false;
-        EM_CHECK(p && box && par && out, MAP_EINVAL, "null argument");
-        EM_CHECK(p->n >= 0 && p->n < (int64_t)INT32_MAX, MAP_EINVAL, "particle count outside [0, 2^31-1)");
-        EM_CHECK(p->mem_kind == MAP_MEM_HOST || p->mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad particle mem_kind");
-        if (p->n > 0) EM_CHECK(p->xyz && p->m && p->h, MAP_EINVAL, "null particle array");
-        for (int d = 0; d < 3; d++)
-            EM_CHECK(std::isfinite(box[d]) && std::isfinite(box[3 + d]) && box[3 + d] > box[d], MAP_EINVAL,
-                     "box must be finite with hi > lo");
-        EM_CHECK(src_xyz && n_src >= 1 && n_src <= 64, MAP_EINVAL, "need 1 to 64 sources");
-        for (int k = 0; k < 3 * n_src; k++) EM_CHECK(std::isfinite(src_xyz[k]), MAP_EINVAL, "non-finite source");
-        EM_CHECK(std::isfinite(par->theta) && par->theta >= 0.0, MAP_EINVAL, "theta must be finite and >= 0");
-        EM_CHECK(std::isfinite(par->r_part) && par->r_part >= 0.0 && std::isfinite(par->r_leaf) &&
-                     par->r_leaf >= 0.0,
-                 MAP_EINVAL, "r_part and r_leaf must be finite and >= 0");
-        EM_CHECK(par->leaf_size >= 1 && par->leaf_size <= 64, MAP_EINVAL, "leaf_size must be in [1, 64]");
-        EM_CHECK(std::isfinite(par->h_fact_node) && par->h_fact_node > 0.0, MAP_EINVAL, "h_fact_node must be > 0");
-        EM_CHECK(out->capacity >= 0, MAP_EINVAL, "negative capacity");
-        EM_CHECK(out->mem_kind == MAP_MEM_HOST || out->mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad output mem_kind");
+        check_pseudo_args(p, box, src_xyz, n_src, par, out);
         hipStream_t s = C->stream;
-        DevParticles dp;
-        dp.n = p->n;
-        dp.xyz = stage(C->ws, S_XYZ, p->xyz, 3 * p->n, p->mem_kind, s);
-        dp.m = stage(C->ws, S_M, p->m, p->n, p->mem_kind, s);
-        dp.h = stage(C->ws, S_H, p->h, p->n, p->mem_kind, s);
-        PseudoDest d;
-        d.capacity = out->capacity;
-        d.xyz = out->xyz;
-        d.m = out->m;
-        d.h = out->h;
-        d.size = out->size;
-        d.kind = out->kind;
-        d.ref = out->ref;
-        d.mem_kind = out->mem_kind;
+        const DevParticles dp = stage_particles(*C, p, s);
         map_pseudo_stats st{};
-        const int64_t n_out = run_pseudo(C->ws, dp, box, src_xyz, n_src, *par, d, &st, s, C->ev);
+        const int64_t n_out = run_pseudo(C->ws, dp, box, src_xyz, n_src, *par, dest_of(out), &st, s, C->ev);
         out->n_out = n_out;
         if (p->n > 0) {
             float t = 0.f;

@@ -74,6 +74,7 @@ enum Slot : int {
     S_CAND_BUF, S_CAND_MAX, S_PBOX, S_NCNT, S_NOFF, S_QCNT, S_ECNT, S_PCNT2, S_BACK_IN, S_BACK_OUT,
     S_PSEUDO0, S_PSEUDO1, S_PSEUDO2, S_PSEUDO3, S_PSEUDO4, S_PSEUDO5, S_PSEUDO6, S_PSEUDO7,
     S_PSEUDO8, S_PSEUDO9, S_PSEUDO10, S_PSEUDO11, S_PSEUDO12, S_PSEUDO13, S_PSEUDO14, S_PSEUDO15,
+    S_ADAPT0, S_ADAPT1, S_ADAPT2, S_ADAPT3, S_ADAPT4, S_ADAPT5, S_ADAPT6, S_ADAPT7,
     S_NUM_SLOTS
 };
 
@@ -193,6 +194,13 @@ struct PseudoDest {
 int64_t run_pseudo(Workspace &ws, const DevParticles &p, const double box[6], const double *src, int n_src,
                    const map_pseudo_params &par, const PseudoDest &dest, map_pseudo_stats *st, hipStream_t s,
                    hipEvent_t *ev);
+// Adaptive walk (Sec. III-B, Eq. (6)): walks until the set passes the check or
+// ap.max_walks walks ran; `regions` (5 doubles each) is read and replaced.
+// ev: at least 2 events (tree timing).  Returns the count of the last set.
+int64_t run_pseudo_adaptive(Workspace &ws, const DevParticles &p, const double box[6], const double *src, int n_src,
+                            const map_pseudo_params &par, const map_adapt_params &ap, std::vector<double> &regions,
+                            const PseudoDest &dest, map_pseudo_stats *st, map_adapt_stats *ast, hipStream_t s,
+                            hipEvent_t *ev);
 
 // One job of a batched integration launch (device-resident table entry).
 struct BatchJob {

@@ -27,7 +27,12 @@
 // order.  One wavefront per node solves N(h) = h_fact^3 by Newton steps kept
 // inside a bisection bracket; each evaluation tests 64 boxes per step against
 // the ball of radius 2h and adds the contributions in point order.
+#include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
 
 #include "em_internal.h"
 
@@ -292,7 +297,43 @@ struct Walk {
     double src[3 * 64];
     int n_src;
     double theta, r_part, r_leaf;
+    // forced openings (re-walk): sorted labels of nodes that failed the
+    // resolution check, and remembered regions (cx, cy, cz, R, s_min)
+    const uint64_t *open;
+    int64_t n_open;
+    const double *reg;
+    int64_t n_reg;
 };
+
+__device__ __forceinline__ double src_dist(const Walk *W, double x, double y, double z)
+{
+    double r = INFINITY;
+    for (int k = 0; k < W->n_src; k++) {
+        const double d = sqrt(dist2(x, y, z, W->src[3 * k], W->src[3 * k + 1], W->src[3 * k + 2]));
+        if (d < r) r = d;
+    }
+    return r;
+}
+
+// an internal node opened by a failed check (label listed) or by a region it
+// comes within (|com - c| - s < R) while larger than the region's s_min
+__device__ __forceinline__ bool forced_open(const Walk *W, uint64_t label, double cx, double cy, double cz, double s)
+{
+#pragma clang fp contract(off)
+    int64_t lo = 0, hi = W->n_open;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (W->open[mid] < label) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo < W->n_open && W->open[lo] == label) return true;
+    for (int64_t k = 0; k < W->n_reg; k++) {
+        const double *g = W->reg + 5 * k;
+        const double d = sqrt(dist2(cx, cy, cz, g[0], g[1], g[2]));
+        if (d - s < g[3] && s > g[4]) return true;
+    }
+    return false;
+}
 
 // opening decision of every node; bit 0: opened, bit 1: leaf opened into particles
 __global__ void k_open(int32_t n_nodes, const Walk *__restrict__ W, Nodes T)
@@ -301,17 +342,13 @@ __global__ void k_open(int32_t n_nodes, const Walk *__restrict__ W, Nodes T)
     const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= n_nodes) return;
     const double cx = T.com[3 * i], cy = T.com[3 * i + 1], cz = T.com[3 * i + 2];
-    double r = INFINITY;
-    for (int k = 0; k < W->n_src; k++) {
-        const double d = sqrt(dist2(cx, cy, cz, W->src[3 * k], W->src[3 * k + 1], W->src[3 * k + 2]));
-        if (d < r) r = d;
-    }
+    const double r = src_dist(W, cx, cy, cz);
     const double s = sqrt(__longlong_as_double((long long)T.d2[i]));
     const bool in_part = r - s < W->r_part;
     const bool in_leaf = r - s < W->r_leaf;
     uint8_t o;
     if (T.leaf[i]) o = in_part ? 3 : 0;
-    else o = (in_part || in_leaf || s > W->theta * r) ? 1 : 0;
+    else o = (in_part || in_leaf || s > W->theta * r || forced_open(W, T.label[i], cx, cy, cz, s)) ? 1 : 0;
     T.open[i] = o;
 }
 
@@ -379,6 +416,7 @@ struct PseudoOut {
     double *xyz, *m, *h, *s;
     int32_t *kind;
     int64_t *ref;
+    int32_t *node;  // tree node of a node pseudo-particle, -1 for a particle
 };
 
 // output records; the points of the h-solve and, for each point that is a
@@ -404,6 +442,7 @@ __global__ void k_emit(int64_t n, const int64_t *__restrict__ omark, const int64
             O.s[o] = sqrt(__longlong_as_double((long long)T.d2[nd]));
             O.kind[o] = MAP_PSEUDO_NODE;
             O.ref[o] = (int64_t)T.label[nd];
+            O.node[o] = nd;
         } else {
             const int64_t a = perm[i];
             O.xyz[3 * o] = xyz[3 * a];
@@ -414,6 +453,7 @@ __global__ void k_emit(int64_t n, const int64_t *__restrict__ omark, const int64
             O.s[o] = 0.0;
             O.kind[o] = MAP_PSEUDO_PARTICLE;
             O.ref[o] = a;
+            O.node[o] = -1;
         }
     }
     if (pmark[i]) {
@@ -645,16 +685,107 @@ T *carve(char *&p, int64_t count)
     return r;
 }
 
-}  // namespace
+// ---------------------------------------------------------------- resolution check (Eq. (6))
+// code 0: passes (or not checked), 1: internal node fails, 2: leaf fails; for
+// a failing leaf, need = r - s (its distance to the nearest source less its size)
+__global__ void k_check(int64_t n_out, const double *__restrict__ xyz, const double *__restrict__ sz,
+                        const int32_t *__restrict__ kind, const int32_t *__restrict__ node,
+                        const uint8_t *__restrict__ leaf, const double *__restrict__ f, double K, double s_root,
+                        const Walk *__restrict__ W, int32_t *__restrict__ code, double *__restrict__ need)
+{
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_out) return;
+    int32_t c = 0;
+    double nd = -INFINITY;
+    if (kind[i] == MAP_PSEUDO_NODE && sz[i] > 0.0) {
+        const double lim = (K - s_root / sz[i]) / K;
+        if (f[i] < lim) {
+            c = leaf[node[i]] ? 2 : 1;
+            if (c == 2) nd = src_dist(W, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]) - sz[i];
+        }
+    }
+    code[i] = c;
+    need[i] = nd;
+}
 
-int64_t run_pseudo(Workspace &ws, const DevParticles &P, const double box[6], const double *src, int n_src,
-                   const map_pseudo_params &par, const PseudoDest &dest, map_pseudo_stats *st, hipStream_t s,
-                   hipEvent_t *ev)
+// One wavefront per remembered region: keep[r] = some pseudo-particle lies
+// inside (|x - c| < R) and the smallest neutral fraction inside is below the
+// limit of Eq. (6) for a node of size R.
+__global__ void k_region_keep(int64_t n_reg, const double *__restrict__ reg, int64_t n_out,
+                              const double *__restrict__ xyz, const double *__restrict__ f, double K, double s_root,
+                              int32_t *__restrict__ keep)
+{
+#pragma clang fp contract(off)
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (r >= n_reg) return;  // whole wavefront
+    const double *g = reg + 5 * r;
+    int any = 0;
+    double mn = INFINITY;
+    for (int64_t i = lane; i < n_out; i += 64) {
+        const double d = sqrt(dist2(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], g[0], g[1], g[2]));
+        if (d < g[3]) {
+            any = 1;
+            mn = fmin(mn, f[i]);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        any |= __shfl_xor(any, o, 64);
+        mn = fmin(mn, __shfl_xor(mn, o, 64));
+    }
+    if (lane == 0) {
+        const double lim = (K - s_root / g[3]) / K;
+        keep[r] = any && !(mn >= lim);
+    }
+}
+
+__device__ __forceinline__ int label_level(uint64_t label) { return (63 - __clzll((long long)label)) / 3; }
+
+// One wavefront per failed node label: the smallest size among the node
+// pseudo-particles that are that node or descend from it (0 if none).
+__global__ void k_region_smin(int64_t n_lab, const uint64_t *__restrict__ lab, int64_t n_out,
+                              const int32_t *__restrict__ kind, const int64_t *__restrict__ ref,
+                              const double *__restrict__ sz, double *__restrict__ smin)
+{
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (w >= n_lab) return;  // whole wavefront
+    const uint64_t a = lab[w];
+    const int la = label_level(a);
+    double mn = INFINITY;
+    for (int64_t i = lane; i < n_out; i += 64) {
+        if (kind[i] != MAP_PSEUDO_NODE) continue;
+        const uint64_t b = (uint64_t)ref[i];
+        const int lb = label_level(b);
+        if (lb >= la && (b >> (3 * (lb - la))) == a) mn = fmin(mn, sz[i]);
+    }
+    for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o, 64));
+    if (lane == 0) smin[w] = mn < INFINITY ? mn : 0.0;
+}
+
+// Tree of one call, kept between its walks.
+struct TreeState {
+    int32_t n_nodes = 0;
+    int max_level = 0;
+    Nodes T;
+    uint32_t *perm = nullptr;
+    int32_t *cur = nullptr, *leaf_of = nullptr;
+    int64_t *flag = nullptr, *off = nullptr;
+    unsigned *small = nullptr;
+};
+
+// Forced openings of a walk (device memory).
+struct Forced {
+    const uint64_t *open = nullptr;
+    int64_t n_open = 0;
+    const double *reg = nullptr;
+    int64_t n_reg = 0;
+};
+
+void check_particles(Workspace &ws, const DevParticles &P, hipStream_t s)
 {
     const int64_t n = P.n;
-    map_pseudo_stats local{};
-    if (ev) EM_HIP(hipEventRecord(ev[0], s));
-    // validation of the particle values
     unsigned *flags = ws.get<unsigned>(S_FLAGS, 4);
     fill_zero_bytes(flags, sizeof(unsigned) * 4, s);
     if (n > 0) {
@@ -667,11 +798,17 @@ int64_t run_pseudo(Workspace &ws, const DevParticles &P, const double box[6], co
     EM_CHECK(!(hf & F_PART_NONFINITE), MAP_EINVAL, "non-finite particle position");
     EM_CHECK(!(hf & F_H_NONPOS), MAP_EINVAL, "smoothing length h <= 0 or non-finite");
     EM_CHECK(!(hf & F_M_BAD), MAP_EINVAL, "particle mass <= 0 or non-finite");
-    if (n == 0) {
-        if (st) *st = local;
-        return 0;
-    }
-    const int ls = par.leaf_size;
+}
+
+}  // namespace
+
+namespace {
+
+// The octree of n > 0 validated particles (Sec. III-A), kept in TS.
+void build_tree(Workspace &ws, const DevParticles &P, const double box[6], int ls, TreeState &TS, hipStream_t s,
+                hipEvent_t *ev)
+{
+    const int64_t n = P.n;
     const int64_t cap64 = n + (int64_t)kMaxLevel * ((n + ls) / (ls + 1)) + 1;
     EM_CHECK(cap64 < (int64_t)INT32_MAX, MAP_EINVAL, "too many particles for this leaf size");
     const int32_t cap = (int32_t)cap64;
@@ -784,7 +921,32 @@ int64_t run_pseudo(Workspace &ws, const DevParticles &P, const double box[6], co
         EM_HIP(hipGetLastError());
     }
     if (ev) EM_HIP(hipEventRecord(ev[1], s));
+    TS.n_nodes = n_nodes;
+    TS.max_level = max_level;
+    TS.T = T;
+    TS.perm = perm;
+    TS.cur = cur;
+    TS.leaf_of = leaf_of;
+    TS.flag = flag;
+    TS.off = off;
+    TS.small = small;
+}
 
+// One walk over the tree (Sec. III-B) with forced openings F.  Returns the
+// pseudo count; when capacity >= it, the set is written to O (workspace
+// memory) with node smoothing lengths (Sec. III-C).
+int64_t walk_tree(Workspace &ws, const TreeState &TS, const DevParticles &P, const double *src, int n_src,
+                  const map_pseudo_params &par, const Forced &F, int64_t capacity, map_pseudo_stats &local,
+                  PseudoOut &O, hipStream_t s, hipEvent_t *ev)
+{
+    const int64_t n = P.n;
+    const int32_t n_nodes = TS.n_nodes;
+    Nodes T = TS.T;
+    const uint32_t *perm = TS.perm;
+    int32_t *cur = TS.cur;
+    const int32_t *leaf_of = TS.leaf_of;
+    int64_t *flag = TS.flag, *off = TS.off;
+    unsigned *small = TS.small;
     // ---------------------------------------------------------------- walk
     Walk Wh{};
     for (int k = 0; k < 3 * n_src; k++) Wh.src[k] = src[k];
@@ -792,6 +954,10 @@ int64_t run_pseudo(Workspace &ws, const DevParticles &P, const double box[6], co
     Wh.theta = par.theta;
     Wh.r_part = par.r_part;
     Wh.r_leaf = par.r_leaf;
+    Wh.open = F.open;
+    Wh.n_open = F.n_open;
+    Wh.reg = F.reg;
+    Wh.n_reg = F.n_reg;
     Walk *Wd = reinterpret_cast<Walk *>(ws.get(S_PSEUDO15, sizeof(Walk)));
     EM_HIP(hipMemcpyAsync(Wd, &Wh, sizeof(Walk), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_open, dim3(grid_of(n_nodes)), dim3(256), 0, s, n_nodes, (const Walk *)Wd, T);
@@ -822,23 +988,21 @@ int64_t run_pseudo(Workspace &ws, const DevParticles &P, const double box[6], co
     EM_HIP(hipStreamSynchronize(s));
     const int64_t n_out = cnts[0], n_pts = cnts[1];
     local.n_tree_nodes = n_nodes;
-    local.max_level = max_level;
+    local.max_level = TS.max_level;
     local.n_pseudo = n_out;
     local.n_leaves = (int64_t)wcnt[0];
     local.n_pseudo_nodes = (int64_t)wcnt[1];
     local.n_substitute_leaves = (int64_t)wcnt[2];
     local.n_particles = (int64_t)wcnt[3];
-    if (dest.capacity < n_out) {
+    if (capacity < n_out) {
         if (ev) {
             EM_HIP(hipEventRecord(ev[2], s));
             EM_HIP(hipEventRecord(ev[3], s));
         }
         EM_HIP(hipStreamSynchronize(s));
-        if (st) *st = local;
         return n_out;
     }
 
-    PseudoOut O;
     double *ob = ws.get<double>(S_PP_PM, (size_t)(6 * n_out + 8));
     O.xyz = ob;
     O.m = ob + 3 * n_out;
@@ -846,6 +1010,7 @@ int64_t run_pseudo(Workspace &ws, const DevParticles &P, const double box[6], co
     O.s = ob + 5 * n_out;
     O.kind = ws.get<int32_t>(S_PC_PM, (size_t)(n_out + 1));
     O.ref = ws.get<int64_t>(S_PAIR_P, (size_t)(n_out + 1));
+    O.node = ws.get<int32_t>(S_ADAPT0, (size_t)(n_out + 1));
     double4 *pts = ws.get<double4>(S_PAIR_C, (size_t)(n_pts + 1));
     int64_t *pt_slot = ws.get<int64_t>(S_CCNT64, (size_t)(n_pts + 1));
     int32_t *pt_node = ws.get<int32_t>(S_CCNT, (size_t)(n_pts + 1));
@@ -873,8 +1038,17 @@ int64_t run_pseudo(Workspace &ws, const DevParticles &P, const double box[6], co
         EM_HIP(hipGetLastError());
     }
     if (ev) EM_HIP(hipEventRecord(ev[3], s));
+    unsigned long long hcnt[3] = {0, 0, 0};
+    EM_HIP(hipMemcpyAsync(hcnt, hc, sizeof(hcnt), hipMemcpyDeviceToHost, s));
+    EM_HIP(hipStreamSynchronize(s));
+    local.n_h_evals = (int64_t)hcnt[0];
+    local.n_neighbours = (int64_t)hcnt[1];
+    local.n_fallbacks = (int64_t)hcnt[2];
+    return n_out;
+}
 
-    // outputs
+void copy_out_set(const PseudoOut &O, int64_t n_out, const PseudoDest &dest, hipStream_t s)
+{
     const hipMemcpyKind kind = dest.mem_kind == MAP_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (n_out > 0) {
         if (dest.xyz) EM_HIP(hipMemcpyAsync(dest.xyz, O.xyz, sizeof(double) * 3 * n_out, kind, s));
@@ -884,13 +1058,218 @@ int64_t run_pseudo(Workspace &ws, const DevParticles &P, const double box[6], co
         if (dest.kind) EM_HIP(hipMemcpyAsync(dest.kind, O.kind, sizeof(int32_t) * n_out, kind, s));
         if (dest.ref) EM_HIP(hipMemcpyAsync(dest.ref, O.ref, sizeof(int64_t) * n_out, kind, s));
     }
-    unsigned long long hcnt[3] = {0, 0, 0};
-    EM_HIP(hipMemcpyAsync(hcnt, hc, sizeof(hcnt), hipMemcpyDeviceToHost, s));
     EM_HIP(hipStreamSynchronize(s));
-    local.n_h_evals = (int64_t)hcnt[0];
-    local.n_neighbours = (int64_t)hcnt[1];
-    local.n_fallbacks = (int64_t)hcnt[2];
+}
+
+}  // namespace
+
+int64_t run_pseudo(Workspace &ws, const DevParticles &P, const double box[6], const double *src, int n_src,
+                   const map_pseudo_params &par, const PseudoDest &dest, map_pseudo_stats *st, hipStream_t s,
+                   hipEvent_t *ev)
+{
+    map_pseudo_stats local{};
+    if (ev) EM_HIP(hipEventRecord(ev[0], s));
+    check_particles(ws, P, s);
+    if (P.n == 0) {
+        if (st) *st = local;
+        return 0;
+    }
+    TreeState TS;
+    build_tree(ws, P, box, par.leaf_size, TS, s, ev);
+    PseudoOut O{};
+    const int64_t n_out = walk_tree(ws, TS, P, src, n_src, par, Forced{}, dest.capacity, local, O, s, ev);
+    if (dest.capacity >= n_out) copy_out_set(O, n_out, dest, s);
     if (st) *st = local;
+    return n_out;
+}
+
+int64_t run_pseudo_adaptive(Workspace &ws, const DevParticles &P, const double box[6], const double *src, int n_src,
+                            const map_pseudo_params &par0, const map_adapt_params &ap, std::vector<double> &regions,
+                            const PseudoDest &dest, map_pseudo_stats *st, map_adapt_stats *ast, hipStream_t s,
+                            hipEvent_t *ev)
+{
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    map_pseudo_stats local{};
+    map_adapt_stats A{};
+    map_pseudo_params par = par0;
+    const int64_t n_reg_in = (int64_t)regions.size() / 5;
+    A.n_regions_in = n_reg_in;
+    A.r_part = par.r_part;
+    A.r_leaf = par.r_leaf;
+    check_particles(ws, P, s);
+    if (P.n == 0) {
+        // nothing lies inside any region: all are dropped
+        A.converged = 1;
+        A.n_regions_dropped = n_reg_in;
+        regions.clear();
+        A.ms_total = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+        if (st) *st = local;
+        if (ast) *ast = A;
+        return 0;
+    }
+    EM_HIP(hipEventRecord(ev[0], s));
+    TreeState TS;
+    build_tree(ws, P, box, par.leaf_size, TS, s, ev);
+    double s_root = 0.0;
+    {
+        uint64_t d2 = 0;
+        EM_HIP(hipMemcpyAsync(&d2, TS.T.d2, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        EM_HIP(hipStreamSynchronize(s));
+        double v;
+        std::memcpy(&v, &d2, sizeof(v));
+        s_root = std::sqrt(v);
+    }
+    float ms_tree = 0.f;
+    EM_HIP(hipEventElapsedTime(&ms_tree, ev[0], ev[1]));
+    A.ms_tree = ms_tree;
+    A.s_root = s_root;
+
+    // remembered regions on the device
+    double *d_reg = ws.get<double>(S_ADAPT1, (size_t)(5 * n_reg_in + 5));
+    if (n_reg_in > 0)
+        EM_HIP(hipMemcpyAsync(d_reg, regions.data(), sizeof(double) * 5 * n_reg_in, hipMemcpyHostToDevice, s));
+    Walk *Wd = reinterpret_cast<Walk *>(ws.get(S_ADAPT7, sizeof(Walk)));
+    {
+        Walk Wh{};
+        for (int k = 0; k < 3 * n_src; k++) Wh.src[k] = src[k];
+        Wh.n_src = n_src;
+        EM_HIP(hipMemcpyAsync(Wd, &Wh, sizeof(Walk), hipMemcpyHostToDevice, s));
+        EM_HIP(hipStreamSynchronize(s));
+    }
+
+    std::vector<uint64_t> opened;     // labels of failed internal nodes (sorted before each walk)
+    std::vector<uint64_t> rec_label;  // every failed node, in failure order
+    std::vector<double> rec_geom;     // its centre of mass and size (4 per node)
+    std::vector<double> hx, hm, hh, hs, hf, hneed;
+    std::vector<int32_t> hk, hcode;
+    std::vector<int64_t> href;
+    PseudoOut O{};
+    int64_t n_out = 0;
+    double ms_cb = 0.0;
+    for (;;) {
+        // forced openings of this walk
+        std::sort(opened.begin(), opened.end());
+        uint64_t *d_open = ws.get<uint64_t>(S_ADAPT2, opened.size() + 1);
+        if (!opened.empty())
+            EM_HIP(hipMemcpyAsync(d_open, opened.data(), sizeof(uint64_t) * opened.size(), hipMemcpyHostToDevice,
+                                  s));
+        Forced F;
+        F.open = d_open;
+        F.n_open = (int64_t)opened.size();
+        F.reg = d_reg;
+        F.n_reg = n_reg_in;
+        local = map_pseudo_stats{};
+        n_out = walk_tree(ws, TS, P, src, n_src, par, F, INT64_MAX, local, O, s, nullptr);
+        A.n_walks++;
+        // the set on the host for the radiative-transfer step
+        hx.resize(3 * n_out);
+        hm.resize(n_out);
+        hh.resize(n_out);
+        hs.resize(n_out);
+        hk.resize(n_out);
+        href.resize(n_out);
+        hf.assign(n_out, 0.0);
+        EM_HIP(hipMemcpyAsync(hx.data(), O.xyz, sizeof(double) * 3 * n_out, hipMemcpyDeviceToHost, s));
+        EM_HIP(hipMemcpyAsync(hm.data(), O.m, sizeof(double) * n_out, hipMemcpyDeviceToHost, s));
+        EM_HIP(hipMemcpyAsync(hh.data(), O.h, sizeof(double) * n_out, hipMemcpyDeviceToHost, s));
+        EM_HIP(hipMemcpyAsync(hs.data(), O.s, sizeof(double) * n_out, hipMemcpyDeviceToHost, s));
+        EM_HIP(hipMemcpyAsync(hk.data(), O.kind, sizeof(int32_t) * n_out, hipMemcpyDeviceToHost, s));
+        EM_HIP(hipMemcpyAsync(href.data(), O.ref, sizeof(int64_t) * n_out, hipMemcpyDeviceToHost, s));
+        EM_HIP(hipStreamSynchronize(s));
+        const auto tc = clk::now();
+        const int rc = ap.neutral(ap.user, n_out, hx.data(), hm.data(), hh.data(), hs.data(), hk.data(), hf.data());
+        ms_cb += std::chrono::duration<double, std::milli>(clk::now() - tc).count();
+        EM_CHECK(rc == 0, MAP_EINVAL, "the neutral-fraction callback returned " + std::to_string(rc));
+        for (int64_t i = 0; i < n_out; i++)
+            EM_CHECK(std::isfinite(hf[i]), MAP_EINVAL, "non-finite neutral fraction from the callback");
+        // the check of Eq. (6)
+        double *d_f = ws.get<double>(S_ADAPT3, (size_t)(n_out + 1));
+        int32_t *d_code = ws.get<int32_t>(S_ADAPT4, (size_t)(n_out + 1));
+        double *d_need = ws.get<double>(S_ADAPT5, (size_t)(n_out + 1));
+        hcode.assign(n_out, 0);
+        hneed.assign(n_out, 0.0);
+        EM_HIP(hipMemcpyAsync(d_f, hf.data(), sizeof(double) * n_out, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_check, dim3(grid_of(n_out)), dim3(256), 0, s, n_out, (const double *)O.xyz,
+                           (const double *)O.s, (const int32_t *)O.kind, (const int32_t *)O.node,
+                           (const uint8_t *)TS.T.leaf, (const double *)d_f, ap.K, s_root, (const Walk *)Wd, d_code,
+                           d_need);
+        EM_HIP(hipGetLastError());
+        EM_HIP(hipMemcpyAsync(hcode.data(), d_code, sizeof(int32_t) * n_out, hipMemcpyDeviceToHost, s));
+        EM_HIP(hipMemcpyAsync(hneed.data(), d_need, sizeof(double) * n_out, hipMemcpyDeviceToHost, s));
+        EM_HIP(hipStreamSynchronize(s));
+        int64_t n_fail = 0;
+        bool leaf_failed = false;
+        double need = -INFINITY;
+        for (int64_t i = 0; i < n_out; i++) {
+            if (!hcode[i]) continue;
+            n_fail++;
+            rec_label.push_back((uint64_t)href[i]);
+            rec_geom.insert(rec_geom.end(), {hx[3 * i], hx[3 * i + 1], hx[3 * i + 2], hs[i]});
+            if (hcode[i] == 1) {
+                opened.push_back((uint64_t)href[i]);
+            } else {
+                leaf_failed = true;
+                need = std::max(need, hneed[i]);
+            }
+        }
+        A.n_failed += n_fail;
+        if (n_fail == 0) {
+            A.converged = 1;
+            break;
+        }
+        if (leaf_failed) {
+            const double grown = need * (1.0 + 0x1p-30) + 1e-300;
+            par.r_leaf = par.r_part > 0.0 ? par.r_leaf * (grown / par.r_part) : std::max(par.r_leaf, grown);
+            par.r_part = grown;
+            A.n_r_part_growths++;
+        }
+        if (A.n_walks >= ap.max_walks) break;
+    }
+    A.r_part = par.r_part;
+    A.r_leaf = par.r_leaf;
+
+    // regions: drop the shielded or empty ones, add the failed nodes
+    std::vector<double> out_reg;
+    if (n_reg_in > 0) {
+        int32_t *d_keep = ws.get<int32_t>(S_ADAPT6, (size_t)n_reg_in);
+        const double *d_f = ws.get<double>(S_ADAPT3, (size_t)(n_out + 1));
+        hipLaunchKernelGGL(k_region_keep, dim3((unsigned)((n_reg_in + 3) / 4)), dim3(256), 0, s, n_reg_in,
+                           (const double *)d_reg, n_out, (const double *)O.xyz, d_f, ap.K, s_root, d_keep);
+        EM_HIP(hipGetLastError());
+        std::vector<int32_t> keep(n_reg_in);
+        EM_HIP(hipMemcpyAsync(keep.data(), d_keep, sizeof(int32_t) * n_reg_in, hipMemcpyDeviceToHost, s));
+        EM_HIP(hipStreamSynchronize(s));
+        for (int64_t r = 0; r < n_reg_in; r++) {
+            if (keep[r]) out_reg.insert(out_reg.end(), regions.begin() + 5 * r, regions.begin() + 5 * r + 5);
+            else A.n_regions_dropped++;
+        }
+    }
+    const int64_t n_new = (int64_t)rec_label.size();
+    if (n_new > 0) {
+        uint64_t *d_lab = ws.get<uint64_t>(S_ADAPT2, (size_t)n_new);
+        double *d_smin = ws.get<double>(S_ADAPT5, (size_t)n_new);
+        EM_HIP(hipMemcpyAsync(d_lab, rec_label.data(), sizeof(uint64_t) * n_new, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_region_smin, dim3((unsigned)((n_new + 3) / 4)), dim3(256), 0, s, n_new,
+                           (const uint64_t *)d_lab, n_out, (const int32_t *)O.kind, (const int64_t *)O.ref,
+                           (const double *)O.s, d_smin);
+        EM_HIP(hipGetLastError());
+        std::vector<double> smin(n_new);
+        EM_HIP(hipMemcpyAsync(smin.data(), d_smin, sizeof(double) * n_new, hipMemcpyDeviceToHost, s));
+        EM_HIP(hipStreamSynchronize(s));
+        for (int64_t k = 0; k < n_new; k++)
+            out_reg.insert(out_reg.end(),
+                           {rec_geom[4 * k], rec_geom[4 * k + 1], rec_geom[4 * k + 2], rec_geom[4 * k + 3], smin[k]});
+    }
+    EM_CHECK((int64_t)out_reg.size() / 5 <= MAP_MAX_REGIONS, MAP_ENOMEM, "more than MAP_MAX_REGIONS regions");
+    if (dest.capacity >= n_out) copy_out_set(O, n_out, dest, s);
+    regions.swap(out_reg);
+    A.n_regions_out = (int64_t)regions.size() / 5;
+    A.ms_callback = ms_cb;
+    A.ms_total = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    A.ms_walks = A.ms_total - A.ms_tree - ms_cb;
+    if (st) *st = local;
+    if (ast) *ast = A;
     return n_out;
 }
 

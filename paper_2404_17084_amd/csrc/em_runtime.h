@@ -5,6 +5,7 @@
 #include <mutex>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "em_internal.h"
 
@@ -38,6 +39,8 @@ struct Ctx {
         bool valid = false, have_view = false;
         int64_t n = 0, n_cells = 0, n_pairs = 0;
     } back;
+    // remembered regions of the adaptive walk (cx, cy, cz, R, s_min per region)
+    std::vector<double> regions;
 };
 
 IntegrateTune default_tune(int precision);
