@@ -135,6 +135,7 @@ def pseudo_leg(em, steps: int, warmup: int):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     st = sts[-1]
+    adaptive = adaptive_leg(em, mp, xyz, m, h, src, par)
     q = synth.Particles(r["xyz"].cpu().numpy().copy(), r["m"].cpu().numpy().copy(), r["h"].cpu().numpy().copy())
     cells = synth.voronoi_cells(q.xyz)
     qx, qm, qh, qc = to_device(q, cells)
@@ -159,7 +160,29 @@ def pseudo_leg(em, steps: int, warmup: int):
             "ms_hsolve": float(np.mean([s["ms_hsolve"] for s in sts])),
             "particles_per_s_front_end": n / dt,
             "pseudo_pairs": ms["n_pairs"], "ms_map_pseudo": 1e3 * dm, "pairs_per_s_pseudo": ms["n_pairs"] / dm,
-            "mass_err_pseudo": abs(ms["mass_out"] - ms["mass_in"])}
+            "mass_err_pseudo": abs(ms["mass_out"] - ms["mass_in"]), "adaptive": adaptive}
+
+
+def adaptive_leg(em, mp, xyz, m, h, src, par):
+    """Adaptive walk (Sec. III-B, Eq. (6), K = 100) on the same cloud, driven by an ionised sphere (radius
+    0.15, linear rise to neutral over 0.05) standing in for the radiative transfer: a first step from no
+    regions, then a second step with the regions and radii it left."""
+    import synth
+    field = lambda P: synth.ionised_spheres(P["xyz"], src, 0.15, 0.05)
+    mp.regions = np.zeros((0, 5))
+    em.map_pseudo_adaptive(mp.ctx, xyz, m, h, synth.BOX, src, field, K=100.0, **par)  # warm-up
+    mp.regions = np.zeros((0, 5))
+    r1 = em.map_pseudo_adaptive(mp.ctx, xyz, m, h, synth.BOX, src, field, K=100.0, **par)
+    a1 = r1["adapt"]
+    par2 = dict(par, r_part=a1["r_part"], r_leaf=a1["r_leaf"])
+    r2 = em.map_pseudo_adaptive(mp.ctx, xyz, m, h, synth.BOX, src, field, K=100.0, **par2)
+    a2 = r2["adapt"]
+    keys = ("n_walks", "converged", "n_failed", "n_r_part_growths", "n_regions_in", "n_regions_dropped",
+            "n_regions_out", "r_part", "r_leaf", "ms_tree", "ms_walks", "ms_callback", "ms_total")
+    one = lambda r, a: dict({k: a[k] for k in keys}, pseudo=int(r["m"].size),
+                            ms_per_walk=a["ms_walks"] / max(a["n_walks"], 1))
+    return {"field": "ionised sphere r 0.15 + 0.05 ramp at the source; K 100",
+            "step1": one(r1, a1), "step2_with_regions": one(r2, a2)}
 
 
 def back_leg(em, mapper, p, M, nc, steps):
