@@ -35,6 +35,7 @@
 #include <vector>
 
 #include "em_internal.h"
+#include "em_wave.h"
 
 namespace em {
 namespace {
@@ -485,6 +486,19 @@ __global__ void k_pt_leaf_boxes(int64_t n_pts, int64_t NL, const double4 *__rest
     }
 }
 
+// boxes of the internal nodes [first, 2 first) of the point tree (heap order)
+__global__ void k_pt_parent_boxes(int64_t first, double *__restrict__ bx)
+{
+    const int64_t i = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * first) return;
+    const double *a = bx + 6 * (2 * i), *b = bx + 6 * (2 * i + 1);
+    double *o = bx + 6 * i;
+    for (int d = 0; d < 3; d++) {
+        o[d] = fmin(a[d], b[d]);
+        o[3 + d] = fmax(a[3 + d], b[3 + d]);
+    }
+}
+
 __device__ __forceinline__ double box_gap2(const double *bb, double px, double py, double pz)
 {
 #pragma clang fp contract(off)
@@ -568,6 +582,140 @@ __device__ NumSum number_sum_wave(double px, double py, double pz, double h, int
     return r;
 }
 
+constexpr int kFront = 512;  // nodes per level (and listed leaves) a wavefront keeps in LDS
+
+// Leaves of the point tree whose boxes lie within sqrt(R2) of p, in
+// increasing order: a level-by-level descent from the root in which every node
+// that passes the box test pushes its two children, in order, to the next
+// level.  On return *out points at the leaf indices (in buf0 or buf1, kFront
+// entries each, this wavefront's LDS); the count is returned, or -1 when a
+// level holds more than kFront nodes.  Wave-uniform control flow.
+__device__ int collect_leaves(double px, double py, double pz, double R2, const double *__restrict__ bx, int64_t NL,
+                              int lane, int32_t *buf0, int32_t *buf1, int32_t **out)
+{
+    int32_t *cur = buf0, *nxt = buf1;
+    if (lane == 0) cur[0] = 1;
+    lds_sync_wave();
+    int n = 1;
+    for (int64_t width = 1; width < NL; width <<= 1) {
+        int m = 0;
+        for (int base = 0; base < n; base += 64) {
+            const int k = base + lane;
+            int32_t node = 0;
+            bool hit = false;
+            if (k < n) {
+                node = cur[k];
+                hit = box_gap2(bx + 6 * (int64_t)node, px, py, pz) <= R2;
+            }
+            int cnt = m / 2;
+            const int slot = 2 * wave_push(hit, cnt);
+            if (hit && slot + 1 < kFront) {
+                nxt[slot] = 2 * node;
+                nxt[slot + 1] = 2 * node + 1;
+            }
+            m = 2 * cnt;
+        }
+        if (m > kFront) return -1;
+        lds_sync_wave();
+        int32_t *t = cur;
+        cur = nxt;
+        nxt = t;
+        n = m;
+        if (n == 0) break;
+    }
+    // cur holds nodes of the leaf level (NL + j): keep those whose box passes
+    int m = 0;
+    for (int base = 0; base < n; base += 64) {
+        const int k = base + lane;
+        int32_t node = 0;
+        bool hit = false;
+        if (k < n) {
+            node = cur[k];
+            hit = box_gap2(bx + 6 * (int64_t)node, px, py, pz) <= R2;
+        }
+        const int slot = wave_push(hit, m);
+        if (hit) nxt[slot] = node - (int32_t)NL;
+    }
+    lds_sync_wave();
+    *out = nxt;
+    return m;
+}
+
+// The number sum of number_sum_wave restricted to listed leaves (a superset
+// of the leaves that meet the ball of radius 2h, in increasing order): the same
+// terms are added in the same order, so the result is bitwise the same.
+__device__ NumSum number_sum_list(double px, double py, double pz, double h, int64_t n_pts,
+                                  const double4 *__restrict__ pts, const double *__restrict__ bx, int64_t NL,
+                                  const int32_t *list, int cnt, int lane)
+{
+#pragma clang fp contract(off)
+    NumSum r{0.0, 0.0, 0};
+    const double R2 = 4.0 * h * h * (1.0 + 1e-9);
+    for (int base = 0; base < cnt; base += 64) {
+        const int i = base + lane;
+        double wv[kPtLeaf], dv[kPtLeaf];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < kPtLeaf; k++) {
+            wv[k] = 0.0;
+            dv[k] = 0.0;
+        }
+        if (i < cnt) {
+            const int64_t j = list[i];
+            if (box_gap2(bx + 6 * (NL + j), px, py, pz) <= R2) {
+#pragma unroll
+                for (int k = 0; k < kPtLeaf; k++) {
+                    const int64_t t = kPtLeaf * j + k;
+                    if (t < n_pts) {
+                        const double4 p = pts[t];
+                        const double q = sqrt(dist2(px, py, pz, p.x, p.y, p.z)) / h;
+                        if (q < 2.0) {
+                            wv[k] = m4_w(q);
+                            dv[k] = m4_qdw(q);
+                            any = true;
+                        }
+                    }
+                }
+            }
+        }
+        unsigned long long mask = __ballot(any);
+        while (mask) {
+            const int l = __ffsll((long long)mask) - 1;
+            mask &= mask - 1;
+#pragma unroll
+            for (int k = 0; k < kPtLeaf; k++) {
+                const double v = __shfl(wv[k], l, 64);
+                const double d = __shfl(dv[k], l, 64);
+                r.sum_w += v;
+                r.sum_qdw += d;
+                r.count += v != 0.0 ? 1 : 0;
+            }
+        }
+    }
+    return r;
+}
+
+// Number sums of one node's solve: the leaves met at the largest h evaluated
+// so far are kept and reused for every smaller h; a larger h lists them again;
+// when a list does not fit, the sum scans all leaves.
+struct LeafCache {
+    int32_t *buf0, *buf1, *list;
+    int cnt;       // -1: no list
+    double h;      // the list holds every leaf within 2 h (1 + 1e-9)
+};
+
+__device__ NumSum number_sum_cached(LeafCache &C, double px, double py, double pz, double h, int64_t n_pts,
+                                    const double4 *__restrict__ pts, const double *__restrict__ bx, int64_t NL,
+                                    int64_t nleaf, int lane)
+{
+    if (!(C.cnt >= 0 && h <= C.h)) {
+        C.cnt = collect_leaves(px, py, pz, 4.0 * h * h * (1.0 + 1e-9), bx, NL, lane, C.buf0, C.buf1, &C.list);
+        C.h = h;
+    }
+    if (C.cnt < 0) return number_sum_wave(px, py, pz, h, n_pts, pts, bx, NL, nleaf, lane);
+    return number_sum_list(px, py, pz, h, n_pts, pts, bx, NL, C.list, C.cnt, lane);
+}
+
 struct HStats {
     unsigned long long evals, neighbours, fallbacks;
 };
@@ -586,6 +734,9 @@ __global__ void __launch_bounds__(256) k_hsolve(int64_t n_pts, const double4 *__
     const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (t >= n_pts || pt_slot[t] < 0) return;  // wave-uniform
+    __shared__ int32_t lds_front[4][2][kFront];
+    const int wv = (int)(threadIdx.x >> 6);
+    LeafCache LC{lds_front[wv][0], lds_front[wv][1], nullptr, -1, 0.0};
     unsigned long long evals = 0, nb = 0, fb = 0;
     const int32_t nd = pt_node[t];
     const double4 x = pts[t];
@@ -604,24 +755,24 @@ __global__ void __launch_bounds__(256) k_hsolve(int64_t n_pts, const double4 *__
     NumSum Nh{};
     if (ok) {
         int k = 0;
-        Nh = number_sum_wave(x.x, x.y, x.z, hi, n_pts, pts, bx, NL, nleaf, lane);
+        Nh = number_sum_cached(LC, x.x, x.y, x.z, hi, n_pts, pts, bx, NL, nleaf, lane);
         evals++;
         if (Nh.sum_w / M_PI < target) {
             do {
                 lo = hi;
                 hi = 2.0 * hi;
-                Nh = number_sum_wave(x.x, x.y, x.z, hi, n_pts, pts, bx, NL, nleaf, lane);
+                Nh = number_sum_cached(LC, x.x, x.y, x.z, hi, n_pts, pts, bx, NL, nleaf, lane);
                 evals++;
             } while (Nh.sum_w / M_PI < target && ++k < 200);
         } else {
             lo = 0.5 * hi;
-            NumSum Nl = number_sum_wave(x.x, x.y, x.z, lo, n_pts, pts, bx, NL, nleaf, lane);
+            NumSum Nl = number_sum_cached(LC, x.x, x.y, x.z, lo, n_pts, pts, bx, NL, nleaf, lane);
             evals++;
             while (Nl.sum_w / M_PI >= target && ++k < 200) {
                 hi = lo;
                 Nh = Nl;
                 lo = 0.5 * lo;
-                Nl = number_sum_wave(x.x, x.y, x.z, lo, n_pts, pts, bx, NL, nleaf, lane);
+                Nl = number_sum_cached(LC, x.x, x.y, x.z, lo, n_pts, pts, bx, NL, nleaf, lane);
                 evals++;
             }
         }
@@ -641,7 +792,7 @@ __global__ void __launch_bounds__(256) k_hsolve(int64_t n_pts, const double4 *__
             double hn = dN > 0.0 ? hc - (N - target) / dN : 0.5 * (lo + hi);
             if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
             if (hn <= lo || hn >= hi) break;
-            const NumSum Nn = number_sum_wave(x.x, x.y, x.z, hn, n_pts, pts, bx, NL, nleaf, lane);
+            const NumSum Nn = number_sum_cached(LC, x.x, x.y, x.z, hn, n_pts, pts, bx, NL, nleaf, lane);
             evals++;
             if (Nn.sum_w / M_PI >= target) {
                 hi = hn;
@@ -1032,6 +1183,10 @@ int64_t walk_tree(Workspace &ws, const TreeState &TS, const DevParticles &P, con
         hipLaunchKernelGGL(k_pt_leaf_boxes, dim3(grid_of(NL)), dim3(256), 0, s, n_pts, NL, (const double4 *)pts,
                            bx);
         EM_HIP(hipGetLastError());
+        for (int64_t first = NL / 2; first >= 1; first /= 2) {
+            hipLaunchKernelGGL(k_pt_parent_boxes, dim3(grid_of(first)), dim3(256), 0, s, first, bx);
+            EM_HIP(hipGetLastError());
+        }
         hipLaunchKernelGGL(k_hsolve, dim3(grid_of(64 * n_pts)), dim3(256), 0, s, n_pts, (const double4 *)pts,
                            (const double *)bx, NL, nleaf, (const int64_t *)pt_slot, (const int32_t *)pt_node, T,
                            (const uint32_t *)perm, P.h, par.h_fact_node, O.h, hc);
