@@ -23,6 +23,7 @@ if os.path.exists(os.path.join(_HERE, "pseudo_oracle.c")):
 
 M4 = 0
 UNIT = 1
+TABLE = 2  # M4 through an interpolated table of the pyramid integral (use_table first)
 
 
 def build_lib(force: bool = True) -> str:
@@ -75,6 +76,11 @@ def _load():
         lib.orc_reduce.argtypes = [i64, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp]
         lib.orc_map_back.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp]
         lib.orc_num_threads.restype = i
+        lib.orc_table_build.argtypes = [i, i, i, vp]
+        lib.orc_table_use.argtypes = [vp, i, i, i]
+        for nm in ("orc_table_interp", "orc_solid_angle"):
+            getattr(lib, nm).restype = d
+            getattr(lib, nm).argtypes = [d, d, d]
         if hasattr(lib, "orp_pseudo"):
             u64 = ctypes.c_uint64
             lib.orp_morton.restype = u64
@@ -141,6 +147,35 @@ def pyramid(r0: float, R0: float, phi: float, profile: int = M4) -> float:
 
 
 # ---------------------------------------------------------------- per pair
+_TABLE = {}
+
+
+def table(n0: int = 64, n1: int = 64, n2: int = 64) -> np.ndarray:
+    """Node values of the pyramid integral (r0, R0 in [0, 2], phi in [0, pi/2]), shape (n0, n1, n2)."""
+    key = (n0, n1, n2)
+    if key not in _TABLE:
+        t = np.zeros((n0, n1, n2))
+        _load().orc_table_build(n0, n1, n2, _p(t))
+        _TABLE[key] = t
+    return _TABLE[key]
+
+
+def use_table(n0: int = 64, n1: int = 64, n2: int = 64) -> np.ndarray:
+    """Make profile TABLE read the table of this size; returns it."""
+    t = table(n0, n1, n2)
+    _load().orc_table_use(_p(t), n0, n1, n2)
+    return t
+
+
+def table_interp(r0: float, R0: float, phi: float) -> float:
+    """The pyramid integral through the table (trilinear on the grid, solid-angle identities outside)."""
+    return _load().orc_table_interp(r0, R0, phi)
+
+
+def solid_angle(r0: float, R0: float, phi: float) -> float:
+    return _load().orc_solid_angle(r0, R0, phi)
+
+
 def pair_fraction(p, h: float, cells, cell: int, profile: int = M4) -> float:
     g = _Geom(cells)
     pp = _f64(p)

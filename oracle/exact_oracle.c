@@ -69,7 +69,7 @@
 /* The integral of W = 1 over a cell is its volume, which pins the geometry. */
 /* ------------------------------------------------------------------------ */
 
-enum { ORC_M4 = 0, ORC_UNIT = 1 };
+enum { ORC_M4 = 0, ORC_UNIT = 1, ORC_TABLE = 2 /* M4 through the table below */ };
 
 static const int NEXP[6] = { -1, 0, 2, 3, 4, 5 };
 
@@ -226,11 +226,106 @@ typedef struct {
 
 static int sgn(double x) { return (x > 0.0) - (x < 0.0); }
 
+/* ------------------------------------------------------------------------ */
+/* Tabulated pyramid integral (the variant Sec. II-B describes: the integral  */
+/* is pre-computed and interpolated).  Reading (the paper gives no layout):   */
+/* I(r0, R0, phi) on a uniform grid of n0 x n1 x n2 nodes over r0 in [0, 2],  */
+/* R0 in [0, 2] and phi in [0, pi/2], read by trilinear interpolation.        */
+/* Outside the grid the pyramid's mass follows from the solid angle Omega of  */
+/* its triangle (elementary): the pyramid holds the kernel mass of its cone,  */
+/* Omega / (4 pi), less D, the mass of the cone beyond the wall.  D = 0 for   */
+/* r0 >= 2 (the wall lies beyond the support), and for R0 >= 2 D no longer    */
+/* depends on R0 (the support's cross-section with the wall, of radius        */
+/* sqrt(4 - r0^2) <= 2 about the foot, lies inside the triangle's wedge), so  */
+/*   r0 >= 2:  I = Omega / (4 pi)                                             */
+/*   R0 > 2:   I = I(r0, 2, phi) + (Omega(r0, R0, phi) - Omega(r0, 2, phi)) / (4 pi). */
+/* Node values come from orc_pyramid; the last phi plane is the limit         */
+/* phi -> pi/2, taken at pi/2 - 1e-12.                                        */
+/* ------------------------------------------------------------------------ */
+static const double *g_tab;
+static int g_tn0, g_tn1, g_tn2;
+
+static double tab_r0(int i, int n0) { return 2.0 * (double)i / (double)(n0 - 1); }
+static double tab_R0(int j, int n1) { return 2.0 * (double)j / (double)(n1 - 1); }
+static double tab_phi(int k, int n2)
+{
+    return k == n2 - 1 ? 0.5 * M_PI - 1e-12 : 0.5 * M_PI * (double)k / (double)(n2 - 1);
+}
+
+/* solid angle of the right triangle (legs R0 at the foot, angle phi there) seen
+ * from the apex at height r0 > 0: phi - r0 P_-1(phi) = phi - atan(r0 tan(phi) / S) */
+double orc_solid_angle(double r0, double R0, double phi)
+{
+    if (r0 <= 0.0 || R0 <= 0.0 || phi <= 0.0) return 0.0;
+    double t = tan(phi);
+    double S = sqrt(r0 * r0 + R0 * R0 * (1.0 + t * t));
+    return phi - atan(r0 * t / S);
+}
+
+/* node values, index (i * n1 + j) * n2 + k */
+void orc_table_build(int n0, int n1, int n2, double *tab)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int i = 0; i < n0; i++)
+        for (int j = 0; j < n1; j++)
+            for (int k = 0; k < n2; k++)
+                tab[((int64_t)i * n1 + j) * n2 + k] =
+                    orc_pyramid(ORC_M4, tab_r0(i, n0), tab_R0(j, n1), tab_phi(k, n2));
+}
+
+/* the table that ORC_TABLE reads (the caller keeps it alive) */
+void orc_table_use(const double *tab, int n0, int n1, int n2)
+{
+    g_tab = tab;
+    g_tn0 = n0;
+    g_tn1 = n1;
+    g_tn2 = n2;
+}
+
+/* grid coordinate x in [0, n - 1] -> lower node and weight */
+static void tab_cell(double x, int n, int *i, double *t)
+{
+    int k = (int)floor(x);
+    if (k < 0) k = 0;
+    if (k > n - 2) k = n - 2;
+    *i = k;
+    *t = x - (double)k;
+}
+
+static double tab_trilinear(double r0, double R0, double phi)
+{
+    int i, j, k;
+    double a, b, c;
+    tab_cell(r0 * (double)(g_tn0 - 1) / 2.0, g_tn0, &i, &a);
+    tab_cell(R0 * (double)(g_tn1 - 1) / 2.0, g_tn1, &j, &b);
+    tab_cell(phi * (double)(g_tn2 - 1) / (0.5 * M_PI), g_tn2, &k, &c);
+    double v = 0.0;
+    for (int di = 0; di < 2; di++)
+        for (int dj = 0; dj < 2; dj++)
+            for (int dk = 0; dk < 2; dk++) {
+                double w = (di ? a : 1.0 - a) * (dj ? b : 1.0 - b) * (dk ? c : 1.0 - c);
+                v += w * g_tab[((int64_t)(i + di) * g_tn1 + (j + dj)) * g_tn2 + (k + dk)];
+            }
+    return v;
+}
+
+/* the pyramid integral through the table */
+double orc_table_interp(double r0, double R0, double phi)
+{
+    if (r0 <= 0.0 || R0 <= 0.0 || phi <= 0.0) return 0.0;
+    if (!(r0 < 2.0)) return orc_solid_angle(r0, R0, phi) / (4.0 * M_PI);
+    if (R0 > 2.0)
+        return tab_trilinear(r0, 2.0, phi) +
+               (orc_solid_angle(r0, R0, phi) - orc_solid_angle(r0, 2.0, phi)) / (4.0 * M_PI);
+    return tab_trilinear(r0, R0, phi);
+}
+
 /* signed right-triangle term T(l) = sign(l) * I(r0, R0, atan(|l|/R0)) */
 static double tri_term(int profile, double r0, double R0, double l)
 {
     if (l == 0.0) return 0.0;
     double phi = atan(fabs(l) / R0);
+    if (profile == ORC_TABLE) return sgn(l) * orc_table_interp(r0, R0, phi);
     return sgn(l) * orc_pyramid(profile, r0, R0, phi);
 }
 
