@@ -57,10 +57,15 @@ enum {
 /* Arithmetic of the per-triangle closed-form terms. */
 enum {
     MAP_FP64 = 0,  /* everything in FP64 */
-    MAP_MIXED = 1  /* FP64 wall distance, foot point and edge projections; FP32
+    MAP_MIXED = 1, /* FP64 wall distance, foot point and edge projections; FP32
                       closed-form terms accumulated in FP64; FP64 recomputation
                       of terms flagged by a conditioning test; FP64
                       normalisation and reductions */
+    MAP_TABLE = 2  /* the pyramid integral read from a table (map_set_table):
+                      FP64 geometry, FP32 solid angle and trilinear
+                      interpolation, FP64 sums; an approximation whose error
+                      is set by the table size, not a precision of the
+                      closed form */
 };
 
 enum { MAP_MEM_HOST = 0, MAP_MEM_DEVICE = 1 };
@@ -69,7 +74,7 @@ typedef struct map_ctx map_ctx;
 
 typedef struct map_config {
     int device;                /* HIP device ordinal */
-    int precision;             /* MAP_FP64 or MAP_MIXED, default for map_particles */
+    int precision;             /* MAP_FP64, MAP_MIXED or MAP_TABLE, default for map_particles */
     uint64_t hbm_budget_bytes; /* serving admission budget; 0 = 80% of free device memory */
     int max_jobs;              /* serving: jobs resident on the device at once (0 = 8) */
     int max_queue;             /* serving: jobs waiting for admission (0 = 1024) */
@@ -143,8 +148,29 @@ int map_init(const map_config *cfg, map_ctx **out);
 /* Drain the serving loop, free all device memory and the context. */
 int map_shutdown(map_ctx *ctx);
 const char *map_last_error(map_ctx *ctx);
-/* Change the default precision of map_particles (MAP_FP64 / MAP_MIXED). */
+/* Change the default precision of map_particles (MAP_FP64 / MAP_MIXED / MAP_TABLE). */
 int map_set_precision(map_ctx *ctx, int precision);
+
+/*
+ * Tabulated variant (Sec. II-B: the vertex-pyramid integral pre-computed and
+ * interpolated).  The table holds I(r0, R0, phi) of the M4 kernel (lengths in
+ * units of h) on a uniform grid of n0 x n1 x n2 nodes,
+ *     r0 = 2 i / (n0 - 1),  R0 = 2 j / (n1 - 1),  phi = (pi/2) k / (n2 - 1)
+ * (the last phi plane at pi/2 - 1e-12), node (i, j, k) at index
+ * (i n1 + j) n2 + k, computed on the device from the FP64 closed form and
+ * read in FP32 by trilinear interpolation.  Outside the grid the pyramid's
+ * mass follows exactly from its triangle's solid angle: beyond r0 = 2 the
+ * pyramid holds its whole cone, and beyond R0 = 2 the mass cut off by the
+ * wall no longer depends on R0.  MAP_TABLE mappings assemble the cell
+ * integrals from it (no FP64 fixups); S_a then deviates from 1 in the interior
+ * by the table's error and the sum-to-one normalisation keeps the total mass.
+ * map_set_table: each size in [8, 1024] and at most 2^27 nodes (default
+ * 64 x 64 x 64); the table is rebuilt on the next MAP_TABLE mapping.
+ * map_get_table: the FP64 node values of the current size (host memory,
+ * n0 n1 n2 doubles; built if needed).
+ */
+int map_set_table(map_ctx *ctx, int n0, int n1, int n2);
+int map_get_table(map_ctx *ctx, double *values);
 
 /*
  * Launch shape of the integration kernel for one precision (the autotuner's

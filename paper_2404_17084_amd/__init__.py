@@ -28,6 +28,7 @@ MAP_ENUMERIC = -7
 MAP_ENOTSUP = -8
 MAP_FP64 = 0
 MAP_MIXED = 1
+MAP_TABLE = 2
 MAP_MEM_HOST = 0
 MAP_MEM_DEVICE = 1
 JOB_PENDING, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
@@ -147,6 +148,8 @@ _SIGS = {
                                     ctypes.POINTER(map_pseudo_params), ctypes.POINTER(map_adapt_params),
                                     ctypes.POINTER(map_pseudo_out), ctypes.POINTER(map_adapt_stats)]),
     "map_get_regions": (c_int, [c_vp, c_i64, c_vp, ctypes.POINTER(c_i64)]),
+    "map_set_table": (c_int, [c_vp, c_int, c_int, c_int]),
+    "map_get_table": (c_int, [c_vp, c_vp]),
     "map_set_regions": (c_int, [c_vp, c_i64, c_vp]),
 }
 
@@ -281,6 +284,18 @@ def map_last_error(ctx) -> str:
 
 def map_set_precision(ctx, precision: int):
     _check(ctx, load().map_set_precision(ctx, precision))
+
+
+def map_set_table(ctx, n0: int = 64, n1: int = 64, n2: int = 64):
+    """Size of the MAP_TABLE table of the pyramid integral (rebuilt on next use)."""
+    _check(ctx, load().map_set_table(ctx, int(n0), int(n1), int(n2)))
+
+
+def map_get_table(ctx, shape):
+    """FP64 node values of the table of the given (current) size, as an array of that shape."""
+    out = np.zeros(tuple(int(x) for x in shape))
+    _check(ctx, load().map_get_table(ctx, _ptr(out)))
+    return out
 
 
 def map_set_tune(ctx, precision, waves=0, tile_waves=1, grid_per_cu=8, persistent=1):
@@ -526,6 +541,13 @@ class Mapper:
 
     def set_precision(self, precision):
         map_set_precision(self.ctx, precision)
+
+    def set_table(self, n0=64, n1=64, n2=64):
+        map_set_table(self.ctx, n0, n1, n2)
+        self._table_shape = (n0, n1, n2)
+
+    def table(self):
+        return map_get_table(self.ctx, getattr(self, "_table_shape", (64, 64, 64)))
 
     def back(self, cell_values, out=None):
         """Inverse mapping with the pairs of this mapper's last map()."""

@@ -34,6 +34,8 @@ Ctx::~Ctx()
     (void)hipSetDevice(device);
     if (stream) (void)hipStreamSynchronize(stream);
     ws.release();
+    if (table.d64) (void)hipFree(table.d64);
+    if (table.d32) (void)hipFree(table.d32);
     for (auto &e : ev)
         if (e) (void)hipEventDestroy(e);
     if (stream) (void)hipStreamDestroy(stream);
@@ -162,7 +164,8 @@ __global__ void k_u32_to_i32(const uint32_t *in, int32_t *out, int64_t n)
 void stage_pairs(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_in *c, int precision,
                  JobState &js, hipStream_t s)
 {
-    EM_CHECK(precision == MAP_FP64 || precision == MAP_MIXED, MAP_EINVAL, "precision must be MAP_FP64 or MAP_MIXED");
+    EM_CHECK(precision == MAP_FP64 || precision == MAP_MIXED || precision == MAP_TABLE, MAP_EINVAL,
+             "precision must be MAP_FP64, MAP_MIXED or MAP_TABLE");
     js.precision = precision;
     prepare(C, ws, p, c, js.in, js.edges, js.aabb, js.flags, js.counters, s);
     if (js.ev_setup) EM_HIP(hipEventRecord(js.ev_setup, s));
@@ -264,6 +267,22 @@ int64_t stage_finish(Ctx &C, Workspace &ws, JobState &js, const map_out *out, hi
     return n_fix;
 }
 
+// The table of the tabulated variant at the context's size (built once per size).
+void ensure_table(Ctx &C, hipStream_t s)
+{
+    if (C.table.built) return;
+    const size_t nodes = (size_t)C.table.n[0] * C.table.n[1] * C.table.n[2];
+    if (C.table.d64) EM_HIP(hipFree(C.table.d64));
+    if (C.table.d32) EM_HIP(hipFree(C.table.d32));
+    C.table.d64 = nullptr;
+    C.table.d32 = nullptr;
+    EM_HIP(hipMalloc(&C.table.d64, sizeof(double) * nodes));
+    EM_HIP(hipMalloc(&C.table.d32, sizeof(float) * nodes));
+    launch_table_build(C.table.n[0], C.table.n[1], C.table.n[2], C.table.d64, C.table.d32, s);
+    EM_HIP(hipStreamSynchronize(s));
+    C.table.built = true;
+}
+
 // The whole synchronous mapping of one job on stream s with workspace ws.
 void run_mapping(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_in *c, const map_out *out,
                  int precision, hipStream_t s, bool timed)
@@ -274,11 +293,18 @@ void run_mapping(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cel
         js.ev_setup = C.ev[1];
     }
     stage_pairs(C, ws, p, c, precision, js, s);
-    const IntegrateTune tune = pick_tune(C, precision, js.ps.n_pairs);
-    if (tune.persistent == 2) build_tiles(ws, js.in, js.ps, s);
-    if (timed) EM_HIP(hipEventRecord(C.ev[2], s));
-    launch_integrate(js.in, js.edges, js.ps, precision, tune, js.f, js.counters, js.tile_ctr, js.fix_items, js.fix_cap,
-                     s);
+    if (precision == MAP_TABLE) {
+        ensure_table(C, s);
+        if (timed) EM_HIP(hipEventRecord(C.ev[2], s));
+        launch_integrate_table(js.in, js.edges, js.ps, C.table.d32, C.table.n[0], C.table.n[1], C.table.n[2], js.f,
+                               js.counters, s);
+    } else {
+        const IntegrateTune tune = pick_tune(C, precision, js.ps.n_pairs);
+        if (tune.persistent == 2) build_tiles(ws, js.in, js.ps, s);
+        if (timed) EM_HIP(hipEventRecord(C.ev[2], s));
+        launch_integrate(js.in, js.edges, js.ps, precision, tune, js.f, js.counters, js.tile_ctr, js.fix_items,
+                         js.fix_cap, s);
+    }
     if (timed) {
         EM_HIP(hipEventRecord(C.ev[3], s));
         js.ev_fix = C.ev[4];
@@ -351,7 +377,8 @@ int map_init(const map_config *cfg, map_ctx **out)
     }
     int dev = cfg ? cfg->device : 0;
     if (dev < 0 || dev >= ndev) return MAP_EINVAL;
-    if (cfg && cfg->precision != MAP_FP64 && cfg->precision != MAP_MIXED) return MAP_EINVAL;
+    if (cfg && cfg->precision != MAP_FP64 && cfg->precision != MAP_MIXED && cfg->precision != MAP_TABLE)
+        return MAP_EINVAL;
     try {
         *out = reinterpret_cast<map_ctx *>(new Ctx(cfg));
     } catch (const em::Error &e) {
@@ -381,8 +408,37 @@ int map_set_precision(map_ctx *h, int precision)
 {
     Ctx *C = reinterpret_cast<Ctx *>(h);
     API_BODY(C, {
-        EM_CHECK(precision == MAP_FP64 || precision == MAP_MIXED, MAP_EINVAL, "precision must be MAP_FP64 or MAP_MIXED");
+        EM_CHECK(precision == MAP_FP64 || precision == MAP_MIXED || precision == MAP_TABLE, MAP_EINVAL,
+                 "precision must be MAP_FP64, MAP_MIXED or MAP_TABLE");
         C->precision = precision;
+    });
+}
+
+int map_set_table(map_ctx *h, int n0, int n1, int n2)
+{
+    Ctx *C = reinterpret_cast<Ctx *>(h);
+    API_BODY(C, {
+        EM_CHECK(n0 >= 8 && n0 <= 1024 && n1 >= 8 && n1 <= 1024 && n2 >= 8 && n2 <= 1024, MAP_EINVAL,
+                 "table sizes must be in [8, 1024]");
+        EM_CHECK((int64_t)n0 * n1 * n2 <= ((int64_t)1 << 27), MAP_EINVAL, "table larger than 2^27 nodes");
+        if (n0 != C->table.n[0] || n1 != C->table.n[1] || n2 != C->table.n[2]) {
+            C->table.n[0] = n0;
+            C->table.n[1] = n1;
+            C->table.n[2] = n2;
+            C->table.built = false;
+        }
+    });
+}
+
+int map_get_table(map_ctx *h, double *values)
+{
+    Ctx *C = reinterpret_cast<Ctx *>(h);
+    API_BODY(C, {
+        EM_CHECK(values, MAP_EINVAL, "null values buffer");
+        ensure_table(*C, C->stream);
+        const size_t nodes = (size_t)C->table.n[0] * C->table.n[1] * C->table.n[2];
+        EM_HIP(hipMemcpyAsync(values, C->table.d64, sizeof(double) * nodes, hipMemcpyDeviceToHost, C->stream));
+        EM_HIP(hipStreamSynchronize(C->stream));
     });
 }
 

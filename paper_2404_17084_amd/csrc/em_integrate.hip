@@ -1215,7 +1215,45 @@ __global__ void k_fixup_apply(int64_t n_fix, const uint64_t *__restrict__ keys, 
     f[k] += sum;
 }
 
+// Node values of the tabulated pyramid integral I(r0, R0, phi) (the variant of
+// Sec. II-B that interpolates a pre-computed table): r0 = 2 i / (n0 - 1),
+// R0 = 2 j / (n1 - 1), phi = (pi/2) k / (n2 - 1) (the last plane at
+// pi/2 - 1e-12), from the FP64 closed form above:
+//     I = Omega / (4 pi) - (1/pi) [pi (Q - phi H)](0 .. l),   l = R0 tan(phi),
+// with the triangle's solid angle Omega = atan2(l R0 (R0^2 + l^2), (S + r0)(R0^2 S + r0 l^2)).
+__global__ void k_table_build(int n0, int n1, int n2, double *__restrict__ tab64, float *__restrict__ tab32)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)n0 * n1 * n2;
+    if (q >= total) return;
+    const int k = (int)(q % n2);
+    const int j = (int)((q / n2) % n1);
+    const int i = (int)(q / ((int64_t)n1 * n2));
+    const double r0 = 2.0 * i / (double)(n0 - 1);
+    const double R0 = 2.0 * j / (double)(n1 - 1);
+    const double phi = k == n2 - 1 ? 0.5 * M_PI - 1e-12 : 0.5 * M_PI * k / (double)(n2 - 1);
+    double I = 0.0;
+    if (r0 > 0.0 && R0 > 0.0 && phi > 0.0) {
+        const double l = R0 * tan(phi);
+        const double S = sqrt(r0 * r0 + R0 * R0 + l * l);
+        const double om = atan2(l * R0 * (R0 * R0 + l * l), (S + r0) * (R0 * R0 * S + r0 * l * l));
+        Work wk;
+        const double e = edge_term<double>(r0, R0, 0.0, l, pi_H<double>(r0), pi_dH<double>(r0), wk);
+        I = om * (0.25 * kInvPi) - e * kInvPi;
+    }
+    tab64[q] = I;
+    tab32[q] = (float)I;
+}
+
 }  // namespace
+
+void launch_table_build(int n0, int n1, int n2, double *tab64, float *tab32, hipStream_t s)
+{
+    const int64_t total = (int64_t)n0 * n1 * n2;
+    hipLaunchKernelGGL(k_table_build, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, n0, n1, n2, tab64,
+                       tab32);
+    EM_HIP(hipGetLastError());
+}
 
 void build_tiles(Workspace &ws, const DevInputs &in, PairSet &ps, hipStream_t s)
 {

@@ -230,6 +230,12 @@ void launch_fixup(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, 
 // adds sorted fixup values into f
 void launch_fixup_apply(const uint64_t *keys, const double *vals, int64_t n_fix, double *f, hipStream_t s);
 
+// em_integrate.hip: node values of the tabulated pyramid integral (FP64 and FP32 copies)
+void launch_table_build(int n0, int n1, int n2, double *tab64, float *tab32, hipStream_t s);
+// em_table.hip: raw f per pair through the table (cell-major order)
+void launch_integrate_table(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, const float *tab, int n0,
+                            int n1, int n2, double *f, int64_t *counters, hipStream_t s);
+
 // em_reduce.hip
 void launch_reduce(const DevInputs &in, const PairSet &ps, const double *f, double *S, double *M,
                    double *rho, double *red, unsigned *flags, hipStream_t s);

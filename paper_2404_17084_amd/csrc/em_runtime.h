@@ -41,6 +41,13 @@ struct Ctx {
     } back;
     // remembered regions of the adaptive walk (cx, cy, cz, R, s_min per region)
     std::vector<double> regions;
+    // table of the pyramid integral for MAP_TABLE (built on first use)
+    struct {
+        int n[3] = {64, 64, 64};
+        bool built = false;
+        double *d64 = nullptr;
+        float *d32 = nullptr;
+    } table;
 };
 
 IntegrateTune default_tune(int precision);
@@ -74,6 +81,8 @@ void prepare(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_i
 void run_mapping(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_in *c, const map_out *out,
                  int precision, hipStream_t s, bool timed);
 void serve_stop(Ctx &C);
+// Builds the context's MAP_TABLE table if its size changed or it was never built.
+void ensure_table(Ctx &C, hipStream_t s);
 // Device-memory footprint estimate of a served job (admission against the budget).
 size_t job_footprint(const map_particles_in *p, const map_cells_in *c);
 // Whether map_submit accepts jobs (em_api.cpp).

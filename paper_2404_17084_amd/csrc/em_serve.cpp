@@ -350,6 +350,8 @@ extern "C" int map_submit(map_ctx *h, const map_particles_in *p, const map_cells
                  "served mapping is switched off: a device run of it stopped making progress and the cause is not "
                  "yet found; use map_particles");
         EM_HIP(hipSetDevice(C->device));
+        EM_CHECK(C->precision == MAP_FP64 || C->precision == MAP_MIXED, MAP_EINVAL,
+                 "served mapping runs at MAP_FP64 or MAP_MIXED");
         EM_CHECK(out && job_id, MAP_EINVAL, "null output descriptor or job id");
         EM_CHECK(out->mem_kind == MAP_MEM_HOST || out->mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad output mem_kind");
         EM_CHECK(p && c, MAP_EINVAL, "null particle or cell descriptor");
