@@ -185,6 +185,36 @@ def adaptive_leg(em, mp, xyz, m, h, src, par):
             "step1": one(r1, a1), "step2_with_regions": one(r2, a2)}
 
 
+def table_leg(em, mapper, p, xyz, m, h, dc, M, rho, S, M_fp64, steps, warmup):
+    """The tabulated variant (MAP_TABLE) on the same workload at two table sizes: throughput, and its
+    error against the FP64 closed form (cell masses, interior S_a)."""
+    import torch
+    interior = np.all((p.xyz > 2 * p.h[:, None]) & (p.xyz < 1 - 2 * p.h[:, None]), axis=1)
+    mapper.set_precision(em.MAP_TABLE)
+    out = {}
+    for n in (64, 128):
+        em.map_set_table(mapper.ctx, n, n, n)
+        for _ in range(max(warmup, 1)):  # the first call builds the table
+            em.map_particles(mapper.ctx, xyz, m, h, dc, M, rho, S)
+        torch.cuda.synchronize()
+        stats = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            stats.append(em.map_particles(mapper.ctx, xyz, m, h, dc, M, rho, S))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        rel = np.abs(M.cpu().numpy() - M_fp64) / np.abs(M_fp64)
+        s_dev = np.abs(S.cpu().numpy()[interior] - 1.0)
+        out[f"{n}^3"] = {"pairs_per_s": stats[-1]["n_pairs"] / dt, "ms_per_step": 1e3 * dt,
+                         "ms_integrate": float(np.mean([s["ms_integrate"] for s in stats])),
+                         "cell_rel_err_vs_fp64_max": float(rel.max()), "cell_rel_err_vs_fp64_mean": float(rel.mean()),
+                         "interior_abs_S_minus_1_max": float(s_dev.max()),
+                         "interior_abs_S_minus_1_mean": float(s_dev.mean())}
+    em.map_set_table(mapper.ctx, 64, 64, 64)
+    mapper.set_precision(em.MAP_FP64)
+    return out
+
+
 def back_leg(em, mapper, p, M, nc, steps):
     """Inverse mapping (Eq. (4)) with the pairs of the last (mixed) mapping: a
     random cell field gathered to the particles, device buffers."""
@@ -282,6 +312,8 @@ def main():
         print(f"bench: {name}: {results[name]}", file=sys.stderr, flush=True)
     back = back_leg(em, mapper, p, M, nc, args.steps)
     print(f"bench: inverse mapping: {back}", file=sys.stderr, flush=True)
+    table = table_leg(em, mapper, p, xyz, m, h, dc, M, rho, S, Ms["fp64"], args.steps, args.warmup)
+    print(f"bench: tabulated variant: {table}", file=sys.stderr, flush=True)
     mapper.close()
     rel = np.abs(Ms["mixed"] - Ms["fp64"]) / np.abs(Ms["fp64"])
 
@@ -313,6 +345,7 @@ def main():
         "stages_ms_mixed": {k: mx[k] for k in ("ms_setup", "ms_pairs", "ms_integrate", "ms_reduce")},
         "launch_shape": tuned,
         "inverse_mapping": back,
+        "tabulated": table,
         "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32, "unit": "TFLOP/s", "frac": ach / PEAK_FP32,
                      "traffic": measured_traffic()},
     }
