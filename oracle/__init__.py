@@ -20,6 +20,8 @@ _SO = os.path.join(_HERE, "_build", "liboracle.so")
 _SRCS = [os.path.join(_HERE, "exact_oracle.c")]
 if os.path.exists(os.path.join(_HERE, "pseudo_oracle.c")):
     _SRCS.append(os.path.join(_HERE, "pseudo_oracle.c"))
+if os.path.exists(os.path.join(_HERE, "voronoi_oracle.c")):
+    _SRCS.append(os.path.join(_HERE, "voronoi_oracle.c"))
 
 M4 = 0
 UNIT = 1
@@ -96,6 +98,8 @@ def _load():
             lib.orp_pseudo2.restype = i64
             lib.orp_pseudo2.argtypes = ([i64, vp, vp, vp, vp, i, vp, d, d, d, i, d, i64, vp, i64, vp, i64] +
                                         [vp] * 7 + [vp, i64, vp])
+        if hasattr(lib, "orv_voronoi"):
+            lib.orv_voronoi.argtypes = [i64, vp, vp, i64, i64] + [vp] * 8
         _lib = lib
     return _lib
 
@@ -487,3 +491,35 @@ def pseudo_adaptive(xyz, m, h, box, sources, field, theta=0.5, r_part=0.05, r_le
     P.update(f_neu=f, walks=walks, converged=converged, r_part=r_part, r_leaf=r_leaf, failed=failed,
              regions=out_regions, dropped=regions_in.shape[0] - len(keep))
     return P
+
+
+# ---------------------------------------------------------------- Voronoi grid (Sec. II-A)
+def voronoi(sites, box):
+    """Box-clipped Voronoi cells of the sites (brute force: every site clips every cell).
+
+    Returns a dict with the cell arrays (cell_face_off, face_vert_off, face_vert, face_plane,
+    face_nb, verts, cell_volume; every face owns its vertex copies) and the cell centroids."""
+    lib = _load()
+    s, bb = _f64(sites).reshape(-1, 3), _f64(box)
+    n = s.shape[0]
+    cnt = np.zeros(3, np.int64)
+    lib.orv_voronoi(n, _p(s), _p(bb), 0, 0, _p(cnt), *([None] * 7))
+    nf, ns = int(cnt[0]), int(cnt[1])
+    out = dict(cell_face_off=np.zeros(n + 1, np.int64), face_vert_off=np.zeros(nf + 1, np.int64),
+               face_plane=np.zeros((nf, 4)), face_nb=np.zeros(nf, np.int64), verts=np.zeros((ns, 3)),
+               cell_volume=np.zeros(n), centroid=np.zeros((n, 3)))
+    lib.orv_voronoi(n, _p(s), _p(bb), nf, ns, _p(cnt), *[_p(out[k]) for k in (
+        "cell_face_off", "face_vert_off", "face_plane", "face_nb", "verts", "cell_volume", "centroid")])
+    out["face_vert"] = np.arange(ns, dtype=np.int32)
+    return out
+
+
+def lloyd(sites, box, iterations: int = 5):
+    """Lloyd iterations (sites moved to their cells' centroids), then the cells of the final sites."""
+    s = _f64(sites).reshape(-1, 3).copy()
+    for _ in range(iterations):
+        s = voronoi(s, box)["centroid"].copy()
+    V = voronoi(s, box)
+    V["sites"] = s
+    return V
+
