@@ -100,6 +100,7 @@ def _load():
                                         [vp] * 7 + [vp, i64, vp])
         if hasattr(lib, "orv_voronoi"):
             lib.orv_voronoi.argtypes = [i64, vp, vp, i64, i64] + [vp] * 8
+            lib.orv_voronoi_sel.argtypes = [i64, vp, vp, vp, i64, i64, i64] + [vp] * 8
         _lib = lib
     return _lib
 
@@ -494,21 +495,29 @@ def pseudo_adaptive(xyz, m, h, box, sources, field, theta=0.5, r_part=0.05, r_le
 
 
 # ---------------------------------------------------------------- Voronoi grid (Sec. II-A)
-def voronoi(sites, box):
+def voronoi(sites, box, sel=None):
     """Box-clipped Voronoi cells of the sites (brute force: every site clips every cell).
 
     Returns a dict with the cell arrays (cell_face_off, face_vert_off, face_vert, face_plane,
-    face_nb, verts, cell_volume; every face owns its vertex copies) and the cell centroids."""
+    face_nb, verts, cell_volume; every face owns its vertex copies) and the cell centroids;
+    with `sel`, only the selected cells, in that order."""
     lib = _load()
     s, bb = _f64(sites).reshape(-1, 3), _f64(box)
     n = s.shape[0]
+    if sel is None:
+        sp, ns_ = None, 0
+        nc = n
+    else:
+        sel = np.ascontiguousarray(sel, dtype=np.int64)
+        sp, ns_ = _p(sel), sel.size
+        nc = sel.size
     cnt = np.zeros(3, np.int64)
-    lib.orv_voronoi(n, _p(s), _p(bb), 0, 0, _p(cnt), *([None] * 7))
+    lib.orv_voronoi_sel(n, _p(s), _p(bb), sp, ns_, 0, 0, _p(cnt), *([None] * 7))
     nf, ns = int(cnt[0]), int(cnt[1])
-    out = dict(cell_face_off=np.zeros(n + 1, np.int64), face_vert_off=np.zeros(nf + 1, np.int64),
+    out = dict(cell_face_off=np.zeros(nc + 1, np.int64), face_vert_off=np.zeros(nf + 1, np.int64),
                face_plane=np.zeros((nf, 4)), face_nb=np.zeros(nf, np.int64), verts=np.zeros((ns, 3)),
-               cell_volume=np.zeros(n), centroid=np.zeros((n, 3)))
-    lib.orv_voronoi(n, _p(s), _p(bb), nf, ns, _p(cnt), *[_p(out[k]) for k in (
+               cell_volume=np.zeros(nc), centroid=np.zeros((nc, 3)))
+    lib.orv_voronoi_sel(n, _p(s), _p(bb), sp, ns_, nf, ns, _p(cnt), *[_p(out[k]) for k in (
         "cell_face_off", "face_vert_off", "face_plane", "face_nb", "verts", "cell_volume", "centroid")])
     out["face_vert"] = np.arange(ns, dtype=np.int32)
     return out

@@ -169,6 +169,27 @@ static void clip(orv_cell *C, const double *n, double c, int64_t nb)
     if (0.5 * fabs(dot3(s, n)) > ORV_EPS * ORV_EPS) C->nf++;
 }
 
+static const double *g_dist;
+static int by_dist(const void *a, const void *b)
+{
+    const double x = g_dist[*(const int64_t *)a], y = g_dist[*(const int64_t *)b];
+    return (x > y) - (x < y);
+}
+
+/* farthest vertex of the cell from s */
+static double max_dist(const orv_cell *C, const double *s)
+{
+    double m = 0.0;
+    for (int i = 0; i < C->nf; i++)
+        for (int a = 0; a < C->f[i].nv; a++) {
+            const double *v = C->f[i].v[a];
+            const double d[3] = {v[0] - s[0], v[1] - s[1], v[2] - s[2]};
+            const double r = sqrt(dot3(d, d));
+            m = r > m ? r : m;
+        }
+    return m;
+}
+
 /* volume and centroid: tetrahedra (apex a point inside, base a fan of each face) */
 static void measure(const orv_cell *C, const double *apex, double *vol, double *cen)
 {
@@ -194,27 +215,50 @@ static void measure(const orv_cell *C, const double *apex, double *vol, double *
 }
 
 /*
- * Box-clipped Voronoi cells of n sites.  Count-then-fill: counts[0..2] =
- * faces, face-vertex slots (= vertices, one copy per face); arrays are
- * written when cap_faces >= faces and cap_verts >= slots:
- *   cell_face_off (n+1), face_vert_off (faces+1), face_plane (4 faces),
- *   face_nb (faces), verts (3 slots; face_vert is the identity), vol (n),
- *   centroid (3n).
+ * Box-clipped Voronoi cells of n sites, or of the n_sel selected ones (sel
+ * non-NULL; outputs then follow the selection order).  A selected cell takes
+ * the other sites in order of distance and stops at the first one at least
+ * twice as far as its farthest vertex: that site's bisector lies half its
+ * distance away, beyond every point of the cell, and so does every farther
+ * one's (this keeps sampled cells of large site sets affordable; without a
+ * selection every site clips every cell).  Count-then-fill:
+ * counts[0..1] = faces, face-vertex slots (= vertices, one copy per face);
+ * arrays are written when cap_faces >= faces and cap_verts >= slots:
+ *   cell_face_off (cells+1), face_vert_off (faces+1), face_plane (4 faces),
+ *   face_nb (faces), verts (3 slots; face_vert is the identity), vol (cells),
+ *   centroid (3 cells).
  */
-void orv_voronoi(int64_t n, const double *sites, const double *box, int64_t cap_faces, int64_t cap_verts,
-                 int64_t *counts, int64_t *cell_face_off, int64_t *face_vert_off, double *face_plane,
-                 int64_t *face_nb, double *verts, double *vol, double *centroid)
+void orv_voronoi_sel(int64_t n, const double *sites, const double *box, const int64_t *sel, int64_t n_sel,
+                     int64_t cap_faces, int64_t cap_verts, int64_t *counts, int64_t *cell_face_off,
+                     int64_t *face_vert_off, double *face_plane, int64_t *face_nb, double *verts, double *vol,
+                     double *centroid)
 {
     orv_cell *C = (orv_cell *)malloc(sizeof(orv_cell));
     int64_t nf = 0, ns = 0;
     const int fill = cell_face_off != NULL;
     if (fill) cell_face_off[0] = 0;
     if (fill) face_vert_off[0] = 0;
-    for (int64_t i = 0; i < n; i++) {
+    const int64_t n_cells = sel ? n_sel : n;
+    double *dist = sel ? (double *)malloc(sizeof(double) * (size_t)n) : NULL;
+    int64_t *ord = sel ? (int64_t *)malloc(sizeof(int64_t) * (size_t)n) : NULL;
+    for (int64_t ci = 0; ci < n_cells; ci++) {
+        const int64_t i = sel ? sel[ci] : ci;
         const double *s = sites + 3 * i;
         box_cell(C, box);
-        for (int64_t j = 0; j < n; j++) {
+        if (sel) {
+            for (int64_t j = 0; j < n; j++) {
+                const double *t = sites + 3 * j;
+                const double d[3] = {t[0] - s[0], t[1] - s[1], t[2] - s[2]};
+                dist[j] = sqrt(dot3(d, d));
+                ord[j] = j;
+            }
+            g_dist = dist;
+            qsort(ord, (size_t)n, sizeof(int64_t), by_dist);
+        }
+        for (int64_t jj = 0; jj < n; jj++) {
+            const int64_t j = sel ? ord[jj] : jj;
             if (j == i) continue;
+            if (sel && dist[j] >= 2.0 * max_dist(C, s)) break;
             const double *t = sites + 3 * j;
             double d[3] = {t[0] - s[0], t[1] - s[1], t[2] - s[2]};
             const double l = sqrt(dot3(d, d));
@@ -238,8 +282,8 @@ void orv_voronoi(int64_t n, const double *sites, const double *box, int64_t cap_
                     for (int k = 0; k < F->nv; k++)
                         memcpy(verts + 3 * (face_vert_off[q] + k), F->v[k], sizeof(double) * 3);
             }
-            cell_face_off[i + 1] = nf + C->nf;
-            measure(C, s, vol + i, centroid + 3 * i);
+            cell_face_off[ci + 1] = nf + C->nf;
+            measure(C, s, vol + ci, centroid + 3 * ci);
         }
         nf += C->nf;
         for (int a = 0; a < C->nf; a++) ns += C->f[a].nv;
@@ -247,4 +291,14 @@ void orv_voronoi(int64_t n, const double *sites, const double *box, int64_t cap_
     counts[0] = nf;
     counts[1] = ns;
     free(C);
+    free(dist);
+    free(ord);
+}
+
+void orv_voronoi(int64_t n, const double *sites, const double *box, int64_t cap_faces, int64_t cap_verts,
+                 int64_t *counts, int64_t *cell_face_off, int64_t *face_vert_off, double *face_plane,
+                 int64_t *face_nb, double *verts, double *vol, double *centroid)
+{
+    orv_voronoi_sel(n, sites, box, NULL, 0, cap_faces, cap_verts, counts, cell_face_off, face_vert_off, face_plane,
+                    face_nb, verts, vol, centroid);
 }

@@ -136,3 +136,17 @@ def test_lloyd_lowers_the_energy():
     V = oracle.lloyd(synth.particles("clumps", 300, 83).xyz, BOX, 5)
     assert np.allclose(V["sites"], s, atol=1e-15)
     assert V["cell_volume"].sum() == pytest.approx(1.0, rel=1e-12)
+
+
+def test_selected_cells_with_the_stopping_rule_equal_the_full_build(clumpy):
+    """Sampled cells stop at the first site twice as far as the farthest vertex; they must equal the cells
+    that every site clipped."""
+    sites, V = clumpy
+    sel = np.arange(0, len(sites), 3)
+    S = oracle.voronoi(sites, BOX, sel=sel)
+    assert np.allclose(S["cell_volume"], V["cell_volume"][sel], rtol=1e-13, atol=0)
+    assert np.allclose(S["centroid"], V["centroid"][sel], atol=1e-14)
+    for t, i in enumerate(sel):
+        a = sorted(S["face_nb"][S["cell_face_off"][t]:S["cell_face_off"][t + 1]].tolist())
+        b = sorted(V["face_nb"][V["cell_face_off"][i]:V["cell_face_off"][i + 1]].tolist())
+        assert a == b
