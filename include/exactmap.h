@@ -380,6 +380,42 @@ int map_get_regions(map_ctx *ctx, int64_t capacity, double *regions, int64_t *n_
 int map_set_regions(map_ctx *ctx, int64_t n_regions, const double *regions);
 
 /*
+ * Voronoi grid (Sec. II-A): the box-clipped Voronoi cells of n sites (the
+ * particle positions, or any distinct points in the box), relaxed by
+ * lloyd_iters Lloyd iterations (each site moved to its cell's centroid, the
+ * grid rebuilt; the paper applies 5).  Cell i belongs to site i.  Each cell is
+ * the box cut by the bisector planes of its nearest sites, taken nearest
+ * first until no farther site can reach it; a vertex within 1e-12 of a
+ * cutting plane counts as on it.  Output in the cell format of
+ * map_cells_in: faces counter-clockwise about outward unit normals (n.x = c),
+ * vertices per cell (shared by its faces), volumes; plus the site or wall
+ * across each face (-1 - w for walls x-, x+, y-, y+, z-, z+), the sites after
+ * the Lloyd iterations and the cell centroids.
+ * The arrays are device memory owned by the context (out->cells has mem_kind
+ * MAP_MEM_DEVICE and can be passed to map_particles as it is), valid until the
+ * next map_voronoi or map_shutdown; map_voronoi_copy copies them into caller
+ * buffers (NULL skips an array) sized by the counts in out.
+ * sites: 3 n doubles in mem_kind memory.  Errors: MAP_EINVAL for n < 1, a
+ * site outside the box or not finite, two coinciding sites (the paper merges
+ * tightly packed cells; the caller merges coinciding sites), lloyd_iters
+ * outside [0, 1000]; MAP_EDEVICE for a cell with more than 64 faces or 128
+ * vertices.  Uses about 7.5 KB of device memory per site while building.
+ */
+typedef struct map_voronoi_out {
+    int64_t n_cells, n_faces, n_face_verts, n_verts;
+    map_cells_in cells;      /* device memory owned by the context */
+    const int64_t *face_nb;  /* n_faces */
+    const double *sites;     /* 3 n_cells: the sites of the cells */
+    const double *centroid;  /* 3 n_cells */
+    double ms;               /* device time of the call */
+} map_voronoi_out;
+int map_voronoi(map_ctx *ctx, int64_t n, const double *sites, int mem_kind, const double box[6], int lloyd_iters,
+                map_voronoi_out *out);
+int map_voronoi_copy(map_ctx *ctx, int mem_kind, int64_t *cell_face_off, int64_t *face_vert_off, int32_t *face_vert,
+                     double *face_plane, int64_t *face_nb, double *verts, double *cell_volume, double *centroid,
+                     double *sites);
+
+/*
  * Served mapping (continuous batching).  map_submit copies the inputs (host or
  * device memory) into library-owned memory before it returns and queues the
  * job at the context's current precision; *job_id identifies it.  Jobs are

@@ -56,6 +56,11 @@ class map_cells_in(ctypes.Structure):
                 ("verts", c_vp), ("cell_volume", c_vp), ("box", c_dbl * 6), ("mem_kind", c_int)]
 
 
+class map_voronoi_out(ctypes.Structure):
+    _fields_ = [("n_cells", c_i64), ("n_faces", c_i64), ("n_face_verts", c_i64), ("n_verts", c_i64),
+                ("cells", map_cells_in), ("face_nb", c_vp), ("sites", c_vp), ("centroid", c_vp), ("ms", c_dbl)]
+
+
 class map_stats(ctypes.Structure):
     _fields_ = [("n_pairs", c_i64), ("n_candidates", c_i64), ("n_edge_terms", c_i64), ("n_fixup_terms", c_i64),
                 ("n_face_visits", c_i64), ("n_edge_visits", c_i64), ("n_moment_evals", c_i64),
@@ -149,6 +154,9 @@ _SIGS = {
                                     ctypes.POINTER(map_pseudo_out), ctypes.POINTER(map_adapt_stats)]),
     "map_get_regions": (c_int, [c_vp, c_i64, c_vp, ctypes.POINTER(c_i64)]),
     "map_set_table": (c_int, [c_vp, c_int, c_int, c_int]),
+    "map_voronoi": (c_int, [c_vp, c_i64, c_vp, c_int, ctypes.POINTER(c_dbl * 6), c_int,
+                            ctypes.POINTER(map_voronoi_out)]),
+    "map_voronoi_copy": (c_int, [c_vp, c_int] + [c_vp] * 9),
     "map_get_table": (c_int, [c_vp, c_vp]),
     "map_set_regions": (c_int, [c_vp, c_i64, c_vp]),
 }
@@ -505,6 +513,58 @@ def map_pseudo_adaptive(ctx, xyz, m, h, box, sources, neutral, K=100.0, max_walk
     return res
 
 
+class VoronoiCells:
+    """Box-clipped Voronoi cells in the library's cell format (numpy or torch CUDA arrays)."""
+
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.cell_face_off.shape[0]) - 1
+
+
+def map_voronoi_copy(ctx, mem_kind, cell_face_off=None, face_vert_off=None, face_vert=None, face_plane=None,
+                     face_nb=None, verts=None, cell_volume=None, centroid=None, sites=None):
+    """Copies the context's last Voronoi grid into the given arrays (None skips one)."""
+    arrs = (cell_face_off, face_vert_off, face_vert, face_plane, face_nb, verts, cell_volume, centroid, sites)
+    _check(ctx, load().map_voronoi_copy(ctx, mem_kind, *[_ptr(a) for a in arrs]))
+
+
+def map_voronoi(ctx, sites, box, lloyd_iters=0, device=False):
+    """Voronoi grid of the sites (Sec. II-A) after lloyd_iters Lloyd iterations.
+
+    Returns VoronoiCells with cell_face_off, face_vert_off, face_vert, face_plane, verts,
+    cell_volume, face_nb, centroid, sites, box and ms; host numpy arrays, or torch CUDA
+    tensors when device=True."""
+    lib = load()
+    if _is_torch(sites):
+        s = sites.contiguous()
+    else:
+        s = np.ascontiguousarray(np.asarray(sites, dtype=np.float64).reshape(-1, 3))
+    bx = (c_dbl * 6)(*[float(b) for b in box])
+    out = map_voronoi_out()
+    _check(ctx, lib.map_voronoi(ctx, int(s.shape[0]), _ptr(s), _kind(s), ctypes.byref(bx), int(lloyd_iters),
+                                ctypes.byref(out)))
+    n, nf, ns, nv = int(out.n_cells), int(out.n_faces), int(out.n_face_verts), int(out.n_verts)
+    shapes = dict(cell_face_off=((n + 1,), np.int64), face_vert_off=((nf + 1,), np.int64),
+                  face_vert=((ns,), np.int32), face_plane=((nf, 4), np.float64), face_nb=((nf,), np.int64),
+                  verts=((nv, 3), np.float64), cell_volume=((n,), np.float64), centroid=((n, 3), np.float64),
+                  sites=((n, 3), np.float64))
+    if device:
+        import torch
+        tdt = {np.int64: torch.int64, np.int32: torch.int32, np.float64: torch.float64}
+        arr = {k: torch.empty(sh, dtype=tdt[dt], device="cuda") for k, (sh, dt) in shapes.items()}
+        kind = MAP_MEM_DEVICE
+    else:
+        arr = {k: np.zeros(sh, dtype=dt) for k, (sh, dt) in shapes.items()}
+        kind = MAP_MEM_HOST
+    order = ("cell_face_off", "face_vert_off", "face_vert", "face_plane", "face_nb", "verts", "cell_volume",
+             "centroid", "sites")
+    map_voronoi_copy(ctx, kind, *[arr[k] for k in order])
+    return VoronoiCells(box=tuple(float(b) for b in box), ms=float(out.ms), **arr)
+
+
 def map_get_regions(ctx):
     """The context's remembered regions, an (n, 5) array of cx, cy, cz, R, s_min."""
     lib = load()
@@ -541,6 +601,9 @@ class Mapper:
 
     def set_precision(self, precision):
         map_set_precision(self.ctx, precision)
+
+    def voronoi(self, sites, box, lloyd_iters=0, device=False):
+        return map_voronoi(self.ctx, sites, box, lloyd_iters, device)
 
     def set_table(self, n0=64, n1=64, n2=64):
         map_set_table(self.ctx, n0, n1, n2)

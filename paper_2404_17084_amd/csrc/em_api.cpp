@@ -34,6 +34,7 @@ Ctx::~Ctx()
     (void)hipSetDevice(device);
     if (stream) (void)hipStreamSynchronize(stream);
     ws.release();
+    free_voronoi(vor);
     if (table.d64) (void)hipFree(table.d64);
     if (table.d32) (void)hipFree(table.d32);
     for (auto &e : ev)
@@ -411,6 +412,91 @@ int map_set_precision(map_ctx *h, int precision)
         EM_CHECK(precision == MAP_FP64 || precision == MAP_MIXED || precision == MAP_TABLE, MAP_EINVAL,
                  "precision must be MAP_FP64, MAP_MIXED or MAP_TABLE");
         C->precision = precision;
+    });
+}
+
+int map_voronoi(map_ctx *h, int64_t n, const double *sites, int mem_kind, const double box[6], int lloyd_iters,
+                map_voronoi_out *out)
+{
+    Ctx *C = reinterpret_cast<Ctx *>(h);
+    API_BODY(C, {
+        C->back.valid = false;
+        EM_CHECK(out && box, MAP_EINVAL, "null output or box");
+        EM_CHECK(n >= 1 && n < (int64_t)INT32_MAX, MAP_EINVAL, "site count outside [1, 2^31-1)");
+        EM_CHECK(sites, MAP_EINVAL, "null sites");
+        EM_CHECK(mem_kind == MAP_MEM_HOST || mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad sites mem_kind");
+        EM_CHECK(lloyd_iters >= 0 && lloyd_iters <= 1000, MAP_EINVAL, "lloyd_iters outside [0, 1000]");
+        for (int d = 0; d < 3; d++)
+            EM_CHECK(std::isfinite(box[d]) && std::isfinite(box[3 + d]) && box[3 + d] > box[d], MAP_EINVAL,
+                     "box must be finite with hi > lo");
+        hipStream_t s = C->stream;
+        VorGrid &V = C->vor;
+        // the sites live in the grid's own buffer (Lloyd steps replace them with the centroids)
+        if (V.cap_sites < (size_t)(3 * n) || !V.sites) {
+            if (V.sites) EM_HIP(hipFree(V.sites));
+            V.sites = nullptr;
+            EM_HIP(hipMalloc(&V.sites, sizeof(double) * 3 * n));
+            V.cap_sites = (size_t)(3 * n);
+        }
+        EM_HIP(hipMemcpyAsync(V.sites, sites, sizeof(double) * 3 * n,
+                              mem_kind == MAP_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        EM_HIP(hipEventRecord(C->ev[0], s));
+        for (int it = 0; it <= lloyd_iters; it++) {
+            V.n = 0;
+            build_voronoi(C->ws, V, n, V.sites, box, s);
+            if (it < lloyd_iters)
+                EM_HIP(hipMemcpyAsync(V.sites, V.cen, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+        }
+        EM_HIP(hipEventRecord(C->ev[1], s));
+        EM_HIP(hipEventSynchronize(C->ev[1]));
+        float ms = 0.f;
+        EM_HIP(hipEventElapsedTime(&ms, C->ev[0], C->ev[1]));
+        for (int d = 0; d < 6; d++) C->vor_box[d] = box[d];
+        out->n_cells = n;
+        out->n_faces = V.n_faces;
+        out->n_face_verts = V.n_slots;
+        out->n_verts = V.n_verts;
+        map_cells_in &c = out->cells;
+        c.n_cells = n;
+        c.n_faces = V.n_faces;
+        c.n_face_verts = V.n_slots;
+        c.n_verts = V.n_verts;
+        c.cell_face_off = V.cfo;
+        c.face_vert_off = V.fvo;
+        c.face_vert = V.fv;
+        c.face_plane = V.plane;
+        c.verts = V.verts;
+        c.cell_volume = V.vol;
+        for (int d = 0; d < 6; d++) c.box[d] = box[d];
+        c.mem_kind = MAP_MEM_DEVICE;
+        out->face_nb = V.fnb;
+        out->sites = V.sites;
+        out->centroid = V.cen;
+        out->ms = ms;
+    });
+}
+
+int map_voronoi_copy(map_ctx *h, int mem_kind, int64_t *cell_face_off, int64_t *face_vert_off, int32_t *face_vert,
+                     double *face_plane, int64_t *face_nb, double *verts, double *cell_volume, double *centroid,
+                     double *sites)
+{
+    Ctx *C = reinterpret_cast<Ctx *>(h);
+    API_BODY(C, {
+        EM_CHECK(mem_kind == MAP_MEM_HOST || mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad mem_kind");
+        const VorGrid &V = C->vor;
+        EM_CHECK(V.n > 0, MAP_EINVAL, "no Voronoi grid in this context");
+        const hipMemcpyKind k = mem_kind == MAP_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        hipStream_t s = C->stream;
+        if (cell_face_off) EM_HIP(hipMemcpyAsync(cell_face_off, V.cfo, sizeof(int64_t) * (V.n + 1), k, s));
+        if (face_vert_off) EM_HIP(hipMemcpyAsync(face_vert_off, V.fvo, sizeof(int64_t) * (V.n_faces + 1), k, s));
+        if (face_vert) EM_HIP(hipMemcpyAsync(face_vert, V.fv, sizeof(int32_t) * V.n_slots, k, s));
+        if (face_plane) EM_HIP(hipMemcpyAsync(face_plane, V.plane, sizeof(double) * 4 * V.n_faces, k, s));
+        if (face_nb) EM_HIP(hipMemcpyAsync(face_nb, V.fnb, sizeof(int64_t) * V.n_faces, k, s));
+        if (verts) EM_HIP(hipMemcpyAsync(verts, V.verts, sizeof(double) * 3 * V.n_verts, k, s));
+        if (cell_volume) EM_HIP(hipMemcpyAsync(cell_volume, V.vol, sizeof(double) * V.n, k, s));
+        if (centroid) EM_HIP(hipMemcpyAsync(centroid, V.cen, sizeof(double) * 3 * V.n, k, s));
+        if (sites) EM_HIP(hipMemcpyAsync(sites, V.sites, sizeof(double) * 3 * V.n, k, s));
+        EM_HIP(hipStreamSynchronize(s));
     });
 }
 

@@ -75,6 +75,8 @@ enum Slot : int {
     S_PSEUDO0, S_PSEUDO1, S_PSEUDO2, S_PSEUDO3, S_PSEUDO4, S_PSEUDO5, S_PSEUDO6, S_PSEUDO7,
     S_PSEUDO8, S_PSEUDO9, S_PSEUDO10, S_PSEUDO11, S_PSEUDO12, S_PSEUDO13, S_PSEUDO14, S_PSEUDO15,
     S_ADAPT0, S_ADAPT1, S_ADAPT2, S_ADAPT3, S_ADAPT4, S_ADAPT5, S_ADAPT6, S_ADAPT7,
+    S_VOR0, S_VOR1, S_VOR2, S_VOR3, S_VOR4, S_VOR5, S_VOR6, S_VOR7, S_VOR8, S_VOR9, S_VOR10, S_VOR11, S_VOR12,
+    S_VOR13, S_VOR14,
     S_NUM_SLOTS
 };
 
@@ -235,6 +237,19 @@ void launch_table_build(int n0, int n1, int n2, double *tab64, float *tab32, hip
 // em_table.hip: raw f per pair through the table (cell-major order)
 void launch_integrate_table(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, const float *tab, int n0,
                             int n1, int n2, double *f, int64_t *counters, hipStream_t s);
+
+// em_voronoi.hip: the box-clipped Voronoi grid of a site set, in the cell
+// format of map_cells_in, in device buffers owned by the context
+struct VorGrid {
+    int64_t n = 0, n_faces = 0, n_slots = 0, n_verts = 0;
+    int64_t *cfo = nullptr, *fvo = nullptr, *fnb = nullptr;
+    int32_t *fv = nullptr;
+    double *plane = nullptr, *verts = nullptr, *vol = nullptr, *cen = nullptr, *sites = nullptr;
+    size_t cap_cells = 0, cap_vol = 0, cap_cen = 0, cap_fvo = 0, cap_fnb = 0, cap_plane = 0, cap_fv = 0,
+           cap_verts = 0, cap_sites = 0;
+};
+void build_voronoi(Workspace &ws, VorGrid &V, int64_t n, const double *sites, const double box[6], hipStream_t s);
+void free_voronoi(VorGrid &V);
 
 // em_reduce.hip
 void launch_reduce(const DevInputs &in, const PairSet &ps, const double *f, double *S, double *M,

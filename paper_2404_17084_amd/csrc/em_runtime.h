@@ -41,6 +41,9 @@ struct Ctx {
     } back;
     // remembered regions of the adaptive walk (cx, cy, cz, R, s_min per region)
     std::vector<double> regions;
+    // the last map_voronoi grid
+    VorGrid vor;
+    double vor_box[6] = {0, 0, 0, 0, 0, 0};
     // table of the pyramid integral for MAP_TABLE (built on first use)
     struct {
         int n[3] = {64, 64, 64};

@@ -1,0 +1,411 @@
+// Box-clipped Voronoi cell of one site (Sec. II-A: the grid whose generating
+// sites are the particle positions), host- and device-callable.
+//
+// The cell is held as the dual of a convex polyhedron: a list of planes
+// (n.x <= d in coordinates centred on the site, n not normalised) and a list
+// of triangles (a, b, c) of plane indices, one per polyhedron vertex (the
+// point where the three planes meet), oriented so that det(n_a, n_b, n_c) > 0;
+// every dual edge then appears once in each direction.  The cell starts as the
+// box (6 planes, 8 triangles) and is cut by bisector planes of other sites:
+// the triangles whose vertex lies beyond the plane are removed, and every edge
+// (x, y) of a removed triangle whose reverse belongs to a kept triangle gets a
+// new triangle (x, y, P).  Sites are taken nearest first from balls of growing
+// radius (a tree of the sites sorted by Morton key, leaves of 8); once the next
+// site is at least twice as far as the farthest vertex, no other site can cut
+// the cell (the bisector of a site at distance D lies D/2 from the site).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace em {
+namespace vor {
+
+constexpr int kMaxPlanes = 64;   // 6 walls + 58 neighbours
+constexpr int kMaxTris = 128;    // vertices (2 faces - 4 for a simple polyhedron)
+constexpr int kMaxCand = 128;    // candidate sites of one ball
+constexpr int kLeaf = 8;         // sites per leaf of the site tree
+constexpr double kEps = 1e-12;   // a vertex within this distance of a cutting plane is on it
+
+enum : int32_t { ST_OK = 0, ST_PLANES = 1, ST_TRIS = 2, ST_PASSES = 3, ST_FACE = 4 };
+
+struct Plane {
+    double nx, ny, nz, d;
+};
+
+// Working state of one cell (device scratch, one block per cell).
+struct Cell {
+    Plane pl[kMaxPlanes];
+    int32_t src[kMaxPlanes];  // site (input index) across the plane, or -1 - wall
+    uint32_t tri[kMaxTris];   // a | b << 8 | c << 16
+    double vx[kMaxTris], vy[kMaxTris], vz[kMaxTris];
+    int32_t cand[kMaxCand];   // sorted-site index
+    double cd2[kMaxCand];     // squared distance, +inf once used
+    int32_t np, nt, status, pad;
+};
+
+__host__ __device__ inline uint32_t tri_pack(int a, int b, int c)
+{
+    return (uint32_t)a | ((uint32_t)b << 8) | ((uint32_t)c << 16);
+}
+__host__ __device__ inline int tri_a(uint32_t t) { return (int)(t & 255u); }
+__host__ __device__ inline int tri_b(uint32_t t) { return (int)((t >> 8) & 255u); }
+__host__ __device__ inline int tri_c(uint32_t t) { return (int)((t >> 16) & 255u); }
+
+// the point where three planes meet
+__host__ __device__ inline void meet(const Plane &A, const Plane &B, const Plane &C, double &x, double &y, double &z)
+{
+    const double bcx = B.ny * C.nz - B.nz * C.ny, bcy = B.nz * C.nx - B.nx * C.nz, bcz = B.nx * C.ny - B.ny * C.nx;
+    const double cax = C.ny * A.nz - C.nz * A.ny, cay = C.nz * A.nx - C.nx * A.nz, caz = C.nx * A.ny - C.ny * A.nx;
+    const double abx = A.ny * B.nz - A.nz * B.ny, aby = A.nz * B.nx - A.nx * B.nz, abz = A.nx * B.ny - A.ny * B.nx;
+    const double det = A.nx * bcx + A.ny * bcy + A.nz * bcz;
+    x = (A.d * bcx + B.d * cax + C.d * abx) / det;
+    y = (A.d * bcy + B.d * cay + C.d * aby) / det;
+    z = (A.d * bcz + B.d * caz + C.d * abz) / det;
+}
+
+__host__ __device__ inline void set_vertex(Cell &C, int t)
+{
+    const uint32_t q = C.tri[t];
+    meet(C.pl[tri_a(q)], C.pl[tri_b(q)], C.pl[tri_c(q)], C.vx[t], C.vy[t], C.vz[t]);
+}
+
+// the box [lo, hi] around site s: planes 0..5 = x-, x+, y-, y+, z-, z+
+__host__ __device__ inline void init_box(Cell &C, const double *box, double sx, double sy, double sz)
+{
+    const double s[3] = {sx, sy, sz};
+    for (int ax = 0; ax < 3; ax++)
+        for (int side = 0; side < 2; side++) {
+            Plane &P = C.pl[2 * ax + side];
+            P.nx = P.ny = P.nz = 0.0;
+            const double sg = side ? 1.0 : -1.0;
+            if (ax == 0) P.nx = sg;
+            if (ax == 1) P.ny = sg;
+            if (ax == 2) P.nz = sg;
+            P.d = side ? box[3 + ax] - s[ax] : s[ax] - box[ax];
+            C.src[2 * ax + side] = -1 - (2 * ax + side);
+        }
+    C.np = 6;
+    C.nt = 0;
+    for (int k = 0; k < 8; k++) {
+        const int px = k & 1, py = (k >> 1) & 1, pz = (k >> 2) & 1;
+        const int a = px, b = 2 + py, c = 4 + pz;
+        // det(n_a, n_b, n_c) = product of the three signs
+        const int sgn = (px ? 1 : -1) * (py ? 1 : -1) * (pz ? 1 : -1);
+        C.tri[C.nt] = sgn > 0 ? tri_pack(a, b, c) : tri_pack(a, c, b);
+        set_vertex(C, C.nt);
+        C.nt++;
+    }
+    C.status = ST_OK;
+}
+
+__host__ __device__ inline double max_r2(const Cell &C)
+{
+    double m = 0.0;
+    for (int t = 0; t < C.nt; t++) {
+        const double r2 = C.vx[t] * C.vx[t] + C.vy[t] * C.vy[t] + C.vz[t] * C.vz[t];
+        m = r2 > m ? r2 : m;
+    }
+    return m;
+}
+
+__host__ __device__ inline bool has_edge(uint32_t t, int x, int y)
+{
+    const int a = tri_a(t), b = tri_b(t), c = tri_c(t);
+    return (a == x && b == y) || (b == x && c == y) || (c == x && a == y);
+}
+
+// Cuts the cell by P (n.x <= d).  Returns true when P removed a vertex.
+__host__ __device__ inline bool clip(Cell &C, const Plane &P, int32_t src)
+{
+    const double nn = sqrt(P.nx * P.nx + P.ny * P.ny + P.nz * P.nz);
+    const double tol = kEps * nn;
+    bool out[kMaxTris];
+    int n_out = 0;
+    for (int t = 0; t < C.nt; t++) {
+        out[t] = P.nx * C.vx[t] + P.ny * C.vy[t] + P.nz * C.vz[t] - P.d > tol;
+        n_out += out[t] ? 1 : 0;
+    }
+    if (n_out == 0) return false;
+    if (C.np >= kMaxPlanes) {
+        C.status = ST_PLANES;
+        return false;
+    }
+    const int p = C.np;
+    C.pl[p] = P;
+    C.src[p] = src;
+    C.np++;
+    // boundary edges of the removed set: edges whose reverse lies in a kept triangle
+    uint32_t add[kMaxTris];
+    int n_add = 0;
+    for (int t = 0; t < C.nt; t++) {
+        if (!out[t]) continue;
+        const uint32_t q = C.tri[t];
+        const int v[3] = {tri_a(q), tri_b(q), tri_c(q)};
+        for (int e = 0; e < 3; e++) {
+            const int x = v[e], y = v[(e + 1) % 3];
+            bool inner = false;
+            for (int u = 0; u < C.nt && !inner; u++)
+                if (out[u] && u != t && has_edge(C.tri[u], y, x)) inner = true;
+            if (!inner) {
+                if (n_add >= kMaxTris) {
+                    C.status = ST_TRIS;
+                    return false;
+                }
+                add[n_add++] = tri_pack(x, y, p);
+            }
+        }
+    }
+    // keep the inside triangles, then add the new ones
+    int k = 0;
+    for (int t = 0; t < C.nt; t++) {
+        if (out[t]) continue;
+        C.tri[k] = C.tri[t];
+        C.vx[k] = C.vx[t];
+        C.vy[k] = C.vy[t];
+        C.vz[k] = C.vz[t];
+        k++;
+    }
+    if (k + n_add > kMaxTris) {
+        C.status = ST_TRIS;
+        return false;
+    }
+    for (int a = 0; a < n_add; a++) {
+        C.tri[k] = add[a];
+        set_vertex(C, k);
+        k++;
+    }
+    C.nt = k;
+    return true;
+}
+
+__host__ __device__ inline double box_gap2(const double *bb, double px, double py, double pz)
+{
+    const double dx = fmax(fmax(bb[0] - px, px - bb[3]), 0.0);
+    const double dy = fmax(fmax(bb[1] - py, py - bb[4]), 0.0);
+    const double dz = fmax(fmax(bb[2] - pz, pz - bb[5]), 0.0);
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// Key order of the candidate sites: squared distance, then sorted index.
+__host__ __device__ inline bool key_less(double d2, int64_t q, double e2, int64_t r)
+{
+    return d2 < e2 || (d2 == e2 && q < r);
+}
+
+// The (up to kMaxCand) nearest sorted sites whose key (|p - s|^2, index)
+// follows (lo2, lo_q) and whose squared distance is below hi2 (other than
+// `self`) into the candidate list; *more is set when further sites qualified.
+// Tree: heap of 2 NL boxes (6 doubles each; leaves NL + j hold sites
+// kLeaf j .. kLeaf j + 7), stackless depth-first walk.
+__host__ __device__ inline int collect(Cell &C, const double *ps, int64_t n, const double *bx, int64_t NL, int64_t self,
+                                       double sx, double sy, double sz, double lo2, int64_t lo_q, double hi2,
+                                       bool *more)
+{
+    int cnt = 0, far = -1;
+    *more = false;
+    int64_t i = 1;
+    for (;;) {
+        if (box_gap2(bx + 6 * i, sx, sy, sz) < hi2) {
+            if (i < NL) {
+                i = 2 * i;
+                continue;
+            }
+            const int64_t j = i - NL;
+            for (int64_t q = kLeaf * j; q < kLeaf * (j + 1) && q < n; q++) {
+                if (q == self) continue;
+                const double dx = ps[3 * q] - sx, dy = ps[3 * q + 1] - sy, dz = ps[3 * q + 2] - sz;
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                if (!(d2 < hi2) || !key_less(lo2, lo_q, d2, q)) continue;
+                if (cnt < kMaxCand) {
+                    C.cand[cnt] = (int32_t)q;
+                    C.cd2[cnt] = d2;
+                    if (far < 0 || key_less(C.cd2[far], C.cand[far], d2, q)) far = cnt;
+                    cnt++;
+                } else {
+                    *more = true;
+                    if (key_less(d2, q, C.cd2[far], C.cand[far])) {  // replace the farthest kept
+                        C.cand[far] = (int32_t)q;
+                        C.cd2[far] = d2;
+                        for (int k = 0; k < cnt; k++)
+                            if (key_less(C.cd2[far], C.cand[far], C.cd2[k], C.cand[k])) far = k;
+                    }
+                }
+            }
+        }
+        while (i & 1) i >>= 1;
+        if (i == 0) break;
+        i += 1;
+    }
+    return cnt;
+}
+
+// The cell of sorted site r (input index orig[r]).
+__host__ __device__ inline void build_cell(Cell &C, const double *ps, const int32_t *orig, int64_t n, const double *bx,
+                                           int64_t NL, const double *box, int64_t r)
+{
+    const double sx = ps[3 * r], sy = ps[3 * r + 1], sz = ps[3 * r + 2];
+    init_box(C, box, sx, sy, sz);
+    // first radius: twice the diagonal of the site's leaf box (at least the mean spacing)
+    const double *lb = bx + 6 * (NL + r / kLeaf);
+    const double ex = box[3] - box[0], ey = box[4] - box[1], ez = box[5] - box[2];
+    const double mean = cbrt(ex * ey * ez / (double)n);
+    double d2 = (lb[3] - lb[0]) * (lb[3] - lb[0]) + (lb[4] - lb[1]) * (lb[4] - lb[1]) + (lb[5] - lb[2]) * (lb[5] - lb[2]);
+    double hi2 = 4.0 * d2;
+    if (hi2 < mean * mean) hi2 = mean * mean;
+    double lo2 = -1.0;  // key (lo2, lo_q) of the last site taken
+    int64_t lo_q = -1;
+    double m2 = max_r2(C);
+    for (int pass = 0; pass < 1024; pass++) {
+        bool more = false;
+        const int cnt = collect(C, ps, n, bx, NL, r, sx, sy, sz, lo2, lo_q, hi2, &more);
+        // sites in key order, nearest first, until no farther site reaches the cell
+        for (int it = 0; it < cnt; it++) {
+            int best = -1;
+            for (int k = 0; k < cnt; k++)
+                if (C.cd2[k] >= 0.0 && (best < 0 || key_less(C.cd2[k], C.cand[k], C.cd2[best], C.cand[best])))
+                    best = k;
+            const double bd = C.cd2[best];
+            const int64_t q = C.cand[best];
+            if (bd >= 4.0 * m2) return;  // the bisector of this site and of every farther one misses the cell
+            lo2 = bd;
+            lo_q = q;
+            C.cd2[best] = -1.0;  // taken
+            Plane P;
+            P.nx = ps[3 * q] - sx;
+            P.ny = ps[3 * q + 1] - sy;
+            P.nz = ps[3 * q + 2] - sz;
+            P.d = 0.5 * (P.nx * P.nx + P.ny * P.ny + P.nz * P.nz);
+            if (P.d == 0.0) continue;  // a coincident site has no bisector
+            if (clip(C, P, orig[q])) m2 = max_r2(C);
+            if (C.status != ST_OK) return;
+        }
+        if (more) continue;  // the ball holds further sites beyond the ones taken
+        if (hi2 >= 4.0 * m2) return;  // every site that could reach the cell was taken
+        lo2 = hi2;  // the next shell: up to twice the farthest vertex
+        lo_q = -1;
+        hi2 = 4.0 * m2 * (1.0 + 1e-12);
+    }
+    C.status = ST_PASSES;
+}
+
+// Faces of a built cell: planes that carry at least 3 vertices.
+__host__ __device__ inline int plane_count(const Cell &C, int p)
+{
+    int c = 0;
+    for (int t = 0; t < C.nt; t++) {
+        const uint32_t q = C.tri[t];
+        c += (tri_a(q) == p || tri_b(q) == p || tri_c(q) == p) ? 1 : 0;
+    }
+    return c;
+}
+
+// Writes the faces of a built cell: for each plane with at least 3 vertices,
+// its vertices in order around it, counter-clockwise seen from outside (the
+// triangle (p, a, b) is followed by the one holding the edge (p, b); the order
+// is reversed if the polygon's vector area points inward), the outward unit
+// normal and offset in box coordinates, and the site or wall across it.
+// Vertices are the cell's triangles (index vbase + t), in box coordinates.
+// Returns the volume and centroid (tetrahedra from the site over face fans);
+// status ST_FACE if a face's vertices do not close into one loop.
+__host__ __device__ inline void extract_cell(Cell &C, double sx, double sy, double sz, int64_t vbase, int64_t fbase,
+                                             int64_t sbase, int64_t *face_vert_off, int32_t *face_vert,
+                                             double *face_plane, int64_t *face_nb, double *verts, double &vol,
+                                             double *cen)
+{
+    for (int t = 0; t < C.nt; t++) {
+        verts[3 * (vbase + t)] = C.vx[t] + sx;
+        verts[3 * (vbase + t) + 1] = C.vy[t] + sy;
+        verts[3 * (vbase + t) + 2] = C.vz[t] + sz;
+    }
+    int64_t f = fbase, slot = sbase;
+    double V = 0.0, M[3] = {0.0, 0.0, 0.0};
+    int ring[kMaxTris];
+    for (int p = 0; p < C.np; p++) {
+        // triangles around p, as (p, a, b) with b the next plane
+        int nr = 0;
+        int first = -1;
+        for (int t = 0; t < C.nt; t++) {
+            const uint32_t q = C.tri[t];
+            if (tri_a(q) == p || tri_b(q) == p || tri_c(q) == p) {
+                nr++;
+                if (first < 0) first = t;
+            }
+        }
+        if (nr < 3) continue;
+        int len = 0, t = first;
+        while (len < nr) {
+            ring[len++] = t;
+            const uint32_t q = C.tri[t];
+            const int b = tri_a(q) == p ? tri_c(q) : (tri_b(q) == p ? tri_a(q) : tri_b(q));
+            // next: the triangle holding the directed edge (p, b)
+            int nx = -1;
+            for (int u = 0; u < C.nt && nx < 0; u++)
+                if (u != t && has_edge(C.tri[u], p, b)) nx = u;
+            if (nx < 0 || nx == first) break;
+            t = nx;
+        }
+        if (len != nr) {
+            C.status = ST_FACE;
+            return;
+        }
+        const Plane &P = C.pl[p];
+        const double nn = sqrt(P.nx * P.nx + P.ny * P.ny + P.nz * P.nz);
+        const double ux = P.nx / nn, uy = P.ny / nn, uz = P.nz / nn;
+        // vector area about the site (local coordinates)
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int k = 0; k < len; k++) {
+            const int a = ring[k], b = ring[(k + 1) % len];
+            ax += C.vy[a] * C.vz[b] - C.vz[a] * C.vy[b];
+            ay += C.vz[a] * C.vx[b] - C.vx[a] * C.vz[b];
+            az += C.vx[a] * C.vy[b] - C.vy[a] * C.vx[b];
+        }
+        const bool rev = ax * ux + ay * uy + az * uz < 0.0;
+        face_vert_off[f] = slot;
+        for (int k = 0; k < len; k++) face_vert[slot + k] = (int32_t)(vbase + ring[rev ? len - 1 - k : k]);
+        slot += len;
+        face_plane[4 * f] = ux;
+        face_plane[4 * f + 1] = uy;
+        face_plane[4 * f + 2] = uz;
+        face_plane[4 * f + 3] = P.d / nn + (ux * sx + uy * sy + uz * sz);
+        face_nb[f] = C.src[p];
+        f++;
+        // tetrahedra (site, v0, vk, vk+1) in counter-clockwise order
+        const int o0 = ring[rev ? len - 1 : 0];
+        for (int k = 1; k + 1 < len; k++) {
+            const int o1 = ring[rev ? len - 1 - k : k], o2 = ring[rev ? len - 2 - k : k + 1];
+            const double x0 = C.vx[o0], y0 = C.vy[o0], z0 = C.vz[o0];
+            const double x1 = C.vx[o1], y1 = C.vy[o1], z1 = C.vz[o1];
+            const double x2 = C.vx[o2], y2 = C.vy[o2], z2 = C.vz[o2];
+            const double tv = (x0 * (y1 * z2 - z1 * y2) + y0 * (z1 * x2 - x1 * z2) + z0 * (x1 * y2 - y1 * x2)) / 6.0;
+            V += tv;
+            M[0] += tv * (x0 + x1 + x2) / 4.0;
+            M[1] += tv * (y0 + y1 + y2) / 4.0;
+            M[2] += tv * (z0 + z1 + z2) / 4.0;
+        }
+    }
+    face_vert_off[f] = slot;
+    vol = V;
+    cen[0] = sx + (V > 0.0 ? M[0] / V : 0.0);
+    cen[1] = sy + (V > 0.0 ? M[1] / V : 0.0);
+    cen[2] = sz + (V > 0.0 ? M[2] / V : 0.0);
+}
+
+// counts of a built cell: faces, face-vertex slots
+__host__ __device__ inline void cell_counts(const Cell &C, int64_t &faces, int64_t &slots)
+{
+    faces = 0;
+    slots = 0;
+    for (int p = 0; p < C.np; p++) {
+        const int c = plane_count(C, p);
+        if (c >= 3) {
+            faces++;
+            slots += c;
+        }
+    }
+}
+
+}  // namespace vor
+}  // namespace em
