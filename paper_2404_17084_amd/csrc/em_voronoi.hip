@@ -119,8 +119,24 @@ __global__ void __launch_bounds__(128) k_vor_build(int64_t n, const double *__re
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     const double box[6] = {B.lo[0], B.lo[1], B.lo[2], B.hi[0], B.hi[1], B.hi[2]};
-    vor::Cell &C = cells[r];
+    // the working cell in private memory (interleaved across the lanes of a
+    // wavefront), then its planes and vertices copied to the record
+    vor::Cell C;
     vor::build_cell(C, ps, orig, n, bx, NL, box, r);
+    vor::Cell &G = cells[r];
+    G.np = C.np;
+    G.nt = C.nt;
+    G.status = C.status;
+    for (int p = 0; p < C.np; p++) {
+        G.pl[p] = C.pl[p];
+        G.src[p] = C.src[p];
+    }
+    for (int t = 0; t < C.nt; t++) {
+        G.tri[t] = C.tri[t];
+        G.vx[t] = C.vx[t];
+        G.vy[t] = C.vy[t];
+        G.vz[t] = C.vz[t];
+    }
     int64_t f = 0, sl = 0;
     if (C.status == vor::ST_OK) vor::cell_counts(C, f, sl);
     else atomicOr(flags, 4u);

@@ -195,84 +195,150 @@ __host__ __device__ inline bool key_less(double d2, int64_t q, double e2, int64_
     return d2 < e2 || (d2 == e2 && q < r);
 }
 
-// The (up to kMaxCand) nearest sorted sites whose key (|p - s|^2, index)
-// follows (lo2, lo_q) and whose squared distance is below hi2 (other than
-// `self`) into the candidate list; *more is set when further sites qualified.
-// Tree: heap of 2 NL boxes (6 doubles each; leaves NL + j hold sites
-// kLeaf j .. kLeaf j + 7), stackless depth-first walk.
+__host__ __device__ inline void heap_down(Cell &C, int k, int cnt)
+{
+    for (;;) {
+        const int l = 2 * k + 1, r = l + 1;
+        int m = k;
+        if (l < cnt && key_less(C.cd2[m], C.cand[m], C.cd2[l], C.cand[l])) m = l;
+        if (r < cnt && key_less(C.cd2[m], C.cand[m], C.cd2[r], C.cand[r])) m = r;
+        if (m == k) return;
+        const double td = C.cd2[k];
+        const int32_t tq = C.cand[k];
+        C.cd2[k] = C.cd2[m];
+        C.cand[k] = C.cand[m];
+        C.cd2[m] = td;
+        C.cand[m] = tq;
+        k = m;
+    }
+}
+
+// Support of the cell's bounding box [lo, hi] (site-centred) along w:
+// max over the box of w.x, the largest reach of any vertex along w.
+__host__ __device__ inline double reach(const double *lo, const double *hi, double wx, double wy, double wz)
+{
+    return fmax(wx * lo[0], wx * hi[0]) + fmax(wy * lo[1], wy * hi[1]) + fmax(wz * lo[2], wz * hi[2]);
+}
+
+// The (up to kMaxCand) nearest sorted sites, in key order (|p - s|^2, then
+// index), whose key follows (lo2, lo_q) and whose bisector can reach the
+// cell's bounding box [blo, bhi] (a site at offset w cuts only if some vertex
+// v has w.v > |w|^2 / 2, and w.v is at most the box's reach along w); *more is
+// set when further sites qualified.  A tree box is skipped when no offset in
+// it can reach (its least |w|^2 / 2 is at least the largest reach over it,
+// the reach being separable and convex), or when the list is full and the box
+// is farther than its farthest entry.  The list is a max-heap on the key
+// during the walk, sorted at the end.  Tree: heap of 2 NL boxes (6 doubles
+// each; leaves NL + j hold sites kLeaf j .. kLeaf j + 7).
 __host__ __device__ inline int collect(Cell &C, const double *ps, int64_t n, const double *bx, int64_t NL, int64_t self,
                                        double sx, double sy, double sz, double lo2, int64_t lo_q, double hi2,
-                                       bool *more)
+                                       const double *blo, const double *bhi, bool *more)
 {
-    int cnt = 0, far = -1;
+    int cnt = 0;
     *more = false;
-    int64_t i = 1;
-    for (;;) {
-        if (box_gap2(bx + 6 * i, sx, sy, sz) < hi2) {
-            if (i < NL) {
-                i = 2 * i;
-                continue;
+    // depth-first, nearer child first; the stack holds at most one pending
+    // sibling per level
+    int64_t stack[64];
+    int sp = 0;
+    stack[sp++] = 1;
+    while (sp > 0) {
+        const int64_t i = stack[--sp];
+        const double *b = bx + 6 * i;
+        const double g2 = box_gap2(b, sx, sy, sz);
+        bool visit = g2 < hi2 && !(cnt == kMaxCand && g2 > C.cd2[0]);
+        if (visit) {
+            const double ax = b[0] - sx, bxx = b[3] - sx, ay = b[1] - sy, by = b[4] - sy, az = b[2] - sz, bz = b[5] - sz;
+            const double gm = fmax(fmax(ax * blo[0], ax * bhi[0]), fmax(bxx * blo[0], bxx * bhi[0])) +
+                              fmax(fmax(ay * blo[1], ay * bhi[1]), fmax(by * blo[1], by * bhi[1])) +
+                              fmax(fmax(az * blo[2], az * bhi[2]), fmax(bz * blo[2], bz * bhi[2]));
+            visit = 0.5 * g2 < gm;
+        } else if (cnt == kMaxCand && g2 < hi2) {
+            *more = true;  // a box skipped for distance may hold qualifying sites
+        }
+        if (!visit) continue;
+        if (i < NL) {
+            const double gl = box_gap2(bx + 6 * (2 * i), sx, sy, sz), gr = box_gap2(bx + 6 * (2 * i + 1), sx, sy, sz);
+            if (sp + 2 > 64) {  // cannot happen for trees of fewer than 2^62 leaves
+                C.status = ST_PASSES;
+                return 0;
             }
-            const int64_t j = i - NL;
-            for (int64_t q = kLeaf * j; q < kLeaf * (j + 1) && q < n; q++) {
-                if (q == self) continue;
-                const double dx = ps[3 * q] - sx, dy = ps[3 * q + 1] - sy, dz = ps[3 * q + 2] - sz;
-                const double d2 = dx * dx + dy * dy + dz * dz;
-                if (!(d2 < hi2) || !key_less(lo2, lo_q, d2, q)) continue;
-                if (cnt < kMaxCand) {
-                    C.cand[cnt] = (int32_t)q;
-                    C.cd2[cnt] = d2;
-                    if (far < 0 || key_less(C.cd2[far], C.cand[far], d2, q)) far = cnt;
-                    cnt++;
-                } else {
-                    *more = true;
-                    if (key_less(d2, q, C.cd2[far], C.cand[far])) {  // replace the farthest kept
-                        C.cand[far] = (int32_t)q;
-                        C.cd2[far] = d2;
-                        for (int k = 0; k < cnt; k++)
-                            if (key_less(C.cd2[far], C.cand[far], C.cd2[k], C.cand[k])) far = k;
-                    }
+            stack[sp++] = gl <= gr ? 2 * i + 1 : 2 * i;  // farther child later
+            stack[sp++] = gl <= gr ? 2 * i : 2 * i + 1;
+            continue;
+        }
+        const int64_t j = i - NL;
+        for (int64_t q = kLeaf * j; q < kLeaf * (j + 1) && q < n; q++) {
+            if (q == self) continue;
+            const double dx = ps[3 * q] - sx, dy = ps[3 * q + 1] - sy, dz = ps[3 * q + 2] - sz;
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            if (!(d2 < hi2) || !key_less(lo2, lo_q, d2, q) || !(0.5 * d2 < reach(blo, bhi, dx, dy, dz))) continue;
+            if (cnt < kMaxCand) {  // push, sift up
+                int k = cnt++;
+                while (k > 0) {
+                    const int pa = (k - 1) / 2;
+                    if (!key_less(C.cd2[pa], C.cand[pa], d2, q)) break;
+                    C.cd2[k] = C.cd2[pa];
+                    C.cand[k] = C.cand[pa];
+                    k = pa;
+                }
+                C.cd2[k] = d2;
+                C.cand[k] = (int32_t)q;
+            } else {
+                *more = true;
+                if (key_less(d2, q, C.cd2[0], C.cand[0])) {  // replace the farthest kept
+                    C.cd2[0] = d2;
+                    C.cand[0] = (int32_t)q;
+                    heap_down(C, 0, cnt);
                 }
             }
         }
-        while (i & 1) i >>= 1;
-        if (i == 0) break;
-        i += 1;
+    }
+    for (int end = cnt - 1; end > 0; end--) {  // heap sort: ascending keys
+        const double td = C.cd2[0];
+        const int32_t tq = C.cand[0];
+        C.cd2[0] = C.cd2[end];
+        C.cand[0] = C.cand[end];
+        C.cd2[end] = td;
+        C.cand[end] = tq;
+        heap_down(C, 0, end);
     }
     return cnt;
 }
 
-// The cell of sorted site r (input index orig[r]).
+// The cell of sorted site r (input index orig[r]).  Passes take the sites
+// that can still reach the cell's bounding box, nearest first, 128 at a time,
+// until a pass finds no more; the first pass only looks within 0.8 times the
+// diagonal of the site's leaf box (about 100 sites when the leaf's 8 sites
+// fill it; at least the mean spacing), later passes anywhere.
 __host__ __device__ inline void build_cell(Cell &C, const double *ps, const int32_t *orig, int64_t n, const double *bx,
                                            int64_t NL, const double *box, int64_t r)
 {
     const double sx = ps[3 * r], sy = ps[3 * r + 1], sz = ps[3 * r + 2];
     init_box(C, box, sx, sy, sz);
-    // first radius: twice the diagonal of the site's leaf box (at least the mean spacing)
     const double *lb = bx + 6 * (NL + r / kLeaf);
     const double ex = box[3] - box[0], ey = box[4] - box[1], ez = box[5] - box[2];
     const double mean = cbrt(ex * ey * ez / (double)n);
-    double d2 = (lb[3] - lb[0]) * (lb[3] - lb[0]) + (lb[4] - lb[1]) * (lb[4] - lb[1]) + (lb[5] - lb[2]) * (lb[5] - lb[2]);
-    double hi2 = 4.0 * d2;
+    double hi2 = 0.64 * ((lb[3] - lb[0]) * (lb[3] - lb[0]) + (lb[4] - lb[1]) * (lb[4] - lb[1]) +
+                         (lb[5] - lb[2]) * (lb[5] - lb[2]));
     if (hi2 < mean * mean) hi2 = mean * mean;
     double lo2 = -1.0;  // key (lo2, lo_q) of the last site taken
     int64_t lo_q = -1;
     double m2 = max_r2(C);
-    for (int pass = 0; pass < 1024; pass++) {
+    for (int pass = 0; pass < 4096; pass++) {
+        double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int t = 0; t < C.nt; t++) {
+            blo[0] = fmin(blo[0], C.vx[t]), bhi[0] = fmax(bhi[0], C.vx[t]);
+            blo[1] = fmin(blo[1], C.vy[t]), bhi[1] = fmax(bhi[1], C.vy[t]);
+            blo[2] = fmin(blo[2], C.vz[t]), bhi[2] = fmax(bhi[2], C.vz[t]);
+        }
         bool more = false;
-        const int cnt = collect(C, ps, n, bx, NL, r, sx, sy, sz, lo2, lo_q, hi2, &more);
-        // sites in key order, nearest first, until no farther site reaches the cell
+        const int cnt = collect(C, ps, n, bx, NL, r, sx, sy, sz, lo2, lo_q, hi2, blo, bhi, &more);
         for (int it = 0; it < cnt; it++) {
-            int best = -1;
-            for (int k = 0; k < cnt; k++)
-                if (C.cd2[k] >= 0.0 && (best < 0 || key_less(C.cd2[k], C.cand[k], C.cd2[best], C.cand[best])))
-                    best = k;
-            const double bd = C.cd2[best];
-            const int64_t q = C.cand[best];
+            const double bd = C.cd2[it];
+            const int64_t q = C.cand[it];
             if (bd >= 4.0 * m2) return;  // the bisector of this site and of every farther one misses the cell
             lo2 = bd;
             lo_q = q;
-            C.cd2[best] = -1.0;  // taken
             Plane P;
             P.nx = ps[3 * q] - sx;
             P.ny = ps[3 * q + 1] - sy;
@@ -282,11 +348,10 @@ __host__ __device__ inline void build_cell(Cell &C, const double *ps, const int3
             if (clip(C, P, orig[q])) m2 = max_r2(C);
             if (C.status != ST_OK) return;
         }
-        if (more) continue;  // the ball holds further sites beyond the ones taken
-        if (hi2 >= 4.0 * m2) return;  // every site that could reach the cell was taken
-        lo2 = hi2;  // the next shell: up to twice the farthest vertex
-        lo_q = -1;
-        hi2 = 4.0 * m2 * (1.0 + 1e-12);
+        if (!more) {
+            if (hi2 == INFINITY) return;  // every site that can reach the cell was taken
+            hi2 = INFINITY;  // beyond the first ball
+        }
     }
     C.status = ST_PASSES;
 }
