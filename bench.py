@@ -215,6 +215,45 @@ def table_leg(em, mapper, p, xyz, m, h, dc, M, rho, S, M_fp64, steps, warmup):
     return out
 
 
+def voronoi_leg(em, mapper, p, xyz, m, h, c, M_fp64, steps, with_oracle):
+    """The box-clipped Voronoi grid of the same 262,144 sites on the device (no Lloyd step, then 5), the
+    FP64 mapping on those cells against the mapping on the host-generated cells, and the oracle's
+    per-cell time on a sample of cells."""
+    import torch
+    import oracle
+    sites = torch.from_numpy(np.ascontiguousarray(p.xyz)).to("cuda:0")
+    out = {}
+    for it in (0, 5):
+        em.map_voronoi(mapper.ctx, sites, synth_box(), it, device=True)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            G = em.map_voronoi(mapper.ctx, sites, synth_box(), it, device=True)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[f"lloyd_{it}"] = {"ms": 1e3 * dt, "ms_device": G.ms, "cells_per_s": p.n / dt}
+    G = em.map_voronoi(mapper.ctx, sites, synth_box(), 0, device=True)
+    mapper.set_precision(em.MAP_FP64)
+    M = torch.zeros(p.n, dtype=torch.float64, device="cuda:0")
+    em.map_particles(mapper.ctx, xyz, m, h, G, M)
+    rel = np.abs(M.cpu().numpy() - M_fp64) / np.abs(M_fp64)
+    out["faces_per_cell"] = float(G.face_plane.shape[0]) / p.n
+    out["mapping_on_device_cells_vs_host_cells_max_rel"] = float(rel.max())
+    if with_oracle:
+        sel = np.arange(0, p.n, p.n // 16)
+        t0 = time.perf_counter()
+        oracle.voronoi(p.xyz, synth_box(), sel=sel)
+        dt = time.perf_counter() - t0
+        out["oracle"] = {"cells_per_s": sel.size / dt, "sample": f"{sel.size} cells (each sorts all sites by "
+                         f"distance, then clips nearest first)", "cores": 1}
+    return out
+
+
+def synth_box():
+    import synth
+    return synth.BOX
+
+
 def back_leg(em, mapper, p, M, nc, steps):
     """Inverse mapping (Eq. (4)) with the pairs of the last (mixed) mapping: a
     random cell field gathered to the particles, device buffers."""
@@ -314,6 +353,8 @@ def main():
     print(f"bench: inverse mapping: {back}", file=sys.stderr, flush=True)
     table = table_leg(em, mapper, p, xyz, m, h, dc, M, rho, S, Ms["fp64"], args.steps, args.warmup)
     print(f"bench: tabulated variant: {table}", file=sys.stderr, flush=True)
+    vor = voronoi_leg(em, mapper, p, xyz, m, h, c, Ms["fp64"], args.steps, not args.no_cpu_baseline)
+    print(f"bench: voronoi grid: {vor}", file=sys.stderr, flush=True)
     mapper.close()
     rel = np.abs(Ms["mixed"] - Ms["fp64"]) / np.abs(Ms["fp64"])
 
@@ -346,6 +387,7 @@ def main():
         "launch_shape": tuned,
         "inverse_mapping": back,
         "tabulated": table,
+        "voronoi_grid": vor,
         "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32, "unit": "TFLOP/s", "frac": ach / PEAK_FP32,
                      "traffic": measured_traffic()},
     }
