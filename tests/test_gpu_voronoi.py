@@ -137,3 +137,27 @@ def test_voronoi_rejects_bad_sites():
             mp.voronoi(s, BOX, lloyd_iters=-1)
         G = mp.voronoi(s, BOX)  # the context still works
         assert G.cell_volume.sum() == pytest.approx(1.0, rel=1e-12)
+
+
+def test_voronoi_edge_cases():
+    say("case: voronoi one site, two sites, sites on the walls, a lattice")
+    g = (np.arange(4) + 0.5) / 4
+    cases = {
+        "one": np.array([[0.3, 0.6, 0.2]]),
+        "two": np.array([[0.25, 0.5, 0.5], [0.75, 0.5, 0.5]]),
+        "walls": np.vstack([np.random.default_rng(4).random((200, 3)),
+                            [[0.0, 0.5, 0.5], [1.0, 1.0, 1.0], [0.0, 0.0, 0.0], [0.5, 0.0, 0.3]]]),
+        "lattice": np.array(np.meshgrid(g, g, g, indexing="ij")).reshape(3, -1).T,
+    }
+    with em.Mapper(device=0) as mp:
+        for name, s in cases.items():
+            G = mp.voronoi(s, BOX)
+            O = oracle.voronoi(s, BOX)
+            assert np.allclose(G.cell_volume, O["cell_volume"], rtol=1e-12, atol=0), name
+            assert _nb_sets(G, range(len(s))) == _nb_sets(O, range(len(s))), name
+            _check_faces(G)
+        G = mp.voronoi(cases["one"], BOX)
+        assert G.face_plane.shape[0] == 6 and G.cell_volume[0] == pytest.approx(1.0, rel=1e-15)
+        G = mp.voronoi(cases["lattice"], BOX)
+        assert np.all(np.diff(G.cell_face_off) == 6) and np.allclose(G.cell_volume, 1 / 64, rtol=1e-13)
+        assert np.allclose(G.centroid, cases["lattice"], atol=1e-15)
