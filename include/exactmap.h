@@ -381,9 +381,14 @@ int map_set_regions(map_ctx *ctx, int64_t n_regions, const double *regions);
 
 /*
  * Voronoi grid (Sec. II-A): the box-clipped Voronoi cells of n sites (the
- * particle positions, or any distinct points in the box), relaxed by
- * lloyd_iters Lloyd iterations (each site moved to its cell's centroid, the
- * grid rebuilt; the paper applies 5).  Cell i belongs to site i.  Each cell is
+ * particle positions, or any points in the box), with tightly packed sites
+ * merged and lloyd_iters Lloyd iterations (each site moved to its cell's
+ * centroid, the grid rebuilt; the paper applies 5).  Merging (merge_dist > 0):
+ * a site is dropped when a site of lower index lies closer than merge_dist
+ * (coinciding sites included); the grid is built from the rest, in input
+ * order, and site_cell[i] names the cell that holds input site i (its
+ * nearest grid site, ties to the lower index; after Lloyd steps a site may lie
+ * in a neighbour's cell).  Without merging cell i belongs to site i.  Each cell is
  * the box cut by the bisector planes of its nearest sites, taken nearest
  * first until no farther site can reach it; a vertex within 1e-12 of a
  * cutting plane counts as on it.  Output in the cell format of
@@ -396,24 +401,26 @@ int map_set_regions(map_ctx *ctx, int64_t n_regions, const double *regions);
  * next map_voronoi or map_shutdown; map_voronoi_copy copies them into caller
  * buffers (NULL skips an array) sized by the counts in out.
  * sites: 3 n doubles in mem_kind memory.  Errors: MAP_EINVAL for n < 1, a
- * site outside the box or not finite, two coinciding sites (the paper merges
- * tightly packed cells; the caller merges coinciding sites), lloyd_iters
- * outside [0, 1000]; MAP_EDEVICE for a cell with more than 64 faces or 128
- * vertices.  Uses about 7.5 KB of device memory per site while building.
+ * site outside the box or not finite, two coinciding sites when merge_dist
+ * is 0, lloyd_iters outside [0, 1000], merge_dist negative or not finite;
+ * MAP_EDEVICE for a cell with more than 64 faces or 128 vertices.  Uses
+ * about 7.5 KB of device memory per site while building.
  */
 typedef struct map_voronoi_out {
     int64_t n_cells, n_faces, n_face_verts, n_verts;
-    map_cells_in cells;      /* device memory owned by the context */
-    const int64_t *face_nb;  /* n_faces */
-    const double *sites;     /* 3 n_cells: the sites of the cells */
-    const double *centroid;  /* 3 n_cells */
-    double ms;               /* device time of the call */
+    map_cells_in cells;        /* device memory owned by the context */
+    const int64_t *face_nb;    /* n_faces */
+    const double *sites;       /* 3 n_cells: the sites of the cells */
+    const double *centroid;    /* 3 n_cells */
+    int64_t n_sites;           /* input sites */
+    const int64_t *site_cell;  /* n_sites: the cell holding each input site */
+    double ms;                 /* device time of the call */
 } map_voronoi_out;
 int map_voronoi(map_ctx *ctx, int64_t n, const double *sites, int mem_kind, const double box[6], int lloyd_iters,
-                map_voronoi_out *out);
+                double merge_dist, map_voronoi_out *out);
 int map_voronoi_copy(map_ctx *ctx, int mem_kind, int64_t *cell_face_off, int64_t *face_vert_off, int32_t *face_vert,
                      double *face_plane, int64_t *face_nb, double *verts, double *cell_volume, double *centroid,
-                     double *sites);
+                     double *sites, int64_t *site_cell);
 
 /*
  * Served mapping (continuous batching).  map_submit copies the inputs (host or

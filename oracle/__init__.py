@@ -532,3 +532,24 @@ def lloyd(sites, box, iterations: int = 5):
     V["sites"] = s
     return V
 
+
+def merge_sites(sites, d: float):
+    """Tightly packed sites merged (reading of Sec. II-A's merging of tightly packed cells): site i is
+    dropped when a site of lower index lies closer than d.  Returns the indices kept, ascending."""
+    s = _f64(sites).reshape(-1, 3)
+    keep = np.ones(len(s), dtype=bool)
+    for i in range(1, len(s)):
+        w = s[:i] - s[i]
+        keep[i] = not np.any(w[:, 0] * w[:, 0] + w[:, 1] * w[:, 1] + w[:, 2] * w[:, 2] < d * d)
+    return np.nonzero(keep)[0]
+
+
+def site_cells(points, sites):
+    """The cell of the grid of `sites` that holds each point: its nearest site (ties to the lower index)."""
+    p, s = _f64(points).reshape(-1, 3), _f64(sites).reshape(-1, 3)
+    out = np.zeros(len(p), dtype=np.int64)
+    for a in range(len(p)):
+        w = s - p[a]
+        out[a] = int(np.argmin(w[:, 0] * w[:, 0] + w[:, 1] * w[:, 1] + w[:, 2] * w[:, 2]))
+    return out
+

@@ -58,7 +58,8 @@ class map_cells_in(ctypes.Structure):
 
 class map_voronoi_out(ctypes.Structure):
     _fields_ = [("n_cells", c_i64), ("n_faces", c_i64), ("n_face_verts", c_i64), ("n_verts", c_i64),
-                ("cells", map_cells_in), ("face_nb", c_vp), ("sites", c_vp), ("centroid", c_vp), ("ms", c_dbl)]
+                ("cells", map_cells_in), ("face_nb", c_vp), ("sites", c_vp), ("centroid", c_vp),
+                ("n_sites", c_i64), ("site_cell", c_vp), ("ms", c_dbl)]
 
 
 class map_stats(ctypes.Structure):
@@ -154,9 +155,9 @@ _SIGS = {
                                     ctypes.POINTER(map_pseudo_out), ctypes.POINTER(map_adapt_stats)]),
     "map_get_regions": (c_int, [c_vp, c_i64, c_vp, ctypes.POINTER(c_i64)]),
     "map_set_table": (c_int, [c_vp, c_int, c_int, c_int]),
-    "map_voronoi": (c_int, [c_vp, c_i64, c_vp, c_int, ctypes.POINTER(c_dbl * 6), c_int,
+    "map_voronoi": (c_int, [c_vp, c_i64, c_vp, c_int, ctypes.POINTER(c_dbl * 6), c_int, c_dbl,
                             ctypes.POINTER(map_voronoi_out)]),
-    "map_voronoi_copy": (c_int, [c_vp, c_int] + [c_vp] * 9),
+    "map_voronoi_copy": (c_int, [c_vp, c_int] + [c_vp] * 10),
     "map_get_table": (c_int, [c_vp, c_vp]),
     "map_set_regions": (c_int, [c_vp, c_i64, c_vp]),
 }
@@ -525,18 +526,19 @@ class VoronoiCells:
 
 
 def map_voronoi_copy(ctx, mem_kind, cell_face_off=None, face_vert_off=None, face_vert=None, face_plane=None,
-                     face_nb=None, verts=None, cell_volume=None, centroid=None, sites=None):
+                     face_nb=None, verts=None, cell_volume=None, centroid=None, sites=None, site_cell=None):
     """Copies the context's last Voronoi grid into the given arrays (None skips one)."""
-    arrs = (cell_face_off, face_vert_off, face_vert, face_plane, face_nb, verts, cell_volume, centroid, sites)
+    arrs = (cell_face_off, face_vert_off, face_vert, face_plane, face_nb, verts, cell_volume, centroid, sites,
+            site_cell)
     _check(ctx, load().map_voronoi_copy(ctx, mem_kind, *[_ptr(a) for a in arrs]))
 
 
-def map_voronoi(ctx, sites, box, lloyd_iters=0, device=False):
-    """Voronoi grid of the sites (Sec. II-A) after lloyd_iters Lloyd iterations.
+def map_voronoi(ctx, sites, box, lloyd_iters=0, merge_dist=0.0, device=False):
+    """Voronoi grid of the sites (Sec. II-A), tightly packed sites merged, after lloyd_iters Lloyd iterations.
 
     Returns VoronoiCells with cell_face_off, face_vert_off, face_vert, face_plane, verts,
-    cell_volume, face_nb, centroid, sites, box and ms; host numpy arrays, or torch CUDA
-    tensors when device=True."""
+    cell_volume, face_nb, centroid, sites, site_cell, box and ms; host numpy arrays, or torch
+    CUDA tensors when device=True."""
     lib = load()
     if _is_torch(sites):
         s = sites.contiguous()
@@ -545,12 +547,13 @@ def map_voronoi(ctx, sites, box, lloyd_iters=0, device=False):
     bx = (c_dbl * 6)(*[float(b) for b in box])
     out = map_voronoi_out()
     _check(ctx, lib.map_voronoi(ctx, int(s.shape[0]), _ptr(s), _kind(s), ctypes.byref(bx), int(lloyd_iters),
-                                ctypes.byref(out)))
+                                float(merge_dist), ctypes.byref(out)))
     n, nf, ns, nv = int(out.n_cells), int(out.n_faces), int(out.n_face_verts), int(out.n_verts)
+    n_in = int(out.n_sites)
     shapes = dict(cell_face_off=((n + 1,), np.int64), face_vert_off=((nf + 1,), np.int64),
                   face_vert=((ns,), np.int32), face_plane=((nf, 4), np.float64), face_nb=((nf,), np.int64),
                   verts=((nv, 3), np.float64), cell_volume=((n,), np.float64), centroid=((n, 3), np.float64),
-                  sites=((n, 3), np.float64))
+                  sites=((n, 3), np.float64), site_cell=((n_in,), np.int64))
     if device:
         import torch
         tdt = {np.int64: torch.int64, np.int32: torch.int32, np.float64: torch.float64}
@@ -560,7 +563,7 @@ def map_voronoi(ctx, sites, box, lloyd_iters=0, device=False):
         arr = {k: np.zeros(sh, dtype=dt) for k, (sh, dt) in shapes.items()}
         kind = MAP_MEM_HOST
     order = ("cell_face_off", "face_vert_off", "face_vert", "face_plane", "face_nb", "verts", "cell_volume",
-             "centroid", "sites")
+             "centroid", "sites", "site_cell")
     map_voronoi_copy(ctx, kind, *[arr[k] for k in order])
     return VoronoiCells(box=tuple(float(b) for b in box), ms=float(out.ms), **arr)
 
@@ -602,8 +605,8 @@ class Mapper:
     def set_precision(self, precision):
         map_set_precision(self.ctx, precision)
 
-    def voronoi(self, sites, box, lloyd_iters=0, device=False):
-        return map_voronoi(self.ctx, sites, box, lloyd_iters, device)
+    def voronoi(self, sites, box, lloyd_iters=0, merge_dist=0.0, device=False):
+        return map_voronoi(self.ctx, sites, box, lloyd_iters, merge_dist, device)
 
     def set_table(self, n0=64, n1=64, n2=64):
         map_set_table(self.ctx, n0, n1, n2)

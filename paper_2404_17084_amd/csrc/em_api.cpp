@@ -416,7 +416,7 @@ int map_set_precision(map_ctx *h, int precision)
 }
 
 int map_voronoi(map_ctx *h, int64_t n, const double *sites, int mem_kind, const double box[6], int lloyd_iters,
-                map_voronoi_out *out)
+                double merge_dist, map_voronoi_out *out)
 {
     Ctx *C = reinterpret_cast<Ctx *>(h);
     API_BODY(C, {
@@ -426,38 +426,58 @@ int map_voronoi(map_ctx *h, int64_t n, const double *sites, int mem_kind, const 
         EM_CHECK(sites, MAP_EINVAL, "null sites");
         EM_CHECK(mem_kind == MAP_MEM_HOST || mem_kind == MAP_MEM_DEVICE, MAP_EINVAL, "bad sites mem_kind");
         EM_CHECK(lloyd_iters >= 0 && lloyd_iters <= 1000, MAP_EINVAL, "lloyd_iters outside [0, 1000]");
+        EM_CHECK(std::isfinite(merge_dist) && merge_dist >= 0.0, MAP_EINVAL, "merge_dist must be finite and >= 0");
         for (int d = 0; d < 3; d++)
             EM_CHECK(std::isfinite(box[d]) && std::isfinite(box[3 + d]) && box[3 + d] > box[d], MAP_EINVAL,
                      "box must be finite with hi > lo");
         hipStream_t s = C->stream;
         VorGrid &V = C->vor;
-        // the sites live in the grid's own buffer (Lloyd steps replace them with the centroids)
-        if (V.cap_sites < (size_t)(3 * n) || !V.sites) {
-            if (V.sites) EM_HIP(hipFree(V.sites));
-            V.sites = nullptr;
-            EM_HIP(hipMalloc(&V.sites, sizeof(double) * 3 * n));
-            V.cap_sites = (size_t)(3 * n);
+        V.n = 0;
+        auto grow = [&](double *&p, size_t &cap, size_t count) {
+            if (cap < count || !p) {
+                if (p) EM_HIP(hipFree(p));
+                p = nullptr;
+                EM_HIP(hipMalloc(&p, sizeof(double) * count));
+                cap = count;
+            }
+        };
+        grow(V.input, V.cap_input, (size_t)(3 * n));
+        grow(V.sites, V.cap_sites, (size_t)(3 * n));
+        if (V.cap_site_cell < (size_t)n || !V.site_cell) {
+            if (V.site_cell) EM_HIP(hipFree(V.site_cell));
+            V.site_cell = nullptr;
+            EM_HIP(hipMalloc(&V.site_cell, sizeof(int64_t) * n));
+            V.cap_site_cell = (size_t)n;
         }
-        EM_HIP(hipMemcpyAsync(V.sites, sites, sizeof(double) * 3 * n,
+        EM_HIP(hipMemcpyAsync(V.input, sites, sizeof(double) * 3 * n,
                               mem_kind == MAP_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
         EM_HIP(hipEventRecord(C->ev[0], s));
+        // merging of tightly packed sites, then the grid and its Lloyd steps (the sites live in the
+        // grid's own buffer: each step replaces them with the centroids)
+        int64_t m = n;
+        if (merge_dist > 0.0)
+            m = merge_sites(C->ws, n, V.input, box, merge_dist, V.sites, s);
+        else
+            EM_HIP(hipMemcpyAsync(V.sites, V.input, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
         for (int it = 0; it <= lloyd_iters; it++) {
             V.n = 0;
-            build_voronoi(C->ws, V, n, V.sites, box, s);
+            build_voronoi(C->ws, V, m, V.sites, box, s);
             if (it < lloyd_iters)
-                EM_HIP(hipMemcpyAsync(V.sites, V.cen, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+                EM_HIP(hipMemcpyAsync(V.sites, V.cen, sizeof(double) * 3 * m, hipMemcpyDeviceToDevice, s));
         }
+        site_cells(C->ws, V, n, V.input, box, V.site_cell, s);
+        V.n_in = n;
         EM_HIP(hipEventRecord(C->ev[1], s));
         EM_HIP(hipEventSynchronize(C->ev[1]));
         float ms = 0.f;
         EM_HIP(hipEventElapsedTime(&ms, C->ev[0], C->ev[1]));
         for (int d = 0; d < 6; d++) C->vor_box[d] = box[d];
-        out->n_cells = n;
+        out->n_cells = m;
         out->n_faces = V.n_faces;
         out->n_face_verts = V.n_slots;
         out->n_verts = V.n_verts;
         map_cells_in &c = out->cells;
-        c.n_cells = n;
+        c.n_cells = m;
         c.n_faces = V.n_faces;
         c.n_face_verts = V.n_slots;
         c.n_verts = V.n_verts;
@@ -472,13 +492,15 @@ int map_voronoi(map_ctx *h, int64_t n, const double *sites, int mem_kind, const 
         out->face_nb = V.fnb;
         out->sites = V.sites;
         out->centroid = V.cen;
+        out->n_sites = n;
+        out->site_cell = V.site_cell;
         out->ms = ms;
     });
 }
 
 int map_voronoi_copy(map_ctx *h, int mem_kind, int64_t *cell_face_off, int64_t *face_vert_off, int32_t *face_vert,
                      double *face_plane, int64_t *face_nb, double *verts, double *cell_volume, double *centroid,
-                     double *sites)
+                     double *sites, int64_t *site_cell)
 {
     Ctx *C = reinterpret_cast<Ctx *>(h);
     API_BODY(C, {
@@ -496,6 +518,7 @@ int map_voronoi_copy(map_ctx *h, int mem_kind, int64_t *cell_face_off, int64_t *
         if (cell_volume) EM_HIP(hipMemcpyAsync(cell_volume, V.vol, sizeof(double) * V.n, k, s));
         if (centroid) EM_HIP(hipMemcpyAsync(centroid, V.cen, sizeof(double) * 3 * V.n, k, s));
         if (sites) EM_HIP(hipMemcpyAsync(sites, V.sites, sizeof(double) * 3 * V.n, k, s));
+        if (site_cell) EM_HIP(hipMemcpyAsync(site_cell, V.site_cell, sizeof(int64_t) * V.n_in, k, s));
         EM_HIP(hipStreamSynchronize(s));
     });
 }

@@ -245,10 +245,19 @@ struct VorGrid {
     int64_t *cfo = nullptr, *fvo = nullptr, *fnb = nullptr;
     int32_t *fv = nullptr;
     double *plane = nullptr, *verts = nullptr, *vol = nullptr, *cen = nullptr, *sites = nullptr;
+    double *input = nullptr;      // the call's input sites (3 n_in)
+    int64_t *site_cell = nullptr; // cell holding each input site (n_in)
+    int64_t n_in = 0;
     size_t cap_cells = 0, cap_vol = 0, cap_cen = 0, cap_fvo = 0, cap_fnb = 0, cap_plane = 0, cap_fv = 0,
-           cap_verts = 0, cap_sites = 0;
+           cap_verts = 0, cap_sites = 0, cap_input = 0, cap_site_cell = 0;
 };
 void build_voronoi(Workspace &ws, VorGrid &V, int64_t n, const double *sites, const double box[6], hipStream_t s);
+// merging of tightly packed sites; returns the number kept (written to out, input order)
+int64_t merge_sites(Workspace &ws, int64_t n_in, const double *in, const double box[6], double d, double *out,
+                    hipStream_t s);
+// the cell of grid V holding each input point (its nearest site, ties to the lower index)
+void site_cells(Workspace &ws, const VorGrid &V, int64_t n_in, const double *in, const double box[6],
+                int64_t *site_cell, hipStream_t s);
 void free_voronoi(VorGrid &V);
 
 // em_reduce.hip

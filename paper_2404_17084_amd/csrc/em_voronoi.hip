@@ -171,6 +171,89 @@ __global__ void __launch_bounds__(128) k_vor_extract(int64_t n, const double *__
     O.vol[i] = vol;
 }
 
+// Merging of tightly packed sites: a site is dropped when a site of lower
+// input index lies closer than sqrt(d2max) (one thread per sorted site, a walk
+// of the site tree that stops at the first such site).
+__global__ void k_vor_merge(int64_t n, const double *__restrict__ ps, const int32_t *__restrict__ orig,
+                            const double *__restrict__ bx, int64_t NL, double d2max, int64_t *__restrict__ keep)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const double sx = ps[3 * r], sy = ps[3 * r + 1], sz = ps[3 * r + 2];
+    const int32_t me = orig[r];
+    bool found = false;
+    int64_t i = 1;
+    while (!found) {
+        if (vor::box_gap2(bx + 6 * i, sx, sy, sz) < d2max) {
+            if (i < NL) {
+                i = 2 * i;
+                continue;
+            }
+            const int64_t j = i - NL;
+            for (int64_t q = vor::kLeaf * j; q < vor::kLeaf * (j + 1) && q < n && !found; q++) {
+                if (orig[q] >= me) continue;
+                const double dx = ps[3 * q] - sx, dy = ps[3 * q + 1] - sy, dz = ps[3 * q + 2] - sz;
+                if (dx * dx + dy * dy + dz * dz < d2max) found = true;
+            }
+        }
+        while (i & 1) i >>= 1;
+        if (i == 0) break;
+        i += 1;
+    }
+    keep[me] = found ? 0 : 1;
+}
+
+// the kept sites, in input order
+__global__ void k_vor_gather(int64_t n, const double *__restrict__ s, const int64_t *__restrict__ keep,
+                             const int64_t *__restrict__ koff, double *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !keep[i]) return;
+    const int64_t k = koff[i];
+    out[3 * k] = s[3 * i];
+    out[3 * k + 1] = s[3 * i + 1];
+    out[3 * k + 2] = s[3 * i + 2];
+}
+
+// The cell holding each input point: its nearest site of the grid (ties to
+// the lower index), by a walk of the grid's site tree, nearer child first,
+// skipping boxes farther than the best so far.
+__global__ void k_vor_site_cell(int64_t n_in, const double *__restrict__ x, int64_t n, const double *__restrict__ ps,
+                                const int32_t *__restrict__ orig, const double *__restrict__ bx, int64_t NL,
+                                int64_t *__restrict__ site_cell)
+{
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n_in) return;
+    const double px = x[3 * a], py = x[3 * a + 1], pz = x[3 * a + 2];
+    double best = INFINITY;
+    int32_t bi = -1;
+    int64_t stack[64];
+    int sp = 0;
+    stack[sp++] = 1;
+    while (sp > 0) {
+        const int64_t i = stack[--sp];
+        if (vor::box_gap2(bx + 6 * i, px, py, pz) > best) continue;
+        if (i < NL) {
+            if (sp + 2 > 64) break;  // cannot happen below 2^62 leaves
+            const double gl = vor::box_gap2(bx + 6 * (2 * i), px, py, pz);
+            const double gr = vor::box_gap2(bx + 6 * (2 * i + 1), px, py, pz);
+            stack[sp++] = gl <= gr ? 2 * i + 1 : 2 * i;
+            stack[sp++] = gl <= gr ? 2 * i : 2 * i + 1;
+            continue;
+        }
+        const int64_t j = i - NL;
+        for (int64_t q = vor::kLeaf * j; q < vor::kLeaf * (j + 1) && q < n; q++) {
+            const double dx = ps[3 * q] - px, dy = ps[3 * q + 1] - py, dz = ps[3 * q + 2] - pz;
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            if (d2 < best || (d2 == best && orig[q] < bi)) {
+                best = d2;
+                bi = orig[q];
+            }
+        }
+    }
+    site_cell[a] = bi;
+}
+
 unsigned vgrid(int64_t n, int block) { return (unsigned)((n + block - 1) / block > 0 ? (n + block - 1) / block : 1); }
 
 template <typename T>
@@ -185,16 +268,19 @@ T *dev_alloc(T *&p, size_t &cap, size_t count)
     return p;
 }
 
-}  // namespace
+struct SiteTree {
+    const double *ps;
+    const int32_t *orig;
+    const int64_t *rank;
+    double *bx;
+    int64_t NL;
+};
 
-// Builds the grid of n sites (device memory) into V; returns the counts.
-void build_voronoi(Workspace &ws, VorGrid &V, int64_t n, const double *sites, const double box[6], hipStream_t s)
+// Sites sorted by Morton key (positions, input index of each sorted site,
+// rank of each input site) and the box tree over leaves of 8.  Rejects sites
+// outside the box or not finite, and (when asked) coinciding sites.
+SiteTree site_tree(Workspace &ws, int64_t n, const double *sites, const VBox &B, bool distinct, hipStream_t s)
 {
-    VBox B;
-    for (int d = 0; d < 3; d++) {
-        B.lo[d] = box[d];
-        B.hi[d] = box[3 + d];
-    }
     unsigned *flags = ws.get<unsigned>(S_FLAGS, 4);
     fill_zero_bytes(flags, sizeof(unsigned) * 4, s);
     uint64_t *key = ws.get<uint64_t>(S_VOR0, (size_t)n);
@@ -214,7 +300,7 @@ void build_voronoi(Workspace &ws, VorGrid &V, int64_t n, const double *sites, co
     EM_HIP(hipMemcpyAsync(&hf, flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     EM_HIP(hipStreamSynchronize(s));
     EM_CHECK(!(hf & 1u), MAP_EINVAL, "a site is not finite or lies outside the box");
-    EM_CHECK(!(hf & 2u), MAP_EINVAL, "two sites coincide (merge them first)");
+    EM_CHECK(!distinct || !(hf & 2u), MAP_EINVAL, "two sites coincide (merge them first)");
 
     const int64_t nleaf = (n + vor::kLeaf - 1) / vor::kLeaf;
     int64_t NL = 1;
@@ -226,6 +312,27 @@ void build_voronoi(Workspace &ws, VorGrid &V, int64_t n, const double *sites, co
         hipLaunchKernelGGL(k_vor_parent_boxes, dim3(vgrid(first, 256)), dim3(256), 0, s, first, bx);
         EM_HIP(hipGetLastError());
     }
+    return SiteTree{ps, orig, rank, bx, NL};
+}
+
+}  // namespace
+
+// Builds the grid of n sites (device memory) into V; returns the counts.
+void build_voronoi(Workspace &ws, VorGrid &V, int64_t n, const double *sites, const double box[6], hipStream_t s)
+{
+    VBox B;
+    for (int d = 0; d < 3; d++) {
+        B.lo[d] = box[d];
+        B.hi[d] = box[3 + d];
+    }
+    const SiteTree T = site_tree(ws, n, sites, B, true, s);
+    const double *ps = T.ps;
+    const int32_t *orig = T.orig;
+    const int64_t *rank = T.rank;
+    const double *bx = T.bx;
+    const int64_t NL = T.NL;
+    unsigned *flags = ws.get<unsigned>(S_FLAGS, 4);
+    unsigned hf = 0;
     vor::Cell *cells = reinterpret_cast<vor::Cell *>(ws.get(S_VOR8, sizeof(vor::Cell) * (size_t)n));
     int64_t *nfc = ws.get<int64_t>(S_VOR9, (size_t)n + 1);
     int64_t *nsc = ws.get<int64_t>(S_VOR10, (size_t)n + 1);
@@ -269,10 +376,51 @@ void build_voronoi(Workspace &ws, VorGrid &V, int64_t n, const double *sites, co
     V.n = n;
 }
 
+// Merging (d > 0): the n_in input sites less those with a lower-index site
+// closer than d, in input order, into out (3 n_in doubles); returns the count.
+int64_t merge_sites(Workspace &ws, int64_t n_in, const double *in, const double box[6], double d, double *out,
+                    hipStream_t s)
+{
+    VBox B;
+    for (int k = 0; k < 3; k++) {
+        B.lo[k] = box[k];
+        B.hi[k] = box[3 + k];
+    }
+    const SiteTree T = site_tree(ws, n_in, in, B, false, s);
+    int64_t *keep = ws.get<int64_t>(S_VOR9, (size_t)n_in + 1);
+    int64_t *koff = ws.get<int64_t>(S_VOR10, (size_t)n_in + 1);
+    hipLaunchKernelGGL(k_vor_merge, dim3(vgrid(n_in, 128)), dim3(128), 0, s, n_in, T.ps, T.orig, (const double *)T.bx,
+                       T.NL, d * d, keep);
+    EM_HIP(hipGetLastError());
+    scan_counts(ws, keep, koff, n_in, s);
+    int64_t m = 0;
+    EM_HIP(hipMemcpyAsync(&m, koff + n_in, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(k_vor_gather, dim3(vgrid(n_in, 256)), dim3(256), 0, s, n_in, in, (const int64_t *)keep,
+                       (const int64_t *)koff, out);
+    EM_HIP(hipGetLastError());
+    EM_HIP(hipStreamSynchronize(s));
+    return m;
+}
+
+// The cell of the grid V that holds each of the n_in input points.
+void site_cells(Workspace &ws, const VorGrid &V, int64_t n_in, const double *in, const double box[6],
+                int64_t *site_cell, hipStream_t s)
+{
+    VBox B;
+    for (int k = 0; k < 3; k++) {
+        B.lo[k] = box[k];
+        B.hi[k] = box[3 + k];
+    }
+    const SiteTree T = site_tree(ws, V.n, V.sites, B, true, s);
+    hipLaunchKernelGGL(k_vor_site_cell, dim3(vgrid(n_in, 128)), dim3(128), 0, s, n_in, in, V.n, T.ps, T.orig,
+                       (const double *)T.bx, T.NL, site_cell);
+    EM_HIP(hipGetLastError());
+}
+
 void free_voronoi(VorGrid &V)
 {
     for (void *p : {(void *)V.cfo, (void *)V.vol, (void *)V.cen, (void *)V.fvo, (void *)V.fnb, (void *)V.plane,
-                    (void *)V.fv, (void *)V.verts, (void *)V.sites})
+                    (void *)V.fv, (void *)V.verts, (void *)V.sites, (void *)V.input, (void *)V.site_cell})
         if (p) (void)hipFree(p);
     V = VorGrid{};
 }

@@ -161,3 +161,28 @@ def test_voronoi_edge_cases():
         G = mp.voronoi(cases["lattice"], BOX)
         assert np.all(np.diff(G.cell_face_off) == 6) and np.allclose(G.cell_volume, 1 / 64, rtol=1e-13)
         assert np.allclose(G.centroid, cases["lattice"], atol=1e-15)
+
+
+def test_merging_and_site_cells():
+    say("case: voronoi with tightly packed sites merged, then Lloyd steps")
+    s = synth.particles("clumps", 2000, 91).xyz
+    s = np.vstack([s, s[:5]])  # coinciding copies are merged too
+    kept = oracle.merge_sites(s, 0.004)
+    assert 0 < kept.size < s.shape[0] - 5
+    with em.Mapper(device=0) as mp:
+        G = mp.voronoi(s, BOX, merge_dist=0.004)
+        assert G.n_cells == kept.size and np.array_equal(G.sites, s[kept])
+        O = oracle.voronoi(s[kept], BOX)
+        assert np.allclose(G.cell_volume, O["cell_volume"], rtol=1e-12, atol=0)
+        assert _nb_sets(G, range(kept.size)) == _nb_sets(O, range(kept.size))
+        assert np.array_equal(G.site_cell, oracle.site_cells(s, s[kept]))
+        # after Lloyd steps the input sites are assigned to the cells of the moved sites
+        L = mp.voronoi(s, BOX, lloyd_iters=2, merge_dist=0.004)
+        OL = oracle.lloyd(s[kept], BOX, 2)
+        assert np.abs(L.sites - OL["sites"]).max() < 1e-12
+        assert np.array_equal(L.site_cell, oracle.site_cells(s, OL["sites"]))
+        # no merging: every site keeps its own cell
+        N = mp.voronoi(s[:2000], BOX)
+        assert np.array_equal(N.site_cell, np.arange(2000))
+        with pytest.raises(em.MapError):
+            mp.voronoi(s, BOX, merge_dist=-1.0)

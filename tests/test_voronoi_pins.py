@@ -150,3 +150,26 @@ def test_selected_cells_with_the_stopping_rule_equal_the_full_build(clumpy):
         a = sorted(S["face_nb"][S["cell_face_off"][t]:S["cell_face_off"][t + 1]].tolist())
         b = sorted(V["face_nb"][V["cell_face_off"][i]:V["cell_face_off"][i + 1]].tolist())
         assert a == b
+
+
+def test_merging_a_chain_of_close_sites():
+    """a, b = a + 0.01 x, c = b + 0.01 x with d = 0.015: b is dropped (a is close), so is c (b, although
+    dropped, is close and of lower index); a far site stays."""
+    s = np.array([[0.5, 0.5, 0.5], [0.51, 0.5, 0.5], [0.52, 0.5, 0.5], [0.1, 0.2, 0.3]])
+    assert oracle.merge_sites(s, 0.015).tolist() == [0, 3]
+    assert oracle.merge_sites(s, 0.0).tolist() == [0, 1, 2, 3]
+    assert oracle.merge_sites(s, 0.02).tolist() == [0, 3]
+    assert oracle.merge_sites(np.vstack([s, s[1:2]]), 1e-9).tolist() == [0, 1, 2, 3]  # the copy of b goes
+
+
+def test_site_cells_hold_their_points():
+    sites = synth.particles("clumps", 600, 89).xyz
+    kept = oracle.merge_sites(sites, 0.01)
+    assert 0 < kept.size < sites.shape[0]
+    V = oracle.voronoi(sites[kept], BOX)
+    cell = oracle.site_cells(sites, sites[kept])
+    assert np.array_equal(cell[kept], np.arange(kept.size))
+    for a in range(sites.shape[0]):  # the point lies inside its cell: on the inner side of every face
+        f0, f1 = V["cell_face_off"][cell[a]], V["cell_face_off"][cell[a] + 1]
+        n, c = V["face_plane"][f0:f1, :3], V["face_plane"][f0:f1, 3]
+        assert np.all(n @ sites[a] <= c + 1e-12)
