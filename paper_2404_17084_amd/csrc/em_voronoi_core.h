@@ -9,10 +9,11 @@
 // box (6 planes, 8 triangles) and is cut by bisector planes of other sites:
 // the triangles whose vertex lies beyond the plane are removed, and every edge
 // (x, y) of a removed triangle whose reverse belongs to a kept triangle gets a
-// new triangle (x, y, P).  Sites are taken nearest first from balls of growing
-// radius (a tree of the sites sorted by Morton key, leaves of 8); once the next
-// site is at least twice as far as the farthest vertex, no other site can cut
-// the cell (the bisector of a site at distance D lies D/2 from the site).
+// new triangle (x, y, P).  Sites are taken nearest first (a tree of the sites
+// sorted by Morton key, leaves of 8), in passes that only consider sites whose
+// bisector can still reach the cell's bounding box; once the next site is at
+// least twice as far as the farthest vertex, no other site can cut the cell
+// (the bisector of a site at distance D lies D/2 from the site).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,7 +26,7 @@ namespace vor {
 
 constexpr int kMaxPlanes = 64;   // 6 walls + 58 neighbours
 constexpr int kMaxTris = 128;    // vertices (2 faces - 4 for a simple polyhedron)
-constexpr int kMaxCand = 128;    // candidate sites of one ball
+constexpr int kMaxCand = 64;     // candidate sites taken per pass
 constexpr int kLeaf = 8;         // sites per leaf of the site tree
 constexpr double kEps = 1e-12;   // a vertex within this distance of a cutting plane is on it
 
@@ -306,9 +307,9 @@ __host__ __device__ inline int collect(Cell &C, const double *ps, int64_t n, con
 }
 
 // The cell of sorted site r (input index orig[r]).  Passes take the sites
-// that can still reach the cell's bounding box, nearest first, 128 at a time,
-// until a pass finds no more; the first pass only looks within 0.8 times the
-// diagonal of the site's leaf box (about 100 sites when the leaf's 8 sites
+// that can still reach the cell's bounding box, nearest first, 64 at a time,
+// until a pass finds no more; the first pass only looks within 0.55 times the
+// diagonal of the site's leaf box (about 30 sites when the leaf's 8 sites
 // fill it; at least the mean spacing), later passes anywhere.
 __host__ __device__ inline void build_cell(Cell &C, const double *ps, const int32_t *orig, int64_t n, const double *bx,
                                            int64_t NL, const double *box, int64_t r)
@@ -318,7 +319,7 @@ __host__ __device__ inline void build_cell(Cell &C, const double *ps, const int3
     const double *lb = bx + 6 * (NL + r / kLeaf);
     const double ex = box[3] - box[0], ey = box[4] - box[1], ez = box[5] - box[2];
     const double mean = cbrt(ex * ey * ez / (double)n);
-    double hi2 = 0.64 * ((lb[3] - lb[0]) * (lb[3] - lb[0]) + (lb[4] - lb[1]) * (lb[4] - lb[1]) +
+    double hi2 = 0.3 * ((lb[3] - lb[0]) * (lb[3] - lb[0]) + (lb[4] - lb[1]) * (lb[4] - lb[1]) +
                          (lb[5] - lb[2]) * (lb[5] - lb[2]));
     if (hi2 < mean * mean) hi2 = mean * mean;
     double lo2 = -1.0;  // key (lo2, lo_q) of the last site taken
