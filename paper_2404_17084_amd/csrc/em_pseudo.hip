@@ -790,6 +790,14 @@ __global__ void __launch_bounds__(256) k_hsolve(int64_t n_pts, const double4 *__
             const double N = Nc.sum_w / M_PI;
             const double dN = -Nc.sum_qdw / (M_PI * hc);
             double hn = dN > 0.0 ? hc - (N - target) / dN : 0.5 * (lo + hi);
+            if (dN > 0.0 && fabs(hn - hc) <= 4e-16 * hc) {
+                // the Newton step no longer moves the iterate (N(hc) is the
+                // target to rounding): hc is the root, whichever side of the
+                // bracket it sits on
+                result = hc;
+                nb = (unsigned long long)Nc.count;
+                break;
+            }
             if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
             if (hn <= lo || hn >= hi) break;
             const NumSum Nn = number_sum_cached(LC, x.x, x.y, x.z, hn, n_pts, pts, bx, NL, nleaf, lane);
