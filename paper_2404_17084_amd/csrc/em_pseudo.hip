@@ -529,55 +529,66 @@ struct NumSum {
     int64_t count;
 };
 
+// The terms of one leaf's (up to 8) points, added in point order.
+__device__ __forceinline__ NumSum leaf_terms(double px, double py, double pz, double h, int64_t n_pts,
+                                            const double4 *__restrict__ pts, int64_t j)
+{
+#pragma clang fp contract(off)
+    NumSum r{0.0, 0.0, 0};
+#pragma unroll
+    for (int k = 0; k < kPtLeaf; k++) {
+        const int64_t t = kPtLeaf * j + k;
+        if (t < n_pts) {
+            const double4 p = pts[t];
+            const double q = sqrt(dist2(px, py, pz, p.x, p.y, p.z)) / h;
+            if (q < 2.0) {
+                r.sum_w += m4_w(q);
+                r.sum_qdw += m4_qdw(q);
+                r.count++;
+            }
+        }
+    }
+    return r;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Adds the leaf sums of the lanes in `mask` to r, in lane order.
+__device__ __forceinline__ void add_leaf_sums(NumSum &r, const NumSum &mine, unsigned long long mask)
+{
+#pragma clang fp contract(off)
+    while (mask) {
+        const int l = __ffsll((long long)mask) - 1;
+        mask &= mask - 1;
+        r.sum_w += readlane_f64(mine.sum_w, l);
+        r.sum_qdw += readlane_f64(mine.sum_qdw, l);
+        r.count += __builtin_amdgcn_readlane((int)mine.count, l);
+    }
+}
+
 // One wavefront evaluates the number sum for one node.  Lane l tests leaf
-// base+l of the point tree and evaluates its (up to 8) points; the values are
-// then added by every lane in point order (leaf by leaf, point by point), so
-// the sum equals the plain sequential sum over all points (terms beyond the
-// support are exact zeros) whatever the launch shape.
+// base+l of the point tree and adds its points' terms in point order; the
+// leaves' sums are then added in leaf order.  Leaves beyond the support add
+// nothing, so the result does not depend on the launch shape nor on which
+// other leaves are scanned (number_sum_list below gives the same bits).
 __device__ NumSum number_sum_wave(double px, double py, double pz, double h, int64_t n_pts,
                                   const double4 *__restrict__ pts, const double *__restrict__ bx, int64_t NL,
                                   int64_t nleaf, int lane)
 {
-#pragma clang fp contract(off)
     NumSum r{0.0, 0.0, 0};
     const double R2 = 4.0 * h * h * (1.0 + 1e-9);
     for (int64_t base = 0; base < nleaf; base += 64) {
         const int64_t j = base + lane;
-        double wv[kPtLeaf], dv[kPtLeaf];
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < kPtLeaf; k++) {
-            wv[k] = 0.0;
-            dv[k] = 0.0;
-        }
-        if (j < nleaf && box_gap2(bx + 6 * (NL + j), px, py, pz) <= R2) {
-#pragma unroll
-            for (int k = 0; k < kPtLeaf; k++) {
-                const int64_t t = kPtLeaf * j + k;
-                if (t < n_pts) {
-                    const double4 p = pts[t];
-                    const double q = sqrt(dist2(px, py, pz, p.x, p.y, p.z)) / h;
-                    if (q < 2.0) {
-                        wv[k] = m4_w(q);
-                        dv[k] = m4_qdw(q);
-                        any = true;
-                    }
-                }
-            }
-        }
-        unsigned long long mask = __ballot(any);
-        while (mask) {
-            const int l = __ffsll((long long)mask) - 1;
-            mask &= mask - 1;
-#pragma unroll
-            for (int k = 0; k < kPtLeaf; k++) {
-                const double v = __shfl(wv[k], l, 64);
-                const double d = __shfl(dv[k], l, 64);
-                r.sum_w += v;
-                r.sum_qdw += d;
-                r.count += v != 0.0 ? 1 : 0;
-            }
-        }
+        NumSum mine{0.0, 0.0, 0};
+        if (j < nleaf && box_gap2(bx + 6 * (NL + j), px, py, pz) <= R2)
+            mine = leaf_terms(px, py, pz, h, n_pts, pts, j);
+        add_leaf_sums(r, mine, __ballot(mine.count > 0));
     }
     return r;
 }
@@ -643,54 +654,21 @@ __device__ int collect_leaves(double px, double py, double pz, double R2, const 
 
 // The number sum of number_sum_wave restricted to listed leaves (a superset
 // of the leaves that meet the ball of radius 2h, in increasing order): the same
-// terms are added in the same order, so the result is bitwise the same.
+// leaf sums are added in the same order, so the result is bitwise the same.
 __device__ NumSum number_sum_list(double px, double py, double pz, double h, int64_t n_pts,
                                   const double4 *__restrict__ pts, const double *__restrict__ bx, int64_t NL,
                                   const int32_t *list, int cnt, int lane)
 {
-#pragma clang fp contract(off)
     NumSum r{0.0, 0.0, 0};
     const double R2 = 4.0 * h * h * (1.0 + 1e-9);
     for (int base = 0; base < cnt; base += 64) {
         const int i = base + lane;
-        double wv[kPtLeaf], dv[kPtLeaf];
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < kPtLeaf; k++) {
-            wv[k] = 0.0;
-            dv[k] = 0.0;
-        }
+        NumSum mine{0.0, 0.0, 0};
         if (i < cnt) {
             const int64_t j = list[i];
-            if (box_gap2(bx + 6 * (NL + j), px, py, pz) <= R2) {
-#pragma unroll
-                for (int k = 0; k < kPtLeaf; k++) {
-                    const int64_t t = kPtLeaf * j + k;
-                    if (t < n_pts) {
-                        const double4 p = pts[t];
-                        const double q = sqrt(dist2(px, py, pz, p.x, p.y, p.z)) / h;
-                        if (q < 2.0) {
-                            wv[k] = m4_w(q);
-                            dv[k] = m4_qdw(q);
-                            any = true;
-                        }
-                    }
-                }
-            }
+            if (box_gap2(bx + 6 * (NL + j), px, py, pz) <= R2) mine = leaf_terms(px, py, pz, h, n_pts, pts, j);
         }
-        unsigned long long mask = __ballot(any);
-        while (mask) {
-            const int l = __ffsll((long long)mask) - 1;
-            mask &= mask - 1;
-#pragma unroll
-            for (int k = 0; k < kPtLeaf; k++) {
-                const double v = __shfl(wv[k], l, 64);
-                const double d = __shfl(dv[k], l, 64);
-                r.sum_w += v;
-                r.sum_qdw += d;
-                r.count += v != 0.0 ? 1 : 0;
-            }
-        }
+        add_leaf_sums(r, mine, __ballot(mine.count > 0));
     }
     return r;
 }
