@@ -181,8 +181,7 @@ def adaptive_leg(em, mp, xyz, m, h, src, par):
             "n_regions_out", "r_part", "r_leaf", "ms_tree", "ms_walks", "ms_callback", "ms_total")
     one = lambda r, a: dict({k: a[k] for k in keys}, pseudo=int(r["m"].size),
                             ms_per_walk=a["ms_walks"] / max(a["n_walks"], 1),
-                            last_walk={k: r["stats"][k]
-                                       for k in ("ms_walk", "ms_hsolve", "n_pseudo_nodes", "n_h_evals")})
+                            last_walk={k: r["stats"][k] for k in ("n_pseudo_nodes", "n_h_evals")})
     return {"field": "ionised sphere r 0.15 + 0.05 ramp at the source; K 100",
             "step1": one(r1, a1), "step2_with_regions": one(r2, a2)}
 
