@@ -772,13 +772,35 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
     const int lane = threadIdx.x & 63;
     WaveStacks &W = stacks[threadIdx.x >> 6];
     const int64_t ntiles = (np + 63) / 64;
+    // Tiles in XCD-aware order: workgroups are dispatched round-robin over the
+    // 8 XCDs, so workgroup b runs on XCD b mod 8; each XCD first takes the
+    // tiles of its own eighth of the (cell-ordered) pair list from its own
+    // counter, so the tiles that share a cell's wall and edge records meet in
+    // one L2, then takes what is left in the other eighths.  A pair's result
+    // does not depend on the wavefront that computes it.
+    const int xcd = (int)(blockIdx.x & 7);
+    const int64_t chunk = (ntiles + 7) / 8;
+    int probe = 0;
     Work wk;
     for (;;) {
-        unsigned t = 0;
-        if (lane == 0) t = atomicAdd(tile_ctr, 1u);
-        t = __builtin_amdgcn_readfirstlane(t);
-        if ((int64_t)t >= ntiles) break;
-        const int64_t k = (int64_t)t * 64 + lane;
+        int64_t t = -1;
+        while (probe < 8) {
+            const int y = (xcd + probe) & 7;
+            const int64_t lo = (int64_t)y * chunk;
+            const int64_t hi = lo + chunk < ntiles ? lo + chunk : ntiles;
+            if (lo < hi) {
+                unsigned v = 0;
+                if (lane == 0) v = atomicAdd(tile_ctr + 16 + y, 1u);
+                v = __builtin_amdgcn_readfirstlane(v);
+                if (lo + (int64_t)v < hi) {
+                    t = lo + (int64_t)v;
+                    break;
+                }
+            }
+            probe++;
+        }
+        if (t < 0) break;
+        const int64_t k = t * 64 + lane;
         const bool active = k < np;
         double px = 0.0, py = 0.0, pz = 0.0, invh = 1.0;
         int32_t s = 0, s_end = 0, j = 0;
@@ -1287,7 +1309,8 @@ void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &
     fx.count = tile_ctr + 1;
     fx.items = fix_items;
     fx.cap = (unsigned)(fix_cap > 0xffffffffLL ? 0xffffffffLL : fix_cap);
-    fill_zero_bytes(tile_ctr, 2 * sizeof(unsigned), s);
+    // [0] tile counter, [1] fixup count, [16..23] per-XCD tile counters
+    fill_zero_bytes(tile_ctr, 24 * sizeof(unsigned), s);
     const int block = 256;
     if (!tune.persistent) {
         const unsigned g = (unsigned)((np + block - 1) / block);

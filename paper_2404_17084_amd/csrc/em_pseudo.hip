@@ -694,10 +694,6 @@ __device__ NumSum number_sum_cached(LeafCache &C, double px, double py, double p
     return number_sum_list(px, py, pz, h, n_pts, pts, bx, NL, C.list, C.cnt, lane);
 }
 
-struct HStats {
-    unsigned long long evals, neighbours, fallbacks;
-};
-
 // One wavefront per point; points that are pseudo nodes solve N(h) = h_fact^3.
 // All lanes run the same control flow on the same (wave-uniform) values.
 __global__ void __launch_bounds__(256) k_hsolve(int64_t n_pts, const double4 *__restrict__ pts,
