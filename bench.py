@@ -36,8 +36,8 @@ FLOP_ANGLE = 6      # angle of one edge part seen from the foot point (one atan2
 # HBM bytes per launch of the mixed integration kernel from FETCH_SIZE/WRITE_SIZE counter runs scaled by a
 # 1 GiB copy (profiles/traffic_integrate_queued_clumps262144.md), valid for the source it was measured on.
 TRAFFIC_SOURCE = "paper_2404_17084_amd/csrc/em_integrate.hip"
-TRAFFIC_SHA256_PREFIX = "d2ea6911357ae1a1"
-TRAFFIC_BYTES = 2.251e9 + 0.283e9
+TRAFFIC_SHA256_PREFIX = "739857dddd99444c"
+TRAFFIC_BYTES = 2.270e9 + 0.283e9
 
 PEAK_FP64 = 78.6   # TFLOP/s, MI355X FP64 vector
 PEAK_FP32 = 157.3  # TFLOP/s, MI355X FP32 vector (packed)

@@ -495,6 +495,33 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_persistent(int64_t np, c
     flush_work(wk, counters);
 }
 
+// Next tile of a persistent kernel in XCD-aware order, or -1 when none is
+// left.  Workgroups are dispatched round-robin over the 8 XCDs, so workgroup
+// b runs on XCD b mod 8; each XCD first takes the tiles of its own eighth of
+// the (cell-ordered) pair list from its own counter ctr[x], so the tiles that
+// share a cell's wall and edge records meet in one L2, then takes what is
+// left in the other eighths.  `probe` (0 at the start) persists between
+// calls.  Wave-uniform.  A pair's result does not depend on the wavefront
+// that computes it.
+__device__ __forceinline__ int64_t next_tile_xcd(unsigned *ctr, int64_t ntiles, int &probe, int lane)
+{
+    const int xcd = (int)(blockIdx.x & 7);
+    const int64_t chunk = (ntiles + 7) / 8;
+    while (probe < 8) {
+        const int y = (xcd + probe) & 7;
+        const int64_t lo = (int64_t)y * chunk;
+        const int64_t hi = lo + chunk < ntiles ? lo + chunk : ntiles;
+        if (lo < hi) {
+            unsigned v = 0;
+            if (lane == 0) v = atomicAdd(ctr + y, 1u);
+            v = __builtin_amdgcn_readfirstlane(v);
+            if (lo + (int64_t)v < hi) return lo + (int64_t)v;
+        }
+        probe++;
+    }
+    return -1;
+}
+
 // ---------------------------------------------------------------- queued tasks (mixed path)
 // The edge terms split into independent tasks of three kinds: angles (one
 // atan2), closed-form points (one trans + core) and shell quadrature
@@ -772,33 +799,10 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
     const int lane = threadIdx.x & 63;
     WaveStacks &W = stacks[threadIdx.x >> 6];
     const int64_t ntiles = (np + 63) / 64;
-    // Tiles in XCD-aware order: workgroups are dispatched round-robin over the
-    // 8 XCDs, so workgroup b runs on XCD b mod 8; each XCD first takes the
-    // tiles of its own eighth of the (cell-ordered) pair list from its own
-    // counter, so the tiles that share a cell's wall and edge records meet in
-    // one L2, then takes what is left in the other eighths.  A pair's result
-    // does not depend on the wavefront that computes it.
-    const int xcd = (int)(blockIdx.x & 7);
-    const int64_t chunk = (ntiles + 7) / 8;
     int probe = 0;
     Work wk;
     for (;;) {
-        int64_t t = -1;
-        while (probe < 8) {
-            const int y = (xcd + probe) & 7;
-            const int64_t lo = (int64_t)y * chunk;
-            const int64_t hi = lo + chunk < ntiles ? lo + chunk : ntiles;
-            if (lo < hi) {
-                unsigned v = 0;
-                if (lane == 0) v = atomicAdd(tile_ctr + 16 + y, 1u);
-                v = __builtin_amdgcn_readfirstlane(v);
-                if (lo + (int64_t)v < hi) {
-                    t = lo + (int64_t)v;
-                    break;
-                }
-            }
-            probe++;
-        }
+        const int64_t t = next_tile_xcd(tile_ctr + 16, ntiles, probe, lane);
         if (t < 0) break;
         const int64_t k = t * 64 + lane;
         const bool active = k < np;
@@ -911,13 +915,12 @@ __global__ void __launch_bounds__(256, 2) k_integrate_queued64(int64_t np, const
     const int lane = threadIdx.x & 63;
     WaveStacks64 &W = stacks[threadIdx.x >> 6];
     const int64_t ntiles = (np + 63) / 64;
+    int probe = 0;
     Work wk;
     for (;;) {
-        unsigned t = 0;
-        if (lane == 0) t = atomicAdd(tile_ctr, 1u);
-        t = __builtin_amdgcn_readfirstlane(t);
-        if ((int64_t)t >= ntiles) break;
-        const int64_t k = (int64_t)t * 64 + lane;
+        const int64_t t = next_tile_xcd(tile_ctr + 16, ntiles, probe, lane);
+        if (t < 0) break;
+        const int64_t k = t * 64 + lane;
         const bool active = k < np;
         double px = 0.0, py = 0.0, pz = 0.0, invh = 1.0;
         int64_t s = 0, s_end = 0, j = 0;

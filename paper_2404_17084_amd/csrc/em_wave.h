@@ -25,4 +25,15 @@ __device__ __forceinline__ void lds_sync_wave()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Logical index of this workgroup in an XCD-aware order.  Workgroups are
+// dispatched round-robin over the 8 XCDs (workgroup b to XCD b mod 8); this
+// gives XCD x a contiguous run of logical indices (x * per + min(x, rem) ...,
+// per = nb / 8, rem = nb mod 8), so neighbouring work shares one L2.  A
+// bijection of [0, nb).
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
+{
+    const unsigned x = b & 7u, k = b >> 3, per = nb >> 3, rem = nb & 7u;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
 }  // namespace em
