@@ -388,7 +388,7 @@ __global__ void __launch_bounds__(256) k_exact(int64_t n_need, const uint32_t *_
     __shared__ CellFast stage[4];
     CellFast &L = stage[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
-    const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = t < n_need;
     int64_t i = 0, c = -1, a = 0;
     double px = 0.0, py = 0.0, pz = 0.0, r2 = 0.0, r = 0.0;

@@ -147,15 +147,40 @@ __global__ void k_lv_flags(int64_t n, int L, const int32_t *__restrict__ cur, co
     flag[i] = (c >= 0 && (i == 0 || cur[i - 1] != c || dlev[i] <= L)) ? 1 : 0;
 }
 
-__global__ void k_lv_nodes(int64_t n, int L, int32_t base, const int32_t *__restrict__ cur,
+// Level state on the device (so a level needs one host read, at its end):
+// lv[0] internal nodes of the level, lv[1] nodes of the level, lv[2] set when
+// the node table would overflow (the level's kernels then write nothing),
+// lv[3] index of the level's first node.
+__global__ void k_lv_init(unsigned *lv)
+{
+    lv[0] = 0u;
+    lv[1] = 0u;
+    lv[2] = 0u;
+    lv[3] = 1u;
+}
+
+__global__ void k_lv_count(int64_t n, const int64_t *__restrict__ off, int32_t cap, unsigned *lv)
+{
+    const int64_t cnt = off[n];
+    lv[0] = 0u;
+    lv[1] = (unsigned)cnt;
+    if ((int64_t)lv[3] + cnt > (int64_t)cap) lv[2] = 1u;
+}
+
+__global__ void k_lv_advance(unsigned *lv)
+{
+    if (!lv[2]) lv[3] += lv[1];
+}
+
+__global__ void k_lv_nodes(int64_t n, int L, const unsigned *__restrict__ lv, const int32_t *__restrict__ cur,
                            const int64_t *__restrict__ flag, const int64_t *__restrict__ off,
                            const uint64_t *__restrict__ key, Nodes T)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || lv[2]) return;
     const int32_t c = cur[i];
     if (c < 0) return;
-    const int32_t nid = base + (int32_t)(off[i] + flag[i] - 1);
+    const int32_t nid = (int32_t)lv[3] + (int32_t)(off[i] + flag[i] - 1);
     if (flag[i]) {
         T.start[nid] = (int32_t)i;
         T.parent[nid] = c;
@@ -165,26 +190,27 @@ __global__ void k_lv_nodes(int64_t n, int L, int32_t base, const int32_t *__rest
     if (i + 1 == n || cur[i + 1] != c || flag[i + 1]) T.end[nid] = (int32_t)(i + 1);
 }
 
-__global__ void k_lv_leaf(int32_t count, int32_t base, int L, int leaf_size, Nodes T, unsigned *internal)
+__global__ void k_lv_leaf(int L, int leaf_size, Nodes T, unsigned *lv)
 {
     const int32_t t = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
     bool inner = false;
-    if (t < count) {
-        const int32_t i = base + t;
+    if (!lv[2] && t < (int32_t)lv[1]) {
+        const int32_t i = (int32_t)lv[3] + t;
         const bool leaf = (T.end[i] - T.start[i] <= leaf_size) || L == kMaxLevel;
         T.leaf[i] = leaf;
         inner = !leaf;
     }
     const unsigned long long b = __ballot(inner);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(internal, (unsigned)__popcll(b));
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(lv, (unsigned)__popcll(b));
 }
 
-__global__ void k_lv_cur(int64_t n, int32_t base, const int64_t *__restrict__ flag, const int64_t *__restrict__ off,
-                         const uint8_t *__restrict__ leaf, int32_t *__restrict__ cur, int32_t *__restrict__ leaf_of)
+__global__ void k_lv_cur(int64_t n, const unsigned *__restrict__ lv, const int64_t *__restrict__ flag,
+                         const int64_t *__restrict__ off, const uint8_t *__restrict__ leaf, int32_t *__restrict__ cur,
+                         int32_t *__restrict__ leaf_of)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || cur[i] < 0) return;
-    const int32_t nid = base + (int32_t)(off[i] + flag[i] - 1);
+    if (i >= n || lv[2] || cur[i] < 0) return;
+    const int32_t nid = (int32_t)lv[3] + (int32_t)(off[i] + flag[i] - 1);
     if (leaf[nid]) {
         leaf_of[i] = nid;
         cur[i] = -1;
@@ -990,7 +1016,7 @@ void build_tree(Workspace &ws, const DevParticles &P, const double box[6], int l
     int32_t *leaf_of = ws.get<int32_t>(S_PSEUDO8, (size_t)n);
     int64_t *flag = ws.get<int64_t>(S_PSEUDO9, (size_t)n + 1);
     int64_t *off = ws.get<int64_t>(S_PSEUDO10, (size_t)n + 1);
-    unsigned *small = ws.get<unsigned>(S_PSEUDO11, 64);  // [0] internal-node count
+    unsigned *small = ws.get<unsigned>(S_PSEUDO11, 64);  // [0..3] level state, see k_lv_init
     hipLaunchKernelGGL(k_root, dim3(grid_of(n)), dim3(256), 0, s, n, ls, T, cur, leaf_of);
     EM_HIP(hipGetLastError());
 
@@ -1000,31 +1026,34 @@ void build_tree(Workspace &ws, const DevParticles &P, const double box[6], int l
     int32_t base = 1;
     int max_level = 0;
     bool inner = n > ls;
+    hipLaunchKernelGGL(k_lv_init, dim3(1), dim3(1), 0, s, small);
+    EM_HIP(hipGetLastError());
     for (int L = 1; L <= kMaxLevel && inner; L++) {
         hipLaunchKernelGGL(k_lv_flags, dim3(grid_of(n)), dim3(256), 0, s, n, L, (const int32_t *)cur,
                            (const uint8_t *)dlev, flag);
         EM_HIP(hipGetLastError());
         scan_counts(ws, flag, off, n, s);
-        int64_t cnt = 0;
-        EM_HIP(hipMemcpyAsync(&cnt, off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        hipLaunchKernelGGL(k_lv_count, dim3(1), dim3(1), 0, s, n, (const int64_t *)off, cap, small);
+        EM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_lv_nodes, dim3(grid_of(n)), dim3(256), 0, s, n, L, (const unsigned *)small,
+                           (const int32_t *)cur, (const int64_t *)flag, (const int64_t *)off, (const uint64_t *)key, T);
+        EM_HIP(hipGetLastError());
+        // a level has at most n nodes
+        hipLaunchKernelGGL(k_lv_leaf, dim3(grid_of(n)), dim3(256), 0, s, L, ls, T, small);
+        EM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_lv_cur, dim3(grid_of(n)), dim3(256), 0, s, n, (const unsigned *)small,
+                           (const int64_t *)flag, (const int64_t *)off, (const uint8_t *)T.leaf, cur, leaf_of);
+        EM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_lv_advance, dim3(1), dim3(1), 0, s, small);
+        EM_HIP(hipGetLastError());
+        unsigned lv[4] = {0u, 0u, 0u, 0u};
+        EM_HIP(hipMemcpyAsync(lv, small, sizeof(lv), hipMemcpyDeviceToHost, s));
         EM_HIP(hipStreamSynchronize(s));
-        EM_CHECK((int64_t)base + cnt <= cap, MAP_EDEVICE, "octree node table overflow");
-        hipLaunchKernelGGL(k_lv_nodes, dim3(grid_of(n)), dim3(256), 0, s, n, L, base, (const int32_t *)cur,
-                           (const int64_t *)flag, (const int64_t *)off, (const uint64_t *)key, T);
-        EM_HIP(hipGetLastError());
-        fill_zero_bytes(small, sizeof(unsigned), s);
-        hipLaunchKernelGGL(k_lv_leaf, dim3(grid_of(cnt)), dim3(256), 0, s, (int32_t)cnt, base, L, ls, T, small);
-        EM_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_lv_cur, dim3(grid_of(n)), dim3(256), 0, s, n, base, (const int64_t *)flag,
-                           (const int64_t *)off, (const uint8_t *)T.leaf, cur, leaf_of);
-        EM_HIP(hipGetLastError());
-        unsigned n_inner = 0;
-        EM_HIP(hipMemcpyAsync(&n_inner, small, sizeof(unsigned), hipMemcpyDeviceToHost, s));
-        EM_HIP(hipStreamSynchronize(s));
-        base += (int32_t)cnt;
+        EM_CHECK(lv[2] == 0u, MAP_EDEVICE, "octree node table overflow");
+        base = (int32_t)lv[3];
         lvl_off[L + 1] = base;
         max_level = L;
-        inner = n_inner > 0;
+        inner = lv[0] > 0u;
     }
     const int32_t n_nodes = base;
     hipLaunchKernelGGL(k_children, dim3(grid_of(n_nodes)), dim3(256), 0, s, n_nodes, T);
