@@ -25,8 +25,10 @@
 // N(h) = (1/pi) sum_b w(|x - x_b| / h) runs over the node pseudo-particles and
 // the leaves standing in for extracted particles, grouped 8 per box in Morton
 // order.  One wavefront per node solves N(h) = h_fact^3 by Newton steps kept
-// inside a bisection bracket; each evaluation tests 64 boxes per step against
-// the ball of radius 2h and adds the contributions in point order.
+// inside a bisection bracket, stopping once a step no longer moves the
+// iterate; each evaluation tests the boxes listed within 2h (64 per step),
+// each lane sums its box's points in point order, and the box sums are added
+// in box order.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
