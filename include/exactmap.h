@@ -79,6 +79,11 @@ typedef struct map_config {
     int max_jobs;              /* serving: jobs resident on the device at once (0 = 8) */
     int max_queue;             /* serving: jobs waiting for admission (0 = 1024) */
     const char *tune_cache_path; /* autotuner cache file (text); NULL = no cache */
+    int serve_timeout_ms;      /* serving: time limit of every device wait of a job (0 = 120000) */
+    int serve_trace;           /* serving: nonzero = one line per job event on stderr */
+    int64_t fixup_cap;         /* MAP_MIXED: capacity of the list of edge terms recomputed in
+                                  FP64 (0 = n_pairs / 8 + 65536); when more edges are flagged,
+                                  every pair of the call is recomputed in FP64 instead */
 } map_config;
 
 /* Particles: structure of arrays, FP64. */
@@ -117,6 +122,8 @@ typedef struct map_stats {
     int64_t n_quad_intervals; /* MAP_MIXED: 8-point Gauss-Legendre sub-intervals (shell piece) */
     int64_t n_angle_evals;  /* angles of edge parts beyond the support or with a piece correction */
     int64_t n_quad_points;  /* Gauss-Legendre points of the shell quadrature (mixed path) */
+    int64_t n_boundary_pairs; /* pairs whose particle lies on two or more wall planes of the cell
+                                 (an edge or a vertex): winding weight recomputed in FP64 */
     double mass_in;         /* sum of m_a */
     double mass_out;        /* sum of M_i */
     double max_abs_S_minus_1; /* over particles whose support lies inside box */
@@ -143,7 +150,11 @@ typedef struct map_out {
     map_stats *stats;      /* host memory; may be NULL */
 } map_out;
 
-/* Create a context on cfg->device (cfg may be NULL: device 0, FP64). */
+/* Create a context on cfg->device (cfg may be NULL: device 0, FP64).
+ * MAP_EDEVICE when no device is visible or when two HIP runtimes (two
+ * libamdhip64 files) are mapped into the process: the library uses the
+ * runtime it was loaded against, and device pointers of another runtime are
+ * not valid in it.  On failure map_last_error(NULL) has the message. */
 int map_init(const map_config *cfg, map_ctx **out);
 /* Drain the serving loop, free all device memory and the context. */
 int map_shutdown(map_ctx *ctx);
@@ -423,31 +434,40 @@ int map_voronoi_copy(map_ctx *ctx, int mem_kind, int64_t *cell_face_off, int64_t
                      double *sites, int64_t *site_cell);
 
 /*
- * Served mapping (continuous batching).  map_submit copies the inputs (host or
- * device memory) into library-owned memory before it returns and queues the
- * job at the context's current precision; *job_id identifies it.  Jobs are
- * admitted in submission order while a slot (cfg->max_jobs) and device memory
- * (cfg->hbm_budget_bytes, by an estimate of the job's footprint) are free; an
- * admitted job's inputs stay resident on the device until it completes.  The
- * pair sets of admitted jobs are built concurrently (one stream per slot),
- * and the integration of every job ready at that moment runs in one
- * persistent launch, so jobs arriving while others integrate join the next
- * launch.  Results are bitwise independent of the other jobs in the mix.
+ * Served mapping (continuous batching; not in the paper, whose mapping runs
+ * once per hydro step).  map_submit queues one mapping job at the context's
+ * current precision (MAP_FP64 or MAP_MIXED) and returns at once; *job_id
+ * identifies it.  Host inputs are copied before map_submit returns; device
+ * inputs (mem_kind MAP_MEM_DEVICE) are borrowed, like the outputs: they must
+ * stay valid and unchanged until map_poll reports the job finished.
+ * Jobs are admitted in submission order while a slot (cfg->max_jobs) and
+ * device memory (cfg->hbm_budget_bytes, by an estimate of the job's
+ * footprint) are free; an admitted job's geometry stays resident on the
+ * device until it completes.  One scheduler thread per context makes all the
+ * device calls: it builds admitted jobs' pair sets on a stage stream and,
+ * whenever no integration is running, integrates every job whose pair set is
+ * ready in one persistent launch of the task-batch kernel (a table of the
+ * jobs), so jobs arriving while others integrate join the next launch and
+ * their staging overlaps it.  A job's results are bitwise those of
+ * map_particles on the same inputs with the default launch shape, alone or in
+ * any mix.
  * The out buffers (and out->stats) are caller-owned and must stay valid until
  * map_poll reports MAP_JOB_DONE or MAP_JOB_FAILED.
  * Errors at submit: MAP_EINVAL/MAP_EGEOM (malformed input), MAP_ENOMEM (job
- * larger than the whole budget), MAP_EBUSY (queue holds cfg->max_queue jobs).
- * A job that fails later does not affect the others.
- *
- * Status: switched off.  map_submit returns MAP_ENOTSUP and queues nothing:
- * a run of the served path on the device stopped making progress and its
- * cause has not been found, so the path is not offered until it is.
+ * larger than the whole budget), MAP_EBUSY (queue holds cfg->max_queue jobs,
+ * or the context is shutting down), MAP_EDEVICE (serving stopped after a
+ * device failure).  A job that fails later does not affect the others.  Every
+ * device wait of the served path is bounded by cfg->serve_timeout_ms; when
+ * one runs out, the jobs in flight and all later ones fail with MAP_EDEVICE
+ * (the device cannot be trusted any more) and map_shutdown returns
+ * MAP_EDEVICE, leaving the context's memory in place.
  */
 enum { MAP_JOB_PENDING = 0, MAP_JOB_RUNNING = 1, MAP_JOB_DONE = 2, MAP_JOB_FAILED = 3 };
 int map_submit(map_ctx *ctx, const map_particles_in *p, const map_cells_in *c, map_out *out, uint64_t *job_id);
 /*
- * Waits up to timeout_us microseconds (0: no wait, negative: until finished)
- * and writes the job's state.  Once DONE or FAILED has been reported the job
+ * Waits up to timeout_us microseconds (0: no wait, negative: until finished,
+ * but at most twice cfg->serve_timeout_ms plus 5 s, after which MAP_EDEVICE
+ * is returned with the job still running) and writes the job's state.  Once DONE or FAILED has been reported the job
  * is forgotten (a later poll returns MAP_ENOTFOUND).  For a failed job the
  * return value is the job's error code and map_last_error has its message.
  */

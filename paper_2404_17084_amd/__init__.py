@@ -43,7 +43,8 @@ c_i64, c_i32, c_int, c_dbl, c_vp, c_u64 = (ctypes.c_int64, ctypes.c_int32, ctype
 
 class map_config(ctypes.Structure):
     _fields_ = [("device", c_int), ("precision", c_int), ("hbm_budget_bytes", c_u64), ("max_jobs", c_int),
-                ("max_queue", c_int), ("tune_cache_path", ctypes.c_char_p)]
+                ("max_queue", c_int), ("tune_cache_path", ctypes.c_char_p), ("serve_timeout_ms", c_int),
+                ("serve_trace", c_int), ("fixup_cap", c_i64)]
 
 
 class map_particles_in(ctypes.Structure):
@@ -66,6 +67,7 @@ class map_stats(ctypes.Structure):
     _fields_ = [("n_pairs", c_i64), ("n_candidates", c_i64), ("n_edge_terms", c_i64), ("n_fixup_terms", c_i64),
                 ("n_face_visits", c_i64), ("n_edge_visits", c_i64), ("n_moment_evals", c_i64),
                 ("n_quad_intervals", c_i64), ("n_angle_evals", c_i64), ("n_quad_points", c_i64),
+                ("n_boundary_pairs", c_i64),
                 ("mass_in", c_dbl), ("mass_out", c_dbl), ("max_abs_S_minus_1", c_dbl), ("ms_setup", c_dbl),
                 ("ms_pairs", c_dbl), ("ms_integrate", c_dbl), ("ms_fixup", c_dbl), ("ms_reduce", c_dbl),
                 ("ms_total", c_dbl), ("ms_queue", c_dbl), ("ms_latency", c_dbl)]
@@ -163,22 +165,31 @@ _SIGS = {
 }
 
 
-def _torch_runtime_first():
-    """Initialise torch's HIP runtime before this library's.
+def _runtime_of_torch():
+    """Load torch (the plumbing for device memory and streams) before the library.
 
-    torch ships its own HIP runtime next to the system one this library links;
-    both can live in one process only when torch's initialises first (device
-    pointers are shared either way).  Counting devices does not initialise
-    anything, so a GPU-less host is left alone."""
+    torch ships a HIP runtime of its own whose soname equals the system one's;
+    when torch is in the process first, the library binds to that same runtime
+    and one runtime serves both.  Loading the library first would map the
+    system runtime and then torch's as a second one."""
     try:
-        import torch
+        import torch  # noqa: F401
     except ImportError:
-        return
-    try:
-        if torch.cuda.device_count() > 0:
-            torch.cuda.init()
-    except Exception:
         pass
+
+
+def hip_runtimes_mapped():
+    """Distinct libamdhip64 files mapped into this process."""
+    seen = []
+    try:
+        with open("/proc/self/maps") as fh:
+            for line in fh:
+                path = line.split()[-1] if "/" in line else ""
+                if "libamdhip64" in path and path not in seen:
+                    seen.append(path)
+    except OSError:
+        pass
+    return seen
 
 
 def load():
@@ -187,8 +198,12 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libexactmap is not built ({LIB_PATH}); run __graft_entry__.build() first")
-        _torch_runtime_first()
+        _runtime_of_torch()
         lib = ctypes.CDLL(LIB_PATH)
+        rts = hip_runtimes_mapped()
+        if len(rts) > 1:
+            raise RuntimeError(f"two HIP runtimes are mapped into this process ({rts}); import torch before "
+                               f"anything else that loads a HIP runtime")
         for name, (res, args) in _SIGS.items():
             if hasattr(lib, name):
                 fn = getattr(lib, name)
@@ -200,7 +215,7 @@ def load():
 
 def _check(ctx, rc):
     if rc != MAP_OK:
-        msg = load().map_last_error(ctx) if ctx else b""
+        msg = load().map_last_error(ctx if ctx else None)
         raise MapError(rc, (msg or b"").decode())
 
 
@@ -274,10 +289,12 @@ def cells_in(cells, device_arrays=None):
 
 # ---------------------------------------------------------------- ABI-named wrappers
 def map_init(device: int = 0, precision: int = MAP_FP64, hbm_budget_bytes: int = 0, max_jobs: int = 0,
-             max_queue: int = 0, tune_cache_path: str | None = None):
+             max_queue: int = 0, tune_cache_path: str | None = None, serve_timeout_ms: int = 0,
+             serve_trace: bool = False, fixup_cap: int = 0):
     lib = load()
     cfg = map_config(device, precision, hbm_budget_bytes, max_jobs, max_queue,
-                     tune_cache_path.encode() if tune_cache_path else None)
+                     tune_cache_path.encode() if tune_cache_path else None, int(serve_timeout_ms),
+                     1 if serve_trace else 0, int(fixup_cap))
     ctx = c_vp()
     _check(None, lib.map_init(ctypes.byref(cfg), ctypes.byref(ctx)))
     return ctx
@@ -413,7 +430,8 @@ def map_submit(ctx, xyz, m, h, cells, cell_mass=None, cell_density=None, frac_su
                 ctypes.pointer(st))
     jid = c_u64()
     _check(ctx, lib.map_submit(ctx, ctypes.byref(P), ctypes.byref(C), ctypes.byref(O), ctypes.byref(jid)))
-    _SERVED[(ctx.value, jid.value)] = (O, st, outs)
+    # outputs, statistics and borrowed device inputs stay referenced until the job has finished
+    _SERVED[(ctx.value, jid.value)] = (O, st, outs, k1, k2, xyz, m, h, cells)
     return jid.value
 
 

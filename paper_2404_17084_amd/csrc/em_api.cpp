@@ -2,8 +2,11 @@
 // mapping pipeline and its statistics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <vector>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -132,7 +135,7 @@ void prepare(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_i
     launch_validate(in, flags, s);
     unsigned hf = 0;
     EM_HIP(hipMemcpyAsync(&hf, flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
-    EM_HIP(hipStreamSynchronize(s));
+    stream_sync(s);
     EM_CHECK(hf == 0, flag_code(hf), flag_text(hf));
 
     edges = ws.get<EdgeRec>(S_EDGE, (size_t)(c->n_face_verts > 0 ? c->n_face_verts : 1));
@@ -174,7 +177,7 @@ void stage_pairs(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cel
     const int64_t np = js.ps.n_pairs;
     js.f = ws.get<double>(S_F, (size_t)(np > 0 ? np : 1));
     js.tile_ctr = ws.get<uint32_t>(S_TILE_CTR, 64);
-    js.fix_cap = np / 8 + 65536;
+    js.fix_cap = C.config.fixup_cap > 0 ? C.config.fixup_cap : np / 8 + 65536;
     js.fix_items = ws.get<uint64_t>(S_FIX_ITEMS, (size_t)js.fix_cap);
     fill_zero_bytes(js.tile_ctr, 2 * sizeof(unsigned), s);
 }
@@ -189,25 +192,49 @@ int64_t stage_finish(Ctx &C, Workspace &ws, JobState &js, const map_out *out, hi
     const int64_t np = ps.n_pairs;
     double *f = js.f;
     int64_t n_fix = 0;
-    if (js.precision == MAP_MIXED && np > 0) {
-        unsigned hfix = 0;
-        EM_HIP(hipMemcpyAsync(&hfix, js.tile_ctr + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s));
-        EM_HIP(hipStreamSynchronize(s));
-        n_fix = hfix;
-        if (n_fix > js.fix_cap) {
-            // too many flagged edges for the fixup list: redo every pair in FP64
-            IntegrateTune t64 = default_tune(MAP_FP64);
-            launch_integrate(in, js.edges, ps, MAP_FP64, t64, f, js.counters, js.tile_ctr, js.fix_items, js.fix_cap, s);
-            n_fix = np;
-        } else if (n_fix > 0) {
-            uint32_t *iv = ws.get<uint32_t>(S_FIX_VAL2, (size_t)n_fix);
-            uint64_t *k2 = ws.get<uint64_t>(S_FIX_KEY2, (size_t)n_fix);
-            uint32_t *v2 = reinterpret_cast<uint32_t *>(ws.get<uint64_t>(S_FIX_VALS, (size_t)n_fix * 2));
-            fill_iota_u32(iv, n_fix, s);
-            radix_sort_u64(ws, js.fix_items, iv, k2, v2, n_fix, 64, s);
+    if ((js.precision == MAP_MIXED || js.precision == MAP_FP64) && np > 0) {
+        // the fixup list: edge terms flagged by the mixed path's conditioning
+        // test, and pairs whose particle lies on two or more of the cell's
+        // wall planes (winding weight), both precisions
+        auto read_count = [&]() -> int64_t {
+            unsigned hfix = 0;
+            EM_HIP(hipMemcpyAsync(&hfix, js.tile_ctr + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+            stream_sync(s);
+            return (int64_t)hfix;
+        };
+        int64_t n_items = read_count();
+        n_fix = n_items;
+        if (n_items > js.fix_cap) {
+            const IntegrateTune t64 = default_tune(MAP_FP64);
+            if (js.precision == MAP_MIXED) {
+                // too many flagged edges for the list: every pair again in FP64
+                // (whose list then holds winding items only)
+                launch_integrate(in, js.edges, ps, MAP_FP64, t64, f, js.counters, js.tile_ctr, js.fix_items,
+                                 js.fix_cap, s);
+                n_items = read_count();
+                n_fix = np;
+            }
+            if (n_items > js.fix_cap) {
+                // more winding items than the list holds: a list that fits them, and the FP64 pass again
+                js.fix_cap = n_items;
+                js.fix_items = ws.get<uint64_t>(S_FIX_ITEMS, (size_t)n_items);
+                launch_integrate(in, js.edges, ps, MAP_FP64, t64, f, js.counters, js.tile_ctr, js.fix_items,
+                                 js.fix_cap, s);
+                n_items = read_count();
+                EM_CHECK(n_items <= js.fix_cap, MAP_EDEVICE, "fixup list overflow after resizing");
+                n_fix = np;
+            }
+        }
+        if (js.precision == MAP_FP64 && n_fix != np) n_fix = 0;  // FP64: no edge terms are recomputed
+        if (n_items > 0) {
+            uint32_t *iv = ws.get<uint32_t>(S_FIX_VAL2, (size_t)n_items);
+            uint64_t *k2 = ws.get<uint64_t>(S_FIX_KEY2, (size_t)n_items);
+            uint32_t *v2 = reinterpret_cast<uint32_t *>(ws.get<uint64_t>(S_FIX_VALS, (size_t)n_items * 2));
+            fill_iota_u32(iv, n_items, s);
+            radix_sort_u64(ws, js.fix_items, iv, k2, v2, n_items, 64, s);
             double *fv = reinterpret_cast<double *>(k2);
-            launch_fixup(in, js.edges, ps, js.fix_items, n_fix, fv, s);
-            launch_fixup_apply(js.fix_items, fv, n_fix, f, s);
+            launch_fixup(in, js.edges, ps, js.fix_items, n_items, fv, js.counters, s);
+            launch_fixup_apply(js.fix_items, fv, n_items, f, s);
         }
     }
     if (js.ev_fix) EM_HIP(hipEventRecord(js.ev_fix, s));
@@ -234,7 +261,7 @@ int64_t stage_finish(Ctx &C, Workspace &ws, JobState &js, const map_out *out, hi
                 copy_out(out->pair_p, (const int32_t *)tmp, cnt, out->mem_kind, s);
             }
             if (out->pair_c) {
-                EM_HIP(hipStreamSynchronize(s));
+                stream_sync(s);
                 hipLaunchKernelGGL(k_u32_to_i32, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, ps.pair_c, tmp,
                                    cnt);
                 copy_out(out->pair_c, (const int32_t *)tmp, cnt, out->mem_kind, s);
@@ -247,7 +274,7 @@ int64_t stage_finish(Ctx &C, Workspace &ws, JobState &js, const map_out *out, hi
     EM_HIP(hipMemcpyAsync(hred, red, sizeof(hred), hipMemcpyDeviceToHost, s));
     EM_HIP(hipMemcpyAsync(hcnt, js.counters, sizeof(hcnt), hipMemcpyDeviceToHost, s));
     EM_HIP(hipMemcpyAsync(&hf, js.flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
-    EM_HIP(hipStreamSynchronize(s));
+    stream_sync(s);
     EM_CHECK(hf == 0, flag_code(hf), flag_text(hf));
     if (st) {
         std::memset(st, 0, sizeof(*st));
@@ -255,6 +282,7 @@ int64_t stage_finish(Ctx &C, Workspace &ws, JobState &js, const map_out *out, hi
         st->n_candidates = hcnt[C_CANDIDATES];
         st->n_edge_terms = hcnt[C_EDGE_TERMS];
         st->n_fixup_terms = n_fix;
+        st->n_boundary_pairs = hcnt[C_WINDING];
         st->n_face_visits = hcnt[C_FACES];
         st->n_edge_visits = hcnt[C_EDGES];
         st->n_moment_evals = hcnt[C_MOMENTS];
@@ -338,10 +366,32 @@ void run_mapping(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cel
 
 }  // namespace em
 
-// The served path (em_serve.cpp) stays off until the stall seen in its first
-// device run is explained; its host logic is exercised on the CPU against a
-// fake device (tests/serve_host).
-bool em::serving_enabled() { return false; }
+// The served path (em_serve.cpp) is part of this build; the fake device of
+// the serving tests replaces this with its own switch.
+bool em::serving_enabled() { return true; }
+
+// Message of the last failed map_init on this thread (map_last_error(NULL)).
+static thread_local std::string g_init_err;
+
+// Distinct files of the HIP runtime (libamdhip64) mapped into this process.
+// Two runtimes in one process each keep their own device state, and device
+// pointers, streams and events of one are not valid in the other.
+static std::vector<std::string> hip_runtimes_mapped()
+{
+    std::vector<std::string> out;
+    FILE *fh = std::fopen("/proc/self/maps", "r");
+    if (!fh) return out;
+    char line[4096];
+    while (std::fgets(line, sizeof(line), fh)) {
+        const char *path = std::strchr(line, '/');
+        if (!path || !std::strstr(path, "libamdhip64")) continue;
+        std::string p(path);
+        while (!p.empty() && (p.back() == '\n' || p.back() == ' ')) p.pop_back();
+        if (std::find(out.begin(), out.end(), p) == out.end()) out.push_back(p);
+    }
+    std::fclose(fh);
+    return out;
+}
 
 // ---------------------------------------------------------------- C ABI
 #define API_BODY(ctx, body)                          \
@@ -369,8 +419,17 @@ extern "C" {
 
 int map_init(const map_config *cfg, map_ctx **out)
 {
+    g_init_err.clear();
     if (!out) return MAP_EINVAL;
     *out = nullptr;
+    {
+        const std::vector<std::string> rt = hip_runtimes_mapped();
+        if (rt.size() > 1) {
+            g_init_err = "two HIP runtimes are loaded in this process (" + rt[0] + ", " + rt[1] +
+                         "); load the one the library should use first (e.g. import torch before the library)";
+            return MAP_EDEVICE;
+        }
+    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
         (void)hipGetLastError();
@@ -394,14 +453,18 @@ int map_shutdown(map_ctx *h)
 {
     if (!h) return MAP_EINVAL;
     Ctx *C = reinterpret_cast<Ctx *>(h);
-    serve_stop(*C);
+    if (serve_stop(*C) != MAP_OK) {
+        // the serving loop failed or is stuck: its device work may still be
+        // pending, so the context stays allocated (released at process exit)
+        return MAP_EDEVICE;
+    }
     delete C;
     return MAP_OK;
 }
 
 const char *map_last_error(map_ctx *h)
 {
-    if (!h) return "null context";
+    if (!h) return g_init_err.c_str();
     return reinterpret_cast<Ctx *>(h)->err.c_str();
 }
 

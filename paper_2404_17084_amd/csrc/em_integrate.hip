@@ -31,6 +31,7 @@
 #include <cmath>
 
 #include "em_internal.h"
+#include "em_boundary.h"
 #include "em_fmath.h"
 #include "em_wave.h"
 
@@ -353,6 +354,7 @@ __device__ __forceinline__ double pair_fraction(double px, double py, double pz,
     using R = typename std::conditional<PREC == MAP_FP64, double, float>::type;
     const double invh = 1.0 / h;
     bool inside = true;
+    int n_on = 0;
     double acc = 0.0;
     const int64_t f0 = cfo[cell], f1 = cfo[cell + 1];
     for (int64_t j = f0; j < f1; j++) {
@@ -361,6 +363,7 @@ __device__ __forceinline__ double pair_fraction(double px, double py, double pz,
         wk.faces++;
         const bool in_j = d >= 0.0;
         inside = inside && in_j;
+        n_on += d == 0.0 ? 1 : 0;
         const double r0d = fabs(d) * invh;
         if (!(r0d < 2.0)) continue;
         const R r0 = (R)r0d;
@@ -387,7 +390,7 @@ __device__ __forceinline__ double pair_fraction(double px, double py, double pz,
         }
         acc += in_j ? face : -face;
     }
-    return (inside ? 1.0 : 0.0) - acc * kInvPi;
+    return winding_term(inside, n_on, px, py, pz, cell, cfo, fvo, plane, edges) - acc * kInvPi;
 }
 
 // FP64 contribution of one edge to f (the fixup pass): the same terms as one
@@ -433,6 +436,14 @@ struct FixList {
     uint64_t *items;
     unsigned cap;
 };
+
+// Appends the fixup item (pair k, slot) when the list has room; the count
+// keeps growing past the capacity, which tells the host that items were lost.
+__device__ __forceinline__ void push_fix(const FixList &fx, int64_t k, uint32_t slot)
+{
+    const unsigned i = atomicAdd(fx.count, 1u);
+    if (i < fx.cap) fx.items[i] = ((uint64_t)k << 32) | (uint64_t)slot;
+}
 
 template <int PREC>
 __device__ __forceinline__ double one_pair(int64_t k, const uint32_t *__restrict__ pair_p,
@@ -783,38 +794,63 @@ __device__ __forceinline__ void mixed_edge_step(WaveStacks &W, int lane, Work &w
     }
 }
 
-template <int WPE>
-__global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const uint32_t *__restrict__ pair_p,
-                                                           const uint32_t *__restrict__ pair_c,
-                                                           const double *__restrict__ xyz,
-                                                           const double *__restrict__ h,
-                                                           const int64_t *__restrict__ cfo,
-                                                           const int64_t *__restrict__ fvo,
-                                                           const double *__restrict__ plane,
-                                                           const EdgeRec *__restrict__ edges,
-                                                           double *__restrict__ f, unsigned long long *counters,
-                                                           unsigned *tile_ctr, FixList fx)
+// The job of global tile t of a launch of several jobs (wave-uniform): the
+// last job whose first tile is at or before t.
+__device__ __forceinline__ int job_of_tile(const JobsArg &A, int64_t t)
+{
+    int lo = 0, hi = A.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (A.table[mid].tile_base <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Field of the current job: the kernel argument itself for a one-job launch
+// (kept in scalar registers as plain arguments would be), the device table
+// entry otherwise.
+#define JOB(field) (MULTI ? A.table[jj].field : A.one.field)
+
+// Marker slot of a fixup item that asks for the winding weight of a pair whose
+// particle lies on two or more of its cell's wall planes (an edge or a vertex
+// of the cell; see em_boundary.h).
+constexpr uint32_t kWindingSlot = 0xffffffffu;
+
+template <int WPE, bool MULTI>
+__global__ void __launch_bounds__(256, WPE) k_integrate_queued(JobsArg A, unsigned *tile_ctr)
 {
     __shared__ WaveStacks stacks[4];
     const int lane = threadIdx.x & 63;
     WaveStacks &W = stacks[threadIdx.x >> 6];
-    const int64_t ntiles = (np + 63) / 64;
     int probe = 0;
+    int cur = MULTI ? -1 : 0;
     Work wk;
     for (;;) {
-        const int64_t t = next_tile_xcd(tile_ctr + 16, ntiles, probe, lane);
+        const int64_t t = next_tile_xcd(tile_ctr + 16, A.n_tiles, probe, lane);
         if (t < 0) break;
-        const int64_t k = t * 64 + lane;
-        const bool active = k < np;
+        const int jj = MULTI ? job_of_tile(A, t) : 0;
+        if (MULTI && jj != cur) {
+            if (cur >= 0) flush_work(wk, A.table[cur].counters);
+            wk = Work();
+            cur = jj;
+        }
+        const FixList fx = {JOB(fix_count), JOB(fix_items), JOB(fix_cap)};
+        const EdgeRec *__restrict__ edges = JOB(edges);
+        const double *__restrict__ plane = JOB(plane);
+        const int64_t *__restrict__ fvo = JOB(fvo);
+        const int64_t k = (t - JOB(tile_base)) * 64 + lane;
+        const bool active = k < JOB(np);
         double px = 0.0, py = 0.0, pz = 0.0, invh = 1.0;
         int32_t s = 0, s_end = 0, j = 0;
         if (active) {
-            const int64_t a = pair_p[k];
-            const int64_t c = pair_c[k];
-            px = xyz[3 * a];
-            py = xyz[3 * a + 1];
-            pz = xyz[3 * a + 2];
-            invh = 1.0 / h[a];
+            const int64_t a = JOB(pair_p)[k];
+            const int64_t c = JOB(pair_c)[k];
+            px = JOB(xyz)[3 * a];
+            py = JOB(xyz)[3 * a + 1];
+            pz = JOB(xyz)[3 * a + 2];
+            invh = 1.0 / JOB(h)[a];
+            const int64_t *__restrict__ cfo = JOB(cfo);
             j = (int32_t)cfo[c] - 1;
             s = (int32_t)fvo[cfo[c]];
             s_end = (int32_t)fvo[cfo[c + 1]];
@@ -825,6 +861,7 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
         int nA = 0, nP = 0, nQ = 0;
         double acc_in = 0.0;  // this lane's terms taken in place (not as tasks)
         bool inside = true;
+        int n_on = 0;  // walls whose plane holds the particle
         bool face_ok = false;
         double r0d = 0.0;
         float r0 = 0.0f, Ht = 0.0f, dH = 0.0f, fsign = 1.0f;
@@ -837,6 +874,7 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
                 wk.faces++;
                 const bool in_j = d >= 0.0;
                 inside = inside && in_j;
+                n_on += d == 0.0 ? 1 : 0;
                 fsign = in_j ? 1.0f : -1.0f;
                 r0d = fabs(d) * invh;
                 face_ok = r0d < 2.0;
@@ -851,10 +889,13 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(int64_t np, const
         run_stack<1>(W, nP, lane, true, wk);
         run_stack<2>(W, nQ, lane, true, wk);
         lds_sync_wave();
-        if (active) f[k] = (inside ? 1.0 : 0.0) - (W.acc[lane] + acc_in) * kInvPi;
+        if (active) {
+            JOB(f)[k] = (inside ? 1.0 : 0.0) - (W.acc[lane] + acc_in) * kInvPi;
+            if (inside && n_on >= 2) push_fix(fx, k, kWindingSlot);
+        }
         lds_sync_wave();
     }
-    flush_work(wk, counters);
+    if (cur >= 0) flush_work(wk, MULTI ? A.table[cur].counters : A.one.counters);
 }
 
 // FP64 form of the task batches: no quadrature (the shell piece keeps its
@@ -900,37 +941,39 @@ __device__ __forceinline__ void run_stack64(WaveStacks64 &W, int &count, int lan
     }
 }
 
-__global__ void __launch_bounds__(256, 2) k_integrate_queued64(int64_t np, const uint32_t *__restrict__ pair_p,
-                                                           const uint32_t *__restrict__ pair_c,
-                                                           const double *__restrict__ xyz,
-                                                           const double *__restrict__ h,
-                                                           const int64_t *__restrict__ cfo,
-                                                           const int64_t *__restrict__ fvo,
-                                                           const double *__restrict__ plane,
-                                                           const EdgeRec *__restrict__ edges,
-                                                           double *__restrict__ f, unsigned long long *counters,
-                                                           unsigned *tile_ctr)
+template <bool MULTI>
+__global__ void __launch_bounds__(256, 2) k_integrate_queued64(JobsArg A, unsigned *tile_ctr)
 {
     __shared__ WaveStacks64 stacks[4];
     const int lane = threadIdx.x & 63;
     WaveStacks64 &W = stacks[threadIdx.x >> 6];
-    const int64_t ntiles = (np + 63) / 64;
     int probe = 0;
+    int cur = MULTI ? -1 : 0;
     Work wk;
     for (;;) {
-        const int64_t t = next_tile_xcd(tile_ctr + 16, ntiles, probe, lane);
+        const int64_t t = next_tile_xcd(tile_ctr + 16, A.n_tiles, probe, lane);
         if (t < 0) break;
-        const int64_t k = t * 64 + lane;
-        const bool active = k < np;
+        const int jj = MULTI ? job_of_tile(A, t) : 0;
+        if (MULTI && jj != cur) {
+            if (cur >= 0) flush_work(wk, A.table[cur].counters);
+            wk = Work();
+            cur = jj;
+        }
+        const EdgeRec *__restrict__ edges = JOB(edges);
+        const double *__restrict__ plane = JOB(plane);
+        const int64_t *__restrict__ fvo = JOB(fvo);
+        const int64_t k = (t - JOB(tile_base)) * 64 + lane;
+        const bool active = k < JOB(np);
         double px = 0.0, py = 0.0, pz = 0.0, invh = 1.0;
         int64_t s = 0, s_end = 0, j = 0;
         if (active) {
-            const int64_t a = pair_p[k];
-            const int64_t c = pair_c[k];
-            px = xyz[3 * a];
-            py = xyz[3 * a + 1];
-            pz = xyz[3 * a + 2];
-            invh = 1.0 / h[a];
+            const int64_t a = JOB(pair_p)[k];
+            const int64_t c = JOB(pair_c)[k];
+            px = JOB(xyz)[3 * a];
+            py = JOB(xyz)[3 * a + 1];
+            pz = JOB(xyz)[3 * a + 2];
+            invh = 1.0 / JOB(h)[a];
+            const int64_t *__restrict__ cfo = JOB(cfo);
             j = cfo[c] - 1;
             s = fvo[cfo[c]];
             s_end = fvo[cfo[c + 1]];
@@ -940,6 +983,7 @@ __global__ void __launch_bounds__(256, 2) k_integrate_queued64(int64_t np, const
         const int n_steps = wave_max((int)(s_end - s));
         int nA = 0, nP = 0;
         bool inside = true;
+        int n_on = 0;  // walls whose plane holds the particle
         bool face_ok = false;
         double r0 = 0.0, Ht = 0.0, dH = 0.0, fsign = 1.0;
         for (int it = 0; it < n_steps; it++, s++) {
@@ -951,6 +995,7 @@ __global__ void __launch_bounds__(256, 2) k_integrate_queued64(int64_t np, const
                 wk.faces++;
                 const bool in_j = d >= 0.0;
                 inside = inside && in_j;
+                n_on += d == 0.0 ? 1 : 0;
                 fsign = in_j ? 1.0 : -1.0;
                 r0 = fabs(d) * invh;
                 face_ok = r0 < 2.0;
@@ -1073,11 +1118,15 @@ __global__ void __launch_bounds__(256, 2) k_integrate_queued64(int64_t np, const
         run_stack64<0>(W, nA, lane, true, wk);
         run_stack64<1>(W, nP, lane, true, wk);
         lds_sync_wave();
-        if (active) f[k] = (inside ? 1.0 : 0.0) - W.acc[lane] * kInvPi;
+        if (active) {
+            JOB(f)[k] = (inside ? 1.0 : 0.0) - W.acc[lane] * kInvPi;
+            if (inside && n_on >= 2) push_fix(FixList{JOB(fix_count), JOB(fix_items), JOB(fix_cap)}, k, kWindingSlot);
+        }
         lds_sync_wave();
     }
-    flush_work(wk, counters);
+    if (cur >= 0) flush_work(wk, MULTI ? A.table[cur].counters : A.one.counters);
 }
+#undef JOB
 
 // ---------------------------------------------------------------- cell tiles
 // A tile is up to 64 consecutive pairs of one cell (key = cell << 32 | tile
@@ -1133,6 +1182,7 @@ __global__ void __launch_bounds__(256) k_integrate_tiles(int64_t n_tiles, const 
         }
         const double invh = 1.0 / hh;
         bool inside = true;
+        int n_on = 0;
         double acc = 0.0;
         const int64_t f0 = uniform64(cfo[cell]), f1 = uniform64(cfo[cell + 1]);
         for (int64_t j = f0; j < f1; j++) {
@@ -1141,6 +1191,7 @@ __global__ void __launch_bounds__(256) k_integrate_tiles(int64_t n_tiles, const 
             wk.faces += active;
             const bool in_j = d >= 0.0;
             inside = inside && in_j;
+            n_on += d == 0.0 ? 1 : 0;
             const double r0d = fabs(d) * invh;
             const int64_t s0 = uniform64(fvo[j]), s1 = uniform64(fvo[j + 1]);
             if (active && r0d < 2.0) {
@@ -1168,40 +1219,9 @@ __global__ void __launch_bounds__(256) k_integrate_tiles(int64_t n_tiles, const 
                 acc += in_j ? face : -face;
             }
         }
-        if (active) f[k] = (inside ? 1.0 : 0.0) - acc * kInvPi;
+        if (active) f[k] = winding_term(inside, n_on, px, py, pz, cell, cfo, fvo, plane, edges) - acc * kInvPi;
     }
     flush_work(wk, counters);
-}
-
-// ---------------------------------------------------------------- batched (served) integration
-// One persistent launch integrates the pairs of several jobs: the global tile
-// space (64 pairs per tile) is the concatenation of the jobs' tiles, and a
-// wavefront maps its tile to the job through the table of tile bases.  Each
-// pair is computed by the same code whatever the batch holds, so a job's
-// results do not depend on the jobs it is batched with.
-template <int PREC>
-__global__ void __launch_bounds__(256) k_integrate_batch(int n_jobs, int64_t n_tiles, const BatchJob *__restrict__ jobs,
-                                                          unsigned *tile_ctr)
-{
-    const int lane = threadIdx.x & 63;
-    for (;;) {
-        unsigned t = 0;
-        if (lane == 0) t = atomicAdd(tile_ctr, 1u);
-        t = __builtin_amdgcn_readfirstlane(t);
-        if ((int64_t)t >= n_tiles) break;
-        int j = 0;
-        while (j + 1 < n_jobs && jobs[j + 1].tile_base <= (int64_t)t) j++;
-        const BatchJob &J = jobs[j];
-        const int64_t k = ((int64_t)t - J.tile_base) * 64 + lane;
-        Work wk;
-        if (k < J.np) {
-            const int64_t a = J.pair_p[k];
-            const int64_t c = J.pair_c[k];
-            J.f[k] = pair_fraction<PREC>(J.xyz[3 * a], J.xyz[3 * a + 1], J.xyz[3 * a + 2], J.h[a], c, J.cfo, J.fvo,
-                                         J.plane, J.edges, wk, (uint64_t)k, J.fix_count, J.fix_items, J.fix_cap);
-        }
-        flush_work(wk, J.counters);
-    }
 }
 
 // FP64 values of flagged edges (fixup items, key = pair << 32 | face-vertex slot)
@@ -1209,7 +1229,8 @@ __global__ void k_fixup_values(int64_t n_fix, const uint64_t *__restrict__ keys,
                                const uint32_t *__restrict__ pair_c, const double *__restrict__ xyz,
                                const double *__restrict__ h, const int64_t *__restrict__ cfo,
                                const int64_t *__restrict__ fvo, const double *__restrict__ plane,
-                               const EdgeRec *__restrict__ edges, double *__restrict__ vals)
+                               const EdgeRec *__restrict__ edges, double *__restrict__ vals,
+                               unsigned long long *counters)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_fix) return;
@@ -1217,6 +1238,12 @@ __global__ void k_fixup_values(int64_t n_fix, const uint64_t *__restrict__ keys,
     const int64_t k = (int64_t)(key >> 32);
     const int64_t s = (int64_t)(key & 0xffffffffu);
     const int64_t a = pair_p[k], c = pair_c[k];
+    if ((uint32_t)s == kWindingSlot) {
+        // the kernel took the winding weight of the particle as 1
+        vals[i] = cell_winding(xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2], c, cfo, fvo, plane, edges) - 1.0;
+        atomicAdd(counters + C_WINDING, 1ull);
+        return;
+    }
     // the face of slot s within the cell
     int64_t lo = cfo[c], hi = cfo[c + 1] - 1;
     while (lo < hi) {
@@ -1292,13 +1319,58 @@ void build_tiles(Workspace &ws, const DevInputs &in, PairSet &ps, hipStream_t s)
     scan_counts(ws, tcnt, toff, nc, s);
     int64_t nt = 0;
     EM_HIP(hipMemcpyAsync(&nt, toff + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    EM_HIP(hipStreamSynchronize(s));
+    stream_sync(s);
     uint64_t *tiles = ws.get<uint64_t>(S_TILES, (size_t)(nt > 0 ? nt : 1));
     hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, nc, (const int64_t *)toff,
                        tiles);
     EM_HIP(hipGetLastError());
     ps.tiles = tiles;
     ps.n_tiles = nt;
+}
+
+// The task-batch kernels (distribution 3) over one job (its entry passed by
+// value) or several (the table in device memory, h_jobs its host copy): the
+// tile space of a launch is the concatenation of the jobs' tiles of 64 pairs.
+static void launch_queued(const IntJob *h_jobs, const IntJob *d_jobs, int n_jobs, int precision,
+                          const IntegrateTune &tune, unsigned *tile_ctr, bool zero_ctr, hipStream_t s)
+{
+    EM_CHECK(n_jobs >= 1 && h_jobs, MAP_EINVAL, "integration launch without jobs");
+    EM_CHECK(n_jobs == 1 || d_jobs, MAP_EINVAL, "integration launch of several jobs without a device table");
+    int64_t tiles = 0;
+    for (int i = 0; i < n_jobs; i++) {
+        EM_CHECK(h_jobs[i].tile_base == tiles && h_jobs[i].np > 0, MAP_EINVAL,
+                 "integration job table: tile bases are not the running tile count");
+        tiles += (h_jobs[i].np + 63) / 64;
+    }
+    JobsArg A;
+    A.table = d_jobs;
+    A.n = n_jobs;
+    A.n_tiles = tiles;
+    A.one = h_jobs[0];
+    // [16..23] per-XCD tile counters
+    if (zero_ctr) fill_zero_bytes(tile_ctr, 24 * sizeof(unsigned), s);
+    const int block = 256;
+    int64_t g = (int64_t)device_cu_count() * (tune.grid_per_cu > 0 ? tune.grid_per_cu : 8);
+    const int64_t need = (tiles + (block / 64) - 1) / (block / 64);
+    if (g > need) g = need;
+    if (g < 1) g = 1;
+    const bool multi = n_jobs > 1;
+#define EM_LAUNCH_Q(...) hipLaunchKernelGGL((__VA_ARGS__), dim3((unsigned)g), dim3(block), 0, s, A, tile_ctr)
+    if (precision == MAP_FP64) {
+        if (multi) EM_LAUNCH_Q(k_integrate_queued64<true>);
+        else EM_LAUNCH_Q(k_integrate_queued64<false>);
+    } else if (tune.waves >= 6 || tune.waves <= 0) {
+        if (multi) EM_LAUNCH_Q(k_integrate_queued<6, true>);
+        else EM_LAUNCH_Q(k_integrate_queued<6, false>);
+    } else if (tune.waves >= 3) {
+        if (multi) EM_LAUNCH_Q(k_integrate_queued<3, true>);
+        else EM_LAUNCH_Q(k_integrate_queued<3, false>);
+    } else {
+        if (multi) EM_LAUNCH_Q(k_integrate_queued<2, true>);
+        else EM_LAUNCH_Q(k_integrate_queued<2, false>);
+    }
+#undef EM_LAUNCH_Q
+    EM_HIP(hipGetLastError());
 }
 
 void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, int precision,
@@ -1326,31 +1398,24 @@ void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &
         EM_HIP(hipGetLastError());
         return;
     }
-    if (tune.persistent == 3 && precision == MAP_FP64) {
-        int64_t g = (int64_t)device_cu_count() * (tune.grid_per_cu > 0 ? tune.grid_per_cu : 8);
-        const int64_t need = ((np + 63) / 64 + (block / 64) - 1) / (block / 64);
-        if (g > need) g = need;
-        if (g < 1) g = 1;
-        hipLaunchKernelGGL(k_integrate_queued64, dim3((unsigned)g), dim3(block), 0, s, np, ps.pair_p, ps.pair_c,
-                           in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, tile_ctr);
-        EM_HIP(hipGetLastError());
-        return;
-    }
-    if (tune.persistent == 3 && precision == MAP_MIXED) {
-        int64_t g = (int64_t)device_cu_count() * (tune.grid_per_cu > 0 ? tune.grid_per_cu : 8);
-        const int64_t need = ((np + 63) / 64 + (block / 64) - 1) / (block / 64);
-        if (g > need) g = need;
-        if (g < 1) g = 1;
-        if (tune.waves >= 6)
-            hipLaunchKernelGGL(k_integrate_queued<6>, dim3((unsigned)g), dim3(block), 0, s, np, ps.pair_p, ps.pair_c,
-                               in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, tile_ctr, fx);
-        else if (tune.waves >= 3)
-            hipLaunchKernelGGL(k_integrate_queued<3>, dim3((unsigned)g), dim3(block), 0, s, np, ps.pair_p, ps.pair_c,
-                               in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, tile_ctr, fx);
-        else
-            hipLaunchKernelGGL(k_integrate_queued<2>, dim3((unsigned)g), dim3(block), 0, s, np, ps.pair_p, ps.pair_c,
-                               in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f, cnt, tile_ctr, fx);
-        EM_HIP(hipGetLastError());
+    if (tune.persistent == 3) {
+        IntJob J;
+        J.np = np;
+        J.tile_base = 0;
+        J.pair_p = ps.pair_p;
+        J.pair_c = ps.pair_c;
+        J.xyz = in.xyz;
+        J.h = in.h;
+        J.cfo = in.cfo;
+        J.fvo = in.fvo;
+        J.plane = in.plane;
+        J.edges = edges;
+        J.f = f;
+        J.counters = cnt;
+        J.fix_count = fx.count;
+        J.fix_items = fx.items;
+        J.fix_cap = fx.cap;
+        launch_queued(&J, nullptr, 1, precision, tune, tile_ctr, false, s);
         return;
     }
     if (tune.persistent == 2 && ps.tiles) {
@@ -1392,31 +1457,19 @@ void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &
     EM_HIP(hipGetLastError());
 }
 
-void launch_integrate_batch(const BatchJob *d_jobs, int n_jobs, int64_t n_tiles, int precision, unsigned *tile_ctr,
-                            hipStream_t s)
+void launch_integrate_jobs(const IntJob *h_jobs, const IntJob *d_jobs, int n_jobs, int precision,
+                           const IntegrateTune &tune, unsigned *tile_ctr, hipStream_t s)
 {
-    if (n_tiles <= 0) return;
-    fill_zero_bytes(tile_ctr, sizeof(unsigned), s);
-    const int block = 256;
-    int64_t g = (int64_t)device_cu_count() * 8;
-    int64_t need = (n_tiles + 3) / 4;
-    if (g > need) g = need;
-    if (g < 1) g = 1;
-    if (precision == MAP_FP64)
-        hipLaunchKernelGGL(k_integrate_batch<MAP_FP64>, dim3((unsigned)g), dim3(block), 0, s, n_jobs, n_tiles, d_jobs,
-                           tile_ctr);
-    else
-        hipLaunchKernelGGL(k_integrate_batch<MAP_MIXED>, dim3((unsigned)g), dim3(block), 0, s, n_jobs, n_tiles, d_jobs,
-                           tile_ctr);
-    EM_HIP(hipGetLastError());
+    launch_queued(h_jobs, d_jobs, n_jobs, precision, tune, tile_ctr, true, s);
 }
 
 void launch_fixup(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, const uint64_t *fix_keys,
-                  int64_t n_fix, double *fix_vals, hipStream_t s)
+                  int64_t n_fix, double *fix_vals, int64_t *counters, hipStream_t s)
 {
     if (n_fix <= 0) return;
     hipLaunchKernelGGL(k_fixup_values, dim3((unsigned)((n_fix + 255) / 256)), dim3(256), 0, s, n_fix, fix_keys,
-                       ps.pair_p, ps.pair_c, in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, fix_vals);
+                       ps.pair_p, ps.pair_c, in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, fix_vals,
+                       reinterpret_cast<unsigned long long *>(counters));
     EM_HIP(hipGetLastError());
 }
 

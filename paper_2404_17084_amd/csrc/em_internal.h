@@ -116,7 +116,8 @@ enum : int {
     C_QUADS = 6,
     C_ANGLES = 7,
     C_QPOINTS = 8,
-    C_NUM = 9
+    C_WINDING = 9,  // pairs whose winding weight was recomputed (particle on two or more wall planes)
+    C_NUM = 10
 };
 
 // Device-resident view of one job's inputs.
@@ -151,6 +152,13 @@ void radix_sort_u32(Workspace &ws, uint32_t *keys, uint32_t *vals, uint32_t *key
 void radix_sort_u64(Workspace &ws, uint64_t *keys, uint32_t *vals, uint64_t *keys2, uint32_t *vals2, int64_t n,
                     int bits, hipStream_t s);
 void fill_iota_u32(uint32_t *p, int64_t n, hipStream_t s);
+// Waits until the work queued on stream s has finished.  On a thread that set
+// a wait limit (set_wait_limit_ms > 0; the serving thread does) the wait polls
+// and throws MAP_EDEVICE with a message containing kWaitLimitText once the
+// limit has passed; otherwise it is hipStreamSynchronize.
+void stream_sync(hipStream_t s);
+void set_wait_limit_ms(double ms);
+constexpr const char *kWaitLimitText = "device work did not finish within the wait limit";
 void fill_zero_bytes(void *p, size_t bytes, hipStream_t s);
 int device_cu_count();
 
@@ -204,31 +212,49 @@ int64_t run_pseudo_adaptive(Workspace &ws, const DevParticles &p, const double b
                             const PseudoDest &dest, map_pseudo_stats *st, map_adapt_stats *ast, hipStream_t s,
                             hipEvent_t *ev);
 
-// One job of a batched integration launch (device-resident table entry).
-struct BatchJob {
-    int64_t np;
-    int64_t tile_base;  // first global tile of this job (64 pairs per tile)
-    const uint32_t *pair_p, *pair_c;
-    const double *xyz, *h;
-    const int64_t *cfo, *fvo;
-    const double *plane;
-    const EdgeRec *edges;
-    double *f;
-    unsigned long long *counters;
-    unsigned *fix_count;
-    uint64_t *fix_items;
-    unsigned fix_cap;
+// One job of an integration launch of the task-batch kernels: its pairs
+// (cell-major), inputs, geometry tables and outputs.  tile_base is the job's
+// first tile (64 pairs each) in the launch's tile space, the running sum of
+// the tiles of the jobs before it.
+struct IntJob {
+    int64_t np = 0;
+    int64_t tile_base = 0;
+    const uint32_t *pair_p = nullptr, *pair_c = nullptr;
+    const double *xyz = nullptr, *h = nullptr;
+    const int64_t *cfo = nullptr, *fvo = nullptr;
+    const double *plane = nullptr;
+    const EdgeRec *edges = nullptr;
+    double *f = nullptr;
+    unsigned long long *counters = nullptr;
+    unsigned *fix_count = nullptr;
+    uint64_t *fix_items = nullptr;
+    unsigned fix_cap = 0;
 };
-void launch_integrate_batch(const BatchJob *d_jobs, int n_jobs, int64_t n_tiles, int precision, unsigned *tile_ctr,
-                            hipStream_t s);
+// Kernel argument: one job by value (n = 1) or a device table of n jobs.
+struct JobsArg {
+    const IntJob *table;
+    int n;
+    int64_t n_tiles;
+    IntJob one;
+};
+// One persistent launch of the task-batch kernel (distribution 3) of
+// `precision` over n_jobs jobs: h_jobs is the host table (checked: tile bases
+// are the running tile counts), d_jobs its device copy (needed when
+// n_jobs > 1, read by the kernel).  tile_ctr: 24 counters of the launch,
+// zeroed here.  A pair's result does not depend on the other jobs.
+void launch_integrate_jobs(const IntJob *h_jobs, const IntJob *d_jobs, int n_jobs, int precision,
+                           const IntegrateTune &tune, unsigned *tile_ctr, hipStream_t s);
 
 // em_integrate.hip: raw f per pair (cell-major order).
 void build_tiles(Workspace &ws, const DevInputs &in, PairSet &ps, hipStream_t s);
 void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, int precision,
                       const IntegrateTune &tune, double *f, int64_t *counters, uint32_t *tile_ctr,
                       uint64_t *fix_items, int64_t fix_cap, hipStream_t s);
+// FP64 values of the fixup items: flagged edge terms, and the winding
+// correction of pairs whose particle lies on two or more wall planes of the
+// cell (counted in counters[C_WINDING]).
 void launch_fixup(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, const uint64_t *fix_items,
-                  int64_t n_fix, double *fix_vals, hipStream_t s);
+                  int64_t n_fix, double *fix_vals, int64_t *counters, hipStream_t s);
 // adds sorted fixup values into f
 void launch_fixup_apply(const uint64_t *keys, const double *vals, int64_t n_fix, double *f, hipStream_t s);
 

@@ -567,7 +567,7 @@ PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, cons
     EM_HIP(hipMemcpyAsync(&ncand, coffs + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     EM_HIP(hipMemcpyAsync(&n_need, noffs + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     EM_HIP(hipMemcpyAsync(&max_cand, cmax, sizeof(unsigned), hipMemcpyDeviceToHost, s));
-    EM_HIP(hipStreamSynchronize(s));
+    stream_sync(s);
     EM_CHECK(ncand < (int64_t)UINT32_MAX, MAP_ENOMEM, "candidate count exceeds 2^32-1");
     uint32_t *cand_c = ws.get<uint32_t>(S_KEY2, (size_t)(ncand > 0 ? ncand : 1));
     uint32_t *cand_p = ws.get<uint32_t>(S_IOTA, (size_t)(ncand > 0 ? ncand : 1));
@@ -605,7 +605,7 @@ PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, cons
     scan_counts(ws, pcount, coff, nc, s);
     int64_t np = 0;
     EM_HIP(hipMemcpyAsync(&np, coff + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    EM_HIP(hipStreamSynchronize(s));
+    stream_sync(s);
     EM_CHECK(np < (int64_t)UINT32_MAX, MAP_ENOMEM, "pair count exceeds 2^32-1");
     ps.n_pairs = np;
     if (np == 0) return ps;

@@ -1,5 +1,8 @@
 // Device primitives: device memory pool, exclusive scan of counts and a
 // stable LSD radix sort (keys with 32-bit values), all written for wave64.
+#include <chrono>
+#include <thread>
+
 #include "em_internal.h"
 
 namespace em {
@@ -45,6 +48,33 @@ void *Workspace::get(int slot, size_t bytes)
 }
 
 size_t Workspace::bytes_held() const { return held_.load(); }
+
+// ---------------------------------------------------------------- bounded stream waits
+static thread_local double t_wait_limit_ms = 0.0;
+
+void set_wait_limit_ms(double ms) { t_wait_limit_ms = ms > 0.0 ? ms : 0.0; }
+
+void stream_sync(hipStream_t s)
+{
+    if (t_wait_limit_ms <= 0.0) {
+        EM_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int spin = 0;; spin++) {
+        const hipError_t e = hipStreamQuery(s);
+        if (e == hipSuccess) return;
+        (void)hipGetLastError();  // a not-ready query is no error of the next call
+        if (e != hipErrorNotReady)
+            throw Error{MAP_EDEVICE, std::string("hipStreamQuery: ") + hipGetErrorString(e)};
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (ms > t_wait_limit_ms)
+            throw Error{MAP_EDEVICE, std::string(kWaitLimitText) + " (" + std::to_string((long long)t_wait_limit_ms) +
+                                         " ms)"};
+        if (spin < 200) std::this_thread::yield();
+        else std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
 
 int device_cu_count()
 {

@@ -83,7 +83,10 @@ void prepare(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_i
              double *&aabb, unsigned *&flags, int64_t *&counters, hipStream_t s);
 void run_mapping(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cells_in *c, const map_out *out,
                  int precision, hipStream_t s, bool timed);
-void serve_stop(Ctx &C);
+// Drains and stops the serving loop (bounded wait).  MAP_OK when it stopped
+// cleanly; MAP_EDEVICE when it had failed or did not stop: its device work may
+// still be pending, so the context must then be left in place (not freed).
+int serve_stop(Ctx &C);
 // Builds the context's MAP_TABLE table if its size changed or it was never built.
 void ensure_table(Ctx &C, hipStream_t s);
 // Device-memory footprint estimate of a served job (admission against the budget).

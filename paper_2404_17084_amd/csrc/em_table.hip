@@ -20,6 +20,7 @@
 // table stays in L2 (1 MiB at 64^3).
 #include <cmath>
 
+#include "em_boundary.h"
 #include "em_internal.h"
 #include "em_fmath.h"
 
@@ -96,6 +97,7 @@ __global__ void __launch_bounds__(256) k_integrate_table(int64_t np, const uint3
         const double px = xyz[3 * a], py = xyz[3 * a + 1], pz = xyz[3 * a + 2];
         const double invh = 1.0 / h[a];
         bool inside = true;
+        int n_on = 0;
         double acc = 0.0;
         for (int64_t j = cfo[cell]; j < cfo[cell + 1]; j++) {
             const double nx = plane[4 * j], ny = plane[4 * j + 1], nz = plane[4 * j + 2], cj = plane[4 * j + 3];
@@ -103,6 +105,7 @@ __global__ void __launch_bounds__(256) k_integrate_table(int64_t np, const uint3
             n_faces++;
             const bool in_j = d >= 0.0;
             inside = inside && in_j;
+            n_on += d == 0.0 ? 1 : 0;
             const double r0d = fabs(d) * invh;
             if (!(r0d < 2.0)) continue;
             const float r0 = (float)r0d;
@@ -122,7 +125,7 @@ __global__ void __launch_bounds__(256) k_integrate_table(int64_t np, const uint3
             }
             acc += in_j ? face : -face;
         }
-        f[q] = (inside ? 1.0 : 0.0) - acc;
+        f[q] = winding_term(inside, n_on, px, py, pz, cell, cfo, fvo, plane, edges) - acc;
     }
     for (int o = 32; o > 0; o >>= 1) {
         n_faces += __shfl_xor(n_faces, o, 64);

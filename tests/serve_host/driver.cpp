@@ -1,6 +1,7 @@
 // Scheduler scenarios of the serving loop on the fake device.  Each prints
 // "ok <name>" or "FAIL <name>: <what>" and the program exits non-zero on the
 // first failure.
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -83,8 +84,15 @@ static Ctx *context(int max_jobs, uint64_t budget = 0, int max_queue = 0)
 
 static void finish(Ctx *C)
 {
-    serve_stop(*C);
+    const int rc = serve_stop(*C);
+    CHECK(rc == MAP_OK, "serve_stop returned %d", rc);
     delete C;
+}
+
+static int threads_used()
+{
+    std::lock_guard<std::mutex> g(g_log.mu);
+    return (int)g_log.device_threads.size();
 }
 
 static int submit(Ctx *C, Job &j) { return map_submit(reinterpret_cast<map_ctx *>(C), &j.p, &j.c, &j.o, &j.id); }
@@ -93,6 +101,7 @@ static int poll(Ctx *C, Job &j, int64_t us, int *state) { return map_poll(reinte
 
 int main()
 {
+    std::setvbuf(stdout, nullptr, _IONBF, 0);  // keep every line if a sanitizer ends the run
     // jobs of one context all complete with the right outputs; slots bound concurrency
     {
         scenario = "complete";
@@ -108,6 +117,7 @@ int main()
             CHECK(j->st.ms_latency >= j->st.ms_queue && j->st.ms_queue >= 0.0, "latency");
         }
         CHECK(g_log.max_live <= 3, "max live %d", g_log.max_live);
+        CHECK(threads_used() == 1, "device calls from %d threads", threads_used());
         finish(C);
         std::printf("ok %s (max live %d, batches %d, largest batch %d)\n", scenario, g_log.max_live, g_log.batches,
                     g_log.max_batch);
@@ -219,6 +229,52 @@ int main()
             finish(C);
         }
         std::printf("ok %s\n", scenario);
+    }
+    // growing workspaces: hipFree waits for the whole device (also for a
+    // launch in flight) and is called from the scheduler thread only
+    {
+        scenario = "device-syncs";
+        Ctx *C = context(2);
+        std::vector<std::unique_ptr<Job>> js;
+        for (int t = 0; t < 8; t++) js.push_back(make(t, 200 + 400 * t));
+        for (auto &j : js) CHECK(submit(C, *j) == MAP_OK, "submit");
+        for (auto &j : js) {
+            int st = -1;
+            CHECK(poll(C, *j, 30000000, &st) == MAP_OK && st == MAP_JOB_DONE, "state %d", st);
+            CHECK(std::fabs(sum(j->M) - 1.0) < 1e-12, "mass");
+        }
+        CHECK(g_log.device_syncs > 0, "no workspace grew");
+        CHECK(threads_used() == 1, "device calls from %d threads", threads_used());
+        finish(C);
+        std::printf("ok %s (%d device-wide syncs)\n", scenario, g_log.device_syncs);
+    }
+    // a launch that never completes: the jobs in flight and later ones fail
+    // with MAP_EDEVICE within the time limit, polls and shutdown return
+    {
+        scenario = "watchdog";
+        map_config cfg{};
+        cfg.max_jobs = 2;
+        cfg.serve_timeout_ms = 300;
+        g_log.reset();
+        g_log.hang_n = 777;
+        Ctx *C = new Ctx(&cfg);
+        auto a = make(0, 300);
+        CHECK(submit(C, *a) == MAP_OK, "submit");
+        int st = -1;
+        CHECK(poll(C, *a, 30000000, &st) == MAP_OK && st == MAP_JOB_DONE, "first job state %d", st);
+        auto hung = make(1, 777);
+        auto b = make(2, 300);
+        CHECK(submit(C, *hung) == MAP_OK && submit(C, *b) == MAP_OK, "submit");
+        const auto t0 = std::chrono::steady_clock::now();
+        CHECK(poll(C, *hung, -1, &st) == MAP_EDEVICE && st == MAP_JOB_FAILED, "hung job state %d", st);
+        CHECK(poll(C, *b, -1, &st) == MAP_EDEVICE && st == MAP_JOB_FAILED, "later job state %d", st);
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        CHECK(ms < 5000, "failure took %.0f ms", ms);
+        auto c = make(3, 300);
+        CHECK(submit(C, *c) == MAP_EDEVICE, "a stopped server accepted a job");
+        CHECK(serve_stop(*C) == MAP_EDEVICE, "shutdown of a failed server reported success");
+        g_log.release_hang();  // the context is left allocated, as map_shutdown does
+        std::printf("ok %s (failed after %.0f ms)\n", scenario, ms);
     }
     std::printf("all scenarios passed\n");
     return 0;

@@ -1,6 +1,8 @@
 #pragma once
+#include <condition_variable>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 namespace em {
@@ -11,6 +13,11 @@ struct FakeLog {
     size_t bytes = 0, max_bytes = 0;
     int batches = 0, max_batch = 0;
     int stage_us = 200;
+    int device_syncs = 0;                      // hipFree / hipHostFree calls (each waits for the device)
+    std::vector<std::thread::id> device_threads;  // threads that ran stages or launches
+    int64_t hang_n = -1;                       // a job of this many particles hangs its launch
+    bool hang_released = false;
+    std::condition_variable hang_cv;
     std::map<const void *, size_t> footprint_of;  // job state -> footprint while in flight
     void reset()
     {
@@ -19,7 +26,13 @@ struct FakeLog {
         live = max_live = 0;
         bytes = max_bytes = 0;
         batches = max_batch = 0;
+        device_syncs = 0;
+        device_threads.clear();
+        hang_n = -1;
+        hang_released = false;
+        footprint_of.clear();
     }
+    void release_hang();
 };
 extern FakeLog g_log;
 }  // namespace em

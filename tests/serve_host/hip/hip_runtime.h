@@ -1,6 +1,9 @@
-// Host-only stand-in for the few HIP runtime calls the serving loop makes, so
-// that its scheduler can be compiled and driven on a CPU (fake device):
-// "device" memory is host memory, streams are tokens, copies are memcpy.
+// Host-only stand-in for the HIP runtime calls the serving loop makes, so that
+// its scheduler can be compiled and driven on a CPU (fake device).  "Device"
+// memory is host memory.  Streams are FIFO queues run in order by one fake
+// device thread (fake_device.cpp); events are markers in them.  hipFree and
+// hipHostFree wait until every queue is empty, as the real calls synchronise
+// the device.  Copies run at once on the calling thread.
 #pragma once
 #include <cstddef>
 #include <cstdlib>
@@ -9,21 +12,34 @@
 typedef int hipError_t;
 typedef struct ihipStream_t *hipStream_t;
 typedef struct ihipEvent_t *hipEvent_t;
-enum { hipSuccess = 0 };
+enum { hipSuccess = 0, hipErrorNotReady = 600, hipErrorOutOfMemory = 2 };
 enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice };
 #define hipStreamNonBlocking 1
+#define hipEventDisableTiming 2
+#define hipHostMallocDefault 0
 
 inline const char *hipGetErrorString(hipError_t) { return "fake device error"; }
 inline hipError_t hipSetDevice(int) { return hipSuccess; }
 inline hipError_t hipGetDevice(int *d) { *d = 0; return hipSuccess; }
 inline hipError_t hipMemGetInfo(size_t *f, size_t *t) { *f = size_t(1) << 34; *t = *f; return hipSuccess; }
-inline hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) { *s = (hipStream_t)std::malloc(8); return hipSuccess; }
-inline hipError_t hipStreamDestroy(hipStream_t s) { std::free(s); return hipSuccess; }
-inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+inline hipError_t hipGetLastError() { return hipSuccess; }
+
+hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned);
+hipError_t hipStreamDestroy(hipStream_t s);
+hipError_t hipStreamSynchronize(hipStream_t s);
+hipError_t hipStreamQuery(hipStream_t s);
+hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned);
+hipError_t hipEventDestroy(hipEvent_t e);
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t s);
+hipError_t hipEventQuery(hipEvent_t e);
+hipError_t hipFreeVoid(void *p);
+hipError_t hipHostFree(void *p);
+
 template <class T>
 inline hipError_t hipMalloc(T **p, size_t n) { *p = (T *)std::malloc(n ? n : 1); return *p ? hipSuccess : 2; }
-inline hipError_t hipFree(void *p) { std::free(p); return hipSuccess; }
-inline hipError_t hipGetLastError() { return hipSuccess; }
+template <class T>
+inline hipError_t hipHostMalloc(T **p, size_t n, unsigned) { *p = (T *)std::malloc(n ? n : 1); return *p ? hipSuccess : 2; }
+inline hipError_t hipFree(void *p) { return hipFreeVoid(p); }
 inline hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind) { std::memcpy(d, s, n); return hipSuccess; }
 inline hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind, hipStream_t)
 {

@@ -87,10 +87,15 @@ def test_pseudo_matches_oracle(mp, case):
     assert abs(G["m"].sum() - p.m.sum()) <= 1e-12
 
 
-def test_pseudo_full_size_lognormal(mp):
+@pytest.fixture(scope="module")
+def lognormal2m():
+    return synth.particles(*synth.LOGNORMAL_2M)
+
+
+def test_pseudo_full_size_lognormal(mp, lognormal2m):
     """2,097,152 particles of the log-normal cloud, one source at the centre, theta 0.5."""
     say("case: pseudo lognormal 2097152 (full size)")
-    p = synth.particles(*synth.LOGNORMAL_2M)
+    p = lognormal2m
     src = [[0.5, 0.5, 0.5]]
     G = mp.pseudo(p, BOX, src, theta=0.5, r_part=0.05, r_leaf=0.1, leaf_size=8)
     O = oracle.pseudo(p.xyz, p.m, p.h, BOX, src, 0.5, 0.05, 0.1, 8, 1.1)
@@ -207,3 +212,26 @@ def test_pseudo_then_mapping(mp):
     O = oracle.map_particles(q, cells)
     assert np.max(np.abs(r["M"] - O["M"]) / O["M"]) < 1e-10
     assert abs(r["M"].sum() - 1.0) < 1e-12
+
+
+def test_pseudo_set_mixed_mapping_full_lognormal(mp, lognormal2m):
+    """The 2,097,152-particle log-normal cloud's pseudo set (one source at the centre, theta 0.5,
+    r_part 0.05, r_leaf 0.1) mapped in mixed precision onto its Voronoi cells, every cell against
+    the oracle's mapping of all its pairs (Sec. III feeding Sec. II-B)."""
+    say("case: full log-normal pseudo set, mixed mapping vs oracle")
+    p = lognormal2m
+    G = mp.pseudo(p, BOX, [[0.5, 0.5, 0.5]], theta=0.5, r_part=0.05, r_leaf=0.1)
+    q = synth.Particles(np.ascontiguousarray(G["xyz"]), np.ascontiguousarray(G["m"]), np.ascontiguousarray(G["h"]))
+    cells = synth.voronoi_cells(q.xyz)
+    mp.set_precision(em.MAP_MIXED)
+    try:
+        r = mp.map(q, cells, want_pairs=True)
+    finally:
+        mp.set_precision(em.MAP_FP64)
+    O = oracle.map_particles(q, cells)
+    assert np.array_equal(r["pair_p"], O["pair_p"]) and np.array_equal(r["pair_c"], O["pair_c"])
+    rel = np.abs(r["M"] - O["M"]) / O["M"]
+    say(f"  pseudo {q.n}, pairs {O['f'].size}, max cell rel {rel.max():.3e}, max pair |df| "
+        f"{np.abs(r['f'] - O['f']).max():.3e}, fixups {r['stats']['n_fixup_terms']}")
+    assert rel.max() < 1e-5
+    assert abs(r["M"].sum() - p.m.sum()) < 1e-9
