@@ -84,6 +84,10 @@ typedef struct map_config {
     int64_t fixup_cap;         /* MAP_MIXED: capacity of the list of edge terms recomputed in
                                   FP64 (0 = n_pairs / 8 + 65536); when more edges are flagged,
                                   every pair of the call is recomputed in FP64 instead */
+    double cell_tol;           /* MAP_MIXED: per-cell error budget.  Each pair carries an
+                                  estimate e_ai of the error of its FP32 terms; a cell with
+                                  sqrt(sum_a (m_a e_ai / S_a)^2) > cell_tol |M_i| has all its
+                                  pairs recomputed in FP64 (0 = 2e-6; negative = never) */
 } map_config;
 
 /* Particles: structure of arrays, FP64. */
@@ -124,6 +128,8 @@ typedef struct map_stats {
     int64_t n_quad_points;  /* Gauss-Legendre points of the shell quadrature (mixed path) */
     int64_t n_boundary_pairs; /* pairs whose particle lies on two or more wall planes of the cell
                                  (an edge or a vertex): winding weight recomputed in FP64 */
+    int64_t n_fp64_cells;   /* MAP_MIXED: cells over the error budget (cfg->cell_tol) */
+    int64_t n_fp64_pairs;   /* MAP_MIXED: their pairs, recomputed in FP64 */
     double mass_in;         /* sum of m_a */
     double mass_out;        /* sum of M_i */
     double max_abs_S_minus_1; /* over particles whose support lies inside box */

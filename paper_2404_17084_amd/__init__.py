@@ -44,7 +44,7 @@ c_i64, c_i32, c_int, c_dbl, c_vp, c_u64 = (ctypes.c_int64, ctypes.c_int32, ctype
 class map_config(ctypes.Structure):
     _fields_ = [("device", c_int), ("precision", c_int), ("hbm_budget_bytes", c_u64), ("max_jobs", c_int),
                 ("max_queue", c_int), ("tune_cache_path", ctypes.c_char_p), ("serve_timeout_ms", c_int),
-                ("serve_trace", c_int), ("fixup_cap", c_i64)]
+                ("serve_trace", c_int), ("fixup_cap", c_i64), ("cell_tol", c_dbl)]
 
 
 class map_particles_in(ctypes.Structure):
@@ -67,7 +67,7 @@ class map_stats(ctypes.Structure):
     _fields_ = [("n_pairs", c_i64), ("n_candidates", c_i64), ("n_edge_terms", c_i64), ("n_fixup_terms", c_i64),
                 ("n_face_visits", c_i64), ("n_edge_visits", c_i64), ("n_moment_evals", c_i64),
                 ("n_quad_intervals", c_i64), ("n_angle_evals", c_i64), ("n_quad_points", c_i64),
-                ("n_boundary_pairs", c_i64),
+                ("n_boundary_pairs", c_i64), ("n_fp64_cells", c_i64), ("n_fp64_pairs", c_i64),
                 ("mass_in", c_dbl), ("mass_out", c_dbl), ("max_abs_S_minus_1", c_dbl), ("ms_setup", c_dbl),
                 ("ms_pairs", c_dbl), ("ms_integrate", c_dbl), ("ms_fixup", c_dbl), ("ms_reduce", c_dbl),
                 ("ms_total", c_dbl), ("ms_queue", c_dbl), ("ms_latency", c_dbl)]
@@ -290,11 +290,11 @@ def cells_in(cells, device_arrays=None):
 # ---------------------------------------------------------------- ABI-named wrappers
 def map_init(device: int = 0, precision: int = MAP_FP64, hbm_budget_bytes: int = 0, max_jobs: int = 0,
              max_queue: int = 0, tune_cache_path: str | None = None, serve_timeout_ms: int = 0,
-             serve_trace: bool = False, fixup_cap: int = 0):
+             serve_trace: bool = False, fixup_cap: int = 0, cell_tol: float = 0.0):
     lib = load()
     cfg = map_config(device, precision, hbm_budget_bytes, max_jobs, max_queue,
                      tune_cache_path.encode() if tune_cache_path else None, int(serve_timeout_ms),
-                     1 if serve_trace else 0, int(fixup_cap))
+                     1 if serve_trace else 0, int(fixup_cap), float(cell_tol))
     ctx = c_vp()
     _check(None, lib.map_init(ctypes.byref(cfg), ctypes.byref(ctx)))
     return ctx

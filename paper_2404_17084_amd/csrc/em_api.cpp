@@ -176,6 +176,7 @@ void stage_pairs(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cel
     js.ps = build_pairs(ws, js.in, js.aabb, js.edges, js.counters, s);
     const int64_t np = js.ps.n_pairs;
     js.f = ws.get<double>(S_F, (size_t)(np > 0 ? np : 1));
+    js.err = precision == MAP_MIXED ? ws.get<float>(S_ERR, (size_t)(np > 0 ? np : 1)) : nullptr;
     js.tile_ctr = ws.get<uint32_t>(S_TILE_CTR, 64);
     js.fix_cap = C.config.fixup_cap > 0 ? C.config.fixup_cap : np / 8 + 65536;
     js.fix_items = ws.get<uint64_t>(S_FIX_ITEMS, (size_t)js.fix_cap);
@@ -209,18 +210,20 @@ int64_t stage_finish(Ctx &C, Workspace &ws, JobState &js, const map_out *out, hi
             if (js.precision == MAP_MIXED) {
                 // too many flagged edges for the list: every pair again in FP64
                 // (whose list then holds winding items only)
-                launch_integrate(in, js.edges, ps, MAP_FP64, t64, f, js.counters, js.tile_ctr, js.fix_items,
-                                 js.fix_cap, s);
+                launch_integrate(in, js.edges, ps, MAP_FP64, t64, f, nullptr, js.counters, js.tile_ctr,
+                                 js.fix_items, js.fix_cap, s);
                 n_items = read_count();
                 n_fix = np;
+                js.err = nullptr;  // FP64 values: nothing left to check
             }
             if (n_items > js.fix_cap) {
                 // more winding items than the list holds: a list that fits them, and the FP64 pass again
                 js.fix_cap = n_items;
                 js.fix_items = ws.get<uint64_t>(S_FIX_ITEMS, (size_t)n_items);
-                launch_integrate(in, js.edges, ps, MAP_FP64, t64, f, js.counters, js.tile_ctr, js.fix_items,
-                                 js.fix_cap, s);
+                launch_integrate(in, js.edges, ps, MAP_FP64, t64, f, nullptr, js.counters, js.tile_ctr,
+                                 js.fix_items, js.fix_cap, s);
                 n_items = read_count();
+                js.err = nullptr;
                 EM_CHECK(n_items <= js.fix_cap, MAP_EDEVICE, "fixup list overflow after resizing");
                 n_fix = np;
             }
@@ -244,6 +247,22 @@ int64_t stage_finish(Ctx &C, Workspace &ws, JobState &js, const map_out *out, hi
     double *red = ws.get<double>(S_RED, 16 + 4 * 256);
     EM_HIP(hipMemcpyAsync(red + 4, in.box, sizeof(double) * 6, hipMemcpyHostToDevice, s));
     launch_reduce(in, ps, f, S, M, rho, red, js.flags, s);
+    int64_t n_cells_fp64 = 0;
+    if (js.err && np > 0 && C.config.cell_tol >= 0.0) {
+        // cells whose estimated FP32 error exceeds the budget: their pairs again in FP64
+        const double tol = C.config.cell_tol > 0.0 ? C.config.cell_tol : kDefaultCellTol;
+        unsigned *cnt = reinterpret_cast<unsigned *>(ws.get<uint32_t>(S_CHECK, (size_t)in.n_cells + 64));
+        uint32_t *list = reinterpret_cast<uint32_t *>(cnt) + 64;
+        launch_cell_check(in, ps, js.err, S, M, tol, cnt, list, in.n_cells, s);
+        unsigned hc = 0;
+        EM_HIP(hipMemcpyAsync(&hc, cnt, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        stream_sync(s);
+        n_cells_fp64 = hc;
+        if (hc > 0) {
+            launch_recompute_cells(in, js.edges, ps, list, (int64_t)hc, f, js.counters, s);
+            launch_reduce(in, ps, f, S, M, rho, red, js.flags, s);
+        }
+    }
     if (js.ev_reduce) EM_HIP(hipEventRecord(js.ev_reduce, s));
 
     // outputs
@@ -283,6 +302,8 @@ int64_t stage_finish(Ctx &C, Workspace &ws, JobState &js, const map_out *out, hi
         st->n_edge_terms = hcnt[C_EDGE_TERMS];
         st->n_fixup_terms = n_fix;
         st->n_boundary_pairs = hcnt[C_WINDING];
+        st->n_fp64_cells = n_cells_fp64;
+        st->n_fp64_pairs = hcnt[C_FP64_PAIRS];
         st->n_face_visits = hcnt[C_FACES];
         st->n_edge_visits = hcnt[C_EDGES];
         st->n_moment_evals = hcnt[C_MOMENTS];
@@ -331,7 +352,7 @@ void run_mapping(Ctx &C, Workspace &ws, const map_particles_in *p, const map_cel
         const IntegrateTune tune = pick_tune(C, precision, js.ps.n_pairs);
         if (tune.persistent == 2) build_tiles(ws, js.in, js.ps, s);
         if (timed) EM_HIP(hipEventRecord(C.ev[2], s));
-        launch_integrate(js.in, js.edges, js.ps, precision, tune, js.f, js.counters, js.tile_ctr, js.fix_items,
+        launch_integrate(js.in, js.edges, js.ps, precision, tune, js.f, js.err, js.counters, js.tile_ctr, js.fix_items,
                          js.fix_cap, s);
     }
     if (timed) {

@@ -316,6 +316,16 @@ __device__ __forceinline__ R edge_term(R r0, R R0, R la, R lb, R Ht, R dH, Work 
 }
 
 constexpr double kInvPi = 0.318309886183790671537767526745;
+constexpr float kInvPiF = 0.318309886183790671537767526745f;
+
+// Error estimate of the FP32 terms of a pair in the mixed path: each term
+// (an angle times its weight, an inner-part closed form, a Gauss-Legendre
+// sub-interval) is taken to carry a relative error of up to 16 units of FP32
+// rounding (a few for the inputs rounded from FP64, up to 5 for each
+// transcendental, the rest for the arithmetic and the truncation of the
+// sub-interval rule), the errors of different terms adding like a random walk:
+// err = 16 * 2^-24 * sqrt(sum of squared terms) / pi, in units of f.
+constexpr float kTermErr = 16.0f * 5.9604644775390625e-08f;
 
 // Conditioning test of one edge in the mixed path: true for near-degenerate
 // triangles that FP32 cannot resolve: the projection point within FP32
@@ -349,7 +359,7 @@ __device__ __forceinline__ double pair_fraction(double px, double py, double pz,
                                                 const int64_t *__restrict__ cfo, const int64_t *__restrict__ fvo,
                                                 const double *__restrict__ plane, const EdgeRec *__restrict__ edges,
                                                 Work &wk, uint64_t pair_k, unsigned *fix_count, uint64_t *fix_items,
-                                                unsigned fix_cap)
+                                                unsigned fix_cap, float &ev)
 {
     using R = typename std::conditional<PREC == MAP_FP64, double, float>::type;
     const double invh = 1.0 / h;
@@ -387,6 +397,7 @@ __device__ __forceinline__ double pair_fraction(double px, double py, double pz,
             }
             const R t = edge_term<R>(r0, (R)R0d, (R)la, (R)lb, Ht, dH, wk);
             face += (rho > 0.0) ? (double)t : -(double)t;
+            if (PREC == MAP_MIXED) ev = fmaf((float)t, (float)t, ev);
         }
         acc += in_j ? face : -face;
     }
@@ -435,6 +446,7 @@ struct FixList {
     unsigned *count;
     uint64_t *items;
     unsigned cap;
+    float *err;  // mixed path: per-pair FP32 error estimates (or null)
 };
 
 // Appends the fixup item (pair k, slot) when the list has room; the count
@@ -454,8 +466,11 @@ __device__ __forceinline__ double one_pair(int64_t k, const uint32_t *__restrict
 {
     const int64_t a = pair_p[k];
     const int64_t c = pair_c[k];
-    return pair_fraction<PREC>(xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2], h[a], c, cfo, fvo, plane, edges, wk,
-                               (uint64_t)k, fx.count, fx.items, fx.cap);
+    float ev = 0.0f;
+    const double v = pair_fraction<PREC>(xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2], h[a], c, cfo, fvo, plane, edges,
+                                         wk, (uint64_t)k, fx.count, fx.items, fx.cap, ev);
+    if (PREC == MAP_MIXED && fx.err) fx.err[k] = kTermErr * kInvPiF * sqrt_f32(ev);
+    return v;
 }
 
 template <int PREC>
@@ -549,10 +564,11 @@ constexpr int kQ = 128;  // stack capacity: below 64 pending before a push of at
 constexpr int kQA = 64;  // angle stack capacity: run before a push that would overflow it
 struct WaveStacks {
     float ang[3][kQA];  // atan2 arguments of the angle (imaginary, real part), weight
-    float pnt[4][kQ];   // r0, R0, x (negated when S = 1), weight (c^2, c and S are recomputed)
-    float qd[5][kQ];    // r0, c2, mid, half-length, weight
+    float pnt[4][kQ];   // inner parts: r0, signed R0 (sign = the term's sign), start a, length L
+    float qd[4][kQ];    // shell sub-intervals: r0, signed R0, mid, half-length
     uint8_t ang_o[kQA], pnt_o[kQ], qd_o[kQ];  // owner lanes
     double acc[64];
+    float ev[64];  // sums of the squared FP32 task values per owner (error estimate)
 };
 
 __device__ __forceinline__ void run_angle(WaveStacks &W, int i, Work &wk)
@@ -560,17 +576,60 @@ __device__ __forceinline__ void run_angle(WaveStacks &W, int i, Work &wk)
     wk.angles++;
     const float v = W.ang[2][i] * atan2_f32(W.ang[0][i], W.ang[1][i]);
     atomicAdd(&W.acc[W.ang_o[i]], (double)v);
+    atomicAdd(&W.ev[W.ang_o[i]], v * v);
 }
 
-__device__ __forceinline__ void run_point(WaveStacks &W, int i, Work &wk)
+// Closed form of the inner piece (s <= 1) over one edge part [a, a + L],
+// a >= -l1, a + L <= l1: the integral along it of pi r0 [G_inner(S) -
+// G_inner(r0)] dalpha, that is the difference of the antiderivative
+//     -beta H_odd + r0 R0 T
+// (see core) between the part's ends, written so that every difference
+// between the ends carries the factor L explicitly instead of subtracting
+// two nearly equal end values (a part much shorter than h would lose most of
+// its digits in FP32 otherwise):
+//   beta_b - beta_a      = 2 atan2(R0 L, S_a S_b + a b + c^2 + r0 (S_a + S_b))
+//                          (the solid angle of the triangle foot-v_a-v_b);
+//   asinh(b/c) - asinh(a/c) = asinh(L (c^2 + S_a S_b - a b) / (c^2 (S_a + S_b)));
+//   b S_b - a S_a         = L (S_b + a (a + b) / (S_a + S_b));
+//   b S_b^3 - a S_a^3     = L (S_b^3 + a (a + b) (S_a^2 + S_a S_b + S_b^2) / (S_a + S_b));
+//   b^3 - a^3             = L (a^2 + a b + b^2);
+// S_a S_b +- a b is formed from (S_a S_b)^2 - (a b)^2 = c^2 (a^2 + b^2 + c^2)
+// on the side where it would cancel.  L comes from the FP64 edge length when
+// the part is the whole edge.
+__device__ __forceinline__ void run_seg(WaveStacks &W, int i, Work &wk)
 {
-    const float r0 = W.pnt[0][i], R0 = W.pnt[1][i];
-    const float c2 = r0 * r0 + R0 * R0, c = sqrt_f32(c2);
-    const float xs = W.pnt[2][i], w = W.pnt[3][i];
-    const float x = fabsf(xs), S = xs < 0.0f ? 1.0f : sqrt_f32(c2 + x * x);
-    const Trans<float> t = trans<float>(r0, R0, c2, c, x, S, wk);
-    const float v = w * core_inner<float>(t, r0, R0, r0 * r0, c2);
+    wk.moments++;
+    const float r0 = W.pnt[0][i], sR0 = W.pnt[1][i], a = W.pnt[2][i], L = W.pnt[3][i];
+    const float R0 = fabsf(sR0), w = sR0 < 0.0f ? -1.0f : 1.0f;
+    const float b = a + L;
+    const float A = r0 * r0, R02 = R0 * R0, c2 = fmaf(R0, R0, A);
+    const float Sa = sqrt_f32(fmaf(a, a, c2)), Sb = sqrt_f32(fmaf(b, b, c2));
+    const float ab = a * b, SS = Sa * Sb, Ssum = Sa + Sb;
+    const float q = c2 * (fmaf(a, a, fmaf(b, b, c2)));  // (S_a S_b)^2 - (a b)^2
+    float sp, sm;                                       // S_a S_b + a b, S_a S_b - a b
+    if (ab > 0.0f) {
+        sp = SS + ab;
+        sm = q * rcp_f32(sp);
+    } else {
+        sm = SS - ab;
+        sp = q * rcp_f32(sm);
+    }
+    const float rs = rcp_f32(Ssum);
+    const float Dbeta = 2.0f * atan2_f32(R0 * L, fmaf(r0, Ssum, sp + c2));
+    const float Z = L * (c2 + sm) * rcp_f32(c2 * Ssum);
+    const float Da = log1p_f32(fmaf(Z * Z, rcp_f32(1.0f + sqrt_f32(fmaf(Z, Z, 1.0f))), Z));
+    const float t = a * (a + b) * rs;
+    const float DxS = L * (Sb + t);
+    const float DxS3 = L * fmaf(t, Sb * Sb + SS + Sa * Sa, Sb * Sb * Sb);
+    const float D3 = L * (fmaf(a, a, ab) + b * b);
+    // inner piece: g_-1 = -1/4, g_2 = -1/6, g_3 = 0, g_4 = 3/40, g_5 = -1/40
+    const float Hodd = -0.25f - 0.025f * A * A * A;
+    const float DP3r = 0.5f * fmaf(c2, Da, DxS) + A * Da;
+    const float DT = (-1.0f / 6.0f) * L + 0.075f * fmaf(2.0f * A + R02, L, D3 * (1.0f / 3.0f)) -
+                     0.025f * (0.25f * DxS3 + 0.375f * c2 * fmaf(c2, Da, DxS) + A * DP3r);
+    const float v = w * fmaf(-Dbeta, Hodd, r0 * R0 * DT);
     atomicAdd(&W.acc[W.pnt_o[i]], (double)v);
+    atomicAdd(&W.ev[W.pnt_o[i]], v * v);
 }
 
 // 4-point Gauss-Legendre nodes and weights on [-1, 1] (nodes in pairs +-x)
@@ -584,7 +643,8 @@ __constant__ float kGL4w[2] = {0.6521451548625461f, 0.3478548451374538f};
 // the term.
 __device__ __forceinline__ void run_quad(WaveStacks &W, int i, Work &wk)
 {
-    const float r0 = W.qd[0][i], c2 = W.qd[1][i], mid = W.qd[2][i], hl = W.qd[3][i], w = W.qd[4][i];
+    const float r0 = W.qd[0][i], sR0 = W.qd[1][i], mid = W.qd[2][i], hl = W.qd[3][i];
+    const float c2 = fmaf(sR0, sR0, r0 * r0), w = sR0 * hl * (1.0f / 120.0f);
     // the numerator (r0+1)(r0 Sigma + V^5) - r0 U^5 as a polynomial in U with
     // coefficients a0..a5 (a1..a4 = (r0+1) r0 V^(4-k), a0 = (r0+1)(V^5 + r0 V^4), a5 = -r0)
     const float V = 2.0f - r0;
@@ -603,14 +663,16 @@ __device__ __forceinline__ void run_quad(WaveStacks &W, int i, Work &wk)
     }
     wk.quads++;
     wk.qpoints += 4;
-    atomicAdd(&W.acc[W.qd_o[i]], (double)(w * acc));
+    const float v = w * acc;
+    atomicAdd(&W.acc[W.qd_o[i]], (double)v);
+    atomicAdd(&W.ev[W.qd_o[i]], v * v);
 }
 
 template <int KIND>
 __device__ __forceinline__ void run_one(WaveStacks &W, int i, Work &wk)
 {
     if (KIND == 0) run_angle(W, i, wk);
-    else if (KIND == 1) run_point(W, i, wk);
+    else if (KIND == 1) run_seg(W, i, wk);
     else run_quad(W, i, wk);
 }
 
@@ -654,9 +716,9 @@ __device__ __forceinline__ int wave_max(int v)
 __device__ __forceinline__ void mixed_edge_step(WaveStacks &W, int lane, Work &wk, int &nA, int &nP, int &nQ, bool live,
                                                 const EdgeRec *__restrict__ edges, int32_t s, double px, double py,
                                                 double pz, double invh, double r0d, float r0, float Ht, float dH,
-                                                float fsign, int64_t k, FixList fx, double &acc_in)
+                                                float fsign, int64_t k, FixList fx, double &acc_in, float &ev_in)
 {
-    float R0 = 0.0f, la = 0.0f, lb = 0.0f, sg = 0.0f;
+    float R0 = 0.0f, la = 0.0f, lb = 0.0f, Le = 0.0f, sg = 0.0f;
     if (live) {
         const EdgeRec E = edges[s];
         const double wx = px - E.vx, wy = py - E.vy, wz = pz - E.vz;
@@ -666,7 +728,7 @@ __device__ __forceinline__ void mixed_edge_step(WaveStacks &W, int lane, Work &w
             live = false;
         } else {
             const double lad = -(E.ex * wx + E.ey * wy + E.ez * wz) * invh;
-            const double lbd = lad + E.L * invh;
+            const double Ld = E.L * invh;
             const float R0f = (float)(fabs(rho) * invh);
             if (needs_fp64_f32(r0, R0f, fmaf(r0, r0, R0f * R0f))) {
                 const unsigned slot = atomicAdd(fx.count, 1u);
@@ -675,11 +737,16 @@ __device__ __forceinline__ void mixed_edge_step(WaveStacks &W, int lane, Work &w
             } else {
                 R0 = R0f;
                 la = (float)lad;
-                lb = (float)lbd;
+                lb = (float)(lad + Ld);
+                Le = (float)Ld;  // the edge's length from FP64: parts spanning the whole edge keep their digits
                 sg = (rho > 0.0 ? 1.0f : -1.0f) * fsign;
             }
         }
     }
+    // length of the part [x, y] of the edge: the FP64-derived length when it
+    // is the whole edge, else the FP32 difference (a clipped end sits on a
+    // kernel sphere, where an end shift changes the integral only to second order)
+    auto part_len = [&](float x, float y) { return (x == la && y == lb) ? Le : y - x; };
     // classification (the mixed form of edge_term).  The edge [la, lb] splits
     // into the parts beyond the support (|l| > l2), the shell parts and the
     // inner part (|l| < l1, when c < 1): [la, ca] + [cb, lb] beyond,
@@ -709,12 +776,16 @@ __device__ __forceinline__ void mixed_edge_step(WaveStacks &W, int lane, Work &w
         const float R02 = R0 * R0;
         const bool b = has_b;
         const float a1 = b ? la : ca, b1 = b ? ca : ia, a2 = b ? cb : ib, b2 = b ? lb : cb;
-        const float x1 = R02 + a1 * b1, y1 = R0 * (b1 - a1), x2 = R02 + a2 * b2, y2 = R0 * (b2 - a2);
+        const float x1 = R02 + a1 * b1, y1 = R0 * part_len(a1, b1), x2 = R02 + a2 * b2, y2 = R0 * part_len(a2, b2);
         zx = x1 * x2 - y1 * y2;
         zy = x1 * y2 + x2 * y1;
     }
     const float w_in = has_b ? -Ht * sg : (has_s ? dH * sg : 0.0f);
-    acc_in += (double)(w_in * atan2_f32(zy, zx));
+    {
+        const float v = w_in * atan2_f32(zy, zx);
+        acc_in += (double)v;
+        ev_in = fmaf(v, v, ev_in);
+    }
     wk.angles += (has_b || has_s) ? 1u : 0u;
     {
         const bool want = has_b && has_s;
@@ -724,7 +795,7 @@ __device__ __forceinline__ void mixed_edge_step(WaveStacks &W, int lane, Work &w
             const int slot = wave_push(want, nA);
             if (want) {
                 const float R02 = R0 * R0;
-                const float x1 = R02 + ca * ia, y1 = R0 * (ia - ca), x2 = R02 + ib * cb, y2 = R0 * (cb - ib);
+                const float x1 = R02 + ca * ia, y1 = R0 * part_len(ca, ia), x2 = R02 + ib * cb, y2 = R0 * part_len(ib, cb);
                 W.ang[0][slot] = x1 * y2 + x2 * y1;
                 W.ang[1][slot] = x1 * x2 - y1 * y2;
                 W.ang[2][slot] = dH * sg;
@@ -733,30 +804,19 @@ __device__ __forceinline__ void mixed_edge_step(WaveStacks &W, int lane, Work &w
             run_stack<0>(W, nA, lane, false, wk);
         }
     }
-    // inner part: closed-form points at its two ends, F(ib) - F(ia) with F odd
-    // in l; an end at +-l1 is the point l1 (weight +1, S = 1), an end of the
-    // edge the point |l| (weight -+sgn l)
+    // inner part [ia, ib]: one closed-form task over the part (run_seg)
     {
-        const bool inner = has_inner && ib > ia;
-        const bool a_l1 = ia != ca, b_l1 = ib != cb;
-        const float xa = a_l1 ? l1 : fabsf(ca), xb = b_l1 ? l1 : fabsf(cb);
-        const float wa = a_l1 ? 1.0f : -sgnr(ca), wb = b_l1 ? 1.0f : sgnr(cb);
-#pragma unroll
-        for (int q = 0; q < 2; q++) {
-            const float x = q == 0 ? xa : xb, wt = q == 0 ? wa : wb;
-            const bool at_l1 = q == 0 ? a_l1 : b_l1;
-            const bool want = inner && wt != 0.0f && x > 0.0f;
-            if (__ballot(want) != 0) {
-                const int slot = wave_push(want, nP);
-                if (want) {
-                    W.pnt[0][slot] = r0;
-                    W.pnt[1][slot] = R0;
-                    W.pnt[2][slot] = at_l1 ? -x : x;
-                    W.pnt[3][slot] = sg * wt;
-                    W.pnt_o[slot] = (uint8_t)lane;
-                }
-                run_stack<1>(W, nP, lane, false, wk);
+        const bool want = has_inner && ib > ia;
+        if (__ballot(want) != 0) {
+            const int slot = wave_push(want, nP);
+            if (want) {
+                W.pnt[0][slot] = r0;
+                W.pnt[1][slot] = sg < 0.0f ? -R0 : R0;
+                W.pnt[2][slot] = ia;
+                W.pnt[3][slot] = part_len(ia, ib);
+                W.pnt_o[slot] = (uint8_t)lane;
             }
+            run_stack<1>(W, nP, lane, false, wk);
         }
     }
     // shell parts by quadrature: [ca, ia] and [ib, cb]
@@ -765,18 +825,23 @@ __device__ __forceinline__ void mixed_edge_step(WaveStacks &W, int lane, Work &w
     // both shell parts' sub-intervals in one uniform loop
     int n0 = 0, n1 = 0;
     float hl0 = 0.0f, hl1 = 0.0f;
+    // sub-intervals no longer than 0.4 times the distance to the branch points
+    // l = +-ic of the integrand, nor than V = 2 - r0: the shell integrand is of
+    // order V^4 on the edge, and a sub-interval longer than V would let the
+    // polynomial in U = 2 - S grow far beyond that inside the ellipse of
+    // analyticity that bounds the Gauss-Legendre error
+    const float Vs = 2.0f - r0;
     if (q0) {
-        const float len = qb0 - qa0;
-        n0 = min(max((int)ceilf(len * rcp_f32(0.4f * qd0)), 1), 16);
+        const float len = part_len(qa0, qb0);
+        n0 = min(max((int)ceilf(len * rcp_f32(fminf(0.4f * qd0, Vs))), 1), 32);
         hl0 = 0.5f * len * rcp_f32((float)n0);
     }
     if (q1) {
-        const float len = qb1 - qa1;
-        n1 = min(max((int)ceilf(len * rcp_f32(0.4f)), 1), 16);
+        const float len = part_len(qa1, qb1);
+        n1 = min(max((int)ceilf(len * rcp_f32(fminf(0.4f, Vs))), 1), 32);
         hl1 = 0.5f * len * rcp_f32((float)n1);
     }
     const int nq = n0 + n1;
-    const float wq0 = sg * R0 * hl0 * (1.0f / 120.0f), wq1 = sg * R0 * hl1 * (1.0f / 120.0f);
     for (int kk = 0; __ballot(kk < nq) != 0; kk++) {
         const bool want = kk < nq;
         const int slot = wave_push(want, nQ);
@@ -784,10 +849,9 @@ __device__ __forceinline__ void mixed_edge_step(WaveStacks &W, int lane, Work &w
             const bool first = kk < n0;
             const float hl = first ? hl0 : hl1;
             W.qd[0][slot] = r0;
-            W.qd[1][slot] = c2;
+            W.qd[1][slot] = sg < 0.0f ? -R0 : R0;
             W.qd[2][slot] = first ? qa0 + (2.0f * (float)kk + 1.0f) * hl0 : qa1 + (2.0f * (float)(kk - n0) + 1.0f) * hl1;
             W.qd[3][slot] = hl;
-            W.qd[4][slot] = first ? wq0 : wq1;
             W.qd_o[slot] = (uint8_t)lane;
         }
         run_stack<2>(W, nQ, lane, false, wk);
@@ -835,7 +899,7 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(JobsArg A, unsign
             wk = Work();
             cur = jj;
         }
-        const FixList fx = {JOB(fix_count), JOB(fix_items), JOB(fix_cap)};
+        const FixList fx = {JOB(fix_count), JOB(fix_items), JOB(fix_cap), nullptr};
         const EdgeRec *__restrict__ edges = JOB(edges);
         const double *__restrict__ plane = JOB(plane);
         const int64_t *__restrict__ fvo = JOB(fvo);
@@ -856,10 +920,12 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(JobsArg A, unsign
             s_end = (int32_t)fvo[cfo[c + 1]];
         }
         W.acc[lane] = 0.0;
+        W.ev[lane] = 0.0f;
         int32_t face_end = s;  // first slot past the current wall: the first step opens the cell's first wall
         const int n_steps = wave_max((int)(s_end - s));
         int nA = 0, nP = 0, nQ = 0;
         double acc_in = 0.0;  // this lane's terms taken in place (not as tasks)
+        float ev_in = 0.0f;   // the sum of their squares
         bool inside = true;
         int n_on = 0;  // walls whose plane holds the particle
         bool face_ok = false;
@@ -883,7 +949,7 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(JobsArg A, unsign
                 dH = pi_dH<float>(r0);
             }
             mixed_edge_step(W, lane, wk, nA, nP, nQ, valid && face_ok, edges, s, px, py, pz, invh, r0d, r0, Ht, dH,
-                            fsign, k, fx, acc_in);
+                            fsign, k, fx, acc_in, ev_in);
         }
         run_stack<0>(W, nA, lane, true, wk);
         run_stack<1>(W, nP, lane, true, wk);
@@ -891,6 +957,8 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(JobsArg A, unsign
         lds_sync_wave();
         if (active) {
             JOB(f)[k] = (inside ? 1.0 : 0.0) - (W.acc[lane] + acc_in) * kInvPi;
+            float *const err = JOB(err);  // null when no estimate is wanted (the autotuner's timing runs)
+            if (err) err[k] = kTermErr * kInvPiF * sqrt_f32(ev_in + W.ev[lane]);
             if (inside && n_on >= 2) push_fix(fx, k, kWindingSlot);
         }
         lds_sync_wave();
@@ -1120,7 +1188,7 @@ __global__ void __launch_bounds__(256, 2) k_integrate_queued64(JobsArg A, unsign
         lds_sync_wave();
         if (active) {
             JOB(f)[k] = (inside ? 1.0 : 0.0) - W.acc[lane] * kInvPi;
-            if (inside && n_on >= 2) push_fix(FixList{JOB(fix_count), JOB(fix_items), JOB(fix_cap)}, k, kWindingSlot);
+            if (inside && n_on >= 2) push_fix(FixList{JOB(fix_count), JOB(fix_items), JOB(fix_cap), nullptr}, k, kWindingSlot);
         }
         lds_sync_wave();
     }
@@ -1184,6 +1252,7 @@ __global__ void __launch_bounds__(256) k_integrate_tiles(int64_t n_tiles, const 
         bool inside = true;
         int n_on = 0;
         double acc = 0.0;
+        float ev = 0.0f;
         const int64_t f0 = uniform64(cfo[cell]), f1 = uniform64(cfo[cell + 1]);
         for (int64_t j = f0; j < f1; j++) {
             const double nx = plane[4 * j], ny = plane[4 * j + 1], nz = plane[4 * j + 2], cj = plane[4 * j + 3];
@@ -1215,11 +1284,15 @@ __global__ void __launch_bounds__(256) k_integrate_tiles(int64_t n_tiles, const 
                     }
                     const R tv = edge_term<R>(r0, (R)R0d, (R)la, (R)lb, Ht, dH, wk);
                     face += (rho > 0.0) ? (double)tv : -(double)tv;
+                    if (PREC == MAP_MIXED) ev = fmaf((float)tv, (float)tv, ev);
                 }
                 acc += in_j ? face : -face;
             }
         }
-        if (active) f[k] = winding_term(inside, n_on, px, py, pz, cell, cfo, fvo, plane, edges) - acc * kInvPi;
+        if (active) {
+            f[k] = winding_term(inside, n_on, px, py, pz, cell, cfo, fvo, plane, edges) - acc * kInvPi;
+            if (PREC == MAP_MIXED && fx.err) fx.err[k] = kTermErr * kInvPiF * sqrt_f32(ev);
+        }
     }
     flush_work(wk, counters);
 }
@@ -1299,6 +1372,28 @@ __global__ void k_table_build(int n0, int n1, int n2, double *__restrict__ tab64
 
 }  // namespace
 
+// One wavefront per listed cell, lanes over its pairs: the pair in FP64.
+__global__ void k_recompute_cells(int64_t n_list, const uint32_t *__restrict__ cells, const int64_t *__restrict__ coff,
+                                  const uint32_t *__restrict__ pair_p, const double *__restrict__ xyz,
+                                  const double *__restrict__ h, const int64_t *__restrict__ cfo,
+                                  const int64_t *__restrict__ fvo, const double *__restrict__ plane,
+                                  const EdgeRec *__restrict__ edges, double *__restrict__ f,
+                                  unsigned long long *counters)
+{
+    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (q >= n_list) return;
+    const int64_t c = cells[q];
+    Work wk;
+    for (int64_t k = coff[c] + lane; k < coff[c + 1]; k += 64) {
+        const int64_t a = pair_p[k];
+        float ev = 0.0f;
+        f[k] = pair_fraction<MAP_FP64>(xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2], h[a], c, cfo, fvo, plane, edges, wk,
+                                       (uint64_t)k, nullptr, nullptr, 0u, ev);
+    }
+    if (lane == 0) atomicAdd(counters + C_FP64_PAIRS, (unsigned long long)(coff[c + 1] - coff[c]));
+}
+
 void launch_table_build(int n0, int n1, int n2, double *tab64, float *tab32, hipStream_t s)
 {
     const int64_t total = (int64_t)n0 * n1 * n2;
@@ -1374,7 +1469,7 @@ static void launch_queued(const IntJob *h_jobs, const IntJob *d_jobs, int n_jobs
 }
 
 void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, int precision,
-                      const IntegrateTune &tune, double *f, int64_t *counters, uint32_t *tile_ctr,
+                      const IntegrateTune &tune, double *f, float *err, int64_t *counters, uint32_t *tile_ctr,
                       uint64_t *fix_items, int64_t fix_cap, hipStream_t s)
 {
     const int64_t np = ps.n_pairs;
@@ -1384,6 +1479,7 @@ void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &
     fx.count = tile_ctr + 1;
     fx.items = fix_items;
     fx.cap = (unsigned)(fix_cap > 0xffffffffLL ? 0xffffffffLL : fix_cap);
+    fx.err = precision == MAP_MIXED ? err : nullptr;
     // [0] tile counter, [1] fixup count, [16..23] per-XCD tile counters
     fill_zero_bytes(tile_ctr, 24 * sizeof(unsigned), s);
     const int block = 256;
@@ -1411,6 +1507,7 @@ void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &
         J.plane = in.plane;
         J.edges = edges;
         J.f = f;
+        J.err = fx.err;
         J.counters = cnt;
         J.fix_count = fx.count;
         J.fix_items = fx.items;
@@ -1461,6 +1558,16 @@ void launch_integrate_jobs(const IntJob *h_jobs, const IntJob *d_jobs, int n_job
                            const IntegrateTune &tune, unsigned *tile_ctr, hipStream_t s)
 {
     launch_queued(h_jobs, d_jobs, n_jobs, precision, tune, tile_ctr, true, s);
+}
+
+void launch_recompute_cells(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, const uint32_t *cells,
+                            int64_t n_cells, double *f, int64_t *counters, hipStream_t s)
+{
+    if (n_cells <= 0) return;
+    hipLaunchKernelGGL(k_recompute_cells, dim3((unsigned)((n_cells * 64 + 255) / 256)), dim3(256), 0, s, n_cells,
+                       cells, ps.coff, ps.pair_p, in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f,
+                       reinterpret_cast<unsigned long long *>(counters));
+    EM_HIP(hipGetLastError());
 }
 
 void launch_fixup(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, const uint64_t *fix_keys,

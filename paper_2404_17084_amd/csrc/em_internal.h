@@ -77,8 +77,12 @@ enum Slot : int {
     S_ADAPT0, S_ADAPT1, S_ADAPT2, S_ADAPT3, S_ADAPT4, S_ADAPT5, S_ADAPT6, S_ADAPT7,
     S_VOR0, S_VOR1, S_VOR2, S_VOR3, S_VOR4, S_VOR5, S_VOR6, S_VOR7, S_VOR8, S_VOR9, S_VOR10, S_VOR11, S_VOR12,
     S_VOR13, S_VOR14,
+    S_ERR, S_CHECK,
     S_NUM_SLOTS
 };
+
+// Default per-cell error budget of the mixed path (relative to the cell's mass).
+constexpr double kDefaultCellTol = 2e-6;
 
 // ---------------------------------------------------------------- geometry records
 // One directed wall edge v_k -> v_{k+1} of a face (slot of face_vert):
@@ -117,7 +121,8 @@ enum : int {
     C_ANGLES = 7,
     C_QPOINTS = 8,
     C_WINDING = 9,  // pairs whose winding weight was recomputed (particle on two or more wall planes)
-    C_NUM = 10
+    C_FP64_PAIRS = 10,  // mixed path: pairs recomputed in FP64 because their cell's error estimate was too large
+    C_NUM = 11
 };
 
 // Device-resident view of one job's inputs.
@@ -225,6 +230,7 @@ struct IntJob {
     const double *plane = nullptr;
     const EdgeRec *edges = nullptr;
     double *f = nullptr;
+    float *err = nullptr;  // mixed path: FP32 error estimate per pair (units of f)
     unsigned long long *counters = nullptr;
     unsigned *fix_count = nullptr;
     uint64_t *fix_items = nullptr;
@@ -247,9 +253,15 @@ void launch_integrate_jobs(const IntJob *h_jobs, const IntJob *d_jobs, int n_job
 
 // em_integrate.hip: raw f per pair (cell-major order).
 void build_tiles(Workspace &ws, const DevInputs &in, PairSet &ps, hipStream_t s);
+// err: MAP_MIXED: per-pair FP32 error estimates (units of f) are written there
+// (may be null; ignored for MAP_FP64).
 void launch_integrate(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, int precision,
-                      const IntegrateTune &tune, double *f, int64_t *counters, uint32_t *tile_ctr,
+                      const IntegrateTune &tune, double *f, float *err, int64_t *counters, uint32_t *tile_ctr,
                       uint64_t *fix_items, int64_t fix_cap, hipStream_t s);
+// FP64 recomputation (the whole pair, winding weight included) of every pair
+// of the n_cells listed cells, written over f; counters[C_FP64_PAIRS] counts them.
+void launch_recompute_cells(const DevInputs &in, const EdgeRec *edges, const PairSet &ps, const uint32_t *cells,
+                            int64_t n_cells, double *f, int64_t *counters, hipStream_t s);
 // FP64 values of the fixup items: flagged edge terms, and the winding
 // correction of pairs whose particle lies on two or more wall planes of the
 // cell (counted in counters[C_WINDING]).
@@ -289,5 +301,10 @@ void free_voronoi(VorGrid &V);
 // em_reduce.hip
 void launch_reduce(const DevInputs &in, const PairSet &ps, const double *f, double *S, double *M,
                    double *rho, double *red, unsigned *flags, hipStream_t s);
+// Mixed path: lists the cells whose estimated FP32 error, sqrt(sum over their
+// pairs of (m_a err_ai / S_a)^2), exceeds tol |M_i| (count in *count, at most
+// cap cells listed; count may exceed cap).
+void launch_cell_check(const DevInputs &in, const PairSet &ps, const float *err, const double *S, const double *M,
+                       double tol, unsigned *count, uint32_t *list, int64_t cap, hipStream_t s);
 
 }  // namespace em

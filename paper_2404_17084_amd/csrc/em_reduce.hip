@@ -82,6 +82,31 @@ __global__ void k_cell_mass(int64_t nc, const int64_t *coff, const uint32_t *pai
     }
 }
 
+// Mixed path: one wavefront per cell, sqrt(sum (m_a err_ai / S_a)^2) against
+// tol |M_i|; the cells over the budget are listed.
+__global__ void k_cell_check(int64_t nc, const int64_t *coff, const uint32_t *pair_p, const float *err,
+                             const double *S, const double *m, const double *M, double tol, unsigned *count,
+                             uint32_t *list, int64_t cap)
+{
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (i >= nc) return;
+    double v = 0.0;
+    for (int64_t k = coff[i] + lane; k < coff[i + 1]; k += 64) {
+        const uint32_t a = pair_p[k];
+        const double sa = S[a];
+        if (sa > 0.0) {
+            const double e = m[a] * (double)err[k] / sa;
+            v += e * e;
+        }
+    }
+    v = wave_sum(v);
+    if (lane == 0 && sqrt(v) > tol * fabs(M[i])) {
+        const unsigned q = atomicAdd(count, 1u);
+        if ((int64_t)q < cap) list[q] = (uint32_t)i;
+    }
+}
+
 // Block partials: [0] sum M, [1] max |S-1| over particles whose support lies in
 // the box, [2] sum m, [3] 1 if any M is not finite.
 constexpr int RB = 256;
@@ -157,6 +182,17 @@ void launch_map_back(int64_t n, const int64_t *poff, const uint32_t *perm, const
     if (n <= 0) return;
     hipLaunchKernelGGL(k_map_back, dim3((unsigned)((n * 64 + 255) / 256)), dim3(256), 0, s, n, poff, perm, pair_c, f,
                        S, q_cell, q_part);
+    EM_HIP(hipGetLastError());
+}
+
+void launch_cell_check(const DevInputs &in, const PairSet &ps, const float *err, const double *S, const double *M,
+                       double tol, unsigned *count, uint32_t *list, int64_t cap, hipStream_t s)
+{
+    const int64_t nc = in.n_cells;
+    fill_zero_bytes(count, sizeof(unsigned), s);
+    if (nc <= 0 || ps.n_pairs <= 0) return;
+    hipLaunchKernelGGL(k_cell_check, dim3((unsigned)((nc * 64 + 255) / 256)), dim3(256), 0, s, nc, ps.coff, ps.pair_p,
+                       err, S, in.m, M, tol, count, list, cap);
     EM_HIP(hipGetLastError());
 }
 

@@ -69,6 +69,7 @@ struct JobState {
     int64_t *counters = nullptr;
     PairSet ps;
     double *f = nullptr;
+    float *err = nullptr;  // mixed path: per-pair FP32 error estimates
     uint32_t *tile_ctr = nullptr;
     uint64_t *fix_items = nullptr;
     int64_t fix_cap = 0;

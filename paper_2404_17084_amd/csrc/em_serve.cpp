@@ -300,7 +300,8 @@ static bool launch_batch(Server &S)
                     // host checks of the entry before the kernel reads it
                     const char *why = nullptr;
                     if (!js.ps.pair_p || !js.ps.pair_c || !js.f || !js.edges || !js.in.xyz || !js.in.h || !js.in.cfo ||
-                        !js.in.fvo || !js.in.plane || !js.counters || !js.tile_ctr || !js.fix_items)
+                        !js.in.fvo || !js.in.plane || !js.counters || !js.tile_ctr || !js.fix_items ||
+                        (prec == MAP_MIXED && !js.err))
                         why = "a device buffer of the job is missing";
                     else if (js.ps.n_pairs >= (int64_t)UINT32_MAX)
                         why = "pair count out of range";
@@ -325,6 +326,7 @@ static bool launch_batch(Server &S)
                     e.plane = js.in.plane;
                     e.edges = js.edges;
                     e.f = js.f;
+                    e.err = js.err;
                     e.counters = reinterpret_cast<unsigned long long *>(js.counters);
                     e.fix_count = js.tile_ctr + 1;
                     e.fix_items = js.fix_items;

@@ -145,9 +145,9 @@ extern "C" int map_autotune(map_ctx *h, const map_particles_in *p, const map_cel
                         t.persistent = d;
                         t.tile_waves = tw;
                         t.grid_per_cu = g;
-                        launch_integrate(in, edges, ps, precision, t, f, counters, tile_ctr, fix_items, fix_cap, s);
+                        launch_integrate(in, edges, ps, precision, t, f, nullptr, counters, tile_ctr, fix_items, fix_cap, s);
                         EM_HIP(hipEventRecord(C->ev[6], s));
-                        launch_integrate(in, edges, ps, precision, t, f, counters, tile_ctr, fix_items, fix_cap, s);
+                        launch_integrate(in, edges, ps, precision, t, f, nullptr, counters, tile_ctr, fix_items, fix_cap, s);
                         EM_HIP(hipEventRecord(C->ev[7], s));
                         EM_HIP(hipEventSynchronize(C->ev[7]));
                         float ms = 0.0f;

@@ -329,3 +329,28 @@ def test_clumps_all_cells_mixed_vs_fp64(clumps256k, clumps_gpu):
     assert rel.max() < MIXED_CELL_REL
     assert df.max() < 1e-6
     assert a["stats"]["n_fixup_terms"] > 0
+
+
+def test_mixed_cell_budget_switches(uniform4k, uniform4k_oracle):
+    """The per-cell error budget of the mixed path: a negative budget leaves every pair in FP32; a
+    budget no cell can meet sends every pair to the FP64 recomputation, whose values then equal the
+    oracle's to the FP64 bar; the default recomputes few cells and meets the mixed bar."""
+    say("case: mixed per-cell error budget")
+    p, c = uniform4k
+    o = uniform4k_oracle
+    with em.Mapper(device=0, precision=em.MAP_MIXED, cell_tol=-1.0) as mp:
+        raw = mp.map(p, c, want_pairs=True)
+    assert raw["stats"]["n_fp64_cells"] == 0 and raw["stats"]["n_fp64_pairs"] == 0
+    with em.Mapper(device=0, precision=em.MAP_MIXED, cell_tol=1e-300) as mp:
+        allc = mp.map(p, c, want_pairs=True)
+    assert allc["stats"]["n_fp64_cells"] == c.n_cells and allc["stats"]["n_fp64_pairs"] == o["f"].size
+    assert np.abs(allc["f"] - o["f"]).max() < FP64_PAIR_ABS
+    assert (np.abs(allc["M"] - o["M"]) / o["M"]).max() < FP64_CELL_REL
+    with em.Mapper(device=0, precision=em.MAP_MIXED) as mp:
+        dflt = mp.map(p, c, want_pairs=True)
+    rel_raw = (np.abs(raw["M"] - o["M"]) / o["M"]).max()
+    rel = (np.abs(dflt["M"] - o["M"]) / o["M"]).max()
+    say(f"  raw mixed max cell rel {rel_raw:.3e}; with the budget {rel:.3e} "
+        f"({dflt['stats']['n_fp64_cells']} cells, {dflt['stats']['n_fp64_pairs']} pairs in FP64)")
+    assert rel < MIXED_CELL_REL
+    assert dflt["stats"]["n_fp64_cells"] < c.n_cells // 10

@@ -232,6 +232,7 @@ def test_pseudo_set_mixed_mapping_full_lognormal(mp, lognormal2m):
     assert np.array_equal(r["pair_p"], O["pair_p"]) and np.array_equal(r["pair_c"], O["pair_c"])
     rel = np.abs(r["M"] - O["M"]) / O["M"]
     say(f"  pseudo {q.n}, pairs {O['f'].size}, max cell rel {rel.max():.3e}, max pair |df| "
-        f"{np.abs(r['f'] - O['f']).max():.3e}, fixups {r['stats']['n_fixup_terms']}")
+        f"{np.abs(r['f'] - O['f']).max():.3e}, fixups {r['stats']['n_fixup_terms']}, cells in FP64 "
+        f"{r['stats']['n_fp64_cells']} ({r['stats']['n_fp64_pairs']} pairs)")
     assert rel.max() < 1e-5
     assert abs(r["M"].sum() - p.m.sum()) < 1e-9
