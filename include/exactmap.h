@@ -78,7 +78,7 @@ typedef struct map_config {
     uint64_t hbm_budget_bytes; /* serving admission budget; 0 = 80% of free device memory */
     int max_jobs;              /* serving: jobs resident on the device at once (0 = 8) */
     int max_queue;             /* serving: jobs waiting for admission (0 = 1024) */
-    const char *tune_cache_path; /* autotuner cache file (text); NULL = no cache */
+    const char *tune_cache_path; /* autotuner cache file (text); NULL = no cache; copied by map_init */
     int serve_timeout_ms;      /* serving: time limit of every device wait of a job (0 = 120000) */
     int serve_trace;           /* serving: nonzero = one line per job event on stderr */
     int64_t fixup_cap;         /* MAP_MIXED: capacity of the list of edge terms recomputed in

@@ -23,6 +23,10 @@ Ctx::Ctx(const map_config *cfg) : ws(cfg ? cfg->device : 0)
     device = cfg ? cfg->device : 0;
     precision = cfg ? cfg->precision : MAP_FP64;
     if (cfg) config = *cfg;
+    if (config.tune_cache_path) {
+        tune_cache_path = config.tune_cache_path;
+        config.tune_cache_path = tune_cache_path.c_str();
+    }
     EM_HIP(hipSetDevice(device));
     EM_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
     for (auto &e : ev) EM_HIP(hipEventCreate(&e));

@@ -31,6 +31,8 @@ struct Ctx {
     bool has_explicit[2] = {false, false};
     std::map<std::pair<int, int>, IntegrateTune> tune_table;
     std::string arch;
+    // the caller's config.tune_cache_path is borrowed only during map_init: a copy
+    std::string tune_cache_path;
     Server *server = nullptr;
     // the last map_particles result, kept in the workspace for map_back: the
     // cell-major pairs, their fractions and S_a (and, once built, the
