@@ -233,6 +233,26 @@ int map_pairs(map_ctx *ctx, const map_particles_in *p, const map_cells_in *c, in
 int map_particles(map_ctx *ctx, const map_particles_in *p, const map_cells_in *c, map_out *out);
 
 /*
+ * map_particles without any device allocation, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same mapping, results bitwise equal
+ * to map_particles with the same launch shape, but every intermediate buffer
+ * lives in one fixed 128 MiB device array that the library holds on each
+ * device it runs on until the process ends (its address is looked up when a
+ * context is created on the device).  Inputs and outputs must be device
+ * memory (mem_kind MAP_MEM_DEVICE for p, c and out; out->stats is host
+ * memory); precision MAP_FP64 or MAP_MIXED.  No hipMalloc, hipFree or other
+ * allocating call is made.  All calls on one device share the array: calls
+ * that overlap in time on one device (other contexts, other threads) race and
+ * must not be made.  The call leaves nothing for map_back.
+ * Errors: those of map_particles; MAP_EINVAL for host memory or MAP_TABLE;
+ * MAP_ENOMEM when the input does not fit the array (about 10,000 Voronoi
+ * cells and their particles fit; checked before any device work from the
+ * geometry sizes, and again as the pair set is built).
+ */
+int map_particles_noalloc(map_ctx *ctx, const map_particles_in *p, const map_cells_in *c, map_out *out);
+
+/*
  * Inverse mapping, Sec. II-B Eq. (4): particle values from cell values with
  * the pair weights of this context's last successful map_particles call,
  * normalised as in the forward mapping,

@@ -147,6 +147,8 @@ _SIGS = {
     "map_particles": (c_int, [c_vp, ctypes.POINTER(map_particles_in), ctypes.POINTER(map_cells_in),
                               ctypes.POINTER(map_out)]),
     "map_back": (c_int, [c_vp, c_vp, c_int, c_vp, c_int]),
+    "map_particles_noalloc": (c_int, [c_vp, ctypes.POINTER(map_particles_in), ctypes.POINTER(map_cells_in),
+                                      ctypes.POINTER(map_out)]),
     "map_submit": (c_int, [c_vp, ctypes.POINTER(map_particles_in), ctypes.POINTER(map_cells_in),
                            ctypes.POINTER(map_out), ctypes.POINTER(c_u64)]),
     "map_poll": (c_int, [c_vp, c_u64, c_i64, ctypes.POINTER(c_int)]),
@@ -381,6 +383,22 @@ def map_particles(ctx, xyz, m, h, cells, cell_mass=None, cell_density=None, frac
     _last_n.pop(_ctx_key(ctx), None)
     _check(ctx, lib.map_particles(ctx, ctypes.byref(P), ctypes.byref(C), ctypes.byref(O)))
     _last_n[_ctx_key(ctx)] = int(P.n)
+    return st.as_dict()
+
+
+def map_particles_noalloc(ctx, xyz, m, h, cells, cell_mass=None, cell_density=None, frac_sum_raw=None):
+    """map_particles with no device allocation (fixed scratch array): inputs and outputs must be
+    contiguous torch CUDA float64/int tensors already of the right size.  Returns the statistics."""
+    lib = load()
+    P, k1 = particles_in(xyz, m, h)
+    C, k2 = cells_in(cells)
+    st = map_stats()
+    outs = [x for x in (cell_mass, cell_density, frac_sum_raw) if x is not None]
+    kind = _kind(outs[0]) if outs else MAP_MEM_DEVICE
+    O = map_out(_ptr(cell_mass), _ptr(cell_density), _ptr(frac_sum_raw), None, None, None, 0, kind,
+                ctypes.pointer(st))
+    _check(ctx, lib.map_particles_noalloc(ctx, ctypes.byref(P), ctypes.byref(C), ctypes.byref(O)))
+    _last_n.pop(_ctx_key(ctx), None)
     return st.as_dict()
 
 

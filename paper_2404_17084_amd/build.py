@@ -12,7 +12,8 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libexactmap.so")
 
 SOURCES = ["em_primitives.hip", "em_geometry.hip", "em_pairs.hip", "em_integrate.hip", "em_reduce.hip",
-           "em_pseudo.hip", "em_table.hip", "em_voronoi.hip", "em_api.cpp", "em_serve.cpp", "em_tune.cpp"]
+           "em_pseudo.hip", "em_table.hip", "em_voronoi.hip", "em_noalloc.hip", "em_api.cpp", "em_serve.cpp",
+           "em_tune.cpp"]
 
 # Packed FP32 instructions are disabled for all device code.
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -28,6 +28,7 @@ Ctx::Ctx(const map_config *cfg) : ws(cfg ? cfg->device : 0)
         config.tune_cache_path = tune_cache_path.c_str();
     }
     EM_HIP(hipSetDevice(device));
+    noalloc_attach(device);
     EM_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
     for (auto &e : ev) EM_HIP(hipEventCreate(&e));
     hipDeviceProp_t prop;

@@ -36,6 +36,11 @@ struct Error {
 // `bytes`, reallocating (and discarding contents) when it is too small.
 // get() and release() belong to the owning thread; bytes_held() may be read
 // from any thread (the slot table is sized once and never reallocated).
+//
+// Arena mode (use_arena): get() hands out 256-byte aligned pieces of one
+// fixed device buffer instead, a slot that needs more than its piece getting
+// a new piece further on; it never allocates or frees device memory and
+// throws MAP_ENOMEM when the buffer is used up.
 class Workspace {
 public:
     explicit Workspace(int device);
@@ -48,6 +53,11 @@ public:
     T *get(int slot, size_t count) { return static_cast<T *>(get(slot, count * sizeof(T))); }
     size_t bytes_held() const;
     void release();
+    void use_arena(void *base, size_t bytes);
+    bool is_arena() const { return arena_base_ != nullptr; }
+    // bytes still free in arena mode (SIZE_MAX otherwise)
+    size_t arena_free() const;
+    size_t arena_used() const { return arena_used_; }
 
 private:
     struct Buf {
@@ -57,6 +67,8 @@ private:
     int device_;
     std::vector<Buf> bufs_;
     std::atomic<size_t> held_{0};
+    char *arena_base_ = nullptr;
+    size_t arena_cap_ = 0, arena_used_ = 0;
 };
 
 // Buffer slots of one mapping job.
@@ -83,6 +95,12 @@ enum Slot : int {
 
 // Default per-cell error budget of the mixed path (relative to the cell's mass).
 constexpr double kDefaultCellTol = 2e-6;
+
+// Size of the fixed device scratch array of map_particles_noalloc (em_noalloc.hip).
+constexpr size_t kNoallocScratchBytes = size_t(128) << 20;
+// Looks up (once per device; the device must be current) the device address
+// of that array.
+void noalloc_attach(int device);
 
 // ---------------------------------------------------------------- geometry records
 // One directed wall edge v_k -> v_{k+1} of a face (slot of face_vert):

@@ -12,8 +12,27 @@ Workspace::Workspace(int device) : device_(device), bufs_(S_NUM_SLOTS) {}
 
 Workspace::~Workspace() { release(); }
 
+void Workspace::use_arena(void *base, size_t bytes)
+{
+    release();
+    arena_base_ = static_cast<char *>(base);
+    arena_cap_ = bytes;
+    arena_used_ = 0;
+}
+
+size_t Workspace::arena_free() const
+{
+    return arena_base_ ? arena_cap_ - arena_used_ : ~size_t(0);
+}
+
 void Workspace::release()
 {
+    if (arena_base_) {
+        for (Buf &b : bufs_) b = Buf();
+        arena_used_ = 0;
+        held_.store(0);
+        return;
+    }
     for (Buf &b : bufs_)
         if (b.p) {
             (void)hipFree(b.p);
@@ -28,6 +47,19 @@ void *Workspace::get(int slot, size_t bytes)
     if (slot < 0 || slot >= (int)bufs_.size()) throw Error{MAP_EINVAL, "workspace slot out of range"};
     Buf &b = bufs_[slot];
     if (bytes == 0) bytes = 256;
+    if (arena_base_) {
+        if (b.cap >= bytes) return b.p;
+        const size_t want = (bytes + 255) & ~size_t(255);
+        if (want > arena_cap_ - arena_used_)
+            throw Error{MAP_ENOMEM, "the fixed scratch buffer (" + std::to_string(arena_cap_ >> 20) +
+                                        " MiB) is too small for this input: " + std::to_string(arena_used_ + want) +
+                                        " bytes needed so far"};
+        b.p = arena_base_ + arena_used_;
+        b.cap = want;
+        arena_used_ += want;
+        held_.store(arena_used_);
+        return b.p;
+    }
     if (b.cap < bytes) {
         if (b.p) EM_HIP(hipFree(b.p));
         held_.fetch_sub(b.cap);
