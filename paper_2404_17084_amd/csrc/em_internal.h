@@ -54,6 +54,10 @@ public:
     size_t bytes_held() const;
     void release();
     void use_arena(void *base, size_t bytes);
+    // Stream-ordered mode: buffers come from the device's memory pool with
+    // hipMallocAsync / hipFreeAsync on stream s (no device-wide
+    // synchronisation when a buffer is replaced or released).
+    void use_stream(hipStream_t s) { stream_ = s; }
     bool is_arena() const { return arena_base_ != nullptr; }
     // bytes still free in arena mode (SIZE_MAX otherwise)
     size_t arena_free() const;
@@ -69,6 +73,7 @@ private:
     std::atomic<size_t> held_{0};
     char *arena_base_ = nullptr;
     size_t arena_cap_ = 0, arena_used_ = 0;
+    hipStream_t stream_ = nullptr;
 };
 
 // Buffer slots of one mapping job.

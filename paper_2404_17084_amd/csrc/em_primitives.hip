@@ -35,7 +35,8 @@ void Workspace::release()
     }
     for (Buf &b : bufs_)
         if (b.p) {
-            (void)hipFree(b.p);
+            if (stream_) (void)hipFreeAsync(b.p, stream_);
+            else (void)hipFree(b.p);
             held_.fetch_sub(b.cap);
             b.p = nullptr;
             b.cap = 0;
@@ -61,13 +62,16 @@ void *Workspace::get(int slot, size_t bytes)
         return b.p;
     }
     if (b.cap < bytes) {
-        if (b.p) EM_HIP(hipFree(b.p));
+        if (b.p) {
+            if (stream_) EM_HIP(hipFreeAsync(b.p, stream_));
+            else EM_HIP(hipFree(b.p));
+        }
         held_.fetch_sub(b.cap);
         b.p = nullptr;
         b.cap = 0;
         size_t want = bytes + bytes / 4 + 256;
         want = (want + 255) & ~size_t(255);
-        hipError_t e = hipMalloc(&b.p, want);
+        hipError_t e = stream_ ? hipMallocAsync(&b.p, want, stream_) : hipMalloc(&b.p, want);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             b.p = nullptr;

@@ -259,10 +259,10 @@ static void finish_job(Server &S, Job *j)
     }
     ServeSlot *sl = j->slot;
     finish_locked(S, j, code, msg);
-    // give the slot's memory back when the slots hold more than the budget
-    size_t held = 0;
-    for (auto &o : S.slots) held += o->ws.bytes_held();
-    if (held > S.budget && sl && !sl->job) {
+    // the job's buffers go back to the device's memory pool (stream-ordered:
+    // no device-wide synchronisation), so the memory held is that of the jobs
+    // in flight plus what the pool keeps cached (up to the budget)
+    if (sl && !sl->job) {
         lk.unlock();
         sl->ws.release();
     }
@@ -477,7 +477,19 @@ static Server &server_of(Ctx &C)
     EM_HIP(hipMalloc(&S->d_table, 2 * sizeof(IntJob) * (size_t)S->table_cap));
     EM_HIP(hipHostMalloc(&S->h_table, 2 * sizeof(IntJob) * (size_t)S->table_cap, hipHostMallocDefault));
     EM_HIP(hipMalloc(&S->d_ctr, 64 * sizeof(unsigned)));
-    for (int i = 0; i < n_slots; i++) S->slots.push_back(std::make_unique<ServeSlot>(C.device));
+    for (int i = 0; i < n_slots; i++) {
+        S->slots.push_back(std::make_unique<ServeSlot>(C.device));
+        S->slots.back()->ws.use_stream(S->sstream);
+    }
+    {
+        // the pool that serves the slots' buffers keeps up to the budget cached
+        hipMemPool_t pool = nullptr;
+        if (hipDeviceGetDefaultMemPool(&pool, C.device) == hipSuccess && pool) {
+            uint64_t keep = (uint64_t)S->budget;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+        (void)hipGetLastError();
+    }
     Server *raw = S.release();
     raw->thread = std::thread(serve_loop, raw);
     C.server = raw;
@@ -508,9 +520,9 @@ int serve_stop(Ctx &C)
     (void)hipSetDevice(C.device);
     const bool failed = S->failed;
     if (!failed) {
+        for (auto &sl : S->slots) sl->ws.release();
         if (S->sstream) (void)hipStreamSynchronize(S->sstream);
         if (S->bstream) (void)hipStreamSynchronize(S->bstream);
-        for (auto &sl : S->slots) sl->ws.release();
         if (S->d_table) (void)hipFree(S->d_table);
         if (S->d_ctr) (void)hipFree(S->d_ctr);
         if (S->h_table) (void)hipHostFree(S->h_table);

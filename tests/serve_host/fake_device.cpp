@@ -208,7 +208,8 @@ void Workspace::release()
 {
     for (Buf &b : bufs_)
         if (b.p) {
-            hipFree(b.p);
+            if (stream_) hipFreeAsync(b.p, stream_);
+            else hipFree(b.p);
             held_.fetch_sub(b.cap);
             b.p = nullptr;
             b.cap = 0;
@@ -218,7 +219,10 @@ void *Workspace::get(int slot, size_t bytes)
 {
     Buf &b = bufs_.at(slot);
     if (b.cap < bytes) {
-        if (b.p) hipFree(b.p);
+        if (b.p) {
+            if (stream_) hipFreeAsync(b.p, stream_);
+            else hipFree(b.p);
+        }
         held_.fetch_sub(b.cap);
         b.p = std::malloc(bytes);
         b.cap = bytes;

@@ -40,6 +40,15 @@ inline hipError_t hipMalloc(T **p, size_t n) { *p = (T *)std::malloc(n ? n : 1);
 template <class T>
 inline hipError_t hipHostMalloc(T **p, size_t n, unsigned) { *p = (T *)std::malloc(n ? n : 1); return *p ? hipSuccess : 2; }
 inline hipError_t hipFree(void *p) { return hipFreeVoid(p); }
+// stream-ordered allocation: no device-wide synchronisation (the fake frees at once; the scheduler
+// only frees buffers whose device work has completed)
+template <class T>
+inline hipError_t hipMallocAsync(T **p, size_t n, hipStream_t) { *p = (T *)std::malloc(n ? n : 1); return *p ? hipSuccess : 2; }
+inline hipError_t hipFreeAsync(void *p, hipStream_t) { std::free(p); return hipSuccess; }
+typedef struct ihipMemPool_t *hipMemPool_t;
+enum hipMemPoolAttr { hipMemPoolAttrReleaseThreshold = 4 };
+inline hipError_t hipDeviceGetDefaultMemPool(hipMemPool_t *p, int) { *p = nullptr; return hipSuccess; }
+inline hipError_t hipMemPoolSetAttribute(hipMemPool_t, hipMemPoolAttr, void *) { return hipSuccess; }
 inline hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind) { std::memcpy(d, s, n); return hipSuccess; }
 inline hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind, hipStream_t)
 {
