@@ -4,10 +4,14 @@
 One step = one synchronous ``map_particles`` call on the 262,144-particle clumpy
 workload (uniform background plus three Gaussian clumps, sigma 0.05 box,
 density contrast 1e4; box-clipped Voronoi cells of the particles): input
-validation, geometry tables, pair search, integration of every pair, the
-sum-to-one normalisation and the per-cell reduction.  Inputs are resident in
-device memory before the timed region.  The mixed path (FP32 closed-form
-terms) is the headline value; the all-FP64 path is timed beside it.
+validation, geometry tables, pair search, integration of every pair, FP64
+fixups, the sum-to-one normalisation and the per-cell reduction.  Inputs are
+resident in device memory before the timed region.  The mixed path (FP32
+closed-form terms, FP64 geometry and sums) is the headline value; the all-FP64
+path is timed beside it.  Further legs: served mapping of 64 jobs with Poisson
+arrivals (p50/p99 latency), inverse mapping, tabulated variant, device Voronoi
+grid, pseudo-particle front end, the oracle on the host cores, and (on
+request) a VALU calibration kernel.
 
 Prints one JSON line.
 """
@@ -24,41 +28,43 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work model of the integration kernel (counted from its formulas,
-# add/mul = 1, fused multiply-add = 2, divide / square root / atan2 / log1p = 1):
-FLOP_FACE = 7       # wall distance d = c - n.p and r0 = |d|/h
-FLOP_EDGE = 19      # projections rho, l_a, l_b and their scaling by 1/h
-FLOP_ETERM = 8      # per-edge setup: c^2, the support crossing l2 and c (2 square roots)
-FLOP_MOMENT = 66    # closed form at one point: sqrt, asinh, angle difference, piece polynomial
-FLOP_QPOINT = 31    # one Gauss-Legendre point of the shell integrand (a sqrt and a reciprocal among them)
-FLOP_ANGLE = 6      # angle of one edge part seen from the foot point (one atan2) times H
+# Work counters of the integration kernel (the GPU's own formulation; transcendentals = 1 flop each),
+# reported beside the model below for comparison.
+FLOP_FACE, FLOP_EDGE, FLOP_ETERM, FLOP_MOMENT, FLOP_QPOINT, FLOP_ANGLE = 7, 19, 8, 66, 31, 6
 
-# HBM bytes per launch of the mixed integration kernel from FETCH_SIZE/WRITE_SIZE counter runs scaled by a
-# 1 GiB copy (profiles/traffic_integrate_queued_clumps262144.md), valid for the source it was measured on.
-TRAFFIC_SOURCE = "paper_2404_17084_amd/csrc/em_integrate.hip"
-TRAFFIC_SHA256_PREFIX = "739857dddd99444c"
-TRAFFIC_BYTES = 2.270e9 + 0.283e9
+# HBM bytes per launch of the mixed integration kernel and its measured VALU counters, valid only for the
+# kernel source they were measured on (profiles/traffic_integrate_queued_clumps262144.md,
+# profiles/valu_integrate_queued_clumps262144.md); null once the source has changed.
+COUNTER_SOURCE = "paper_2404_17084_amd/csrc/em_integrate.hip"
+COUNTER_SHA256_PREFIX = None
+TRAFFIC_BYTES = None
+VALU_FLOPS_PER_LAUNCH = None
 
 PEAK_FP64 = 78.6   # TFLOP/s, MI355X FP64 vector
 PEAK_FP32 = 157.3  # TFLOP/s, MI355X FP32 vector (packed)
 
+WORKLOAD = ("clumps-262144: uniform background + 3 Gaussian clumps (sigma 0.05 box, contrast 1e4, seed 2); "
+            "h = 1.2 (m/rho)^(1/3) with rho a top-hat density over the 58 nearest neighbours (h = r_58/2, "
+            "58 particles within 2h); box-clipped Voronoi cells of the particles")
 
-def algorithmic_flops(st) -> float:
+
+def counters_valid():
+    import hashlib
+
+    if COUNTER_SHA256_PREFIX is None:
+        return False
+    try:
+        with open(os.path.join(ROOT, COUNTER_SOURCE), "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()
+    except OSError:
+        return False
+    return digest.startswith(COUNTER_SHA256_PREFIX)
+
+
+def kernel_work_flops(st) -> float:
     return (FLOP_FACE * st["n_face_visits"] + FLOP_EDGE * st["n_edge_visits"] + FLOP_ETERM * st["n_edge_terms"]
             + FLOP_MOMENT * st["n_moment_evals"] + FLOP_QPOINT * st["n_quad_points"]
             + FLOP_ANGLE * st["n_angle_evals"])
-
-
-def measured_traffic():
-    """Counter-based HBM bytes of the integration kernel, or None once its source has changed."""
-    import hashlib
-
-    try:
-        with open(os.path.join(ROOT, TRAFFIC_SOURCE), "rb") as fh:
-            digest = hashlib.sha256(fh.read()).hexdigest()
-    except OSError:
-        return None
-    return TRAFFIC_BYTES if digest.startswith(TRAFFIC_SHA256_PREFIX) else None
 
 
 def to_device(p, c):
@@ -81,27 +87,134 @@ def to_device(p, c):
     return t(p.xyz), t(p.m), t(p.h), dc
 
 
-def cpu_baseline(p, c, target_s: float = 12.0):
-    """The FP64 oracle, untuned, on a seeded sample of cells with all their pairs."""
+def oracle_sample(p, c, n_cells, seed=12345):
     import oracle
 
-    rng = np.random.default_rng(12345)
-    n_try = 400
-    sel = np.sort(rng.choice(c.n_cells, n_try, replace=False))
+    rng = np.random.default_rng(seed)
+    sel = np.sort(rng.choice(c.n_cells, n_cells, replace=False))
+    return sel, oracle.pairs_for_cells(p.xyz, p.h, c, sel)
+
+
+def cpu_baseline(p, c, target_s: float = 12.0):
+    """The FP64 oracle, untuned, on a seeded sample of cells with all their pairs (pair search and
+    closed-form integrals): on all host cores, then on one core for a smaller sample.  Also returns the
+    operation count of the oracle's formulas over the larger sample (the flop model of the roofline)."""
+    import oracle
+
     t0 = time.perf_counter()
-    pp, pc = oracle.pairs_for_cells(p.xyz, p.h, c, sel)
+    sel, (pp, pc) = oracle_sample(p, c, 400)
     oracle.pair_fractions(p.xyz, p.h, c, pp, pc)
     dt = time.perf_counter() - t0
-    n_cells = int(min(c.n_cells, max(n_try, n_try * target_s / max(dt, 1e-3))))
-    sel = np.sort(rng.choice(c.n_cells, n_cells, replace=False))
+    n_cells = int(min(c.n_cells, max(400, 400 * target_s / max(dt, 1e-3))))
     t0 = time.perf_counter()
-    pp, pc = oracle.pairs_for_cells(p.xyz, p.h, c, sel)
+    sel, (pp, pc) = oracle_sample(p, c, n_cells)
     f = oracle.pair_fractions(p.xyz, p.h, c, pp, pc)
     dt = time.perf_counter() - t0
     assert np.all(np.isfinite(f))
-    return {"value": pp.size / dt, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    fm = oracle.flop_model(p.xyz, p.h, c, pp, pc)
+    # one core: a sample sized for about 6 s
+    oracle.set_num_threads(1)
+    try:
+        n1 = max(50, int(n_cells * 6.0 / max(dt * cores, 1e-3)))
+        t0 = time.perf_counter()
+        _, (qp, qc) = oracle_sample(p, c, n1, seed=54321)
+        oracle.pair_fractions(p.xyz, p.h, c, qp, qc)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(cores)
+    base = {"value": pp.size / dt, "unit": "pairs/s", "cores": cores, "kind": "oracle",
             "sample": f"{n_cells} of {c.n_cells} cells (seeded), all {pp.size} of their pairs: pair search + "
-                      f"closed-form integrals, {dt:.1f} s"}
+                      f"closed-form integrals, {dt:.1f} s on {cores} threads",
+            "one_core": {"value": qp.size / dt1, "unit": "pairs/s",
+                         "sample": f"{n1} cells, {qp.size} pairs, {dt1:.1f} s on 1 thread"}}
+    model = {"flops_per_pair": fm["flops"] / max(pp.size, 1), "sample_pairs": int(pp.size),
+             "faces_per_pair": fm["faces"] / max(pp.size, 1), "edges_per_pair": fm["edges"] / max(pp.size, 1),
+             "pyramids_per_pair": fm["pyramids"] / max(pp.size, 1), "pieces_per_pair": fm["pieces"] / max(pp.size, 1)}
+    return base, model
+
+
+def flop_model_only(p, c, n_cells=6000):
+    import oracle
+
+    _, (pp, pc) = oracle_sample(p, c, n_cells)
+    fm = oracle.flop_model(p.xyz, p.h, c, pp, pc)
+    return {"flops_per_pair": fm["flops"] / max(pp.size, 1), "sample_pairs": int(pp.size),
+            "faces_per_pair": fm["faces"] / max(pp.size, 1), "edges_per_pair": fm["edges"] / max(pp.size, 1),
+            "pyramids_per_pair": fm["pyramids"] / max(pp.size, 1), "pieces_per_pair": fm["pieces"] / max(pp.size, 1)}
+
+
+def serve_leg(em, seed_sizes=4, n_jobs=64, budget=32_000_000_000, max_jobs=8, arrival_seeds=5, load=0.7):
+    """Served mapping (continuous batching): n_jobs clumpy jobs of log-uniform sizes 1e4-1e6 particles
+    (per-job seeds 1000 + j), their Voronoi cells built on the device beforehand; admission by the
+    device-memory estimate against a 32 GB budget, mixed precision, device-resident inputs.  First all
+    jobs at once (sustained rate), then Poisson arrivals at `load` times that rate for several arrival
+    seeds: latency = completion - submission, p50/p99 by nearest rank."""
+    import torch
+    import synth
+
+    rng = np.random.default_rng(seed_sizes)
+    sizes = np.floor(10 ** rng.uniform(4, 6, n_jobs)).astype(int)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    jobs = []
+    t_gen = time.perf_counter()
+    with em.Mapper(device=0) as gen:
+        for j, n in enumerate(sizes):
+            p = synth.particles("clumps", int(n), 1000 + j)
+            xyz = t(p.xyz)
+            G = em.map_voronoi(gen.ctx, xyz, synth.BOX, 0, device=True)
+            M = torch.zeros(int(n), dtype=torch.float64, device=dev)
+            jobs.append((xyz, t(p.m), t(p.h), G, M, float(p.m.sum())))
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    print(f"bench: serving inputs ready ({sizes.sum()} particles in {n_jobs} jobs, {t_gen:.1f} s)", file=sys.stderr,
+          flush=True)
+
+    def run(mp, order, arrivals=None):
+        ids = []
+        t0 = time.perf_counter()
+        for k, j in enumerate(order):
+            if arrivals is not None:
+                wait = t0 + arrivals[k] - time.perf_counter()
+                if wait > 0:
+                    time.sleep(wait)
+            xyz, m, h, G, M, _ = jobs[j]
+            ids.append((j, em.map_submit(mp.ctx, xyz, m, h, G, M)))
+        stats = []
+        for j, jid in ids:
+            state, st = em.map_poll(mp.ctx, jid, 120_000_000)
+            assert state == em.JOB_DONE
+            stats.append((j, st))
+        return time.perf_counter() - t0, stats
+
+    with em.Mapper(device=0, precision=em.MAP_MIXED, hbm_budget_bytes=budget, max_jobs=max_jobs) as mp:
+        run(mp, list(range(4)))  # warm-up
+        wall, stats = run(mp, list(range(n_jobs)))
+        pairs = sum(st["n_pairs"] for _, st in stats)
+        rate = n_jobs / wall
+        mass_err = max(abs(float(jobs[j][4].sum()) - jobs[j][5]) for j, _ in stats)
+        lam = load * rate
+        lat = []
+        open_wall = open_pairs = 0.0
+        for s in range(arrival_seeds):
+            arr = np.cumsum(np.random.default_rng(100 + s).exponential(1.0 / lam, n_jobs))
+            order = list(np.random.default_rng(200 + s).permutation(n_jobs))
+            w, st2 = run(mp, order, arr)
+            lat.extend(st["ms_latency"] for _, st in st2)
+            open_wall += w
+            open_pairs += sum(st["n_pairs"] for _, st in st2)
+    lat = np.sort(np.array(lat))
+    rank = lambda q: float(lat[max(0, int(np.ceil(q * lat.size)) - 1)])
+    return {"workload": f"{n_jobs} clumpy jobs, sizes log-uniform 1e4-1e6 (seed {seed_sizes}; {int(sizes.sum())} "
+                        f"particles), per-job seeds 1000+j, device-built Voronoi cells, mixed precision, "
+                        f"budget {budget / 1e9:.0f} GB, {max_jobs} slots",
+            "closed_loop": {"jobs_per_s": rate, "pairs_per_s": pairs / wall, "wall_s": wall, "pairs": pairs,
+                            "max_mass_err": mass_err},
+            "open_loop": {"arrival_rate_per_s": lam, "load": load, "arrival_seeds": arrival_seeds,
+                          "samples": int(lat.size), "p50_ms": rank(0.50), "p99_ms": rank(0.99),
+                          "mean_ms": float(lat.mean()), "max_ms": float(lat[-1]),
+                          "pairs_per_s": open_pairs / open_wall}}
 
 
 def pseudo_leg(em, steps: int, warmup: int):
@@ -160,6 +273,7 @@ def pseudo_leg(em, steps: int, warmup: int):
             "ms_hsolve": float(np.mean([s["ms_hsolve"] for s in sts])),
             "particles_per_s_front_end": n / dt,
             "pseudo_pairs": ms["n_pairs"], "ms_map_pseudo": 1e3 * dm, "pairs_per_s_pseudo": ms["n_pairs"] / dm,
+            "fp64_cells_pseudo": ms["n_fp64_cells"], "fp64_pairs_pseudo": ms["n_fp64_pairs"],
             "mass_err_pseudo": abs(ms["mass_out"] - ms["mass_in"]), "adaptive": adaptive}
 
 
@@ -222,18 +336,19 @@ def voronoi_leg(em, mapper, p, xyz, m, h, c, M_fp64, steps, with_oracle):
     per-cell time on a sample of cells."""
     import torch
     import oracle
+    import synth
     sites = torch.from_numpy(np.ascontiguousarray(p.xyz)).to("cuda:0")
     out = {}
     for it in (0, 5):
-        em.map_voronoi(mapper.ctx, sites, synth_box(), it, device=True)  # warm-up
+        em.map_voronoi(mapper.ctx, sites, synth.BOX, it, device=True)  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            G = em.map_voronoi(mapper.ctx, sites, synth_box(), it, device=True)
+            G = em.map_voronoi(mapper.ctx, sites, synth.BOX, it, device=True)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         out[f"lloyd_{it}"] = {"ms": 1e3 * dt, "ms_device": G.ms, "cells_per_s": p.n / dt}
-    G = em.map_voronoi(mapper.ctx, sites, synth_box(), 0, device=True)
+    G = em.map_voronoi(mapper.ctx, sites, synth.BOX, 0, device=True)
     mapper.set_precision(em.MAP_FP64)
     M = torch.zeros(p.n, dtype=torch.float64, device="cuda:0")
     em.map_particles(mapper.ctx, xyz, m, h, G, M)
@@ -243,16 +358,11 @@ def voronoi_leg(em, mapper, p, xyz, m, h, c, M_fp64, steps, with_oracle):
     if with_oracle:
         sel = np.arange(0, p.n, p.n // 16)
         t0 = time.perf_counter()
-        oracle.voronoi(p.xyz, synth_box(), sel=sel)
+        oracle.voronoi(p.xyz, synth.BOX, sel=sel)
         dt = time.perf_counter() - t0
         out["oracle"] = {"cells_per_s": sel.size / dt, "sample": f"{sel.size} cells (each sorts all sites by "
                          f"distance, then clips nearest first)", "cores": 1}
     return out
-
-
-def synth_box():
-    import synth
-    return synth.BOX
 
 
 def back_leg(em, mapper, p, M, nc, steps):
@@ -278,6 +388,24 @@ def back_leg(em, mapper, p, M, nc, steps):
     return {"ms_first_call": 1e3 * first, "ms": 1e3 * dt, "mass_rel_err": abs(mq - mref) / abs(mref)}
 
 
+def valu_calibration():
+    """The calibration kernel (16 independent FP32 FMA chains per lane, 8 workgroups of 256 per CU): its
+    FLOP rate is the measured non-packed FP32 vector rate of the device."""
+    import ctypes
+    from paper_2404_17084_amd import build as hipbuild
+
+    lib = ctypes.CDLL(hipbuild.CALIB_LIB)
+    ms = ctypes.c_double()
+    fma = ctypes.c_double()
+    blocks, iters = 256 * 8, 20000
+    rc = lib.em_calib_valu(0, blocks, iters, 5, ctypes.byref(ms), ctypes.byref(fma))
+    assert rc == 0, rc
+    tf = 2.0 * fma.value / (ms.value * 1e-3) / 1e12
+    return {"kernel": "k_valu_fma", "workgroups": blocks, "iterations": iters, "ms_per_launch": ms.value,
+            "fma_per_launch": fma.value, "valu_instructions_per_launch": fma.value / 64.0,
+            "tflops_fp32_nonpacked": tf, "frac_of_157_3": tf / PEAK_FP32}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,10 +414,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-pseudo", action="store_true", help="skip the pseudo-particle leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-mapping leg")
+    ap.add_argument("--quick", action="store_true",
+                    help="only the FP64 and mixed steps of the main workload (for profiling runs)")
     ap.add_argument("--mixed-shape", default=None,
                     help="explicit mixed launch shape 'waves,tile_waves,grid_per_cu,distribution' instead of tuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with one plain 1 GiB device-to-device copy (scale for HBM byte counters)")
+    ap.add_argument("--valu-calibration", action="store_true",
+                    help="run the VALU calibration kernel (scale for the VALU counters; measured FP32 rate)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the mapping runs on a single "
@@ -320,7 +453,7 @@ def main():
             w, tw, g, d = (int(v) for v in args.mixed_shape.split(","))
             em.map_set_tune(mapper.ctx, prec, w, tw, g, d)
             tuned[name] = {"waves": w, "tile_waves": tw, "grid_per_cu": g, "distribution": d, "ms_integrate": None}
-        elif not args.no_tune:
+        elif not args.no_tune and not args.quick:
             shape, ms = em.map_autotune(mapper.ctx, xyz, m, h, dc, prec)
             tuned[name] = {"waves": shape[0], "tile_waves": shape[1], "grid_per_cu": shape[2],
                            "distribution": shape[3], "ms_integrate": ms}
@@ -334,33 +467,56 @@ def main():
             stats.append(em.map_particles(mapper.ctx, xyz, m, h, dc, M, rho, S))
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        npairs = stats[-1]["n_pairs"]
+        st = stats[-1]
+        npairs = st["n_pairs"]
         ms_int = float(np.mean([s["ms_integrate"] for s in stats]))
-        flops = algorithmic_flops(stats[-1])
         results[name] = {"pairs_per_s": args.steps * npairs / dt, "ms_per_step": 1e3 * dt / args.steps,
                          "ms_integrate": ms_int, "ms_pairs": float(np.mean([s["ms_pairs"] for s in stats])),
+                         "ms_fixup": float(np.mean([s["ms_fixup"] for s in stats])),
                          "ms_reduce": float(np.mean([s["ms_reduce"] for s in stats])),
                          "ms_setup": float(np.mean([s["ms_setup"] for s in stats])),
-                         "flops_per_launch": flops, "tflops_integrate": flops / (ms_int * 1e-3) / 1e12,
-                         "mass_err": abs(stats[-1]["mass_out"] - stats[-1]["mass_in"]),
-                         "max_abs_S_minus_1": stats[-1]["max_abs_S_minus_1"], "n_pairs": npairs,
-                         "n_fixup_terms": stats[-1]["n_fixup_terms"], "n_moment_evals": stats[-1]["n_moment_evals"],
-                         "n_quad_intervals": stats[-1]["n_quad_intervals"], "n_quad_points": stats[-1]["n_quad_points"],
-                         "n_angle_evals": stats[-1]["n_angle_evals"],
-                         "n_edge_visits": stats[-1]["n_edge_visits"], "n_candidates": stats[-1]["n_candidates"]}
+                         "kernel_work_flops": kernel_work_flops(st),
+                         "mass_err": abs(st["mass_out"] - st["mass_in"]),
+                         "max_abs_S_minus_1": st["max_abs_S_minus_1"], "n_pairs": npairs,
+                         "n_fixup_terms": st["n_fixup_terms"], "n_boundary_pairs": st["n_boundary_pairs"],
+                         "n_fp64_cells": st["n_fp64_cells"], "n_fp64_pairs": st["n_fp64_pairs"],
+                         "n_moment_evals": st["n_moment_evals"], "n_quad_intervals": st["n_quad_intervals"],
+                         "n_quad_points": st["n_quad_points"], "n_angle_evals": st["n_angle_evals"],
+                         "n_edge_visits": st["n_edge_visits"], "n_candidates": st["n_candidates"]}
         Ms[name] = M.cpu().numpy().copy()
         print(f"bench: {name}: {results[name]}", file=sys.stderr, flush=True)
-    back = back_leg(em, mapper, p, M, nc, args.steps)
-    print(f"bench: inverse mapping: {back}", file=sys.stderr, flush=True)
-    table = table_leg(em, mapper, p, xyz, m, h, dc, M, rho, S, Ms["fp64"], args.steps, args.warmup)
-    print(f"bench: tabulated variant: {table}", file=sys.stderr, flush=True)
-    vor = voronoi_leg(em, mapper, p, xyz, m, h, c, Ms["fp64"], args.steps, not args.no_cpu_baseline)
-    print(f"bench: voronoi grid: {vor}", file=sys.stderr, flush=True)
-    mapper.close()
     rel = np.abs(Ms["mixed"] - Ms["fp64"]) / np.abs(Ms["fp64"])
+    extra = {}
+    if not args.quick:
+        extra["inverse_mapping"] = back_leg(em, mapper, p, M, nc, args.steps)
+        print(f"bench: inverse mapping: {extra['inverse_mapping']}", file=sys.stderr, flush=True)
+        extra["tabulated"] = table_leg(em, mapper, p, xyz, m, h, dc, M, rho, S, Ms["fp64"], args.steps, args.warmup)
+        print(f"bench: tabulated variant: {extra['tabulated']}", file=sys.stderr, flush=True)
+        extra["voronoi_grid"] = voronoi_leg(em, mapper, p, xyz, m, h, c, Ms["fp64"], args.steps,
+                                            not args.no_cpu_baseline)
+        print(f"bench: voronoi grid: {extra['voronoi_grid']}", file=sys.stderr, flush=True)
+    mapper.close()
+    if not args.quick and not args.no_serve:
+        extra["served"] = serve_leg(em)
+        print(f"bench: served: {extra['served']}", file=sys.stderr, flush=True)
+    if not args.quick and not args.no_pseudo:
+        extra["pseudo_path"] = pseudo_leg(em, args.steps, args.warmup)
+        print(f"bench: pseudo path: {extra['pseudo_path']}", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline and not args.quick:
+        print("bench: timing the oracle on a cell sample", file=sys.stderr, flush=True)
+        cpu, model = cpu_baseline(p, c)
+    else:
+        model = flop_model_only(p, c)
+    if args.valu_calibration:
+        extra["valu_calibration"] = valu_calibration()
+        print(f"bench: valu calibration: {extra['valu_calibration']}", file=sys.stderr, flush=True)
 
-    mx = results["mixed"]
-    ach = mx["tflops_integrate"]
+    mx, fp = results["mixed"], results["fp64"]
+    model_flops = model["flops_per_pair"] * mx["n_pairs"]
+    ach = model_flops / (mx["ms_integrate"] * 1e-3) / 1e12
+    ach64 = model_flops / (fp["ms_integrate"] * 1e-3) / 1e12
+    valid = counters_valid()
     line = {
         "metric": "particle-cell pairs mapped/s (mixed FP32/FP64, <=1e-5 rel err per cell)",
         "value": mx["pairs_per_s"],
@@ -374,30 +530,29 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 terms, f64 geometry/sums",
         "data": "synthetic",
-        "config": {"workload": "clumps-262144: uniform background + 3 Gaussian clumps (sigma 0.05 box, contrast "
-                               "1e4, seed 2), h from 58 neighbours, box-clipped Voronoi cells",
-                   "particles": p.n, "cells": nc, "pairs": mx["n_pairs"], "precision": "mixed"},
-        "fp64": {"pairs_per_s": results["fp64"]["pairs_per_s"], "ms_per_step": results["fp64"]["ms_per_step"],
-                 "ms_integrate": results["fp64"]["ms_integrate"],
-                 "tflops_integrate": results["fp64"]["tflops_integrate"],
-                 "roofline_frac": results["fp64"]["tflops_integrate"] / PEAK_FP64},
-        "speedup_mixed_vs_fp64": mx["pairs_per_s"] / results["fp64"]["pairs_per_s"],
+        "config": {"workload": WORKLOAD, "particles": p.n, "cells": nc, "pairs": mx["n_pairs"], "precision": "mixed"},
+        "fp64": {"pairs_per_s": fp["pairs_per_s"], "ms_per_step": fp["ms_per_step"],
+                 "ms_integrate": fp["ms_integrate"], "model_tflops_integrate": ach64,
+                 "roofline_frac": ach64 / PEAK_FP64},
+        "speedup_mixed_vs_fp64": mx["pairs_per_s"] / fp["pairs_per_s"],
         "mixed_vs_fp64_max_cell_rel": float(rel.max()),
+        "mixed_vs_fp64_mean_cell_rel": float(rel.mean()),
         "mass_err_mixed": mx["mass_err"],
-        "stages_ms_mixed": {k: mx[k] for k in ("ms_setup", "ms_pairs", "ms_integrate", "ms_reduce")},
+        "mixed_fp64_work": {k: mx[k] for k in ("n_fixup_terms", "n_boundary_pairs", "n_fp64_cells", "n_fp64_pairs")},
+        "stages_ms_mixed": {k: mx[k] for k in ("ms_setup", "ms_pairs", "ms_integrate", "ms_fixup", "ms_reduce")},
+        "stages_ms_fp64": {k: fp[k] for k in ("ms_setup", "ms_pairs", "ms_integrate", "ms_fixup", "ms_reduce")},
+        "flop_model": dict(model, source="static count of the oracle's direct-form formulas (orc_flop_model) "
+                                         "over a seeded sample of cells"),
+        "kernel_work_tflops_integrate": mx["kernel_work_flops"] / (mx["ms_integrate"] * 1e-3) / 1e12,
         "launch_shape": tuned,
-        "inverse_mapping": back,
-        "tabulated": table,
-        "voronoi_grid": vor,
         "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32, "unit": "TFLOP/s", "frac": ach / PEAK_FP32,
-                     "traffic": measured_traffic()},
+                     "traffic": TRAFFIC_BYTES if valid else None,
+                     "measured_valu_tflops": (VALU_FLOPS_PER_LAUNCH / (mx["ms_integrate"] * 1e-3) / 1e12
+                                              if valid and VALU_FLOPS_PER_LAUNCH else None)},
     }
-    if not args.no_pseudo:
-        line["pseudo_path"] = pseudo_leg(em, args.steps, args.warmup)
-        print(f"bench: pseudo path: {line['pseudo_path']}", file=sys.stderr, flush=True)
-    if not args.no_cpu_baseline:
-        print("bench: timing the oracle on a cell sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(p, c)
+    line.update(extra)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     if args.copy_calibration:
         src_t = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
         dst_t = torch.empty_like(src_t)

@@ -78,6 +78,8 @@ def _load():
         lib.orc_reduce.argtypes = [i64, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp]
         lib.orc_map_back.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp]
         lib.orc_num_threads.restype = i
+        lib.orc_set_num_threads.argtypes = [i]
+        lib.orc_flop_model.argtypes = [vp, vp, ctypes.POINTER(_Cells), i64, vp, vp, vp]
         lib.orc_table_build.argtypes = [i, i, i, vp]
         lib.orc_table_use.argtypes = [vp, i, i, i]
         for nm in ("orc_table_interp", "orc_solid_angle"):
@@ -308,8 +310,28 @@ def map_back(q_cell, mapping, n):
     return out
 
 
+def flop_model(xyz, h, cells, pair_p, pair_c) -> dict:
+    """Operation count of the direct form (orc_pair_fraction) over the given pairs: faces, edges,
+    triangle terms, pyramids, pieces, moment evaluations and flops (see orc_flop_model)."""
+    lib = _load()
+    g = _Geom(cells)
+    xyz = _f64(xyz)
+    h = _f64(h)
+    pp = np.ascontiguousarray(pair_p, dtype=np.int32)
+    pc = np.ascontiguousarray(pair_c, dtype=np.int32)
+    cnt = np.zeros(7, np.int64)
+    lib.orc_flop_model(_p(xyz), _p(h), ctypes.byref(g.s), pp.size, _p(pp), _p(pc), _p(cnt))
+    keys = ("faces", "edges", "triangle_terms", "pyramids", "pieces", "moments", "flops")
+    return {k: int(v) for k, v in zip(keys, cnt)}
+
+
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the oracle's parallel loops."""
+    _load().orc_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------- pseudo-particle front end (Sec. III)

@@ -726,6 +726,15 @@ void orc_map_back(int64_t n, int64_t npairs, const int32_t *pair_p, const int32_
     for (int64_t a = 0; a < n; a++) q_part[a] = S[a] > 0.0 ? q_part[a] / S[a] : 0.0;
 }
 
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
@@ -733,4 +742,117 @@ int orc_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Operation count of the direct form above (the flop model of the mapping). */
+/* Counted by hand from the statements of orc_moments, orc_pyramid, tri_term */
+/* and orc_pair_fraction: every add, subtract, multiply, divide, square root */
+/* and elementary function (tan, atan, asinh, pow) counts one; compares,     */
+/* sign tests and fabs count zero (the file is built without fused           */
+/* multiply-add, so every operation is one IEEE operation).                  */
+/*   orc_moments                      61  (5 of them sqrt/tan/asinh/atan)    */
+/*   orc_pyramid   3 (c^2) + 4 per breakpoint found (sub, sqrt, div, atan)   */
+/*                 + 153 per piece (midpoint 2, tan 1, S 5, two moments 122, */
+/*                   the g_0 term 2, five g_n terms 4 each, sum 1)           */
+/*                 + 3 per nonzero coefficient of G(r0) (pow, mul, add)       */
+/*                 + 4 (r0 phi G(r0), the subtraction, the scale)            */
+/*   tri_term      3 (|l|/R0, atan, the sign) + the pyramid (l != 0)         */
+/*   edge          29 up to rho (e 3, |e| 6, e/|e| 3, m 9, rho 8); when      */
+/*                 rho != 0, 28 more (g 6, l_a 8, l_b 8, R0 1, l/h 2, the    */
+/*                 update 3) and its two tri_terms                           */
+/*   face          6 (d); when d != 0, 9 more (r0 1, f 6, the update 2) and  */
+/*                 its edges                                                 */
+/* The walk below follows orc_pair_fraction's control flow (the same skips,  */
+/* the same breakpoints and pieces) without the arithmetic of the integrals. */
+/* counts[0..6]: faces, edges, triangle terms, pyramids, pieces, moment      */
+/* evaluations, flops (all summed over the pairs).                           */
+/* ------------------------------------------------------------------------ */
+static void count_pyramid(double r0, double R0, double phi, int64_t *cnt)
+{
+    if (r0 <= 0.0 || R0 <= 0.0 || phi <= 0.0) return;
+    double c2 = r0 * r0 + R0 * R0;
+    double bounds[4];
+    int nb = 0;
+    int64_t fl = 3;
+    bounds[nb++] = 0.0;
+    for (int k = 1; k <= 2; k++) {
+        double kk = (double)(k * k);
+        if (kk > c2) {
+            double ak = atan(sqrt(kk - c2) / R0);
+            fl += 4;
+            if (ak < phi) bounds[nb++] = ak;
+        }
+    }
+    bounds[nb++] = phi;
+    for (int s = 0; s + 1 < nb; s++) {
+        if (bounds[s + 1] <= bounds[s]) continue;
+        fl += 153;
+        cnt[4] += 1;
+        cnt[5] += 2;
+    }
+    const double *g0 = g_piece(ORC_M4, r0);
+    for (int k = 0; k < 6; k++)
+        if (g0[k] != 0.0) fl += 3;
+    fl += 4;
+    cnt[3] += 1;
+    cnt[6] += fl;
+}
+
+static void count_pair(const double *p, double h, const orc_cells *C, int64_t cell, int64_t *cnt)
+{
+    for (int64_t j = C->cell_face_off[cell]; j < C->cell_face_off[cell + 1]; j++) {
+        const double *pl = C->face_plane + 4 * j;
+        double nx = pl[0], ny = pl[1], nz = pl[2], cc = pl[3];
+        double d = cc - (nx * p[0] + ny * p[1] + nz * p[2]);
+        cnt[0] += 1;
+        cnt[6] += 6;
+        if (d == 0.0) continue;
+        cnt[6] += 9;
+        double r0 = fabs(d) / h;
+        double fx = p[0] + d * nx, fy = p[1] + d * ny, fz = p[2] + d * nz;
+        int64_t k0 = C->face_vert_off[j], k1 = C->face_vert_off[j + 1];
+        int64_t nv = k1 - k0;
+        for (int64_t k = 0; k < nv; k++) {
+            const double *va = C->verts + 3 * (int64_t)C->face_vert[k0 + k];
+            const double *vb = C->verts + 3 * (int64_t)C->face_vert[k0 + (k + 1) % nv];
+            double ex = vb[0] - va[0], ey = vb[1] - va[1], ez = vb[2] - va[2];
+            double len = sqrt(ex * ex + ey * ey + ez * ez);
+            cnt[1] += 1;
+            cnt[6] += 9;
+            if (len == 0.0) continue;
+            cnt[6] += 20;
+            ex /= len; ey /= len; ez /= len;
+            double mx = ny * ez - nz * ey, my = nz * ex - nx * ez, mz = nx * ey - ny * ex;
+            double rho = mx * (fx - va[0]) + my * (fy - va[1]) + mz * (fz - va[2]);
+            if (rho == 0.0) continue;
+            cnt[6] += 28;
+            double gx = fx - rho * mx, gy = fy - rho * my, gz = fz - rho * mz;
+            double la = ex * (va[0] - gx) + ey * (va[1] - gy) + ez * (va[2] - gz);
+            double lb = ex * (vb[0] - gx) + ey * (vb[1] - gy) + ez * (vb[2] - gz);
+            double R0 = fabs(rho) / h;
+            double ls[2] = { lb / h, la / h };
+            for (int q = 0; q < 2; q++) {
+                if (ls[q] == 0.0) continue;
+                cnt[2] += 1;
+                cnt[6] += 3;
+                count_pyramid(r0, R0, atan(fabs(ls[q]) / R0), cnt);
+            }
+        }
+    }
+}
+
+void orc_flop_model(const double *xyz, const double *h, const orc_cells *C, int64_t npairs, const int32_t *pair_p,
+                    const int32_t *pair_c, int64_t counts[7])
+{
+    for (int k = 0; k < 7; k++) counts[k] = 0;
+#pragma omp parallel
+    {
+        int64_t loc[7] = { 0, 0, 0, 0, 0, 0, 0 };
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t q = 0; q < npairs; q++)
+            count_pair(xyz + 3 * (int64_t)pair_p[q], h[pair_p[q]], C, pair_c[q], loc);
+#pragma omp critical
+        for (int k = 0; k < 7; k++) counts[k] += loc[k];
+    }
 }

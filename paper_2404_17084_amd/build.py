@@ -30,6 +30,22 @@ def _compile(src: str) -> str:
     return obj
 
 
+CALIB_SRC = os.path.join(CSRC, "calib", "em_calib.hip")
+CALIB_LIB = os.path.join(OUT_DIR, "libemcalib.so")
+
+
+def build_calib() -> str:
+    """The benchmark's VALU calibration kernel (a separate library; not part of the mapping ABI)."""
+    os.makedirs(OUT_DIR, exist_ok=True)
+    tmp = CALIB_LIB + ".tmp"
+    cmd = ["hipcc", "-x", "hip"] + FLAGS + ["-shared", CALIB_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"calibration build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, CALIB_LIB)
+    return CALIB_LIB
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
@@ -41,8 +57,9 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_calib()
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", CALIB_LIB)
     return LIB
 
 

@@ -389,3 +389,18 @@ def test_cell_distance_against_sampling():
             assert d_or == 0.0
         else:
             assert d_or <= d_s + 1e-12 and d_s - d_or < 0.02
+
+
+@pytest.mark.parametrize("h,expected", [(1.0 / 3.0, 10146), (2.0 / 3.0, 9906)])
+def test_flop_model_hand_count(h, expected):
+    """The operation count of the direct form, on a cube of half-side 1/2 about the particle
+    (6 walls, 24 edges, 48 right-triangle pyramids with r0 = R0 = L/h, phi = pi/4), equals the
+    count done by hand from the per-statement costs listed in orc_flop_model's comment:
+    L/h = 1.5: no breakpoint (c^2 = 4.5), one shell-piece G(r0) (6 terms): pyramid 3 + 153 + 18 + 4;
+    L/h = 0.75: the s = 2 breakpoint computed but beyond phi, one piece, inner G(r0) (3 terms):
+    pyramid 3 + 4 + 153 + 9 + 4; then 3 per triangle term, 57 + two terms per edge, 15 per wall."""
+    c = box_cell([0.0, 0.0, 0.0], [1.0, 1.0, 1.0])
+    xyz = np.array([[0.5, 0.5, 0.5]])
+    fm = oracle.flop_model(xyz, np.array([h]), c, np.array([0]), np.array([0]))
+    assert fm["faces"] == 6 and fm["edges"] == 24 and fm["pyramids"] == 48
+    assert fm["flops"] == expected
