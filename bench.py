@@ -277,6 +277,145 @@ def pseudo_leg(em, steps: int, warmup: int):
             "mass_err_pseudo": abs(ms["mass_out"] - ms["mass_in"]), "adaptive": adaptive}
 
 
+LARGE_N, LARGE_SEED = 8388608, 5
+LARGE_SOURCES = [[0.25, 0.25, 0.25], [0.75, 0.75, 0.25], [0.25, 0.75, 0.75], [0.75, 0.25, 0.75]]
+
+
+def large_leg(em, steps: int, with_oracle: bool):
+    """The largest single-GPU job: 8,388,608 log-normal particles, their device-built Voronoi cells, the
+    full-resolution mapping in both precisions (mixed vs FP64 over every cell), the oracle on a seeded 1 % of
+    the cells (all their pairs) and on S_a of 8,000 particles, and the pseudo variant with four sources mapped
+    in mixed precision and checked by the oracle over every cell."""
+    import torch
+    import oracle
+    import synth
+
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    print(f"bench: generating the {LARGE_N:,}-particle log-normal cloud", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    p = synth.particles("lognormal", LARGE_N, LARGE_SEED)
+    gen_s = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    mp = em.Mapper(device=0, precision=em.MAP_MIXED)
+    xyz, m, h = t(p.xyz), t(p.m), t(p.h)
+    G = em.map_voronoi(mp.ctx, xyz, synth.BOX, 0, device=True)
+    torch.cuda.synchronize()
+    nc = G.n_cells
+    res = {"workload": f"lognormal-{LARGE_N}: log-normal density (sigma_ln 1.5, P(k) ~ k^-4, 256^3 mesh, seed "
+                       f"{LARGE_SEED}), h from 58 neighbours; box-clipped Voronoi cells of the particles built on "
+                       f"the device; pseudo variant with 4 sources",
+           "particles": p.n, "cells": nc, "walls": int(G.face_plane.shape[0]),
+           "wall_vertex_slots": int(G.face_vert.shape[0]), "host_generation_s": gen_s, "ms_voronoi": G.ms}
+    M = torch.zeros(nc, dtype=torch.float64, device=dev)
+    Ms = {}
+    for prec, name, k in ((em.MAP_MIXED, "mixed", steps), (em.MAP_FP64, "fp64", 1)):
+        mp.set_precision(prec)
+        em.map_particles(mp.ctx, xyz, m, h, G, M)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [em.map_particles(mp.ctx, xyz, m, h, G, M) for _ in range(k)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / k
+        st = sts[-1]
+        Ms[name] = M.cpu().numpy().copy()
+        res[name] = {"pairs": st["n_pairs"], "pairs_per_s": st["n_pairs"] / dt, "ms_per_step": 1e3 * dt,
+                     "ms_integrate": float(np.mean([x["ms_integrate"] for x in sts])),
+                     "stages_ms": {q: float(np.mean([x[q] for x in sts]))
+                                   for q in ("ms_setup", "ms_pairs", "ms_integrate", "ms_fixup", "ms_reduce")},
+                     "mass_rel_err": abs(st["mass_out"] - st["mass_in"]) / st["mass_in"],
+                     "n_fixup_terms": st["n_fixup_terms"], "n_fp64_cells": st["n_fp64_cells"],
+                     "n_candidates": st["n_candidates"]}
+        print(f"bench: large {name}: {res[name]}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    res["device_bytes_in_use"] = int(free0 - torch.cuda.mem_get_info()[0])
+    rel = np.abs(Ms["mixed"] - Ms["fp64"]) / Ms["fp64"]
+    res["mixed_vs_fp64_max_cell_rel"] = float(rel.max())
+    res["mixed_vs_fp64_mean_cell_rel"] = float(rel.mean())
+    res["speedup_mixed_vs_fp64"] = res["mixed"]["pairs_per_s"] / res["fp64"]["pairs_per_s"]
+    if with_oracle:
+        mp.set_precision(em.MAP_MIXED)
+        npairs = res["mixed"]["pairs"]
+        F = torch.empty(npairs, dtype=torch.float64, device=dev)
+        PP = torch.empty(npairs, dtype=torch.int32, device=dev)
+        PC = torch.empty(npairs, dtype=torch.int32, device=dev)
+        S = torch.zeros(p.n, dtype=torch.float64, device=dev)
+        em.map_particles(mp.ctx, xyz, m, h, G, cell_mass=M, frac_sum_raw=S, pair_frac=F, pair_p=PP, pair_c=PC)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rng = np.random.default_rng(2025)
+        sel = np.sort(rng.choice(nc, nc // 100, replace=False))
+        cells = synth.cells_from(G)
+        sub = synth.cells_subset(cells, sel)
+        op, oc_local = oracle.pairs(p.xyz, p.h, sub)
+        lut = torch.zeros(nc, dtype=torch.bool, device=dev)
+        lut[t(sel)] = True
+        mask = lut[PC.long()]
+        gp, gc, gf = PP[mask].cpu().numpy(), PC[mask].cpu().numpy(), F[mask].cpu().numpy()
+        o_ord = np.lexsort((op, sel[oc_local]))
+        same = bool(np.array_equal(gp, op[o_ord]) and np.array_equal(gc, sel[oc_local][o_ord]))
+        fo = oracle.pair_fractions(p.xyz, p.h, sub, op, oc_local)[o_ord] if same else None
+        ocell = {"cells": int(sel.size), "pairs": int(op.size), "pair_sets_equal": same}
+        if same:
+            idx = np.searchsorted(sel, gc)
+            raw_g = np.bincount(idx, weights=p.m[gp] * gf, minlength=sel.size)
+            raw_o = np.bincount(idx, weights=p.m[gp] * fo, minlength=sel.size)
+            Sg = S.cpu().numpy()
+            Mo = np.bincount(idx, weights=p.m[gp] * fo / Sg[gp], minlength=sel.size)
+            ocell.update(max_abs_pair_frac_err=float(np.abs(gf - fo).max()),
+                         max_rel_raw_cell_sum=float((np.abs(raw_g - raw_o) / raw_o).max()),
+                         max_rel_cell_mass=float((np.abs(M.cpu().numpy()[sel] - Mo) / Mo).max()))
+            psel = np.sort(rng.choice(p.n, 8000, replace=False))
+            qp, qc = oracle.pairs(p.xyz[psel], p.h[psel], cells)
+            fq = oracle.pair_fractions(p.xyz[psel], p.h[psel], cells, qp, qc)
+            So = np.bincount(qp, weights=fq, minlength=psel.size)
+            plut = torch.zeros(p.n, dtype=torch.bool, device=dev)
+            plut[t(psel)] = True
+            ocell["S_sample"] = {"particles": int(psel.size), "pairs": int(qp.size),
+                                 "pair_counts_equal": int(plut[PP.long()].sum()) == int(qp.size),
+                                 "max_abs_S_err": float(np.abs(Sg[psel] - So).max())}
+        ocell["oracle_s"] = time.perf_counter() - t0
+        res["oracle_sample"] = ocell
+        del F, PP, PC, S, lut, mask
+        print(f"bench: large oracle sample: {ocell}", file=sys.stderr, flush=True)
+    # pseudo variant
+    n = p.n
+    out = dict(xyz=torch.zeros((n, 3), dtype=torch.float64, device=dev),
+               m=torch.zeros(n, dtype=torch.float64, device=dev), h=torch.zeros(n, dtype=torch.float64, device=dev),
+               size=torch.zeros(n, dtype=torch.float64, device=dev),
+               kind=torch.zeros(n, dtype=torch.int32, device=dev), ref=torch.zeros(n, dtype=torch.int64, device=dev))
+    par = dict(theta=0.5, r_part=0.05, r_leaf=0.1, leaf_size=8, h_fact_node=1.1)
+    em.map_pseudo(mp.ctx, xyz, m, h, synth.BOX, LARGE_SOURCES, out=out, **par)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = em.map_pseudo(mp.ctx, xyz, m, h, synth.BOX, LARGE_SOURCES, out=out, **par)
+    torch.cuda.synchronize()
+    ms_front = 1e3 * (time.perf_counter() - t0)
+    qx, qm, qh = r["xyz"].contiguous(), r["m"].contiguous(), r["h"].contiguous()
+    Gq = em.map_voronoi(mp.ctx, qx, synth.BOX, 0, device=True)
+    mp.set_precision(em.MAP_MIXED)
+    Mq = torch.zeros(Gq.n_cells, dtype=torch.float64, device=dev)
+    em.map_particles(mp.ctx, qx, qm, qh, Gq, Mq)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stq = em.map_particles(mp.ctx, qx, qm, qh, Gq, Mq)
+    torch.cuda.synchronize()
+    dq = time.perf_counter() - t0
+    ps = {"sources": LARGE_SOURCES, "pseudo": int(qm.shape[0]), "pseudo_nodes": r["stats"]["n_pseudo_nodes"],
+          "ms_front_end": ms_front, "ms_voronoi": Gq.ms, "pairs": stq["n_pairs"], "ms_map": 1e3 * dq,
+          "pairs_per_s": stq["n_pairs"] / dq, "mass_rel_err": abs(stq["mass_out"] - stq["mass_in"]) / stq["mass_in"]}
+    if with_oracle:
+        q = synth.Particles(qx.cpu().numpy(), qm.cpu().numpy(), qh.cpu().numpy())
+        O = oracle.map_particles(q, synth.cells_from(Gq))
+        ps["oracle_all_cells"] = {"pairs_equal_count": int(O["pair_p"].size) == int(stq["n_pairs"]),
+                                  "max_cell_rel": float((np.abs(Mq.cpu().numpy() - O["M"]) / O["M"]).max())}
+    res["pseudo_variant"] = ps
+    del out, r
+    mp.close()
+    return res
+
+
 def adaptive_leg(em, mp, xyz, m, h, src, par):
     """Adaptive walk (Sec. III-B, Eq. (6), K = 100) on the same cloud, driven by an ionised sphere (radius
     0.15, linear rise to neutral over 0.05) standing in for the radiative transfer: a first step from no
@@ -415,6 +554,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-pseudo", action="store_true", help="skip the pseudo-particle leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-mapping leg")
+    ap.add_argument("--no-large", action="store_true", help="skip the 8,388,608-particle job")
     ap.add_argument("--quick", action="store_true",
                     help="only the FP64 and mixed steps of the main workload (for profiling runs)")
     ap.add_argument("--mixed-shape", default=None,
@@ -502,6 +642,9 @@ def main():
     if not args.quick and not args.no_pseudo:
         extra["pseudo_path"] = pseudo_leg(em, args.steps, args.warmup)
         print(f"bench: pseudo path: {extra['pseudo_path']}", file=sys.stderr, flush=True)
+    if not args.quick and not args.no_large:
+        extra["large_job"] = large_leg(em, 2, not args.no_cpu_baseline)
+        print(f"bench: large job: {extra['large_job']}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline and not args.quick:
         print("bench: timing the oracle on a cell sample", file=sys.stderr, flush=True)

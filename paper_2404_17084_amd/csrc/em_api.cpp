@@ -560,6 +560,8 @@ int map_voronoi(map_ctx *h, int64_t n, const double *sites, int mem_kind, const 
         EM_HIP(hipEventSynchronize(C->ev[1]));
         float ms = 0.f;
         EM_HIP(hipEventElapsedTime(&ms, C->ev[0], C->ev[1]));
+        // the per-cell working records of the build (about 6.7 kB per cell) are not kept
+        C->ws.drop(S_VOR8);
         for (int d = 0; d < 6; d++) C->vor_box[d] = box[d];
         out->n_cells = m;
         out->n_faces = V.n_faces;

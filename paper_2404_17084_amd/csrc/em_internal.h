@@ -53,6 +53,8 @@ public:
     T *get(int slot, size_t count) { return static_cast<T *>(get(slot, count * sizeof(T))); }
     size_t bytes_held() const;
     void release();
+    // frees one slot's buffer (not in arena mode, where it stays reserved)
+    void drop(int slot);
     void use_arena(void *base, size_t bytes);
     // Stream-ordered mode: buffers come from the device's memory pool with
     // hipMallocAsync / hipFreeAsync on stream s (no device-wide

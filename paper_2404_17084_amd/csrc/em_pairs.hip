@@ -548,9 +548,10 @@ PairSet build_pairs(Workspace &ws, const DevInputs &in, const double *aabb, cons
     int64_t *ncount = ws.get<int64_t>(S_NCNT, (size_t)nc);
     int64_t *noffs = ws.get<int64_t>(S_NOFF, (size_t)(nc + 1));
     int64_t *qcount = ws.get<int64_t>(S_QCNT, (size_t)nc);
-    // candidate slots per cell: at most 2^28 in all, and in arena mode at most
-    // a quarter of the free scratch (cells with more candidates walk again)
-    const int64_t slot_cap = std::min<int64_t>(int64_t(1) << 28, (int64_t)std::min<size_t>(ws.arena_free() / 16, size_t(1) << 40));
+    // candidate slots per cell: at most 2^30 in all (4 GiB; 128 per cell at
+    // 8.4 million cells), and in arena mode at most a quarter of the free
+    // scratch (cells with more candidates walk again)
+    const int64_t slot_cap = std::min<int64_t>(int64_t(1) << 30, (int64_t)std::min<size_t>(ws.arena_free() / 16, size_t(1) << 40));
     const int K = (int)std::max<int64_t>(32, std::min<int64_t>(512, slot_cap / nc));
     uint32_t *cbuf = ws.get<uint32_t>(S_CAND_BUF, (size_t)(nc * K));
     unsigned *cmax = ws.get<unsigned>(S_CAND_MAX, 64);

@@ -1,5 +1,6 @@
 // Device primitives: device memory pool, exclusive scan of counts and a
 // stable LSD radix sort (keys with 32-bit values), all written for wave64.
+#include <algorithm>
 #include <chrono>
 #include <thread>
 
@@ -43,6 +44,17 @@ void Workspace::release()
         }
 }
 
+void Workspace::drop(int slot)
+{
+    if (arena_base_ || slot < 0 || slot >= (int)bufs_.size()) return;
+    Buf &b = bufs_[slot];
+    if (!b.p) return;
+    if (stream_) (void)hipFreeAsync(b.p, stream_);
+    else (void)hipFree(b.p);
+    held_.fetch_sub(b.cap);
+    b = Buf();
+}
+
 void *Workspace::get(int slot, size_t bytes)
 {
     if (slot < 0 || slot >= (int)bufs_.size()) throw Error{MAP_EINVAL, "workspace slot out of range"};
@@ -69,7 +81,8 @@ void *Workspace::get(int slot, size_t bytes)
         held_.fetch_sub(b.cap);
         b.p = nullptr;
         b.cap = 0;
-        size_t want = bytes + bytes / 4 + 256;
+        // growth slack: a quarter, at most 256 MiB (buffers of tens of GB are not padded by a quarter)
+        size_t want = bytes + std::min(bytes / 4, size_t(256) << 20) + 256;
         want = (want + 255) & ~size_t(255);
         hipError_t e = stream_ ? hipMallocAsync(&b.p, want, stream_) : hipMalloc(&b.p, want);
         if (e != hipSuccess) {

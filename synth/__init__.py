@@ -121,6 +121,42 @@ class Cells:
         return self.verts[sorted(set(ids))]
 
 
+def cells_subset(cells: Cells, sel) -> Cells:
+    """The selected cells alone, in selection order (cell t of the result is cell sel[t]).
+
+    Faces, their vertex lists and planes are gathered; the vertex array is kept
+    whole (face_vert still indexes it).  Used to run a pair search over a sample
+    of the cells of a large grid.
+    """
+    sel = np.asarray(sel, dtype=np.int64)
+    cfo = np.asarray(cells.cell_face_off, dtype=np.int64)
+    fvo = np.asarray(cells.face_vert_off, dtype=np.int64)
+    nf = cfo[sel + 1] - cfo[sel]
+    new_cfo = np.zeros(sel.size + 1, np.int64)
+    np.cumsum(nf, out=new_cfo[1:])
+    faces = np.repeat(cfo[sel], nf) + (np.arange(new_cfo[-1]) - np.repeat(new_cfo[:-1], nf))
+    nv = fvo[faces + 1] - fvo[faces]
+    new_fvo = np.zeros(faces.size + 1, np.int64)
+    np.cumsum(nv, out=new_fvo[1:])
+    slots = np.repeat(fvo[faces], nv) + (np.arange(new_fvo[-1]) - np.repeat(new_fvo[:-1], nv))
+    face_nb = np.asarray(cells.face_nb)[faces] if cells.face_nb is not None else np.zeros(faces.size, np.int64)
+    return Cells(new_cfo, new_fvo, np.ascontiguousarray(np.asarray(cells.face_vert)[slots]),
+                 np.ascontiguousarray(np.asarray(cells.face_plane)[faces]), np.ascontiguousarray(face_nb),
+                 np.asarray(cells.verts), np.ascontiguousarray(np.asarray(cells.cell_volume)[sel]),
+                 tuple(cells.box))
+
+
+def cells_from(obj) -> Cells:
+    """A Cells on the host from any object with the same fields (numpy arrays or torch tensors)."""
+    def host(a):
+        if a is None:
+            return None
+        return a.detach().cpu().numpy() if hasattr(a, "detach") else np.asarray(a)
+
+    return Cells(host(obj.cell_face_off), host(obj.face_vert_off), host(obj.face_vert), host(obj.face_plane),
+                 host(getattr(obj, "face_nb", None)), host(obj.verts), host(obj.cell_volume), tuple(obj.box))
+
+
 # --------------------------------------------------------------------------
 # positions
 # --------------------------------------------------------------------------
