@@ -139,14 +139,19 @@ __constant__ float kGLw[4] = {0.3626837833783620f, 0.3137066458778873f, 0.222381
 
 __device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// shell piece by Gauss-Legendre:  pi r0 R0 int_a^b D_shell(R0^2 + l^2) dl,  a < b
+// shell piece by Gauss-Legendre:  pi r0 R0 int_a^b D_shell(R0^2 + l^2) dl,  a < b.
+// 8 points per sub-interval, sub-intervals at most 0.8 dsing long (dsing: a
+// lower bound of the distance from the part to the integrand's branch points
+// l = +-ic), so the branch points stay outside the Bernstein ellipse of
+// parameter 2.5 + sqrt(7.25) of every sub-interval and the truncation is far
+// below the FP32 rounding of the term.
 __device__ __forceinline__ float shell_quad(float r0, float R0, float c2, float dsing, float a, float b, Work &wk)
 {
     const float V = 2.0f - r0;
     const float V2 = V * V, V4 = V2 * V2, V5 = V4 * V;
     const float rp1 = r0 + 1.0f;
     const float len = b - a;
-    int nsub = (int)ceilf(len * rcp32(1.5f * dsing));
+    int nsub = (int)ceilf(len * rcp32(0.8f * dsing));
     nsub = nsub < 1 ? 1 : (nsub > 8 ? 8 : nsub);
     const float hl = 0.5f * len * rcp_f32((float)nsub);
     float tot = 0.0f;
@@ -551,7 +556,7 @@ __device__ __forceinline__ int64_t next_tile_xcd(unsigned *ctr, int64_t ntiles, 
 // ---------------------------------------------------------------- queued tasks (mixed path)
 // The edge terms split into independent tasks of three kinds: angles (one
 // atan2), closed-form points (one trans + core) and shell quadrature
-// sub-intervals (8 Gauss-Legendre points).  In a wavefront of 64 pairs most
+// sub-intervals (4 Gauss-Legendre points each, see run_quad).  In a wavefront of 64 pairs most
 // lanes need only a few of the possible tasks at a given edge, so running
 // every kind whenever any lane needs it leaves most lanes idle.  Here each
 // lane classifies its edge and pushes its tasks, with their weights and the
@@ -638,9 +643,11 @@ __constant__ float kGL4w[2] = {0.6521451548625461f, 0.3478548451374538f};
 
 // One sub-interval of the shell integrand (the integrand of shell_quad) by
 // 4-point Gauss-Legendre.  Sub-intervals are at most 0.4 times the distance
-// to the integrand's branch points l = +-ic long: measured truncation below
-// 1.5e-9 of the pair fraction per sub-interval, under the FP32 rounding of
-// the term.
+// to the integrand's branch points l = +-ic long (and at most 2 - r0), so
+// the branch points lie outside the Bernstein ellipse of parameter
+// 5 + sqrt(26) of every sub-interval; the Gauss-Legendre error theorem for
+// analytic integrands then bounds the truncation by 1e-8 of the pair fraction
+// per sub-interval over the whole (r0, c) range (measured: below 3e-10).
 __device__ __forceinline__ void run_quad(WaveStacks &W, int i, Work &wk)
 {
     const float r0 = W.qd[0][i], sR0 = W.qd[1][i], mid = W.qd[2][i], hl = W.qd[3][i];
