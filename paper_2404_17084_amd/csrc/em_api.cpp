@@ -246,28 +246,25 @@ int64_t stage_finish(Ctx &C, Workspace &ws, JobState &js, const map_out *out, hi
         }
     }
     if (js.ev_fix) EM_HIP(hipEventRecord(js.ev_fix, s));
-    double *S = ws.get<double>(S_S, (size_t)(in.n > 0 ? in.n : 1));
-    double *M = ws.get<double>(S_MCELL, (size_t)(in.n_cells > 0 ? in.n_cells : 1));
-    double *rho = ws.get<double>(S_RHO, (size_t)(in.n_cells > 0 ? in.n_cells : 1));
-    double *red = ws.get<double>(S_RED, 16 + 4 * 256);
-    EM_HIP(hipMemcpyAsync(red + 4, in.box, sizeof(double) * 6, hipMemcpyHostToDevice, s));
-    launch_reduce(in, ps, f, S, M, rho, red, js.flags, s);
     int64_t n_cells_fp64 = 0;
     if (js.err && np > 0 && C.config.cell_tol >= 0.0) {
         // cells whose estimated FP32 error exceeds the budget: their pairs again in FP64
         const double tol = C.config.cell_tol > 0.0 ? C.config.cell_tol : kDefaultCellTol;
         unsigned *cnt = reinterpret_cast<unsigned *>(ws.get<uint32_t>(S_CHECK, (size_t)in.n_cells + 64));
         uint32_t *list = reinterpret_cast<uint32_t *>(cnt) + 64;
-        launch_cell_check(in, ps, js.err, S, M, tol, cnt, list, in.n_cells, s);
+        launch_cell_check(in, ps, js.err, f, tol, cnt, list, in.n_cells, s);
         unsigned hc = 0;
         EM_HIP(hipMemcpyAsync(&hc, cnt, sizeof(unsigned), hipMemcpyDeviceToHost, s));
         stream_sync(s);
         n_cells_fp64 = hc;
-        if (hc > 0) {
-            launch_recompute_cells(in, js.edges, ps, list, (int64_t)hc, f, js.counters, s);
-            launch_reduce(in, ps, f, S, M, rho, red, js.flags, s);
-        }
+        if (hc > 0) launch_recompute_cells(in, js.edges, ps, list, (int64_t)hc, f, js.counters, s);
     }
+    double *S = ws.get<double>(S_S, (size_t)(in.n > 0 ? in.n : 1));
+    double *M = ws.get<double>(S_MCELL, (size_t)(in.n_cells > 0 ? in.n_cells : 1));
+    double *rho = ws.get<double>(S_RHO, (size_t)(in.n_cells > 0 ? in.n_cells : 1));
+    double *red = ws.get<double>(S_RED, 16 + 4 * 256);
+    EM_HIP(hipMemcpyAsync(red + 4, in.box, sizeof(double) * 6, hipMemcpyHostToDevice, s));
+    launch_reduce(in, ps, f, S, M, rho, red, js.flags, s);
     if (js.ev_reduce) EM_HIP(hipEventRecord(js.ev_reduce, s));
 
     // outputs

@@ -23,7 +23,8 @@ __device__ __forceinline__ float rcp_f32(float x) { return __builtin_amdgcn_rcpf
 __device__ __forceinline__ float atan2_f32(float y, float x)
 {
     const float ax = fabsf(x);
-    const float mn = fminf(ax, y), mx = fmaxf(ax, y);
+    const bool steep = y > ax;  // selects instead of fminf/fmaxf (no NaN handling needed here)
+    const float mn = steep ? ax : y, mx = steep ? y : ax;
     const float t = mx > 0.0f ? mn * rcp_f32(mx) : 0.0f;
     const float z = t * t;
     float p = 0.0028501402121037245f;
@@ -36,7 +37,7 @@ __device__ __forceinline__ float atan2_f32(float y, float x)
     p = fmaf(p, z, -0.33333075046539307f);
     p = fmaf(p, z, 1.0f);
     float r = t * p;
-    r = y > ax ? 1.5707963267948966f - r : r;
+    r = steep ? 1.5707963267948966f - r : r;
     return x < 0.0f ? 3.141592653589793f - r : r;
 }
 

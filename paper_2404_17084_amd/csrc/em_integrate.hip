@@ -766,10 +766,12 @@ __device__ __forceinline__ void mixed_edge_step(WaveStacks &W, int lane, Work &w
     const float l2 = near ? sqrt_f32(4.0f - c2) : 0.0f;
     const float l1 = has_inner ? sqrt_f32(1.0f - c2) : 0.0f;
     const float c = near && !has_inner ? sqrt_f32(c2) : 1.0f;
-    const float ca = fminf(fmaxf(-l2, la), lb);
-    const float cb = fminf(fmaxf(l2, ca), lb);
-    const float ia = has_inner ? fminf(fmaxf(-l1, ca), cb) : cb;
-    const float ib = has_inner ? fminf(fmaxf(l1, ia), cb) : cb;
+    // clamps as medians of three (la <= lb, so min(max(x, lo), hi) is the
+    // median of x, lo and hi also when lo > hi: one instruction each)
+    const float ca = __builtin_amdgcn_fmed3f(la, -l2, lb);
+    const float cb = __builtin_amdgcn_fmed3f(ca, l2, lb);
+    const float ia = has_inner ? __builtin_amdgcn_fmed3f(ca, -l1, cb) : cb;
+    const float ib = has_inner ? __builtin_amdgcn_fmed3f(ia, l1, cb) : cb;
     if (near) wk.eterms++;
     // angle terms: -H times the beyond parts' angle, dH times the shell
     // parts' angle.  The angle of two parts is the argument of the product of
@@ -978,10 +980,9 @@ __global__ void __launch_bounds__(256, WPE) k_integrate_queued(JobsArg A, unsign
 // both piece weights.
 struct WaveStacks64 {
     double ang[4][kQ];  // R0, a, b, weight
-    int ang_o[kQ];
     double pnt[8][kQ];  // r0, R0, c2, c, x, S, inner weight, shell weight
-    int pnt_o[kQ];
     double acc[64];
+    uint8_t ang_o[kQ], pnt_o[kQ];  // owner lanes
 };
 
 template <int KIND>
@@ -1016,8 +1017,11 @@ __device__ __forceinline__ void run_stack64(WaveStacks64 &W, int &count, int lan
     }
 }
 
-template <bool MULTI>
-__global__ void __launch_bounds__(256, 2) k_integrate_queued64(JobsArg A, unsigned *tile_ctr)
+// WPE: resident wavefronts per SIMD the register budget is cut for (2: no
+// spills; 3: the LDS stacks of three workgroups fit a compute unit, at the
+// price of a few spilled registers)
+template <int WPE, bool MULTI>
+__global__ void __launch_bounds__(256, WPE) k_integrate_queued64(JobsArg A, unsigned *tile_ctr)
 {
     __shared__ WaveStacks64 stacks[4];
     const int lane = threadIdx.x & 63;
@@ -1164,7 +1168,7 @@ __global__ void __launch_bounds__(256, 2) k_integrate_queued64(JobsArg A, unsign
                     W.ang[1][slot] = aa[q];
                     W.ang[2][slot] = ab[q];
                     W.ang[3][slot] = sg * aw[q];
-                    W.ang_o[slot] = lane;
+                    W.ang_o[slot] = (uint8_t)lane;
                 }
                 run_stack64<0>(W, nA, lane, false, wk);
             }
@@ -1184,7 +1188,7 @@ __global__ void __launch_bounds__(256, 2) k_integrate_queued64(JobsArg A, unsign
                         W.pnt[5][slot] = q == 2 ? 1.0 : (x == l2 ? 2.0 : sqrt(c2 + x * x));
                         W.pnt[6][slot] = sg * wi[q];
                         W.pnt[7][slot] = sg * wsh[q];
-                        W.pnt_o[slot] = lane;
+                        W.pnt_o[slot] = (uint8_t)lane;
                     }
                     run_stack64<1>(W, nP, lane, false, wk);
                 }
@@ -1387,18 +1391,20 @@ __global__ void k_recompute_cells(int64_t n_list, const uint32_t *__restrict__ c
                                   const EdgeRec *__restrict__ edges, double *__restrict__ f,
                                   unsigned long long *counters)
 {
-    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
+    // one workgroup of 256 per listed cell: the pairs of a cell are done in one
+    // round (about 125 per cell), the FP64 closed forms' latency spread over
+    // four wavefronts
+    const int64_t q = blockIdx.x;
     if (q >= n_list) return;
     const int64_t c = cells[q];
     Work wk;
-    for (int64_t k = coff[c] + lane; k < coff[c + 1]; k += 64) {
+    for (int64_t k = coff[c] + threadIdx.x; k < coff[c + 1]; k += blockDim.x) {
         const int64_t a = pair_p[k];
         float ev = 0.0f;
         f[k] = pair_fraction<MAP_FP64>(xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2], h[a], c, cfo, fvo, plane, edges, wk,
                                        (uint64_t)k, nullptr, nullptr, 0u, ev);
     }
-    if (lane == 0) atomicAdd(counters + C_FP64_PAIRS, (unsigned long long)(coff[c + 1] - coff[c]));
+    if (threadIdx.x == 0) atomicAdd(counters + C_FP64_PAIRS, (unsigned long long)(coff[c + 1] - coff[c]));
 }
 
 void launch_table_build(int n0, int n1, int n2, double *tab64, float *tab32, hipStream_t s)
@@ -1458,9 +1464,12 @@ static void launch_queued(const IntJob *h_jobs, const IntJob *d_jobs, int n_jobs
     if (g < 1) g = 1;
     const bool multi = n_jobs > 1;
 #define EM_LAUNCH_Q(...) hipLaunchKernelGGL((__VA_ARGS__), dim3((unsigned)g), dim3(block), 0, s, A, tile_ctr)
-    if (precision == MAP_FP64) {
-        if (multi) EM_LAUNCH_Q(k_integrate_queued64<true>);
-        else EM_LAUNCH_Q(k_integrate_queued64<false>);
+    if (precision == MAP_FP64 && tune.waves >= 3) {
+        if (multi) EM_LAUNCH_Q(k_integrate_queued64<3, true>);
+        else EM_LAUNCH_Q(k_integrate_queued64<3, false>);
+    } else if (precision == MAP_FP64) {
+        if (multi) EM_LAUNCH_Q(k_integrate_queued64<2, true>);
+        else EM_LAUNCH_Q(k_integrate_queued64<2, false>);
     } else if (tune.waves >= 6 || tune.waves <= 0) {
         if (multi) EM_LAUNCH_Q(k_integrate_queued<6, true>);
         else EM_LAUNCH_Q(k_integrate_queued<6, false>);
@@ -1571,7 +1580,7 @@ void launch_recompute_cells(const DevInputs &in, const EdgeRec *edges, const Pai
                             int64_t n_cells, double *f, int64_t *counters, hipStream_t s)
 {
     if (n_cells <= 0) return;
-    hipLaunchKernelGGL(k_recompute_cells, dim3((unsigned)((n_cells * 64 + 255) / 256)), dim3(256), 0, s, n_cells,
+    hipLaunchKernelGGL(k_recompute_cells, dim3((unsigned)n_cells), dim3(256), 0, s, n_cells,
                        cells, ps.coff, ps.pair_p, in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f,
                        reinterpret_cast<unsigned long long *>(counters));
     EM_HIP(hipGetLastError());

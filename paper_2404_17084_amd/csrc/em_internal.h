@@ -326,10 +326,11 @@ void free_voronoi(VorGrid &V);
 // em_reduce.hip
 void launch_reduce(const DevInputs &in, const PairSet &ps, const double *f, double *S, double *M,
                    double *rho, double *red, unsigned *flags, hipStream_t s);
-// Mixed path: lists the cells whose estimated FP32 error, sqrt(sum over their
-// pairs of (m_a err_ai / S_a)^2), exceeds tol |M_i| (count in *count, at most
-// cap cells listed; count may exceed cap).
-void launch_cell_check(const DevInputs &in, const PairSet &ps, const float *err, const double *S, const double *M,
-                       double tol, unsigned *count, uint32_t *list, int64_t cap, hipStream_t s);
+// Mixed path, before the reduction: lists the cells whose estimated FP32
+// error, sqrt(sum over their pairs of (m_a err_ai)^2), exceeds tol times their
+// raw mass |sum m_a f_ai| (count in *count, at most cap cells listed; count
+// may exceed cap).
+void launch_cell_check(const DevInputs &in, const PairSet &ps, const float *err, const double *f, double tol,
+                       unsigned *count, uint32_t *list, int64_t cap, hipStream_t s);
 
 }  // namespace em

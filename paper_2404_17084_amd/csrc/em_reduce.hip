@@ -82,26 +82,27 @@ __global__ void k_cell_mass(int64_t nc, const int64_t *coff, const uint32_t *pai
     }
 }
 
-// Mixed path: one wavefront per cell, sqrt(sum (m_a err_ai / S_a)^2) against
-// tol |M_i|; the cells over the budget are listed.
+// Mixed path, before the normalisation: one wavefront per cell,
+// sqrt(sum (m_a err_ai)^2) against tol |sum m_a f_ai| (the cell's estimated
+// FP32 error relative to its raw mass; the sum-to-one normalisation divides
+// both by S_a, close to one); the cells over the budget are listed.
 __global__ void k_cell_check(int64_t nc, const int64_t *coff, const uint32_t *pair_p, const float *err,
-                             const double *S, const double *m, const double *M, double tol, unsigned *count,
-                             uint32_t *list, int64_t cap)
+                             const double *f, const double *m, double tol, unsigned *count, uint32_t *list,
+                             int64_t cap)
 {
     const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (i >= nc) return;
-    double v = 0.0;
+    double v = 0.0, raw = 0.0;
     for (int64_t k = coff[i] + lane; k < coff[i + 1]; k += 64) {
-        const uint32_t a = pair_p[k];
-        const double sa = S[a];
-        if (sa > 0.0) {
-            const double e = m[a] * (double)err[k] / sa;
-            v += e * e;
-        }
+        const double ma = m[pair_p[k]];
+        const double e = ma * (double)err[k];
+        v += e * e;
+        raw += ma * f[k];
     }
     v = wave_sum(v);
-    if (lane == 0 && sqrt(v) > tol * fabs(M[i])) {
+    raw = wave_sum(raw);
+    if (lane == 0 && sqrt(v) > tol * fabs(raw)) {
         const unsigned q = atomicAdd(count, 1u);
         if ((int64_t)q < cap) list[q] = (uint32_t)i;
     }
@@ -185,14 +186,14 @@ void launch_map_back(int64_t n, const int64_t *poff, const uint32_t *perm, const
     EM_HIP(hipGetLastError());
 }
 
-void launch_cell_check(const DevInputs &in, const PairSet &ps, const float *err, const double *S, const double *M,
-                       double tol, unsigned *count, uint32_t *list, int64_t cap, hipStream_t s)
+void launch_cell_check(const DevInputs &in, const PairSet &ps, const float *err, const double *f, double tol,
+                       unsigned *count, uint32_t *list, int64_t cap, hipStream_t s)
 {
     const int64_t nc = in.n_cells;
     fill_zero_bytes(count, sizeof(unsigned), s);
     if (nc <= 0 || ps.n_pairs <= 0) return;
     hipLaunchKernelGGL(k_cell_check, dim3((unsigned)((nc * 64 + 255) / 256)), dim3(256), 0, s, nc, ps.coff, ps.pair_p,
-                       err, S, in.m, M, tol, count, list, cap);
+                       err, f, in.m, tol, count, list, cap);
     EM_HIP(hipGetLastError());
 }
 

@@ -20,7 +20,7 @@ namespace em {
 
 // Untuned shape: task batches (distribution 3) for both precisions, with the
 // register budgets and workgroup counts measured fastest on MI355X for the
-// 262,144-particle clumpy workload (FP64: 2 waves per SIMD, 4 workgroups per
+// 262,144-particle clumpy workload (FP64: 3 waves per SIMD, 4 workgroups per
 // CU; mixed: 6 and 6).
 IntegrateTune default_tune(int precision)
 {
@@ -28,7 +28,7 @@ IntegrateTune default_tune(int precision)
     t.persistent = 3;
     t.tile_waves = 1;
     t.grid_per_cu = precision == MAP_FP64 ? 4 : 6;
-    t.waves = precision == MAP_FP64 ? 2 : 6;
+    t.waves = precision == MAP_FP64 ? 3 : 6;
     return t;
 }
 
