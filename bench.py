@@ -32,13 +32,15 @@ sys.path.insert(0, ROOT)
 # reported beside the model below for comparison.
 FLOP_FACE, FLOP_EDGE, FLOP_ETERM, FLOP_MOMENT, FLOP_QPOINT, FLOP_ANGLE = 7, 19, 8, 66, 31, 6
 
-# HBM bytes per launch of the mixed integration kernel and its measured VALU counters, valid only for the
-# kernel source they were measured on (profiles/traffic_integrate_queued_clumps262144.md,
-# profiles/valu_integrate_queued_clumps262144.md); null once the source has changed.
+# HBM bytes per launch of the mixed integration kernel (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy) and
+# its measured VALU FLOPs (the SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F32/F64 counters, 64 lanes per instruction,
+# FMA = 2), valid only for the kernel source they were measured on
+# (profiles/traffic_integrate_queued_clumps262144.md, profiles/valu_integrate_queued_clumps262144.md); null
+# once the source has changed.
 COUNTER_SOURCE = "paper_2404_17084_amd/csrc/em_integrate.hip"
-COUNTER_SHA256_PREFIX = None
-TRAFFIC_BYTES = None
-VALU_FLOPS_PER_LAUNCH = None
+COUNTER_SHA256_PREFIX = "156ce6bfcba6938a"
+TRAFFIC_BYTES = 2.636e9
+VALU_FLOPS_PER_LAUNCH = 5.581e11
 
 PEAK_FP64 = 78.6   # TFLOP/s, MI355X FP64 vector
 PEAK_FP32 = 157.3  # TFLOP/s, MI355X FP32 vector (packed)
