@@ -350,6 +350,7 @@ def large_leg(em, steps: int, with_oracle: bool):
         sel = np.sort(rng.choice(nc, nc // 100, replace=False))
         cells = synth.cells_from(G)
         sub = synth.cells_subset(cells, sel)
+        print(f"bench: large oracle sample: pairs of {sel.size} cells", file=sys.stderr, flush=True)
         op, oc_local = oracle.pairs(p.xyz, p.h, sub)
         lut = torch.zeros(nc, dtype=torch.bool, device=dev)
         lut[t(sel)] = True
@@ -369,6 +370,7 @@ def large_leg(em, steps: int, with_oracle: bool):
                          max_rel_raw_cell_sum=float((np.abs(raw_g - raw_o) / raw_o).max()),
                          max_rel_cell_mass=float((np.abs(M.cpu().numpy()[sel] - Mo) / Mo).max()))
             psel = np.sort(rng.choice(p.n, 8000, replace=False))
+            print(f"bench: large oracle sample: S_a of {psel.size} particles", file=sys.stderr, flush=True)
             qp, qc = oracle.pairs(p.xyz[psel], p.h[psel], cells)
             fq = oracle.pair_fractions(p.xyz[psel], p.h[psel], cells, qp, qc)
             So = np.bincount(qp, weights=fq, minlength=psel.size)
@@ -408,6 +410,7 @@ def large_leg(em, steps: int, with_oracle: bool):
           "ms_front_end": ms_front, "ms_voronoi": Gq.ms, "pairs": stq["n_pairs"], "ms_map": 1e3 * dq,
           "pairs_per_s": stq["n_pairs"] / dq, "mass_rel_err": abs(stq["mass_out"] - stq["mass_in"]) / stq["mass_in"]}
     if with_oracle:
+        print(f"bench: large pseudo variant: oracle over {stq['n_pairs']} pairs", file=sys.stderr, flush=True)
         q = synth.Particles(qx.cpu().numpy(), qm.cpu().numpy(), qh.cpu().numpy())
         O = oracle.map_particles(q, synth.cells_from(Gq))
         ps["oracle_all_cells"] = {"pairs_equal_count": int(O["pair_p"].size) == int(stq["n_pairs"]),
@@ -557,6 +560,9 @@ def main():
     ap.add_argument("--no-pseudo", action="store_true", help="skip the pseudo-particle leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-mapping leg")
     ap.add_argument("--no-large", action="store_true", help="skip the 8,388,608-particle job")
+    ap.add_argument("--oracle-full", action="store_true",
+                    help="also run the oracle over the whole 262,144-particle workload (about 80 s on 16 cores) and "
+                         "compare every cell of both precisions with it")
     ap.add_argument("--quick", action="store_true",
                     help="only the FP64 and mixed steps of the main workload (for profiling runs)")
     ap.add_argument("--mixed-shape", default=None,
@@ -629,6 +635,20 @@ def main():
         print(f"bench: {name}: {results[name]}", file=sys.stderr, flush=True)
     rel = np.abs(Ms["mixed"] - Ms["fp64"]) / np.abs(Ms["fp64"])
     extra = {}
+    if args.oracle_full:
+        import oracle
+
+        print("bench: the oracle over the whole workload", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        O = oracle.map_particles(p, c)
+        dt = time.perf_counter() - t0
+        extra["oracle_full"] = {
+            "pairs": int(O["pair_p"].size), "pairs_equal_count": int(O["pair_p"].size) == results["mixed"]["n_pairs"],
+            "seconds": dt, "pairs_per_s": O["pair_p"].size / dt, "cores": oracle.num_threads(),
+            "max_cell_rel_mixed": float((np.abs(Ms["mixed"] - O["M"]) / O["M"]).max()),
+            "max_cell_rel_fp64": float((np.abs(Ms["fp64"] - O["M"]) / O["M"]).max()),
+            "mass_rel_err_oracle": float(abs(O["M"].sum() - p.m.sum()) / p.m.sum())}
+        print(f"bench: oracle over the whole workload: {extra['oracle_full']}", file=sys.stderr, flush=True)
     if not args.quick:
         extra["inverse_mapping"] = back_leg(em, mapper, p, M, nc, args.steps)
         print(f"bench: inverse mapping: {extra['inverse_mapping']}", file=sys.stderr, flush=True)

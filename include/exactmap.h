@@ -476,16 +476,19 @@ int map_voronoi_copy(map_ctx *ctx, int mem_kind, int64_t *cell_face_off, int64_t
  * inputs (mem_kind MAP_MEM_DEVICE) are borrowed, like the outputs: they must
  * stay valid and unchanged until map_poll reports the job finished.
  * Jobs are admitted in submission order while a slot (cfg->max_jobs) and
- * device memory (cfg->hbm_budget_bytes, by an estimate of the job's
- * footprint) are free; an admitted job's geometry stays resident on the
- * device until it completes.  One scheduler thread per context makes all the
- * device calls: it builds admitted jobs' pair sets on a stage stream and,
- * whenever no integration is running, integrates every job whose pair set is
- * ready in one persistent launch of the task-batch kernel (a table of the
- * jobs), so jobs arriving while others integrate join the next launch and
- * their staging overlaps it.  A job's results are bitwise those of
- * map_particles on the same inputs with the default launch shape, alone or in
- * any mix.
+ * device memory (cfg->hbm_budget_bytes bounds the estimated footprint of the
+ * jobs in flight) are free; an admitted job's geometry stays resident on the
+ * device until it completes.  Each slot keeps its grow-only buffers from one
+ * job to the next (memory held: at most max_jobs times the largest job's
+ * buffers, returned at map_shutdown).  One scheduler thread per context makes
+ * all the device calls, in rounds: it builds the pair set of every admitted
+ * job, integrates all of them in one persistent launch of the task-batch
+ * kernel (a table of the jobs), builds the pair sets of the jobs admitted
+ * meanwhile while that launch runs, and finishes the launch's jobs
+ * (fixups, reductions, outputs) before the next launch; jobs arriving while
+ * others integrate join the next launch.  A job's results are bitwise those
+ * of map_particles on the same inputs with the default launch shape, alone or
+ * in any mix.
  * The out buffers (and out->stats) are caller-owned and must stay valid until
  * map_poll reports MAP_JOB_DONE or MAP_JOB_FAILED.
  * Errors at submit: MAP_EINVAL/MAP_EGEOM (malformed input), MAP_ENOMEM (job

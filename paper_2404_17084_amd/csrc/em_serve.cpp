@@ -8,15 +8,21 @@
 // and the batch stream (integration launches).
 //
 // Jobs are admitted in submission order while a slot is free and the job's
-// footprint estimate fits the device-memory budget; a slot keeps its
-// grow-only device workspace from one job to the next.  Whenever the batch
-// stream is idle and admitted jobs have their pair sets, one persistent launch
-// of the task-batch kernel integrates all of them (one launch per precision,
-// over a table of the jobs), so jobs that arrive while others integrate join
-// the next launch, and their staging on the stage stream overlaps the running
-// launch on the device.  The kernel computes each pair the same way whatever
-// the table holds, so a job's results are bitwise those of a synchronous
-// map_particles call with the same launch shape.
+// footprint estimate fits the device-memory budget (the budget bounds the
+// estimated footprint of the jobs in flight); a slot keeps its grow-only
+// buffers from one job to the next (the memory held is at most the number of
+// slots times the largest job's buffers), taken from the device's memory pool
+// in stream order, so that a slot that grows does not synchronise the device.  The scheduler works in rounds: it stages every admitted job
+// (pair sets), makes one persistent launch of the task-batch kernel over all
+// of them (one launch per precision, over a table of the jobs), stages the
+// jobs admitted meanwhile while that launch runs, and when it is done
+// finishes its jobs (fixups, reductions, outputs) before the next launch.
+// Jobs that arrive while others integrate thus join the next launch; the
+// persistent kernel holds every compute unit, so the jobs of one launch
+// share the device tile by tile instead of queueing behind each other.  The
+// kernel computes each pair the same way whatever the table holds, so a
+// job's results are bitwise those of a synchronous map_particles call with
+// the same launch shape.
 //
 // Every wait is bounded by the context's job time limit: the stage functions'
 // stream waits (thread-local wait limit), the launch completion (polled), the
@@ -257,15 +263,10 @@ static void finish_job(Server &S, Job *j)
         fail_server_locked(S, msg);
         return;
     }
-    ServeSlot *sl = j->slot;
     finish_locked(S, j, code, msg);
-    // the job's buffers go back to the device's memory pool (stream-ordered:
-    // no device-wide synchronisation), so the memory held is that of the jobs
-    // in flight plus what the pool keeps cached (up to the budget)
-    if (sl && !sl->job) {
-        lk.unlock();
-        sl->ws.release();
-    }
+    // the slot keeps its buffers for its next job: mapping them anew for
+    // every job (from the driver, gigabytes for the largest jobs) costs more
+    // than the jobs' own stages
 }
 
 // One integration launch per precision over every staged job; returns
@@ -392,7 +393,7 @@ static void serve_loop(Server *Sp)
     set_wait_limit_ms(S.limit_ms);
     (void)hipSetDevice(S.C->device);
     for (;;) {
-        Job *to_stage = nullptr;
+        std::vector<Job *> to_stage;
         {
             std::unique_lock<std::mutex> lk(S.mu);
             admit_locked(S);
@@ -404,34 +405,32 @@ static void serve_loop(Server *Sp)
             }
             if (S.stopping && S.queue.empty() && S.admitted.empty()) break;
             for (Job *j : S.admitted)
-                if (j->phase == P_ADMITTED) {
-                    to_stage = j;
-                    break;
-                }
+                if (j->phase == P_ADMITTED) to_stage.push_back(j);
         }
         bool progress = false;
-        std::vector<Job *> done;
+        // 1. the launch in flight: when it is done, its jobs are finished
+        //    (fixups, reductions, outputs) before anything else, so that their
+        //    results do not wait behind the next launch, and the slots and
+        //    budget they free are used by the next round of admissions
         if (!S.batch.empty()) {
             const int st = batch_state(S);
+            if (st < 0) continue;
             if (st == 1) {
+                std::vector<Job *> done;
                 done.swap(S.batch);
                 for (Job *j : done) trace(S, j, "integration done");
-            } else if (st < 0) {
+                for (Job *j : done) finish_job(S, j);
                 continue;
             }
         }
-        // the next launch first, so that the device integrates while the
-        // finished jobs are reduced and new ones staged
+        // 2. every admitted job gets its pair set (while a launch is in flight
+        //    the staging kernels fill the compute units its tail frees)
+        for (Job *j : to_stage) {
+            stage_job(S, j);
+            progress = true;
+        }
+        // 3. one launch over every staged job
         if (S.batch.empty() && launch_batch(S)) progress = true;
-        for (Job *j : done) {
-            finish_job(S, j);
-            progress = true;
-        }
-        if (to_stage) {
-            stage_job(S, to_stage);
-            progress = true;
-            if (S.batch.empty() && launch_batch(S)) progress = true;
-        }
         if (!progress) {
             std::unique_lock<std::mutex> lk(S.mu);
             if (!S.batch.empty()) {
@@ -482,10 +481,14 @@ static Server &server_of(Ctx &C)
         S->slots.back()->ws.use_stream(S->sstream);
     }
     {
-        // the pool that serves the slots' buffers keeps up to the budget cached
+        // the pool that serves the slots' buffers keeps what it has while the
+        // server runs (a trim would hand memory back to the driver at the next
+        // stream synchronisation, and the next job would map it again); the
+        // jobs in flight are bounded by the budget, so is what it holds, up
+        // to fragmentation.  serve_stop trims it.
         hipMemPool_t pool = nullptr;
         if (hipDeviceGetDefaultMemPool(&pool, C.device) == hipSuccess && pool) {
-            uint64_t keep = (uint64_t)S->budget;
+            uint64_t keep = ~uint64_t(0);
             (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
         }
         (void)hipGetLastError();
@@ -523,6 +526,14 @@ int serve_stop(Ctx &C)
         for (auto &sl : S->slots) sl->ws.release();
         if (S->sstream) (void)hipStreamSynchronize(S->sstream);
         if (S->bstream) (void)hipStreamSynchronize(S->bstream);
+        // the pool's cached memory back to the driver, and its default threshold back
+        hipMemPool_t pool = nullptr;
+        if (hipDeviceGetDefaultMemPool(&pool, C.device) == hipSuccess && pool) {
+            (void)hipMemPoolTrimTo(pool, 0);
+            uint64_t keep = 0;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+        (void)hipGetLastError();
         if (S->d_table) (void)hipFree(S->d_table);
         if (S->d_ctr) (void)hipFree(S->d_ctr);
         if (S->h_table) (void)hipHostFree(S->h_table);
