@@ -94,6 +94,32 @@ def box_cell(lo, hi):
                  np.array([vol]), tuple(lo) + tuple(hi))
 
 
+# ------------------------------------------------------------------ P0: the kernel profile
+def test_w_is_the_m4_spline():
+    """w(q) is the M4 cubic spline of Sec. III-C up to its normalisation: w(0) = 1, zero from q = 2
+    on, value and slope continuous at the piece boundaries q = 1 and 2 (finite differences), a
+    cubic on each piece (four samples fix the cubic, others lie on it), and sigma = 1/pi makes it
+    integrate to one over 3-D space."""
+    assert oracle.w(0.0) == 1.0
+    for q in (2.0, 2.5, 7.0):
+        assert oracle.w(q) == 0.0
+    h = 1e-6
+    for q in (1.0, 2.0):
+        lo, hi = oracle.w(q - h), oracle.w(q + h)
+        assert abs(hi - lo) < 1e-5
+        dl = (oracle.w(q - h) - oracle.w(q - 2 * h)) / h
+        dr = (oracle.w(q + 2 * h) - oracle.w(q + h)) / h
+        assert abs(dl - dr) < 1e-4
+    # exactly cubic on each piece: four samples determine the cubic, a fifth lies on it
+    for a, b in ((0.05, 0.95), (1.05, 1.95)):
+        xs = np.linspace(a, b, 4)
+        c = np.polyfit(xs, [oracle.w(x) for x in xs], 3)
+        for x in np.linspace(a, b, 9):
+            assert oracle.w(x) == pytest.approx(np.polyval(c, x), abs=1e-14)
+    total = integrate.quad(lambda q: oracle.w(q) * q * q, 0.0, 2.0, points=[1.0], epsabs=1e-15)[0]
+    assert 4.0 * PI * total / PI == pytest.approx(1.0, abs=1e-13)
+
+
 # ------------------------------------------------------------------ P1: radial profile
 @pytest.mark.parametrize("s", [0.1, 0.5, 0.9, 1.0, 1.3, 1.7, 1.99, 2.0, 3.0])
 def test_F_is_kernel_mass_per_steradian(s):
