@@ -15,6 +15,7 @@
 
 #include "em_internal.h"
 #include "em_voronoi_core.h"
+#include "em_wave.h"
 
 namespace em {
 
@@ -144,6 +145,427 @@ __global__ void __launch_bounds__(128) k_vor_build(int64_t n, const double *__re
     nfc[i] = f;
     nsc[i] = sl;
     nvc[i] = C.status == vor::ST_OK ? C.nt : 0;
+}
+
+// ---------------------------------------------------------------- one wavefront per cell
+// The same construction as k_vor_build (em_voronoi_core.h), with the working
+// cell of each wavefront in LDS instead of each lane's private memory: the
+// lanes own the cell's triangles (lane l: triangles l and l + 64), so a cut
+// tests every vertex at once, finds the boundary of the removed triangles
+// through a bit set of the kept triangles' directed edges (each dual edge is
+// in exactly one triangle, so the reverse of a removed triangle's edge is
+// kept exactly when it is in no removed triangle), and compacts kept and new
+// triangles with prefix counts in the order the serial cut uses.  Lane 0
+// walks the site tree for the candidate sites (the walk's stack and the
+// candidate heap in LDS).  Private-memory arrays of the per-lane form were
+// read with a different index on every lane (heaps, searches), so each access
+// fetched a cache line per lane: about 450 kB per cell.
+constexpr int kWCand = 256;   // candidates of one pass (wavefront walk); the serial walk uses the first 64
+constexpr int kWFront = 128;  // tree nodes of one level of the wavefront walk
+static_assert(kWCand >= vor::kMaxCand, "the serial walk's candidate heap lives in the same arrays");
+
+struct WCell {
+    vor::Plane pl[vor::kMaxPlanes];
+    double vx[vor::kMaxTris], vy[vor::kMaxTris], vz[vor::kMaxTris];
+    uint32_t tri[vor::kMaxTris];
+    int32_t src[vor::kMaxPlanes];
+    uint32_t bits[vor::kMaxPlanes * vor::kMaxPlanes / 32];  // directed edge (x, y) of a kept triangle: bit 64 x + y
+    double cd2[kWCand];
+    int32_t cand[kWCand];
+    union {
+        int32_t front[2][kWFront];  // the wavefront walk's levels
+        int64_t stack[64];          // the serial walk's stack (never live at the same time)
+    };
+    int32_t np, nt, status, cnt;
+    int32_t more, pad[3];
+};
+
+__device__ __forceinline__ double wave_max_d(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ double wave_min_d(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Set lanes of mask m below this lane.
+__device__ __forceinline__ int lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// vor::bounds over the wavefront's cell: the farthest vertex's squared
+// distance and the vertices' bounding box (max and min are exact, so the same
+// values as the serial pass).
+__device__ double wbounds(const WCell &W, int nt, int lane, double *blo, double *bhi)
+{
+    double m = 0.0, lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
+    for (int t = lane; t < nt; t += 64) {
+        const double x = W.vx[t], y = W.vy[t], z = W.vz[t];
+        m = fmax(m, x * x + y * y + z * z);
+        lx = fmin(lx, x), hx = fmax(hx, x);
+        ly = fmin(ly, y), hy = fmax(hy, y);
+        lz = fmin(lz, z), hz = fmax(hz, z);
+    }
+    blo[0] = wave_min_d(lx), blo[1] = wave_min_d(ly), blo[2] = wave_min_d(lz);
+    bhi[0] = wave_max_d(hx), bhi[1] = wave_max_d(hy), bhi[2] = wave_max_d(hz);
+    return wave_max_d(m);
+}
+
+// Bitonic sort of the first cnt candidates by key (squared distance, then
+// index), in LDS; entries up to the next power of two are padded.
+__device__ void sort_cands(WCell &W, int cnt, int lane)
+{
+    if (cnt <= 1) return;
+    int N = 2;
+    while (N < cnt) N <<= 1;
+    for (int i = cnt + lane; i < N; i += 64) {
+        W.cd2[i] = INFINITY;
+        W.cand[i] = 0x7fffffff;
+    }
+    lds_sync_wave();
+    for (int k = 2; k <= N; k <<= 1)
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int i = lane; i < N; i += 64) {
+                const int l = i ^ jj;
+                if (l > i) {
+                    const double a = W.cd2[i], b = W.cd2[l];
+                    const int32_t qa = W.cand[i], qb = W.cand[l];
+                    const bool up = (i & k) == 0;
+                    if (up ? vor::key_less(b, qb, a, qa) : vor::key_less(a, qa, b, qb)) {
+                        W.cd2[i] = b;
+                        W.cd2[l] = a;
+                        W.cand[i] = qb;
+                        W.cand[l] = qa;
+                    }
+                }
+            }
+            lds_sync_wave();
+        }
+}
+
+// The candidate sites of one pass with the whole wavefront: the tree is
+// walked level by level (each lane takes one node of the level; an internal
+// node puts those of its children that pass the visit test on the next level,
+// a leaf tests its sites), with the tests of the serial walk (vor::collect),
+// and the candidates are sorted by key (squared distance, then index).  The
+// list holds 256: when it fills up, it is sorted and cut to the sites nearer
+// than its 128th, whose distance becomes the walk's radius (as the serial
+// walk's heap prunes with its farthest entry), and *more is set.  So the
+// result is the nearest sites of the ball whose key follows (lo2, lo_q) and
+// whose bisector can reach the box [blo, bhi], in key order, all of them
+// unless *more.  Returns the count, or -1 when a level of the walk would
+// overflow LDS or a cut list keeps nothing (the caller then takes the serial
+// walk).
+__device__ int collect_wave(WCell &W, const double *__restrict__ ps, int64_t n, const double *__restrict__ bx,
+                            int64_t NL, int64_t self, double sx, double sy, double sz, double lo2, int64_t lo_q,
+                            double hi2, const double *blo, const double *bhi, int lane, bool *more)
+{
+    double h2 = hi2;
+    *more = false;
+    auto visit = [&](int64_t node) {
+        const double *b = bx + 6 * node;
+        const double g2 = vor::box_gap2(b, sx, sy, sz);
+        if (!(g2 < h2)) return false;
+        const double ax = b[0] - sx, bxx = b[3] - sx, ay = b[1] - sy, by = b[4] - sy, az = b[2] - sz, bz = b[5] - sz;
+        const double gm = fmax(fmax(ax * blo[0], ax * bhi[0]), fmax(bxx * blo[0], bxx * bhi[0])) +
+                          fmax(fmax(ay * blo[1], ay * bhi[1]), fmax(by * blo[1], by * bhi[1])) +
+                          fmax(fmax(az * blo[2], az * bhi[2]), fmax(bz * blo[2], bz * bhi[2]));
+        return 0.5 * g2 < gm;
+    };
+    int cur = 0, cnt = 0;
+    if (!visit(1)) return 0;  // (wave-uniform)
+    int fc = 1;
+    if (lane == 0) W.front[0][0] = 1;
+    lds_sync_wave();
+    while (fc > 0) {
+        int nf = 0;
+        for (int base = 0; base < fc; base += 64) {
+            const int i = base + lane;
+            const bool act = i < fc;
+            const int64_t node = act ? (int64_t)W.front[cur][i] : 0;
+            const bool internal = act && node < NL, leaf = act && node >= NL;
+            const bool v1 = internal && visit(2 * node), v2 = internal && visit(2 * node + 1);
+            const int c1 = wave_push(v1, nf);
+            const int c2 = wave_push(v2, nf);
+            if (v1 && c1 < kWFront) W.front[cur ^ 1][c1] = (int32_t)(2 * node);
+            if (v2 && c2 < kWFront) W.front[cur ^ 1][c2] = (int32_t)(2 * node + 1);
+            const int64_t j = node - NL;
+            for (int k = 0; k < vor::kLeaf; k++) {
+                if (cnt > kWCand - 64) {
+                    // full: keep the sites nearer than the 128th
+                    lds_sync_wave();
+                    sort_cands(W, cnt, lane);
+                    h2 = W.cd2[kWCand / 2 - 1];
+                    int keep = 0;
+                    for (int t = lane; t < cnt; t += 64) keep += W.cd2[t] < h2 ? 1 : 0;
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) keep += __shfl_xor(keep, o, 64);
+                    cnt = keep;
+                    *more = true;
+                    if (cnt == 0) return -1;  // ties: the serial walk orders them by index
+                    lds_sync_wave();
+                }
+                const int64_t q = vor::kLeaf * j + k;
+                bool take = false;
+                double d2 = 0.0;
+                if (leaf && q < n && q != self) {
+                    const double dx = ps[3 * q] - sx, dy = ps[3 * q + 1] - sy, dz = ps[3 * q + 2] - sz;
+                    d2 = dx * dx + dy * dy + dz * dz;
+                    take = d2 < h2 && vor::key_less(lo2, lo_q, d2, q) && 0.5 * d2 < vor::reach(blo, bhi, dx, dy, dz);
+                }
+                const int c = wave_push(take, cnt);
+                if (take) {
+                    W.cd2[c] = d2;
+                    W.cand[c] = (int32_t)q;
+                }
+            }
+        }
+        lds_sync_wave();
+        if (nf > kWFront) return -1;
+        cur ^= 1;
+        fc = nf;
+    }
+    sort_cands(W, cnt, lane);
+    return cnt;
+}
+
+// Cut by P (n.x <= d) in wave-uniform control flow; np, nt, status are
+// wave-uniform copies of the cell's counts.  Returns true when P removed a vertex.
+__device__ bool wclip(WCell &W, int &np, int &nt, int &status, const vor::Plane &P, int32_t src, int lane)
+{
+    const double nn = sqrt(P.nx * P.nx + P.ny * P.ny + P.nz * P.nz);
+    const double tol = vor::kEps * nn;
+    const int t0 = lane, t1 = lane + 64;
+    const bool h0 = t0 < nt, h1 = t1 < nt;
+    uint32_t q0 = 0, q1 = 0;
+    double x0 = 0.0, y0 = 0.0, z0 = 0.0, x1 = 0.0, y1 = 0.0, z1 = 0.0;
+    if (h0) {
+        q0 = W.tri[t0];
+        x0 = W.vx[t0];
+        y0 = W.vy[t0];
+        z0 = W.vz[t0];
+    }
+    if (h1) {
+        q1 = W.tri[t1];
+        x1 = W.vx[t1];
+        y1 = W.vy[t1];
+        z1 = W.vz[t1];
+    }
+    const bool o0 = h0 && P.nx * x0 + P.ny * y0 + P.nz * z0 - P.d > tol;
+    const bool o1 = h1 && P.nx * x1 + P.ny * y1 + P.nz * z1 - P.d > tol;
+    const uint64_t m0 = __ballot(o0), m1 = __ballot(o1);
+    if ((m0 | m1) == 0) return false;
+    if (np >= vor::kMaxPlanes) {
+        status = vor::ST_PLANES;
+        return false;
+    }
+    const int p = np;
+    if (lane == 0) {
+        W.pl[p] = P;
+        W.src[p] = src;
+    }
+    np++;
+    // directed edges of the kept triangles
+    W.bits[lane] = 0u;
+    W.bits[lane + 64] = 0u;
+    lds_sync_wave();
+    auto mark = [&](uint32_t q) {
+        const int a = vor::tri_a(q), b = vor::tri_b(q), c = vor::tri_c(q);
+        const int e0 = 64 * a + b, e1 = 64 * b + c, e2 = 64 * c + a;
+        atomicOr(&W.bits[e0 >> 5], 1u << (e0 & 31));
+        atomicOr(&W.bits[e1 >> 5], 1u << (e1 & 31));
+        atomicOr(&W.bits[e2 >> 5], 1u << (e2 & 31));
+    };
+    if (h0 && !o0) mark(q0);
+    if (h1 && !o1) mark(q1);
+    lds_sync_wave();
+    // new triangles (x, y, p) on the boundary edges (x, y) of the removed
+    // ones, in the serial order: by removed triangle, then edge
+    uint32_t n0[3], n1[3];
+    int c0 = 0, c1 = 0;
+    auto boundary = [&](uint32_t q, uint32_t *out, int &c) {
+        const int v[3] = {vor::tri_a(q), vor::tri_b(q), vor::tri_c(q)};
+        for (int e = 0; e < 3; e++) {
+            const int x = v[e], y = v[(e + 1) % 3];
+            const int r = 64 * y + x;
+            if ((W.bits[r >> 5] >> (r & 31)) & 1u) out[c++] = vor::tri_pack(x, y, p);
+        }
+    };
+    if (o0) boundary(q0, n0, c0);
+    if (o1) boundary(q1, n1, c1);
+    const uint64_t a0 = __ballot(c0 & 1), b0 = __ballot(c0 & 2), a1 = __ballot(c1 & 1), b1 = __ballot(c1 & 2);
+    const int s0 = lanes_below(a0) + 2 * lanes_below(b0), s1 = lanes_below(a1) + 2 * lanes_below(b1);
+    const int tot0 = __popcll(a0) + 2 * __popcll(b0), tot1 = __popcll(a1) + 2 * __popcll(b1);
+    const uint64_t k0 = __ballot(h0 && !o0), k1 = __ballot(h1 && !o1);
+    const int kept = __popcll(k0) + __popcll(k1);
+    if (kept + tot0 + tot1 > vor::kMaxTris) {
+        status = vor::ST_TRIS;
+        return false;
+    }
+    // every lane holds its triangles in registers: compact in place
+    if (h0 && !o0) {
+        const int k = lanes_below(k0);
+        W.tri[k] = q0;
+        W.vx[k] = x0;
+        W.vy[k] = y0;
+        W.vz[k] = z0;
+    }
+    if (h1 && !o1) {
+        const int k = __popcll(k0) + lanes_below(k1);
+        W.tri[k] = q1;
+        W.vx[k] = x1;
+        W.vy[k] = y1;
+        W.vz[k] = z1;
+    }
+    for (int i = 0; i < c0; i++) {
+        const int k = kept + s0 + i;
+        const uint32_t q = n0[i];
+        W.tri[k] = q;
+        vor::meet(W.pl[vor::tri_a(q)], W.pl[vor::tri_b(q)], W.pl[vor::tri_c(q)], W.vx[k], W.vy[k], W.vz[k]);
+    }
+    for (int i = 0; i < c1; i++) {
+        const int k = kept + tot0 + s1 + i;
+        const uint32_t q = n1[i];
+        W.tri[k] = q;
+        vor::meet(W.pl[vor::tri_a(q)], W.pl[vor::tri_b(q)], W.pl[vor::tri_c(q)], W.vx[k], W.vy[k], W.vz[k]);
+    }
+    nt = kept + tot0 + tot1;
+    lds_sync_wave();
+    return true;
+}
+
+// One wavefront per sorted site: the cell (as build_cell), its record and its counts.
+__global__ void __launch_bounds__(128) k_vor_build_wave(int64_t n, const double *__restrict__ ps,
+                                                        const int32_t *__restrict__ orig,
+                                                        const double *__restrict__ bx, int64_t NL, VBox B,
+                                                        vor::Cell *__restrict__ cells, int64_t *__restrict__ nfc,
+                                                        int64_t *__restrict__ nsc, int64_t *__restrict__ nvc,
+                                                        unsigned *flags)
+{
+    __shared__ WCell cellbuf[2];
+    const int lane = threadIdx.x & 63;
+    WCell &W = cellbuf[threadIdx.x >> 6];
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (r >= n) return;  // whole wavefronts
+    const double box[6] = {B.lo[0], B.lo[1], B.lo[2], B.hi[0], B.hi[1], B.hi[2]};
+    const double sx = ps[3 * r], sy = ps[3 * r + 1], sz = ps[3 * r + 2];
+    if (lane == 0) {
+        vor::init_box(W, box, sx, sy, sz);
+        W.status = vor::ST_OK;
+    }
+    lds_sync_wave();
+    int np = 6, nt = 8, status = vor::ST_OK;
+    // the first pass's ball, as in build_cell
+    const double *lb = bx + 6 * (NL + r / vor::kLeaf);
+    const double ex = box[3] - box[0], ey = box[4] - box[1], ez = box[5] - box[2];
+    const double mean = cbrt(ex * ey * ez / (double)n);
+    double hi2 = 0.3 * ((lb[3] - lb[0]) * (lb[3] - lb[0]) + (lb[4] - lb[1]) * (lb[4] - lb[1]) +
+                        (lb[5] - lb[2]) * (lb[5] - lb[2]));
+    if (hi2 < mean * mean) hi2 = mean * mean;
+    double lo2 = -1.0;
+    int64_t lo_q = -1;
+    double blo[3], bhi[3];
+    double m2 = wbounds(W, nt, lane, blo, bhi);
+    // Passes as in build_cell: the ball first, then everything that can still
+    // reach the cell; each pass lists the nearest sites whose key follows the
+    // last one taken.  The sites are taken in the serial construction's order,
+    // so the cell is the same.
+    bool done = false;
+    int pass = 0;
+    for (; pass < 4096 && !done && status == vor::ST_OK; pass++) {
+        bool more = false;
+        int cnt = collect_wave(W, ps, n, bx, NL, r, sx, sy, sz, lo2, lo_q, hi2, blo, bhi, lane, &more);
+        if (cnt < 0) {  // the serial walk, 64 at a time
+            if (lane == 0) {
+                bool m = false;
+                W.cnt = vor::collect(W, ps, n, bx, NL, r, sx, sy, sz, lo2, lo_q, hi2, blo, bhi, &m, W.stack);
+                W.more = m ? 1 : 0;
+            }
+            lds_sync_wave();
+            cnt = __builtin_amdgcn_readfirstlane(W.cnt);
+            more = __builtin_amdgcn_readfirstlane(W.more) != 0;
+            if (__builtin_amdgcn_readfirstlane(W.status) != vor::ST_OK) {
+                status = vor::ST_PASSES;
+                break;
+            }
+        }
+        for (int it = 0; it < cnt; it++) {
+            const double bd = W.cd2[it];
+            const int64_t q = W.cand[it];
+            if (bd >= 4.0 * m2) {  // this site and every farther one miss the cell
+                done = true;
+                break;
+            }
+            lo2 = bd;
+            lo_q = q;
+            vor::Plane P;
+            P.nx = ps[3 * q] - sx;
+            P.ny = ps[3 * q + 1] - sy;
+            P.nz = ps[3 * q + 2] - sz;
+            P.d = 0.5 * (P.nx * P.nx + P.ny * P.ny + P.nz * P.nz);
+            if (P.d == 0.0) continue;
+            if (!(P.d < vor::reach(blo, bhi, P.nx, P.ny, P.nz))) continue;
+            if (wclip(W, np, nt, status, P, orig[q], lane)) m2 = wbounds(W, nt, lane, blo, bhi);
+            if (status != vor::ST_OK) break;
+        }
+        if (done || status != vor::ST_OK) break;
+        if (!more) {
+            if (hi2 == INFINITY) {
+                done = true;
+                break;
+            }
+            hi2 = INFINITY;
+        }
+        lds_sync_wave();  // the candidate list is rewritten by the next pass
+    }
+    if (!done && status == vor::ST_OK) status = vor::ST_PASSES;
+    // the record for the extraction pass, and the counts
+    vor::Cell &G = cells[r];
+    if (lane == 0) {
+        G.np = np;
+        G.nt = nt;
+        G.status = status;
+    }
+    if (lane < np) {
+        G.pl[lane] = W.pl[lane];
+        G.src[lane] = W.src[lane];
+    }
+    for (int t = lane; t < nt; t += 64) {
+        G.tri[t] = W.tri[t];
+        G.vx[t] = W.vx[t];
+        G.vy[t] = W.vy[t];
+        G.vz[t] = W.vz[t];
+    }
+    int64_t f = 0, sl = 0;
+    if (status == vor::ST_OK) {
+        int c = 0;
+        if (lane < np)
+            for (int t = 0; t < nt; t++) {
+                const uint32_t q = W.tri[t];
+                c += (vor::tri_a(q) == lane || vor::tri_b(q) == lane || vor::tri_c(q) == lane) ? 1 : 0;
+            }
+        const bool face = c >= 3;
+        f = __popcll(__ballot(face));
+        int cs = face ? c : 0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) cs += __shfl_xor(cs, o, 64);
+        sl = cs;
+    } else if (lane == 0) {
+        atomicOr(flags, 4u);
+    }
+    if (lane == 0) {
+        const int64_t i = orig[r];
+        nfc[i] = f;
+        nsc[i] = sl;
+        nvc[i] = status == vor::ST_OK ? nt : 0;
+    }
 }
 
 struct VorOut {
@@ -337,7 +759,7 @@ void build_voronoi(Workspace &ws, VorGrid &V, int64_t n, const double *sites, co
     int64_t *nfc = ws.get<int64_t>(S_VOR9, (size_t)n + 1);
     int64_t *nsc = ws.get<int64_t>(S_VOR10, (size_t)n + 1);
     int64_t *nvc = ws.get<int64_t>(S_VOR11, (size_t)n + 1);
-    hipLaunchKernelGGL(k_vor_build, dim3(vgrid(n, 128)), dim3(128), 0, s, n, (const double *)ps,
+    hipLaunchKernelGGL(k_vor_build_wave, dim3(vgrid(64 * n, 128)), dim3(128), 0, s, n, (const double *)ps,
                        (const int32_t *)orig, (const double *)bx, NL, B, cells, nfc, nsc, nvc, flags);
     EM_HIP(hipGetLastError());
     int64_t *foff = ws.get<int64_t>(S_VOR12, (size_t)n + 1);

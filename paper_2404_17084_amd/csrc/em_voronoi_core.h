@@ -67,14 +67,16 @@ __host__ __device__ inline void meet(const Plane &A, const Plane &B, const Plane
     z = (A.d * bcz + B.d * caz + C.d * abz) / det;
 }
 
-__host__ __device__ inline void set_vertex(Cell &C, int t)
+template <class CellT>
+__host__ __device__ inline void set_vertex(CellT &C, int t)
 {
     const uint32_t q = C.tri[t];
     meet(C.pl[tri_a(q)], C.pl[tri_b(q)], C.pl[tri_c(q)], C.vx[t], C.vy[t], C.vz[t]);
 }
 
 // the box [lo, hi] around site s: planes 0..5 = x-, x+, y-, y+, z-, z+
-__host__ __device__ inline void init_box(Cell &C, const double *box, double sx, double sy, double sz)
+template <class CellT>
+__host__ __device__ inline void init_box(CellT &C, const double *box, double sx, double sy, double sz)
 {
     const double s[3] = {sx, sy, sz};
     for (int ax = 0; ax < 3; ax++)
@@ -102,12 +104,19 @@ __host__ __device__ inline void init_box(Cell &C, const double *box, double sx, 
     C.status = ST_OK;
 }
 
-__host__ __device__ inline double max_r2(const Cell &C)
+// the farthest vertex's squared distance and the vertices' bounding box (one pass)
+__host__ __device__ inline double bounds(const Cell &C, double *blo, double *bhi)
 {
     double m = 0.0;
+    blo[0] = blo[1] = blo[2] = INFINITY;
+    bhi[0] = bhi[1] = bhi[2] = -INFINITY;
     for (int t = 0; t < C.nt; t++) {
-        const double r2 = C.vx[t] * C.vx[t] + C.vy[t] * C.vy[t] + C.vz[t] * C.vz[t];
+        const double x = C.vx[t], y = C.vy[t], z = C.vz[t];
+        const double r2 = x * x + y * y + z * z;
         m = r2 > m ? r2 : m;
+        blo[0] = fmin(blo[0], x), bhi[0] = fmax(bhi[0], x);
+        blo[1] = fmin(blo[1], y), bhi[1] = fmax(bhi[1], y);
+        blo[2] = fmin(blo[2], z), bhi[2] = fmax(bhi[2], z);
     }
     return m;
 }
@@ -138,18 +147,23 @@ __host__ __device__ inline bool clip(Cell &C, const Plane &P, int32_t src)
     C.pl[p] = P;
     C.src[p] = src;
     C.np++;
-    // boundary edges of the removed set: edges whose reverse lies in a kept triangle
+    // boundary edges of the removed set: edges whose reverse lies in a kept
+    // triangle, i.e. in no other removed one (searched in a compact list of
+    // the removed triangles, a few out of the cell's tens)
+    uint32_t gone[kMaxTris];
+    int n_gone = 0;
+    for (int t = 0; t < C.nt; t++)
+        if (out[t]) gone[n_gone++] = C.tri[t];
     uint32_t add[kMaxTris];
     int n_add = 0;
-    for (int t = 0; t < C.nt; t++) {
-        if (!out[t]) continue;
-        const uint32_t q = C.tri[t];
+    for (int g = 0; g < n_gone; g++) {
+        const uint32_t q = gone[g];
         const int v[3] = {tri_a(q), tri_b(q), tri_c(q)};
         for (int e = 0; e < 3; e++) {
             const int x = v[e], y = v[(e + 1) % 3];
             bool inner = false;
-            for (int u = 0; u < C.nt && !inner; u++)
-                if (out[u] && u != t && has_edge(C.tri[u], y, x)) inner = true;
+            for (int u = 0; u < n_gone && !inner; u++)
+                if (u != g && has_edge(gone[u], y, x)) inner = true;
             if (!inner) {
                 if (n_add >= kMaxTris) {
                     C.status = ST_TRIS;
@@ -196,7 +210,8 @@ __host__ __device__ inline bool key_less(double d2, int64_t q, double e2, int64_
     return d2 < e2 || (d2 == e2 && q < r);
 }
 
-__host__ __device__ inline void heap_down(Cell &C, int k, int cnt)
+template <class CellT>
+__host__ __device__ inline void heap_down(CellT &C, int k, int cnt)
 {
     for (;;) {
         const int l = 2 * k + 1, r = l + 1;
@@ -231,15 +246,15 @@ __host__ __device__ inline double reach(const double *lo, const double *hi, doub
 // is farther than its farthest entry.  The list is a max-heap on the key
 // during the walk, sorted at the end.  Tree: heap of 2 NL boxes (6 doubles
 // each; leaves NL + j hold sites kLeaf j .. kLeaf j + 7).
-__host__ __device__ inline int collect(Cell &C, const double *ps, int64_t n, const double *bx, int64_t NL, int64_t self,
-                                       double sx, double sy, double sz, double lo2, int64_t lo_q, double hi2,
-                                       const double *blo, const double *bhi, bool *more)
+template <class CellT>
+__host__ __device__ inline int collect(CellT &C, const double *ps, int64_t n, const double *bx, int64_t NL,
+                                       int64_t self, double sx, double sy, double sz, double lo2, int64_t lo_q,
+                                       double hi2, const double *blo, const double *bhi, bool *more, int64_t *stack)
 {
     int cnt = 0;
     *more = false;
-    // depth-first, nearer child first; the stack holds at most one pending
-    // sibling per level
-    int64_t stack[64];
+    // depth-first, nearer child first; the stack (64 entries) holds at most
+    // one pending sibling per level
     int sp = 0;
     stack[sp++] = 1;
     while (sp > 0) {
@@ -324,16 +339,13 @@ __host__ __device__ inline void build_cell(Cell &C, const double *ps, const int3
     if (hi2 < mean * mean) hi2 = mean * mean;
     double lo2 = -1.0;  // key (lo2, lo_q) of the last site taken
     int64_t lo_q = -1;
-    double m2 = max_r2(C);
+    // the farthest vertex and the vertices' bounding box, kept current after every cut
+    double blo[3], bhi[3];
+    double m2 = bounds(C, blo, bhi);
     for (int pass = 0; pass < 4096; pass++) {
-        double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        for (int t = 0; t < C.nt; t++) {
-            blo[0] = fmin(blo[0], C.vx[t]), bhi[0] = fmax(bhi[0], C.vx[t]);
-            blo[1] = fmin(blo[1], C.vy[t]), bhi[1] = fmax(bhi[1], C.vy[t]);
-            blo[2] = fmin(blo[2], C.vz[t]), bhi[2] = fmax(bhi[2], C.vz[t]);
-        }
         bool more = false;
-        const int cnt = collect(C, ps, n, bx, NL, r, sx, sy, sz, lo2, lo_q, hi2, blo, bhi, &more);
+        int64_t stack[64];
+        const int cnt = collect(C, ps, n, bx, NL, r, sx, sy, sz, lo2, lo_q, hi2, blo, bhi, &more, stack);
         for (int it = 0; it < cnt; it++) {
             const double bd = C.cd2[it];
             const int64_t q = C.cand[it];
@@ -346,7 +358,11 @@ __host__ __device__ inline void build_cell(Cell &C, const double *ps, const int3
             P.nz = ps[3 * q + 2] - sz;
             P.d = 0.5 * (P.nx * P.nx + P.ny * P.ny + P.nz * P.nz);
             if (P.d == 0.0) continue;  // a coincident site has no bisector
-            if (clip(C, P, orig[q])) m2 = max_r2(C);
+            // a bisector that cannot reach the vertices' bounding box cuts no
+            // vertex (w.v <= reach for every vertex; the cut test's tolerance
+            // is far above the rounding of either side): no test needed
+            if (!(P.d < reach(blo, bhi, P.nx, P.ny, P.nz))) continue;
+            if (clip(C, P, orig[q])) m2 = bounds(C, blo, bhi);
             if (C.status != ST_OK) return;
         }
         if (!more) {
