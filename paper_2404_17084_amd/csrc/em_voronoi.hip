@@ -3,9 +3,9 @@
 // particle positions and relaxed by Lloyd iterations).
 //
 // Sites are sorted by Morton key and grouped 8 per leaf of a box tree (heap
-// order, internal boxes bottom-up).  One thread builds one cell
-// (em_voronoi_core.h: the box cut by bisector planes, nearest sites first,
-// until no farther site can reach it) in a per-cell record in device memory;
+// order, internal boxes bottom-up).  One wavefront builds one cell (the box
+// cut by bisector planes, nearest sites first, until no farther site can
+// reach it; em_voronoi_core.h) into a per-cell record in device memory;
 // its face, face-vertex and vertex counts are scanned into offsets in input
 // order, and a second pass writes the cells in the library's cell format
 // (faces counter-clockwise about outward unit normals, vertices per cell),
@@ -108,60 +108,19 @@ __global__ void k_vor_parent_boxes(int64_t first, double *__restrict__ bx)
     }
 }
 
-// one thread per sorted site: build its cell, count faces, face-vertex slots
-// and vertices (stored at the site's input index); flags bit 2: a cell needed
-// more planes, vertices or passes than its record holds
-__global__ void __launch_bounds__(128) k_vor_build(int64_t n, const double *__restrict__ ps,
-                                                   const int32_t *__restrict__ orig, const double *__restrict__ bx,
-                                                   int64_t NL, VBox B, vor::Cell *__restrict__ cells,
-                                                   int64_t *__restrict__ nfc, int64_t *__restrict__ nsc,
-                                                   int64_t *__restrict__ nvc, unsigned *flags)
-{
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    const double box[6] = {B.lo[0], B.lo[1], B.lo[2], B.hi[0], B.hi[1], B.hi[2]};
-    // the working cell in private memory (interleaved across the lanes of a
-    // wavefront), then its planes and vertices copied to the record
-    vor::Cell C;
-    vor::build_cell(C, ps, orig, n, bx, NL, box, r);
-    vor::Cell &G = cells[r];
-    G.np = C.np;
-    G.nt = C.nt;
-    G.status = C.status;
-    for (int p = 0; p < C.np; p++) {
-        G.pl[p] = C.pl[p];
-        G.src[p] = C.src[p];
-    }
-    for (int t = 0; t < C.nt; t++) {
-        G.tri[t] = C.tri[t];
-        G.vx[t] = C.vx[t];
-        G.vy[t] = C.vy[t];
-        G.vz[t] = C.vz[t];
-    }
-    int64_t f = 0, sl = 0;
-    if (C.status == vor::ST_OK) vor::cell_counts(C, f, sl);
-    else atomicOr(flags, 4u);
-    const int64_t i = orig[r];
-    nfc[i] = f;
-    nsc[i] = sl;
-    nvc[i] = C.status == vor::ST_OK ? C.nt : 0;
-}
-
 // ---------------------------------------------------------------- one wavefront per cell
-// The same construction as k_vor_build (em_voronoi_core.h), with the working
-// cell of each wavefront in LDS instead of each lane's private memory: the
-// lanes own the cell's triangles (lane l: triangles l and l + 64), so a cut
-// tests every vertex at once, finds the boundary of the removed triangles
-// through a bit set of the kept triangles' directed edges (each dual edge is
-// in exactly one triangle, so the reverse of a removed triangle's edge is
-// kept exactly when it is in no removed triangle), and compacts kept and new
-// triangles with prefix counts in the order the serial cut uses.  Lane 0
-// walks the site tree for the candidate sites (the walk's stack and the
-// candidate heap in LDS).  Private-memory arrays of the per-lane form were
-// read with a different index on every lane (heaps, searches), so each access
-// fetched a cache line per lane: about 450 kB per cell.
+// The working cell of each wavefront is in LDS: the lanes own the cell's
+// triangles (lane l: triangles l and l + 64), so a cut tests every vertex at
+// once, finds the boundary of the removed triangles through a bit set of the
+// kept triangles' directed edges (each dual edge is in exactly one triangle,
+// so the reverse of a removed triangle's edge is kept exactly when it is in
+// no removed triangle), and compacts kept and new triangles with prefix
+// counts.  The candidate sites of a pass come from a walk of the site tree by
+// the whole wavefront (a node stack in LDS, 64 nodes at a time).  A cell built
+// by one lane in private memory instead reads its arrays with a different
+// index on every lane, so that each access fetches a cache line per lane.
 constexpr int kWCand = 256;   // candidates of one pass (wavefront walk); the serial walk uses the first 64
-constexpr int kWFront = 128;  // tree nodes of one level of the wavefront walk
+constexpr int kWStack = 512;  // tree nodes pending in the wavefront walk
 static_assert(kWCand >= vor::kMaxCand, "the serial walk's candidate heap lives in the same arrays");
 
 struct WCell {
@@ -169,12 +128,12 @@ struct WCell {
     double vx[vor::kMaxTris], vy[vor::kMaxTris], vz[vor::kMaxTris];
     uint32_t tri[vor::kMaxTris];
     int32_t src[vor::kMaxPlanes];
-    uint32_t bits[vor::kMaxPlanes * vor::kMaxPlanes / 32];  // directed edge (x, y) of a kept triangle: bit 64 x + y
     double cd2[kWCand];
     int32_t cand[kWCand];
-    union {
-        int32_t front[2][kWFront];  // the wavefront walk's levels
-        int64_t stack[64];          // the serial walk's stack (never live at the same time)
+    union {  // (never live at the same time)
+        int32_t nodes[kWStack];                                 // the wavefront walk's pending nodes
+        int64_t stack[64];                                      // the serial walk's stack
+        uint32_t bits[vor::kMaxPlanes * vor::kMaxPlanes / 32];  // a cut's directed edges (x, y) of kept triangles: bit 64 x + y
     };
     int32_t np, nt, status, cnt;
     int32_t more, pad[3];
@@ -200,9 +159,8 @@ __device__ __forceinline__ int lanes_below(uint64_t m)
     return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
-// vor::bounds over the wavefront's cell: the farthest vertex's squared
-// distance and the vertices' bounding box (max and min are exact, so the same
-// values as the serial pass).
+// The farthest vertex's squared distance and the vertices' bounding box
+// (site-centred) of the wavefront's cell.
 __device__ double wbounds(const WCell &W, int nt, int lane, double *blo, double *bhi)
 {
     double m = 0.0, lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
@@ -218,51 +176,56 @@ __device__ double wbounds(const WCell &W, int nt, int lane, double *blo, double 
     return wave_max_d(m);
 }
 
-// Bitonic sort of the first cnt candidates by key (squared distance, then
-// index), in LDS; entries up to the next power of two are padded.
+// Sorts the first cnt (<= kWCand) candidates by key (squared distance, then
+// index) in LDS: each lane holds up to 4 of them and counts the keys below
+// each (keys are distinct: the index breaks ties), reading the list with
+// broadcast loads; then writes each at its rank.
 __device__ void sort_cands(WCell &W, int cnt, int lane)
 {
     if (cnt <= 1) return;
-    int N = 2;
-    while (N < cnt) N <<= 1;
-    for (int i = cnt + lane; i < N; i += 64) {
-        W.cd2[i] = INFINITY;
-        W.cand[i] = 0x7fffffff;
+    static_assert(kWCand <= 256, "four candidates per lane");
+    double d[4];
+    int32_t q[4];
+    int rk[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const int i = lane + 64 * u;
+        d[u] = i < cnt ? W.cd2[i] : INFINITY;
+        q[u] = i < cnt ? W.cand[i] : 0x7fffffff;
+        rk[u] = 0;
     }
-    lds_sync_wave();
-    for (int k = 2; k <= N; k <<= 1)
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            for (int i = lane; i < N; i += 64) {
-                const int l = i ^ jj;
-                if (l > i) {
-                    const double a = W.cd2[i], b = W.cd2[l];
-                    const int32_t qa = W.cand[i], qb = W.cand[l];
-                    const bool up = (i & k) == 0;
-                    if (up ? vor::key_less(b, qb, a, qa) : vor::key_less(a, qa, b, qb)) {
-                        W.cd2[i] = b;
-                        W.cd2[l] = a;
-                        W.cand[i] = qb;
-                        W.cand[l] = qa;
-                    }
-                }
-            }
-            lds_sync_wave();
+    const int per = (cnt + 63) >> 6;  // wave-uniform
+    for (int j = 0; j < cnt; j++) {
+        const double e = W.cd2[j];
+        const int32_t eq = W.cand[j];
+        rk[0] += vor::key_less(e, eq, d[0], q[0]) ? 1 : 0;
+        if (per > 1) rk[1] += vor::key_less(e, eq, d[1], q[1]) ? 1 : 0;
+        if (per > 2) rk[2] += vor::key_less(e, eq, d[2], q[2]) ? 1 : 0;
+        if (per > 3) rk[3] += vor::key_less(e, eq, d[3], q[3]) ? 1 : 0;
+    }
+    lds_sync_wave();  // every read done before the list is rewritten
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+        if (lane + 64 * u < cnt) {
+            W.cd2[rk[u]] = d[u];
+            W.cand[rk[u]] = q[u];
         }
+    lds_sync_wave();
 }
 
-// The candidate sites of one pass with the whole wavefront: the tree is
-// walked level by level (each lane takes one node of the level; an internal
-// node puts those of its children that pass the visit test on the next level,
-// a leaf tests its sites), with the tests of the serial walk (vor::collect),
-// and the candidates are sorted by key (squared distance, then index).  The
-// list holds 256: when it fills up, it is sorted and cut to the sites nearer
-// than its 128th, whose distance becomes the walk's radius (as the serial
-// walk's heap prunes with its farthest entry), and *more is set.  So the
-// result is the nearest sites of the ball whose key follows (lo2, lo_q) and
-// whose bisector can reach the box [blo, bhi], in key order, all of them
-// unless *more.  Returns the count, or -1 when a level of the walk would
-// overflow LDS or a cut list keeps nothing (the caller then takes the serial
-// walk).
+// The candidate sites of one pass with the whole wavefront: pending tree
+// nodes sit on a stack in LDS, and each step takes the top 64 (one per lane):
+// an internal node pushes those of its children that pass the visit test, a
+// leaf tests its sites, with the tests of the serial walk (vor::collect).  The
+// walk starts from the (at most 64) nodes of the tree's level 6.  The list of
+// candidates holds 256: when it fills up, it is sorted and cut to the sites
+// nearer than its 128th, whose distance becomes the walk's radius (as the
+// serial walk's heap prunes with its farthest entry), and *more is set.  So
+// the result is the nearest sites of the ball whose key follows (lo2, lo_q)
+// and whose bisector can reach the box [blo, bhi], sorted by key (squared
+// distance, then index), all of them unless *more.  Returns the count, or -1
+// when the node stack would overflow or a cut list keeps nothing (the caller
+// then takes the serial walk).
 __device__ int collect_wave(WCell &W, const double *__restrict__ ps, int64_t n, const double *__restrict__ bx,
                             int64_t NL, int64_t self, double sx, double sy, double sz, double lo2, int64_t lo_q,
                             double hi2, const double *blo, const double *bhi, int lane, bool *more)
@@ -279,58 +242,68 @@ __device__ int collect_wave(WCell &W, const double *__restrict__ ps, int64_t n, 
                           fmax(fmax(az * blo[2], az * bhi[2]), fmax(bz * blo[2], bz * bhi[2]));
         return 0.5 * g2 < gm;
     };
-    int cur = 0, cnt = 0;
-    if (!visit(1)) return 0;  // (wave-uniform)
-    int fc = 1;
-    if (lane == 0) W.front[0][0] = 1;
+    // level 6 of the tree (or the leaves, for a tree of fewer than 64): nodes
+    // first .. 2 first - 1; NL is a power of two
+    const int64_t first = NL < 64 ? NL : 64;
+    int sp = 0, cnt = 0;
+    bool cut = false;  // h2 was lowered: popped nodes are tested again
+    {
+        const bool v = lane < first && visit(first + lane);
+        const int c = wave_push(v, sp);
+        if (v) W.nodes[c] = (int32_t)(first + lane);
+    }
     lds_sync_wave();
-    while (fc > 0) {
-        int nf = 0;
-        for (int base = 0; base < fc; base += 64) {
-            const int i = base + lane;
-            const bool act = i < fc;
-            const int64_t node = act ? (int64_t)W.front[cur][i] : 0;
-            const bool internal = act && node < NL, leaf = act && node >= NL;
-            const bool v1 = internal && visit(2 * node), v2 = internal && visit(2 * node + 1);
-            const int c1 = wave_push(v1, nf);
-            const int c2 = wave_push(v2, nf);
-            if (v1 && c1 < kWFront) W.front[cur ^ 1][c1] = (int32_t)(2 * node);
-            if (v2 && c2 < kWFront) W.front[cur ^ 1][c2] = (int32_t)(2 * node + 1);
-            const int64_t j = node - NL;
-            for (int k = 0; k < vor::kLeaf; k++) {
-                if (cnt > kWCand - 64) {
-                    // full: keep the sites nearer than the 128th
-                    lds_sync_wave();
-                    sort_cands(W, cnt, lane);
-                    h2 = W.cd2[kWCand / 2 - 1];
-                    int keep = 0;
-                    for (int t = lane; t < cnt; t += 64) keep += W.cd2[t] < h2 ? 1 : 0;
+    while (sp > 0) {
+        const int k = sp < 64 ? sp : 64;
+        sp -= k;
+        const int64_t node = lane < k ? (int64_t)W.nodes[sp + lane] : 0;
+        lds_sync_wave();  // read before the pushes below overwrite these slots
+        const bool act = lane < k && (!cut || visit(node));
+        const bool internal = act && node < NL, leaf = act && node >= NL;
+        const bool v1 = internal && visit(2 * node), v2 = internal && visit(2 * node + 1);
+        const int c1 = wave_push(v1, sp);
+        const int c2 = wave_push(v2, sp);
+        if (v1 && c1 < kWStack) W.nodes[c1] = (int32_t)(2 * node);
+        if (v2 && c2 < kWStack) W.nodes[c2] = (int32_t)(2 * node + 1);
+        // a leaf's sites, all loaded before any is pushed
+        const int64_t j = leaf ? node - NL : 0;
+        double d2[vor::kLeaf];
+        bool take[vor::kLeaf];
 #pragma unroll
-                    for (int o = 32; o > 0; o >>= 1) keep += __shfl_xor(keep, o, 64);
-                    cnt = keep;
-                    *more = true;
-                    if (cnt == 0) return -1;  // ties: the serial walk orders them by index
-                    lds_sync_wave();
-                }
-                const int64_t q = vor::kLeaf * j + k;
-                bool take = false;
-                double d2 = 0.0;
-                if (leaf && q < n && q != self) {
-                    const double dx = ps[3 * q] - sx, dy = ps[3 * q + 1] - sy, dz = ps[3 * q + 2] - sz;
-                    d2 = dx * dx + dy * dy + dz * dz;
-                    take = d2 < h2 && vor::key_less(lo2, lo_q, d2, q) && 0.5 * d2 < vor::reach(blo, bhi, dx, dy, dz);
-                }
-                const int c = wave_push(take, cnt);
-                if (take) {
-                    W.cd2[c] = d2;
-                    W.cand[c] = (int32_t)q;
-                }
+        for (int t = 0; t < vor::kLeaf; t++) {
+            const int64_t q = vor::kLeaf * j + t;
+            const bool ok = leaf && q < n && q != self;
+            const int64_t qq = ok ? q : 0;
+            const double dx = ps[3 * qq] - sx, dy = ps[3 * qq + 1] - sy, dz = ps[3 * qq + 2] - sz;
+            d2[t] = dx * dx + dy * dy + dz * dz;
+            take[t] = ok && vor::key_less(lo2, lo_q, d2[t], q) && 0.5 * d2[t] < vor::reach(blo, bhi, dx, dy, dz);
+        }
+#pragma unroll
+        for (int t = 0; t < vor::kLeaf; t++) {
+            if (cnt > kWCand - 64) {
+                // full: keep the sites nearer than the 128th
+                lds_sync_wave();
+                sort_cands(W, cnt, lane);
+                h2 = W.cd2[kWCand / 2 - 1];
+                int keep = 0;
+                for (int u = lane; u < cnt; u += 64) keep += W.cd2[u] < h2 ? 1 : 0;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) keep += __shfl_xor(keep, o, 64);
+                cnt = keep;
+                *more = true;
+                cut = true;
+                if (cnt == 0) return -1;  // ties: the serial walk orders them by index
+                lds_sync_wave();
+            }
+            const bool tk = take[t] && d2[t] < h2;
+            const int c = wave_push(tk, cnt);
+            if (tk) {
+                W.cd2[c] = d2[t];
+                W.cand[c] = (int32_t)(vor::kLeaf * j + t);
             }
         }
         lds_sync_wave();
-        if (nf > kWFront) return -1;
-        cur ^= 1;
-        fc = nf;
+        if (sp > kWStack) return -1;
     }
     sort_cands(W, cnt, lane);
     return cnt;
@@ -441,7 +414,9 @@ __device__ bool wclip(WCell &W, int &np, int &nt, int &status, const vor::Plane 
     return true;
 }
 
-// One wavefront per sorted site: the cell (as build_cell), its record and its counts.
+// One wavefront per sorted site: its cell, the cell's record and its face,
+// face-vertex slot and vertex counts (stored at the site's input index); flags
+// bit 2: a cell needed more planes, vertices or passes than its record holds.
 __global__ void __launch_bounds__(128) k_vor_build_wave(int64_t n, const double *__restrict__ ps,
                                                         const int32_t *__restrict__ orig,
                                                         const double *__restrict__ bx, int64_t NL, VBox B,
@@ -462,21 +437,28 @@ __global__ void __launch_bounds__(128) k_vor_build_wave(int64_t n, const double 
     }
     lds_sync_wave();
     int np = 6, nt = 8, status = vor::ST_OK;
-    // the first pass's ball, as in build_cell
+    // The first pass only looks within 0.87 times the diagonal of the site's
+    // leaf box (about 110 sites when the leaf's 8 sites fill it: most cells
+    // end within it), at least an eighth of the mean spacing (a leaf of
+    // coincident sites); later passes look anywhere.  The cell does not depend
+    // on this choice (see below).
     const double *lb = bx + 6 * (NL + r / vor::kLeaf);
     const double ex = box[3] - box[0], ey = box[4] - box[1], ez = box[5] - box[2];
     const double mean = cbrt(ex * ey * ez / (double)n);
-    double hi2 = 0.3 * ((lb[3] - lb[0]) * (lb[3] - lb[0]) + (lb[4] - lb[1]) * (lb[4] - lb[1]) +
-                        (lb[5] - lb[2]) * (lb[5] - lb[2]));
-    if (hi2 < mean * mean) hi2 = mean * mean;
+    double hi2 = 0.75 * ((lb[3] - lb[0]) * (lb[3] - lb[0]) + (lb[4] - lb[1]) * (lb[4] - lb[1]) +
+                         (lb[5] - lb[2]) * (lb[5] - lb[2]));
+    if (hi2 < mean * mean / 64.0) hi2 = mean * mean / 64.0;
     double lo2 = -1.0;
     int64_t lo_q = -1;
     double blo[3], bhi[3];
     double m2 = wbounds(W, nt, lane, blo, bhi);
-    // Passes as in build_cell: the ball first, then everything that can still
-    // reach the cell; each pass lists the nearest sites whose key follows the
-    // last one taken.  The sites are taken in the serial construction's order,
-    // so the cell is the same.
+    // Passes: the ball first, then everything that can still reach the cell;
+    // each pass lists the nearest sites whose key follows the last one taken.
+    // The sites are cut in key order, skipping those whose bisector cannot
+    // reach the vertices' current bounding box (a pass's own reach filter used
+    // the box at its start, which contains the current one), until one is at
+    // least twice as far as the farthest vertex: the sequence of cuts, and so
+    // the cell, is the same however the passes split it.
     bool done = false;
     int pass = 0;
     for (; pass < 4096 && !done && status == vor::ST_OK; pass++) {
@@ -639,8 +621,12 @@ __global__ void k_vor_gather(int64_t n, const double *__restrict__ s, const int6
 
 // The cell holding each input point: its nearest site of the grid (ties to
 // the lower index), by a walk of the grid's site tree, nearer child first,
-// skipping boxes farther than the best so far.
-__global__ void k_vor_site_cell(int64_t n_in, const double *__restrict__ x, int64_t n, const double *__restrict__ ps,
+// skipping boxes farther than the best so far.  Each thread's stack is a
+// column of an LDS array (at most one pending sibling per level: 32 entries
+// hold trees of up to 2^30 leaves).
+constexpr int kSiteStack = 32;
+
+__global__ void __launch_bounds__(128) k_vor_site_cell(int64_t n_in, const double *__restrict__ x, int64_t n, const double *__restrict__ ps,
                                 const int32_t *__restrict__ orig, const double *__restrict__ bx, int64_t NL,
                                 int64_t *__restrict__ site_cell)
 {
@@ -649,18 +635,20 @@ __global__ void k_vor_site_cell(int64_t n_in, const double *__restrict__ x, int6
     const double px = x[3 * a], py = x[3 * a + 1], pz = x[3 * a + 2];
     double best = INFINITY;
     int32_t bi = -1;
-    int64_t stack[64];
+    __shared__ int32_t stk[kSiteStack][128];
+    int32_t *stack = &stk[0][threadIdx.x];  // entry k at stack[128 k]
     int sp = 0;
-    stack[sp++] = 1;
+    stack[0] = 1;
+    sp = 1;
     while (sp > 0) {
-        const int64_t i = stack[--sp];
+        const int64_t i = stack[128 * --sp];
         if (vor::box_gap2(bx + 6 * i, px, py, pz) > best) continue;
         if (i < NL) {
-            if (sp + 2 > 64) break;  // cannot happen below 2^62 leaves
+            if (sp + 2 > kSiteStack) break;  // cannot happen below 2^30 leaves
             const double gl = vor::box_gap2(bx + 6 * (2 * i), px, py, pz);
             const double gr = vor::box_gap2(bx + 6 * (2 * i + 1), px, py, pz);
-            stack[sp++] = gl <= gr ? 2 * i + 1 : 2 * i;
-            stack[sp++] = gl <= gr ? 2 * i : 2 * i + 1;
+            stack[128 * sp++] = (int32_t)(gl <= gr ? 2 * i + 1 : 2 * i);
+            stack[128 * sp++] = (int32_t)(gl <= gr ? 2 * i : 2 * i + 1);
             continue;
         }
         const int64_t j = i - NL;

@@ -1,5 +1,7 @@
 // Box-clipped Voronoi cell of one site (Sec. II-A: the grid whose generating
-// sites are the particle positions), host- and device-callable.
+// sites are the particle positions): the cell representation, the box, the
+// site-tree tests and the serial candidate walk, host- and device-callable.
+// The construction itself runs one wavefront per cell (em_voronoi.hip).
 //
 // The cell is held as the dual of a convex polyhedron: a list of planes
 // (n.x <= d in coordinates centred on the site, n not normalised) and a list
@@ -9,7 +11,8 @@
 // box (6 planes, 8 triangles) and is cut by bisector planes of other sites:
 // the triangles whose vertex lies beyond the plane are removed, and every edge
 // (x, y) of a removed triangle whose reverse belongs to a kept triangle gets a
-// new triangle (x, y, P).  Sites are taken nearest first (a tree of the sites
+// new triangle (x, y, P).  This is the dual-triangle clipping of Ray, Sokolov,
+// Lefebvre and Levy ("Meshless Voronoi on the GPU", ACM Trans. Graph. 2018).  Sites are taken nearest first (a tree of the sites
 // sorted by Morton key, leaves of 8), in passes that only consider sites whose
 // bisector can still reach the cell's bounding box; once the next site is at
 // least twice as far as the farthest vertex, no other site can cut the cell
@@ -36,14 +39,12 @@ struct Plane {
     double nx, ny, nz, d;
 };
 
-// Working state of one cell (device scratch, one block per cell).
+// A built cell as the extraction pass reads it (device memory, one per site).
 struct Cell {
     Plane pl[kMaxPlanes];
     int32_t src[kMaxPlanes];  // site (input index) across the plane, or -1 - wall
     uint32_t tri[kMaxTris];   // a | b << 8 | c << 16
     double vx[kMaxTris], vy[kMaxTris], vz[kMaxTris];
-    int32_t cand[kMaxCand];   // sorted-site index
-    double cd2[kMaxCand];     // squared distance, +inf once used
     int32_t np, nt, status, pad;
 };
 
@@ -104,96 +105,11 @@ __host__ __device__ inline void init_box(CellT &C, const double *box, double sx,
     C.status = ST_OK;
 }
 
-// the farthest vertex's squared distance and the vertices' bounding box (one pass)
-__host__ __device__ inline double bounds(const Cell &C, double *blo, double *bhi)
-{
-    double m = 0.0;
-    blo[0] = blo[1] = blo[2] = INFINITY;
-    bhi[0] = bhi[1] = bhi[2] = -INFINITY;
-    for (int t = 0; t < C.nt; t++) {
-        const double x = C.vx[t], y = C.vy[t], z = C.vz[t];
-        const double r2 = x * x + y * y + z * z;
-        m = r2 > m ? r2 : m;
-        blo[0] = fmin(blo[0], x), bhi[0] = fmax(bhi[0], x);
-        blo[1] = fmin(blo[1], y), bhi[1] = fmax(bhi[1], y);
-        blo[2] = fmin(blo[2], z), bhi[2] = fmax(bhi[2], z);
-    }
-    return m;
-}
-
+// true when triangle t holds the directed dual edge (x, y)
 __host__ __device__ inline bool has_edge(uint32_t t, int x, int y)
 {
     const int a = tri_a(t), b = tri_b(t), c = tri_c(t);
     return (a == x && b == y) || (b == x && c == y) || (c == x && a == y);
-}
-
-// Cuts the cell by P (n.x <= d).  Returns true when P removed a vertex.
-__host__ __device__ inline bool clip(Cell &C, const Plane &P, int32_t src)
-{
-    const double nn = sqrt(P.nx * P.nx + P.ny * P.ny + P.nz * P.nz);
-    const double tol = kEps * nn;
-    bool out[kMaxTris];
-    int n_out = 0;
-    for (int t = 0; t < C.nt; t++) {
-        out[t] = P.nx * C.vx[t] + P.ny * C.vy[t] + P.nz * C.vz[t] - P.d > tol;
-        n_out += out[t] ? 1 : 0;
-    }
-    if (n_out == 0) return false;
-    if (C.np >= kMaxPlanes) {
-        C.status = ST_PLANES;
-        return false;
-    }
-    const int p = C.np;
-    C.pl[p] = P;
-    C.src[p] = src;
-    C.np++;
-    // boundary edges of the removed set: edges whose reverse lies in a kept
-    // triangle, i.e. in no other removed one (searched in a compact list of
-    // the removed triangles, a few out of the cell's tens)
-    uint32_t gone[kMaxTris];
-    int n_gone = 0;
-    for (int t = 0; t < C.nt; t++)
-        if (out[t]) gone[n_gone++] = C.tri[t];
-    uint32_t add[kMaxTris];
-    int n_add = 0;
-    for (int g = 0; g < n_gone; g++) {
-        const uint32_t q = gone[g];
-        const int v[3] = {tri_a(q), tri_b(q), tri_c(q)};
-        for (int e = 0; e < 3; e++) {
-            const int x = v[e], y = v[(e + 1) % 3];
-            bool inner = false;
-            for (int u = 0; u < n_gone && !inner; u++)
-                if (u != g && has_edge(gone[u], y, x)) inner = true;
-            if (!inner) {
-                if (n_add >= kMaxTris) {
-                    C.status = ST_TRIS;
-                    return false;
-                }
-                add[n_add++] = tri_pack(x, y, p);
-            }
-        }
-    }
-    // keep the inside triangles, then add the new ones
-    int k = 0;
-    for (int t = 0; t < C.nt; t++) {
-        if (out[t]) continue;
-        C.tri[k] = C.tri[t];
-        C.vx[k] = C.vx[t];
-        C.vy[k] = C.vy[t];
-        C.vz[k] = C.vz[t];
-        k++;
-    }
-    if (k + n_add > kMaxTris) {
-        C.status = ST_TRIS;
-        return false;
-    }
-    for (int a = 0; a < n_add; a++) {
-        C.tri[k] = add[a];
-        set_vertex(C, k);
-        k++;
-    }
-    C.nt = k;
-    return true;
 }
 
 __host__ __device__ inline double box_gap2(const double *bb, double px, double py, double pz)
@@ -321,69 +237,6 @@ __host__ __device__ inline int collect(CellT &C, const double *ps, int64_t n, co
     return cnt;
 }
 
-// The cell of sorted site r (input index orig[r]).  Passes take the sites
-// that can still reach the cell's bounding box, nearest first, 64 at a time,
-// until a pass finds no more; the first pass only looks within 0.55 times the
-// diagonal of the site's leaf box (about 30 sites when the leaf's 8 sites
-// fill it; at least the mean spacing), later passes anywhere.
-__host__ __device__ inline void build_cell(Cell &C, const double *ps, const int32_t *orig, int64_t n, const double *bx,
-                                           int64_t NL, const double *box, int64_t r)
-{
-    const double sx = ps[3 * r], sy = ps[3 * r + 1], sz = ps[3 * r + 2];
-    init_box(C, box, sx, sy, sz);
-    const double *lb = bx + 6 * (NL + r / kLeaf);
-    const double ex = box[3] - box[0], ey = box[4] - box[1], ez = box[5] - box[2];
-    const double mean = cbrt(ex * ey * ez / (double)n);
-    double hi2 = 0.3 * ((lb[3] - lb[0]) * (lb[3] - lb[0]) + (lb[4] - lb[1]) * (lb[4] - lb[1]) +
-                         (lb[5] - lb[2]) * (lb[5] - lb[2]));
-    if (hi2 < mean * mean) hi2 = mean * mean;
-    double lo2 = -1.0;  // key (lo2, lo_q) of the last site taken
-    int64_t lo_q = -1;
-    // the farthest vertex and the vertices' bounding box, kept current after every cut
-    double blo[3], bhi[3];
-    double m2 = bounds(C, blo, bhi);
-    for (int pass = 0; pass < 4096; pass++) {
-        bool more = false;
-        int64_t stack[64];
-        const int cnt = collect(C, ps, n, bx, NL, r, sx, sy, sz, lo2, lo_q, hi2, blo, bhi, &more, stack);
-        for (int it = 0; it < cnt; it++) {
-            const double bd = C.cd2[it];
-            const int64_t q = C.cand[it];
-            if (bd >= 4.0 * m2) return;  // the bisector of this site and of every farther one misses the cell
-            lo2 = bd;
-            lo_q = q;
-            Plane P;
-            P.nx = ps[3 * q] - sx;
-            P.ny = ps[3 * q + 1] - sy;
-            P.nz = ps[3 * q + 2] - sz;
-            P.d = 0.5 * (P.nx * P.nx + P.ny * P.ny + P.nz * P.nz);
-            if (P.d == 0.0) continue;  // a coincident site has no bisector
-            // a bisector that cannot reach the vertices' bounding box cuts no
-            // vertex (w.v <= reach for every vertex; the cut test's tolerance
-            // is far above the rounding of either side): no test needed
-            if (!(P.d < reach(blo, bhi, P.nx, P.ny, P.nz))) continue;
-            if (clip(C, P, orig[q])) m2 = bounds(C, blo, bhi);
-            if (C.status != ST_OK) return;
-        }
-        if (!more) {
-            if (hi2 == INFINITY) return;  // every site that can reach the cell was taken
-            hi2 = INFINITY;  // beyond the first ball
-        }
-    }
-    C.status = ST_PASSES;
-}
-
-// Faces of a built cell: planes that carry at least 3 vertices.
-__host__ __device__ inline int plane_count(const Cell &C, int p)
-{
-    int c = 0;
-    for (int t = 0; t < C.nt; t++) {
-        const uint32_t q = C.tri[t];
-        c += (tri_a(q) == p || tri_b(q) == p || tri_c(q) == p) ? 1 : 0;
-    }
-    return c;
-}
-
 // Writes the faces of a built cell: for each plane with at least 3 vertices,
 // its vertices in order around it, counter-clockwise seen from outside (the
 // triangle (p, a, b) is followed by the one holding the edge (p, b); the order
@@ -473,20 +326,6 @@ __host__ __device__ inline void extract_cell(Cell &C, double sx, double sy, doub
     cen[0] = sx + (V > 0.0 ? M[0] / V : 0.0);
     cen[1] = sy + (V > 0.0 ? M[1] / V : 0.0);
     cen[2] = sz + (V > 0.0 ? M[2] / V : 0.0);
-}
-
-// counts of a built cell: faces, face-vertex slots
-__host__ __device__ inline void cell_counts(const Cell &C, int64_t &faces, int64_t &slots)
-{
-    faces = 0;
-    slots = 0;
-    for (int p = 0; p < C.np; p++) {
-        const int c = plane_count(C, p);
-        if (c >= 3) {
-            faces++;
-            slots += c;
-        }
-    }
 }
 
 }  // namespace vor
