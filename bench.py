@@ -550,6 +550,40 @@ def valu_calibration():
             "tflops_fp32_nonpacked": tf, "frac_of_157_3": tf / PEAK_FP32}
 
 
+def voronoi_only(em, args):
+    """The device Voronoi grid alone (profiling mode): timings of the 262,144-site build."""
+    import torch
+    import synth
+
+    p = synth.particles(*synth.CLUMPS_256K)
+    sites = torch.from_numpy(np.ascontiguousarray(p.xyz)).to("cuda:0")
+    out = {}
+    with em.Mapper(device=0) as mp:
+        G = em.map_voronoi(mp.ctx, sites, synth.BOX, 0, device=True)  # warm-up
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            G = em.map_voronoi(mp.ctx, sites, synth.BOX, 0, device=True)
+            torch.cuda.synchronize()
+            ms.append(1e3 * (time.perf_counter() - t0))
+        out["lloyd_0"] = {"ms": float(np.mean(ms)), "ms_device": G.ms, "faces": int(G.face_plane.shape[0])}
+        t0 = time.perf_counter()
+        G = em.map_voronoi(mp.ctx, sites, synth.BOX, 5, device=True)
+        torch.cuda.synchronize()
+        out["lloyd_5"] = {"ms": 1e3 * (time.perf_counter() - t0), "ms_device": G.ms,
+                          "faces": int(G.face_plane.shape[0])}
+    line = {"voronoi_grid": out, "sites": p.n, "steps": args.steps}
+    if args.copy_calibration:
+        src_t = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        dst_t = torch.empty_like(src_t)
+        torch.cuda.synchronize()
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = 1 << 30
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -571,6 +605,9 @@ def main():
                     help="finish with one plain 1 GiB device-to-device copy (scale for HBM byte counters)")
     ap.add_argument("--valu-calibration", action="store_true",
                     help="run the VALU calibration kernel (scale for the VALU counters; measured FP32 rate)")
+    ap.add_argument("--voronoi-only", action="store_true",
+                    help="only build the device Voronoi grid of the 262,144 clumpy sites (1 warm-up, then --steps "
+                         "builds, then one with 5 Lloyd iterations) and print its timings (for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the mapping runs on a single "
@@ -582,6 +619,9 @@ def main():
     import paper_2404_17084_amd as em
 
     em.load()
+    if args.voronoi_only:
+        voronoi_only(em, args)
+        return
     print("bench: generating the 262,144-particle clumpy workload", file=sys.stderr, flush=True)
     p, c = synth.workload(*synth.CLUMPS_256K)
     xyz, m, h, dc = to_device(p, c)

@@ -556,23 +556,161 @@ struct VorOut {
     double *plane, *verts, *vol, *cen;
 };
 
-// one thread per input site: write its cell at the scanned offsets
+// One wavefront per input site writes its cell at the scanned offsets: for
+// each plane with at least 3 vertices (lane p: plane p), its vertices in
+// order around it, counter-clockwise seen from outside (the triangle (p, a, b)
+// is followed by the one holding the directed edge (p, b), found in a table of
+// the cell's directed edges; the order is reversed if the polygon's vector
+// area points inward), the outward unit normal and offset in box
+// coordinates, and the site or wall across it; the cell's vertices (in box
+// coordinates), volume and centroid (tetrahedra from the site over face fans,
+// summed over the faces of each lane and then across the wavefront).  The
+// record is read once into LDS.  flags bit 3: a face's vertices did not close
+// into one loop.
+struct XCell {
+    vor::Plane pl[vor::kMaxPlanes];
+    double vx[vor::kMaxTris], vy[vor::kMaxTris], vz[vor::kMaxTris];
+    uint32_t tri[vor::kMaxTris];
+    int32_t src[vor::kMaxPlanes];
+    uint8_t et[vor::kMaxPlanes * vor::kMaxPlanes];  // directed edge (x, y): its triangle at 64 x + y, 0xff: none
+    uint8_t ring[vor::kMaxPlanes][64];               // ring[k][p]: the k-th triangle around plane p
+};
+static_assert(vor::kMaxTris < 255 && vor::kMaxPlanes <= 64, "triangle ids in bytes, one plane per lane");
+
 __global__ void __launch_bounds__(128) k_vor_extract(int64_t n, const double *__restrict__ s,
-                                                     const int64_t *__restrict__ rank, vor::Cell *__restrict__ cells,
+                                                     const int64_t *__restrict__ rank,
+                                                     const vor::Cell *__restrict__ cells,
                                                      const int64_t *__restrict__ foff, const int64_t *__restrict__ soff,
                                                      const int64_t *__restrict__ voff, VorOut O, unsigned *flags)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    vor::Cell &C = cells[rank[i]];
-    O.cfo[i] = foff[i];
-    if (i == n - 1) O.cfo[n] = foff[n];
+    __shared__ XCell xbuf[2];
+    const int lane = threadIdx.x & 63;
+    XCell &X = xbuf[threadIdx.x >> 6];
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (i >= n) return;  // whole wavefronts
+    const vor::Cell &C = cells[rank[i]];
+    if (lane == 0) {
+        O.cfo[i] = foff[i];
+        if (i == n - 1) O.cfo[n] = foff[n];
+    }
     if (C.status != vor::ST_OK) return;
-    double vol = 0.0;
-    vor::extract_cell(C, s[3 * i], s[3 * i + 1], s[3 * i + 2], voff[i], foff[i], soff[i], O.fvo, O.fv, O.plane, O.fnb,
-                      O.verts, vol, O.cen + 3 * i);
-    if (C.status != vor::ST_OK) atomicOr(flags, 8u);
-    O.vol[i] = vol;
+    const int np = C.np, nt = C.nt;
+    const double sx = s[3 * i], sy = s[3 * i + 1], sz = s[3 * i + 2];
+    const int64_t vbase = voff[i], fbase = foff[i], sbase = soff[i];
+    uint32_t *et32 = reinterpret_cast<uint32_t *>(X.et);
+    for (int k = lane; k < vor::kMaxPlanes * vor::kMaxPlanes / 4; k += 64) et32[k] = 0xffffffffu;
+    if (lane < np) {
+        X.pl[lane] = C.pl[lane];
+        X.src[lane] = C.src[lane];
+    }
+    for (int t = lane; t < nt; t += 64) {
+        const double x = C.vx[t], y = C.vy[t], z = C.vz[t];
+        X.tri[t] = C.tri[t];
+        X.vx[t] = x;
+        X.vy[t] = y;
+        X.vz[t] = z;
+        O.verts[3 * (vbase + t)] = x + sx;
+        O.verts[3 * (vbase + t) + 1] = y + sy;
+        O.verts[3 * (vbase + t) + 2] = z + sz;
+    }
+    lds_sync_wave();
+    for (int t = lane; t < nt; t += 64) {
+        const uint32_t q = X.tri[t];
+        const int a = vor::tri_a(q), b = vor::tri_b(q), c = vor::tri_c(q);
+        X.et[64 * a + b] = (uint8_t)t;
+        X.et[64 * b + c] = (uint8_t)t;
+        X.et[64 * c + a] = (uint8_t)t;
+    }
+    lds_sync_wave();
+    // the ring of triangles around plane p = lane, from the first that holds it
+    const int p = lane;
+    int nr = 0, first = -1;
+    for (int t = 0; t < nt; t++) {
+        const uint32_t q = X.tri[t];
+        if (vor::tri_a(q) == p || vor::tri_b(q) == p || vor::tri_c(q) == p) {
+            nr++;
+            if (first < 0) first = t;
+        }
+    }
+    const bool face = p < np && nr >= 3;
+    int len = 0;
+    if (face) {
+        int t = first;
+        while (len < nr && len < vor::kMaxPlanes) {  // (a valid cell has at most np - 1)
+            X.ring[len][p] = (uint8_t)t;
+            len++;
+            const uint32_t q = X.tri[t];
+            const int b = vor::tri_a(q) == p ? vor::tri_c(q) : (vor::tri_b(q) == p ? vor::tri_a(q) : vor::tri_b(q));
+            const int nx = X.et[64 * p + b];  // the triangle holding the directed edge (p, b)
+            if (nx == 0xff || nx == first) break;
+            t = nx;
+        }
+    }
+    if (__ballot(face && len != nr) != 0) {
+        if (lane == 0) atomicOr(flags, 8u);
+        return;
+    }
+    // face index and first slot: prefix counts over the lanes below
+    const uint64_t fm = __ballot(face);
+    const int nf = __popcll(fm);
+    int incl = face ? len : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    const int total = __shfl(incl, 63, 64);
+    double V = 0.0, M0 = 0.0, M1 = 0.0, M2 = 0.0;
+    if (face) {
+        const int64_t f = fbase + lanes_below(fm), slot = sbase + incl - len;
+        const vor::Plane P = X.pl[p];
+        const double nn = sqrt(P.nx * P.nx + P.ny * P.ny + P.nz * P.nz);
+        const double ux = P.nx / nn, uy = P.ny / nn, uz = P.nz / nn;
+        // vector area about the site (local coordinates)
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int k = 0; k < len; k++) {
+            const int a = X.ring[k][p], b = X.ring[k + 1 < len ? k + 1 : 0][p];
+            ax += X.vy[a] * X.vz[b] - X.vz[a] * X.vy[b];
+            ay += X.vz[a] * X.vx[b] - X.vx[a] * X.vz[b];
+            az += X.vx[a] * X.vy[b] - X.vy[a] * X.vx[b];
+        }
+        const bool rev = ax * ux + ay * uy + az * uz < 0.0;
+        auto at = [&](int k) { return (int)X.ring[rev ? len - 1 - k : k][p]; };
+        O.fvo[f] = slot;
+        for (int k = 0; k < len; k++) O.fv[slot + k] = (int32_t)(vbase + at(k));
+        O.plane[4 * f] = ux;
+        O.plane[4 * f + 1] = uy;
+        O.plane[4 * f + 2] = uz;
+        O.plane[4 * f + 3] = P.d / nn + (ux * sx + uy * sy + uz * sz);
+        O.fnb[f] = X.src[p];
+        // tetrahedra (site, v0, vk, vk+1) in counter-clockwise order
+        const int o0 = at(0);
+        const double x0 = X.vx[o0], y0 = X.vy[o0], z0 = X.vz[o0];
+        for (int k = 1; k + 1 < len; k++) {
+            const int o1 = at(k), o2 = at(k + 1);
+            const double x1 = X.vx[o1], y1 = X.vy[o1], z1 = X.vz[o1];
+            const double x2 = X.vx[o2], y2 = X.vy[o2], z2 = X.vz[o2];
+            const double tv = (x0 * (y1 * z2 - z1 * y2) + y0 * (z1 * x2 - x1 * z2) + z0 * (x1 * y2 - y1 * x2)) / 6.0;
+            V += tv;
+            M0 += tv * (x0 + x1 + x2) / 4.0;
+            M1 += tv * (y0 + y1 + y2) / 4.0;
+            M2 += tv * (z0 + z1 + z2) / 4.0;
+        }
+    }
+    if (lane == 0) O.fvo[fbase + nf] = sbase + total;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        V += __shfl_xor(V, o, 64);
+        M0 += __shfl_xor(M0, o, 64);
+        M1 += __shfl_xor(M1, o, 64);
+        M2 += __shfl_xor(M2, o, 64);
+    }
+    if (lane == 0) {
+        O.vol[i] = V;
+        O.cen[3 * i] = sx + (V > 0.0 ? M0 / V : 0.0);
+        O.cen[3 * i + 1] = sy + (V > 0.0 ? M1 / V : 0.0);
+        O.cen[3 * i + 2] = sz + (V > 0.0 ? M2 / V : 0.0);
+    }
 }
 
 // Merging of tightly packed sites: a site is dropped when a site of lower
@@ -777,7 +915,8 @@ void build_voronoi(Workspace &ws, VorGrid &V, int64_t n, const double *sites, co
     O.plane = dev_alloc(V.plane, V.cap_plane, (size_t)(4 * tot[0]));
     O.fv = dev_alloc(V.fv, V.cap_fv, (size_t)tot[1]);
     O.verts = dev_alloc(V.verts, V.cap_verts, (size_t)(3 * tot[2]));
-    hipLaunchKernelGGL(k_vor_extract, dim3(vgrid(n, 128)), dim3(128), 0, s, n, sites, (const int64_t *)rank, cells,
+    hipLaunchKernelGGL(k_vor_extract, dim3(vgrid(64 * n, 128)), dim3(128), 0, s, n, sites, (const int64_t *)rank,
+                       (const vor::Cell *)cells,
                        (const int64_t *)foff, (const int64_t *)soff, (const int64_t *)voff, O, flags);
     EM_HIP(hipGetLastError());
     EM_HIP(hipMemcpyAsync(&hf, flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));

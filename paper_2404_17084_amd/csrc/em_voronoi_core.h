@@ -105,13 +105,6 @@ __host__ __device__ inline void init_box(CellT &C, const double *box, double sx,
     C.status = ST_OK;
 }
 
-// true when triangle t holds the directed dual edge (x, y)
-__host__ __device__ inline bool has_edge(uint32_t t, int x, int y)
-{
-    const int a = tri_a(t), b = tri_b(t), c = tri_c(t);
-    return (a == x && b == y) || (b == x && c == y) || (c == x && a == y);
-}
-
 __host__ __device__ inline double box_gap2(const double *bb, double px, double py, double pz)
 {
     const double dx = fmax(fmax(bb[0] - px, px - bb[3]), 0.0);
@@ -235,97 +228,6 @@ __host__ __device__ inline int collect(CellT &C, const double *ps, int64_t n, co
         heap_down(C, 0, end);
     }
     return cnt;
-}
-
-// Writes the faces of a built cell: for each plane with at least 3 vertices,
-// its vertices in order around it, counter-clockwise seen from outside (the
-// triangle (p, a, b) is followed by the one holding the edge (p, b); the order
-// is reversed if the polygon's vector area points inward), the outward unit
-// normal and offset in box coordinates, and the site or wall across it.
-// Vertices are the cell's triangles (index vbase + t), in box coordinates.
-// Returns the volume and centroid (tetrahedra from the site over face fans);
-// status ST_FACE if a face's vertices do not close into one loop.
-__host__ __device__ inline void extract_cell(Cell &C, double sx, double sy, double sz, int64_t vbase, int64_t fbase,
-                                             int64_t sbase, int64_t *face_vert_off, int32_t *face_vert,
-                                             double *face_plane, int64_t *face_nb, double *verts, double &vol,
-                                             double *cen)
-{
-    for (int t = 0; t < C.nt; t++) {
-        verts[3 * (vbase + t)] = C.vx[t] + sx;
-        verts[3 * (vbase + t) + 1] = C.vy[t] + sy;
-        verts[3 * (vbase + t) + 2] = C.vz[t] + sz;
-    }
-    int64_t f = fbase, slot = sbase;
-    double V = 0.0, M[3] = {0.0, 0.0, 0.0};
-    int ring[kMaxTris];
-    for (int p = 0; p < C.np; p++) {
-        // triangles around p, as (p, a, b) with b the next plane
-        int nr = 0;
-        int first = -1;
-        for (int t = 0; t < C.nt; t++) {
-            const uint32_t q = C.tri[t];
-            if (tri_a(q) == p || tri_b(q) == p || tri_c(q) == p) {
-                nr++;
-                if (first < 0) first = t;
-            }
-        }
-        if (nr < 3) continue;
-        int len = 0, t = first;
-        while (len < nr) {
-            ring[len++] = t;
-            const uint32_t q = C.tri[t];
-            const int b = tri_a(q) == p ? tri_c(q) : (tri_b(q) == p ? tri_a(q) : tri_b(q));
-            // next: the triangle holding the directed edge (p, b)
-            int nx = -1;
-            for (int u = 0; u < C.nt && nx < 0; u++)
-                if (u != t && has_edge(C.tri[u], p, b)) nx = u;
-            if (nx < 0 || nx == first) break;
-            t = nx;
-        }
-        if (len != nr) {
-            C.status = ST_FACE;
-            return;
-        }
-        const Plane &P = C.pl[p];
-        const double nn = sqrt(P.nx * P.nx + P.ny * P.ny + P.nz * P.nz);
-        const double ux = P.nx / nn, uy = P.ny / nn, uz = P.nz / nn;
-        // vector area about the site (local coordinates)
-        double ax = 0.0, ay = 0.0, az = 0.0;
-        for (int k = 0; k < len; k++) {
-            const int a = ring[k], b = ring[(k + 1) % len];
-            ax += C.vy[a] * C.vz[b] - C.vz[a] * C.vy[b];
-            ay += C.vz[a] * C.vx[b] - C.vx[a] * C.vz[b];
-            az += C.vx[a] * C.vy[b] - C.vy[a] * C.vx[b];
-        }
-        const bool rev = ax * ux + ay * uy + az * uz < 0.0;
-        face_vert_off[f] = slot;
-        for (int k = 0; k < len; k++) face_vert[slot + k] = (int32_t)(vbase + ring[rev ? len - 1 - k : k]);
-        slot += len;
-        face_plane[4 * f] = ux;
-        face_plane[4 * f + 1] = uy;
-        face_plane[4 * f + 2] = uz;
-        face_plane[4 * f + 3] = P.d / nn + (ux * sx + uy * sy + uz * sz);
-        face_nb[f] = C.src[p];
-        f++;
-        // tetrahedra (site, v0, vk, vk+1) in counter-clockwise order
-        const int o0 = ring[rev ? len - 1 : 0];
-        for (int k = 1; k + 1 < len; k++) {
-            const int o1 = ring[rev ? len - 1 - k : k], o2 = ring[rev ? len - 2 - k : k + 1];
-            const double x0 = C.vx[o0], y0 = C.vy[o0], z0 = C.vz[o0];
-            const double x1 = C.vx[o1], y1 = C.vy[o1], z1 = C.vz[o1];
-            const double x2 = C.vx[o2], y2 = C.vy[o2], z2 = C.vz[o2];
-            const double tv = (x0 * (y1 * z2 - z1 * y2) + y0 * (z1 * x2 - x1 * z2) + z0 * (x1 * y2 - y1 * x2)) / 6.0;
-            V += tv;
-            M[0] += tv * (x0 + x1 + x2) / 4.0;
-            M[1] += tv * (y0 + y1 + y2) / 4.0;
-            M[2] += tv * (z0 + z1 + z2) / 4.0;
-        }
-    }
-    face_vert_off[f] = slot;
-    vol = V;
-    cen[0] = sx + (V > 0.0 ? M[0] / V : 0.0);
-    cen[1] = sy + (V > 0.0 ? M[1] / V : 0.0);
-    cen[2] = sz + (V > 0.0 ? M[2] / V : 0.0);
 }
 
 }  // namespace vor
