@@ -182,6 +182,7 @@ void radix_sort_u32(Workspace &ws, uint32_t *keys, uint32_t *vals, uint32_t *key
 void radix_sort_u64(Workspace &ws, uint64_t *keys, uint32_t *vals, uint64_t *keys2, uint32_t *vals2, int64_t n,
                     int bits, hipStream_t s);
 void fill_iota_u32(uint32_t *p, int64_t n, hipStream_t s);
+void fill_iota_i64(int64_t *p, int64_t n, hipStream_t s);
 // Waits until the work queued on stream s has finished.  On a thread that set
 // a wait limit (set_wait_limit_ms > 0; the serving thread does) the wait polls
 // and throws MAP_EDEVICE with a message containing kWaitLimitText once the

@@ -141,6 +141,13 @@ __global__ void k_iota_u32(uint32_t *p, int64_t n)
     for (; i < n; i += stride) p[i] = (uint32_t)i;
 }
 
+__global__ void k_iota_i64(int64_t *p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = i;
+}
+
 __global__ void k_zero_u64(uint64_t *p, int64_t n)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -166,6 +173,13 @@ void fill_iota_u32(uint32_t *p, int64_t n, hipStream_t s)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_iota_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n);
+    EM_HIP(hipGetLastError());
+}
+
+void fill_iota_i64(int64_t *p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_iota_i64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n);
     EM_HIP(hipGetLastError());
 }
 

@@ -439,8 +439,8 @@ __global__ void __launch_bounds__(128) k_vor_build_wave(int64_t n, const double 
     int np = 6, nt = 8, status = vor::ST_OK;
     // The first pass only looks within 0.87 times the diagonal of the site's
     // leaf box (about 110 sites when the leaf's 8 sites fill it: most cells
-    // end within it), at least an eighth of the mean spacing (a leaf of
-    // coincident sites); later passes look anywhere.  The cell does not depend
+    // end within it), at least an eighth of the mean spacing (for a leaf of
+    // very close sites); later passes look anywhere.  The cell does not depend
     // on this choice (see below).
     const double *lb = bx + 6 * (NL + r / vor::kLeaf);
     const double ex = box[3] - box[0], ey = box[4] - box[1], ez = box[5] - box[2];
