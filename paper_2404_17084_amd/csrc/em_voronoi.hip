@@ -119,8 +119,8 @@ __global__ void k_vor_parent_boxes(int64_t first, double *__restrict__ bx)
 // the whole wavefront (a node stack in LDS, 64 nodes at a time).  A cell built
 // by one lane in private memory instead reads its arrays with a different
 // index on every lane, so that each access fetches a cache line per lane.
-constexpr int kWCand = 256;   // candidates of one pass (wavefront walk); the serial walk uses the first 64
-constexpr int kWStack = 512;  // tree nodes pending in the wavefront walk
+constexpr int kWCand = 192;   // candidates of one pass (wavefront walk); the serial walk uses the first 64
+constexpr int kWStack = 384;  // tree nodes pending in the wavefront walk (with kWCand: 9.7 kB of LDS per cell, 4 cells per SIMD)
 static_assert(kWCand >= vor::kMaxCand, "the serial walk's candidate heap lives in the same arrays");
 
 struct WCell {
@@ -218,8 +218,8 @@ __device__ void sort_cands(WCell &W, int cnt, int lane)
 // an internal node pushes those of its children that pass the visit test, a
 // leaf tests its sites, with the tests of the serial walk (vor::collect).  The
 // walk starts from the (at most 64) nodes of the tree's level 6.  The list of
-// candidates holds 256: when it fills up, it is sorted and cut to the sites
-// nearer than its 128th, whose distance becomes the walk's radius (as the
+// candidates holds kWCand: when it fills up, it is sorted and cut to the
+// sites nearer than its (kWCand / 2)th, whose distance becomes the walk's radius (as the
 // serial walk's heap prunes with its farthest entry), and *more is set.  So
 // the result is the nearest sites of the ball whose key follows (lo2, lo_q)
 // and whose bisector can reach the box [blo, bhi], sorted by key (squared
@@ -281,7 +281,7 @@ __device__ int collect_wave(WCell &W, const double *__restrict__ ps, int64_t n, 
 #pragma unroll
         for (int t = 0; t < vor::kLeaf; t++) {
             if (cnt > kWCand - 64) {
-                // full: keep the sites nearer than the 128th
+                // full: keep the sites nearer than the (kWCand / 2)th
                 lds_sync_wave();
                 sort_cands(W, cnt, lane);
                 h2 = W.cd2[kWCand / 2 - 1];

@@ -7,8 +7,9 @@ and the set of neighbours across the faces (exact); every face is planar,
 counter-clockwise about its outward unit normal, and shared faces have equal
 areas; the cells feed the FP64 mapping to the same cell masses as the oracle's
 cells (1e-10); five Lloyd iterations give the oracle's sites to 1e-12.  At
-262,144 clumpy sites, 32 sampled cells are checked against the oracle's
-selected cells, and the whole grid fills the box.
+262,144 clumpy sites, 32 seeded cells and the largest cells and those with
+the most faces are checked against the oracle's selected cells, and the whole
+grid fills the box.
 """
 import sys
 
@@ -112,7 +113,12 @@ def test_voronoi_full_size_sampled():
         G = mp.voronoi(p.xyz, BOX)
     say(f"  built in {G.ms:.2f} ms, {G.face_plane.shape[0] / G.n_cells:.2f} faces per cell")
     assert G.cell_volume.sum() == pytest.approx(1.0, rel=1e-11)
-    sel = np.sort(np.random.default_rng(17).choice(p.n, 32, replace=False))
+    # 32 seeded cells, and the 16 largest cells and the 16 with the most faces: large cells next to
+    # the clumps have the longest candidate walks (the ones that can leave the wavefront walk's node
+    # stack for the serial walk)
+    nf = np.diff(G.cell_face_off)
+    sel = np.unique(np.concatenate([np.random.default_rng(17).choice(p.n, 32, replace=False),
+                                    np.argsort(G.cell_volume)[-16:], np.argsort(nf, kind="stable")[-16:]]))
     O = oracle.voronoi(p.xyz, BOX, sel=sel)
     rel = np.abs(G.cell_volume[sel] - O["cell_volume"]) / O["cell_volume"]
     assert rel.max() < 1e-12
