@@ -92,13 +92,18 @@ void launch_validate(const DevInputs &in, unsigned *flags, hipStream_t s)
 // Directed edges of every face (counter-clockwise about the outward normal
 // n) with unit direction e and in-plane inward normal m = n x e, one record
 // per slot.  A wavefront takes 64 consecutive faces and gives its lanes
-// consecutive slots (coalesced 80-byte record stores); a lane finds its
-// slot's face by binary search in the wavefront's face offsets (faces have
-// at least 3 slots, checked by the structure validation that runs first).
+// consecutive slots; a lane finds its slot's face by binary search in the
+// wavefront's face offsets (faces have at least 3 slots, checked by the
+// structure validation that runs first).  The 64 records of a round are
+// staged in LDS and stored as consecutive 16-byte chunks: stored straight
+// from the lanes, each store instruction would touch every fifth 16 bytes of
+// forty cache lines.
 __global__ void __launch_bounds__(256) k_edge_table(int64_t n_faces, const int64_t *fvo, const int32_t *fv,
                                                     const double *plane, const double *verts, EdgeRec *edges)
 {
+    static_assert(sizeof(EdgeRec) == 80, "records of five 16-byte chunks");
     __shared__ int64_t off[4][65];
+    __shared__ float4 stage[4][5 * 64];  // a wavefront's 64 records, written out in whole 16-byte chunks
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t j0 = ((int64_t)blockIdx.x * 4 + w) * 64;
     if (j0 >= n_faces) return;
@@ -107,36 +112,44 @@ __global__ void __launch_bounds__(256) k_edge_table(int64_t n_faces, const int64
     if (lane == 0) off[w][nf] = fvo[j0 + nf];
     lds_sync_wave();
     const int64_t s_end = off[w][nf];
-    for (int64_t q = off[w][0] + lane; q < s_end; q += 64) {
-        int lo = 0, hi = nf - 1;  // face f with off[f] <= q < off[f + 1]
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (off[w][mid] <= q) lo = mid;
-            else hi = mid - 1;
+    for (int64_t q0 = off[w][0]; q0 < s_end; q0 += 64) {
+        const int64_t q = q0 + lane;
+        const int cnt = (int)(s_end - q0 < 64 ? s_end - q0 : 64);
+        if (q < s_end) {
+            int lo = 0, hi = nf - 1;  // face f with off[f] <= q < off[f + 1]
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (off[w][mid] <= q) lo = mid;
+                else hi = mid - 1;
+            }
+            const int64_t j = j0 + lo;
+            const int64_t qn = q + 1 == off[w][lo + 1] ? off[w][lo] : q + 1;
+            const double *a = verts + 3 * (int64_t)fv[q];
+            const double *b = verts + 3 * (int64_t)fv[qn];
+            const double nx = plane[4 * j], ny = plane[4 * j + 1], nz = plane[4 * j + 2];
+            double ex = b[0] - a[0], ey = b[1] - a[1], ez = b[2] - a[2];
+            const double L = sqrt(ex * ex + ey * ey + ez * ez);
+            const double inv = L > 0.0 ? 1.0 / L : 0.0;
+            ex *= inv;
+            ey *= inv;
+            ez *= inv;
+            EdgeRec &r = *reinterpret_cast<EdgeRec *>(&stage[w][5 * lane]);
+            r.vx = a[0];
+            r.vy = a[1];
+            r.vz = a[2];
+            r.L = L;
+            r.ex = ex;
+            r.ey = ey;
+            r.ez = ez;
+            r.mx = ny * ez - nz * ey;
+            r.my = nz * ex - nx * ez;
+            r.mz = nx * ey - ny * ex;
         }
-        const int64_t j = j0 + lo;
-        const int64_t qn = q + 1 == off[w][lo + 1] ? off[w][lo] : q + 1;
-        const double *a = verts + 3 * (int64_t)fv[q];
-        const double *b = verts + 3 * (int64_t)fv[qn];
-        const double nx = plane[4 * j], ny = plane[4 * j + 1], nz = plane[4 * j + 2];
-        double ex = b[0] - a[0], ey = b[1] - a[1], ez = b[2] - a[2];
-        const double L = sqrt(ex * ex + ey * ey + ez * ez);
-        const double inv = L > 0.0 ? 1.0 / L : 0.0;
-        ex *= inv;
-        ey *= inv;
-        ez *= inv;
-        EdgeRec r;
-        r.vx = a[0];
-        r.vy = a[1];
-        r.vz = a[2];
-        r.L = L;
-        r.ex = ex;
-        r.ey = ey;
-        r.ez = ez;
-        r.mx = ny * ez - nz * ey;
-        r.my = nz * ex - nx * ez;
-        r.mz = nx * ey - ny * ex;
-        edges[q] = r;
+        lds_sync_wave();
+        // records q0 .. q0 + cnt - 1 are 5 cnt consecutive chunks: lane k writes chunks k, k + 64, ...
+        float4 *dst = reinterpret_cast<float4 *>(edges + q0);
+        for (int c = lane; c < 5 * cnt; c += 64) dst[c] = stage[w][c];
+        lds_sync_wave();  // the chunks are read before the next records overwrite them
     }
 }
 
