@@ -239,14 +239,26 @@ __global__ void k_candidates(int64_t n_cells, const double *__restrict__ aabb, c
     const int64_t out = (MODE == 1 && active) ? coffs[c] : 0;
     const int64_t nout = (MODE == 1 && active) ? noffs[c] : 0;
     uint32_t *mine = buf + (MODE == 0 ? c * (int64_t)K : 0);
+    // The walk is a chain of dependent loads of node boxes (wave-uniform).  A
+    // descent loads both children's boxes at once (adjacent in the heap), so
+    // that a left child that is a leaf or not entered hands over to its right
+    // sibling without a load.
     int64_t i = 1;
+    double b[6], sib[6];
+    bool have_sib = false;
+    for (int d = 0; d < 6; d++) b[d] = nodes[6 + d];
     for (;;) {
-        const double *nb = nodes + 6 * i;
-        const bool hit = active && nb[0] <= hi0 && lo0 <= nb[3] && nb[1] <= hi1 && lo1 <= nb[4] && nb[2] <= hi2 &&
-                         lo2 <= nb[5];
+        const bool hit = active && b[0] <= hi0 && lo0 <= b[3] && b[1] <= hi1 && lo1 <= b[4] && b[2] <= hi2 &&
+                         lo2 <= b[5];
         const bool any = __ballot(hit) != 0;
         if (any && i < NL) {
             i = 2 * i;
+            const double *nb = nodes + 6 * i;
+            for (int d = 0; d < 6; d++) {
+                b[d] = nb[d];
+                sib[d] = nb[6 + d];
+            }
+            have_sib = true;
             continue;
         }
         if (hit) {
@@ -275,9 +287,17 @@ __global__ void k_candidates(int64_t n_cells, const double *__restrict__ aabb, c
                 count++;
             }
         }
+        if ((i & 1) == 0 && have_sib) {  // the right sibling, loaded with this node
+            i += 1;
+            for (int d = 0; d < 6; d++) b[d] = sib[d];
+            have_sib = false;
+            continue;
+        }
         while (i & 1) i >>= 1;
         if (i == 0) break;
         i += 1;
+        for (int d = 0; d < 6; d++) b[d] = nodes[6 * i + d];
+        have_sib = false;
     }
     if (MODE == 0) {
         if (active) {
