@@ -1383,28 +1383,96 @@ __global__ void k_table_build(int n0, int n1, int n2, double *__restrict__ tab64
 
 }  // namespace
 
-// One wavefront per listed cell, lanes over its pairs: the pair in FP64.
-__global__ void k_recompute_cells(int64_t n_list, const uint32_t *__restrict__ cells, const int64_t *__restrict__ coff,
-                                  const uint32_t *__restrict__ pair_p, const double *__restrict__ xyz,
-                                  const double *__restrict__ h, const int64_t *__restrict__ cfo,
-                                  const int64_t *__restrict__ fvo, const double *__restrict__ plane,
-                                  const EdgeRec *__restrict__ edges, double *__restrict__ f,
-                                  unsigned long long *counters)
+// The listed cells' pairs in FP64, to the bit as pair_fraction<MAP_FP64>
+// (the per-pair FP64 form): each workgroup takes chunks of 32 of a cell's pairs (kRecBlocks workgroups
+// per cell, chunks round-robin), computes every (pair, wall) term of a chunk
+// in parallel (the wall's edge loop of pair_fraction), then one thread per
+// pair adds its walls in wall order, as pair_fraction does, so the result is
+// the FP64 path's to the bit (cells of up to 64 walls; larger ones take one
+// thread per pair).  One thread per pair left most of the
+// workgroup idle and each thread with all of its pair's edge terms in a row.
+constexpr int kRecPairs = 32, kRecBlocks = 4, kRecWalls = 64;
+
+__global__ void __launch_bounds__(256) k_recompute_cells(int64_t n_list, const uint32_t *__restrict__ cells,
+                                                         const int64_t *__restrict__ coff,
+                                                         const uint32_t *__restrict__ pair_p,
+                                                         const double *__restrict__ xyz, const double *__restrict__ h,
+                                                         const int64_t *__restrict__ cfo,
+                                                         const int64_t *__restrict__ fvo,
+                                                         const double *__restrict__ plane,
+                                                         const EdgeRec *__restrict__ edges, double *__restrict__ f,
+                                                         unsigned long long *counters)
 {
-    // one workgroup of 256 per listed cell: the pairs of a cell are done in one
-    // round (about 125 per cell), the FP64 closed forms' latency spread over
-    // four wavefronts
+    static_assert(kRecPairs * kRecWalls <= 2048, "one chunk's terms in LDS");
+    __shared__ double term[kRecPairs * kRecWalls];
+    __shared__ uint8_t side[kRecPairs * kRecWalls];  // bit 0: d >= 0, bit 1: d == 0
     const int64_t q = blockIdx.x;
     if (q >= n_list) return;
     const int64_t c = cells[q];
-    Work wk;
-    for (int64_t k = coff[c] + threadIdx.x; k < coff[c + 1]; k += blockDim.x) {
-        const int64_t a = pair_p[k];
-        float ev = 0.0f;
-        f[k] = pair_fraction<MAP_FP64>(xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2], h[a], c, cfo, fvo, plane, edges, wk,
-                                       (uint64_t)k, nullptr, nullptr, 0u, ev);
+    const int64_t f0 = cfo[c], nw = cfo[c + 1] - f0;
+    const int64_t k0 = coff[c], np = coff[c + 1] - k0;
+    if (nw > kRecWalls) {  // cells of more walls: one thread per pair
+        for (int64_t k = k0 + (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < k0 + np;
+             k += (int64_t)gridDim.y * blockDim.x) {
+            const int64_t a = pair_p[k];
+            Work wk;
+            float ev = 0.0f;
+            f[k] = pair_fraction<MAP_FP64>(xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2], h[a], c, cfo, fvo, plane,
+                                           edges, wk, (uint64_t)k, nullptr, nullptr, 0u, ev);
+        }
+    } else {
+        const int W = (int)nw;
+        for (int64_t pb = (int64_t)blockIdx.y * kRecPairs; pb < np; pb += (int64_t)gridDim.y * kRecPairs) {
+            const int nc = (int)(np - pb < kRecPairs ? np - pb : kRecPairs);
+            __syncthreads();  // the previous chunk's sums are done
+            for (int it = threadIdx.x; it < nc * W; it += blockDim.x) {
+                const int p = it / W, w = it - p * W;
+                const int64_t a = pair_p[k0 + pb + p];
+                const double px = xyz[3 * a], py = xyz[3 * a + 1], pz = xyz[3 * a + 2];
+                const double invh = 1.0 / h[a];
+                const int64_t j = f0 + w;
+                const double nx = plane[4 * j], ny = plane[4 * j + 1], nz = plane[4 * j + 2], cj = plane[4 * j + 3];
+                const double d = cj - (nx * px + ny * py + nz * pz);
+                side[it] = (uint8_t)((d >= 0.0 ? 1 : 0) | (d == 0.0 ? 2 : 0));
+                const double r0d = fabs(d) * invh;
+                double face = 0.0;
+                if (r0d < 2.0) {
+                    Work wk;
+                    const double Ht = pi_H<double>(r0d), dH = pi_dH<double>(r0d);
+                    for (int64_t sl = fvo[j]; sl < fvo[j + 1]; sl++) {
+                        const EdgeRec E = edges[sl];
+                        const double wx = px - E.vx, wy = py - E.vy, wz = pz - E.vz;
+                        const double rho = E.mx * wx + E.my * wy + E.mz * wz;
+                        if (rho == 0.0) continue;
+                        const double la = -(E.ex * wx + E.ey * wy + E.ez * wz) * invh;
+                        const double lb = la + E.L * invh;
+                        const double t = edge_term<double>(r0d, fabs(rho) * invh, la, lb, Ht, dH, wk);
+                        face += (rho > 0.0) ? t : -t;
+                    }
+                }
+                term[it] = face;
+            }
+            __syncthreads();
+            for (int p = threadIdx.x; p < nc; p += blockDim.x) {
+                const int64_t k = k0 + pb + p, a = pair_p[k];
+                bool inside = true;
+                int n_on = 0;
+                double acc = 0.0;
+                for (int w = 0; w < W; w++) {
+                    const uint8_t sd = side[p * W + w];
+                    const bool in_j = (sd & 1) != 0;
+                    inside = inside && in_j;
+                    n_on += (sd >> 1) & 1;
+                    const double face = term[p * W + w];
+                    acc += in_j ? face : -face;
+                }
+                f[k] = winding_term(inside, n_on, xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2], c, cfo, fvo, plane,
+                                    edges) -
+                       acc * kInvPi;
+            }
+        }
     }
-    if (threadIdx.x == 0) atomicAdd(counters + C_FP64_PAIRS, (unsigned long long)(coff[c + 1] - coff[c]));
+    if (threadIdx.x == 0 && blockIdx.y == 0) atomicAdd(counters + C_FP64_PAIRS, (unsigned long long)np);
 }
 
 void launch_table_build(int n0, int n1, int n2, double *tab64, float *tab32, hipStream_t s)
@@ -1580,7 +1648,7 @@ void launch_recompute_cells(const DevInputs &in, const EdgeRec *edges, const Pai
                             int64_t n_cells, double *f, int64_t *counters, hipStream_t s)
 {
     if (n_cells <= 0) return;
-    hipLaunchKernelGGL(k_recompute_cells, dim3((unsigned)n_cells), dim3(256), 0, s, n_cells,
+    hipLaunchKernelGGL(k_recompute_cells, dim3((unsigned)n_cells, kRecBlocks), dim3(256), 0, s, n_cells,
                        cells, ps.coff, ps.pair_p, in.xyz, in.h, in.cfo, in.fvo, in.plane, edges, f,
                        reinterpret_cast<unsigned long long *>(counters));
     EM_HIP(hipGetLastError());

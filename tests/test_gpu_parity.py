@@ -346,6 +346,12 @@ def test_mixed_cell_budget_switches(uniform4k, uniform4k_oracle):
     assert allc["stats"]["n_fp64_cells"] == c.n_cells and allc["stats"]["n_fp64_pairs"] == o["f"].size
     assert np.abs(allc["f"] - o["f"]).max() < FP64_PAIR_ABS
     assert (np.abs(allc["M"] - o["M"]) / o["M"]).max() < FP64_CELL_REL
+    # the recomputation (pair, wall terms in parallel, walls added in order) is the per-pair FP64 form
+    # (distribution 0, one thread per pair) to the bit
+    with em.Mapper(device=0, precision=em.MAP_FP64) as mp:
+        em.map_set_tune(mp.ctx, em.MAP_FP64, 0, 1, 4, 0)
+        flat = mp.map(p, c, want_pairs=True)
+    assert np.array_equal(allc["pair_p"], flat["pair_p"]) and np.array_equal(allc["f"], flat["f"])
     with em.Mapper(device=0, precision=em.MAP_MIXED) as mp:
         dflt = mp.map(p, c, want_pairs=True)
     rel_raw = (np.abs(raw["M"] - o["M"]) / o["M"]).max()
