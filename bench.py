@@ -38,8 +38,8 @@ FLOP_FACE, FLOP_EDGE, FLOP_ETERM, FLOP_MOMENT, FLOP_QPOINT, FLOP_ANGLE = 7, 19, 
 # (profiles/traffic_integrate_queued_clumps262144.md, profiles/valu_integrate_queued_clumps262144.md); null
 # once the source has changed.
 COUNTER_SOURCE = "paper_2404_17084_amd/csrc/em_integrate.hip"
-COUNTER_SHA256_PREFIX = "156ce6bfcba6938a"
-TRAFFIC_BYTES = 2.636e9
+COUNTER_SHA256_PREFIX = "e913931a62f3ef08"
+TRAFFIC_BYTES = 2.631e9
 VALU_FLOPS_PER_LAUNCH = 5.581e11
 
 PEAK_FP64 = 78.6   # TFLOP/s, MI355X FP64 vector
