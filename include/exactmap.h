@@ -450,7 +450,8 @@ int map_set_regions(map_ctx *ctx, int64_t n_regions, const double *regions);
  * site outside the box or not finite, two coinciding sites when merge_dist
  * is 0, lloyd_iters outside [0, 1000], merge_dist negative or not finite;
  * MAP_EDEVICE for a cell with more than 64 faces or 128 vertices.  Uses
- * about 7.5 KB of device memory per site while building.
+ * about 7 kB of device memory per site while building (a 5.9 kB record per
+ * cell, released when the grid is done).
  */
 typedef struct map_voronoi_out {
     int64_t n_cells, n_faces, n_face_verts, n_verts;
