@@ -16,7 +16,9 @@ against the same device run:
     the whole grid) agrees with the oracle;
   * over all 8.4 million cells, the mixed result agrees with the FP64 result
     within 1e-5 relative, and mass is conserved to 1e-9 in both.
-The pseudo variant is small enough for the oracle to map in full.
+The device grid itself is checked against the oracle's cells on sampled cells
+(the largest and most-faceted among them).  The pseudo variant is small enough
+for the oracle to map in full.
 """
 import sys
 import time
@@ -153,6 +155,27 @@ def test_large_full_resolution(large):
     assert relall.max() <= 1e-5
     del F, PP, PC, F64, PP64, PC64
     torch.cuda.empty_cache()
+
+
+def test_large_voronoi_sampled(large):
+    """The device grid of the 8.4 million sites against the oracle's cells on 16 seeded cells, the 8
+    largest and the 8 with the most faces (the longest candidate walks: those that can leave the
+    wavefront walk for the serial one): volumes to 1e-12 relative, neighbour sets exact."""
+    L = large
+    cells = synth.cells_from(L["G"])
+    nf = np.diff(cells.cell_face_off)
+    rng = np.random.default_rng(99)
+    sel = np.unique(np.concatenate([rng.choice(N_LARGE, 16, replace=False), np.argsort(cells.cell_volume)[-8:],
+                                    np.argsort(nf, kind="stable")[-8:]]))
+    say(f"case: large job, device Voronoi cells against the oracle on {sel.size} cells")
+    O = oracle.voronoi(L["p"].xyz, synth.BOX, sel=sel)
+    rel = np.abs(cells.cell_volume[sel] - O["cell_volume"]) / O["cell_volume"]
+    say(f"  volume max rel {rel.max():.3e}")
+    assert rel.max() < 1e-12
+    for k, c in enumerate(sel):
+        dev = set(cells.face_nb[cells.cell_face_off[c]:cells.cell_face_off[c + 1]].tolist())
+        orc = set(O["face_nb"][O["cell_face_off"][k]:O["cell_face_off"][k + 1]].tolist())
+        assert dev == orc, (int(c), sorted(dev ^ orc))
 
 
 def test_large_pseudo_variant(large):
