@@ -550,6 +550,19 @@ def valu_calibration():
             "tflops_fp32_nonpacked": tf, "frac_of_157_3": tf / PEAK_FP32}
 
 
+def copy_calibration():
+    """One plain 1 GiB device-to-device copy: the known byte count that scales the HBM byte counters
+    (FETCH_SIZE, WRITE_SIZE) of a profiled run."""
+    import torch
+
+    src_t = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+    dst_t = torch.empty_like(src_t)
+    torch.cuda.synchronize()
+    dst_t.copy_(src_t)
+    torch.cuda.synchronize()
+    return 1 << 30
+
+
 def voronoi_only(em, args):
     """The device Voronoi grid alone (profiling mode): timings of the 262,144-site build."""
     import torch
@@ -575,12 +588,7 @@ def voronoi_only(em, args):
                           "faces": int(G.face_plane.shape[0])}
     line = {"voronoi_grid": out, "sites": p.n, "steps": args.steps}
     if args.copy_calibration:
-        src_t = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
-        dst_t = torch.empty_like(src_t)
-        torch.cuda.synchronize()
-        dst_t.copy_(src_t)
-        torch.cuda.synchronize()
-        line["copy_calibration_bytes"] = 1 << 30
+        line["copy_calibration_bytes"] = copy_calibration()
     print(json.dumps(line), flush=True)
 
 
@@ -759,12 +767,7 @@ def main():
     if cpu is not None:
         line["cpu_baseline"] = cpu
     if args.copy_calibration:
-        src_t = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
-        dst_t = torch.empty_like(src_t)
-        torch.cuda.synchronize()
-        dst_t.copy_(src_t)
-        torch.cuda.synchronize()
-        line["copy_calibration_bytes"] = 1 << 30
+        line["copy_calibration_bytes"] = copy_calibration()
     print(json.dumps(line), flush=True)
 
 
