@@ -757,6 +757,69 @@ __global__ void k_vor_gather(int64_t n, const double *__restrict__ s, const int6
     out[3 * k + 2] = s[3 * i + 2];
 }
 
+// The cell holding each input point by a walk over the grid's cells: from a
+// start cell, move to the face neighbour whose site is nearest the point, as
+// long as one is nearer than the current site.  Over the box-clipped Voronoi
+// grid this ends at the cell that holds the point (the segment from a site to
+// the point leaves the site's cell through a face whose neighbour is nearer;
+// the cells fill the box).  A point with a face neighbour at the current
+// distance or within a relative 1e-10 of it (a tie, or one that rounding could
+// decide: a site tied at an edge or vertex of the cell is tied with a face
+// neighbour too), or a walk longer than 4096 steps, is listed for the tree
+// walk below instead, which breaks ties by the lower index.  Points take as
+// start the cell of the same relative index (the point's own site after Lloyd
+// steps; near it for points in a spatially coherent order).
+__global__ void __launch_bounds__(128) k_vor_site_walk(int64_t n_in, const double *__restrict__ x, int64_t n,
+                                                       const double *__restrict__ sites,
+                                                       const int64_t *__restrict__ cfo,
+                                                       const int64_t *__restrict__ fnb,
+                                                       int64_t *__restrict__ site_cell, int64_t *__restrict__ list,
+                                                       unsigned long long *__restrict__ n_list)
+{
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n_in) return;
+    const double px = x[3 * a], py = x[3 * a + 1], pz = x[3 * a + 2];
+    auto dist2 = [&](int64_t q) {
+        const double dx = sites[3 * q] - px, dy = sites[3 * q + 1] - py, dz = sites[3 * q + 2] - pz;
+        return dx * dx + dy * dy + dz * dz;
+    };
+    int64_t c = n_in == n ? a : (int64_t)((double)a * (double)n / (double)n_in);
+    if (c >= n) c = n - 1;
+    double d = dist2(c);
+    bool settled = false;
+    for (int step = 0; step < 4096; step++) {
+        int64_t best = -1;
+        double bd = d;
+        for (int64_t f = cfo[c]; f < cfo[c + 1]; f++) {
+            const int64_t q = fnb[f];
+            if (q < 0) continue;  // a wall
+            const double dq = dist2(q);
+            if (dq < bd) {
+                bd = dq;
+                best = q;
+            }
+        }
+        if (best < 0) {
+            settled = true;
+            break;
+        }
+        c = best;
+        d = bd;
+    }
+    bool tie = !settled;
+    if (settled)
+        for (int64_t f = cfo[c]; f < cfo[c + 1] && !tie; f++) {
+            const int64_t q = fnb[f];
+            tie = q >= 0 && dist2(q) <= d * (1.0 + 1e-10);
+        }
+    if (tie) {
+        const unsigned long long k = atomicAdd(n_list, 1ull);
+        list[k] = a;
+    } else {
+        site_cell[a] = c;
+    }
+}
+
 // The cell holding each input point: its nearest site of the grid (ties to
 // the lower index), by a walk of the grid's site tree, nearer child first,
 // skipping boxes farther than the best so far.  Each thread's stack is a
@@ -764,12 +827,15 @@ __global__ void k_vor_gather(int64_t n, const double *__restrict__ s, const int6
 // hold trees of up to 2^30 leaves).
 constexpr int kSiteStack = 32;
 
-__global__ void __launch_bounds__(128) k_vor_site_cell(int64_t n_in, const double *__restrict__ x, int64_t n, const double *__restrict__ ps,
-                                const int32_t *__restrict__ orig, const double *__restrict__ bx, int64_t NL,
-                                int64_t *__restrict__ site_cell)
+__global__ void __launch_bounds__(128) k_vor_site_cell(int64_t n_in, const int64_t *__restrict__ list,
+                                                       const double *__restrict__ x, int64_t n,
+                                                       const double *__restrict__ ps, const int32_t *__restrict__ orig,
+                                                       const double *__restrict__ bx, int64_t NL,
+                                                       int64_t *__restrict__ site_cell)
 {
-    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= n_in) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_in) return;
+    const int64_t a = list ? list[t] : t;  // the listed points, or every point
     const double px = x[3 * a], py = x[3 * a + 1], pz = x[3 * a + 2];
     double best = INFINITY;
     int32_t bi = -1;
@@ -960,9 +1026,21 @@ void site_cells(Workspace &ws, const VorGrid &V, int64_t n_in, const double *in,
         B.lo[k] = box[k];
         B.hi[k] = box[3 + k];
     }
+    // the walk over the cells, then the tree walk for the points it lists
+    int64_t *list = ws.get<int64_t>(S_VOR9, (size_t)n_in);
+    unsigned long long *n_list = reinterpret_cast<unsigned long long *>(ws.get<int64_t>(S_VOR10, 1));
+    fill_zero_bytes(n_list, sizeof(unsigned long long), s);
+    hipLaunchKernelGGL(k_vor_site_walk, dim3(vgrid(n_in, 128)), dim3(128), 0, s, n_in, in, V.n,
+                       (const double *)V.sites, (const int64_t *)V.cfo, (const int64_t *)V.fnb, site_cell, list,
+                       n_list);
+    EM_HIP(hipGetLastError());
+    unsigned long long n_tree = 0;
+    EM_HIP(hipMemcpyAsync(&n_tree, n_list, sizeof(n_tree), hipMemcpyDeviceToHost, s));
+    EM_HIP(hipStreamSynchronize(s));
+    if (n_tree == 0) return;
     const SiteTree T = site_tree(ws, V.n, V.sites, B, true, s);
-    hipLaunchKernelGGL(k_vor_site_cell, dim3(vgrid(n_in, 128)), dim3(128), 0, s, n_in, in, V.n, T.ps, T.orig,
-                       (const double *)T.bx, T.NL, site_cell);
+    hipLaunchKernelGGL(k_vor_site_cell, dim3(vgrid((int64_t)n_tree, 128)), dim3(128), 0, s, (int64_t)n_tree,
+                       (const int64_t *)list, in, V.n, T.ps, T.orig, (const double *)T.bx, T.NL, site_cell);
     EM_HIP(hipGetLastError());
 }
 

@@ -169,6 +169,19 @@ def test_voronoi_edge_cases():
         assert np.allclose(G.centroid, cases["lattice"], atol=1e-15)
 
 
+def test_site_cell_ties():
+    """An input point equidistant from two grid sites belongs to the lower index: the walk over the
+    cells lists it for the tree walk, which breaks the tie."""
+    say("case: voronoi site cells with a tie")
+    s = np.array([[0.25, 0.5, 0.5], [0.75, 0.5, 0.5], [0.5, 0.5, 0.5], [0.5, 0.25, 0.25]])
+    kept = oracle.merge_sites(s, 0.3)
+    assert kept.tolist() == [0, 1, 3]  # the midpoint is merged away
+    with em.Mapper(device=0) as mp:
+        G = mp.voronoi(s, BOX, merge_dist=0.3)
+    assert np.array_equal(G.site_cell, oracle.site_cells(s, s[kept]))
+    assert G.site_cell[2] == 0
+
+
 def test_merging_and_site_cells():
     say("case: voronoi with tightly packed sites merged, then Lloyd steps")
     s = synth.particles("clumps", 2000, 91).xyz
