@@ -492,6 +492,7 @@ def voronoi_leg(em, mapper, p, xyz, m, h, c, M_fp64, steps, with_oracle):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         out[f"lloyd_{it}"] = {"ms": 1e3 * dt, "ms_device": G.ms, "cells_per_s": p.n / dt}
+    out["merge_lloyd_5"] = merge_timing(em, mapper.ctx, sites, p.n)
     G = em.map_voronoi(mapper.ctx, sites, synth.BOX, 0, device=True)
     mapper.set_precision(em.MAP_FP64)
     M = torch.zeros(p.n, dtype=torch.float64, device="cuda:0")
@@ -563,6 +564,22 @@ def copy_calibration():
     return 1 << 30
 
 
+def merge_timing(em, ctx, sites, n):
+    """The grid with merging and 5 Lloyd steps: sites closer than 1 % of the mean spacing to a site of
+    lower index merged (the paper gives no merge criterion)."""
+    import torch
+    import synth
+
+    d = 0.01 / n ** (1.0 / 3.0)
+    em.map_voronoi(ctx, sites, synth.BOX, 5, merge_dist=d, device=True)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    G = em.map_voronoi(ctx, sites, synth.BOX, 5, merge_dist=d, device=True)
+    torch.cuda.synchronize()
+    return {"merge_dist": d, "cells": int(G.n_cells), "merged": int(n - G.n_cells),
+            "ms": 1e3 * (time.perf_counter() - t0), "ms_device": G.ms}
+
+
 def voronoi_only(em, args):
     """The device Voronoi grid alone (profiling mode): timings of the 262,144-site build."""
     import torch
@@ -586,6 +603,7 @@ def voronoi_only(em, args):
         torch.cuda.synchronize()
         out["lloyd_5"] = {"ms": 1e3 * (time.perf_counter() - t0), "ms_device": G.ms,
                           "faces": int(G.face_plane.shape[0])}
+        out["merge_lloyd_5"] = merge_timing(em, mp.ctx, sites, p.n)
     line = {"voronoi_grid": out, "sites": p.n, "steps": args.steps}
     if args.copy_calibration:
         line["copy_calibration_bytes"] = copy_calibration()
@@ -615,7 +633,8 @@ def main():
                     help="run the VALU calibration kernel (scale for the VALU counters; measured FP32 rate)")
     ap.add_argument("--voronoi-only", action="store_true",
                     help="only build the device Voronoi grid of the 262,144 clumpy sites (1 warm-up, then --steps "
-                         "builds, then one with 5 Lloyd iterations) and print its timings (for profiling runs)")
+                         "builds, then one with 5 Lloyd iterations, then one with merging and 5 Lloyd iterations) "
+                         "and print its timings (for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the mapping runs on a single "
