@@ -265,7 +265,7 @@ static void finish_job(Server &S, Job *j)
     }
     finish_locked(S, j, code, msg);
     // the slot keeps its buffers for its next job: mapping them anew for
-    // every job (from the driver, gigabytes for the largest jobs) costs more
+    // every job (from the kernel-mode GPU driver, gigabytes for the largest jobs) costs more
     // than the jobs' own stages
 }
 
@@ -482,7 +482,7 @@ static Server &server_of(Ctx &C)
     }
     {
         // the pool that serves the slots' buffers keeps what it has while the
-        // server runs (a trim would hand memory back to the driver at the next
+        // server runs (a trim would hand memory back to the GPU driver at the next
         // stream synchronisation, and the next job would map it again); the
         // jobs in flight are bounded by the budget, so is what it holds, up
         // to fragmentation.  serve_stop trims it.
@@ -526,7 +526,7 @@ int serve_stop(Ctx &C)
         for (auto &sl : S->slots) sl->ws.release();
         if (S->sstream) (void)hipStreamSynchronize(S->sstream);
         if (S->bstream) (void)hipStreamSynchronize(S->bstream);
-        // the pool's cached memory back to the driver, and its default threshold back
+        // the pool's cached memory back to the GPU driver, and its default threshold back
         hipMemPool_t pool = nullptr;
         if (hipDeviceGetDefaultMemPool(&pool, C.device) == hipSuccess && pool) {
             (void)hipMemPoolTrimTo(pool, 0);
